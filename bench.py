@@ -1,0 +1,249 @@
+"""Surfactant-step throughput on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c1i|c2|c0]
+
+A step is one pass of the whole path (redistancing of the moving interface,
+the fused transport kernel, the FP64 reductions) over the workload's grid.
+The default workload is the 1024^2 FP32 soluble expanding circle.  Inputs
+(the VoF field at every step, the face velocities, the initial state) are
+generated before the timed region and resident in HBM.
+
+Timed regions:
+  1. the K steps replayed from one HIP graph (captured after W eager steps):
+     `value` (Gcell-updates/s) and `ms_per_step`;
+  2. the same K steps launched eagerly with the library's per-launch HIP
+     events: average duration of the fused transport kernel -> `roofline`.
+The FP64 CPU oracle is timed on a bounded sample of the same workload on the
+host (`cpu_baseline`).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c1i", "c2"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def workload(name, K, W):
+    from paper_2605_27534_amd import configs as C
+    if name == "c0":
+        return C.c0_static_circle()
+    if name == "c1":
+        return C.c1_expanding_circle(soluble=True)
+    if name == "c1i":
+        return C.c1_expanding_circle(soluble=False)
+    return C.c2_translating_sphere()
+
+
+def algorithmic_bytes(cfg, es):
+    """(transport-kernel bytes per cell, whole-step bytes per cell): every
+    compulsory field counted once, read or written."""
+    p = cfg["prob"]
+    dim = p["dim"]
+    bulk = p.get("bulk_enabled", 1)
+    has_u = cfg.get("u") is not None or cfg.get("u_seq") is not None
+    fields = 2 if bulk else 1
+    words = 1 + fields + (dim if has_u else 0) + fields + 1  # chi, state, u | state, sigma
+    step_words = words + (2 if cfg.get("vof_seq") else 0)     # + vof read, chi write
+    return words * es, step_words * es
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2605_27534_amd import surf as S
+
+    K, W = args.steps, args.warmup
+    cfg = workload(args.workload, K, W)
+    prob, prec = dict(cfg["prob"]), cfg["precision"]
+    prob["hj_iters_step"] = cfg.get("hj_step", 8)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    side = torch.cuda.Stream(dev)
+    ncell = int(np.prod(prob["n"]))
+    es = 8 if prec == 1 else 4
+
+    with torch.cuda.stream(side):
+        s = S.Surf(prob, cfg["dt"], prec)
+        tens = s.tensor
+        print("# generating inputs: %s, %d steps" % (cfg["name"], W + K), file=sys.stderr, flush=True)
+        vof0 = tens(cfg["vof0"]())
+        vofs = None
+        if cfg.get("vof_seq"):
+            vofs = [tens(cfg["vof_seq"](k)) for k in range(W + K)]
+        u_static = [tens(x) for x in cfg["u"]()] if cfg.get("u") else None
+        u_list = None
+        if cfg.get("u_seq"):
+            u_list = [[tens(x) for x in cfg["u_seq"](k)] for k in range(W + K)]
+        c0 = tens(cfg["c0"]()) if cfg.get("c0") else None
+        bulk = prob.get("bulk_enabled", 1)
+        bufs = [[s.empty() if bulk else None, s.empty()] for _ in range(2)]
+        sig = s.empty()
+        hist = torch.zeros((W + K, 16), dtype=torch.float64, device=dev)
+
+        def reset():
+            s.set_geometry(vof0, full=True)
+            F, P = s.init_state(c0, cfg.get("c0_const", 1.0), cfg.get("gamma0", 0.0))
+            if F is not None:
+                bufs[0][0].copy_(F)
+            bufs[0][1].copy_(P)
+
+        def do_step(k):
+            a, b = bufs[k % 2], bufs[(k + 1) % 2]
+            u = u_list[k] if u_list is not None else u_static
+            v = vofs[k] if vofs is not None else None
+            s.step(a[0], a[1], b[0], b[1], u=u, vof_next=v, sigma_out=sig, totals=hist[k])
+
+        # ---- region 1: graph replay of K steps
+        reset()
+        for k in range(W):
+            do_step(k)
+        side.synchronize()
+        graph = None
+        if not args.no_graph:
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=side):
+                for k in range(W, W + K):
+                    do_step(k)
+        side.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        wall0 = time.perf_counter()
+        t0.record(side)
+        if graph is not None:
+            graph.replay()
+        else:
+            for k in range(W, W + K):
+                do_step(k)
+        t1.record(side)
+        side.synchronize()
+        wall = time.perf_counter() - wall0
+        ms_total = t0.elapsed_time(t1)
+        h1 = hist.cpu().numpy()
+        assert np.all(np.isfinite(h1[W:W + K, S.T_MTOT])), "non-finite totals"
+        status = s.status()
+
+        # ---- region 2: eager K steps with per-launch events
+        reset()
+        for k in range(W):
+            do_step(k)
+        s.profile_read()
+        s.profile(True)
+        for k in range(W, W + K):
+            do_step(k)
+        side.synchronize()
+        step_ms, step_n, geom_ms, geom_n = s.profile_read()
+        s.profile(False)
+        h2 = hist.cpu().numpy()
+
+    ms_per_step = ms_total / K
+    value = ncell * K / (ms_total * 1e-3) / 1e9
+    kbytes, sbytes = algorithmic_bytes(cfg, es)
+    k_avg_ms = step_ms / max(step_n, 1)
+    achieved = kbytes * ncell / (k_avg_ms * 1e-3) / 1e9
+    step_gbs = sbytes * ncell / (ms_per_step * 1e-3) / 1e9
+    out = {
+        "metric": "surfactant-step Gcell-updates/s (+ % HBM roofline)",
+        "value": round(value, 4),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms_per_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == 1 else "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "cells": ncell, "dt": cfg["dt"],
+                   "hj_sweeps_per_step": prob["hj_iters_step"] if vofs is not None else 0,
+                   "graph": graph is not None},
+        "roofline": {
+            "bound": "hbm", "kernel": "k_step (fused transport)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_cell": kbytes, "avg_launch_us": round(k_avg_ms * 1e3, 3),
+            "step_bytes_per_cell": sbytes, "step_frac": round(step_gbs / HBM_PEAK_GBS, 4),
+            "redistancing_us_per_step": round(geom_ms / K * 1e3, 3),
+            "redistancing_sweeps": int(geom_n),
+        },
+        "status": status,
+        "wall_s": round(wall, 4),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(cfg, seconds):
+    """The FP64 oracle as it stands, single-threaded, on a bounded sample of
+    the same workload: the first S steps (geometry warm start + step), S
+    chosen from a one-step probe to take about `seconds`."""
+    import numpy as np
+    from oracle import oracle as O
+    prob = dict(cfg["prob"])
+    q = O.full(prob)
+    ncell = int(np.prod(q["n"]))
+    vof0 = cfg["vof0"]()
+    import math
+    iters = 2 * int(math.ceil(q["chi_max_eps"] * q["eps"] / (q["h"] / q["dim"]) - 1e-9))
+    chi = O.geometry(prob, vof0, iters)
+    c0 = cfg["c0"]() if cfg.get("c0") else None
+    F, P = O.init_state(prob, chi, c0=c0, c0_const=cfg.get("c0_const", 1.0),
+                        gamma0=cfg.get("gamma0", 0.0))
+    u = cfg["u"]() if cfg.get("u") else None
+    hj = cfg.get("hj_step", 8)
+
+    def one(k, chi, F, P, tot):
+        if cfg.get("vof_seq"):
+            chi = O.geometry(prob, cfg["vof_seq"](k), hj, chi=chi)
+        uk = cfg["u_seq"](k) if cfg.get("u_seq") else u
+        F, P, _, tot = O.step(prob, chi, uk, F, P, cfg["dt"], tot)
+        return chi, F, P, tot
+
+    tot = np.zeros(16)
+    t = time.perf_counter()
+    chi, F, P, tot = one(0, chi, F, P, tot)
+    probe = time.perf_counter() - t
+    nsteps = max(1, min(200, int(seconds / max(probe, 1e-6))))
+    el = 0.0
+    for k in range(1, nsteps + 1):
+        # inputs of the next step are generated outside the timed part
+        vk = cfg["vof_seq"](k) if cfg.get("vof_seq") else None
+        uk = cfg["u_seq"](k) if cfg.get("u_seq") else u
+        t = time.perf_counter()
+        if vk is not None:
+            chi = O.geometry(prob, vk, hj, chi=chi)
+        F, P, _, tot = O.step(prob, chi, uk, F, P, cfg["dt"], tot)
+        el += time.perf_counter() - t
+    return {"value": round(ncell * nsteps / el / 1e9, 6), "unit": "Gcell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "first %d steps of the same workload (geometry warm start + step), "
+                      "FP64, one host thread, %.1f s" % (nsteps, el)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * surf.h -- C ABI of libsurf, the MI355X (gfx950) hybrid VoF/Phase-Field
+ * soluble-surfactant transport step.
+ *
+ * One step advances the bulk concentration F and the interfacial carrier
+ * psi = Gamma * delta (paper section 2.6) across a time step:
+ *   geometry   VoF fraction -> signed distance chi by Hamilton-Jacobi
+ *              redistancing (section 2.5), phi = 1/(1+exp(chi/eps)),
+ *              delta = phi (1-phi)/eps (eq. (redistance), section 2.6);
+ *   substep 1  explicit conservative advection (section 3.1);
+ *   substep 2  confinement + diffusion + exchange source, explicit
+ *              (sections 2.6, 3.1, 3.2, Appendices A and C);
+ *   EoS        sigma(Gamma) (sections 2.3, 5, 6);
+ * plus the Marangoni face force delta (I - n n) grad sigma (section 2.4).
+ *
+ * Conventions
+ *  - Every function returns SURF_OK (0) or a negative SURF_E* code; no
+ *    exception crosses the ABI.  surf_strerror() names a code.
+ *  - Ownership: the caller owns every field buffer and the workspace (device
+ *    memory).  The library never allocates or frees device memory; it owns
+ *    only its host-side context objects.
+ *  - Streams: every call is asynchronous on the HIP stream given at init
+ *    (a hipStream_t passed as void*; NULL = the null stream).  A context is
+ *    bound to one stream and is not thread-safe.
+ *  - Layout: cell fields are contiguous [nz][ny][nx] (x fastest), one buffer
+ *    per field.  Face fields along axis d hold n_d + 1 entries along d:
+ *    x faces [nz][ny][nx+1], y faces [nz][ny+1][nx], z faces [nz+1][ny][nx].
+ *    2D problems use dim = 2, n[2] = 1 and no z face array.
+ *  - Element type: every field buffer has the context precision (float for
+ *    SURF_F32, double for SURF_F64).  Totals are always double.
+ *  - Pointers must be device pointers aligned to their element size.
+ *  - Numerical health is reported through a sticky status word
+ *    (surf_get_status), not through return codes.
+ */
+#ifndef SURF_H
+#define SURF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define SURF_OK 0
+#define SURF_EINVAL (-1)    /* bad argument (null, size, range, alias)      */
+#define SURF_ENOMEM (-2)    /* workspace too small                          */
+#define SURF_EDEVICE (-3)   /* a HIP runtime error (launch or device)       */
+#define SURF_ESTATE (-4)    /* call-order violation (e.g. no geometry yet)  */
+#define SURF_EUNSTABLE (-5) /* reserved: reported through status bits       */
+
+/* status bits (sticky until surf_clear_status) */
+#define SURF_STATUS_NONFINITE 1u /* a non-finite F, psi or sigma was produced */
+#define SURF_STATUS_NEGATIVE 2u  /* a negative F or psi was produced          */
+#define SURF_STATUS_UNSTABLE 4u  /* dt exceeded the explicit stability bound  */
+
+enum { SURF_F32 = 0, SURF_F64 = 1 };
+/* substep-2 flux: weighted form D wbar grad(xi/w) (default) or the paper's
+ * centred-diffusion + upwind anti-diffusion form (section 3.2) */
+enum { SURF_FLUX_WEIGHTED = 0, SURF_FLUX_PAPER = 1 };
+/* exchange law: Langmuir J = k_a c (Gamma_inf - Gamma) - k_d Gamma
+ * (section 2.6) or constant adsorption flux J = k_a c Gamma_inf - k_d Gamma
+ * (section 4.3.1) */
+enum { SURF_KIN_LANGMUIR = 0, SURF_KIN_HENRY = 1 };
+/* sigma0 (1 - E x), sigma0 (1 + E ln(1 - x)), sigma0 (1 - tanh(E x)),
+ * x = Gamma / Gamma_inf (sections 2.3, 5 and 6) */
+enum { SURF_EOS_LINEAR = 0, SURF_EOS_LANGMUIR = 1, SURF_EOS_TANH = 2 };
+/* box faces: no flux; wrap; open (advective outflow/inflow of the adjacent
+ * cell value, no diffusive flux, counted in the boundary total) */
+enum { SURF_BC_WALL = 0, SURF_BC_PERIODIC = 1, SURF_BC_OPEN = 2 };
+
+/* slots of the 16-double totals record written by surf_step */
+enum {
+  SURF_T_MASS_BULK = 0,   /* sum F h^d after the step                      */
+  SURF_T_MASS_SURF = 1,   /* sum psi h^d                                   */
+  SURF_T_OUTFLOW = 2,     /* amount leaving through open faces this step   */
+  SURF_T_OUTFLOW_CUM = 3, /* cumulative outflow since init_state           */
+  SURF_T_SUM_DELTA = 4,   /* sum delta h^d (interface measure)             */
+  SURF_T_SUM_SIGDELTA = 5,/* sum sigma delta h^d                           */
+  SURF_T_MAX_USUM = 6,    /* max over cells of sum_d |cell-mean u_d|       */
+  SURF_T_DT_NEXT = 7,     /* safety-factored explicit dt bound             */
+  SURF_T_MIN_F = 8,       /* min F                                         */
+  SURF_T_MIN_PSI = 9,     /* min psi                                       */
+  SURF_T_NONFINITE = 10,  /* count of cells with a non-finite output       */
+  SURF_T_TIME = 11,       /* time after the step                           */
+  SURF_T_GAMMA_AVG = 12,  /* interface average sum psi / sum delta         */
+  SURF_T_SIGMA_AVG = 13,  /* interface average sum sigma delta / sum delta */
+  SURF_T_MASS_TOTAL = 14, /* bulk + interfacial + cumulative outflow       */
+  SURF_T_C_MAX = 15       /* max F / (phi + eta)                           */
+};
+
+typedef struct surf_ctx surf_ctx;
+typedef struct surf_batch surf_batch;
+
+/* The domain (section 3.2 and Appendix A: uniform Cartesian cells). */
+typedef struct {
+  int32_t dim;       /* 2 or 3                                     */
+  int32_t n[3];      /* cells per axis; n[2] = 1 in 2D              */
+  int32_t bc[3][2];  /* SURF_BC_* per box face (lo, hi); periodic
+                        axes must be periodic on both sides          */
+  int32_t pad_;
+  double h;          /* cell size (cubic cells)                    */
+  double origin[3];  /* position of the lower box corner (informative) */
+} surf_grid;
+
+/* The problem's parameters (sections 2.3-2.6, Appendix C). */
+typedef struct {
+  int32_t precision;    /* SURF_F32 | SURF_F64                            */
+  int32_t flux_form;    /* SURF_FLUX_*                                    */
+  int32_t kinetics;     /* SURF_KIN_*                                     */
+  int32_t eos;          /* SURF_EOS_*                                     */
+  int32_t bulk_enabled; /* 0: insoluble (no bulk field, no exchange)      */
+  int32_t hj_iters_init;/* redistancing sweeps for a full build (0: 2 ceil(chi_max/dtau)) */
+  int32_t hj_iters_step;/* warm-start sweeps per step when the VoF moves (0: 8) */
+  int32_t pad_;
+  double eps;           /* phase-field width (section 2.5)                */
+  double D_b, D_s;      /* bulk and interfacial diffusivities             */
+  double k_a, k_d;      /* adsorption and desorption rates                */
+  double gamma_inf;     /* saturation concentration                       */
+  double sigma0, eos_E; /* clean surface tension and elasticity E         */
+  double eta;           /* small constant added to phi when dividing (section 2.6); 0: 1e-12 */
+  double chi_max_eps;   /* distance clamp |chi| <= chi_max_eps * eps; 0: 12 */
+  double cfl_adv, cfl_diff; /* safety factors of SURF_T_DT_NEXT; 0: 0.5, 0.8 */
+  double dt;            /* time step used by surf_step (> 0)              */
+} surf_params;
+
+/* Bytes of device workspace a context needs. */
+int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_t* bytes);
+
+/* Validates the problem, carves the caller's workspace (device memory of at
+ * least surf_workspace_bytes, 256-byte aligned) and binds the stream.  No
+ * device work is issued. */
+int surf_init(surf_ctx** ctx, const surf_grid* grid, const surf_params* params,
+              void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* VoF fraction of fluid 1 (cell field, values in [0,1]) -> signed distance
+ * chi (section 2.5).  full_rebuild = 1 starts from chi0 = (f - 1/2) h and runs
+ * hj_iters_init sweeps; 0 warm-starts from the cached chi with hj_iters_step
+ * sweeps (SURF_ESTATE if there is no cached chi). */
+int surf_set_geometry(surf_ctx* ctx, const void* vof, int full_rebuild);
+
+/* Installs a signed-distance field directly (cell field, > 0 inside fluid 1). */
+int surf_set_levelset(surf_ctx* ctx, const void* chi);
+
+/* Copies the cached signed distance into chi_out (cell field). */
+int surf_get_levelset(surf_ctx* ctx, void* chi_out);
+
+/* Initial state F = c0 phi, psi = gamma0 delta (section 2.6, f = Gamma delta).
+ * c0 is a cell field or NULL for the constant c0_const.  Resets the running
+ * time, the cumulative outflow and the status word.  F_out may be NULL when
+ * the bulk is disabled. */
+int surf_init_state(surf_ctx* ctx, const void* c0, double c0_const, double gamma0,
+                    void* F_out, void* psi_out);
+
+/* One step from (F_in, psi_in) at t^n to (F_out, psi_out) at t^{n+1}.
+ *   vof_next  VoF at t^{n+1} (after the caller's VoF advection) or NULL when
+ *             the interface does not move; when given, chi is warm-started
+ *             with hj_iters_step sweeps before the transport.
+ *   u         face velocities u^n: u[0..dim-1] (face layouts above), or
+ *             u == NULL / u[0] == NULL for no flow (substep 1 skipped).
+ *   sigma_out cell field or NULL; totals_dev 16 doubles (device) or NULL.
+ * Inputs and outputs must not alias (ping-pong buffers).  F_in/F_out are
+ * ignored (may be NULL) when the bulk is disabled. */
+int surf_step(surf_ctx* ctx, const void* vof_next, const void* const* u,
+              const void* F_in, const void* psi_in, void* F_out, void* psi_out,
+              void* sigma_out, double* totals_dev);
+
+/* Marangoni face force (section 2.4) from sigma (cell field) and the cached
+ * chi: on each face along d, delta_face [ (grad sigma)_d - n_d (n . grad
+ * sigma) ] with n = grad chi/|grad chi| from the face gradient (compact normal
+ * difference, averaged transverse centred differences).  force[d] uses the
+ * face layout of u.  Faces on walls and open boundaries get 0. */
+int surf_force(surf_ctx* ctx, const void* sigma, void* const* force);
+
+/* Changes the time step used by the following steps. */
+int surf_set_dt(surf_ctx* ctx, double dt);
+
+/* Reads (synchronously: waits for the stream) and clears the status word. */
+int surf_get_status(surf_ctx* ctx, uint32_t* bits);
+int surf_clear_status(surf_ctx* ctx);
+
+int surf_destroy(surf_ctx* ctx);
+const char* surf_strerror(int code);
+
+/* Kernel timing.  While enabled, every launch of the fused transport kernel
+ * and of each redistancing sweep is bracketed by HIP events recorded on the
+ * context stream.  surf_profile_read waits for the recorded events, returns
+ * the summed elapsed milliseconds and launch counts per kind (transport,
+ * redistancing) and forgets them.  Any output pointer may be NULL. */
+int surf_profile_enable(surf_ctx* ctx, int enable);
+int surf_profile_read(surf_ctx* ctx, double* step_ms, int64_t* step_launches,
+                      double* geom_ms, int64_t* geom_launches);
+
+/* Library version string. */
+const char* surf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SURF_H */

@@ -571,7 +571,7 @@ int or_step(const int* ip, const double* dp, const double* chi,
     if (p.bulk) lam += p.ka * p.ginf / p.eps + p.ka * (cmax > 0 ? cmax : 0.0) + p.kd;
     double dta = su > 0 ? p.cfl_a * p.h / su : INFINITY;
     double dtd = p.cfl_d / lam;
-    totals[T_MB] = mb.s;
+    totals[T_MB] = p.bulk ? mb.s : 0.0; /* the insoluble model has no bulk field */
     totals[T_MS] = ms.s;
     totals[T_OUT] = outstep;
     totals[T_OUTCUM] = outcum;

@@ -1,0 +1,125 @@
+"""The five benchmark workloads as plain problem descriptions.
+
+Each function returns a dict with the problem (the keys of the library's
+parameter structs), the time step, the step count and callables producing the
+seeded inputs (all FP64 NumPy, from `synth`).  Time steps are fixed numbers
+chosen at or below the explicit stability bound of the split step (the bound
+is the library's SURF_T_DT_NEXT; the values below were read from it for the
+analytic velocity fields and rounded down).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import synth
+
+
+def c0_static_circle():
+    """128^2 FP64, unit box, walls, static circle R = 0.25, u = 0, Langmuir
+    kinetics k_a = k_d = Gamma_inf = 1, D_b = 1e-2, D_s = 1e-3, linear EoS
+    sigma = 1 - 0.5 Gamma; F0 = phi (c = 1 in the liquid), psi0 = 0;
+    200 steps at dt = 0.2 h^2 / D_b."""
+    n = 128
+    h = 1.0 / n
+    prob = dict(dim=2, n=(n, n), h=h, bc=((0, 0), (0, 0)), eos=0, eos_E=0.5, sigma0=1.0,
+                k_a=1.0, k_d=1.0, gamma_inf=1.0, D_b=1e-2, D_s=1e-3)
+    return dict(name="static circle 128^2 fp64", prob=prob, precision=1,
+                dt=0.2 * h * h / 1e-2, steps=200,
+                vof0=lambda: synth.vof_ball((n, n), h, (0.5, 0.5, 0), 0.25, 2),
+                vof_seq=None, u=None, c0=None, c0_const=1.0, gamma0=0.0, hj_step=8)
+
+
+def c1_expanding_circle(n=1024, soluble=True):
+    """1024^2 FP32, open box, circle R(t) = sqrt(R0^2 + Q t / pi), R0 = 0.1,
+    Q = 0.05, centred, under the 2D source flow (core radius 0.02); VoF at
+    t^{n+1} each step; Gamma0 = 0.5; c0 ~ U[0.8, 1.2] (seed 1) in the liquid;
+    Langmuir EoS sigma0 = 1, E = 0.2; kinetics and diffusivities as the static
+    circle; 2000 steps.  The insoluble variant switches the bulk off."""
+    h = 1.0 / n
+    R0, Q = 0.1, 0.05
+    prob = dict(dim=2, n=(n, n), h=h, bc=((2, 2), (2, 2)), eos=1, eos_E=0.2, sigma0=1.0,
+                k_a=1.0, k_d=1.0, gamma_inf=1.0, D_b=1e-2, D_s=1e-3,
+                bulk_enabled=1 if soluble else 0)
+    # explicit bound at 1024^2: substep 2 limits (soluble 1.776e-5, insoluble 1.803e-4)
+    dt = (1.77e-5 if soluble else 1.80e-4) * (1024.0 / n) ** 2
+    Rt = lambda t: math.sqrt(R0 ** 2 + Q * t / math.pi)
+    return dict(name="expanding circle %d^2 fp32 %s" % (n, "soluble" if soluble else "insoluble"),
+                prob=prob, precision=0, dt=dt, steps=2000, R=Rt,
+                vof0=lambda: synth.vof_ball((n, n), h, (0.5, 0.5, 0), R0, 2),
+                vof_seq=lambda k: synth.vof_ball((n, n), h, (0.5, 0.5, 0), Rt((k + 1) * dt), 2),
+                u=lambda: synth.u_source2d((n, n), h, (0.5, 0.5, 0), Q),
+                c0=lambda: synth.uniform_field((n, n), 1, 0.8, 1.2) if soluble else None,
+                c0_const=1.0, gamma0=0.5, hj_step=8)
+
+
+def c2_translating_sphere(n=256):
+    """256^3 FP32, periodic in z, open in x and y; sphere R = 0.15 with centre
+    (0.5, 0.5, 0.25 + U t), U = 0.5, VoF each step; lab-frame
+    Hadamard-Rybczynski flow (viscosity ratio 0.01, sphere-frame stream -U)
+    plus U along z, nearest periodic image; bubble-scaled parameters with
+    d = 0.3: D_b = U d / Pe_b (Pe_b = 100), D_s = U d / Pe_s (Pe_s = 1000),
+    k_d = Bi U / d (Bi = 1), k_a = Da U / (d c0) (Da = 0.1), Langmuir EoS with
+    E = 0.3, c0 = 1, Gamma0 = 0; 1000 steps."""
+    h = 1.0 / n
+    U, R, d = 0.5, 0.15, 0.3
+    prob = dict(dim=3, n=(n, n, n), h=h, bc=((2, 2), (2, 2), (1, 1)), eos=1, eos_E=0.3,
+                sigma0=1.0, gamma_inf=1.0, D_b=U * d / 100, D_s=U * d / 1000,
+                k_d=1.0 * U / d, k_a=0.1 * U / d, hj_iters_step=16)
+    dt = 1.24e-3 * (256.0 / n) ** 2
+    zc = lambda t: (0.25 + U * t) % 1.0
+    cen = lambda t: (0.5, 0.5, zc(t))
+    return dict(name="translating sphere %d^3 fp32" % n, prob=prob, precision=0, dt=dt,
+                steps=1000,
+                vof0=lambda: synth.vof_ball((n, n, n), h, cen(0.0), R, 3, period_z=1.0),
+                vof_seq=lambda k: synth.vof_ball((n, n, n), h, cen((k + 1) * dt), R, 3,
+                                                 period_z=1.0),
+                u_seq=lambda k: synth.u_hadamard((n, n, n), h, cen(k * dt), R, -U, 0.01,
+                                                 frame_shift=U, period_z=1.0),
+                c0=None, c0_const=1.0, gamma0=0.0, hj_step=16)
+
+
+def c3_ensemble(seed=3, count=64):
+    """64 independent 2D static-circle instances: n ~ choice{128, 256, 512,
+    1024}, R ~ U[0.15, 0.3] centred, Bi, Da ~ 10^U[-2, 2] (drawn in the order
+    n, R, Bi, Da), flat-interface scalings with D_b = 1e-2: k_a = 1e-2 Da,
+    k_d = 1e-2 Bi; the rest as the static circle but FP32; 500 steps at
+    dt = 0.2 h^2 / D_b each."""
+    rng = np.random.default_rng(seed)
+    ns = rng.choice([128, 256, 512, 1024], size=count)
+    Rs = rng.uniform(0.15, 0.3, size=count)
+    Bi = 10.0 ** rng.uniform(-2, 2, size=count)
+    Da = 10.0 ** rng.uniform(-2, 2, size=count)
+    out = []
+    for i in range(count):
+        n = int(ns[i])
+        h = 1.0 / n
+        prob = dict(dim=2, n=(n, n), h=h, bc=((0, 0), (0, 0)), eos=0, eos_E=0.5, sigma0=1.0,
+                    gamma_inf=1.0, D_b=1e-2, D_s=1e-3, k_a=1e-2 * Da[i], k_d=1e-2 * Bi[i])
+        R = float(Rs[i])
+        out.append(dict(prob=prob, dt=0.2 * h * h / 1e-2, steps=500, precision=0, R=R,
+                        vof0=(lambda n=n, h=h, R=R: synth.vof_ball((n, n), h, (0.5, 0.5, 0), R, 2)),
+                        c0_const=1.0, gamma0=0.0))
+    return out
+
+
+def c4_adjoint(n=128):
+    """128^3 FP32 (FP64 oracle), static sphere R = 0.2 at the centre, walls in
+    x and y, open in z, sphere-frame Hadamard-Rybczynski flow with stream
+    V = -0.2 and viscosity ratio 0.01; nominal (k_a, k_d, D_b, D_s) =
+    (1, 1, 0.01, 0.001), target run at (1.3, 0.7, 0.012, 0.0008); Langmuir EoS
+    E = 0.3, Gamma0 = 0; c0 = 1 + 0.1 s(x) with s a seeded sum of 8 cosine
+    modes (seed 4); 500 steps, checkpoint every 50."""
+    h = 1.0 / n
+    prob = dict(dim=3, n=(n, n, n), h=h, bc=((0, 0), (0, 0), (2, 2)), eos=1, eos_E=0.3,
+                sigma0=1.0, gamma_inf=1.0, k_a=1.0, k_d=1.0, D_b=0.01, D_s=0.001)
+    dt = 5.97e-4 * (128.0 / n) ** 2
+    c = (0.5, 0.5, 0.5)
+    return dict(name="adjoint sphere %d^3 fp32" % n, prob=prob, precision=0, dt=dt, steps=500,
+                checkpoint=50, theta_nominal=(1.0, 1.0, 0.01, 0.001),
+                theta_target=(1.3, 0.7, 0.012, 0.0008),
+                vof0=lambda: synth.vof_ball((n, n, n), h, c, 0.2, 3),
+                u=lambda: synth.u_hadamard((n, n, n), h, c, 0.2, -0.2, 0.01),
+                c0=lambda: 1.0 + 0.1 * synth.smooth_modes((n, n, n), h, 4),
+                gamma0=0.0)

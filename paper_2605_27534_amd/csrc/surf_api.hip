@@ -1,0 +1,486 @@
+// surf_api.hip -- the C ABI of libsurf (declared in include/surf.h): argument
+// checks, workspace carving and kernel launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/surf.h"
+#include "surf_kernels.hpp"
+
+using namespace surf;
+
+struct surf_ctx {
+  surf_grid grid;
+  surf_params prm;
+  Grid g;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  double* state;
+  double* part;
+  void* chi[2];
+  void* g0;
+  int chi_cur;
+  bool has_chi;
+  long long ncell;
+  int tiles[3];
+  int nblk;
+  double dt;
+  // optional per-launch event timing
+  bool profile;
+  struct Mark { hipEvent_t a, b; int kind; };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+// tile shapes of the step kernel per (precision, dim)
+void tile_shape(int prec, int dim, int* t) {
+  if (dim == 2) { t[0] = 64; t[1] = 16; t[2] = 1; }
+  else if (prec == SURF_F32) { t[0] = 16; t[1] = 8; t[2] = 8; }
+  else { t[0] = 8; t[1] = 8; t[2] = 4; }
+}
+
+int check_grid_params(const surf_grid* gr, const surf_params* p) {
+  if (!gr || !p) return SURF_EINVAL;
+  if (gr->dim != 2 && gr->dim != 3) return SURF_EINVAL;
+  for (int d = 0; d < 3; ++d) {
+    if (d < gr->dim) {
+      if (gr->n[d] < 4) return SURF_EINVAL;  // mirror ghosts need 3 interior cells
+      for (int s = 0; s < 2; ++s)
+        if (gr->bc[d][s] < 0 || gr->bc[d][s] > 2) return SURF_EINVAL;
+      if ((gr->bc[d][0] == SURF_BC_PERIODIC) != (gr->bc[d][1] == SURF_BC_PERIODIC)) return SURF_EINVAL;
+    } else if (gr->n[d] != 1) {
+      return SURF_EINVAL;
+    }
+  }
+  if (!(gr->h > 0) || !std::isfinite(gr->h)) return SURF_EINVAL;
+  double ncell = (double)gr->n[0] * gr->n[1] * gr->n[2];
+  if (ncell > 4.0e9) return SURF_EINVAL;
+  if (p->precision != SURF_F32 && p->precision != SURF_F64) return SURF_EINVAL;
+  if (p->flux_form < 0 || p->flux_form > 1) return SURF_EINVAL;
+  if (p->kinetics < 0 || p->kinetics > 1) return SURF_EINVAL;
+  if (p->eos < 0 || p->eos > 2) return SURF_EINVAL;
+  if (!(p->eps > 0) || !(p->D_b >= 0) || !(p->D_s >= 0) || !(p->k_a >= 0) || !(p->k_d >= 0))
+    return SURF_EINVAL;
+  if (!(p->gamma_inf > 0)) return SURF_EINVAL;
+  if (!(p->dt > 0) || !std::isfinite(p->dt)) return SURF_EINVAL;
+  if (p->hj_iters_init < 0 || p->hj_iters_step < 0) return SURF_EINVAL;
+  return SURF_OK;
+}
+
+surf_params with_defaults(const surf_params* in, int dim) {
+  surf_params p = *in;
+  if (p.eta == 0) p.eta = 1e-12;
+  if (p.chi_max_eps == 0) p.chi_max_eps = 12.0;
+  if (p.cfl_adv == 0) p.cfl_adv = 0.5;
+  if (p.cfl_diff == 0) p.cfl_diff = 0.8;
+  if (p.hj_iters_step == 0) p.hj_iters_step = 8;
+  return p;
+}
+
+int hj_init_iters(const surf_ctx* c) {
+  if (c->prm.hj_iters_init > 0) return c->prm.hj_iters_init;
+  double chimax = c->prm.chi_max_eps * c->prm.eps;
+  double dtau = c->grid.h / c->grid.dim;
+  return 2 * (int)std::ceil(chimax / dtau - 1e-9);
+}
+
+template <typename R>
+Par<R> make_par(const surf_ctx* c) {
+  Par<R> p;
+  const surf_params& q = c->prm;
+  p.h = (R)c->grid.h;
+  p.inv_h = (R)(1.0 / c->grid.h);
+  p.eps = (R)q.eps;
+  p.inv_eps = (R)(1.0 / q.eps);
+  p.Db = (R)q.D_b;
+  p.Ds = (R)q.D_s;
+  p.ka = (R)q.k_a;
+  p.kd = (R)q.k_d;
+  p.ginf = (R)q.gamma_inf;
+  p.sigma0 = (R)q.sigma0;
+  p.E = (R)q.eos_E;
+  p.eta = (R)q.eta;
+  p.eta_eps = (R)(q.eta / q.eps);
+  p.chimax = (R)(q.chi_max_eps * q.eps);
+  p.form = q.flux_form;
+  p.kin = q.kinetics;
+  p.eos = q.eos;
+  p.bulk = q.bulk_enabled ? 1 : 0;
+  return p;
+}
+
+size_t esize(const surf_params* p) { return p->precision == SURF_F64 ? 8 : 4; }
+
+int nblocks_step(const surf_grid* gr, const surf_params* p, int* tiles) {
+  int t[3];
+  tile_shape(p->precision, gr->dim, t);
+  long long nb = 1;
+  for (int d = 0; d < 3; ++d) {
+    tiles[d] = d < gr->dim ? (gr->n[d] + t[d] - 1) / t[d] : 1;
+    nb *= tiles[d];
+  }
+  return (int)nb;
+}
+
+int status_of_launch() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SURF_OK : SURF_EDEVICE;
+}
+
+unsigned grid1d(long long n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
+
+hipEvent_t take_event(surf_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// brackets one launch with events when profiling is on
+struct Timed {
+  surf_ctx* c;
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timed(surf_ctx* cc, int k) : c(cc), kind(k) {
+    if (c->profile) {
+      a = take_event(c);
+      b = take_event(c);
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~Timed() {
+    if (c->profile && a && b) {
+      (void)hipEventRecord(b, c->stream);
+      c->marks.push_back({a, b, kind});
+    }
+  }
+};
+
+template <typename R>
+int geometry_impl(surf_ctx* c, const void* vof, int full) {
+  Par<R> p = make_par<R>(c);
+  long long n = c->ncell;
+  const R* f = (const R*)vof;
+  hipLaunchKernelGGL(k_pin<R>, dim3(grid1d(n)), dim3(BLOCK), 0, c->stream, c->g, p, f,
+                     (R*)c->g0, n);
+  int iters;
+  if (full) {
+    hipLaunchKernelGGL(k_chi0<R>, dim3(grid1d(n)), dim3(BLOCK), 0, c->stream, c->g, p, f,
+                       (R*)c->chi[c->chi_cur], n);
+    iters = hj_init_iters(c);
+  } else {
+    iters = c->prm.hj_iters_step;
+  }
+  R dtau = (R)(c->grid.h / c->grid.dim);
+  for (int it = 0; it < iters; ++it) {
+    int nxt = 1 - c->chi_cur;
+    Timed tm(c, 1);
+    hipLaunchKernelGGL(k_hj<R>, dim3(grid1d(n)), dim3(BLOCK), 0, c->stream, c->g, p,
+                       (const R*)c->chi[c->chi_cur], (const R*)c->g0, (R*)c->chi[nxt], dtau, n);
+    c->chi_cur = nxt;
+  }
+  c->has_chi = true;
+  return status_of_launch();
+}
+
+template <typename R, int DIM, int TX, int TY, int TZ>
+void launch_step(surf_ctx* c, const StepArgs<R>& a) {
+  hipLaunchKernelGGL((k_step<R, DIM, TX, TY, TZ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+}
+
+template <typename R>
+int step_impl(surf_ctx* c, const void* const* u, const void* F_in, const void* psi_in,
+              void* F_out, void* psi_out, void* sigma_out, double* totals) {
+  StepArgs<R> a;
+  a.g = c->g;
+  a.p = make_par<R>(c);
+  a.chi = (const R*)c->chi[c->chi_cur];
+  a.has_u = (u && u[0]) ? 1 : 0;
+  for (int d = 0; d < 3; ++d) a.u[d] = (a.has_u && d < c->grid.dim) ? (const R*)u[d] : nullptr;
+  a.F = (const R*)F_in;
+  a.psi = (const R*)psi_in;
+  a.Fo = (R*)F_out;
+  a.Po = (R*)psi_out;
+  a.sig = (R*)sigma_out;
+  a.part = c->part;
+  a.dt = (R)c->dt;
+  a.area_dt = (R)((c->grid.dim == 3 ? c->grid.h * c->grid.h : c->grid.h) * c->dt);
+  for (int d = 0; d < 3; ++d) a.tiles[d] = c->tiles[d];
+  {
+    Timed tm(c, 0);
+    if (c->grid.dim == 2) {
+      launch_step<R, 2, 64, 16, 1>(c, a);
+    } else {
+      if constexpr (sizeof(R) == 4) launch_step<R, 3, 16, 8, 8>(c, a);
+      else launch_step<R, 3, 8, 8, 4>(c, a);
+    }
+  }
+  FinalArgs f;
+  f.nblk = c->nblk;
+  f.dim = c->grid.dim;
+  f.bulk = c->prm.bulk_enabled ? 1 : 0;
+  f.form = c->prm.flux_form;
+  f.h = c->grid.h;
+  f.eps = c->prm.eps;
+  f.Dmax = f.bulk ? std::fmax(c->prm.D_b, c->prm.D_s) : c->prm.D_s;
+  f.ka = c->prm.k_a;
+  f.kd = c->prm.k_d;
+  f.ginf = c->prm.gamma_inf;
+  f.cfl_a = c->prm.cfl_adv;
+  f.cfl_d = c->prm.cfl_diff;
+  f.dt = c->dt;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, c->stream, f, (const double*)c->part,
+                     c->state, totals);
+  return status_of_launch();
+}
+
+template <typename R>
+int init_impl(surf_ctx* c, const void* c0, double c0_const, double gamma0, void* F, void* psi) {
+  Par<R> p = make_par<R>(c);
+  long long n = c->ncell;
+  hipLaunchKernelGGL(k_init<R>, dim3(grid1d(n)), dim3(BLOCK), 0, c->stream, c->g, p,
+                     (const R*)c->chi[c->chi_cur], (const R*)c0, (R)c0_const, (R)gamma0,
+                     c->prm.bulk_enabled ? (R*)F : (R*)nullptr, (R*)psi, n);
+  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, c->stream, c->state);
+  return status_of_launch();
+}
+
+template <typename R>
+int force_impl(surf_ctx* c, const void* sigma, void* const* force) {
+  Par<R> p = make_par<R>(c);
+  for (int d = 0; d < c->grid.dim; ++d) {
+    long long nf = c->ncell / c->grid.n[d] * (c->grid.n[d] + 1);
+    hipLaunchKernelGGL(k_force<R>, dim3(grid1d(nf)), dim3(BLOCK), 0, c->stream, c->g, p,
+                       (const R*)c->chi[c->chi_cur], (const R*)sigma, (R*)force[d], d, nf);
+  }
+  return status_of_launch();
+}
+
+bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char* surf_version(void) { return "surf 0.1 gfx950"; }
+
+const char* surf_strerror(int code) {
+  switch (code) {
+    case SURF_OK: return "ok";
+    case SURF_EINVAL: return "invalid argument";
+    case SURF_ENOMEM: return "workspace too small";
+    case SURF_EDEVICE: return "HIP runtime error";
+    case SURF_ESTATE: return "call-order violation";
+    case SURF_EUNSTABLE: return "time step above the stability bound";
+    default: return "unknown error";
+  }
+}
+
+int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_t* bytes) {
+  if (!bytes) return SURF_EINVAL;
+  int rc = check_grid_params(grid, params);
+  if (rc) return rc;
+  int tiles[3];
+  int nblk = nblocks_step(grid, params, tiles);
+  size_t n = (size_t)grid->n[0] * grid->n[1] * grid->n[2];
+  size_t es = esize(params);
+  size_t b = align_up(NSTATE * sizeof(double));
+  b += align_up((size_t)nblk * NPART * sizeof(double));
+  b += 3 * align_up(n * es);
+  *bytes = b;
+  return SURF_OK;
+}
+
+int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, void* workspace,
+              size_t ws_bytes, void* hip_stream) {
+  if (!out) return SURF_EINVAL;
+  *out = nullptr;
+  size_t need = 0;
+  int rc = surf_workspace_bytes(grid, params, &need);
+  if (rc) return rc;
+  if (!workspace || !aligned(workspace, ALIGN)) return SURF_EINVAL;
+  if (ws_bytes < need) return SURF_ENOMEM;
+  surf_ctx* c = new (std::nothrow) surf_ctx();
+  if (!c) return SURF_EINVAL;
+  c->grid = *grid;
+  c->prm = with_defaults(params, grid->dim);
+  c->g.dim = grid->dim;
+  for (int d = 0; d < 3; ++d) {
+    c->g.n[d] = grid->n[d];
+    c->g.bc[d][0] = d < grid->dim ? grid->bc[d][0] : 0;
+    c->g.bc[d][1] = d < grid->dim ? grid->bc[d][1] : 0;
+  }
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (char*)workspace;
+  c->ws_bytes = ws_bytes;
+  c->ncell = (long long)grid->n[0] * grid->n[1] * grid->n[2];
+  c->nblk = nblocks_step(grid, params, c->tiles);
+  size_t es = esize(params);
+  char* p = c->ws;
+  c->state = (double*)p;
+  p += align_up(NSTATE * sizeof(double));
+  c->part = (double*)p;
+  p += align_up((size_t)c->nblk * NPART * sizeof(double));
+  c->chi[0] = p;
+  p += align_up(c->ncell * es);
+  c->chi[1] = p;
+  p += align_up(c->ncell * es);
+  c->g0 = p;
+  c->chi_cur = 0;
+  c->has_chi = false;
+  c->dt = params->dt;
+  *out = c;
+  return SURF_OK;
+}
+
+int surf_set_geometry(surf_ctx* c, const void* vof, int full_rebuild) {
+  if (!c || !vof) return SURF_EINVAL;
+  if (!full_rebuild && !c->has_chi) return SURF_ESTATE;
+  if (c->prm.precision == SURF_F64) return geometry_impl<double>(c, vof, full_rebuild);
+  return geometry_impl<float>(c, vof, full_rebuild);
+}
+
+int surf_set_levelset(surf_ctx* c, const void* chi) {
+  if (!c || !chi) return SURF_EINVAL;
+  size_t bytes = (size_t)c->ncell * esize(&c->prm);
+  if (hipMemcpyAsync(c->chi[c->chi_cur], chi, bytes, hipMemcpyDeviceToDevice, c->stream) !=
+      hipSuccess)
+    return SURF_EDEVICE;
+  c->has_chi = true;
+  return SURF_OK;
+}
+
+int surf_get_levelset(surf_ctx* c, void* chi_out) {
+  if (!c || !chi_out) return SURF_EINVAL;
+  if (!c->has_chi) return SURF_ESTATE;
+  size_t bytes = (size_t)c->ncell * esize(&c->prm);
+  if (hipMemcpyAsync(chi_out, c->chi[c->chi_cur], bytes, hipMemcpyDeviceToDevice, c->stream) !=
+      hipSuccess)
+    return SURF_EDEVICE;
+  return SURF_OK;
+}
+
+int surf_init_state(surf_ctx* c, const void* c0, double c0_const, double gamma0, void* F_out,
+                    void* psi_out) {
+  if (!c || !psi_out) return SURF_EINVAL;
+  if (c->prm.bulk_enabled && !F_out) return SURF_EINVAL;
+  if (!c->has_chi) return SURF_ESTATE;
+  if (c->prm.precision == SURF_F64) return init_impl<double>(c, c0, c0_const, gamma0, F_out, psi_out);
+  return init_impl<float>(c, c0, c0_const, gamma0, F_out, psi_out);
+}
+
+int surf_step(surf_ctx* c, const void* vof_next, const void* const* u, const void* F_in,
+              const void* psi_in, void* F_out, void* psi_out, void* sigma_out,
+              double* totals_dev) {
+  if (!c || !psi_in || !psi_out) return SURF_EINVAL;
+  bool bulk = c->prm.bulk_enabled != 0;
+  if (bulk && (!F_in || !F_out)) return SURF_EINVAL;
+  if (psi_in == psi_out || (bulk && (F_in == F_out || F_in == psi_out || psi_in == F_out)))
+    return SURF_EINVAL;
+  if (u && u[0])
+    for (int d = 0; d < c->grid.dim; ++d)
+      if (!u[d]) return SURF_EINVAL;
+  size_t es = esize(&c->prm);
+  if (!aligned(psi_in, es) || !aligned(psi_out, es)) return SURF_EINVAL;
+  if (vof_next) {
+    if (!c->has_chi) return SURF_ESTATE;
+    int rc = surf_set_geometry(c, vof_next, 0);
+    if (rc) return rc;
+  }
+  if (!c->has_chi) return SURF_ESTATE;
+  if (c->prm.precision == SURF_F64)
+    return step_impl<double>(c, u, F_in, psi_in, F_out, psi_out, sigma_out, totals_dev);
+  return step_impl<float>(c, u, F_in, psi_in, F_out, psi_out, sigma_out, totals_dev);
+}
+
+int surf_force(surf_ctx* c, const void* sigma, void* const* force) {
+  if (!c || !sigma || !force) return SURF_EINVAL;
+  for (int d = 0; d < c->grid.dim; ++d)
+    if (!force[d]) return SURF_EINVAL;
+  if (!c->has_chi) return SURF_ESTATE;
+  if (c->prm.precision == SURF_F64) return force_impl<double>(c, sigma, force);
+  return force_impl<float>(c, sigma, force);
+}
+
+int surf_set_dt(surf_ctx* c, double dt) {
+  if (!c || !(dt > 0) || !std::isfinite(dt)) return SURF_EINVAL;
+  c->dt = dt;
+  return SURF_OK;
+}
+
+int surf_get_status(surf_ctx* c, uint32_t* bits) {
+  if (!c || !bits) return SURF_EINVAL;
+  double s = 0;
+  if (hipMemcpyAsync(&s, c->state + S_STATUS, sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+      hipSuccess)
+    return SURF_EDEVICE;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return SURF_EDEVICE;
+  *bits = (uint32_t)s;
+  return SURF_OK;
+}
+
+int surf_clear_status(surf_ctx* c) {
+  if (!c) return SURF_EINVAL;
+  static const double zero = 0.0;
+  if (hipMemcpyAsync(c->state + S_STATUS, &zero, sizeof(double), hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess)
+    return SURF_EDEVICE;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return SURF_EDEVICE;
+  return SURF_OK;
+}
+
+int surf_profile_enable(surf_ctx* c, int enable) {
+  if (!c) return SURF_EINVAL;
+  c->profile = enable != 0;
+  return SURF_OK;
+}
+
+int surf_profile_read(surf_ctx* c, double* step_ms, int64_t* step_n, double* geom_ms,
+                      int64_t* geom_n) {
+  if (!c) return SURF_EINVAL;
+  double ms[2] = {0.0, 0.0};
+  int64_t cnt[2] = {0, 0};
+  int rc = SURF_OK;
+  for (auto& m : c->marks) {
+    float t = 0.f;
+    if (hipEventSynchronize(m.b) != hipSuccess || hipEventElapsedTime(&t, m.a, m.b) != hipSuccess)
+      rc = SURF_EDEVICE;
+    ms[m.kind] += t;
+    cnt[m.kind] += 1;
+    c->pool.push_back(m.a);
+    c->pool.push_back(m.b);
+  }
+  c->marks.clear();
+  if (step_ms) *step_ms = ms[0];
+  if (step_n) *step_n = cnt[0];
+  if (geom_ms) *geom_ms = ms[1];
+  if (geom_n) *geom_n = cnt[1];
+  return rc;
+}
+
+int surf_destroy(surf_ctx* c) {
+  if (!c) return SURF_OK;
+  for (auto& m : c->marks) {
+    (void)hipEventDestroy(m.a);
+    (void)hipEventDestroy(m.b);
+  }
+  for (auto e : c->pool) (void)hipEventDestroy(e);
+  delete c;
+  return SURF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+// surf_common.hpp -- device-side building blocks shared by the libsurf
+// kernels: problem descriptors, index/ghost mapping, the phase-field maps,
+// the equation of state and wave64 reductions.  gfx950 only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace surf {
+
+enum { BC_WALL = 0, BC_PERIODIC = 1, BC_OPEN = 2 };
+enum { FORM_W = 0, FORM_P = 1 };
+enum { KIN_LANGMUIR = 0, KIN_HENRY = 1 };
+enum { EOS_LIN = 0, EOS_LANG = 1, EOS_TANH = 2 };
+
+// per-workgroup reduction record of the step kernel
+enum {
+  P_SUM_F = 0, P_SUM_PSI, P_SUM_DELTA, P_SUM_SIGDELTA, P_OUTFLOW,
+  P_MAX_USUM, P_MAX_C, P_MIN_F, P_MIN_PSI, P_NBAD, NPART
+};
+
+// device-resident running state (doubles) in the workspace
+enum { S_TIME = 0, S_OUTCUM = 1, S_STEPS = 2, S_STATUS = 3, NSTATE = 8 };
+
+struct Grid {
+  int dim;
+  int n[3];
+  int bc[3][2];
+};
+
+template <typename R>
+struct Par {
+  R h, inv_h, eps, inv_eps, Db, Ds, ka, kd, ginf, sigma0, E, eta, eta_eps, chimax;
+  int form, kin, eos, bulk;
+};
+
+// Cell coordinate q along axis d mapped into the box: periodic axes wrap,
+// other boundaries mirror about the boundary face (zero-gradient ghost).
+// The result is clamped into [0, n) so that halo cells of ragged tiles, which
+// are never consumed, still address memory inside the field.
+__device__ __forceinline__ int map_axis(int q, int n, int lo_bc, int hi_bc) {
+  if (q < 0) {
+    q = (lo_bc == BC_PERIODIC) ? q + n : -1 - q;
+  } else if (q >= n) {
+    q = (hi_bc == BC_PERIODIC) ? q - n : 2 * n - 1 - q;
+  }
+  q = q < 0 ? 0 : q;
+  q = q >= n ? n - 1 : q;
+  return q;
+}
+
+__device__ __forceinline__ long long cell_index(const Grid& g, int i, int j, int k) {
+  return (long long)i + (long long)g.n[0] * ((long long)j + (long long)g.n[1] * k);
+}
+
+// face index along d: the d-coordinate runs 0..n_d
+__device__ __forceinline__ long long face_index(const Grid& g, int d, int i, int j, int k) {
+  long long mx = g.n[0] + (d == 0), my = g.n[1] + (d == 1);
+  return (long long)i + mx * ((long long)j + my * k);
+}
+
+template <typename R> __device__ __forceinline__ R rexp(R x);
+template <> __device__ __forceinline__ float rexp<float>(float x) { return expf(x); }
+template <> __device__ __forceinline__ double rexp<double>(double x) { return exp(x); }
+
+template <typename R> __device__ __forceinline__ R rlog(R x);
+template <> __device__ __forceinline__ float rlog<float>(float x) { return logf(x); }
+template <> __device__ __forceinline__ double rlog<double>(double x) { return log(x); }
+
+template <typename R> __device__ __forceinline__ R rtanh(R x);
+template <> __device__ __forceinline__ float rtanh<float>(float x) { return tanhf(x); }
+template <> __device__ __forceinline__ double rtanh<double>(double x) { return tanh(x); }
+
+template <typename R> __device__ __forceinline__ R rsqrt_(R x);
+template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return sqrtf(x); }
+template <> __device__ __forceinline__ double rsqrt_<double>(double x) { return sqrt(x); }
+
+// phi = 1/(1+e^{chi/eps}) (0 in fluid 1, 1 in the liquid), omega = 1 - phi
+// evaluated without cancellation, delta = phi omega / eps.
+template <typename R>
+__device__ __forceinline__ void phase(R chi, const Par<R>& p, R& phi, R& om, R& del) {
+  R e = rexp<R>(chi * p.inv_eps);
+  phi = R(1) / (R(1) + e);
+  om = e * phi;
+  del = phi * om * p.inv_eps;
+}
+
+template <typename R>
+__device__ __forceinline__ R eos(R G, const Par<R>& p) {
+  R x = G / p.ginf;
+  if (p.eos == EOS_LIN) return p.sigma0 * (R(1) - p.E * x);
+  if (p.eos == EOS_LANG) {
+    x = x < R(0) ? R(0) : x;
+    x = x > R(1) - R(1e-6) ? R(1) - R(1e-6) : x;
+    return p.sigma0 * (R(1) + p.E * rlog<R>(R(1) - x));
+  }
+  return p.sigma0 * (R(1) - rtanh<R>(p.E * x));
+}
+
+// minmod of two one-sided differences; the sign test avoids the underflow
+// of a*b for tiny differences in FP32
+template <typename R>
+__device__ __forceinline__ R minmod(R a, R b) {
+  R m = fabs(a) < fabs(b) ? a : b;
+  bool same = (a > R(0) && b > R(0)) || (a < R(0) && b < R(0));
+  return same ? m : R(0);
+}
+
+// wave64 reductions (gfx950 wavefronts are 64 lanes)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+}  // namespace surf

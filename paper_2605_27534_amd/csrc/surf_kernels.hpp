@@ -1,0 +1,571 @@
+// surf_kernels.hpp -- HIP kernels of libsurf for gfx950.
+//
+//   k_pin      VoF -> redistancing pin data (section 2.5)
+//   k_chi0     initial level set chi0 = (f - 1/2) h
+//   k_hj       one Godunov Hamilton-Jacobi sweep (section 2.5)
+//   k_step     the fused transport step: advection (section 3.1 substep 1),
+//              confinement + diffusion + exchange (substep 2, sections 2.6,
+//              3.2, Appendices A and C), equation of state (sections 2.3, 5,
+//              6) and per-workgroup FP64 partial reductions
+//   k_finalize deterministic reduction of the partials -> totals, status
+//   k_init     F = c0 phi, psi = gamma0 delta
+//   k_force    Marangoni face force (section 2.4)
+#pragma once
+#include "surf_common.hpp"
+
+namespace surf {
+
+constexpr int BLOCK = 256;
+
+// ---------------------------------------------------------------- geometry
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_chi0(Grid g, Par<R> p, const R* __restrict__ vof,
+                                                R* __restrict__ chi, long long ncell) {
+  long long c = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (c >= ncell) return;
+  chi[c] = (vof[c] - R(0.5)) * p.h;
+}
+
+// Pin data: cells whose face neighbour has chi0 of the opposite (or zero)
+// sign are pinned to the subcell distance h chi0 / Delta (Russo-Smereka);
+// the others carry only the sign of chi0, stored as +-infinity.
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_pin(Grid g, Par<R> p, const R* __restrict__ vof,
+                                               R* __restrict__ g0, long long ncell) {
+  long long c = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (c >= ncell) return;
+  int i = (int)(c % g.n[0]);
+  int j = (int)((c / g.n[0]) % g.n[1]);
+  int k = (int)(c / ((long long)g.n[0] * g.n[1]));
+  int xyz[3] = {i, j, k};
+  R x0 = (vof[c] - R(0.5)) * p.h;
+  bool cut = false;
+  R jump = R(0), grad2 = R(0);
+  for (int d = 0; d < g.dim; ++d) {
+    int a[3] = {i, j, k}, b[3] = {i, j, k};
+    a[d] = map_axis(xyz[d] - 1, g.n[d], g.bc[d][0], g.bc[d][1]);
+    b[d] = map_axis(xyz[d] + 1, g.n[d], g.bc[d][0], g.bc[d][1]);
+    R xm = (vof[cell_index(g, a[0], a[1], a[2])] - R(0.5)) * p.h;
+    R xp = (vof[cell_index(g, b[0], b[1], b[2])] - R(0.5)) * p.h;
+    cut = cut || (x0 * xm <= R(0)) || (x0 * xp <= R(0));
+    jump = fmax(jump, fabs(xm - x0));
+    jump = fmax(jump, fabs(xp - x0));
+    R cd = R(0.5) * (xp - xm);
+    grad2 += cd * cd;
+  }
+  R Delta = fmax(fmax(rsqrt_<R>(grad2), jump), R(1e-30) * p.h);
+  R inf = R(INFINITY);
+  g0[c] = cut ? p.h * x0 / Delta : (x0 > R(0) ? inf : -inf);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_hj(Grid g, Par<R> p, const R* __restrict__ src,
+                                              const R* __restrict__ g0, R* __restrict__ dst,
+                                              R dtau, long long ncell) {
+  long long c = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (c >= ncell) return;
+  R gv = g0[c];
+  R v;
+  if (fabs(gv) < R(INFINITY)) {
+    v = gv;
+  } else {
+    int i = (int)(c % g.n[0]);
+    int j = (int)((c / g.n[0]) % g.n[1]);
+    int k = (int)(c / ((long long)g.n[0] * g.n[1]));
+    int xyz[3] = {i, j, k};
+    R x = src[c];
+    R G2 = R(0);
+    bool pos = gv > R(0);
+    for (int d = 0; d < g.dim; ++d) {
+      int a[3] = {i, j, k}, b[3] = {i, j, k};
+      a[d] = map_axis(xyz[d] - 1, g.n[d], g.bc[d][0], g.bc[d][1]);
+      b[d] = map_axis(xyz[d] + 1, g.n[d], g.bc[d][0], g.bc[d][1]);
+      R bw = (x - src[cell_index(g, a[0], a[1], a[2])]) * p.inv_h;
+      R fw = (src[cell_index(g, b[0], b[1], b[2])] - x) * p.inv_h;
+      R t1, t2;
+      if (pos) {
+        t1 = bw > R(0) ? bw * bw : R(0);
+        t2 = fw < R(0) ? fw * fw : R(0);
+      } else {
+        t1 = bw < R(0) ? bw * bw : R(0);
+        t2 = fw > R(0) ? fw * fw : R(0);
+      }
+      G2 += t1 > t2 ? t1 : t2;
+    }
+    R s = pos ? R(1) : R(-1);
+    v = x - dtau * s * (rsqrt_<R>(G2) - R(1));
+  }
+  v = v > p.chimax ? p.chimax : v;
+  v = v < -p.chimax ? -p.chimax : v;
+  dst[c] = v;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_init(Grid g, Par<R> p, const R* __restrict__ chi,
+                                                const R* __restrict__ c0, R c0_const, R gamma0,
+                                                R* __restrict__ F, R* __restrict__ psi,
+                                                long long ncell) {
+  long long c = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (c >= ncell) return;
+  R ph, om, de;
+  phase<R>(chi[c], p, ph, om, de);
+  if (F) F[c] = (c0 ? c0[c] : c0_const) * ph;
+  psi[c] = gamma0 * de;
+}
+
+// ---------------------------------------------------------------- the step
+template <typename R>
+struct StepArgs {
+  Grid g;
+  Par<R> p;
+  const R* chi;
+  const R* u[3];
+  const R* F;
+  const R* psi;
+  R* Fo;
+  R* Po;
+  R* sig;
+  double* part;
+  R dt;
+  R area_dt;   // h^(dim-1) * dt, for the open-boundary budget
+  int has_u;
+  int tiles[3];
+};
+
+// Advective flux u xi_f through a face (section 3.1): xi_f is the upwind
+// value plus the minmod-limited slope carried to the half-step foot of the
+// characteristic, xi_U +- (1 - |u| dt/h)/2 minmod(dxi-, dxi+).
+template <typename R>
+__device__ __forceinline__ R adv_flux(R uf, R xLm, R xL, R xR, R xRp, R cfl_scale) {
+  R c = R(0.5) * (R(1) - fabs(uf) * cfl_scale);
+  R xf = uf > R(0) ? xL + c * minmod<R>(xL - xLm, xR - xL) : xR - c * minmod<R>(xR - xL, xRp - xR);
+  return uf * xf;
+}
+
+// Paper-form anti-diffusion coefficient of a cell along d (section 3.2,
+// Appendix C): B_F = -D_b (1-phi)/eps n_d, B_psi = -D_s (1-2 phi)/eps n_d with
+// n = -grad chi/|grad chi| from centred differences read from global memory.
+template <typename R>
+__device__ R paper_B(const Grid& g, const Par<R>& p, const R* __restrict__ chi, const int* m,
+                     int d, bool bulk_field) {
+  R grad[3] = {R(0), R(0), R(0)};
+  R nrm = R(0);
+  for (int e = 0; e < g.dim; ++e) {
+    int a[3] = {m[0], m[1], m[2]}, b[3] = {m[0], m[1], m[2]};
+    a[e] = map_axis(m[e] - 1, g.n[e], g.bc[e][0], g.bc[e][1]);
+    b[e] = map_axis(m[e] + 1, g.n[e], g.bc[e][0], g.bc[e][1]);
+    grad[e] = (chi[cell_index(g, b[0], b[1], b[2])] - chi[cell_index(g, a[0], a[1], a[2])]) *
+              (R(0.5) * p.inv_h);
+    nrm += grad[e] * grad[e];
+  }
+  nrm = rsqrt_<R>(nrm);
+  nrm = nrm < R(1e-6) ? R(1e-6) : nrm;
+  R nd = -grad[d] / nrm;
+  R ph, om, de;
+  phase<R>(chi[cell_index(g, m[0], m[1], m[2])], p, ph, om, de);
+  R w = bulk_field ? om : (om - ph);
+  return -(bulk_field ? p.Db : p.Ds) * w * p.inv_eps * nd;
+}
+
+template <typename R, int NT>
+__device__ __forceinline__ void block_partials(double* v, double* out) {
+  __shared__ double red[NT / 64][NPART];
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int s = 0; s < NPART; ++s) {
+    double x = v[s];
+    if (s == P_MAX_USUM || s == P_MAX_C) x = wave_max(x);
+    else if (s == P_MIN_F || s == P_MIN_PSI) x = wave_min(x);
+    else x = wave_sum(x);
+    if (lane == 0) red[w][s] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < NPART) {
+    int s = threadIdx.x;
+    double x = red[0][s];
+    for (int q = 1; q < NT / 64; ++q) {
+      double y = red[q][s];
+      if (s == P_MAX_USUM || s == P_MAX_C) x = fmax(x, y);
+      else if (s == P_MIN_F || s == P_MIN_PSI) x = fmin(x, y);
+      else x += y;
+    }
+    out[s] = x;
+  }
+}
+
+// Fused step on one tile of TX x TY (x TZ) cells.  LDS holds the old state
+// with a 3-cell halo (region A), then the advected state, phi and delta on a
+// 1-cell halo (region C); region A is reused for c* = F*/(phi+eta) and
+// Gamma* = psi*/(delta + eta/eps).
+template <typename R, int DIM, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(BLOCK) k_step(StepArgs<R> a) {
+  constexpr int TZ_ = DIM == 3 ? TZ : 1;
+  constexpr int EX3 = TX + 6, EY3 = TY + 6, EZ3 = DIM == 3 ? TZ + 6 : 1;
+  constexpr int EX1 = TX + 2, EY1 = TY + 2, EZ1 = DIM == 3 ? TZ + 2 : 1;
+  constexpr int N3 = EX3 * EY3 * EZ3, N1 = EX1 * EY1 * EZ1, NTILE = TX * TY * TZ_;
+  static_assert(2 * N1 <= 2 * N3, "region reuse");
+  __shared__ R sA[2 * N3];
+  __shared__ R sC[4 * N1];
+  R* sF1 = sC;
+  R* sP1 = sC + N1;
+  R* sPhi = sC + 2 * N1;
+  R* sDel = sC + 3 * N1;
+
+  const Grid& g = a.g;
+  const Par<R>& p = a.p;
+  const bool bulk = p.bulk != 0;
+  int b = blockIdx.x;
+  int bx = b % a.tiles[0];
+  int by = (b / a.tiles[0]) % a.tiles[1];
+  int bz = b / (a.tiles[0] * a.tiles[1]);
+  int org[3] = {bx * TX, by * TY, DIM == 3 ? bz * TZ : 0};
+  int tid = threadIdx.x;
+
+  double acc[NPART];
+#pragma unroll
+  for (int s = 0; s < NPART; ++s) acc[s] = 0.0;
+  acc[P_MAX_USUM] = 0.0;
+  acc[P_MAX_C] = -INFINITY;
+  acc[P_MIN_F] = INFINITY;
+  acc[P_MIN_PSI] = INFINITY;
+
+  // phase 1: old state into LDS
+  if (a.has_u) {
+    for (int l = tid; l < N3; l += BLOCK) {
+      int lx = l % EX3, ly = (l / EX3) % EY3, lz = l / (EX3 * EY3);
+      int mx = map_axis(org[0] + lx - 3, g.n[0], g.bc[0][0], g.bc[0][1]);
+      int my = map_axis(org[1] + ly - 3, g.n[1], g.bc[1][0], g.bc[1][1]);
+      int mz = DIM == 3 ? map_axis(org[2] + lz - 3, g.n[2], g.bc[2][0], g.bc[2][1]) : 0;
+      long long c = cell_index(g, mx, my, mz);
+      sA[l] = bulk ? a.F[c] : R(0);
+      sA[N3 + l] = a.psi[c];
+    }
+  } else {
+    for (int l = tid; l < N1; l += BLOCK) {
+      int lx = l % EX1, ly = (l / EX1) % EY1, lz = l / (EX1 * EY1);
+      int mx = map_axis(org[0] + lx - 1, g.n[0], g.bc[0][0], g.bc[0][1]);
+      int my = map_axis(org[1] + ly - 1, g.n[1], g.bc[1][0], g.bc[1][1]);
+      int mz = DIM == 3 ? map_axis(org[2] + lz - 1, g.n[2], g.bc[2][0], g.bc[2][1]) : 0;
+      long long c = cell_index(g, mx, my, mz);
+      sF1[l] = bulk ? a.F[c] : R(0);
+      sP1[l] = a.psi[c];
+    }
+  }
+  __syncthreads();
+
+  // phase 2: advected state xi* and the phase field on the 1-cell halo
+  const int s3[3] = {1, EX3, EX3 * EY3};
+  const R cfl = a.dt * p.inv_h;
+  for (int l = tid; l < N1; l += BLOCK) {
+    int l1[3] = {l % EX1, (l / EX1) % EY1, l / (EX1 * EY1)};
+    int gc[3], m[3];
+    bool ghost = false, inside = true;
+    for (int d = 0; d < 3; ++d) {
+      if (d < DIM) {
+        gc[d] = org[d] + l1[d] - 1;
+        m[d] = map_axis(gc[d], g.n[d], g.bc[d][0], g.bc[d][1]);
+        bool lo_out = gc[d] < 0, hi_out = gc[d] >= g.n[d];
+        if ((lo_out && g.bc[d][0] != BC_PERIODIC) || (hi_out && g.bc[d][1] != BC_PERIODIC)) ghost = true;
+        if (lo_out || hi_out) inside = false;
+      } else {
+        gc[d] = 0;
+        m[d] = 0;
+      }
+    }
+    long long cm = cell_index(g, m[0], m[1], m[2]);
+    R ph, om, de;
+    phase<R>(a.chi[cm], p, ph, om, de);
+    sPhi[l] = ph;
+    sDel[l] = de;
+    bool interior = inside && l1[0] >= 1 && l1[0] <= TX && l1[1] >= 1 && l1[1] <= TY &&
+                    (DIM == 2 || (l1[2] >= 1 && l1[2] <= TZ));
+    if (a.has_u) {
+      int l3 = (l1[0] + 2) + EX3 * ((l1[1] + 2) + EY3 * (DIM == 3 ? l1[2] + 2 : 0));
+      R divF = R(0), divP = R(0);
+      double usum = 0.0;
+      if (!ghost) {
+        for (int d = 0; d < DIM; ++d) {
+          int st = s3[d];
+          // face indices: lo face of the mapped cell, hi face (wrapped when periodic)
+          int flo[3] = {m[0], m[1], m[2]}, fhi[3] = {m[0], m[1], m[2]};
+          fhi[d] = m[d] + 1;
+          if (fhi[d] == g.n[d] && g.bc[d][1] == BC_PERIODIC) fhi[d] = 0;
+          R ulo = a.u[d][face_index(g, d, flo[0], flo[1], flo[2])];
+          R uhi = a.u[d][face_index(g, d, fhi[0], fhi[1], fhi[2])];
+          bool blo = gc[d] == 0 && g.bc[d][0] != BC_PERIODIC;
+          bool bhi = gc[d] == g.n[d] - 1 && g.bc[d][1] != BC_PERIODIC;
+          for (int f = 0; f < 2; ++f) {
+            if (f == 0 && !bulk) continue;
+            const R* x = sA + f * N3;
+            R Flo, Fhi;
+            if (blo) {
+              Flo = g.bc[d][0] == BC_OPEN ? ulo * x[l3] : R(0);
+            } else {
+              Flo = adv_flux<R>(ulo, x[l3 - 2 * st], x[l3 - st], x[l3], x[l3 + st], cfl);
+            }
+            if (bhi) {
+              Fhi = g.bc[d][1] == BC_OPEN ? uhi * x[l3] : R(0);
+            } else {
+              Fhi = adv_flux<R>(uhi, x[l3 - st], x[l3], x[l3 + st], x[l3 + 2 * st], cfl);
+            }
+            if (f == 0) divF += Fhi - Flo; else divP += Fhi - Flo;
+            if (interior) {
+              if (blo && g.bc[d][0] == BC_OPEN) acc[P_OUTFLOW] -= (double)(a.area_dt * Flo);
+              if (bhi && g.bc[d][1] == BC_OPEN) acc[P_OUTFLOW] += (double)(a.area_dt * Fhi);
+            }
+          }
+          if (interior) {
+            int fl[3] = {m[0], m[1], m[2]};
+            fl[d] = m[d] + 1;  // literal upper face for the cell-mean velocity
+            R uup = a.u[d][face_index(g, d, fl[0], fl[1], fl[2])];
+            usum += fabs((double)(R(0.5) * (ulo + uup)));
+          }
+        }
+        if (interior) acc[P_MAX_USUM] = fmax(acc[P_MAX_USUM], usum);
+        sF1[l] = bulk ? sA[l3] - cfl * divF : R(0);
+        sP1[l] = sA[N3 + l3] - cfl * divP;
+      } else {
+        sF1[l] = R(0);
+        sP1[l] = R(0);
+      }
+    }
+  }
+  __syncthreads();
+
+  // phase 3: c* and Gamma* (weighted form) into region A
+  R* sc = sA;
+  R* sG = sA + N1;
+  if (p.form == FORM_W) {
+    for (int l = tid; l < N1; l += BLOCK) {
+      sc[l] = sF1[l] / (sPhi[l] + p.eta);
+      sG[l] = sP1[l] / (sDel[l] + p.eta_eps);
+    }
+  }
+  __syncthreads();
+
+  // phase 4: substep 2 on the tile interior, EoS, outputs, partial sums
+  const int s1[3] = {1, EX1, EX1 * EY1};
+  for (int t = tid; t < NTILE; t += BLOCK) {
+    int it[3] = {t % TX, (t / TX) % TY, t / (TX * TY)};
+    int gc[3];
+    bool inside = true;
+    for (int d = 0; d < 3; ++d) {
+      gc[d] = d < DIM ? org[d] + it[d] : 0;
+      if (d < DIM && gc[d] >= g.n[d]) inside = false;
+    }
+    if (!inside) continue;
+    int l = (it[0] + 1) + EX1 * ((it[1] + 1) + EY1 * (DIM == 3 ? it[2] + 1 : 0));
+    R divF = R(0), divP = R(0);
+    for (int d = 0; d < DIM; ++d) {
+      int st = s1[d];
+      bool blo = gc[d] == 0 && g.bc[d][0] != BC_PERIODIC;
+      bool bhi = gc[d] == g.n[d] - 1 && g.bc[d][1] != BC_PERIODIC;
+      R FloF = R(0), FhiF = R(0), FloP = R(0), FhiP = R(0);
+      if (p.form == FORM_W) {
+        if (!blo) {
+          FloF = p.Db * R(0.5) * (sPhi[l - st] + sPhi[l]) * (sc[l] - sc[l - st]) * p.inv_h;
+          FloP = p.Ds * R(0.5) * (sDel[l - st] + sDel[l]) * (sG[l] - sG[l - st]) * p.inv_h;
+        }
+        if (!bhi) {
+          FhiF = p.Db * R(0.5) * (sPhi[l] + sPhi[l + st]) * (sc[l + st] - sc[l]) * p.inv_h;
+          FhiP = p.Ds * R(0.5) * (sDel[l] + sDel[l + st]) * (sG[l + st] - sG[l]) * p.inv_h;
+        }
+      } else {
+        int m0[3], mm[3], mp[3];
+        for (int e = 0; e < 3; ++e) {
+          m0[e] = e < DIM ? gc[e] : 0;
+          mm[e] = m0[e];
+          mp[e] = m0[e];
+        }
+        mm[d] = map_axis(gc[d] - 1, g.n[d], g.bc[d][0], g.bc[d][1]);
+        mp[d] = map_axis(gc[d] + 1, g.n[d], g.bc[d][0], g.bc[d][1]);
+        for (int f = 0; f < 2; ++f) {
+          if (f == 0 && !bulk) continue;
+          const R* x = f == 0 ? sF1 : sP1;
+          R D = f == 0 ? p.Db : p.Ds;
+          R Bc = paper_B<R>(g, p, a.chi, m0, d, f == 0);
+          R lo = R(0), hi = R(0);
+          if (!blo) {
+            R Bm = paper_B<R>(g, p, a.chi, mm, d, f == 0);
+            R Bf = R(0.5) * (Bm + Bc);
+            lo = D * (x[l] - x[l - st]) * p.inv_h + Bf * (Bf < R(0) ? x[l - st] : x[l]);
+          }
+          if (!bhi) {
+            R Bp = paper_B<R>(g, p, a.chi, mp, d, f == 0);
+            R Bf = R(0.5) * (Bc + Bp);
+            hi = D * (x[l + st] - x[l]) * p.inv_h + Bf * (Bf < R(0) ? x[l] : x[l + st]);
+          }
+          if (f == 0) { FloF = lo; FhiF = hi; } else { FloP = lo; FhiP = hi; }
+        }
+      }
+      divF += (FhiF - FloF) * p.inv_h;
+      divP += (FhiP - FloP) * p.inv_h;
+    }
+    R Fs = sF1[l], Ps = sP1[l], ph = sPhi[l], de = sDel[l];
+    R cs = Fs / (ph + p.eta);
+    R q = R(0);
+    if (bulk) {
+      q = p.kin == KIN_LANGMUIR ? p.ka * cs * (p.ginf * de - Ps) - p.kd * Ps
+                                : p.ka * cs * p.ginf * de - p.kd * Ps;
+    }
+    R Fn = bulk ? Fs + a.dt * (divF - q) : R(0);
+    R Pn = Ps + a.dt * (divP + q);
+    R G = Pn / (de + p.eta_eps);
+    R sg = eos<R>(G, p);
+    long long c = cell_index(g, gc[0], gc[1], gc[2]);
+    if (bulk) a.Fo[c] = Fn;
+    a.Po[c] = Pn;
+    if (a.sig) a.sig[c] = sg;
+    acc[P_SUM_F] += (double)Fn;
+    acc[P_SUM_PSI] += (double)Pn;
+    acc[P_SUM_DELTA] += (double)de;
+    acc[P_SUM_SIGDELTA] += (double)sg * (double)de;
+    if (bulk) {
+      acc[P_MAX_C] = fmax(acc[P_MAX_C], (double)(Fn / (ph + p.eta)));
+      acc[P_MIN_F] = fmin(acc[P_MIN_F], (double)Fn);
+    }
+    acc[P_MIN_PSI] = fmin(acc[P_MIN_PSI], (double)Pn);
+    bool bad = !isfinite(Pn) || !isfinite(sg) || (bulk && !isfinite(Fn));
+    acc[P_NBAD] += bad ? 1.0 : 0.0;
+  }
+  block_partials<R, BLOCK>(acc, a.part + (long long)blockIdx.x * NPART);
+}
+
+// ---------------------------------------------------------------- finalize
+struct FinalArgs {
+  int nblk;
+  int dim, bulk, form;
+  double h, eps, Dmax, ka, kd, ginf, cfl_a, cfl_d, dt;
+};
+
+__global__ void __launch_bounds__(BLOCK) k_finalize(FinalArgs f, const double* __restrict__ part,
+                                                    double* __restrict__ state,
+                                                    double* __restrict__ totals) {
+  double v[NPART];
+#pragma unroll
+  for (int s = 0; s < NPART; ++s) v[s] = 0.0;
+  v[P_MAX_USUM] = 0.0;
+  v[P_MAX_C] = -INFINITY;
+  v[P_MIN_F] = INFINITY;
+  v[P_MIN_PSI] = INFINITY;
+  for (int b = threadIdx.x; b < f.nblk; b += BLOCK) {
+    const double* q = part + (long long)b * NPART;
+#pragma unroll
+    for (int s = 0; s < NPART; ++s) {
+      if (s == P_MAX_USUM || s == P_MAX_C) v[s] = fmax(v[s], q[s]);
+      else if (s == P_MIN_F || s == P_MIN_PSI) v[s] = fmin(v[s], q[s]);
+      else v[s] += q[s];
+    }
+  }
+  __shared__ double tot[NPART];
+  block_partials<double, BLOCK>(v, tot);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double vol = f.dim == 3 ? f.h * f.h * f.h : f.h * f.h;
+  double MB = f.bulk ? tot[P_SUM_F] * vol : 0.0;
+  double MS = tot[P_SUM_PSI] * vol;
+  double SD = tot[P_SUM_DELTA] * vol;
+  double SSD = tot[P_SUM_SIGDELTA] * vol;
+  double out = tot[P_OUTFLOW];
+  double outcum = state[S_OUTCUM] + out;
+  double t = state[S_TIME] + f.dt;
+  double su = tot[P_MAX_USUM];
+  double cmax = f.bulk ? tot[P_MAX_C] : 0.0;
+  double nd = f.dim;
+  double lam = f.form == FORM_W ? f.Dmax * (2.0 * nd - 1.0 + cosh(f.h / f.eps)) / (f.h * f.h)
+                                : f.Dmax * (2.0 * nd / (f.h * f.h) + sqrt(nd) / (f.eps * f.h));
+  if (f.bulk) lam += f.ka * f.ginf / f.eps + f.ka * (cmax > 0 ? cmax : 0.0) + f.kd;
+  double dta = su > 0 ? f.cfl_a * f.h / su : INFINITY;
+  double dtd = f.cfl_d / lam;
+  double bound = fmin(su > 0 ? f.h / su : INFINITY, 1.0 / lam);
+  unsigned status = (unsigned)state[S_STATUS];
+  if (tot[P_NBAD] > 0) status |= 1u;
+  if ((f.bulk && tot[P_MIN_F] < 0) || tot[P_MIN_PSI] < 0) status |= 2u;
+  if (f.dt > bound) status |= 4u;
+  state[S_TIME] = t;
+  state[S_OUTCUM] = outcum;
+  state[S_STEPS] += 1.0;
+  state[S_STATUS] = (double)status;
+  if (totals) {
+    totals[0] = MB;
+    totals[1] = MS;
+    totals[2] = out;
+    totals[3] = outcum;
+    totals[4] = SD;
+    totals[5] = SSD;
+    totals[6] = su;
+    totals[7] = fmin(dta, dtd);
+    totals[8] = f.bulk ? tot[P_MIN_F] : 0.0;
+    totals[9] = tot[P_MIN_PSI];
+    totals[10] = tot[P_NBAD];
+    totals[11] = t;
+    totals[12] = MS / SD;
+    totals[13] = SSD / SD;
+    totals[14] = MB + MS + outcum;
+    totals[15] = cmax;
+  }
+}
+
+__global__ void k_reset_state(double* state) {
+  if (threadIdx.x < NSTATE) state[threadIdx.x] = 0.0;
+}
+
+// ---------------------------------------------------------------- force
+template <typename R>
+__device__ __forceinline__ void face_grad(const Grid& g, const Par<R>& p, const R* __restrict__ v,
+                                          int d, const int* cL, const int* cR, long long L,
+                                          long long Rr, R* out) {
+  for (int e = 0; e < g.dim; ++e) {
+    if (e == d) {
+      out[e] = (v[Rr] - v[L]) * p.inv_h;
+    } else {
+      int a[3] = {cL[0], cL[1], cL[2]}, b[3] = {cL[0], cL[1], cL[2]};
+      a[e] = map_axis(cL[e] + 1, g.n[e], g.bc[e][0], g.bc[e][1]);
+      b[e] = map_axis(cL[e] - 1, g.n[e], g.bc[e][0], g.bc[e][1]);
+      R tl = v[cell_index(g, a[0], a[1], a[2])] - v[cell_index(g, b[0], b[1], b[2])];
+      int c[3] = {cR[0], cR[1], cR[2]}, dd[3] = {cR[0], cR[1], cR[2]};
+      c[e] = map_axis(cR[e] + 1, g.n[e], g.bc[e][0], g.bc[e][1]);
+      dd[e] = map_axis(cR[e] - 1, g.n[e], g.bc[e][0], g.bc[e][1]);
+      R tr = v[cell_index(g, c[0], c[1], c[2])] - v[cell_index(g, dd[0], dd[1], dd[2])];
+      out[e] = (tl + tr) * (R(0.25) * p.inv_h);
+    }
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_force(Grid g, Par<R> p, const R* __restrict__ chi,
+                                                 const R* __restrict__ sig, R* __restrict__ out,
+                                                 int d, long long nface) {
+  long long fi = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (fi >= nface) return;
+  int m[3] = {g.n[0], g.n[1], g.n[2]};
+  m[d] += 1;
+  int c[3] = {(int)(fi % m[0]), (int)((fi / m[0]) % m[1]), (int)(fi / ((long long)m[0] * m[1]))};
+  int fd = c[d], nd = g.n[d];
+  if ((fd == 0 || fd == nd) && g.bc[d][fd == nd] != BC_PERIODIC) {
+    out[fi] = R(0);
+    return;
+  }
+  int cR[3] = {c[0], c[1], c[2]};
+  if (fd == nd) cR[d] = 0;
+  int cL[3] = {cR[0], cR[1], cR[2]};
+  cL[d] = cR[d] - 1 < 0 ? nd - 1 : cR[d] - 1;
+  long long Rr = cell_index(g, cR[0], cR[1], cR[2]);
+  long long L = cell_index(g, cL[0], cL[1], cL[2]);
+  R gn[3] = {R(0), R(0), R(0)}, gs[3] = {R(0), R(0), R(0)};
+  face_grad<R>(g, p, chi, d, cL, cR, L, Rr, gn);
+  face_grad<R>(g, p, sig, d, cL, cR, L, Rr, gs);
+  R nrm = R(0);
+  for (int e = 0; e < g.dim; ++e) nrm += gn[e] * gn[e];
+  nrm = rsqrt_<R>(nrm);
+  nrm = nrm < R(1e-6) ? R(1e-6) : nrm;
+  R ndot = R(0);
+  for (int e = 0; e < g.dim; ++e) ndot += gn[e] / nrm * gs[e];
+  R phL, omL, deL, phR, omR, deR;
+  phase<R>(chi[L], p, phL, omL, deL);
+  phase<R>(chi[Rr], p, phR, omR, deR);
+  R dbar = R(0.5) * (deL + deR);
+  out[fi] = dbar * (gs[d] - gn[d] / nrm * ndot);
+}
+
+}  // namespace surf

@@ -1,0 +1,291 @@
+"""Python binding of libsurf (include/surf.h): argument marshalling only.
+
+Every step of the surfactant path runs in the HIP kernels of libsurf.so;
+torch tensors serve as device buffers and torch's current HIP stream as the
+stream.  Importing this module loads the library and raises if it is missing
+(there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsurf.so")
+
+SURF_F32, SURF_F64 = 0, 1
+FLUX_WEIGHTED, FLUX_PAPER = 0, 1
+KIN_LANGMUIR, KIN_HENRY = 0, 1
+EOS_LINEAR, EOS_LANGMUIR, EOS_TANH = 0, 1, 2
+BC_WALL, BC_PERIODIC, BC_OPEN = 0, 1, 2
+STATUS_NONFINITE, STATUS_NEGATIVE, STATUS_UNSTABLE = 1, 2, 4
+
+# totals slots
+T_MB, T_MS, T_OUT, T_OUTCUM, T_SDELTA, T_SSIGD, T_SU, T_DTNEXT = range(8)
+T_MINF, T_MINPSI, T_NBAD, T_T, T_GAVG, T_SAVG, T_MTOT, T_CMAX = range(8, 16)
+
+ERRORS = {0: "ok", -1: "invalid argument", -2: "workspace too small",
+          -3: "HIP runtime error", -4: "call-order violation", -5: "unstable"}
+
+EXPORTS = [
+    "surf_workspace_bytes", "surf_init", "surf_set_geometry", "surf_set_levelset",
+    "surf_get_levelset", "surf_init_state", "surf_step", "surf_force", "surf_set_dt",
+    "surf_get_status", "surf_clear_status", "surf_destroy", "surf_strerror", "surf_version",
+    "surf_profile_enable", "surf_profile_read",
+]
+
+
+class SurfError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__("%s failed: %s (%d)" % (what, ERRORS.get(code, "?"), code))
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3),
+                ("bc", (ctypes.c_int32 * 2) * 3), ("pad_", ctypes.c_int32),
+                ("h", ctypes.c_double), ("origin", ctypes.c_double * 3)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("flux_form", ctypes.c_int32),
+                ("kinetics", ctypes.c_int32), ("eos", ctypes.c_int32),
+                ("bulk_enabled", ctypes.c_int32), ("hj_iters_init", ctypes.c_int32),
+                ("hj_iters_step", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("eps", ctypes.c_double), ("D_b", ctypes.c_double), ("D_s", ctypes.c_double),
+                ("k_a", ctypes.c_double), ("k_d", ctypes.c_double),
+                ("gamma_inf", ctypes.c_double), ("sigma0", ctypes.c_double),
+                ("eos_E", ctypes.c_double), ("eta", ctypes.c_double),
+                ("chi_max_eps", ctypes.c_double), ("cfl_adv", ctypes.c_double),
+                ("cfl_diff", ctypes.c_double), ("dt", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsurf.so (built by paper_2605_27534_amd.build); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsurf.so is not built (%s); run "
+                               "`python -m paper_2605_27534_amd.build`" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32 = ctypes.c_void_p, ctypes.c_int
+        L.surf_workspace_bytes.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.surf_init.argtypes = [ctypes.POINTER(vp), vp, vp, vp, ctypes.c_size_t, vp]
+        L.surf_set_geometry.argtypes = [vp, vp, i32]
+        L.surf_set_levelset.argtypes = [vp, vp]
+        L.surf_get_levelset.argtypes = [vp, vp]
+        L.surf_init_state.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp]
+        L.surf_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.surf_force.argtypes = [vp, vp, vp]
+        L.surf_set_dt.argtypes = [vp, ctypes.c_double]
+        L.surf_get_status.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
+        L.surf_clear_status.argtypes = [vp]
+        L.surf_destroy.argtypes = [vp]
+        L.surf_strerror.argtypes = [i32]
+        L.surf_strerror.restype = ctypes.c_char_p
+        L.surf_version.restype = ctypes.c_char_p
+        L.surf_profile_enable.argtypes = [vp, i32]
+        L.surf_profile_read.argtypes = [vp, vp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+DEFAULTS = dict(flux_form=0, kinetics=0, eos=0, bulk_enabled=1, D_b=1e-2, D_s=1e-3,
+                k_a=1.0, k_d=1.0, gamma_inf=1.0, sigma0=1.0, eos_E=0.5, eta=1e-12,
+                chi_max_eps=12.0, cfl_adv=0.5, cfl_diff=0.8, hj_iters_init=0,
+                hj_iters_step=0)
+
+
+def make_structs(prob: dict, dt: float, precision: int):
+    q = dict(DEFAULTS)
+    q.update(prob)
+    n = list(q["n"]) + [1] * (3 - len(q["n"]))
+    bc = [tuple(b) for b in q.get("bc", ())] + [(0, 0)] * 3
+    g = Grid()
+    g.dim = q["dim"]
+    for d in range(3):
+        g.n[d] = int(n[d])
+        g.bc[d][0], g.bc[d][1] = bc[d]
+    g.h = q["h"]
+    org = q.get("origin", (0.0, 0.0, 0.0))
+    for d in range(3):
+        g.origin[d] = org[d] if d < len(org) else 0.0
+    p = Params()
+    p.precision = precision
+    for k in ("flux_form", "kinetics", "eos", "bulk_enabled", "hj_iters_init", "hj_iters_step"):
+        setattr(p, k, int(q[k]))
+    for k in ("D_b", "D_s", "k_a", "k_d", "gamma_inf", "sigma0", "eos_E", "eta",
+              "chi_max_eps", "cfl_adv", "cfl_diff"):
+        setattr(p, k, float(q[k]))
+    p.eps = float(q.get("eps", 1.5 * q["h"]))
+    p.dt = float(dt)
+    return g, p, q
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Surf:
+    """One surfactant problem on the current CUDA/HIP device and stream."""
+
+    def __init__(self, prob: dict, dt: float, precision: int = SURF_F32, device="cuda"):
+        self.L = lib()
+        self.grid, self.params, self.prob = make_structs(prob, dt, precision)
+        self.dtype = torch.float64 if precision == SURF_F64 else torch.float32
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        nb = ctypes.c_size_t(0)
+        self._check(self.L.surf_workspace_bytes(ctypes.byref(self.grid), ctypes.byref(self.params),
+                                                ctypes.byref(nb)), "surf_workspace_bytes")
+        self.workspace = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        ws_ptr = self.workspace.data_ptr() + off
+        self.stream = torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        self._check(self.L.surf_init(ctypes.byref(ctx), ctypes.byref(self.grid),
+                                     ctypes.byref(self.params), ctypes.c_void_p(ws_ptr),
+                                     ctypes.c_size_t(int(nb.value)),
+                                     ctypes.c_void_p(self.stream.cuda_stream)), "surf_init")
+        self.ctx = ctx
+        n = list(self.prob["n"]) + [1] * 3
+        self.shape = (int(n[2]), int(n[1]), int(n[0]))
+        self.dim = int(self.prob["dim"])
+
+    # -- helpers
+    def _check(self, rc, what):
+        if rc != 0:
+            raise SurfError(rc, what)
+
+    def face_shape(self, d):
+        s = list(self.shape)
+        s[2 - d] += 1
+        return tuple(s)
+
+    def empty(self):
+        return torch.empty(self.shape, dtype=self.dtype, device=self.device)
+
+    def tensor(self, a):
+        return torch.as_tensor(a).to(device=self.device, dtype=self.dtype).contiguous()
+
+    def _cell(self, t, name):
+        if t is None:
+            return None
+        if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous() \
+                or tuple(t.shape) != self.shape:
+            raise ValueError("%s: expected contiguous %s %s on %s" % (name, self.dtype, self.shape,
+                                                                    self.device))
+        return t
+
+    def _faces(self, u, name):
+        if u is None:
+            return None
+        for d in range(self.dim):
+            t = u[d]
+            if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous() \
+                    or tuple(t.shape) != self.face_shape(d):
+                raise ValueError("%s[%d]: expected contiguous %s %s" % (name, d, self.dtype,
+                                                                       self.face_shape(d)))
+        arr = (ctypes.c_void_p * 3)(*[u[d].data_ptr() if d < self.dim else None for d in range(3)])
+        return arr
+
+    # -- API
+    def set_geometry(self, vof, full=True):
+        self._check(self.L.surf_set_geometry(self.ctx, _ptr(self._cell(vof, "vof")), int(full)),
+                    "surf_set_geometry")
+
+    def set_levelset(self, chi):
+        self._check(self.L.surf_set_levelset(self.ctx, _ptr(self._cell(chi, "chi"))),
+                    "surf_set_levelset")
+
+    def levelset(self):
+        out = self.empty()
+        self._check(self.L.surf_get_levelset(self.ctx, _ptr(out)), "surf_get_levelset")
+        return out
+
+    def init_state(self, c0=None, c0_const=1.0, gamma0=0.0):
+        F = self.empty() if self.params.bulk_enabled else None
+        psi = self.empty()
+        self._check(self.L.surf_init_state(self.ctx, _ptr(self._cell(c0, "c0")),
+                                           float(c0_const), float(gamma0), _ptr(F), _ptr(psi)),
+                    "surf_init_state")
+        return F, psi
+
+    def step(self, F_in, psi_in, F_out, psi_out, u=None, vof_next=None, sigma_out=None,
+             totals=None):
+        ua = self._faces(u, "u")
+        if totals is not None and (totals.dtype != torch.float64 or totals.numel() < 16
+                                   or totals.device != self.device):
+            raise ValueError("totals: 16 float64 on the device")
+        self._check(self.L.surf_step(self.ctx, _ptr(self._cell(vof_next, "vof_next")), ua,
+                                     _ptr(self._cell(F_in, "F_in")),
+                                     _ptr(self._cell(psi_in, "psi_in")),
+                                     _ptr(self._cell(F_out, "F_out")),
+                                     _ptr(self._cell(psi_out, "psi_out")),
+                                     _ptr(self._cell(sigma_out, "sigma_out")), _ptr(totals)),
+                    "surf_step")
+
+    def force(self, sigma):
+        out = [torch.empty(self.face_shape(d), dtype=self.dtype, device=self.device)
+               for d in range(self.dim)]
+        arr = (ctypes.c_void_p * 3)(*[out[d].data_ptr() if d < self.dim else None
+                                      for d in range(3)])
+        self._check(self.L.surf_force(self.ctx, _ptr(self._cell(sigma, "sigma")), arr),
+                    "surf_force")
+        return out
+
+    def set_dt(self, dt):
+        self._check(self.L.surf_set_dt(self.ctx, float(dt)), "surf_set_dt")
+
+    def status(self):
+        b = ctypes.c_uint32(0)
+        self._check(self.L.surf_get_status(self.ctx, ctypes.byref(b)), "surf_get_status")
+        return int(b.value)
+
+    def clear_status(self):
+        self._check(self.L.surf_clear_status(self.ctx), "surf_clear_status")
+
+    def profile(self, enable=True):
+        self._check(self.L.surf_profile_enable(self.ctx, int(enable)), "surf_profile_enable")
+
+    def profile_read(self):
+        """(transport ms, transport launches, redistancing ms, sweeps)."""
+        a, c = ctypes.c_double(0), ctypes.c_double(0)
+        b, d = ctypes.c_int64(0), ctypes.c_int64(0)
+        self._check(self.L.surf_profile_read(self.ctx, ctypes.byref(a), ctypes.byref(b),
+                                             ctypes.byref(c), ctypes.byref(d)),
+                    "surf_profile_read")
+        return a.value, b.value, c.value, d.value
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.surf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, F, psi, nsteps, u=None, vof_seq=None, sigma=None, totals_hist=None):
+        """nsteps steps with ping-pong buffers; returns (F, psi, sigma).
+        vof_seq(n) gives the VoF at t^{n+1} (device tensor) or None.
+        totals_hist: float64 device tensor [nsteps, 16] or None."""
+        F2 = self.empty() if F is not None else None
+        P2 = self.empty()
+        S = sigma if sigma is not None else self.empty()
+        for n in range(nsteps):
+            v = vof_seq(n) if vof_seq is not None else None
+            tot = totals_hist[n] if totals_hist is not None else None
+            self.step(F, psi, F2, P2, u=u, vof_next=v, sigma_out=S, totals=tot)
+            F, F2 = F2, F
+            psi, P2 = P2, psi
+        return F, psi, S

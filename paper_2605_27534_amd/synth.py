@@ -36,26 +36,46 @@ def _subcell_offsets(sub, dim, h):
 def vof_ball(n, h, centre, R, dim, sub=8, origin=(0.0, 0.0, 0.0), period_z=None):
     """Fraction of sub^dim subcell centres inside a circle (dim 2) or sphere
     (dim 3) of radius R.  Values are k / sub^dim, exact in binary for
-    sub = 8.  `period_z` (box length) takes the nearest periodic image in z."""
+    sub = 8.  `period_z` (box length) takes the nearest periodic image in z.
+    Only the cells of the ball's bounding box are visited."""
     x, y, z = cell_centres(n, h, origin)
     nx, ny, nz = len(x), len(y), len(z)
     f = np.zeros((nz, ny, nx))
-    dz = (z - centre[2]) if dim == 3 else np.zeros(nz)
-    if dim == 3 and period_z is not None:
-        dz = dz - period_z * np.round(dz / period_z)
-    dy = y - centre[1]
-    dx = x - centre[0]
-    r = np.sqrt(dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2)
+    pad = R + h
+
+    def span(coord, c):
+        lo = np.searchsorted(coord, c - pad, side="left")
+        hi = np.searchsorted(coord, c + pad, side="right")
+        return slice(int(lo), int(hi))
+
+    sx, sy = span(x, centre[0]), span(y, centre[1])
+    if dim == 3:
+        zs = [centre[2]]
+        if period_z is not None:
+            zs = [centre[2] - period_z, centre[2], centre[2] + period_z]
+        szs = [(span(z, zc), zc) for zc in zs]
+    else:
+        szs = [(slice(0, nz), None)]
     half_diag = 0.5 * h * math.sqrt(dim) * (1 + 1e-9)
-    f[r <= R - half_diag] = 1.0
-    cut = np.nonzero(np.abs(r - R) < half_diag)
-    if cut[0].size:
-        ox, oy, oz = _subcell_offsets(sub, dim, h)
-        px = dx[cut[2]][:, None] + ox[None, :]
-        py = dy[cut[1]][:, None] + oy[None, :]
-        pz = dz[cut[0]][:, None] + oz[None, :]
-        inside = (px * px + py * py + pz * pz) < R * R
-        f[cut] = inside.sum(axis=1) / float(sub ** dim)
+    ox, oy, oz = _subcell_offsets(sub, dim, h)
+    for sz, zc in szs:
+        xs, ys, zz = x[sx], y[sy], z[sz]
+        if xs.size == 0 or ys.size == 0 or zz.size == 0:
+            continue
+        dx = xs - centre[0]
+        dy = ys - centre[1]
+        dz = (zz - zc) if dim == 3 else np.zeros(zz.size)
+        r = np.sqrt(dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2)
+        block = np.zeros(r.shape)
+        block[r <= R - half_diag] = 1.0
+        cut = np.nonzero(np.abs(r - R) < half_diag)
+        if cut[0].size:
+            px = dx[cut[2]][:, None] + ox[None, :]
+            py = dy[cut[1]][:, None] + oy[None, :]
+            pz = dz[cut[0]][:, None] + oz[None, :]
+            inside = (px * px + py * py + pz * pz) < R * R
+            block[cut] = inside.sum(axis=1) / float(sub ** dim)
+        f[sz, sy, sx] = np.maximum(f[sz, sy, sx], block)
     return f
 
 

@@ -1,0 +1,90 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "surf.h")).read()
+    return sorted(set(re.findall(r"\b(surf_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2605_27534_amd import surf as S
+    L = S.lib()
+    syms = header_symbols()
+    assert "surf_step" in syms and "surf_force" in syms
+    for name in syms:
+        assert hasattr(L, name), name
+    assert set(S.EXPORTS) >= set(syms)
+    assert L.surf_version().startswith(b"surf")
+
+
+def _structs(**over):
+    from paper_2605_27534_amd import surf as S
+    prob = dict(dim=2, n=(32, 24), h=1.0 / 32, bc=((0, 0), (1, 1)))
+    prob.update(over)
+    return S.make_structs(prob, 1e-3, S.SURF_F32)
+
+
+def test_workspace_bytes_and_init_validate_arguments():
+    from paper_2605_27534_amd import surf as S
+    L = S.lib()
+    g, p, _ = _structs()
+    nb = ctypes.c_size_t(0)
+    assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == 0
+    assert nb.value >= 3 * 32 * 24 * 4
+    # a host buffer stands in for the workspace: init issues no device work
+    buf = ctypes.create_string_buffer(nb.value + 512)
+    base = (ctypes.addressof(buf) + 255) // 256 * 256
+    ctx = ctypes.c_void_p()
+    assert L.surf_init(ctypes.byref(ctx), ctypes.byref(g), ctypes.byref(p),
+                       ctypes.c_void_p(base), nb, None) == 0
+    # call-order checks happen before any launch
+    assert L.surf_init_state(ctx, None, ctypes.c_double(1.0), ctypes.c_double(0.0),
+                             ctypes.c_void_p(base), ctypes.c_void_p(base)) == -4
+    assert L.surf_set_geometry(ctx, ctypes.c_void_p(base), 0) == -4
+    assert L.surf_step(ctx, None, None, None, None, None, None, None, None) == -1
+    assert L.surf_set_dt(ctx, ctypes.c_double(-1.0)) == -1
+    assert L.surf_destroy(ctx) == 0
+    # too small a workspace, misaligned workspace
+    ctx2 = ctypes.c_void_p()
+    assert L.surf_init(ctypes.byref(ctx2), ctypes.byref(g), ctypes.byref(p),
+                       ctypes.c_void_p(base), ctypes.c_size_t(nb.value - 1), None) == -2
+    assert L.surf_init(ctypes.byref(ctx2), ctypes.byref(g), ctypes.byref(p),
+                       ctypes.c_void_p(base + 8), nb, None) == -1
+
+
+@pytest.mark.parametrize("over", [
+    dict(dim=4), dict(n=(3, 24)), dict(bc=((1, 0), (0, 0))), dict(h=0.0),
+    dict(n=(32, 24, 2)),
+])
+def test_bad_grids_rejected(over):
+    from paper_2605_27534_amd import surf as S
+    L = S.lib()
+    g, p, _ = _structs(**over)
+    nb = ctypes.c_size_t(0)
+    assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == -1
+
+
+def test_bad_params_rejected():
+    from paper_2605_27534_amd import surf as S
+    L = S.lib()
+    for field, val in (("precision", 7), ("eos", 3), ("eps", 0.0), ("dt", 0.0),
+                       ("gamma_inf", -1.0), ("k_a", -1.0)):
+        g, p, _ = _structs()
+        setattr(p, field, val)
+        nb = ctypes.c_size_t(0)
+        assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == -1, field
+
+
+def test_strerror():
+    from paper_2605_27534_amd import surf as S
+    L = S.lib()
+    assert L.surf_strerror(0) == b"ok"
+    assert L.surf_strerror(-2) == b"workspace too small"
