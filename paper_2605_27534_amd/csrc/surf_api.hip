@@ -10,6 +10,7 @@
 
 #include "../../include/surf.h"
 #include "surf_kernels.hpp"
+#include "surf_step2d.hpp"
 
 using namespace surf;
 
@@ -30,6 +31,12 @@ struct surf_ctx {
   int tiles[3];
   int nblk;
   double dt;
+  // 2D fused path: per-tile quiescence flags of each level-set buffer
+  uint8_t* q[2];
+  int tiles2d[2];
+  int ntiles2d;
+  int per_xcd;
+  bool materialized;  // chi[chi_cur] holds explicit values on every tile
   // optional per-launch event timing
   bool profile;
   struct Mark { hipEvent_t a, b; int kind; };
@@ -107,6 +114,7 @@ Par<R> make_par(const surf_ctx* c) {
   p.ka = (R)q.k_a;
   p.kd = (R)q.k_d;
   p.ginf = (R)q.gamma_inf;
+  p.inv_ginf = (R)(1.0 / q.gamma_inf);
   p.sigma0 = (R)q.sigma0;
   p.E = (R)q.eos_E;
   p.eta = (R)q.eta;
@@ -130,6 +138,15 @@ int nblocks_step(const surf_grid* gr, const surf_params* p, int* tiles) {
     nb *= tiles[d];
   }
   return (int)nb;
+}
+
+constexpr int T2X = 64, T2Y = 16, STEP2D_THREADS = 512;
+
+int ntiles_2d(const surf_grid* gr, int* t) {
+  if (gr->dim != 2) { t[0] = t[1] = 0; return 0; }
+  t[0] = (gr->n[0] + T2X - 1) / T2X;
+  t[1] = (gr->n[1] + T2Y - 1) / T2Y;
+  return t[0] * t[1];
 }
 
 int status_of_launch() {
@@ -171,10 +188,29 @@ struct Timed {
 };
 
 template <typename R>
+void materialize(surf_ctx* c) {
+  if (c->materialized || c->ntiles2d == 0) {
+    c->materialized = true;
+    return;
+  }
+  hipLaunchKernelGGL((k_materialize<R, T2X, T2Y>), dim3(c->ntiles2d), dim3(BLOCK), 0, c->stream,
+                     c->g, (R*)c->chi[c->chi_cur], (const uint8_t*)c->q[c->chi_cur],
+                     (R)(c->prm.chi_max_eps * c->prm.eps), c->tiles2d[0], c->ntiles2d);
+  c->materialized = true;
+}
+
+void flags_live(surf_ctx* c) {
+  if (c->ntiles2d == 0) return;
+  hipLaunchKernelGGL(k_fill_u8, dim3((c->ntiles2d + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, c->stream,
+                     c->q[c->chi_cur], (uint8_t)Q_LIVE, c->ntiles2d);
+}
+
+template <typename R>
 int geometry_impl(surf_ctx* c, const void* vof, int full) {
   Par<R> p = make_par<R>(c);
   long long n = c->ncell;
   const R* f = (const R*)vof;
+  if (!full) materialize<R>(c);
   hipLaunchKernelGGL(k_pin<R>, dim3(grid1d(n)), dim3(BLOCK), 0, c->stream, c->g, p, f,
                      (R*)c->g0, n);
   int iters;
@@ -194,6 +230,8 @@ int geometry_impl(surf_ctx* c, const void* vof, int full) {
     c->chi_cur = nxt;
   }
   c->has_chi = true;
+  c->materialized = true;
+  flags_live(c);
   return status_of_launch();
 }
 
@@ -202,9 +240,81 @@ void launch_step(surf_ctx* c, const StepArgs<R>& a) {
   hipLaunchKernelGGL((k_step<R, DIM, TX, TY, TZ>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
 }
 
+// The fused 2D kernel handles both the static and the moving interface (the
+// latter with its redistancing sweeps inside, FP32 only, up to 16 sweeps and
+// grids of at least 2 (K + 2) cells per axis so mirror ghosts stay inside).
+template <typename R>
+bool fused_moving_ok(const surf_ctx* c) {
+  if (c->grid.dim != 2 || sizeof(R) != 4) return false;
+  int K = c->prm.hj_iters_step;
+  if (K > 16) return false;
+  int KH = K <= 8 ? 8 : 16;
+  return c->grid.n[0] >= 2 * (KH + 2) && c->grid.n[1] >= 2 * (KH + 2);
+}
+
+template <typename R, int KH>
+void launch_step2d(surf_ctx* c, const Step2dArgs<R>& a) {
+  hipLaunchKernelGGL((k_step2d<R, KH, STEP2D_THREADS, T2X, T2Y>), dim3(8 * c->per_xcd),
+                     dim3(STEP2D_THREADS), 0, c->stream, a);
+}
+
+template <typename R>
+void finalize(surf_ctx* c, double* totals, int nblk);
+
+template <typename R>
+int step2d_impl(surf_ctx* c, const void* vof_next, const void* const* u, const void* F_in,
+                const void* psi_in, void* F_out, void* psi_out, void* sigma_out,
+                double* totals) {
+  Step2dArgs<R> a;
+  a.g = c->g;
+  a.p = make_par<R>(c);
+  bool moving = vof_next != nullptr;
+  a.vof = (const R*)vof_next;
+  a.chi_in = (const R*)c->chi[c->chi_cur];
+  a.chi_out = (R*)c->chi[1 - c->chi_cur];
+  a.q_in = c->q[c->chi_cur];
+  a.q_out = c->q[1 - c->chi_cur];
+  a.has_u = (u && u[0]) ? 1 : 0;
+  a.u[0] = a.has_u ? (const R*)u[0] : nullptr;
+  a.u[1] = a.has_u ? (const R*)u[1] : nullptr;
+  a.F = (const R*)F_in;
+  a.psi = (const R*)psi_in;
+  a.Fo = (R*)F_out;
+  a.Po = (R*)psi_out;
+  a.sig = (R*)sigma_out;
+  a.part = c->part;
+  a.state = c->state;
+  a.dt = (R)c->dt;
+  a.area_dt = (R)(c->grid.h * c->dt);
+  a.dtau = (R)(c->grid.h / 2);
+  a.ksweeps = c->prm.hj_iters_step;
+  a.tiles[0] = c->tiles2d[0];
+  a.tiles[1] = c->tiles2d[1];
+  a.ntiles = c->ntiles2d;
+  a.per_xcd = c->per_xcd;
+  {
+    Timed tm(c, 0);
+    if (!moving) {
+      launch_step2d<R, 0>(c, a);
+    } else if constexpr (sizeof(R) == 4) {
+      if (a.ksweeps <= 8) launch_step2d<R, 8>(c, a);
+      else launch_step2d<R, 16>(c, a);
+    }
+  }
+  if (moving) {
+    c->chi_cur = 1 - c->chi_cur;
+    c->materialized = false;
+  }
+  finalize<R>(c, totals, c->ntiles2d);
+  return status_of_launch();
+}
+
 template <typename R>
 int step_impl(surf_ctx* c, const void* const* u, const void* F_in, const void* psi_in,
               void* F_out, void* psi_out, void* sigma_out, double* totals) {
+  if (c->grid.dim == 2)
+    return step2d_impl<R>(c, nullptr, u, F_in, psi_in, F_out, psi_out, sigma_out, totals);
+  materialize<R>(c);
   StepArgs<R> a;
   a.g = c->g;
   a.p = make_par<R>(c);
@@ -229,8 +339,14 @@ int step_impl(surf_ctx* c, const void* const* u, const void* F_in, const void* p
       else launch_step<R, 3, 8, 8, 4>(c, a);
     }
   }
+  finalize<R>(c, totals, c->nblk);
+  return status_of_launch();
+}
+
+template <typename R>
+void finalize(surf_ctx* c, double* totals, int nblk) {
   FinalArgs f;
-  f.nblk = c->nblk;
+  f.nblk = nblk;
   f.dim = c->grid.dim;
   f.bulk = c->prm.bulk_enabled ? 1 : 0;
   f.form = c->prm.flux_form;
@@ -243,13 +359,13 @@ int step_impl(surf_ctx* c, const void* const* u, const void* F_in, const void* p
   f.cfl_a = c->prm.cfl_adv;
   f.cfl_d = c->prm.cfl_diff;
   f.dt = c->dt;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLOCK), 0, c->stream, f, (const double*)c->part,
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_BLOCK), 0, c->stream, f, (const double*)c->part,
                      c->state, totals);
-  return status_of_launch();
 }
 
 template <typename R>
 int init_impl(surf_ctx* c, const void* c0, double c0_const, double gamma0, void* F, void* psi) {
+  materialize<R>(c);
   Par<R> p = make_par<R>(c);
   long long n = c->ncell;
   hipLaunchKernelGGL(k_init<R>, dim3(grid1d(n)), dim3(BLOCK), 0, c->stream, c->g, p,
@@ -261,6 +377,7 @@ int init_impl(surf_ctx* c, const void* c0, double c0_const, double gamma0, void*
 
 template <typename R>
 int force_impl(surf_ctx* c, const void* sigma, void* const* force) {
+  materialize<R>(c);
   Par<R> p = make_par<R>(c);
   for (int d = 0; d < c->grid.dim; ++d) {
     long long nf = c->ncell / c->grid.n[d] * (c->grid.n[d] + 1);
@@ -294,13 +411,16 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   if (!bytes) return SURF_EINVAL;
   int rc = check_grid_params(grid, params);
   if (rc) return rc;
-  int tiles[3];
+  int tiles[3], t2[2];
   int nblk = nblocks_step(grid, params, tiles);
+  int n2 = ntiles_2d(grid, t2);
+  int npart = nblk > n2 ? nblk : n2;
   size_t n = (size_t)grid->n[0] * grid->n[1] * grid->n[2];
   size_t es = esize(params);
   size_t b = align_up(NSTATE * sizeof(double));
-  b += align_up((size_t)nblk * NPART * sizeof(double));
+  b += align_up((size_t)npart * NPART * sizeof(double));
   b += 3 * align_up(n * es);
+  b += 2 * align_up((size_t)n2 + 1);
   *bytes = b;
   return SURF_OK;
 }
@@ -329,17 +449,25 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
   c->ws_bytes = ws_bytes;
   c->ncell = (long long)grid->n[0] * grid->n[1] * grid->n[2];
   c->nblk = nblocks_step(grid, params, c->tiles);
+  c->ntiles2d = ntiles_2d(grid, c->tiles2d);
+  c->per_xcd = (c->ntiles2d + 7) / 8;
+  int npart = c->nblk > c->ntiles2d ? c->nblk : c->ntiles2d;
   size_t es = esize(params);
   char* p = c->ws;
   c->state = (double*)p;
   p += align_up(NSTATE * sizeof(double));
   c->part = (double*)p;
-  p += align_up((size_t)c->nblk * NPART * sizeof(double));
+  p += align_up((size_t)npart * NPART * sizeof(double));
   c->chi[0] = p;
   p += align_up(c->ncell * es);
   c->chi[1] = p;
   p += align_up(c->ncell * es);
   c->g0 = p;
+  p += align_up(c->ncell * es);
+  c->q[0] = (uint8_t*)p;
+  p += align_up((size_t)c->ntiles2d + 1);
+  c->q[1] = (uint8_t*)p;
+  c->materialized = true;
   c->chi_cur = 0;
   c->has_chi = false;
   c->dt = params->dt;
@@ -361,12 +489,16 @@ int surf_set_levelset(surf_ctx* c, const void* chi) {
       hipSuccess)
     return SURF_EDEVICE;
   c->has_chi = true;
-  return SURF_OK;
+  c->materialized = true;
+  flags_live(c);
+  return status_of_launch();
 }
 
 int surf_get_levelset(surf_ctx* c, void* chi_out) {
   if (!c || !chi_out) return SURF_EINVAL;
   if (!c->has_chi) return SURF_ESTATE;
+  if (c->prm.precision == SURF_F64) materialize<double>(c);
+  else materialize<float>(c);
   size_t bytes = (size_t)c->ncell * esize(&c->prm);
   if (hipMemcpyAsync(chi_out, c->chi[c->chi_cur], bytes, hipMemcpyDeviceToDevice, c->stream) !=
       hipSuccess)
@@ -396,12 +528,14 @@ int surf_step(surf_ctx* c, const void* vof_next, const void* const* u, const voi
       if (!u[d]) return SURF_EINVAL;
   size_t es = esize(&c->prm);
   if (!aligned(psi_in, es) || !aligned(psi_out, es)) return SURF_EINVAL;
+  if (!c->has_chi) return SURF_ESTATE;
   if (vof_next) {
-    if (!c->has_chi) return SURF_ESTATE;
+    if (c->prm.precision == SURF_F32 && fused_moving_ok<float>(c))
+      return step2d_impl<float>(c, vof_next, u, F_in, psi_in, F_out, psi_out, sigma_out,
+                                totals_dev);
     int rc = surf_set_geometry(c, vof_next, 0);
     if (rc) return rc;
   }
-  if (!c->has_chi) return SURF_ESTATE;
   if (c->prm.precision == SURF_F64)
     return step_impl<double>(c, u, F_in, psi_in, F_out, psi_out, sigma_out, totals_dev);
   return step_impl<float>(c, u, F_in, psi_in, F_out, psi_out, sigma_out, totals_dev);
@@ -435,8 +569,8 @@ int surf_get_status(surf_ctx* c, uint32_t* bits) {
 
 int surf_clear_status(surf_ctx* c) {
   if (!c) return SURF_EINVAL;
-  static const double zero = 0.0;
-  if (hipMemcpyAsync(c->state + S_STATUS, &zero, sizeof(double), hipMemcpyHostToDevice,
+  static const double zero[2] = {0.0, 0.0};  // S_STATUS and the S_FLAGS word
+  if (hipMemcpyAsync(c->state + S_STATUS, zero, 2 * sizeof(double), hipMemcpyHostToDevice,
                      c->stream) != hipSuccess)
     return SURF_EDEVICE;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return SURF_EDEVICE;

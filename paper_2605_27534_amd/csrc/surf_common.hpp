@@ -18,8 +18,9 @@ enum {
   P_MAX_USUM, P_MAX_C, P_MIN_F, P_MIN_PSI, P_NBAD, NPART
 };
 
-// device-resident running state (doubles) in the workspace
-enum { S_TIME = 0, S_OUTCUM = 1, S_STEPS = 2, S_STATUS = 3, NSTATE = 8 };
+// device-resident running state (doubles) in the workspace; slot S_FLAGS
+// holds a 32-bit word of status bits raised outside the finalize kernel
+enum { S_TIME = 0, S_OUTCUM = 1, S_STEPS = 2, S_STATUS = 3, S_FLAGS = 4, NSTATE = 8 };
 
 struct Grid {
   int dim;
@@ -29,7 +30,7 @@ struct Grid {
 
 template <typename R>
 struct Par {
-  R h, inv_h, eps, inv_eps, Db, Ds, ka, kd, ginf, sigma0, E, eta, eta_eps, chimax;
+  R h, inv_h, eps, inv_eps, Db, Ds, ka, kd, ginf, inv_ginf, sigma0, E, eta, eta_eps, chimax;
   int form, kin, eos, bulk;
 };
 
@@ -58,35 +59,48 @@ __device__ __forceinline__ long long face_index(const Grid& g, int d, int i, int
   return (long long)i + mx * ((long long)j + my * k);
 }
 
+// Elementary functions.  FP32 uses the hardware approximations (exp2, log2,
+// reciprocal and square root instructions, ~1 ulp), well inside the FP32
+// parity budget; FP64 keeps the correctly rounded library functions.
 template <typename R> __device__ __forceinline__ R rexp(R x);
-template <> __device__ __forceinline__ float rexp<float>(float x) { return expf(x); }
+template <> __device__ __forceinline__ float rexp<float>(float x) { return __expf(x); }
 template <> __device__ __forceinline__ double rexp<double>(double x) { return exp(x); }
 
 template <typename R> __device__ __forceinline__ R rlog(R x);
-template <> __device__ __forceinline__ float rlog<float>(float x) { return logf(x); }
+template <> __device__ __forceinline__ float rlog<float>(float x) { return __logf(x); }
 template <> __device__ __forceinline__ double rlog<double>(double x) { return log(x); }
 
+template <typename R> __device__ __forceinline__ R rrcp(R x);
+template <> __device__ __forceinline__ float rrcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double rrcp<double>(double x) { return 1.0 / x; }
+
 template <typename R> __device__ __forceinline__ R rtanh(R x);
-template <> __device__ __forceinline__ float rtanh<float>(float x) { return tanhf(x); }
+template <> __device__ __forceinline__ float rtanh<float>(float x) {
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * x));
+}
 template <> __device__ __forceinline__ double rtanh<double>(double x) { return tanh(x); }
 
 template <typename R> __device__ __forceinline__ R rsqrt_(R x);
-template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return sqrtf(x); }
+template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> __device__ __forceinline__ double rsqrt_<double>(double x) { return sqrt(x); }
+
+// a / b: reciprocal-multiply in FP32, division in FP64
+template <typename R> __device__ __forceinline__ R rdiv(R a, R b) { return a * rrcp<R>(b); }
+template <> __device__ __forceinline__ double rdiv<double>(double a, double b) { return a / b; }
 
 // phi = 1/(1+e^{chi/eps}) (0 in fluid 1, 1 in the liquid), omega = 1 - phi
 // evaluated without cancellation, delta = phi omega / eps.
 template <typename R>
 __device__ __forceinline__ void phase(R chi, const Par<R>& p, R& phi, R& om, R& del) {
   R e = rexp<R>(chi * p.inv_eps);
-  phi = R(1) / (R(1) + e);
+  phi = rrcp<R>(R(1) + e);
   om = e * phi;
   del = phi * om * p.inv_eps;
 }
 
 template <typename R>
 __device__ __forceinline__ R eos(R G, const Par<R>& p) {
-  R x = G / p.ginf;
+  R x = G * p.inv_ginf;
   if (p.eos == EOS_LIN) return p.sigma0 * (R(1) - p.E * x);
   if (p.eos == EOS_LANG) {
     x = x < R(0) ? R(0) : x;
@@ -105,21 +119,48 @@ __device__ __forceinline__ R minmod(R a, R b) {
   return same ? m : R(0);
 }
 
-// wave64 reductions (gfx950 wavefronts are 64 lanes)
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// wave64 reductions (gfx950 wavefronts are 64 lanes) with DPP row
+// rotations inside each 16-lane row, then the four row results combined in
+// a fixed order through readlane: no LDS permutes, deterministic.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  long long b = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  long long b = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
+constexpr int DPP_ROR8 = 0x128, DPP_ROR4 = 0x124, DPP_ROR2 = 0x122, DPP_ROR1 = 0x121;
+
+enum { RED_SUM = 0, RED_MAX = 1, RED_MIN = 2 };
+
+template <int OP>
+__device__ __forceinline__ double red_op(double a, double b) {
+  return OP == RED_SUM ? a + b : (OP == RED_MAX ? fmax(a, b) : fmin(a, b));
+}
+
+// every lane of the wave receives the reduction of all 64 lanes
+template <int OP>
+__device__ __forceinline__ double wave_reduce(double v) {
+  v = red_op<OP>(v, dpp_d<DPP_ROR8>(v));
+  v = red_op<OP>(v, dpp_d<DPP_ROR4>(v));
+  v = red_op<OP>(v, dpp_d<DPP_ROR2>(v));
+  v = red_op<OP>(v, dpp_d<DPP_ROR1>(v));
+  double r0 = readlane_d(v, 0), r1 = readlane_d(v, 16);
+  double r2 = readlane_d(v, 32), r3 = readlane_d(v, 48);
+  return red_op<OP>(red_op<OP>(r0, r1), red_op<OP>(r2, r3));
+}
+__device__ __forceinline__ double wave_sum(double v) { return wave_reduce<RED_SUM>(v); }
+__device__ __forceinline__ double wave_max(double v) { return wave_reduce<RED_MAX>(v); }
+__device__ __forceinline__ double wave_min(double v) { return wave_reduce<RED_MIN>(v); }
 
 }  // namespace surf

@@ -137,9 +137,12 @@ struct StepArgs {
 // characteristic, xi_U +- (1 - |u| dt/h)/2 minmod(dxi-, dxi+).
 template <typename R>
 __device__ __forceinline__ R adv_flux(R uf, R xLm, R xL, R xR, R xRp, R cfl_scale) {
-  R c = R(0.5) * (R(1) - fabs(uf) * cfl_scale);
-  R xf = uf > R(0) ? xL + c * minmod<R>(xL - xLm, xR - xL) : xR - c * minmod<R>(xR - xL, xRp - xR);
-  return uf * xf;
+  const bool pos = uf > R(0);
+  const R a = pos ? xLm : xRp;  // cell behind the upwind cell
+  const R b = pos ? xL : xR;    // upwind cell
+  const R c = pos ? xR : xL;    // downwind cell
+  const R k = R(0.5) * (R(1) - fabs(uf) * cfl_scale);
+  return uf * (b + k * minmod<R>(b - a, c - b));
 }
 
 // Paper-form anti-diffusion coefficient of a cell along d (section 3.2,
@@ -167,6 +170,8 @@ __device__ R paper_B(const Grid& g, const Par<R>& p, const R* __restrict__ chi, 
   return -(bulk_field ? p.Db : p.Ds) * w * p.inv_eps * nd;
 }
 
+// Per-workgroup partial record: wave reductions, then the NT/64 wave results
+// combined in wave order by threads 0..NPART-1.
 template <typename R, int NT>
 __device__ __forceinline__ void block_partials(double* v, double* out) {
   __shared__ double red[NT / 64][NPART];
@@ -438,9 +443,11 @@ struct FinalArgs {
   double h, eps, Dmax, ka, kd, ginf, cfl_a, cfl_d, dt;
 };
 
-__global__ void __launch_bounds__(BLOCK) k_finalize(FinalArgs f, const double* __restrict__ part,
-                                                    double* __restrict__ state,
-                                                    double* __restrict__ totals) {
+constexpr int FIN_BLOCK = 1024;
+
+__global__ void __launch_bounds__(FIN_BLOCK) k_finalize(FinalArgs f, const double* __restrict__ part,
+                                                        double* __restrict__ state,
+                                                        double* __restrict__ totals) {
   double v[NPART];
 #pragma unroll
   for (int s = 0; s < NPART; ++s) v[s] = 0.0;
@@ -448,7 +455,7 @@ __global__ void __launch_bounds__(BLOCK) k_finalize(FinalArgs f, const double* _
   v[P_MAX_C] = -INFINITY;
   v[P_MIN_F] = INFINITY;
   v[P_MIN_PSI] = INFINITY;
-  for (int b = threadIdx.x; b < f.nblk; b += BLOCK) {
+  for (int b = threadIdx.x; b < f.nblk; b += FIN_BLOCK) {
     const double* q = part + (long long)b * NPART;
 #pragma unroll
     for (int s = 0; s < NPART; ++s) {
@@ -458,7 +465,7 @@ __global__ void __launch_bounds__(BLOCK) k_finalize(FinalArgs f, const double* _
     }
   }
   __shared__ double tot[NPART];
-  block_partials<double, BLOCK>(v, tot);
+  block_partials<double, FIN_BLOCK>(v, tot);
   __syncthreads();
   if (threadIdx.x != 0) return;
   double vol = f.dim == 3 ? f.h * f.h * f.h : f.h * f.h;
@@ -478,7 +485,7 @@ __global__ void __launch_bounds__(BLOCK) k_finalize(FinalArgs f, const double* _
   double dta = su > 0 ? f.cfl_a * f.h / su : INFINITY;
   double dtd = f.cfl_d / lam;
   double bound = fmin(su > 0 ? f.h / su : INFINITY, 1.0 / lam);
-  unsigned status = (unsigned)state[S_STATUS];
+  unsigned status = (unsigned)state[S_STATUS] | *(const unsigned*)(state + S_FLAGS);
   if (tot[P_NBAD] > 0) status |= 1u;
   if ((f.bulk && tot[P_MIN_F] < 0) || tot[P_MIN_PSI] < 0) status |= 2u;
   if (f.dt > bound) status |= 4u;

@@ -1,0 +1,597 @@
+// surf_step2d.hpp -- the fused 2D step for gfx950: warm-started redistancing
+// of the moving interface (section 2.5), advection (section 3.1 substep 1),
+// confinement + diffusion + exchange (substep 2, sections 2.6 and 3.2,
+// Appendix C), equation of state (sections 2.3, 5, 6) and FP64 partial sums,
+// in one launch over 64 x 16 tiles.
+//
+// Far-field tiles.  Beyond the clamp |chi| <= chi_max the signed distance is
+// the constant s chi_max; a tile all of whose cells hold that value is
+// "quiescent" and is stored only as a per-tile flag (1: +chi_max inside fluid
+// 1, 2: -chi_max in the liquid, 0: field values live in the chi buffer).  A
+// tile whose own VoF is uniform and whose neighbour tiles were quiescent with
+// the same sign stays quiescent: K Jacobi sweeps cannot reach it from any
+// interface cell, since the warm start assumes the interface moved less than
+// the clamp distance in one step (a violation raises status bit 8).  Only the
+// other tiles run the K redistancing sweeps, temporally blocked in LDS on the
+// tile plus a (K + 2)-cell halo, which gives chi exactly (as K global Jacobi
+// sweeps would) on the tile plus the 2-cell halo the transport needs.
+#pragma once
+#include "surf_kernels.hpp"
+
+namespace surf {
+
+enum { Q_LIVE = 0, Q_POS = 1, Q_NEG = 2 };
+enum { STATUS_GEOM_JUMP = 8 };
+
+template <typename R>
+struct Step2dArgs {
+  Grid g;
+  Par<R> p;
+  const R* vof;      // VoF at t^{n+1} or nullptr (static geometry)
+  const R* chi_in;   // level set buffer of the current geometry
+  R* chi_out;        // moving geometry: buffer receiving chi^{n+1}
+  const uint8_t* q_in;
+  uint8_t* q_out;
+  const R* u[2];
+  const R* F;
+  const R* psi;
+  R* Fo;
+  R* Po;
+  R* sig;
+  double* part;      // [ntiles][NPART]
+  double* state;     // status bits for the jump flag
+  R dt;
+  R area_dt;
+  R dtau;
+  int has_u;
+  int ksweeps;       // sweeps this step (<= KH)
+  int tiles[2];
+  int ntiles;
+  int per_xcd;       // tiles per XCD chunk
+};
+
+// Paper-form anti-diffusion coefficient of halo-1 cell (cx, cy) along d
+// (section 3.2, Appendix C): B_F = -D_b (1-phi)/eps n_d, B_psi = -D_s
+// (1-2 phi)/eps n_d, n = -grad chi/|grad chi| by centred differences of the
+// level set held in LDS with a halo of at least 2.
+template <typename R>
+__device__ __forceinline__ R paper_B_lds(const R* chiL, int EXC, int HC, int cx, int cy, int d,
+                                         bool bulk_field, const Par<R>& p) {
+  int lc = (cx + HC - 1) + EXC * (cy + HC - 1);
+  R gx = (chiL[lc + 1] - chiL[lc - 1]) * (R(0.5) * p.inv_h);
+  R gy = (chiL[lc + EXC] - chiL[lc - EXC]) * (R(0.5) * p.inv_h);
+  R nrm = rsqrt_<R>(gx * gx + gy * gy);
+  nrm = nrm < R(1e-6) ? R(1e-6) : nrm;
+  R nd = -(d == 0 ? gx : gy) / nrm;
+  R ph, om, de;
+  phase<R>(chiL[lc], p, ph, om, de);
+  R w = bulk_field ? om : (om - ph);
+  return -(bulk_field ? p.Db : p.Ds) * w * p.inv_eps * nd;
+}
+
+template <int TX, int TY>
+__device__ __forceinline__ int tile_of(const Grid& g, int tilesx, int x, int y) {
+  return (x / TX) + tilesx * (y / TY);
+}
+
+template <typename R, int KH, int NT = 512, int TX = 64, int TY = 16>
+__global__ void __launch_bounds__(NT) k_step2d(Step2dArgs<R> a) {
+  // K sweeps reach K cells: within the 3 x 3 tile neighbourhood used to
+  // decide which tiles stay quiescent
+  static_assert(KH <= TY && KH <= TX, "sweeps must stay within the neighbour tiles");
+  constexpr int HC = KH > 0 ? KH + 2 : 2;        // chi halo held in LDS
+  constexpr int EXC = TX + 2 * HC, EYC = TY + 2 * HC, NC = EXC * EYC;
+  constexpr int EX3 = TX + 6, EY3 = TY + 6, N3 = EX3 * EY3;
+  constexpr int EX1 = TX + 2, EY1 = TY + 2, N1 = EX1 * EY1;
+  constexpr int NUX = (TX + 3) * EY1, NUY = EX1 * (TY + 3);
+  constexpr int I3 = (N3 + NT - 1) / NT, IUX = (NUX + NT - 1) / NT;
+  constexpr int IUY = (NUY + NT - 1) / NT, IC = (NC + NT - 1) / NT;
+  constexpr int IT = (TX * TY + NT - 1) / NT;
+  constexpr int RX = (HC + TX - 1) / TX, RY = (HC + TY - 1) / TY;   // flag neighbourhood
+  constexpr int QW = 2 * RX + 1, QN = QW * (2 * RY + 1);
+  // LDS: the final level set (tile + HC halo) stays live throughout; the
+  // redistancing scratch (second sweep buffer, VoF, pin data) and the
+  // transport arrays share one pool
+  constexpr int NTR = 2 * N3 + 3 * (NUX + NUY) + 4 * N1;
+  constexpr int NGEO = KH > 0 ? 3 * NC : 0;
+  constexpr int NPOOL = NGEO > NTR ? NGEO : NTR;
+  __shared__ R sChi[NC];
+  __shared__ R sPool[NPOOL];
+  __shared__ uint8_t sQ[QN];
+  R* sF3 = sPool;              // old F (halo 3), later c* in place
+  R* sP3 = sPool + N3;         // old psi (halo 3), later Gamma* in place
+  R* sUx = sPool + 2 * N3;     // x-face velocities of the halo-1 cells
+  R* sUy = sUx + NUX;          // y-face velocities
+  R* sFlx = sUy + NUY;         // x-face advective fluxes (F, psi)
+  R* sFly = sFlx + 2 * NUX;    // y-face advective fluxes (F, psi)
+  R* sC = sFly + 2 * NUY;      // F*, psi*, phi, delta (halo 1)
+
+  const Grid& g = a.g;
+  const Par<R>& p = a.p;
+  const bool bulk = p.bulk != 0;
+  const bool has_u = a.has_u != 0;
+  const int tid = threadIdx.x;
+  const int nx = g.n[0], ny = g.n[1];
+
+  // XCD-aware order: consecutive blocks land on different XCDs, so block b
+  // takes tile (b % 8) * per_xcd + b / 8 and each XCD walks a contiguous band
+  const int t = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
+  if (t >= a.ntiles) return;
+  const int tx = t % a.tiles[0], ty = t / a.tiles[0];
+  const int x0 = tx * TX, y0 = ty * TY;
+  const bool moving = KH > 0 && a.vof != nullptr;
+
+  // ---------------------------------------------------------- prefetch
+  // every input of the transport, loaded up front with independent loads
+  R rF[I3], rP[I3], rUx[IUX], rUy[IUY];
+#pragma unroll
+  for (int it = 0; it < I3; ++it) {
+    int l = tid + it * NT;
+    rF[it] = R(0);
+    rP[it] = R(0);
+    if (l < N3) {
+      int mx = map_axis(x0 + l % EX3 - 3, nx, g.bc[0][0], g.bc[0][1]);
+      int my = map_axis(y0 + l / EX3 - 3, ny, g.bc[1][0], g.bc[1][1]);
+      long long c = (long long)mx + (long long)nx * my;
+      if (bulk) rF[it] = a.F[c];
+      rP[it] = a.psi[c];
+    }
+  }
+  // face velocities: wrapped on periodic axes (the last face is face 0),
+  // zero on faces of ghost cells
+#pragma unroll
+  for (int it = 0; it < IUX; ++it) {
+    int l = tid + it * NT;
+    rUx[it] = R(0);
+    if (has_u && l < NUX) {
+      int gx = x0 + l % (TX + 3) - 1, gy = y0 + l / (TX + 3) - 1;
+      bool ok = true;
+      if (gx < 0) { if (g.bc[0][0] == BC_PERIODIC) gx += nx; else ok = false; }
+      if (gx > nx) { if (g.bc[0][1] == BC_PERIODIC) gx -= nx; else ok = false; }
+      if (gx == nx && g.bc[0][1] == BC_PERIODIC) gx = 0;
+      if (gy < 0 || gy >= ny) {
+        if (g.bc[1][gy < 0 ? 0 : 1] == BC_PERIODIC) gy = gy < 0 ? gy + ny : gy - ny; else ok = false;
+      }
+      if (ok) rUx[it] = a.u[0][(long long)gx + (long long)(nx + 1) * gy];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < IUY; ++it) {
+    int l = tid + it * NT;
+    rUy[it] = R(0);
+    if (has_u && l < NUY) {
+      int gx = x0 + l % EX1 - 1, gy = y0 + l / EX1 - 1;
+      bool ok = true;
+      if (gy < 0) { if (g.bc[1][0] == BC_PERIODIC) gy += ny; else ok = false; }
+      if (gy > ny) { if (g.bc[1][1] == BC_PERIODIC) gy -= ny; else ok = false; }
+      if (gy == ny && g.bc[1][1] == BC_PERIODIC) gy = 0;
+      if (gx < 0 || gx >= nx) {
+        if (g.bc[0][gx < 0 ? 0 : 1] == BC_PERIODIC) gx = gx < 0 ? gx + nx : gx - nx; else ok = false;
+      }
+      if (ok) rUy[it] = a.u[1][(long long)gx + (long long)nx * gy];
+    }
+  }
+  // quiescence flags of the neighbour tiles (255: outside a non-periodic side)
+  if (tid < QN) {
+    int ux = tx + tid % QW - RX, uy = ty + tid / QW - RY;
+    bool ok = true;
+    if (ux < 0 || ux >= a.tiles[0]) {
+      if (g.bc[0][ux < 0 ? 0 : 1] == BC_PERIODIC) ux = (ux + a.tiles[0]) % a.tiles[0]; else ok = false;
+    }
+    if (uy < 0 || uy >= a.tiles[1]) {
+      if (g.bc[1][uy < 0 ? 0 : 1] == BC_PERIODIC) uy = (uy + a.tiles[1]) % a.tiles[1]; else ok = false;
+    }
+    sQ[tid] = ok ? a.q_in[ux + a.tiles[0] * uy] : (uint8_t)255;
+  }
+  // own VoF: uniform 1, uniform 0 or mixed
+  bool all1 = true, all0 = true;
+  if (moving) {
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      int l = tid + it * NT;
+      int gx = x0 + l % TX, gy = y0 + l / TX;
+      if (l < TX * TY && gx < nx && gy < ny) {
+        R f = a.vof[(long long)gx + (long long)nx * gy];
+        all1 = all1 && f == R(1);
+        all0 = all0 && f == R(0);
+      }
+    }
+  }
+  __syncthreads();
+
+  // level set of a (mapped) cell: the clamp value on quiescent tiles
+  auto chi_at = [&](int gx, int gy) -> R {
+    int mx = map_axis(gx, nx, g.bc[0][0], g.bc[0][1]);
+    int my = map_axis(gy, ny, g.bc[1][0], g.bc[1][1]);
+    int dx = mx / TX - tx, dy = my / TY - ty;
+    if (dx > RX) dx -= a.tiles[0];
+    if (dx < -RX) dx += a.tiles[0];
+    if (dy > RY) dy -= a.tiles[1];
+    if (dy < -RY) dy += a.tiles[1];
+    uint8_t q = sQ[(dx + RX) + QW * (dy + RY)];
+    if (q == Q_POS) return p.chimax;
+    if (q == Q_NEG) return -p.chimax;
+    return a.chi_in[(long long)mx + (long long)nx * my];
+  };
+
+  // ---------------------------------------------------------- geometry
+  bool active = false;
+  if (moving) {
+    all1 = __syncthreads_and(all1);
+    all0 = __syncthreads_and(all0);
+    int want = all1 ? Q_POS : (all0 ? Q_NEG : -1);
+    bool quiet = true, nb_quiet = true;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        uint8_t q = sQ[(dx + RX) + QW * (dy + RY)];
+        if (q == 255) continue;
+        if ((int)q != want) quiet = false;
+        if (q == Q_LIVE) nb_quiet = false;
+      }
+    active = !quiet;
+    // the VoF changed under a tile whose whole neighbourhood was quiescent:
+    // the interface moved farther than the clamp distance in one step
+    if (tid == 0 && active && nb_quiet)
+      atomicOr((unsigned*)(a.state + S_FLAGS), (unsigned)STATUS_GEOM_JUMP);
+    if (!active) {
+      R v = want == Q_POS ? p.chimax : -p.chimax;
+      for (int l = tid; l < NC; l += NT) sChi[l] = v;
+      if (tid == 0) a.q_out[t] = (uint8_t)want;
+    }
+  }
+  if constexpr (KH > 0) {
+    if (active) {
+      R* sB = sPool;           // second sweep buffer
+      R* sV = sPool + NC;      // VoF, then
+      R* sG = sPool + 2 * NC;  // pin data
+      R rv[IC], rc[IC];
+#pragma unroll
+      for (int it = 0; it < IC; ++it) {
+        int l = tid + it * NT;
+        if (l < NC) {
+          int gx = x0 + l % EXC - HC, gy = y0 + l / EXC - HC;
+          int mx = map_axis(gx, nx, g.bc[0][0], g.bc[0][1]);
+          int my = map_axis(gy, ny, g.bc[1][0], g.bc[1][1]);
+          rv[it] = a.vof[(long long)mx + (long long)nx * my];
+          rc[it] = chi_at(gx, gy);
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < IC; ++it) {
+        int l = tid + it * NT;
+        if (l < NC) {
+          sV[l] = rv[it];
+          sChi[l] = rc[it];
+        }
+      }
+      __syncthreads();
+      // pin data on the tile + (HC - 1) halo: subcell distance of cut cells
+      // (Russo-Smereka), +-infinity carrying the sign elsewhere
+      for (int l = tid; l < NC; l += NT) {
+        int lx = l % EXC, ly = l / EXC;
+        if (lx < 1 || lx >= EXC - 1 || ly < 1 || ly >= EYC - 1) continue;
+        R c0 = (sV[l] - R(0.5)) * p.h;
+        R xm = (sV[l - 1] - R(0.5)) * p.h, xp = (sV[l + 1] - R(0.5)) * p.h;
+        R ym = (sV[l - EXC] - R(0.5)) * p.h, yp = (sV[l + EXC] - R(0.5)) * p.h;
+        bool cut = (c0 * xm <= R(0)) || (c0 * xp <= R(0)) || (c0 * ym <= R(0)) || (c0 * yp <= R(0));
+        R jump = fmax(fmax(fabs(xm - c0), fabs(xp - c0)), fmax(fabs(ym - c0), fabs(yp - c0)));
+        R cx = R(0.5) * (xp - xm), cy = R(0.5) * (yp - ym);
+        R Delta = fmax(fmax(rsqrt_<R>(cx * cx + cy * cy), jump), R(1e-30) * p.h);
+        sG[l] = cut ? p.h * c0 / Delta : (c0 > R(0) ? R(INFINITY) : R(-INFINITY));
+      }
+      __syncthreads();
+      // K Jacobi sweeps on shrinking regions
+      int cur = 0;
+      for (int k = 1; k <= a.ksweeps; ++k) {
+        const R* src = cur ? sB : sChi;
+        R* dst = cur ? sChi : sB;
+        int r = HC - k;  // halo of the region updated by this sweep
+        // only the region's cells: the next sweep reads nothing outside it
+        for (int l = tid; l < NC; l += NT) {
+          const int lx = l % EXC, ly = l / EXC;
+          if (lx < HC - r || lx >= HC + TX + r || ly < HC - r || ly >= HC + TY + r) continue;
+          R v = src[l];
+          {
+            R gv = sG[l];
+            if (fabs(gv) < R(INFINITY)) {
+              v = gv;
+            } else {
+              R x = v;
+              R bwx = (x - src[l - 1]) * p.inv_h, fwx = (src[l + 1] - x) * p.inv_h;
+              R bwy = (x - src[l - EXC]) * p.inv_h, fwy = (src[l + EXC] - x) * p.inv_h;
+              R sgn = gv > R(0) ? R(1) : R(-1);
+              // Godunov: upwind one-sided differences for the sign of chi0
+              R a1 = sgn * bwx, b1 = sgn * fwx, a2 = sgn * bwy, b2 = sgn * fwy;
+              R t1 = a1 > R(0) ? a1 * a1 : R(0), t2 = b1 < R(0) ? b1 * b1 : R(0);
+              R G2 = t1 > t2 ? t1 : t2;
+              t1 = a2 > R(0) ? a2 * a2 : R(0);
+              t2 = b2 < R(0) ? b2 * b2 : R(0);
+              G2 += t1 > t2 ? t1 : t2;
+              v = x - a.dtau * sgn * (rsqrt_<R>(G2) - R(1));
+            }
+            v = v > p.chimax ? p.chimax : v;
+            v = v < -p.chimax ? -p.chimax : v;
+          }
+          dst[l] = v;
+        }
+        __syncthreads();
+        cur ^= 1;
+      }
+      if (cur != 0) {
+        for (int l = tid; l < NC; l += NT) sChi[l] = sB[l];
+        __syncthreads();
+      }
+      // chi^{n+1} of the tile interior and its quiescence flag
+      bool allpos = true, allneg = true;
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        int l = tid + it * NT;
+        int ix = l % TX, iy = l / TX;
+        int gx = x0 + ix, gy = y0 + iy;
+        if (l < TX * TY && gx < nx && gy < ny) {
+          R v = sChi[(ix + HC) + EXC * (iy + HC)];
+          a.chi_out[(long long)gx + (long long)nx * gy] = v;
+          allpos = allpos && v == p.chimax;
+          allneg = allneg && v == -p.chimax;
+        }
+      }
+      allpos = __syncthreads_and(allpos);
+      allneg = __syncthreads_and(allneg);
+      if (tid == 0) a.q_out[t] = allpos ? Q_POS : (allneg ? Q_NEG : Q_LIVE);
+    }
+  }
+  if (!moving) {
+    // static geometry: the current level set on tile + 2 halo
+    R rc[IC];
+#pragma unroll
+    for (int it = 0; it < IC; ++it) {
+      int l = tid + it * NT;
+      rc[it] = R(0);
+      int lx = l % EXC, ly = l / EXC;
+      if (l < NC && lx >= HC - 2 && lx < HC + TX + 2 && ly >= HC - 2 && ly < HC + TY + 2)
+        rc[it] = chi_at(x0 + lx - HC, y0 + ly - HC);
+    }
+#pragma unroll
+    for (int it = 0; it < IC; ++it) {
+      int l = tid + it * NT;
+      if (l < NC) sChi[l] = rc[it];
+    }
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------- transport
+#pragma unroll
+  for (int it = 0; it < I3; ++it) {
+    int l = tid + it * NT;
+    if (l < N3) {
+      sF3[l] = rF[it];
+      sP3[l] = rP[it];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < IUX; ++it) {
+    int l = tid + it * NT;
+    if (l < NUX) sUx[l] = rUx[it];
+  }
+#pragma unroll
+  for (int it = 0; it < IUY; ++it) {
+    int l = tid + it * NT;
+    if (l < NUY) sUy[l] = rUy[it];
+  }
+  __syncthreads();
+
+  double acc[NPART];
+#pragma unroll
+  for (int s = 0; s < NPART; ++s) acc[s] = 0.0;
+  acc[P_MAX_C] = -INFINITY;
+  acc[P_MIN_F] = INFINITY;
+  acc[P_MIN_PSI] = INFINITY;
+
+  R* sF1 = sC;
+  R* sP1 = sC + N1;
+  R* sPhi = sC + 2 * N1;
+  R* sDel = sC + 3 * N1;
+  const R cfl = a.dt * p.inv_h;
+  const bool px = g.bc[0][0] == BC_PERIODIC, py = g.bc[1][0] == BC_PERIODIC;
+
+  // substep 1: the advective flux through every face of the halo-1 cells,
+  // once per face.  x-face fi (0..TX+2) of row fj lies between halo-1 cells
+  // fi-1 and fi; the cell on its + side is global (x0+fi-1, y0+fj-1).
+  if (has_u) {
+    for (int m = tid; m < NUX + NUY; m += NT) {
+      const bool xf = m < NUX;
+      const int mm = xf ? m : m - NUX;
+      const int fi = xf ? mm % (TX + 3) : mm % EX1;
+      const int fj = xf ? mm / (TX + 3) : mm / EX1;
+      const int gx = x0 + fi - 1, gy = y0 + fj - 1;
+      const int gd = xf ? gx : gy, nd = xf ? nx : ny;
+      const int gt = xf ? gy : gx, nt = xf ? ny : nx;
+      const bool per = xf ? px : py, pert = xf ? py : px;
+      const bool blo = !per && gd == 0, bhi = !per && gd == nd;
+      const bool ghost = (!per && (gd < 0 || gd > nd)) || (!pert && (gt < 0 || gt >= nt));
+      const R uf = xf ? sUx[mm] : sUy[mm];
+      const int st = xf ? 1 : EX3;
+      const int lp = (fi + 2) + EX3 * (fj + 2);
+      const int dd = xf ? 0 : 1;
+      R fF = R(0), fP = R(0);
+      if (!ghost) {
+        if (blo) {
+          if (g.bc[dd][0] == BC_OPEN) { fF = uf * sF3[lp]; fP = uf * sP3[lp]; }
+        } else if (bhi) {
+          if (g.bc[dd][1] == BC_OPEN) { fF = uf * sF3[lp - st]; fP = uf * sP3[lp - st]; }
+        } else {
+          fF = adv_flux<R>(uf, sF3[lp - 2 * st], sF3[lp - st], sF3[lp], sF3[lp + st], cfl);
+          fP = adv_flux<R>(uf, sP3[lp - 2 * st], sP3[lp - st], sP3[lp], sP3[lp + st], cfl);
+        }
+        if (!bulk) fF = R(0);
+        // open-boundary budget, counted by the tile owning the interior cell
+        const int fa = xf ? fi : fj, ta = xf ? TX : TY;
+        const bool own_t = xf ? (fj >= 1 && fj <= TY && gy < ny) : (fi >= 1 && fi <= TX && gx < nx);
+        if (own_t) {
+          if (blo && g.bc[dd][0] == BC_OPEN && fa >= 1 && fa <= ta)
+            acc[P_OUTFLOW] -= (double)(a.area_dt * (fF + fP));
+          if (bhi && g.bc[dd][1] == BC_OPEN && fa >= 2 && fa <= ta + 1)
+            acc[P_OUTFLOW] += (double)(a.area_dt * (fF + fP));
+        }
+      }
+      if (xf) { sFlx[mm] = fF; sFlx[NUX + mm] = fP; }
+      else { sFly[mm] = fF; sFly[NUY + mm] = fP; }
+    }
+    __syncthreads();
+  }
+
+  // advected state and phase field on the halo-1 cells; c* and Gamma* are
+  // written over the old state of the same cell (only that cell reads it)
+  for (int l = tid; l < N1; l += NT) {
+    const int lx = l % EX1, ly = l / EX1;
+    const int gx = x0 + lx - 1, gy = y0 + ly - 1;
+    R ph, om, de;
+    phase<R>(sChi[(lx + HC - 1) + EXC * (ly + HC - 1)], p, ph, om, de);
+    const int l3 = (lx + 2) + EX3 * (ly + 2);
+    const bool ghost = (!px && (gx < 0 || gx >= nx)) || (!py && (gy < 0 || gy >= ny));
+    R Fs = R(0), Ps = R(0);
+    if (!ghost) {
+      Fs = bulk ? sF3[l3] : R(0);
+      Ps = sP3[l3];
+      if (has_u) {
+        const int xl = lx + (TX + 3) * ly, yl = lx + EX1 * ly;
+        const R dF = (sFlx[xl + 1] - sFlx[xl]) + (sFly[yl + EX1] - sFly[yl]);
+        const R dP = (sFlx[NUX + xl + 1] - sFlx[NUX + xl]) + (sFly[NUY + yl + EX1] - sFly[NUY + yl]);
+        Fs = Fs - cfl * dF;
+        Ps = Ps - cfl * dP;
+        if (lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && gx < nx && gy < ny) {
+          // cell-mean velocity magnitudes (the literal upper face of a
+          // periodic axis)
+          R uxl = sUx[xl], uxh = sUx[xl + 1], uyl = sUy[yl], uyh = sUy[yl + EX1];
+          if (px && gx == nx - 1) uxh = a.u[0][(long long)nx + (long long)(nx + 1) * gy];
+          if (py && gy == ny - 1) uyh = a.u[1][(long long)gx + (long long)nx * ny];
+          double us = fabs((double)(R(0.5) * (uxl + uxh))) + fabs((double)(R(0.5) * (uyl + uyh)));
+          acc[P_MAX_USUM] = fmax(acc[P_MAX_USUM], us);
+        }
+      }
+    }
+    sF1[l] = bulk ? Fs : R(0);
+    sP1[l] = Ps;
+    sPhi[l] = ph;
+    sDel[l] = de;
+    sF3[l3] = rdiv<R>(Fs, ph + p.eta);
+    sP3[l3] = rdiv<R>(Ps, de + p.eta_eps);
+  }
+  __syncthreads();
+
+  // per-thread sums and extrema in the working precision (at most IT cells)
+  R sF = R(0), sP = R(0), sD = R(0), sSD = R(0), nbad = R(0);
+  R mxC = R(-INFINITY), mnF = R(INFINITY), mnP = R(INFINITY);
+  // substep 2 on the interior cells
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int l = tid + it * NT;
+    const int ix = l % TX, iy = l / TX;
+    const int gx = x0 + ix, gy = y0 + iy;
+    if (l >= TX * TY || gx >= nx || gy >= ny) continue;
+    const int c = (ix + 1) + EX1 * (iy + 1);
+    const int c3 = (ix + 3) + EX3 * (iy + 3);
+    const bool bxl = !px && gx == 0, bxh = !px && gx == nx - 1;
+    const bool byl = !py && gy == 0, byh = !py && gy == ny - 1;
+    R divF = R(0), divP = R(0);
+    if (p.form == FORM_W) {
+      const R cw = sF3[c3], gw = sP3[c3], pw = sPhi[c], dw = sDel[c];
+      R aF = R(0), aP = R(0);
+#define SURF_WFACE(o, o3, skip)                                    \
+      if (!(skip)) {                                               \
+        aF += (pw + sPhi[o]) * (sF3[o3] - cw);                     \
+        aP += (dw + sDel[o]) * (sP3[o3] - gw);                     \
+      }
+      SURF_WFACE(c - 1, c3 - 1, bxl)
+      SURF_WFACE(c + 1, c3 + 1, bxh)
+      SURF_WFACE(c - EX1, c3 - EX3, byl)
+      SURF_WFACE(c + EX1, c3 + EX3, byh)
+#undef SURF_WFACE
+      divF = p.Db * R(0.5) * aF * p.inv_h * p.inv_h;
+      divP = p.Ds * R(0.5) * aP * p.inv_h * p.inv_h;
+    } else {
+      // paper form: B from the centred chi gradient (chi held with halo 2)
+      const int cx = ix + 1, cy = iy + 1;
+      for (int f = 0; f < 2; ++f) {
+        if (f == 0 && !bulk) continue;
+        const R* x = f == 0 ? sF1 : sP1;
+        const R D = f == 0 ? p.Db : p.Ds;
+        R acc2 = R(0);
+        for (int d = 0; d < 2; ++d) {
+          const int st = d == 0 ? 1 : EX1;
+          const bool blo = d == 0 ? bxl : byl, bhi = d == 0 ? bxh : byh;
+          const R Bc = paper_B_lds<R>(sChi, EXC, HC, cx, cy, d, f == 0, p);
+          if (!blo) {
+            R Bm = paper_B_lds<R>(sChi, EXC, HC, cx - (d == 0), cy - (d == 1), d, f == 0, p);
+            R Bf = R(0.5) * (Bm + Bc);
+            acc2 -= D * (x[c] - x[c - st]) * p.inv_h + Bf * (Bf < R(0) ? x[c - st] : x[c]);
+          }
+          if (!bhi) {
+            R Bp = paper_B_lds<R>(sChi, EXC, HC, cx + (d == 0), cy + (d == 1), d, f == 0, p);
+            R Bf = R(0.5) * (Bc + Bp);
+            acc2 += D * (x[c + st] - x[c]) * p.inv_h + Bf * (Bf < R(0) ? x[c] : x[c + st]);
+          }
+        }
+        if (f == 0) divF = acc2 * p.inv_h; else divP = acc2 * p.inv_h;
+      }
+    }
+    const R Fs = sF1[c], Ps = sP1[c], ph = sPhi[c], de = sDel[c];
+    R q = R(0);
+    if (bulk) {
+      const R cs = sF3[c3];  // c* = F* / (phi + eta)
+      q = p.kin == KIN_LANGMUIR ? p.ka * cs * (p.ginf * de - Ps) - p.kd * Ps
+                                : p.ka * cs * p.ginf * de - p.kd * Ps;
+    }
+    const R Fn = bulk ? Fs + a.dt * (divF - q) : R(0);
+    const R Pn = Ps + a.dt * (divP + q);
+    const R sg = eos<R>(rdiv<R>(Pn, de + p.eta_eps), p);
+    const long long ci = (long long)gx + (long long)nx * gy;
+    if (bulk) a.Fo[ci] = Fn;
+    a.Po[ci] = Pn;
+    if (a.sig) a.sig[ci] = sg;
+    sF += Fn;
+    sP += Pn;
+    sD += de;
+    sSD += sg * de;
+    if (bulk) {
+      mxC = fmax(mxC, rdiv<R>(Fn, ph + p.eta));
+      mnF = fmin(mnF, Fn);
+    }
+    mnP = fmin(mnP, Pn);
+    const bool bad = !isfinite(Pn) || !isfinite(sg) || (bulk && !isfinite(Fn));
+    nbad += bad ? R(1) : R(0);
+  }
+  acc[P_SUM_F] = (double)sF;
+  acc[P_SUM_PSI] = (double)sP;
+  acc[P_SUM_DELTA] = (double)sD;
+  acc[P_SUM_SIGDELTA] = (double)sSD;
+  acc[P_MAX_C] = (double)mxC;
+  acc[P_MIN_F] = (double)mnF;
+  acc[P_MIN_PSI] = (double)mnP;
+  acc[P_NBAD] = (double)nbad;
+  block_partials<R, NT>(acc, a.part + (long long)t * NPART);
+}
+
+// Writes the clamp value into the level-set buffer for every quiescent tile
+// (consumers that read chi directly need the explicit field).
+template <typename R, int TX = 64, int TY = 16>
+__global__ void __launch_bounds__(BLOCK) k_materialize(Grid g, R* chi, const uint8_t* q, R chimax,
+                                                       int tilesx, int ntiles) {
+  int t = blockIdx.x;
+  if (t >= ntiles) return;
+  uint8_t f = q[t];
+  if (f == Q_LIVE) return;
+  R v = f == Q_POS ? chimax : -chimax;
+  int x0 = (t % tilesx) * TX, y0 = (t / tilesx) * TY;
+  for (int l = threadIdx.x; l < TX * TY; l += BLOCK) {
+    int gx = x0 + l % TX, gy = y0 + l / TX;
+    if (gx < g.n[0] && gy < g.n[1]) chi[(long long)gx + (long long)g.n[0] * gy] = v;
+  }
+}
+
+__global__ void k_fill_u8(uint8_t* q, uint8_t v, int n) {
+  int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) q[i] = v;
+}
+
+}  // namespace surf
