@@ -199,3 +199,77 @@ def run(prob, chi, u, F, psi, dt, nsteps, vof_seq=None, hj_iters=8, totals=None,
         F, psi, S, tot = step(prob, chi, un, F, psi, dt, tot)
         hist.append(tot.copy())
     return chi, F, psi, S, np.array(hist)
+
+
+# ---------------------------------------------------------------- adjoint
+def adjoint_step(prob, chi, u, F, psi, dt, mF, mP):
+    """lambda^n from lambda^{n+1} = (mF, mP) for the step from (F, psi);
+    returns (lF, lP, dtheta[4]) with dtheta = d/d(k_a, k_d, D_b, D_s)."""
+    ip, dp = pack(prob)
+    us = [None] * 3 if u is None else [None if v is None else _f64(v)
+                                       for v in (list(u) + [None] * 3)[:3]]
+    lF, lP = np.zeros(shape(prob)), np.zeros(shape(prob))
+    dth = np.zeros(4)
+    rc = lib().or_adjoint_step(_p(ip), _p(dp), _p(_f64(chi)), _p(us[0]), _p(us[1]), _p(us[2]),
+                               _p(_f64(F)), _p(_f64(psi)), ctypes.c_double(dt),
+                               _p(_f64(mF)), _p(_f64(mP)), _p(lF), _p(lP), _p(dth))
+    assert rc == 0
+    return lF, lP, dth
+
+
+def loss_grad(prob, chi, psi, w):
+    ip, dp = pack(prob)
+    g = np.zeros(shape(prob))
+    lib().or_loss_grad(_p(ip), _p(dp), _p(_f64(chi)), _p(_f64(psi)), ctypes.c_double(w), _p(g))
+    return g
+
+
+def with_theta(prob, theta):
+    q = dict(prob)
+    q["k_a"], q["k_d"], q["D_b"], q["D_s"] = (float(v) for v in theta)
+    return q
+
+
+def rollout(prob, chi, u, c0, gamma0, dt, nsteps, theta):
+    """Forward run from F0 = c0 phi, psi0 = gamma0 delta at parameters theta;
+    returns the states [x^0 .. x^N] and <sigma>^n for n = 1..N."""
+    q = with_theta(prob, theta)
+    F, P = init_state(q, chi, c0=c0, gamma0=gamma0)
+    states = [(F, P)]
+    sig = []
+    tot = np.zeros(16)
+    for _ in range(nsteps):
+        F, P, _, tot = step(q, chi, u, F, P, dt, tot)
+        states.append((F, P))
+        sig.append(tot[T_SAVG])
+    return states, np.array(sig)
+
+
+def sigma_history_loss(prob, chi, u, c0, gamma0, dt, nsteps, theta, target):
+    """L = mean over steps n = 1..N of (<sigma>^n - target^n)^2."""
+    _, sig = rollout(prob, chi, u, c0, gamma0, dt, nsteps, theta)
+    return float(np.mean((sig - target) ** 2))
+
+
+def sigma_history_grad(prob, chi, u, c0, gamma0, dt, nsteps, theta, target):
+    """Loss and its gradient with respect to theta (4) and the initial bulk
+    concentration field c0, by the discrete adjoint (all states stored)."""
+    q = with_theta(prob, theta)
+    states, sig = rollout(prob, chi, u, c0, gamma0, dt, nsteps, theta)
+    loss = float(np.mean((sig - target) ** 2))
+    phi, _, de = cell_geometry(q, chi)
+    sd = de.sum() * q["h"] ** q["dim"]
+    vol = q["h"] ** q["dim"]
+    # d<sigma>/dpsi_i = sigma'(Gamma_i) delta_i vol / (sum delta vol (delta_i + eta/eps))
+    w = lambda n: 2.0 / nsteps * (sig[n - 1] - target[n - 1]) * vol / sd
+    lF = np.zeros(shape(q))
+    lP = loss_grad(q, chi, states[nsteps][1], w(nsteps))
+    dth = np.zeros(4)
+    for n in range(nsteps - 1, -1, -1):
+        F, P = states[n]
+        lF, lP, d = adjoint_step(q, chi, u, F, P, dt, lF, lP)
+        dth += d
+        if n >= 1:
+            lP = lP + loss_grad(q, chi, P, w(n))
+    gc0 = lF * phi
+    return loss, dth, gc0

@@ -656,3 +656,224 @@ int or_force(const int* ip, const double* dp, const double* chi,
   free(del);
   return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Discrete adjoint of one step (weighted flux form) and the gradient  */
+/* of the interface-averaged surface tension                           */
+/* ------------------------------------------------------------------ */
+
+/* Linearisation of the advective flux through one face with the minmod
+ * branch frozen at the current state: flux = wa xi[a] + wb xi[b] + wc xi[c]
+ * (a behind the upwind cell b, c downwind).  Returns the number of cells
+ * used (0 wall, 1 open boundary, 3 interior) and the left/right cells of the
+ * face (-1 when outside the box). */
+static int flux_lin(const Prob* p, int d, int i, int j, int k, const double* u,
+                    const double* xi, double dt, long* cells, double* w,
+                    long* L, long* R) {
+  int c[3] = {i, j, k};
+  int fd = c[d], nd = p->n[d];
+  long fi = face(p, d, i, j, k);
+  int lo = fd == 0, hi = fd == nd;
+  *L = -1;
+  *R = -1;
+  if ((lo || hi) && p->bc[d][hi] != BC_PERIODIC) {
+    if (p->bc[d][hi] == BC_WALL) return 0;
+    int ci[3] = {i, j, k};
+    ci[d] = hi ? nd - 1 : 0;
+    long b = cell(p, ci[0], ci[1], ci[2]);
+    if (hi) *L = b; else *R = b;
+    cells[0] = b;
+    w[0] = u[fi];
+    return 1;
+  }
+  int cR[3] = {i, j, k};
+  if (fd == nd) cR[d] = 0;
+  long Rc = cell(p, cR[0], cR[1], cR[2]);
+  long Lc = nbr(p, cR[0], cR[1], cR[2], d, -1);
+  *L = Lc;
+  *R = Rc;
+  double uf = u[face(p, d, cR[0], cR[1], cR[2])];
+  int Uc[3] = {cR[0], cR[1], cR[2]};
+  double sg;
+  if (uf > 0.0) { Uc[d] = cR[d] - 1; if (Uc[d] < 0) Uc[d] += nd; sg = 1.0; }
+  else sg = -1.0;
+  long b = cell(p, Uc[0], Uc[1], Uc[2]);
+  long m = nbr(p, Uc[0], Uc[1], Uc[2], d, -1);
+  long q = nbr(p, Uc[0], Uc[1], Uc[2], d, +1);
+  /* slope g = minmod(s1, s2), s1 = (xi_b - xi_m)/h, s2 = (xi_q - xi_b)/h */
+  double s1 = (xi[b] - xi[m]) / p->h, s2 = (xi[q] - xi[b]) / p->h;
+  double sel1 = 0.0, sel2 = 0.0;
+  if (s1 * s2 > 0.0) {
+    if (fabs(s1) < fabs(s2)) sel1 = 1.0; else sel2 = 1.0;
+  }
+  /* xi_f = xi_b + kk (sel1 s1 + sel2 s2), kk = sg (h - |u| dt)/2 */
+  double kk = sg * 0.5 * (p->h - fabs(uf) * dt) / p->h;
+  cells[0] = m; w[0] = uf * (-kk * sel1);
+  cells[1] = b; w[1] = uf * (1.0 + kk * sel1 - kk * sel2);
+  cells[2] = q; w[2] = uf * (kk * sel2);
+  return 3;
+}
+
+/* lamF, lamP (the adjoint state at t^n) from mF, mP (at t^{n+1}) for the step
+ * taken from (F, psi) at t^n; adds dL/d(k_a, k_d, D_b, D_s) to dtheta.  The
+ * loss term of t^n is not included (see or_loss_grad). */
+int or_adjoint_step(const int* ip, const double* dp, const double* chi,
+                    const double* ux, const double* uy, const double* uz,
+                    const double* F, const double* psi, double dt,
+                    const double* mF, const double* mP, double* lF, double* lP,
+                    double* dtheta) {
+  Prob p = unpack(ip, dp);
+  if (p.form != FORM_WEIGHTED) return -1;
+  long N = p.ncell;
+  const double* u[3] = {ux, uy, uz};
+  double* phi = malloc(N * sizeof(double));
+  double* om = malloc(N * sizeof(double));
+  double* del = malloc(N * sizeof(double));
+  double* Fs = malloc(N * sizeof(double));
+  double* Ps = malloc(N * sizeof(double));
+  double* nF = malloc(N * sizeof(double));
+  double* nP = malloc(N * sizeof(double));
+  double* SF = calloc(N, sizeof(double));
+  double* SP = calloc(N, sizeof(double));
+  if (!phi || !om || !del || !Fs || !Ps || !nF || !nP || !SF || !SP) return -2;
+  or_cell_geometry(ip, dp, chi, phi, om, del);
+
+  /* forward substep 1 (the advected state the source and fluxes act on) */
+  if (ux) {
+    if (p.bulk) or_advect(ip, dp, ux, uy, uz, F, dt, Fs, NULL);
+    else memcpy(Fs, F, N * sizeof(double));
+    or_advect(ip, dp, ux, uy, uz, psi, dt, Ps, NULL);
+  } else {
+    memcpy(Fs, F, N * sizeof(double));
+    memcpy(Ps, psi, N * sizeof(double));
+  }
+
+  /* transpose of substep 2: nu = mu + dt (L^T mu + dq^T (mu_psi - mu_F)) */
+  for (long c = 0; c < N; ++c) {
+    nF[c] = mF[c];
+    nP[c] = mP[c];
+  }
+  for (int d = 0; d < p.dim; ++d) {
+    int m[3] = {p.n[0], p.n[1], p.n[2]};
+    m[d] += 1;
+    for (int k = 0; k < m[2]; ++k)
+      for (int j = 0; j < m[1]; ++j)
+        for (int i = 0; i < m[0]; ++i) {
+          int cc[3] = {i, j, k};
+          int fd = cc[d], nd = p.n[d];
+          if (fd == nd && p.bc[d][1] == BC_PERIODIC) continue; /* face 0 covers it */
+          if ((fd == 0 || fd == nd) && p.bc[d][fd == nd] != BC_PERIODIC) continue;
+          int cR[3] = {i, j, k};
+          long R = cell(&p, cR[0], cR[1], cR[2]);
+          long L = nbr(&p, cR[0], cR[1], cR[2], d, -1);
+          double h2 = p.h * p.h;
+          if (p.bulk) {
+            /* forward: F+_L += dt wF (c_R - c_L), F+_R -= dt wF (c_R - c_L) */
+            double wF = p.Db * 0.5 * (phi[L] + phi[R]) / h2;
+            double dmu = mF[L] - mF[R];
+            nF[R] += dt * wF * dmu / (phi[R] + p.eta);
+            nF[L] -= dt * wF * dmu / (phi[L] + p.eta);
+            double flux = 0.5 * (phi[L] + phi[R]) / h2 *
+                          (Fs[R] / (phi[R] + p.eta) - Fs[L] / (phi[L] + p.eta));
+            SF[L] += flux;
+            SF[R] -= flux;
+          }
+          double wP = p.Ds * 0.5 * (del[L] + del[R]) / h2;
+          double eL = del[L] + p.eta / p.eps, eR = del[R] + p.eta / p.eps;
+          double dmu = mP[L] - mP[R];
+          nP[R] += dt * wP * dmu / eR;
+          nP[L] -= dt * wP * dmu / eL;
+          double flux = 0.5 * (del[L] + del[R]) / h2 * (Ps[R] / eR - Ps[L] / eL);
+          SP[L] += flux;
+          SP[R] -= flux;
+        }
+  }
+  double dka = 0.0, dkd = 0.0, dDb = 0.0, dDs = 0.0;
+  for (long c = 0; c < N; ++c) {
+    double diff = mP[c] - mF[c];
+    if (p.bulk) {
+      double cs = Fs[c] / (phi[c] + p.eta);
+      double dqdF, dqdP, dqdka, dqdkd = -Ps[c];
+      if (p.kin == KIN_LANGMUIR) {
+        dqdF = p.ka * (p.ginf * del[c] - Ps[c]) / (phi[c] + p.eta);
+        dqdP = -p.ka * cs - p.kd;
+        dqdka = cs * (p.ginf * del[c] - Ps[c]);
+      } else {
+        dqdF = p.ka * p.ginf * del[c] / (phi[c] + p.eta);
+        dqdP = -p.kd;
+        dqdka = cs * p.ginf * del[c];
+      }
+      nF[c] += dt * dqdF * diff;
+      nP[c] += dt * dqdP * diff;
+      dka += dt * dqdka * diff;
+      dkd += dt * dqdkd * diff;
+      dDb += dt * SF[c] * mF[c];
+    }
+    dDs += dt * SP[c] * mP[c];
+  }
+  dtheta[0] += dka;
+  dtheta[1] += dkd;
+  dtheta[2] += dDb;
+  dtheta[3] += dDs;
+
+  /* transpose of substep 1 */
+  for (long c = 0; c < N; ++c) {
+    lF[c] = p.bulk ? nF[c] : mF[c];
+    lP[c] = nP[c];
+  }
+  if (ux) {
+    for (int d = 0; d < p.dim; ++d) {
+      int m[3] = {p.n[0], p.n[1], p.n[2]};
+      m[d] += 1;
+      for (int k = 0; k < m[2]; ++k)
+        for (int j = 0; j < m[1]; ++j)
+          for (int i = 0; i < m[0]; ++i) {
+            int cc[3] = {i, j, k};
+            if (cc[d] == p.n[d] && p.bc[d][1] == BC_PERIODIC) continue;
+            long cells[3], L, R;
+            double w[3];
+            for (int f = 0; f < 2; ++f) {
+              if (f == 0 && !p.bulk) continue;
+              const double* xi = f == 0 ? F : psi;
+              const double* nu = f == 0 ? nF : nP;
+              double* lam = f == 0 ? lF : lP;
+              int nc = flux_lin(&p, d, i, j, k, u[d], xi, dt, cells, w, &L, &R);
+              double g = (R >= 0 ? nu[R] : 0.0) - (L >= 0 ? nu[L] : 0.0);
+              for (int s = 0; s < nc; ++s) lam[cells[s]] += dt / p.h * w[s] * g;
+            }
+          }
+    }
+  }
+  free(phi); free(om); free(del); free(Fs); free(Ps); free(nF); free(nP);
+  free(SF); free(SP);
+  return 0;
+}
+
+/* derivative of the equation of state */
+static double eos_prime(const Prob* p, double G) {
+  double x = G / p->ginf;
+  if (p->eos == EOS_LINEAR) return -p->sigma0 * p->E / p->ginf;
+  if (p->eos == EOS_LANGMUIR) {
+    if (x <= 0.0 || x >= 1.0 - 1e-6) return 0.0; /* clamped */
+    return -p->sigma0 * p->E / (p->ginf * (1.0 - x));
+  }
+  double t = tanh(p->E * x);
+  return -p->sigma0 * p->E / p->ginf * (1.0 - t * t);
+}
+
+/* gP = w d<sigma>/dpsi * sum(delta) = w sigma'(Gamma) delta / (delta + eta/eps)
+ * where <sigma> = sum sigma delta / sum delta and Gamma = psi/(delta+eta/eps):
+ * the loss term of a step for the weight w = dL/d<sigma> / sum(delta). */
+int or_loss_grad(const int* ip, const double* dp, const double* chi, const double* psi,
+                 double w, double* gP) {
+  Prob p = unpack(ip, dp);
+  double* del = malloc(p.ncell * sizeof(double));
+  if (!del) return -2;
+  or_cell_geometry(ip, dp, chi, NULL, NULL, del);
+  for (long c = 0; c < p.ncell; ++c) {
+    double e = del[c] + p.eta / p.eps;
+    gP[c] = w * eos_prime(&p, psi[c] / e) * del[c] / e;
+  }
+  free(del);
+  return 0;
+}
