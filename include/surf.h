@@ -113,7 +113,7 @@ typedef struct {
   int32_t bulk_enabled; /* 0: insoluble (no bulk field, no exchange)      */
   int32_t hj_iters_init;/* redistancing sweeps for a full build (0: 2 ceil(chi_max/dtau)) */
   int32_t hj_iters_step;/* warm-start sweeps per step when the VoF moves (0: 8) */
-  int32_t pad_;
+  int32_t adjoint;      /* 1: reserve workspace for surf_adjoint_step         */
   double eps;           /* phase-field width (section 2.5)                */
   double D_b, D_s;      /* bulk and interfacial diffusivities             */
   double k_a, k_d;      /* adsorption and desorption rates                */
@@ -182,6 +182,42 @@ int surf_clear_status(surf_ctx* ctx);
 
 int surf_destroy(surf_ctx* ctx);
 const char* surf_strerror(int code);
+
+/* ---- Discrete adjoint (growth direction; weighted flux form only) ------
+ * Gradients of L = (1/N) sum_{n=1..N} (<sigma>^n - target^n)^2, with
+ * <sigma> = sum sigma delta / sum delta after step n, with respect to
+ * (k_a, k_d, D_b, D_s) and the initial bulk field c0 (F^0 = c0 phi), by the
+ * exact transpose of the discrete step: the advection with its minmod
+ * branches frozen at the state, substep 2 and the exchange source.  Needs
+ * params.adjoint = 1 at init, a static interface and a fixed dt. */
+
+/* Replaces (k_a, k_d, D_b, D_s) for the following calls. */
+int surf_set_kinetics(surf_ctx* ctx, double k_a, double k_d, double D_b, double D_s);
+
+/* From the forward totals of steps 1..N (rows of `stride` doubles, device)
+ * and the target history (N doubles, device): the loss weights
+ * w_n = dL/d<sigma>^n / sum(delta h^d) (N doubles, device) and the loss
+ * (1 double, device; may be NULL). */
+int surf_loss_weights(surf_ctx* ctx, const double* totals_hist, int64_t stride,
+                      const double* sigma_target, int32_t nsteps, double* w_out,
+                      double* loss_out);
+
+/* lambda^N: lamF = 0, lamPsi = w sigma'(Gamma) delta/(delta + eta/eps) at the
+ * state psi^N, w = &w_out[N-1] (device). */
+int surf_adjoint_seed(surf_ctx* ctx, const void* psi_N, const double* w_N, void* lamF,
+                      void* lamPsi);
+
+/* lambda^n from lambda^{n+1} for the step taken from (F_n, psi_n) with the
+ * face velocities u (NULL: no flow); adds the loss term of t^n when w_n is
+ * not NULL (device pointer to w_out[n-1]); adds dL/d(k_a, k_d, D_b, D_s) of
+ * this step to dtheta_dev (4 doubles, device).  lamF_n/lamPsi_n must not
+ * alias the inputs. */
+int surf_adjoint_step(surf_ctx* ctx, const void* const* u, const void* F_n, const void* psi_n,
+                      const void* lamF_np1, const void* lamPsi_np1, const double* w_n,
+                      void* lamF_n, void* lamPsi_n, double* dtheta_dev);
+
+/* dL/dc0 = lamF^0 phi (cell field). */
+int surf_adjoint_c0(surf_ctx* ctx, const void* lamF0, void* grad_c0);
 
 /* Kernel timing.  While enabled, every launch of the fused transport kernel
  * and of each redistancing sweep is bracketed by HIP events recorded on the

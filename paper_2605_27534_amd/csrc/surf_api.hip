@@ -11,6 +11,7 @@
 #include "../../include/surf.h"
 #include "surf_kernels.hpp"
 #include "surf_step2d.hpp"
+#include "surf_adjoint.hpp"
 
 using namespace surf;
 
@@ -37,6 +38,9 @@ struct surf_ctx {
   int ntiles2d;
   int per_xcd;
   bool materialized;  // chi[chi_cur] holds explicit values on every tile
+  // adjoint scratch: advected state, nu, per-workgroup dtheta partials
+  void* adj[4];
+  double* adj_part;
   // optional per-launch event timing
   bool profile;
   struct Mark { hipEvent_t a, b; int kind; };
@@ -389,6 +393,49 @@ int force_impl(surf_ctx* c, const void* sigma, void* const* force) {
 
 bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
+template <typename R>
+int adjoint_step_impl(surf_ctx* c, const void* const* u, const void* F, const void* psi,
+                      const void* mF, const void* mP, const double* w, void* lF, void* lP,
+                      double* dtheta) {
+  materialize<R>(c);
+  AdjArgs<R> a;
+  a.g = c->g;
+  a.p = make_par<R>(c);
+  a.chi = (const R*)c->chi[c->chi_cur];
+  a.has_u = (u && u[0]) ? 1 : 0;
+  for (int d = 0; d < 3; ++d) a.u[d] = (a.has_u && d < c->grid.dim) ? (const R*)u[d] : nullptr;
+  a.F = (const R*)F;
+  a.psi = (const R*)psi;
+  a.Fs = (const R*)c->adj[0];
+  a.Ps = (const R*)c->adj[1];
+  a.mF = (const R*)mF;
+  a.mP = (const R*)mP;
+  a.nF = (R*)c->adj[2];
+  a.nP = (R*)c->adj[3];
+  a.lF = (R*)lF;
+  a.lP = (R*)lP;
+  a.w = w;
+  a.part = c->adj_part;
+  a.dt = (R)c->dt;
+  a.ncell = c->ncell;
+  unsigned nb = grid1d(c->ncell);
+  if (a.has_u) {
+    hipLaunchKernelGGL(k_adv_star<R>, dim3(nb), dim3(BLOCK), 0, c->stream, a);
+  } else {
+    size_t bytes = (size_t)c->ncell * sizeof(R);
+    if (c->prm.bulk_enabled &&
+        hipMemcpyAsync(c->adj[0], F, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+      return SURF_EDEVICE;
+    if (hipMemcpyAsync(c->adj[1], psi, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+      return SURF_EDEVICE;
+  }
+  hipLaunchKernelGGL(k_adj_src<R>, dim3(nb), dim3(BLOCK), 0, c->stream, a);
+  hipLaunchKernelGGL(k_adj_adv<R>, dim3(nb), dim3(BLOCK), 0, c->stream, a);
+  hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(FIN_BLOCK), 0, c->stream,
+                     (const double*)c->adj_part, (int)nb, dtheta);
+  return status_of_launch();
+}
+
 }  // namespace
 
 extern "C" {
@@ -421,6 +468,10 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   b += align_up((size_t)npart * NPART * sizeof(double));
   b += 3 * align_up(n * es);
   b += 2 * align_up((size_t)n2 + 1);
+  if (params->adjoint) {
+    b += 4 * align_up(n * es);
+    b += align_up((size_t)((n + BLOCK - 1) / BLOCK) * NADJ * sizeof(double));
+  }
   *bytes = b;
   return SURF_OK;
 }
@@ -467,6 +518,12 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
   c->q[0] = (uint8_t*)p;
   p += align_up((size_t)c->ntiles2d + 1);
   c->q[1] = (uint8_t*)p;
+  p += align_up((size_t)c->ntiles2d + 1);
+  for (int i = 0; i < 4; ++i) {
+    c->adj[i] = params->adjoint ? (void*)p : nullptr;
+    if (params->adjoint) p += align_up(c->ncell * es);
+  }
+  c->adj_part = params->adjoint ? (double*)p : nullptr;
   c->materialized = true;
   c->chi_cur = 0;
   c->has_chi = false;
@@ -575,6 +632,78 @@ int surf_clear_status(surf_ctx* c) {
     return SURF_EDEVICE;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return SURF_EDEVICE;
   return SURF_OK;
+}
+
+int surf_set_kinetics(surf_ctx* c, double k_a, double k_d, double D_b, double D_s) {
+  if (!c || !(k_a >= 0) || !(k_d >= 0) || !(D_b >= 0) || !(D_s >= 0)) return SURF_EINVAL;
+  c->prm.k_a = k_a;
+  c->prm.k_d = k_d;
+  c->prm.D_b = D_b;
+  c->prm.D_s = D_s;
+  return SURF_OK;
+}
+
+int surf_loss_weights(surf_ctx* c, const double* tot, int64_t stride, const double* target,
+                      int32_t nsteps, double* w, double* loss) {
+  if (!c || !tot || !target || !w || nsteps <= 0 || stride < 16) return SURF_EINVAL;
+  double vol = c->grid.dim == 3 ? c->grid.h * c->grid.h * c->grid.h : c->grid.h * c->grid.h;
+  hipLaunchKernelGGL(k_loss_w, dim3(1), dim3(BLOCK), 0, c->stream, tot, (long long)stride, target,
+                     (int)nsteps, vol, w, loss);
+  return status_of_launch();
+}
+
+int surf_adjoint_seed(surf_ctx* c, const void* psi, const double* w, void* lF, void* lP) {
+  if (!c || !psi || !w || !lP) return SURF_EINVAL;
+  if (!c->prm.adjoint) return SURF_ESTATE;
+  if (!c->has_chi) return SURF_ESTATE;
+  long long n = c->ncell;
+  if (c->prm.precision == SURF_F64) {
+    materialize<double>(c);
+    hipLaunchKernelGGL(k_loss_seed<double>, dim3(grid1d(n)), dim3(BLOCK), 0, c->stream, c->g,
+                       make_par<double>(c), (const double*)c->chi[c->chi_cur], (const double*)psi,
+                       w, (double*)lF, (double*)lP, n);
+  } else {
+    materialize<float>(c);
+    hipLaunchKernelGGL(k_loss_seed<float>, dim3(grid1d(n)), dim3(BLOCK), 0, c->stream, c->g,
+                       make_par<float>(c), (const float*)c->chi[c->chi_cur], (const float*)psi, w,
+                       (float*)lF, (float*)lP, n);
+  }
+  return status_of_launch();
+}
+
+int surf_adjoint_step(surf_ctx* c, const void* const* u, const void* F, const void* psi,
+                      const void* mF, const void* mP, const double* w, void* lF, void* lP,
+                      double* dtheta) {
+  if (!c || !psi || !mP || !lP || !dtheta) return SURF_EINVAL;
+  if (!c->prm.adjoint || c->prm.flux_form != SURF_FLUX_WEIGHTED) return SURF_ESTATE;
+  if (!c->has_chi) return SURF_ESTATE;
+  bool bulk = c->prm.bulk_enabled != 0;
+  if (bulk && (!F || !mF || !lF)) return SURF_EINVAL;
+  if (lP == mP || lP == psi || (bulk && (lF == mF || lF == F))) return SURF_EINVAL;
+  if (u && u[0])
+    for (int d = 0; d < c->grid.dim; ++d)
+      if (!u[d]) return SURF_EINVAL;
+  if (c->prm.precision == SURF_F64)
+    return adjoint_step_impl<double>(c, u, F, psi, mF, mP, w, lF, lP, dtheta);
+  return adjoint_step_impl<float>(c, u, F, psi, mF, mP, w, lF, lP, dtheta);
+}
+
+int surf_adjoint_c0(surf_ctx* c, const void* lF0, void* gc0) {
+  if (!c || !lF0 || !gc0) return SURF_EINVAL;
+  if (!c->has_chi) return SURF_ESTATE;
+  long long n = c->ncell;
+  if (c->prm.precision == SURF_F64) {
+    materialize<double>(c);
+    hipLaunchKernelGGL(k_adj_c0<double>, dim3(grid1d(n)), dim3(BLOCK), 0, c->stream, c->g,
+                       make_par<double>(c), (const double*)c->chi[c->chi_cur],
+                       (const double*)lF0, (double*)gc0, n);
+  } else {
+    materialize<float>(c);
+    hipLaunchKernelGGL(k_adj_c0<float>, dim3(grid1d(n)), dim3(BLOCK), 0, c->stream, c->g,
+                       make_par<float>(c), (const float*)c->chi[c->chi_cur], (const float*)lF0,
+                       (float*)gc0, n);
+  }
+  return status_of_launch();
 }
 
 int surf_profile_enable(surf_ctx* c, int enable) {

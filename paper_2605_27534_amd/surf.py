@@ -33,7 +33,8 @@ EXPORTS = [
     "surf_workspace_bytes", "surf_init", "surf_set_geometry", "surf_set_levelset",
     "surf_get_levelset", "surf_init_state", "surf_step", "surf_force", "surf_set_dt",
     "surf_get_status", "surf_clear_status", "surf_destroy", "surf_strerror", "surf_version",
-    "surf_profile_enable", "surf_profile_read",
+    "surf_profile_enable", "surf_profile_read", "surf_set_kinetics", "surf_loss_weights",
+    "surf_adjoint_seed", "surf_adjoint_step", "surf_adjoint_c0",
 ]
 
 
@@ -53,7 +54,7 @@ class Params(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("flux_form", ctypes.c_int32),
                 ("kinetics", ctypes.c_int32), ("eos", ctypes.c_int32),
                 ("bulk_enabled", ctypes.c_int32), ("hj_iters_init", ctypes.c_int32),
-                ("hj_iters_step", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("hj_iters_step", ctypes.c_int32), ("adjoint", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("D_b", ctypes.c_double), ("D_s", ctypes.c_double),
                 ("k_a", ctypes.c_double), ("k_d", ctypes.c_double),
                 ("gamma_inf", ctypes.c_double), ("sigma0", ctypes.c_double),
@@ -90,6 +91,12 @@ def lib():
         L.surf_strerror.restype = ctypes.c_char_p
         L.surf_version.restype = ctypes.c_char_p
         L.surf_profile_enable.argtypes = [vp, i32]
+        d = ctypes.c_double
+        L.surf_set_kinetics.argtypes = [vp, d, d, d, d]
+        L.surf_loss_weights.argtypes = [vp, vp, ctypes.c_int64, vp, ctypes.c_int32, vp, vp]
+        L.surf_adjoint_seed.argtypes = [vp, vp, vp, vp, vp]
+        L.surf_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.surf_adjoint_c0.argtypes = [vp, vp, vp]
         L.surf_profile_read.argtypes = [vp, vp, vp, vp, vp]
         _lib = L
     return _lib
@@ -98,7 +105,7 @@ def lib():
 DEFAULTS = dict(flux_form=0, kinetics=0, eos=0, bulk_enabled=1, D_b=1e-2, D_s=1e-3,
                 k_a=1.0, k_d=1.0, gamma_inf=1.0, sigma0=1.0, eos_E=0.5, eta=1e-12,
                 chi_max_eps=12.0, cfl_adv=0.5, cfl_diff=0.8, hj_iters_init=0,
-                hj_iters_step=0)
+                hj_iters_step=0, adjoint=0)
 
 
 def make_structs(prob: dict, dt: float, precision: int):
@@ -117,7 +124,8 @@ def make_structs(prob: dict, dt: float, precision: int):
         g.origin[d] = org[d] if d < len(org) else 0.0
     p = Params()
     p.precision = precision
-    for k in ("flux_form", "kinetics", "eos", "bulk_enabled", "hj_iters_init", "hj_iters_step"):
+    for k in ("flux_form", "kinetics", "eos", "bulk_enabled", "hj_iters_init", "hj_iters_step",
+              "adjoint"):
         setattr(p, k, int(q[k]))
     for k in ("D_b", "D_s", "k_a", "k_d", "gamma_inf", "sigma0", "eos_E", "eta",
               "chi_max_eps", "cfl_adv", "cfl_diff"):
@@ -251,6 +259,38 @@ class Surf:
 
     def clear_status(self):
         self._check(self.L.surf_clear_status(self.ctx), "surf_clear_status")
+
+    # -- adjoint
+    def set_kinetics(self, k_a, k_d, D_b, D_s):
+        self._check(self.L.surf_set_kinetics(self.ctx, float(k_a), float(k_d), float(D_b),
+                                             float(D_s)), "surf_set_kinetics")
+
+    def loss_weights(self, totals_hist, target, w_out, loss_out=None):
+        n = int(target.numel())
+        self._check(self.L.surf_loss_weights(self.ctx, _ptr(totals_hist),
+                                             ctypes.c_int64(totals_hist.stride(0)),
+                                             _ptr(target), ctypes.c_int32(n), _ptr(w_out),
+                                             _ptr(loss_out)), "surf_loss_weights")
+
+    def adjoint_seed(self, psi, w, lamF, lamP):
+        self._check(self.L.surf_adjoint_seed(self.ctx, _ptr(self._cell(psi, "psi")), _ptr(w),
+                                             _ptr(self._cell(lamF, "lamF")),
+                                             _ptr(self._cell(lamP, "lamP"))), "surf_adjoint_seed")
+
+    def adjoint_step(self, F, psi, mF, mP, lF, lP, dtheta, u=None, w=None):
+        ua = self._faces(u, "u")
+        self._check(self.L.surf_adjoint_step(self.ctx, ua, _ptr(self._cell(F, "F")),
+                                             _ptr(self._cell(psi, "psi")),
+                                             _ptr(self._cell(mF, "mF")), _ptr(self._cell(mP, "mP")),
+                                             _ptr(w), _ptr(self._cell(lF, "lF")),
+                                             _ptr(self._cell(lP, "lP")), _ptr(dtheta)),
+                    "surf_adjoint_step")
+
+    def adjoint_c0(self, lF0):
+        out = self.empty()
+        self._check(self.L.surf_adjoint_c0(self.ctx, _ptr(self._cell(lF0, "lF0")), _ptr(out)),
+                    "surf_adjoint_c0")
+        return out
 
     def profile(self, enable=True):
         self._check(self.L.surf_profile_enable(self.ctx, int(enable)), "surf_profile_enable")

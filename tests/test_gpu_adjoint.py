@@ -1,0 +1,113 @@
+"""The GPU discrete adjoint (through the C ABI and the autograd wrapper)
+against the FP64 oracle adjoint and against central differences."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2605_27534_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def problem(dim):
+    if dim == 2:
+        n = (40, 34)
+        h = 1.0 / 40
+        prob = dict(dim=2, n=n, h=h, bc=((0, 0), (2, 2)), eos=1, eos_E=0.3)
+        chi = O.geometry(prob, synth.vof_ball(n, h, (0.5, 0.45, 0), 0.22, 2), 72)
+        u = synth.u_rotation(n, h, (0.5, 0.45, 0), 1.0)
+        u = [u[0] + 0.2, u[1] - 0.1]
+        c0 = 1 + 0.1 * synth.smooth_modes(n, h, 4, dim=2)
+        dt = 0.1 * h * h / 1e-2
+    else:
+        n = (16, 14, 12)
+        h = 1.0 / 16
+        prob = dict(dim=3, n=n, h=h, bc=((0, 0), (0, 0), (2, 2)), eos=1, eos_E=0.3)
+        chi = O.geometry(prob, synth.vof_ball(n, h, (0.5, 0.45, 0.4), 0.25, 3), 108)
+        u = synth.u_hadamard(n, h, (0.5, 0.45, 0.4), 0.25, -0.2, 0.01)
+        c0 = 1 + 0.1 * synth.smooth_modes(n, h, 4)
+        dt = 0.08 * h * h / 1e-2
+    return prob, chi, u, c0, dt, n, h
+
+
+def gpu_grad(prob, chi, u, c0, dt, N, theta, target, precision, K):
+    import torch
+    from paper_2605_27534_amd.adjoint import Rollout, SurfRollout
+    ro = Rollout(prob, dt, precision, chi=chi, u=u, gamma0=0.2, nsteps=N, checkpoint=K)
+    th = torch.tensor(theta, dtype=torch.float64, device="cuda", requires_grad=True)
+    c = torch.tensor(c0, dtype=ro.s.dtype, device="cuda", requires_grad=True)
+    tg = torch.tensor(target, dtype=torch.float64, device="cuda")
+    loss = SurfRollout.apply(th, c, ro, tg)
+    gth, gc = torch.autograd.grad(loss, (th, c))
+    return float(loss), gth.cpu().numpy(), gc.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_fp64_adjoint_matches_oracle(dim):
+    prob, chi, u, c0, dt, n, h = problem(dim)
+    N = 12
+    theta = np.array([1.3, 0.7, 0.012, 0.0008])
+    target = np.linspace(0.97, 0.93, N)
+    Lo, dto, gco = O.sigma_history_grad(prob, chi, u, c0, 0.2, dt, N, theta, target)
+    Lg, dtg, gcg = gpu_grad(prob, chi, u, c0, dt, N, theta, target, 1, 5)
+    assert abs(Lg - Lo) <= 1e-12 * Lo
+    assert np.max(np.abs(dtg - dto) / np.abs(dto)) <= 1e-10, (dtg, dto)
+    assert np.max(np.abs(gcg - gco)) <= 1e-10 * np.max(np.abs(gco))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_fp32_adjoint_against_fp64_oracle(dim):
+    # FP32 forward + adjoint against the FP64 oracle: the loss to 2e-5 and
+    # the gradients to 2e-4 relative (the gradient of a misfit is a difference
+    # of nearby sums, so it carries a larger relative error than the fields)
+    prob, chi, u, c0, dt, n, h = problem(dim)
+    N = 12
+    theta = np.array([1.3, 0.7, 0.012, 0.0008])
+    target = np.linspace(0.97, 0.93, N)
+    Lo, dto, gco = O.sigma_history_grad(prob, chi, u, c0, 0.2, dt, N, theta, target)
+    Lg, dtg, gcg = gpu_grad(prob, chi, u, c0, dt, N, theta, target, 0, 4)
+    assert abs(Lg - Lo) <= 2e-5 * Lo
+    assert np.max(np.abs(dtg - dto) / np.abs(dto)) <= 2e-4, (dtg, dto)
+    assert np.max(np.abs(gcg - gco)) <= 2e-4 * np.max(np.abs(gco))
+
+
+def test_checkpoint_interval_does_not_change_gradients():
+    prob, chi, u, c0, dt, n, h = problem(2)
+    N = 11
+    theta = np.array([1.0, 1.0, 0.01, 0.001])
+    target = np.linspace(0.97, 0.93, N)
+    ref = gpu_grad(prob, chi, u, c0, dt, N, theta, target, 0, N)
+    for K in (1, 3, 5):
+        g = gpu_grad(prob, chi, u, c0, dt, N, theta, target, 0, K)
+        assert g[0] == ref[0]
+        assert np.array_equal(g[1], ref[1]) and np.array_equal(g[2], ref[2])
+
+
+def test_gradients_match_central_differences_fp64():
+    # GPU FP64 forward differences on the four scalars and 8 seeded smooth
+    # directions of c0 against the adjoint
+    import torch
+    from paper_2605_27534_amd.adjoint import Rollout
+    prob, chi, u, c0, dt, n, h = problem(2)
+    N = 10
+    theta = np.array([1.3, 0.7, 0.012, 0.0008])
+    target = np.linspace(0.97, 0.93, N)
+    _, dtg, gcg = gpu_grad(prob, chi, u, c0, dt, N, theta, target, 1, 4)
+    ro = Rollout(prob, dt, 1, chi=chi, u=u, gamma0=0.2, nsteps=N, checkpoint=N)
+    tg = torch.tensor(target, dtype=torch.float64, device="cuda")
+
+    def L(th, c):
+        loss, _, _, _ = ro.forward(torch.tensor(th, device="cuda", dtype=torch.float64),
+                                   torch.tensor(c, device="cuda", dtype=torch.float64), tg)
+        return float(loss)
+
+    for k in range(4):
+        e = np.zeros(4)
+        e[k] = 1e-4 * theta[k]
+        fd = (L(theta + e, c0) - L(theta - e, c0)) / (2 * e[k])
+        assert abs(fd - dtg[k]) <= 1e-5 * abs(fd) + 1e-10, (k, fd, dtg[k])
+    for seed in range(44, 52):
+        v = synth.smooth_modes(n, h, seed, dim=2)
+        e = 1e-4
+        fd = (L(theta, c0 + e * v) - L(theta, c0 - e * v)) / (2 * e)
+        assert abs(fd - (gcg * v).sum()) <= 1e-5 * abs(fd) + 1e-10, seed
