@@ -219,6 +219,48 @@ int surf_adjoint_step(surf_ctx* ctx, const void* const* u, const void* F_n, cons
 /* dL/dc0 = lamF^0 phi (cell field). */
 int surf_adjoint_c0(surf_ctx* ctx, const void* lamF0, void* grad_c0);
 
+/* ---- Batched form (growth direction) -----------------------------------
+ * n_inst independent 2D problems (their own grid sizes, parameters and time
+ * steps; one precision), static interfaces, advanced together: each step is
+ * one persistent launch over the flattened queue of all their 64 x 16 tiles
+ * plus one per-instance reduction; surf_batch_step records nsteps of them in
+ * one HIP graph and replays it on later calls with the same step count. */
+
+/* Bytes of device workspace for the batch. */
+int surf_batch_workspace_bytes(int32_t n_inst, const surf_grid* grids, const surf_params* params,
+                               size_t* bytes);
+
+/* Validates every instance (dim 2, same precision, weighted or paper form)
+ * and carves the workspace.  F and psi: 2 n_inst device buffers each, the
+ * state pair of instance i at [2i] and [2i+1]; sigma: n_inst buffers or NULL.
+ * The state of instance i lives in buffer [2i + surf_batch_parity()]. */
+int surf_batch_create(surf_batch** batch, int32_t n_inst, const surf_grid* grids,
+                      const surf_params* params, void* const* F, void* const* psi,
+                      void* const* sigma, void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Full level-set build of instance i from its VoF field (section 2.5). */
+int surf_batch_set_geometry(surf_batch* batch, int32_t i, const void* vof);
+
+/* F = c0 phi, psi = gamma0 delta into buffer [2i]; resets the parity to 0
+ * (initialise every instance before stepping). */
+int surf_batch_init_state(surf_batch* batch, int32_t i, const void* c0, double c0_const,
+                          double gamma0);
+
+/* nsteps steps of every instance; totals_dev ([n_inst][16] doubles, device,
+ * may be NULL) receives the totals of the last step. */
+int surf_batch_step(surf_batch* batch, int32_t nsteps, double* totals_dev);
+
+/* Which buffer of each pair holds the current state (0 or 1). */
+int surf_batch_parity(surf_batch* batch);
+
+/* Times the candidate launch shapes (threads per workgroup, persistent
+ * workgroup count) on the bound buffers with HIP events and keeps the
+ * fastest; results are unchanged by the choice.  *choice (may be NULL)
+ * receives its index; times_us (may be NULL) one time per candidate. */
+int surf_batch_tune(surf_batch* batch, int32_t* choice, double* times_us, int32_t max_times);
+
+int surf_batch_destroy(surf_batch* batch);
+
 /* Kernel timing.  While enabled, every launch of the fused transport kernel
  * and of each redistancing sweep is bracketed by HIP events recorded on the
  * context stream.  surf_profile_read waits for the recorded events, returns

@@ -48,6 +48,40 @@ struct surf_ctx {
   std::vector<hipEvent_t> pool;
 };
 
+struct surf_batch {
+  int n = 0;
+  int prec = 0;
+  std::vector<surf_grid> grids;
+  std::vector<surf_params> prm;
+  hipStream_t stream = nullptr;
+  double* states = nullptr;
+  double* part = nullptr;
+  void* inst_tab = nullptr;
+  int2* queue = nullptr;
+  void* fargs = nullptr;
+  int* first = nullptr;
+  void* scratch[2] = {nullptr, nullptr};
+  std::vector<void*> chi;
+  std::vector<uint8_t*> q;
+  std::vector<int> ntiles, tx;
+  int total_tiles = 0;
+  std::vector<char> host_inst;
+  std::vector<int2> host_queue;
+  std::vector<char> host_fargs;
+  std::vector<int> host_first;
+  std::vector<void*> F, P, S;
+  int parity = 0;
+  int nt = 512;      // threads per workgroup
+  int grid = 0;      // persistent workgroups
+  struct Graph {
+    int nsteps, parity;
+    double* totals;
+    hipGraph_t g;
+    hipGraphExec_t e;
+  };
+  std::vector<Graph> graphs;
+};
+
 namespace {
 
 constexpr size_t ALIGN = 256;
@@ -393,6 +427,44 @@ int force_impl(surf_ctx* c, const void* sigma, void* const* force) {
 
 bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
+// ---------------------------------------------------------------- batches
+Grid grid_of(const surf_grid& gr) {
+  Grid g;
+  g.dim = gr.dim;
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = gr.n[d];
+    g.bc[d][0] = d < gr.dim ? gr.bc[d][0] : 0;
+    g.bc[d][1] = d < gr.dim ? gr.bc[d][1] : 0;
+  }
+  return g;
+}
+
+template <typename R>
+Par<R> par_of(const surf_grid& gr, const surf_params& q) {
+  surf_ctx tmp;
+  tmp.grid = gr;
+  tmp.prm = q;
+  return make_par<R>(&tmp);
+}
+
+FinalArgs final_of(const surf_grid& gr, const surf_params& q, int nblk) {
+  FinalArgs f;
+  f.nblk = nblk;
+  f.dim = gr.dim;
+  f.bulk = q.bulk_enabled ? 1 : 0;
+  f.form = q.flux_form;
+  f.h = gr.h;
+  f.eps = q.eps;
+  f.Dmax = f.bulk ? std::fmax(q.D_b, q.D_s) : q.D_s;
+  f.ka = q.k_a;
+  f.kd = q.k_d;
+  f.ginf = q.gamma_inf;
+  f.cfl_a = q.cfl_adv;
+  f.cfl_d = q.cfl_diff;
+  f.dt = q.dt;
+  return f;
+}
+
 template <typename R>
 int adjoint_step_impl(surf_ctx* c, const void* const* u, const void* F, const void* psi,
                       const void* mF, const void* mP, const double* w, void* lF, void* lP,
@@ -704,6 +776,336 @@ int surf_adjoint_c0(surf_ctx* c, const void* lF0, void* gc0) {
                        (float*)gc0, n);
   }
   return status_of_launch();
+}
+
+}  // extern "C"
+
+namespace {
+
+struct BatchLayout {
+  size_t total = 0;
+  size_t states, part, inst, queue, fargs, first, scratch0, scratch1;
+  std::vector<size_t> chi, q;
+  int total_tiles = 0;
+};
+
+int batch_layout(int32_t n, const surf_grid* grids, const surf_params* prm, BatchLayout* L) {
+  if (n <= 0 || !grids || !prm) return SURF_EINVAL;
+  size_t es = esize(&prm[0]);
+  size_t maxcell = 0, off = 0;
+  int tt = 0;
+  L->chi.resize(n);
+  L->q.resize(n);
+  for (int i = 0; i < n; ++i) {
+    int rc = check_grid_params(&grids[i], &prm[i]);
+    if (rc) return rc;
+    if (grids[i].dim != 2 || prm[i].precision != prm[0].precision) return SURF_EINVAL;
+    int t2[2];
+    tt += ntiles_2d(&grids[i], t2);
+    size_t nc = (size_t)grids[i].n[0] * grids[i].n[1];
+    if (nc > maxcell) maxcell = nc;
+  }
+  size_t inst_bytes = prm[0].precision == SURF_F64 ? sizeof(Step2dArgs<double>) : sizeof(Step2dArgs<float>);
+  L->states = off; off += align_up((size_t)n * NSTATE * sizeof(double));
+  L->part = off; off += align_up((size_t)tt * NPART * sizeof(double));
+  L->inst = off; off += align_up((size_t)n * inst_bytes);
+  L->queue = off; off += align_up((size_t)tt * sizeof(int2));
+  L->fargs = off; off += align_up((size_t)n * sizeof(FinalArgs));
+  L->first = off; off += align_up((size_t)n * sizeof(int));
+  L->scratch0 = off; off += align_up(maxcell * es);
+  L->scratch1 = off; off += align_up(maxcell * es);
+  for (int i = 0; i < n; ++i) {
+    int t2[2];
+    int nt2 = ntiles_2d(&grids[i], t2);
+    L->chi[i] = off; off += align_up((size_t)grids[i].n[0] * grids[i].n[1] * es);
+    L->q[i] = off; off += align_up((size_t)nt2 + 1);
+  }
+  L->total = off;
+  L->total_tiles = tt;
+  return SURF_OK;
+}
+
+template <typename R>
+void batch_tables(surf_batch* b) {
+  b->host_inst.resize(sizeof(Step2dArgs<R>) * b->n);
+  b->host_fargs.resize(sizeof(FinalArgs) * b->n);
+  b->host_first.resize(b->n);
+  b->host_queue.clear();
+  for (int i = 0; i < b->n; ++i) {
+    const surf_grid& gr = b->grids[i];
+    const surf_params& q = b->prm[i];
+    Step2dArgs<R> a{};
+    a.g = grid_of(gr);
+    a.p = par_of<R>(gr, q);
+    a.vof = nullptr;
+    a.chi_in = (const R*)b->chi[i];
+    a.chi_out = nullptr;
+    a.q_in = b->q[i];
+    a.q_out = b->q[i];
+    a.u[0] = a.u[1] = nullptr;
+    a.F = (const R*)b->F[2 * i];
+    a.Fo = (R*)b->F[2 * i + 1];
+    a.psi = (const R*)b->P[2 * i];
+    a.Po = (R*)b->P[2 * i + 1];
+    a.sig = b->S.empty() ? nullptr : (R*)b->S[i];
+    a.part = nullptr;
+    a.state = b->states + (size_t)i * NSTATE;
+    a.dt = (R)q.dt;
+    a.area_dt = (R)(gr.h * q.dt);
+    a.dtau = (R)(gr.h / 2);
+    a.has_u = 0;
+    a.ksweeps = 0;
+    int t2[2];
+    a.ntiles = ntiles_2d(&gr, t2);
+    a.tiles[0] = t2[0];
+    a.tiles[1] = t2[1];
+    a.per_xcd = (a.ntiles + 7) / 8;
+    std::memcpy(b->host_inst.data() + sizeof(a) * i, &a, sizeof(a));
+    b->host_first[i] = (int)b->host_queue.size();
+    for (int t = 0; t < a.ntiles; ++t) b->host_queue.push_back(make_int2(i, t));
+    FinalArgs f = final_of(gr, q, a.ntiles);
+    std::memcpy(b->host_fargs.data() + sizeof(f) * i, &f, sizeof(f));
+  }
+}
+
+template <typename R>
+void batch_launch_step(surf_batch* b, int nt, int grid, int parity) {
+  if (nt == 256)
+    hipLaunchKernelGGL((k_batch2d<R, 256>), dim3(grid), dim3(256), 0, b->stream,
+                       (const Step2dArgs<R>*)b->inst_tab, (const int2*)b->queue, b->total_tiles,
+                       parity, b->part);
+  else
+    hipLaunchKernelGGL((k_batch2d<R, 512>), dim3(grid), dim3(512), 0, b->stream,
+                       (const Step2dArgs<R>*)b->inst_tab, (const int2*)b->queue, b->total_tiles,
+                       parity, b->part);
+}
+
+void batch_step_kernels(surf_batch* b, int parity, double* totals) {
+  if (b->prec == SURF_F64) batch_launch_step<double>(b, b->nt, b->grid, parity);
+  else batch_launch_step<float>(b, b->nt, b->grid, parity);
+  hipLaunchKernelGGL(k_batch_final, dim3(b->n), dim3(FIN_BLOCK), 0, b->stream,
+                     (const FinalArgs*)b->fargs, (const int*)b->first, (const double*)b->part,
+                     b->states, totals);
+}
+
+void batch_drop_graphs(surf_batch* b) {
+  for (auto& g : b->graphs) {
+    (void)hipGraphExecDestroy(g.e);
+    (void)hipGraphDestroy(g.g);
+  }
+  b->graphs.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+int surf_batch_workspace_bytes(int32_t n, const surf_grid* grids, const surf_params* params,
+                               size_t* bytes) {
+  if (!bytes) return SURF_EINVAL;
+  BatchLayout L;
+  int rc = batch_layout(n, grids, params, &L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return SURF_OK;
+}
+
+int surf_batch_create(surf_batch** out, int32_t n, const surf_grid* grids,
+                      const surf_params* params, void* const* F, void* const* psi,
+                      void* const* sigma, void* workspace, size_t ws_bytes, void* stream) {
+  if (!out) return SURF_EINVAL;
+  *out = nullptr;
+  BatchLayout L;
+  int rc = batch_layout(n, grids, params, &L);
+  if (rc) return rc;
+  if (!F || !psi || !workspace || !aligned(workspace, ALIGN)) return SURF_EINVAL;
+  if (ws_bytes < L.total) return SURF_ENOMEM;
+  for (int i = 0; i < 2 * n; ++i)
+    if (!psi[i] || (params[i / 2].bulk_enabled && !F[i])) return SURF_EINVAL;
+  surf_batch* b = new (std::nothrow) surf_batch();
+  if (!b) return SURF_EINVAL;
+  b->n = n;
+  b->prec = params[0].precision;
+  b->stream = (hipStream_t)stream;
+  for (int i = 0; i < n; ++i) {
+    b->grids.push_back(grids[i]);
+    b->prm.push_back(with_defaults(&params[i], 2));
+  }
+  char* base = (char*)workspace;
+  b->states = (double*)(base + L.states);
+  b->part = (double*)(base + L.part);
+  b->inst_tab = base + L.inst;
+  b->queue = (int2*)(base + L.queue);
+  b->fargs = base + L.fargs;
+  b->first = (int*)(base + L.first);
+  b->scratch[0] = base + L.scratch0;
+  b->scratch[1] = base + L.scratch1;
+  for (int i = 0; i < n; ++i) {
+    b->chi.push_back(base + L.chi[i]);
+    b->q.push_back((uint8_t*)(base + L.q[i]));
+  }
+  b->total_tiles = L.total_tiles;
+  for (int i = 0; i < 2 * n; ++i) {
+    b->F.push_back(F[i]);
+    b->P.push_back(psi[i]);
+  }
+  if (sigma)
+    for (int i = 0; i < n; ++i) b->S.push_back(sigma[i]);
+  if (b->prec == SURF_F64) batch_tables<double>(b);
+  else batch_tables<float>(b);
+  b->grid = b->total_tiles < 2048 ? b->total_tiles : 2048;
+  bool ok = hipMemcpyAsync(b->inst_tab, b->host_inst.data(), b->host_inst.size(),
+                           hipMemcpyHostToDevice, b->stream) == hipSuccess &&
+            hipMemcpyAsync(b->queue, b->host_queue.data(), b->host_queue.size() * sizeof(int2),
+                           hipMemcpyHostToDevice, b->stream) == hipSuccess &&
+            hipMemcpyAsync(b->fargs, b->host_fargs.data(), b->host_fargs.size(),
+                           hipMemcpyHostToDevice, b->stream) == hipSuccess &&
+            hipMemcpyAsync(b->first, b->host_first.data(), b->host_first.size() * sizeof(int),
+                           hipMemcpyHostToDevice, b->stream) == hipSuccess;
+  if (!ok || hipStreamSynchronize(b->stream) != hipSuccess) {
+    delete b;
+    return SURF_EDEVICE;
+  }
+  for (int i = 0; i < n; ++i)
+    hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, b->stream, b->states + (size_t)i * NSTATE);
+  *out = b;
+  return status_of_launch();
+}
+
+int surf_batch_set_geometry(surf_batch* b, int32_t i, const void* vof) {
+  if (!b || !vof || i < 0 || i >= b->n) return SURF_EINVAL;
+  // a throw-away context over the batch's buffers drives the global sweeps
+  surf_ctx c;
+  c.grid = b->grids[i];
+  c.prm = b->prm[i];
+  c.g = grid_of(c.grid);
+  c.stream = b->stream;
+  c.ncell = (long long)c.grid.n[0] * c.grid.n[1];
+  c.chi[0] = b->chi[i];
+  c.chi[1] = b->scratch[1];
+  c.g0 = b->scratch[0];
+  c.chi_cur = 0;
+  c.has_chi = false;
+  c.materialized = true;
+  c.ntiles2d = 0;
+  c.profile = false;
+  int rc = c.prm.precision == SURF_F64 ? geometry_impl<double>(&c, vof, 1)
+                                       : geometry_impl<float>(&c, vof, 1);
+  if (rc) return rc;
+  if (c.chi_cur != 0) {
+    size_t bytes = (size_t)c.ncell * esize(&c.prm);
+    if (hipMemcpyAsync(b->chi[i], b->scratch[1], bytes, hipMemcpyDeviceToDevice, b->stream) !=
+        hipSuccess)
+      return SURF_EDEVICE;
+  }
+  int t2[2];
+  int nt2 = ntiles_2d(&b->grids[i], t2);
+  hipLaunchKernelGGL(k_fill_u8, dim3((nt2 + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, b->stream, b->q[i],
+                     (uint8_t)Q_LIVE, nt2);
+  return status_of_launch();
+}
+
+int surf_batch_init_state(surf_batch* b, int32_t i, const void* c0, double c0_const,
+                          double gamma0) {
+  if (!b || i < 0 || i >= b->n) return SURF_EINVAL;
+  long long n = (long long)b->grids[i].n[0] * b->grids[i].n[1];
+  const surf_grid& gr = b->grids[i];
+  const surf_params& q = b->prm[i];
+  void* F = q.bulk_enabled ? b->F[2 * i] : nullptr;
+  if (b->prec == SURF_F64)
+    hipLaunchKernelGGL(k_init<double>, dim3(grid1d(n)), dim3(BLOCK), 0, b->stream, grid_of(gr),
+                       par_of<double>(gr, q), (const double*)b->chi[i], (const double*)c0,
+                       c0_const, gamma0, (double*)F, (double*)b->P[2 * i], n);
+  else
+    hipLaunchKernelGGL(k_init<float>, dim3(grid1d(n)), dim3(BLOCK), 0, b->stream, grid_of(gr),
+                       par_of<float>(gr, q), (const float*)b->chi[i], (const float*)c0,
+                       (float)c0_const, (float)gamma0, (float*)F, (float*)b->P[2 * i], n);
+  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, b->stream, b->states + (size_t)i * NSTATE);
+  b->parity = 0;
+  return status_of_launch();
+}
+
+int surf_batch_step(surf_batch* b, int32_t nsteps, double* totals) {
+  if (!b || nsteps <= 0) return SURF_EINVAL;
+  if (!b->stream) {
+    // no graph capture on the null stream: launch eagerly
+    for (int k = 0; k < nsteps; ++k)
+      batch_step_kernels(b, (b->parity + k) & 1, k == nsteps - 1 ? totals : nullptr);
+    b->parity ^= nsteps & 1;
+    return status_of_launch();
+  }
+  surf_batch::Graph* gr = nullptr;
+  for (auto& g : b->graphs)
+    if (g.nsteps == nsteps && g.parity == b->parity && g.totals == totals) gr = &g;
+  if (!gr) {
+    surf_batch::Graph g{nsteps, b->parity, totals, nullptr, nullptr};
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return SURF_EDEVICE;
+    for (int k = 0; k < nsteps; ++k)
+      batch_step_kernels(b, (b->parity + k) & 1, k == nsteps - 1 ? totals : nullptr);
+    if (hipStreamEndCapture(b->stream, &g.g) != hipSuccess) return SURF_EDEVICE;
+    if (hipGraphInstantiate(&g.e, g.g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g.g);
+      return SURF_EDEVICE;
+    }
+    b->graphs.push_back(g);
+    gr = &b->graphs.back();
+  }
+  if (hipGraphLaunch(gr->e, b->stream) != hipSuccess) return SURF_EDEVICE;
+  b->parity ^= nsteps & 1;
+  return SURF_OK;
+}
+
+int surf_batch_parity(surf_batch* b) { return b ? b->parity : SURF_EINVAL; }
+
+int surf_batch_tune(surf_batch* b, int32_t* choice, double* times_us, int32_t max_times) {
+  if (!b) return SURF_EINVAL;
+  const int T = b->total_tiles;
+  const int cand[][2] = {{256, T}, {512, T}, {512, T < 512 ? T : 512},
+                         {512, T < 1024 ? T : 1024}, {256, T < 2048 ? T : 2048},
+                         {512, T < 2048 ? T : 2048}};
+  const int nc = (int)(sizeof(cand) / sizeof(cand[0]));
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SURF_EDEVICE;
+  int best = 0;
+  double best_t = 1e300;
+  for (int k = 0; k < nc; ++k) {
+    // reads the current buffers and writes the other ones: the state is
+    // untouched and the next step overwrites the scratch results
+    auto run = [&]() {
+      if (b->prec == SURF_F64) batch_launch_step<double>(b, cand[k][0], cand[k][1], b->parity);
+      else batch_launch_step<float>(b, cand[k][0], cand[k][1], b->parity);
+    };
+    run();
+    (void)hipEventRecord(e0, b->stream);
+    for (int r = 0; r < 3; ++r) run();
+    (void)hipEventRecord(e1, b->stream);
+    if (hipEventSynchronize(e1) != hipSuccess) return SURF_EDEVICE;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    double us = ms * 1e3 / 3;
+    if (times_us && k < max_times) times_us[k] = us;
+    if (us < best_t) {
+      best_t = us;
+      best = k;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->nt = cand[best][0];
+  b->grid = cand[best][1];
+  batch_drop_graphs(b);
+  if (choice) *choice = best;
+  return status_of_launch();
+}
+
+int surf_batch_destroy(surf_batch* b) {
+  if (!b) return SURF_OK;
+  // graphs may still be in flight on the stream
+  (void)hipStreamSynchronize(b->stream);
+  batch_drop_graphs(b);
+  delete b;
+  return SURF_OK;
 }
 
 int surf_profile_enable(surf_ctx* c, int enable) {

@@ -445,9 +445,9 @@ struct FinalArgs {
 
 constexpr int FIN_BLOCK = 1024;
 
-__global__ void __launch_bounds__(FIN_BLOCK) k_finalize(FinalArgs f, const double* __restrict__ part,
-                                                        double* __restrict__ state,
-                                                        double* __restrict__ totals) {
+__device__ __forceinline__ void finalize_body(const FinalArgs& f, const double* __restrict__ part,
+                                              double* __restrict__ state,
+                                              double* __restrict__ totals) {
   double v[NPART];
 #pragma unroll
   for (int s = 0; s < NPART; ++s) v[s] = 0.0;
@@ -511,6 +511,23 @@ __global__ void __launch_bounds__(FIN_BLOCK) k_finalize(FinalArgs f, const doubl
     totals[14] = MB + MS + outcum;
     totals[15] = cmax;
   }
+}
+
+__global__ void __launch_bounds__(FIN_BLOCK) k_finalize(FinalArgs f, const double* __restrict__ part,
+                                                        double* __restrict__ state,
+                                                        double* __restrict__ totals) {
+  finalize_body(f, part, state, totals);
+}
+
+// one workgroup per instance: part + first[i] NPART holds instance i's records
+__global__ void __launch_bounds__(FIN_BLOCK) k_batch_final(const FinalArgs* __restrict__ fa,
+                                                           const int* __restrict__ first,
+                                                           const double* __restrict__ part,
+                                                           double* __restrict__ states,
+                                                           double* __restrict__ totals) {
+  const int i = blockIdx.x;
+  finalize_body(fa[i], part + (long long)first[i] * NPART, states + (long long)i * NSTATE,
+                totals ? totals + 16ll * i : nullptr);
 }
 
 __global__ void k_reset_state(double* state) {

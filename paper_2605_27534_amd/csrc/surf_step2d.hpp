@@ -74,8 +74,9 @@ __device__ __forceinline__ int tile_of(const Grid& g, int tilesx, int x, int y) 
   return (x / TX) + tilesx * (y / TY);
 }
 
-template <typename R, int KH, int NT = 512, int TX = 64, int TY = 16>
-__global__ void __launch_bounds__(NT) k_step2d(Step2dArgs<R> a) {
+// One tile of the step; its FP64 partial record goes to a.part[t].
+template <typename R, int KH, int NT, int TX, int TY>
+__device__ __forceinline__ void step2d_tile(const Step2dArgs<R>& a, const int t) {
   // K sweeps reach K cells: within the 3 x 3 tile neighbourhood used to
   // decide which tiles stay quiescent
   static_assert(KH <= TY && KH <= TX, "sweeps must stay within the neighbour tiles");
@@ -113,10 +114,6 @@ __global__ void __launch_bounds__(NT) k_step2d(Step2dArgs<R> a) {
   const int tid = threadIdx.x;
   const int nx = g.n[0], ny = g.n[1];
 
-  // XCD-aware order: consecutive blocks land on different XCDs, so block b
-  // takes tile (b % 8) * per_xcd + b / 8 and each XCD walks a contiguous band
-  const int t = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
-  if (t >= a.ntiles) return;
   const int tx = t % a.tiles[0], ty = t / a.tiles[0];
   const int x0 = tx * TX, y0 = ty * TY;
   const bool moving = KH > 0 && a.vof != nullptr;
@@ -570,6 +567,42 @@ __global__ void __launch_bounds__(NT) k_step2d(Step2dArgs<R> a) {
   acc[P_MIN_PSI] = (double)mnP;
   acc[P_NBAD] = (double)nbad;
   block_partials<R, NT>(acc, a.part + (long long)t * NPART);
+}
+
+template <typename R, int KH, int NT = 512, int TX = 64, int TY = 16>
+__global__ void __launch_bounds__(NT) k_step2d(Step2dArgs<R> a) {
+  // XCD-aware order: consecutive blocks land on different XCDs, so block b
+  // takes tile (b % 8) * per_xcd + b / 8 and each XCD walks a contiguous band
+  const int t = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
+  if (t >= a.ntiles) return;
+  step2d_tile<R, KH, NT, TX, TY>(a, t);
+}
+
+// Batched form: independent static-interface instances of different sizes,
+// one persistent launch walking the flattened queue of all their tiles.
+// inst[i] describes instance i with its two state buffers (F/Fo, psi/Po);
+// parity 1 reads the second and writes the first.  queue[q] = (instance,
+// tile of that instance); the partial record of queue entry q goes to
+// part[q], so each instance's records are contiguous.
+template <typename R, int NT>
+__global__ void __launch_bounds__(NT) k_batch2d(const Step2dArgs<R>* __restrict__ inst,
+                                                const int2* __restrict__ queue, int nqueue,
+                                                int parity, double* __restrict__ part) {
+  for (int q = blockIdx.x; q < nqueue; q += gridDim.x) {
+    const int2 e = queue[q];
+    Step2dArgs<R> a = inst[e.x];
+    if (parity) {
+      const R* f = a.F;
+      a.F = a.Fo;
+      a.Fo = (R*)f;
+      const R* ps = a.psi;
+      a.psi = a.Po;
+      a.Po = (R*)ps;
+    }
+    a.part = part + (long long)(q - e.y) * NPART;
+    step2d_tile<R, 0, NT, 64, 16>(a, e.y);
+    __syncthreads();
+  }
 }
 
 // Writes the clamp value into the level-set buffer for every quiescent tile

@@ -35,6 +35,9 @@ EXPORTS = [
     "surf_get_status", "surf_clear_status", "surf_destroy", "surf_strerror", "surf_version",
     "surf_profile_enable", "surf_profile_read", "surf_set_kinetics", "surf_loss_weights",
     "surf_adjoint_seed", "surf_adjoint_step", "surf_adjoint_c0",
+    "surf_batch_workspace_bytes", "surf_batch_create", "surf_batch_set_geometry",
+    "surf_batch_init_state", "surf_batch_step", "surf_batch_parity", "surf_batch_tune",
+    "surf_batch_destroy",
 ]
 
 

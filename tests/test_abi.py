@@ -88,3 +88,31 @@ def test_strerror():
     L = S.lib()
     assert L.surf_strerror(0) == b"ok"
     assert L.surf_strerror(-2) == b"workspace too small"
+
+
+def test_batch_workspace_validates_instances():
+    from paper_2605_27534_amd import surf as S
+    from paper_2605_27534_amd.batch import _bind
+    L = _bind(S.lib())
+    probs = [dict(dim=2, n=(96, 80), h=1 / 96.0), dict(dim=2, n=(130, 70), h=1 / 130.0,
+                                                       bc=((1, 1), (0, 0)))]
+    grids = (S.Grid * 2)()
+    params = (S.Params * 2)()
+    for i, p in enumerate(probs):
+        grids[i], params[i], _ = S.make_structs(p, 1e-4, S.SURF_F32)
+    nb = ctypes.c_size_t(0)
+    assert L.surf_batch_workspace_bytes(2, grids, params, ctypes.byref(nb)) == 0
+    # two level sets and the per-tile records at least
+    assert nb.value >= (96 * 80 + 130 * 70) * 4
+    assert L.surf_batch_workspace_bytes(0, grids, params, ctypes.byref(nb)) == -1
+    # mixed precision and a 3D instance are rejected
+    params[1].precision = S.SURF_F64
+    assert L.surf_batch_workspace_bytes(2, grids, params, ctypes.byref(nb)) == -1
+    params[1].precision = S.SURF_F32
+    g3, p3, _ = S.make_structs(dict(dim=3, n=(16, 16, 16), h=1 / 16.0), 1e-4, S.SURF_F32)
+    grids[1], params[1] = g3, p3
+    assert L.surf_batch_workspace_bytes(2, grids, params, ctypes.byref(nb)) == -1
+    # creation needs device buffers: a null handle array is rejected first
+    h = ctypes.c_void_p()
+    assert L.surf_batch_create(ctypes.byref(h), 2, grids, params, None, None, None, None, 0,
+                               None) == -1
