@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy kernel of MIB MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -53,9 +55,20 @@ def workload(name, K, W):
     return C.c2_translating_sphere()
 
 
+def fused_moving(cfg):
+    """True when the library runs the moving-interface step as one fused 2D
+    kernel (redistancing inside): FP32, 2D, at most 16 sweeps per step."""
+    p = cfg["prob"]
+    return (cfg.get("vof_seq") is not None and p["dim"] == 2 and cfg["precision"] == 0
+            and cfg.get("hj_step", 8) <= 16 and min(p["n"][:2]) >= 36)
+
+
 def algorithmic_bytes(cfg, es):
-    """(transport-kernel bytes per cell, whole-step bytes per cell): every
-    compulsory field counted once, read or written."""
+    """(dominant-kernel bytes per cell, whole-step bytes per cell): every
+    compulsory field counted once, read or written.  Transport reads chi, the
+    state and the face velocities and writes the state and sigma; a moving
+    interface adds the VoF read and the level-set write, which belong to the
+    kernel itself when the step is fused."""
     p = cfg["prob"]
     dim = p["dim"]
     bulk = p.get("bulk_enabled", 1)
@@ -63,7 +76,56 @@ def algorithmic_bytes(cfg, es):
     fields = 2 if bulk else 1
     words = 1 + fields + (dim if has_u else 0) + fields + 1  # chi, state, u | state, sigma
     step_words = words + (2 if cfg.get("vof_seq") else 0)     # + vof read, chi write
-    return words * es, step_words * es
+    kwords = step_words if fused_moving(cfg) else words
+    return kwords * es, step_words * es
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step2d_expanding_circle_1024_traffic.md")
+KERNEL_SOURCES = ("surf_common.hpp", "surf_step2d.hpp")
+
+
+def kernel_source_digest():
+    import hashlib
+    hs = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2605_27534_amd", "csrc", f), "rb") as fh:
+            hs.update(fh.read())
+    return hs.hexdigest()[:16]
+
+
+def measured_traffic(workload_name):
+    """HBM-side bytes per launch of the fused kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or
+    None when there is none for this workload or the kernel source changed
+    since the counters were taken."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    kv = {}
+    for line in txt.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            kv[k.strip()] = v.strip().strip("`")
+    if kv.get("workload") != workload_name or kv.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mb):
+    """A plain device copy of `mb` MiB (read mb, write mb) repeated 5 times,
+    for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = mb * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5}), flush=True)
 
 
 def main():
@@ -72,6 +134,9 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import numpy as np
     import torch
     from paper_2605_27534_amd import surf as S
@@ -160,6 +225,7 @@ def main():
         h2 = hist.cpu().numpy()
 
     ms_per_step = ms_total / K
+    traffic = measured_traffic(cfg["name"])
     value = ncell * K / (ms_total * 1e-3) / 1e9
     kbytes, sbytes = algorithmic_bytes(cfg, es)
     k_avg_ms = step_ms / max(step_n, 1)
@@ -182,9 +248,9 @@ def main():
                    "hj_sweeps_per_step": prob["hj_iters_step"] if vofs is not None else 0,
                    "graph": graph is not None},
         "roofline": {
-            "bound": "hbm", "kernel": "k_step (fused transport)",
+            "bound": "hbm", "kernel": "k_step2d" if prob["dim"] == 2 else "k_step",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_cell": kbytes, "avg_launch_us": round(k_avg_ms * 1e3, 3),
             "step_bytes_per_cell": sbytes, "step_frac": round(step_gbs / HBM_PEAK_GBS, 4),
             "redistancing_us_per_step": round(geom_ms / K * 1e3, 3),
