@@ -11,6 +11,7 @@
 #include "../../include/surf.h"
 #include "surf_kernels.hpp"
 #include "surf_step2d.hpp"
+#include "surf_col2d.hpp"
 #include "surf_adjoint.hpp"
 
 using namespace surf;
@@ -36,7 +37,15 @@ struct surf_ctx {
   uint8_t* q[2];
   int tiles2d[2];
   int ntiles2d;
+  // weighted-form geometry tiles (GEO_T x GEO_T) and the flag array length
+  int gtiles[2];
+  int ngtiles;
+  int nflags;
+  int* nlive;    // [2] live-tile counters (one per level-set buffer)
+  int* live;     // [ngtiles] live-tile list
   int per_xcd;
+  // 2D weighted-form transport: column-streaming waves
+  int col_strips, col_groups, col_nwg;
   bool materialized;  // chi[chi_cur] holds explicit values on every tile
   // adjoint scratch: advected state, nu, per-workgroup dtheta partials
   void* adj[4];
@@ -187,6 +196,36 @@ int ntiles_2d(const surf_grid* gr, int* t) {
   return t[0] * t[1];
 }
 
+// Column-streaming launch shape of the 2D weighted-form transport: strips of
+// COL_OUT columns, row chunks of COL_TY rows (FP32) or COL_TY64 (FP64),
+// COL_WAVES chunks per workgroup.  Returns the workgroup count (0 when the
+// kernel does not apply).
+constexpr int COL_TY = 8, COL_TY64 = 8;
+int col_shape(const surf_grid* gr, const surf_params* p, int* strips, int* groups) {
+  *strips = *groups = 0;
+  if (gr->dim != 2 || p->flux_form != SURF_FLUX_WEIGHTED) return 0;
+  int ty = p->precision == SURF_F64 ? COL_TY64 : COL_TY;
+  int chunks = (gr->n[1] + ty - 1) / ty;
+  *strips = (gr->n[0] + COL_OUT - 1) / COL_OUT;
+  *groups = (chunks + COL_WAVES - 1) / COL_WAVES;
+  return *strips * *groups;
+}
+
+// Tiles of the weighted-form geometry kernel (0 when it does not apply).
+int geo_tiles(const surf_grid* gr, const surf_params* p, int* t) {
+  t[0] = t[1] = 0;
+  if (gr->dim != 2 || p->flux_form != SURF_FLUX_WEIGHTED) return 0;
+  t[0] = (gr->n[0] + GEO_T - 1) / GEO_T;
+  t[1] = (gr->n[1] + GEO_T - 1) / GEO_T;
+  return t[0] * t[1];
+}
+
+int flag_count(const surf_grid* gr, const surf_params* p) {
+  int t2[2], tg[2];
+  int a = ntiles_2d(gr, t2), b = geo_tiles(gr, p, tg);
+  return a > b ? a : b;
+}
+
 int status_of_launch() {
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? SURF_OK : SURF_EDEVICE;
@@ -238,9 +277,12 @@ void materialize(surf_ctx* c) {
 }
 
 void flags_live(surf_ctx* c) {
-  if (c->ntiles2d == 0) return;
-  hipLaunchKernelGGL(k_fill_u8, dim3((c->ntiles2d + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, c->stream,
-                     c->q[c->chi_cur], (uint8_t)Q_LIVE, c->ntiles2d);
+  if (c->ngtiles > 0)
+    hipLaunchKernelGGL(k_fill_u8, dim3(1), dim3(64), 0, c->stream, (uint8_t*)c->nlive, (uint8_t)0,
+                       (int)(2 * sizeof(int)));
+  if (c->nflags == 0) return;
+  hipLaunchKernelGGL(k_fill_u8, dim3((c->nflags + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, c->stream,
+                     c->q[c->chi_cur], (uint8_t)Q_LIVE, c->nflags);
 }
 
 template <typename R>
@@ -290,14 +332,132 @@ bool fused_moving_ok(const surf_ctx* c) {
   return c->grid.n[0] >= 2 * (KH + 2) && c->grid.n[1] >= 2 * (KH + 2);
 }
 
+// The standalone geometry kernel of the weighted-form path: up to 16 sweeps,
+// grids of at least 2 (K + 2) cells per axis (mirror ghosts stay inside).
+template <typename R>
+bool geom2d_ok(const surf_ctx* c) {
+  if (c->grid.dim != 2 || c->col_nwg == 0) return false;
+  int K = c->prm.hj_iters_step;
+  if (K > 16) return false;
+  int KH = K <= 8 ? 8 : 16;
+  return c->grid.n[0] >= 2 * (KH + 2) && c->grid.n[1] >= 2 * (KH + 2);
+}
+
+template <typename R, int TY>
+void launch_col2d(surf_ctx* c, const ColArgs<R>& a, bool has_u, bool bulk) {
+  const dim3 grid(8 * a.per_xcd), block(64 * COL_WAVES);
+  if (has_u && bulk) hipLaunchKernelGGL((k_col2d<R, TY, true, true>), grid, block, 0, c->stream, a);
+  else if (has_u) hipLaunchKernelGGL((k_col2d<R, TY, true, false>), grid, block, 0, c->stream, a);
+  else if (bulk) hipLaunchKernelGGL((k_col2d<R, TY, false, true>), grid, block, 0, c->stream, a);
+  else hipLaunchKernelGGL((k_col2d<R, TY, false, false>), grid, block, 0, c->stream, a);
+}
+
 template <typename R, int KH>
 void launch_step2d(surf_ctx* c, const Step2dArgs<R>& a) {
   hipLaunchKernelGGL((k_step2d<R, KH, STEP2D_THREADS, T2X, T2Y>), dim3(8 * c->per_xcd),
                      dim3(STEP2D_THREADS), 0, c->stream, a);
 }
 
+FinalArgs final_of(const surf_grid& gr, const surf_params& q, int nblk, double dt) {
+  FinalArgs f;
+  f.nblk = nblk;
+  f.dim = gr.dim;
+  f.bulk = q.bulk_enabled ? 1 : 0;
+  f.h = gr.h;
+  f.ka = q.k_a;
+  f.cfl_a = q.cfl_adv;
+  f.cfl_d = q.cfl_diff;
+  f.dt = dt;
+  // explicit bound of substep 2: diffusion (with the weighted form's
+  // neighbour-weight excess cosh(h/eps) - 1, or the paper form's B term) plus
+  // the source's rates; the c_max term is added on the device
+  const double nd = gr.dim, h = gr.h, eps = q.eps;
+  const double Dmax = f.bulk ? std::fmax(q.D_b, q.D_s) : q.D_s;
+  double lam = q.flux_form == SURF_FLUX_WEIGHTED
+                   ? Dmax * (2.0 * nd - 1.0 + std::cosh(h / eps)) / (h * h)
+                   : Dmax * (2.0 * nd / (h * h) + std::sqrt(nd) / (eps * h));
+  if (f.bulk) lam += q.k_a * q.gamma_inf / eps + q.k_d;
+  f.lam0 = lam;
+  return f;
+}
+
 template <typename R>
 void finalize(surf_ctx* c, double* totals, int nblk);
+
+// Weighted form in 2D: the moving geometry as its own tile kernel (every
+// tile writes chi^{n+1}), then the column-streaming transport on the new
+// level set, then the reduction.
+template <typename R>
+int col2d_impl(surf_ctx* c, const void* vof_next, const void* const* u, const void* F_in,
+               const void* psi_in, void* F_out, void* psi_out, void* sigma_out,
+               double* totals) {
+  if (vof_next) {
+    Step2dArgs<R> a{};
+    a.g = c->g;
+    a.p = make_par<R>(c);
+    a.vof = (const R*)vof_next;
+    a.chi_in = (const R*)c->chi[c->chi_cur];
+    a.chi_out = (R*)c->chi[1 - c->chi_cur];
+    a.q_in = c->q[c->chi_cur];
+    a.q_out = c->q[1 - c->chi_cur];
+    a.state = c->state;
+    a.dtau = (R)(c->grid.h / 2);
+    a.ksweeps = c->prm.hj_iters_step;
+    a.tiles[0] = c->gtiles[0];
+    a.tiles[1] = c->gtiles[1];
+    a.ntiles = c->ngtiles;
+    a.per_xcd = (c->ngtiles + 7) / 8;
+    a.diag = (c->gtiles[0] % 8) == 0 ? 1 : 0;
+    {
+      Timed tm(c, 1);
+      int* cnt = c->nlive + c->chi_cur;
+      int* cnt_next = c->nlive + (1 - c->chi_cur);
+      const dim3 gc((c->ngtiles + 3) / 4), gl(c->ngtiles);
+      if (a.ksweeps <= 8) {
+        hipLaunchKernelGGL((k_geo_classify<R, 8>), gc, dim3(256), 0, c->stream, a, cnt, c->live,
+                           cnt_next);
+        hipLaunchKernelGGL((k_geo_live<R, 8>), gl, dim3(GEO_THREADS), 0, c->stream, a,
+                           (const int*)cnt, (const int*)c->live);
+      } else {
+        hipLaunchKernelGGL((k_geo_classify<R, 16>), gc, dim3(256), 0, c->stream, a, cnt, c->live,
+                           cnt_next);
+        hipLaunchKernelGGL((k_geo_live<R, 16>), gl, dim3(GEO_THREADS), 0, c->stream, a,
+                           (const int*)cnt, (const int*)c->live);
+      }
+    }
+    c->chi_cur = 1 - c->chi_cur;
+    c->materialized = true;
+  } else {
+    materialize<R>(c);
+  }
+  ColArgs<R> a;
+  a.g = c->g;
+  a.p = make_par<R>(c);
+  a.chi = (const R*)c->chi[c->chi_cur];
+  const bool has_u = u && u[0];
+  const bool bulk = c->prm.bulk_enabled != 0;
+  a.u[0] = has_u ? (const R*)u[0] : nullptr;
+  a.u[1] = has_u ? (const R*)u[1] : nullptr;
+  a.F = (const R*)F_in;
+  a.psi = (const R*)psi_in;
+  a.Fo = (R*)F_out;
+  a.Po = (R*)psi_out;
+  a.sig = (R*)sigma_out;
+  a.part = c->part;
+  a.dt = (R)c->dt;
+  a.area_dt = (R)(c->grid.h * c->dt);
+  a.strips = c->col_strips;
+  a.groups = c->col_groups;
+  a.nwg = c->col_nwg;
+  a.per_xcd = (c->col_nwg + 7) / 8;
+  {
+    Timed tm(c, 0);
+    if constexpr (sizeof(R) == 4) launch_col2d<R, COL_TY>(c, a, has_u, bulk);
+    else launch_col2d<R, COL_TY64>(c, a, has_u, bulk);
+  }
+  finalize<R>(c, totals, c->col_nwg);
+  return status_of_launch();
+}
 
 template <typename R>
 int step2d_impl(surf_ctx* c, const void* vof_next, const void* const* u, const void* F_in,
@@ -307,6 +467,8 @@ int step2d_impl(surf_ctx* c, const void* vof_next, const void* const* u, const v
   a.g = c->g;
   a.p = make_par<R>(c);
   bool moving = vof_next != nullptr;
+  if (c->col_nwg > 0) return col2d_impl<R>(c, vof_next, u, F_in, psi_in, F_out, psi_out,
+                                           sigma_out, totals);
   a.vof = (const R*)vof_next;
   a.chi_in = (const R*)c->chi[c->chi_cur];
   a.chi_out = (R*)c->chi[1 - c->chi_cur];
@@ -330,6 +492,7 @@ int step2d_impl(surf_ctx* c, const void* vof_next, const void* const* u, const v
   a.tiles[1] = c->tiles2d[1];
   a.ntiles = c->ntiles2d;
   a.per_xcd = c->per_xcd;
+  a.diag = (c->tiles2d[0] % 8) == 0 ? 1 : 0;
   {
     Timed tm(c, 0);
     if (!moving) {
@@ -383,20 +546,7 @@ int step_impl(surf_ctx* c, const void* const* u, const void* F_in, const void* p
 
 template <typename R>
 void finalize(surf_ctx* c, double* totals, int nblk) {
-  FinalArgs f;
-  f.nblk = nblk;
-  f.dim = c->grid.dim;
-  f.bulk = c->prm.bulk_enabled ? 1 : 0;
-  f.form = c->prm.flux_form;
-  f.h = c->grid.h;
-  f.eps = c->prm.eps;
-  f.Dmax = f.bulk ? std::fmax(c->prm.D_b, c->prm.D_s) : c->prm.D_s;
-  f.ka = c->prm.k_a;
-  f.kd = c->prm.k_d;
-  f.ginf = c->prm.gamma_inf;
-  f.cfl_a = c->prm.cfl_adv;
-  f.cfl_d = c->prm.cfl_diff;
-  f.dt = c->dt;
+  FinalArgs f = final_of(c->grid, c->prm, nblk, c->dt);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_BLOCK), 0, c->stream, f, (const double*)c->part,
                      c->state, totals);
 }
@@ -447,23 +597,6 @@ Par<R> par_of(const surf_grid& gr, const surf_params& q) {
   return make_par<R>(&tmp);
 }
 
-FinalArgs final_of(const surf_grid& gr, const surf_params& q, int nblk) {
-  FinalArgs f;
-  f.nblk = nblk;
-  f.dim = gr.dim;
-  f.bulk = q.bulk_enabled ? 1 : 0;
-  f.form = q.flux_form;
-  f.h = gr.h;
-  f.eps = q.eps;
-  f.Dmax = f.bulk ? std::fmax(q.D_b, q.D_s) : q.D_s;
-  f.ka = q.k_a;
-  f.kd = q.k_d;
-  f.ginf = q.gamma_inf;
-  f.cfl_a = q.cfl_adv;
-  f.cfl_d = q.cfl_diff;
-  f.dt = q.dt;
-  return f;
-}
 
 template <typename R>
 int adjoint_step_impl(surf_ctx* c, const void* const* u, const void* F, const void* psi,
@@ -533,13 +666,21 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   int tiles[3], t2[2];
   int nblk = nblocks_step(grid, params, tiles);
   int n2 = ntiles_2d(grid, t2);
+  int cs, cg;
+  int ncol = col_shape(grid, params, &cs, &cg);
   int npart = nblk > n2 ? nblk : n2;
+  npart = ncol > npart ? ncol : npart;
   size_t n = (size_t)grid->n[0] * grid->n[1] * grid->n[2];
   size_t es = esize(params);
   size_t b = align_up(NSTATE * sizeof(double));
   b += align_up((size_t)npart * NPART * sizeof(double));
   b += 3 * align_up(n * es);
-  b += 2 * align_up((size_t)n2 + 1);
+  b += 2 * align_up((size_t)flag_count(grid, params) + 1);
+  {
+    int tg[2];
+    int ng = geo_tiles(grid, params, tg);
+    b += align_up(2 * sizeof(int)) + align_up((size_t)(ng + 1) * sizeof(int));
+  }
   if (params->adjoint) {
     b += 4 * align_up(n * es);
     b += align_up((size_t)((n + BLOCK - 1) / BLOCK) * NADJ * sizeof(double));
@@ -574,7 +715,11 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
   c->nblk = nblocks_step(grid, params, c->tiles);
   c->ntiles2d = ntiles_2d(grid, c->tiles2d);
   c->per_xcd = (c->ntiles2d + 7) / 8;
+  c->ngtiles = geo_tiles(grid, params, c->gtiles);
+  c->nflags = flag_count(grid, params);
+  c->col_nwg = col_shape(grid, params, &c->col_strips, &c->col_groups);
   int npart = c->nblk > c->ntiles2d ? c->nblk : c->ntiles2d;
+  npart = c->col_nwg > npart ? c->col_nwg : npart;
   size_t es = esize(params);
   char* p = c->ws;
   c->state = (double*)p;
@@ -588,9 +733,13 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
   c->g0 = p;
   p += align_up(c->ncell * es);
   c->q[0] = (uint8_t*)p;
-  p += align_up((size_t)c->ntiles2d + 1);
+  p += align_up((size_t)c->nflags + 1);
   c->q[1] = (uint8_t*)p;
-  p += align_up((size_t)c->ntiles2d + 1);
+  p += align_up((size_t)c->nflags + 1);
+  c->nlive = (int*)p;
+  p += align_up(2 * sizeof(int));
+  c->live = (int*)p;
+  p += align_up((size_t)(c->ngtiles + 1) * sizeof(int));
   for (int i = 0; i < 4; ++i) {
     c->adj[i] = params->adjoint ? (void*)p : nullptr;
     if (params->adjoint) p += align_up(c->ncell * es);
@@ -659,9 +808,18 @@ int surf_step(surf_ctx* c, const void* vof_next, const void* const* u, const voi
   if (!aligned(psi_in, es) || !aligned(psi_out, es)) return SURF_EINVAL;
   if (!c->has_chi) return SURF_ESTATE;
   if (vof_next) {
-    if (c->prm.precision == SURF_F32 && fused_moving_ok<float>(c))
+    // 2D: the redistancing sweeps run inside tile kernels when they fit
+    if (c->col_nwg > 0) {
+      if (c->prm.precision == SURF_F32 && geom2d_ok<float>(c))
+        return col2d_impl<float>(c, vof_next, u, F_in, psi_in, F_out, psi_out, sigma_out,
+                                 totals_dev);
+      if (c->prm.precision == SURF_F64 && geom2d_ok<double>(c))
+        return col2d_impl<double>(c, vof_next, u, F_in, psi_in, F_out, psi_out, sigma_out,
+                                  totals_dev);
+    } else if (c->prm.precision == SURF_F32 && fused_moving_ok<float>(c)) {
       return step2d_impl<float>(c, vof_next, u, F_in, psi_in, F_out, psi_out, sigma_out,
                                 totals_dev);
+    }
     int rc = surf_set_geometry(c, vof_next, 0);
     if (rc) return rc;
   }
@@ -860,10 +1018,11 @@ void batch_tables(surf_batch* b) {
     a.tiles[0] = t2[0];
     a.tiles[1] = t2[1];
     a.per_xcd = (a.ntiles + 7) / 8;
+    a.diag = 0;
     std::memcpy(b->host_inst.data() + sizeof(a) * i, &a, sizeof(a));
     b->host_first[i] = (int)b->host_queue.size();
     for (int t = 0; t < a.ntiles; ++t) b->host_queue.push_back(make_int2(i, t));
-    FinalArgs f = final_of(gr, q, a.ntiles);
+    FinalArgs f = final_of(gr, q, a.ntiles, q.dt);
     std::memcpy(b->host_fargs.data() + sizeof(f) * i, &f, sizeof(f));
   }
 }
@@ -988,6 +1147,9 @@ int surf_batch_set_geometry(surf_batch* b, int32_t i, const void* vof) {
   c.has_chi = false;
   c.materialized = true;
   c.ntiles2d = 0;
+  c.ngtiles = 0;
+  c.nflags = 0;
+  c.col_nwg = 0;
   c.profile = false;
   int rc = c.prm.precision == SURF_F64 ? geometry_impl<double>(&c, vof, 1)
                                        : geometry_impl<float>(&c, vof, 1);

@@ -439,11 +439,12 @@ __global__ void __launch_bounds__(BLOCK) k_step(StepArgs<R> a) {
 // ---------------------------------------------------------------- finalize
 struct FinalArgs {
   int nblk;
-  int dim, bulk, form;
-  double h, eps, Dmax, ka, kd, ginf, cfl_a, cfl_d, dt;
+  int dim, bulk;
+  double h, ka, cfl_a, cfl_d, dt;
+  double lam0;  // stability rate of substep 2 without the c_max term
 };
 
-constexpr int FIN_BLOCK = 1024;
+constexpr int FIN_BLOCK = 256;
 
 __device__ __forceinline__ void finalize_body(const FinalArgs& f, const double* __restrict__ part,
                                               double* __restrict__ state,
@@ -478,10 +479,8 @@ __device__ __forceinline__ void finalize_body(const FinalArgs& f, const double* 
   double t = state[S_TIME] + f.dt;
   double su = tot[P_MAX_USUM];
   double cmax = f.bulk ? tot[P_MAX_C] : 0.0;
-  double nd = f.dim;
-  double lam = f.form == FORM_W ? f.Dmax * (2.0 * nd - 1.0 + cosh(f.h / f.eps)) / (f.h * f.h)
-                                : f.Dmax * (2.0 * nd / (f.h * f.h) + sqrt(nd) / (f.eps * f.h));
-  if (f.bulk) lam += f.ka * f.ginf / f.eps + f.ka * (cmax > 0 ? cmax : 0.0) + f.kd;
+  double lam = f.lam0;
+  if (f.bulk) lam += f.ka * (cmax > 0 ? cmax : 0.0);
   double dta = su > 0 ? f.cfl_a * f.h / su : INFINITY;
   double dtd = f.cfl_d / lam;
   double bound = fmin(su > 0 ? f.h / su : INFINITY, 1.0 / lam);

@@ -48,7 +48,23 @@ struct Step2dArgs {
   int tiles[2];
   int ntiles;
   int per_xcd;       // tiles per XCD chunk
+  int diag;          // 1: diagonal XCD mapping (tiles[0] % 8 == 0), 0: banded
 };
+
+// Workgroup -> tile.  Consecutive workgroups land on consecutive XCDs
+// (b % 8).  Banded: XCD x walks the contiguous tile range [x per_xcd,
+// (x + 1) per_xcd), which keeps vertical halos in one L2 but puts a band of
+// tile rows on one XCD.  Diagonal: in tile row ty, XCD x takes the tiles whose
+// column is (x + 3 ty) mod 8 in every group of 8 columns, so any localized
+// feature (the interface band, where the tiles do redistancing work) spreads
+// over all eight XCDs.
+__device__ __forceinline__ int tile_of_block(int b, int ntx, int per_xcd, int diag) {
+  const int x = b & 7, j = b >> 3;
+  if (!diag) return x * per_xcd + j;
+  const int m = ntx >> 3;
+  const int ty = j / m, k = j - ty * m;
+  return 8 * k + ((x + 3 * ty) & 7) + ntx * ty;
+}
 
 // Paper-form anti-diffusion coefficient of halo-1 cell (cx, cy) along d
 // (section 3.2, Appendix C): B_F = -D_b (1-phi)/eps n_d, B_psi = -D_s
@@ -74,31 +90,275 @@ __device__ __forceinline__ int tile_of(const Grid& g, int tilesx, int x, int y) 
   return (x / TX) + tilesx * (y / TY);
 }
 
+// Sizes of the per-tile LDS arrays of the 2D tile kernels.
+template <int KH, int TX, int TY>
+struct Tile2 {
+  static constexpr int HC = KH > 0 ? KH + 2 : 2;        // chi halo held in LDS
+  static constexpr int EXC = TX + 2 * HC, EYC = TY + 2 * HC, NC = EXC * EYC;
+  static constexpr int RX = (HC + TX - 1) / TX, RY = (HC + TY - 1) / TY;  // flag neighbourhood
+  static constexpr int QW = 2 * RX + 1, QN = QW * (2 * RY + 1);
+};
+
+// Level set of the (mapped) cell (gx, gy) for tile (tx, ty): the clamp value
+// on tiles flagged quiescent in sQ (the flag neighbourhood), else the buffer.
+template <typename R, int KH, int TX, int TY>
+__device__ __forceinline__ R chi_at_tile(const Step2dArgs<R>& a, const uint8_t* sQ, int tx, int ty,
+                                         int gx, int gy) {
+  using T = Tile2<KH, TX, TY>;
+  const Grid& g = a.g;
+  const int nx = g.n[0], ny = g.n[1];
+  int mx = map_axis(gx, nx, g.bc[0][0], g.bc[0][1]);
+  int my = map_axis(gy, ny, g.bc[1][0], g.bc[1][1]);
+  int dx = mx / TX - tx, dy = my / TY - ty;
+  if (dx > T::RX) dx -= a.tiles[0];
+  if (dx < -T::RX) dx += a.tiles[0];
+  if (dy > T::RY) dy -= a.tiles[1];
+  if (dy < -T::RY) dy += a.tiles[1];
+  uint8_t q = sQ[(dx + T::RX) + T::QW * (dy + T::RY)];
+  if (q == Q_POS) return a.p.chimax;
+  if (q == Q_NEG) return -a.p.chimax;
+  return a.chi_in[(long long)mx + (long long)nx * my];
+}
+
+// Quiescence flags of the neighbour tiles into sQ (255: outside a
+// non-periodic side).  Ends with a barrier.
+template <typename R, int KH, int NT, int TX, int TY>
+__device__ __forceinline__ void load_flags(const Step2dArgs<R>& a, uint8_t* sQ, int tx, int ty) {
+  using T = Tile2<KH, TX, TY>;
+  const Grid& g = a.g;
+  const int tid = threadIdx.x;
+  if (tid < T::QN) {
+    int ux = tx + tid % T::QW - T::RX, uy = ty + tid / T::QW - T::RY;
+    bool ok = true;
+    if (ux < 0 || ux >= a.tiles[0]) {
+      if (g.bc[0][ux < 0 ? 0 : 1] == BC_PERIODIC) ux = (ux + a.tiles[0]) % a.tiles[0]; else ok = false;
+    }
+    if (uy < 0 || uy >= a.tiles[1]) {
+      if (g.bc[1][uy < 0 ? 0 : 1] == BC_PERIODIC) uy = (uy + a.tiles[1]) % a.tiles[1]; else ok = false;
+    }
+    sQ[tid] = ok ? a.q_in[ux + a.tiles[0] * uy] : (uint8_t)255;
+  }
+  __syncthreads();
+}
+
+// The moving-interface geometry of tile t (section 2.5): decides from the
+// tile's VoF and the neighbour flags whether the tile stays quiescent (level
+// set at the clamp); otherwise rebuilds it with K warm-start Jacobi sweeps
+// (Russo-Smereka pinned cut cells, Godunov elsewhere) on the tile plus a
+// halo that shrinks by one cell per sweep, all in LDS.  Each thread keeps
+// the pin data and the current value of its cells in registers; LDS holds
+// the two sweep buffers (the second one first holds the VoF).  On return
+// sChi holds chi^{n+1} on the tile and its halo of 2 (HC - K) for live
+// tiles (and, unless write_quiet, the clamp value on quiescent ones),
+// chi_out the tile's values of live tiles (and, with write_quiet, of
+// quiescent tiles too), q_out[t] the new flag.  Returns whether the tile was
+// live.  sQ must hold the flags (load_flags) and all1 / all0 the VoF
+// uniformity of the tile (block-wide); sB has NC elements.
+// Whether the VoF of tile t is uniformly 1 / uniformly 0 (block-wide).
+template <typename R, int NT, int TX, int TY>
+__device__ __forceinline__ void tile_vof_uniform(const Step2dArgs<R>& a, const int t, bool& all1,
+                                                 bool& all0) {
+  constexpr int IT = (TX * TY + NT - 1) / NT;
+  const int nx = a.g.n[0], ny = a.g.n[1];
+  const int x0 = (t % a.tiles[0]) * TX, y0 = (t / a.tiles[0]) * TY;
+  all1 = true;
+  all0 = true;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    int l = threadIdx.x + it * NT;
+    int gx = x0 + l % TX, gy = y0 + l / TX;
+    if (l < TX * TY && gx < nx && gy < ny) {
+      R f = a.vof[(long long)gx + (long long)nx * gy];
+      all1 = all1 && f == R(1);
+      all0 = all0 && f == R(0);
+    }
+  }
+  all1 = __syncthreads_and(all1);
+  all0 = __syncthreads_and(all0);
+}
+
+template <typename R, int KH, int NT, int TX, int TY>
+__device__ __forceinline__ bool tile_geometry(const Step2dArgs<R>& a, const int t, R* sChi,
+                                              R* sB, const uint8_t* sQ, bool write_quiet,
+                                              const bool all1, const bool all0) {
+  using T = Tile2<KH, TX, TY>;
+  constexpr int HC = T::HC, EXC = T::EXC, EYC = T::EYC, NC = T::NC;
+  constexpr int IC = (NC + NT - 1) / NT, IT = (TX * TY + NT - 1) / NT;
+  const Grid& g = a.g;
+  const Par<R>& p = a.p;
+  const int tid = threadIdx.x;
+  const int nx = g.n[0], ny = g.n[1];
+  const int tx = t % a.tiles[0], ty = t / a.tiles[0];
+  const int x0 = tx * TX, y0 = ty * TY;
+  int want = all1 ? Q_POS : (all0 ? Q_NEG : -1);
+  bool quiet = true, nb_quiet = true;
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) {
+      uint8_t q = sQ[(dx + T::RX) + T::QW * (dy + T::RY)];
+      if (q == 255) continue;
+      if ((int)q != want) quiet = false;
+      if (q == Q_LIVE) nb_quiet = false;
+    }
+  const bool active = !quiet;
+  // the VoF changed under a tile whose whole neighbourhood was quiescent:
+  // the interface moved farther than the clamp distance in one step
+  if (tid == 0 && active && nb_quiet)
+    atomicOr((unsigned*)(a.state + S_FLAGS), (unsigned)STATUS_GEOM_JUMP);
+  if (!active) {
+    R v = want == Q_POS ? p.chimax : -p.chimax;
+    if (write_quiet) {
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        int l = tid + it * NT;
+        int gx = x0 + l % TX, gy = y0 + l / TX;
+        if (l < TX * TY && gx < nx && gy < ny) a.chi_out[(long long)gx + (long long)nx * gy] = v;
+      }
+    } else {
+      for (int l = tid; l < NC; l += NT) sChi[l] = v;
+    }
+    if (tid == 0) a.q_out[t] = (uint8_t)want;
+    return false;
+  }
+  R* sV = sB;  // the VoF until the pin data is in registers
+  // this thread's cells of the tile + HC region
+  int cl[IC], cx[IC], cy[IC];
+#pragma unroll
+  for (int it = 0; it < IC; ++it) {
+    cl[it] = tid + it * NT;
+    cx[it] = cl[it] % EXC;
+    cy[it] = cl[it] / EXC;
+  }
+  {
+    R rv[IC], rc[IC];
+#pragma unroll
+    for (int it = 0; it < IC; ++it) {
+      if (cl[it] < NC) {
+        int gx = x0 + cx[it] - HC, gy = y0 + cy[it] - HC;
+        int mx = map_axis(gx, nx, g.bc[0][0], g.bc[0][1]);
+        int my = map_axis(gy, ny, g.bc[1][0], g.bc[1][1]);
+        rv[it] = a.vof[(long long)mx + (long long)nx * my];
+        rc[it] = chi_at_tile<R, KH, TX, TY>(a, sQ, tx, ty, gx, gy);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IC; ++it) {
+      if (cl[it] < NC) {
+        sV[cl[it]] = rv[it];
+        sChi[cl[it]] = rc[it];
+      }
+    }
+  }
+  __syncthreads();
+  // pin data on the tile + (HC - 1) halo: subcell distance of cut cells
+  // (Russo-Smereka), +-infinity carrying the sign elsewhere
+  R G[IC], cur[IC];
+#pragma unroll
+  for (int it = 0; it < IC; ++it) {
+    const int l = cl[it];
+    G[it] = R(0);
+    cur[it] = R(0);
+    if (l >= NC) continue;
+    cur[it] = sChi[l];
+    if (cx[it] < 1 || cx[it] >= EXC - 1 || cy[it] < 1 || cy[it] >= EYC - 1) continue;
+    R c0 = (sV[l] - R(0.5)) * p.h;
+    R xm = (sV[l - 1] - R(0.5)) * p.h, xp = (sV[l + 1] - R(0.5)) * p.h;
+    R ym = (sV[l - EXC] - R(0.5)) * p.h, yp = (sV[l + EXC] - R(0.5)) * p.h;
+    bool cut = (c0 * xm <= R(0)) || (c0 * xp <= R(0)) || (c0 * ym <= R(0)) || (c0 * yp <= R(0));
+    R jump = fmax(fmax(fabs(xm - c0), fabs(xp - c0)), fmax(fabs(ym - c0), fabs(yp - c0)));
+    R ccx = R(0.5) * (xp - xm), ccy = R(0.5) * (yp - ym);
+    R Delta = fmax(fmax(rsqrt_<R>(ccx * ccx + ccy * ccy), jump), R(1e-30) * p.h);
+    G[it] = cut ? p.h * c0 / Delta : (c0 > R(0) ? R(INFINITY) : R(-INFINITY));
+  }
+  __syncthreads();  // sV is read; sB becomes the second sweep buffer
+  // K Jacobi sweeps on shrinking regions
+  int par = 0;
+  for (int k = 1; k <= a.ksweeps; ++k) {
+    const R* src = par ? sB : sChi;
+    R* dst = par ? sChi : sB;
+    const int r = HC - k;  // halo of the region updated by this sweep
+#pragma unroll
+    for (int it = 0; it < IC; ++it) {
+      const int l = cl[it];
+      // only the region's cells: the next sweep reads nothing outside it
+      if (l >= NC || cx[it] < HC - r || cx[it] >= HC + TX + r || cy[it] < HC - r ||
+          cy[it] >= HC + TY + r)
+        continue;
+      R v;
+      const R gv = G[it];
+      if (fabs(gv) < R(INFINITY)) {
+        v = gv;
+      } else {
+        const R x = cur[it];
+        const R bwx = (x - src[l - 1]) * p.inv_h, fwx = (src[l + 1] - x) * p.inv_h;
+        const R bwy = (x - src[l - EXC]) * p.inv_h, fwy = (src[l + EXC] - x) * p.inv_h;
+        const R sgn = gv > R(0) ? R(1) : R(-1);
+        // Godunov: upwind one-sided differences for the sign of chi0
+        const R a1 = sgn * bwx, b1 = sgn * fwx, a2 = sgn * bwy, b2 = sgn * fwy;
+        R t1 = a1 > R(0) ? a1 * a1 : R(0), t2 = b1 < R(0) ? b1 * b1 : R(0);
+        R G2 = t1 > t2 ? t1 : t2;
+        t1 = a2 > R(0) ? a2 * a2 : R(0);
+        t2 = b2 < R(0) ? b2 * b2 : R(0);
+        G2 += t1 > t2 ? t1 : t2;
+        v = x - a.dtau * sgn * (rsqrt_<R>(G2) - R(1));
+      }
+      v = v > p.chimax ? p.chimax : v;
+      v = v < -p.chimax ? -p.chimax : v;
+      cur[it] = v;
+      dst[l] = v;
+    }
+    __syncthreads();
+    par ^= 1;
+  }
+  if (par != 0) {
+    // the last sweep wrote sB: bring the result back into sChi
+#pragma unroll
+    for (int it = 0; it < IC; ++it)
+      if (cl[it] < NC) sChi[cl[it]] = sB[cl[it]];
+    __syncthreads();
+  }
+  // chi^{n+1} of the tile interior and its quiescence flag
+  bool allpos = true, allneg = true;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    int l = tid + it * NT;
+    int ix = l % TX, iy = l / TX;
+    int gx = x0 + ix, gy = y0 + iy;
+    if (l < TX * TY && gx < nx && gy < ny) {
+      R v = sChi[(ix + HC) + EXC * (iy + HC)];
+      a.chi_out[(long long)gx + (long long)nx * gy] = v;
+      allpos = allpos && v == p.chimax;
+      allneg = allneg && v == -p.chimax;
+    }
+  }
+  allpos = __syncthreads_and(allpos);
+  allneg = __syncthreads_and(allneg);
+  if (tid == 0) a.q_out[t] = allpos ? Q_POS : (allneg ? Q_NEG : Q_LIVE);
+  return true;
+}
+
 // One tile of the step; its FP64 partial record goes to a.part[t].
 template <typename R, int KH, int NT, int TX, int TY>
 __device__ __forceinline__ void step2d_tile(const Step2dArgs<R>& a, const int t) {
   // K sweeps reach K cells: within the 3 x 3 tile neighbourhood used to
   // decide which tiles stay quiescent
   static_assert(KH <= TY && KH <= TX, "sweeps must stay within the neighbour tiles");
-  constexpr int HC = KH > 0 ? KH + 2 : 2;        // chi halo held in LDS
-  constexpr int EXC = TX + 2 * HC, EYC = TY + 2 * HC, NC = EXC * EYC;
+  using T = Tile2<KH, TX, TY>;
+  constexpr int HC = T::HC, EXC = T::EXC, NC = T::NC;
   constexpr int EX3 = TX + 6, EY3 = TY + 6, N3 = EX3 * EY3;
   constexpr int EX1 = TX + 2, EY1 = TY + 2, N1 = EX1 * EY1;
   constexpr int NUX = (TX + 3) * EY1, NUY = EX1 * (TY + 3);
   constexpr int I3 = (N3 + NT - 1) / NT, IUX = (NUX + NT - 1) / NT;
   constexpr int IUY = (NUY + NT - 1) / NT, IC = (NC + NT - 1) / NT;
   constexpr int IT = (TX * TY + NT - 1) / NT;
-  constexpr int RX = (HC + TX - 1) / TX, RY = (HC + TY - 1) / TY;   // flag neighbourhood
-  constexpr int QW = 2 * RX + 1, QN = QW * (2 * RY + 1);
   // LDS: the final level set (tile + HC halo) stays live throughout; the
   // redistancing scratch (second sweep buffer, VoF, pin data) and the
   // transport arrays share one pool
   constexpr int NTR = 2 * N3 + 3 * (NUX + NUY) + 4 * N1;
-  constexpr int NGEO = KH > 0 ? 3 * NC : 0;
+  constexpr int NGEO = KH > 0 ? NC : 0;
   constexpr int NPOOL = NGEO > NTR ? NGEO : NTR;
   __shared__ R sChi[NC];
   __shared__ R sPool[NPOOL];
-  __shared__ uint8_t sQ[QN];
+  __shared__ uint8_t sQ[T::QN];
   R* sF3 = sPool;              // old F (halo 3), later c* in place
   R* sP3 = sPool + N3;         // old psi (halo 3), later Gamma* in place
   R* sUx = sPool + 2 * N3;     // x-face velocities of the halo-1 cells
@@ -168,173 +428,14 @@ __device__ __forceinline__ void step2d_tile(const Step2dArgs<R>& a, const int t)
       if (ok) rUy[it] = a.u[1][(long long)gx + (long long)nx * gy];
     }
   }
-  // quiescence flags of the neighbour tiles (255: outside a non-periodic side)
-  if (tid < QN) {
-    int ux = tx + tid % QW - RX, uy = ty + tid / QW - RY;
-    bool ok = true;
-    if (ux < 0 || ux >= a.tiles[0]) {
-      if (g.bc[0][ux < 0 ? 0 : 1] == BC_PERIODIC) ux = (ux + a.tiles[0]) % a.tiles[0]; else ok = false;
-    }
-    if (uy < 0 || uy >= a.tiles[1]) {
-      if (g.bc[1][uy < 0 ? 0 : 1] == BC_PERIODIC) uy = (uy + a.tiles[1]) % a.tiles[1]; else ok = false;
-    }
-    sQ[tid] = ok ? a.q_in[ux + a.tiles[0] * uy] : (uint8_t)255;
-  }
-  // own VoF: uniform 1, uniform 0 or mixed
-  bool all1 = true, all0 = true;
-  if (moving) {
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      int l = tid + it * NT;
-      int gx = x0 + l % TX, gy = y0 + l / TX;
-      if (l < TX * TY && gx < nx && gy < ny) {
-        R f = a.vof[(long long)gx + (long long)nx * gy];
-        all1 = all1 && f == R(1);
-        all0 = all0 && f == R(0);
-      }
-    }
-  }
-  __syncthreads();
-
-  // level set of a (mapped) cell: the clamp value on quiescent tiles
-  auto chi_at = [&](int gx, int gy) -> R {
-    int mx = map_axis(gx, nx, g.bc[0][0], g.bc[0][1]);
-    int my = map_axis(gy, ny, g.bc[1][0], g.bc[1][1]);
-    int dx = mx / TX - tx, dy = my / TY - ty;
-    if (dx > RX) dx -= a.tiles[0];
-    if (dx < -RX) dx += a.tiles[0];
-    if (dy > RY) dy -= a.tiles[1];
-    if (dy < -RY) dy += a.tiles[1];
-    uint8_t q = sQ[(dx + RX) + QW * (dy + RY)];
-    if (q == Q_POS) return p.chimax;
-    if (q == Q_NEG) return -p.chimax;
-    return a.chi_in[(long long)mx + (long long)nx * my];
-  };
+  load_flags<R, KH, NT, TX, TY>(a, sQ, tx, ty);
 
   // ---------------------------------------------------------- geometry
-  bool active = false;
-  if (moving) {
-    all1 = __syncthreads_and(all1);
-    all0 = __syncthreads_and(all0);
-    int want = all1 ? Q_POS : (all0 ? Q_NEG : -1);
-    bool quiet = true, nb_quiet = true;
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        uint8_t q = sQ[(dx + RX) + QW * (dy + RY)];
-        if (q == 255) continue;
-        if ((int)q != want) quiet = false;
-        if (q == Q_LIVE) nb_quiet = false;
-      }
-    active = !quiet;
-    // the VoF changed under a tile whose whole neighbourhood was quiescent:
-    // the interface moved farther than the clamp distance in one step
-    if (tid == 0 && active && nb_quiet)
-      atomicOr((unsigned*)(a.state + S_FLAGS), (unsigned)STATUS_GEOM_JUMP);
-    if (!active) {
-      R v = want == Q_POS ? p.chimax : -p.chimax;
-      for (int l = tid; l < NC; l += NT) sChi[l] = v;
-      if (tid == 0) a.q_out[t] = (uint8_t)want;
-    }
-  }
   if constexpr (KH > 0) {
-    if (active) {
-      R* sB = sPool;           // second sweep buffer
-      R* sV = sPool + NC;      // VoF, then
-      R* sG = sPool + 2 * NC;  // pin data
-      R rv[IC], rc[IC];
-#pragma unroll
-      for (int it = 0; it < IC; ++it) {
-        int l = tid + it * NT;
-        if (l < NC) {
-          int gx = x0 + l % EXC - HC, gy = y0 + l / EXC - HC;
-          int mx = map_axis(gx, nx, g.bc[0][0], g.bc[0][1]);
-          int my = map_axis(gy, ny, g.bc[1][0], g.bc[1][1]);
-          rv[it] = a.vof[(long long)mx + (long long)nx * my];
-          rc[it] = chi_at(gx, gy);
-        }
-      }
-#pragma unroll
-      for (int it = 0; it < IC; ++it) {
-        int l = tid + it * NT;
-        if (l < NC) {
-          sV[l] = rv[it];
-          sChi[l] = rc[it];
-        }
-      }
-      __syncthreads();
-      // pin data on the tile + (HC - 1) halo: subcell distance of cut cells
-      // (Russo-Smereka), +-infinity carrying the sign elsewhere
-      for (int l = tid; l < NC; l += NT) {
-        int lx = l % EXC, ly = l / EXC;
-        if (lx < 1 || lx >= EXC - 1 || ly < 1 || ly >= EYC - 1) continue;
-        R c0 = (sV[l] - R(0.5)) * p.h;
-        R xm = (sV[l - 1] - R(0.5)) * p.h, xp = (sV[l + 1] - R(0.5)) * p.h;
-        R ym = (sV[l - EXC] - R(0.5)) * p.h, yp = (sV[l + EXC] - R(0.5)) * p.h;
-        bool cut = (c0 * xm <= R(0)) || (c0 * xp <= R(0)) || (c0 * ym <= R(0)) || (c0 * yp <= R(0));
-        R jump = fmax(fmax(fabs(xm - c0), fabs(xp - c0)), fmax(fabs(ym - c0), fabs(yp - c0)));
-        R cx = R(0.5) * (xp - xm), cy = R(0.5) * (yp - ym);
-        R Delta = fmax(fmax(rsqrt_<R>(cx * cx + cy * cy), jump), R(1e-30) * p.h);
-        sG[l] = cut ? p.h * c0 / Delta : (c0 > R(0) ? R(INFINITY) : R(-INFINITY));
-      }
-      __syncthreads();
-      // K Jacobi sweeps on shrinking regions
-      int cur = 0;
-      for (int k = 1; k <= a.ksweeps; ++k) {
-        const R* src = cur ? sB : sChi;
-        R* dst = cur ? sChi : sB;
-        int r = HC - k;  // halo of the region updated by this sweep
-        // only the region's cells: the next sweep reads nothing outside it
-        for (int l = tid; l < NC; l += NT) {
-          const int lx = l % EXC, ly = l / EXC;
-          if (lx < HC - r || lx >= HC + TX + r || ly < HC - r || ly >= HC + TY + r) continue;
-          R v = src[l];
-          {
-            R gv = sG[l];
-            if (fabs(gv) < R(INFINITY)) {
-              v = gv;
-            } else {
-              R x = v;
-              R bwx = (x - src[l - 1]) * p.inv_h, fwx = (src[l + 1] - x) * p.inv_h;
-              R bwy = (x - src[l - EXC]) * p.inv_h, fwy = (src[l + EXC] - x) * p.inv_h;
-              R sgn = gv > R(0) ? R(1) : R(-1);
-              // Godunov: upwind one-sided differences for the sign of chi0
-              R a1 = sgn * bwx, b1 = sgn * fwx, a2 = sgn * bwy, b2 = sgn * fwy;
-              R t1 = a1 > R(0) ? a1 * a1 : R(0), t2 = b1 < R(0) ? b1 * b1 : R(0);
-              R G2 = t1 > t2 ? t1 : t2;
-              t1 = a2 > R(0) ? a2 * a2 : R(0);
-              t2 = b2 < R(0) ? b2 * b2 : R(0);
-              G2 += t1 > t2 ? t1 : t2;
-              v = x - a.dtau * sgn * (rsqrt_<R>(G2) - R(1));
-            }
-            v = v > p.chimax ? p.chimax : v;
-            v = v < -p.chimax ? -p.chimax : v;
-          }
-          dst[l] = v;
-        }
-        __syncthreads();
-        cur ^= 1;
-      }
-      if (cur != 0) {
-        for (int l = tid; l < NC; l += NT) sChi[l] = sB[l];
-        __syncthreads();
-      }
-      // chi^{n+1} of the tile interior and its quiescence flag
-      bool allpos = true, allneg = true;
-#pragma unroll
-      for (int it = 0; it < IT; ++it) {
-        int l = tid + it * NT;
-        int ix = l % TX, iy = l / TX;
-        int gx = x0 + ix, gy = y0 + iy;
-        if (l < TX * TY && gx < nx && gy < ny) {
-          R v = sChi[(ix + HC) + EXC * (iy + HC)];
-          a.chi_out[(long long)gx + (long long)nx * gy] = v;
-          allpos = allpos && v == p.chimax;
-          allneg = allneg && v == -p.chimax;
-        }
-      }
-      allpos = __syncthreads_and(allpos);
-      allneg = __syncthreads_and(allneg);
-      if (tid == 0) a.q_out[t] = allpos ? Q_POS : (allneg ? Q_NEG : Q_LIVE);
+    if (moving) {
+      bool all1, all0;
+      tile_vof_uniform<R, NT, TX, TY>(a, t, all1, all0);
+      tile_geometry<R, KH, NT, TX, TY>(a, t, sChi, sPool, sQ, false, all1, all0);
     }
   }
   if (!moving) {
@@ -346,7 +447,7 @@ __device__ __forceinline__ void step2d_tile(const Step2dArgs<R>& a, const int t)
       rc[it] = R(0);
       int lx = l % EXC, ly = l / EXC;
       if (l < NC && lx >= HC - 2 && lx < HC + TX + 2 && ly >= HC - 2 && ly < HC + TY + 2)
-        rc[it] = chi_at(x0 + lx - HC, y0 + ly - HC);
+        rc[it] = chi_at_tile<R, KH, TX, TY>(a, sQ, tx, ty, x0 + lx - HC, y0 + ly - HC);
     }
 #pragma unroll
     for (int it = 0; it < IC; ++it) {
@@ -571,11 +672,95 @@ __device__ __forceinline__ void step2d_tile(const Step2dArgs<R>& a, const int t)
 
 template <typename R, int KH, int NT = 512, int TX = 64, int TY = 16>
 __global__ void __launch_bounds__(NT) k_step2d(Step2dArgs<R> a) {
-  // XCD-aware order: consecutive blocks land on different XCDs, so block b
-  // takes tile (b % 8) * per_xcd + b / 8 and each XCD walks a contiguous band
-  const int t = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
+  const int t = tile_of_block(blockIdx.x, a.tiles[0], a.per_xcd, a.diag);
   if (t >= a.ntiles) return;
   step2d_tile<R, KH, NT, TX, TY>(a, t);
+}
+
+// The moving-interface geometry alone (the step then runs the transport on
+// chi_out): every tile writes its chi^{n+1}, quiescent tiles the clamp value,
+// so that chi_out holds explicit values everywhere.  Small tiles (GEO_T x
+// GEO_T) spread the sweeps of the interface band over many CUs.
+constexpr int GEO_T = 16, GEO_THREADS = 256;
+// Pass 1 of the weighted-form geometry: one wave per tile, no LDS, no
+// barrier.  Decides quiescence from the tile's VoF and the neighbour flags
+// (wave votes); a quiescent tile gets its clamp value and flag, a live tile
+// is appended to live[] (count in *nlive).  Also clears the other step's
+// counter (*nlive_next) for the next call.
+template <typename R, int KH>
+__global__ void __launch_bounds__(256) k_geo_classify(Step2dArgs<R> a, int* nlive, int* live,
+                                                    int* nlive_next) {
+  using T = Tile2<KH, GEO_T, GEO_T>;
+  constexpr int CPL = GEO_T * GEO_T / 64;  // cells per lane
+  static_assert(T::QN <= 64, "flag neighbourhood fits one wave");
+  if (blockIdx.x == 0 && threadIdx.x == 0) *nlive_next = 0;
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= a.ntiles) return;  // whole waves
+  const int lane = threadIdx.x & 63;
+  const int nx = a.g.n[0], ny = a.g.n[1];
+  const int tx = t % a.tiles[0], ty = t / a.tiles[0];
+  const int x0 = tx * GEO_T, y0 = ty * GEO_T;
+  bool one = true, zero = true;
+  long long ci[CPL];
+  bool in[CPL];
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) {
+    const int c = lane + 64 * k;
+    const int gx = x0 + c % GEO_T, gy = y0 + c / GEO_T;
+    in[k] = gx < nx && gy < ny;
+    ci[k] = (long long)gx + (long long)nx * gy;
+    if (in[k]) {
+      const R f = a.vof[ci[k]];
+      one = one && f == R(1);
+      zero = zero && f == R(0);
+    }
+  }
+  int q = 255;
+  if (lane < T::QN) {
+    int ux = tx + lane % T::QW - T::RX, uy = ty + lane / T::QW - T::RY;
+    bool ok = true;
+    if (ux < 0 || ux >= a.tiles[0]) {
+      if (a.g.bc[0][ux < 0 ? 0 : 1] == BC_PERIODIC) ux = (ux + a.tiles[0]) % a.tiles[0]; else ok = false;
+    }
+    if (uy < 0 || uy >= a.tiles[1]) {
+      if (a.g.bc[1][uy < 0 ? 0 : 1] == BC_PERIODIC) uy = (uy + a.tiles[1]) % a.tiles[1]; else ok = false;
+    }
+    if (ok) q = a.q_in[ux + a.tiles[0] * uy];
+  }
+  const bool all1 = __all(one), all0 = __all(zero);
+  const int want = all1 ? Q_POS : (all0 ? Q_NEG : -1);
+  // the 3 x 3 neighbourhood (the flag window may be larger)
+  const int dx = lane % T::QW - T::RX, dy = lane / T::QW - T::RY;
+  const bool near = lane < T::QN && dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && q != 255;
+  const bool quiet = __all(!near || q == want);
+  const bool nb_quiet = __all(!near || q != Q_LIVE);
+  if (!quiet) {
+    if (lane == 0) {
+      if (nb_quiet) atomicOr((unsigned*)(a.state + S_FLAGS), (unsigned)STATUS_GEOM_JUMP);
+      live[atomicAdd(nlive, 1)] = t;
+    }
+    return;
+  }
+  const R v = want == Q_POS ? a.p.chimax : -a.p.chimax;
+#pragma unroll
+  for (int k = 0; k < CPL; ++k)
+    if (in[k]) a.chi_out[ci[k]] = v;
+  if (lane == 0) a.q_out[t] = (uint8_t)want;
+}
+
+// Pass 2: the live tiles of pass 1, one workgroup each (workgroups past the
+// count exit at once), rebuilt by tile_geometry.
+template <typename R, int KH>
+__global__ void __launch_bounds__(GEO_THREADS) k_geo_live(Step2dArgs<R> a, const int* nlive,
+                                                          const int* live) {
+  using T = Tile2<KH, GEO_T, GEO_T>;
+  if ((int)blockIdx.x >= *nlive) return;
+  const int t = live[blockIdx.x];
+  __shared__ R sChi[T::NC];
+  __shared__ R sB[T::NC];
+  __shared__ uint8_t sQ[T::QN];
+  load_flags<R, KH, GEO_THREADS, GEO_T, GEO_T>(a, sQ, t % a.tiles[0], t / a.tiles[0]);
+  tile_geometry<R, KH, GEO_THREADS, GEO_T, GEO_T>(a, t, sChi, sB, sQ, true, false, false);
 }
 
 // Batched form: independent static-interface instances of different sizes,

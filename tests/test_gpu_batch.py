@@ -75,15 +75,14 @@ def run_single(prob, dt, vof, c0, prec, nsteps):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_batch_matches_single_problem_path(prec):
-    # the batched kernel inlines the same per-tile code as the single-problem
-    # kernel; the compiler may still contract a multiply-add differently in
-    # the two kernels, so agreement is to rounding level rather than bitwise
-    # (observed: bitwise on the weighted form, ~1 ulp in a few cells of the
-    # paper-form instance)
+    # the batched kernel (64 x 16 tiles) and the single-problem path (column
+    # streaming for the weighted form) order and contract the same arithmetic
+    # differently, so they agree to rounding level, not bitwise; each is
+    # checked against the FP64 oracle on its own
     insts = instances()
     N = 9
     got = run_batch(insts, prec, [4, 5])
-    ftol, ttol = (1e-14, 1e-13) if prec == 1 else (1e-6, 1e-8)
+    ftol, ttol = (1e-13, 1e-12) if prec == 1 else (2e-6, 2e-6)
     for i, (p, dt, vof, c0) in enumerate(insts):
         ref = run_single(p, dt, vof, c0, prec, N)
         for name, a, b in zip(("F", "psi", "sigma"), got[i][:3], ref[:3]):
