@@ -55,20 +55,20 @@ def workload(name, K, W):
     return C.c2_translating_sphere()
 
 
-def fused_moving(cfg):
-    """True when the library runs the moving-interface step as one fused 2D
-    kernel (redistancing inside): FP32, 2D, at most 16 sweeps per step."""
+def transport_kernel(cfg):
+    """Name of the transport kernel the library runs for the workload."""
     p = cfg["prob"]
-    return (cfg.get("vof_seq") is not None and p["dim"] == 2 and cfg["precision"] == 0
-            and cfg.get("hj_step", 8) <= 16 and min(p["n"][:2]) >= 36)
+    if p["dim"] == 3:
+        return "k_step"
+    return "k_col2d" if p.get("flux_form", 0) == 0 else "k_step2d"
 
 
 def algorithmic_bytes(cfg, es):
-    """(dominant-kernel bytes per cell, whole-step bytes per cell): every
-    compulsory field counted once, read or written.  Transport reads chi, the
-    state and the face velocities and writes the state and sigma; a moving
-    interface adds the VoF read and the level-set write, which belong to the
-    kernel itself when the step is fused."""
+    """(transport-kernel bytes per cell, whole-step bytes per cell): every
+    compulsory field counted once, read or written.  The transport reads chi,
+    the state and the face velocities and writes the state and sigma; a
+    moving interface adds the VoF read and the level-set write, done by the
+    geometry kernels before it."""
     p = cfg["prob"]
     dim = p["dim"]
     bulk = p.get("bulk_enabled", 1)
@@ -76,12 +76,11 @@ def algorithmic_bytes(cfg, es):
     fields = 2 if bulk else 1
     words = 1 + fields + (dim if has_u else 0) + fields + 1  # chi, state, u | state, sigma
     step_words = words + (2 if cfg.get("vof_seq") else 0)     # + vof read, chi write
-    kwords = step_words if fused_moving(cfg) else words
-    return kwords * es, step_words * es
+    return words * es, step_words * es
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step2d_expanding_circle_1024_traffic.md")
-KERNEL_SOURCES = ("surf_common.hpp", "surf_step2d.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_col2d_expanding_circle_1024_traffic.md")
+KERNEL_SOURCES = ("surf_common.hpp", "surf_kernels.hpp", "surf_col2d.hpp")
 
 
 def kernel_source_digest():
@@ -248,13 +247,12 @@ def main():
                    "hj_sweeps_per_step": prob["hj_iters_step"] if vofs is not None else 0,
                    "graph": graph is not None},
         "roofline": {
-            "bound": "hbm", "kernel": "k_step2d" if prob["dim"] == 2 else "k_step",
+            "bound": "hbm", "kernel": transport_kernel(cfg),
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_cell": kbytes, "avg_launch_us": round(k_avg_ms * 1e3, 3),
             "step_bytes_per_cell": sbytes, "step_frac": round(step_gbs / HBM_PEAK_GBS, 4),
-            "redistancing_us_per_step": round(geom_ms / K * 1e3, 3),
-            "redistancing_sweeps": int(geom_n),
+            "geometry_us_per_step": round(geom_ms / K * 1e3, 3),
         },
         "status": status,
         "wall_s": round(wall, 4),
