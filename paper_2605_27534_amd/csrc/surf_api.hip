@@ -41,8 +41,8 @@ struct surf_ctx {
   int gtiles[2];
   int ngtiles;
   int nflags;
-  int* nlive;    // [2] live-tile counters (one per level-set buffer)
-  int* live;     // [ngtiles] live-tile list
+  int* live;  // [1 + ngtiles]: count, then the live geometry tiles
+
   int per_xcd;
   // 2D weighted-form transport: column-streaming waves
   int col_strips, col_groups, col_nwg;
@@ -277,9 +277,6 @@ void materialize(surf_ctx* c) {
 }
 
 void flags_live(surf_ctx* c) {
-  if (c->ngtiles > 0)
-    hipLaunchKernelGGL(k_fill_u8, dim3(1), dim3(64), 0, c->stream, (uint8_t*)c->nlive, (uint8_t)0,
-                       (int)(2 * sizeof(int)));
   if (c->nflags == 0) return;
   hipLaunchKernelGGL(k_fill_u8, dim3((c->nflags + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, c->stream,
                      c->q[c->chi_cur], (uint8_t)Q_LIVE, c->nflags);
@@ -410,20 +407,19 @@ int col2d_impl(surf_ctx* c, const void* vof_next, const void* const* u, const vo
     a.diag = (c->gtiles[0] % 8) == 0 ? 1 : 0;
     {
       Timed tm(c, 1);
-      int* cnt = c->nlive + c->chi_cur;
-      int* cnt_next = c->nlive + (1 - c->chi_cur);
-      const dim3 gc((c->ngtiles + 3) / 4), gl(c->ngtiles);
-      if (a.ksweeps <= 8) {
-        hipLaunchKernelGGL((k_geo_classify<R, 8>), gc, dim3(256), 0, c->stream, a, cnt, c->live,
-                           cnt_next);
-        hipLaunchKernelGGL((k_geo_live<R, 8>), gl, dim3(GEO_THREADS), 0, c->stream, a,
-                           (const int*)cnt, (const int*)c->live);
-      } else {
-        hipLaunchKernelGGL((k_geo_classify<R, 16>), gc, dim3(256), 0, c->stream, a, cnt, c->live,
-                           cnt_next);
-        hipLaunchKernelGGL((k_geo_live<R, 16>), gl, dim3(GEO_THREADS), 0, c->stream, a,
-                           (const int*)cnt, (const int*)c->live);
-      }
+      const dim3 gc((c->ngtiles + 3) / 4), gl(GEO_LIVE_GRID);
+      if (a.ksweeps <= 8)
+        hipLaunchKernelGGL((k_geo_classify<R, 8>), gc, dim3(256), 0, c->stream, a);
+      else
+        hipLaunchKernelGGL((k_geo_classify<R, 16>), gc, dim3(256), 0, c->stream, a);
+      hipLaunchKernelGGL(k_geo_list, dim3(1), dim3(GEO_LIST_THREADS), 0, c->stream,
+                         (const uint8_t*)a.q_out, c->ngtiles, c->live);
+      if (a.ksweeps <= 8)
+        hipLaunchKernelGGL((k_geo_live<R, 8>), gl, dim3(GEO_WG), 0, c->stream, a,
+                           (const int*)c->live);
+      else
+        hipLaunchKernelGGL((k_geo_live<R, 16>), gl, dim3(GEO_WG), 0, c->stream, a,
+                           (const int*)c->live);
     }
     c->chi_cur = 1 - c->chi_cur;
     c->materialized = true;
@@ -678,9 +674,9 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   b += 2 * align_up((size_t)flag_count(grid, params) + 1);
   {
     int tg[2];
-    int ng = geo_tiles(grid, params, tg);
-    b += align_up(2 * sizeof(int)) + align_up((size_t)(ng + 1) * sizeof(int));
+    b += align_up((size_t)(geo_tiles(grid, params, tg) + 1) * sizeof(int));
   }
+
   if (params->adjoint) {
     b += 4 * align_up(n * es);
     b += align_up((size_t)((n + BLOCK - 1) / BLOCK) * NADJ * sizeof(double));
@@ -736,10 +732,9 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
   p += align_up((size_t)c->nflags + 1);
   c->q[1] = (uint8_t*)p;
   p += align_up((size_t)c->nflags + 1);
-  c->nlive = (int*)p;
-  p += align_up(2 * sizeof(int));
   c->live = (int*)p;
   p += align_up((size_t)(c->ngtiles + 1) * sizeof(int));
+
   for (int i = 0; i < 4; ++i) {
     c->adj[i] = params->adjoint ? (void*)p : nullptr;
     if (params->adjoint) p += align_up(c->ncell * es);

@@ -20,7 +20,7 @@
 
 namespace surf {
 
-enum { Q_LIVE = 0, Q_POS = 1, Q_NEG = 2 };
+enum { Q_LIVE = 0, Q_POS = 1, Q_NEG = 2, Q_TODO = 3 };  // Q_TODO: live, not yet rebuilt
 enum { STATUS_GEOM_JUMP = 8 };
 
 template <typename R>
@@ -153,7 +153,9 @@ __device__ __forceinline__ void load_flags(const Step2dArgs<R>& a, uint8_t* sQ, 
 // chi_out the tile's values of live tiles (and, with write_quiet, of
 // quiescent tiles too), q_out[t] the new flag.  Returns whether the tile was
 // live.  sQ must hold the flags (load_flags) and all1 / all0 the VoF
-// uniformity of the tile (block-wide); sB has NC elements.
+// uniformity of the tile (block-wide); sB has NC elements.  DECIDED: the
+// tile is known to be live and chi_in holds explicit values everywhere (sQ
+// and all1 / all0 are not used).
 // Whether the VoF of tile t is uniformly 1 / uniformly 0 (block-wide).
 template <typename R, int NT, int TX, int TY>
 __device__ __forceinline__ void tile_vof_uniform(const Step2dArgs<R>& a, const int t, bool& all1,
@@ -177,7 +179,7 @@ __device__ __forceinline__ void tile_vof_uniform(const Step2dArgs<R>& a, const i
   all0 = __syncthreads_and(all0);
 }
 
-template <typename R, int KH, int NT, int TX, int TY>
+template <typename R, int KH, int NT, int TX, int TY, bool DECIDED = false>
 __device__ __forceinline__ bool tile_geometry(const Step2dArgs<R>& a, const int t, R* sChi,
                                               R* sB, const uint8_t* sQ, bool write_quiet,
                                               const bool all1, const bool all0) {
@@ -190,34 +192,36 @@ __device__ __forceinline__ bool tile_geometry(const Step2dArgs<R>& a, const int 
   const int nx = g.n[0], ny = g.n[1];
   const int tx = t % a.tiles[0], ty = t / a.tiles[0];
   const int x0 = tx * TX, y0 = ty * TY;
-  int want = all1 ? Q_POS : (all0 ? Q_NEG : -1);
-  bool quiet = true, nb_quiet = true;
-  for (int dy = -1; dy <= 1; ++dy)
-    for (int dx = -1; dx <= 1; ++dx) {
-      uint8_t q = sQ[(dx + T::RX) + T::QW * (dy + T::RY)];
-      if (q == 255) continue;
-      if ((int)q != want) quiet = false;
-      if (q == Q_LIVE) nb_quiet = false;
-    }
-  const bool active = !quiet;
-  // the VoF changed under a tile whose whole neighbourhood was quiescent:
-  // the interface moved farther than the clamp distance in one step
-  if (tid == 0 && active && nb_quiet)
-    atomicOr((unsigned*)(a.state + S_FLAGS), (unsigned)STATUS_GEOM_JUMP);
-  if (!active) {
-    R v = want == Q_POS ? p.chimax : -p.chimax;
-    if (write_quiet) {
-#pragma unroll
-      for (int it = 0; it < IT; ++it) {
-        int l = tid + it * NT;
-        int gx = x0 + l % TX, gy = y0 + l / TX;
-        if (l < TX * TY && gx < nx && gy < ny) a.chi_out[(long long)gx + (long long)nx * gy] = v;
+  if constexpr (!DECIDED) {
+    int want = all1 ? Q_POS : (all0 ? Q_NEG : -1);
+    bool quiet = true, nb_quiet = true;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        uint8_t q = sQ[(dx + T::RX) + T::QW * (dy + T::RY)];
+        if (q == 255) continue;
+        if ((int)q != want) quiet = false;
+        if (q == Q_LIVE) nb_quiet = false;
       }
-    } else {
-      for (int l = tid; l < NC; l += NT) sChi[l] = v;
+    const bool active = !quiet;
+    // the VoF changed under a tile whose whole neighbourhood was quiescent:
+    // the interface moved farther than the clamp distance in one step
+    if (tid == 0 && active && nb_quiet)
+      atomicOr((unsigned*)(a.state + S_FLAGS), (unsigned)STATUS_GEOM_JUMP);
+    if (!active) {
+      R v = want == Q_POS ? p.chimax : -p.chimax;
+      if (write_quiet) {
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+          int l = tid + it * NT;
+          int gx = x0 + l % TX, gy = y0 + l / TX;
+          if (l < TX * TY && gx < nx && gy < ny) a.chi_out[(long long)gx + (long long)nx * gy] = v;
+        }
+      } else {
+        for (int l = tid; l < NC; l += NT) sChi[l] = v;
+      }
+      if (tid == 0) a.q_out[t] = (uint8_t)want;
+      return false;
     }
-    if (tid == 0) a.q_out[t] = (uint8_t)want;
-    return false;
   }
   R* sV = sB;  // the VoF until the pin data is in registers
   // this thread's cells of the tile + HC region
@@ -237,7 +241,8 @@ __device__ __forceinline__ bool tile_geometry(const Step2dArgs<R>& a, const int 
         int mx = map_axis(gx, nx, g.bc[0][0], g.bc[0][1]);
         int my = map_axis(gy, ny, g.bc[1][0], g.bc[1][1]);
         rv[it] = a.vof[(long long)mx + (long long)nx * my];
-        rc[it] = chi_at_tile<R, KH, TX, TY>(a, sQ, tx, ty, gx, gy);
+        if constexpr (DECIDED) rc[it] = a.chi_in[(long long)mx + (long long)nx * my];
+        else rc[it] = chi_at_tile<R, KH, TX, TY>(a, sQ, tx, ty, gx, gy);
       }
     }
 #pragma unroll
@@ -270,27 +275,38 @@ __device__ __forceinline__ bool tile_geometry(const Step2dArgs<R>& a, const int 
     G[it] = cut ? p.h * c0 / Delta : (c0 > R(0) ? R(INFINITY) : R(-INFINITY));
   }
   __syncthreads();  // sV is read; sB becomes the second sweep buffer
-  // K Jacobi sweeps on shrinking regions
+  // K Jacobi sweeps on shrinking regions: the cell at depth d (distance to
+  // the edge of the tile + HC region) is updated by sweeps 1 .. d, so the
+  // next sweep never reads a value this one did not write
+  int dep[IC];
+#pragma unroll
+  for (int it = 0; it < IC; ++it) {
+    const int dx = min(cx[it], EXC - 1 - cx[it]), dy = min(cy[it], EYC - 1 - cy[it]);
+    dep[it] = cl[it] < NC ? min(dx, dy) : -1;
+  }
   int par = 0;
   for (int k = 1; k <= a.ksweeps; ++k) {
     const R* src = par ? sB : sChi;
     R* dst = par ? sChi : sB;
-    const int r = HC - k;  // halo of the region updated by this sweep
+    R xm[IC], xp[IC], ym[IC], yp[IC];
 #pragma unroll
     for (int it = 0; it < IC; ++it) {
-      const int l = cl[it];
-      // only the region's cells: the next sweep reads nothing outside it
-      if (l >= NC || cx[it] < HC - r || cx[it] >= HC + TX + r || cy[it] < HC - r ||
-          cy[it] >= HC + TY + r)
-        continue;
-      R v;
+      // neighbour reads first (an in-range index for cells off this sweep)
+      const int l = dep[it] >= k ? cl[it] : EXC + 1;
+      xm[it] = src[l - 1];
+      xp[it] = src[l + 1];
+      ym[it] = src[l - EXC];
+      yp[it] = src[l + EXC];
+    }
+#pragma unroll
+    for (int it = 0; it < IC; ++it) {
+      if (dep[it] < k) continue;
       const R gv = G[it];
-      if (fabs(gv) < R(INFINITY)) {
-        v = gv;
-      } else {
+      R v = gv;
+      if (!(fabs(gv) < R(INFINITY))) {
         const R x = cur[it];
-        const R bwx = (x - src[l - 1]) * p.inv_h, fwx = (src[l + 1] - x) * p.inv_h;
-        const R bwy = (x - src[l - EXC]) * p.inv_h, fwy = (src[l + EXC] - x) * p.inv_h;
+        const R bwx = (x - xm[it]) * p.inv_h, fwx = (xp[it] - x) * p.inv_h;
+        const R bwy = (x - ym[it]) * p.inv_h, fwy = (yp[it] - x) * p.inv_h;
         const R sgn = gv > R(0) ? R(1) : R(-1);
         // Godunov: upwind one-sided differences for the sign of chi0
         const R a1 = sgn * bwx, b1 = sgn * fwx, a2 = sgn * bwy, b2 = sgn * fwy;
@@ -304,7 +320,7 @@ __device__ __forceinline__ bool tile_geometry(const Step2dArgs<R>& a, const int 
       v = v > p.chimax ? p.chimax : v;
       v = v < -p.chimax ? -p.chimax : v;
       cur[it] = v;
-      dst[l] = v;
+      dst[cl[it]] = v;
     }
     __syncthreads();
     par ^= 1;
@@ -330,9 +346,19 @@ __device__ __forceinline__ bool tile_geometry(const Step2dArgs<R>& a, const int 
       allneg = allneg && v == -p.chimax;
     }
   }
-  allpos = __syncthreads_and(allpos);
-  allneg = __syncthreads_and(allneg);
-  if (tid == 0) a.q_out[t] = allpos ? Q_POS : (allneg ? Q_NEG : Q_LIVE);
+  // both votes with one barrier: per-wave votes through LDS (the sweep
+  // buffer sB is free again)
+  {
+    int* sVote = reinterpret_cast<int*>(sB);
+    const bool wp = __all(allpos), wn = __all(allneg);
+    if ((tid & 63) == 0) sVote[tid >> 6] = (wp ? 1 : 0) | (wn ? 2 : 0);
+    __syncthreads();
+    if (tid == 0) {
+      int m = 3;
+      for (int w = 0; w < (NT + 63) / 64; ++w) m &= sVote[w];
+      a.q_out[t] = (m & 1) ? Q_POS : ((m & 2) ? Q_NEG : Q_LIVE);
+    }
+  }
   return true;
 }
 
@@ -682,18 +708,21 @@ __global__ void __launch_bounds__(NT) k_step2d(Step2dArgs<R> a) {
 // so that chi_out holds explicit values everywhere.  Small tiles (GEO_T x
 // GEO_T) spread the sweeps of the interface band over many CUs.
 constexpr int GEO_T = 16, GEO_THREADS = 256;
-// Pass 1 of the weighted-form geometry: one wave per tile, no LDS, no
-// barrier.  Decides quiescence from the tile's VoF and the neighbour flags
-// (wave votes); a quiescent tile gets its clamp value and flag, a live tile
-// is appended to live[] (count in *nlive).  Also clears the other step's
-// counter (*nlive_next) for the next call.
+// The weighted-form moving geometry in three launches, none with a
+// device-wide atomic (those serialise across the XCDs):
+//  1. k_geo_classify: one wave per tile decides from the tile's VoF and the
+//     neighbour flags of the previous step whether it stays quiescent (clamp
+//     value and flag written) or is live (flag Q_TODO);
+//  2. k_geo_list: one workgroup compacts the live tiles, in tile order, into
+//     a list and a count;
+//  3. k_geo_live: a fixed grid takes list entries w, w + G, ... and rebuilds
+//     each with tile_geometry (1024 threads: 16 waves overlap each sweep's
+//     LDS and barrier latency).
 template <typename R, int KH>
-__global__ void __launch_bounds__(256) k_geo_classify(Step2dArgs<R> a, int* nlive, int* live,
-                                                    int* nlive_next) {
+__global__ void __launch_bounds__(256) k_geo_classify(Step2dArgs<R> a) {
   using T = Tile2<KH, GEO_T, GEO_T>;
   constexpr int CPL = GEO_T * GEO_T / 64;  // cells per lane
   static_assert(T::QN <= 64, "flag neighbourhood fits one wave");
-  if (blockIdx.x == 0 && threadIdx.x == 0) *nlive_next = 0;
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= a.ntiles) return;  // whole waves
   const int lane = threadIdx.x & 63;
@@ -736,8 +765,10 @@ __global__ void __launch_bounds__(256) k_geo_classify(Step2dArgs<R> a, int* nliv
   const bool nb_quiet = __all(!near || q != Q_LIVE);
   if (!quiet) {
     if (lane == 0) {
+      // the VoF changed under a tile whose whole neighbourhood was
+      // quiescent: the interface moved farther than the clamp in one step
       if (nb_quiet) atomicOr((unsigned*)(a.state + S_FLAGS), (unsigned)STATUS_GEOM_JUMP);
-      live[atomicAdd(nlive, 1)] = t;
+      a.q_out[t] = (uint8_t)Q_TODO;
     }
     return;
   }
@@ -748,19 +779,48 @@ __global__ void __launch_bounds__(256) k_geo_classify(Step2dArgs<R> a, int* nliv
   if (lane == 0) a.q_out[t] = (uint8_t)want;
 }
 
-// Pass 2: the live tiles of pass 1, one workgroup each (workgroups past the
-// count exit at once), rebuilt by tile_geometry.
+constexpr int GEO_LIST_THREADS = 1024;
+// live[0] = count, live[1 + r] = the r-th live tile in tile order
+__global__ void __launch_bounds__(GEO_LIST_THREADS) k_geo_list(const uint8_t* __restrict__ q,
+                                                               int ntiles, int* __restrict__ live) {
+  __shared__ int sWave[GEO_LIST_THREADS / 64];
+  __shared__ int sBase;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) sBase = 0;
+  __syncthreads();
+  for (int base = 0; base < ntiles; base += GEO_LIST_THREADS) {
+    const int t = base + tid;
+    const bool todo = t < ntiles && q[t] == Q_TODO;
+    const unsigned long long m = __ballot(todo);
+    const int below = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) sWave[wv] = __popcll(m);
+    __syncthreads();
+    int off = sBase;
+    for (int w = 0; w < wv; ++w) off += sWave[w];
+    if (todo) live[1 + off + below] = t;
+    __syncthreads();
+    if (tid == 0) {
+      int tot = 0;
+      for (int w = 0; w < GEO_LIST_THREADS / 64; ++w) tot += sWave[w];
+      sBase += tot;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) live[0] = sBase;
+}
+
+constexpr int GEO_WG = 1024, GEO_LIVE_GRID = 512;
 template <typename R, int KH>
-__global__ void __launch_bounds__(GEO_THREADS) k_geo_live(Step2dArgs<R> a, const int* nlive,
-                                                          const int* live) {
+__global__ void __launch_bounds__(GEO_WG) k_geo_live(Step2dArgs<R> a, const int* __restrict__ live) {
   using T = Tile2<KH, GEO_T, GEO_T>;
-  if ((int)blockIdx.x >= *nlive) return;
-  const int t = live[blockIdx.x];
   __shared__ R sChi[T::NC];
   __shared__ R sB[T::NC];
-  __shared__ uint8_t sQ[T::QN];
-  load_flags<R, KH, GEO_THREADS, GEO_T, GEO_T>(a, sQ, t % a.tiles[0], t / a.tiles[0]);
-  tile_geometry<R, KH, GEO_THREADS, GEO_T, GEO_T>(a, t, sChi, sB, sQ, true, false, false);
+  const int n = live[0];
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    tile_geometry<R, KH, GEO_WG, GEO_T, GEO_T, true>(a, live[1 + i], sChi, sB, nullptr, true,
+                                                     false, false);
+    __syncthreads();
+  }
 }
 
 // Batched form: independent static-interface instances of different sizes,
