@@ -41,7 +41,7 @@ struct surf_ctx {
   int gtiles[2];
   int ngtiles;
   int nflags;
-  int* live;  // [1 + ngtiles]: count, then the live geometry tiles
+
 
   int per_xcd;
   // 2D weighted-form transport: column-streaming waves
@@ -204,6 +204,9 @@ constexpr int COL_TY = 8, COL_TY64 = 8;
 int col_shape(const surf_grid* gr, const surf_params* p, int* strips, int* groups) {
   *strips = *groups = 0;
   if (gr->dim != 2 || p->flux_form != SURF_FLUX_WEIGHTED) return 0;
+  // 32-bit byte offsets of the buffer-resource access
+  const long long es = p->precision == SURF_F64 ? 8 : 4;
+  if ((long long)(gr->n[0] + 1) * (gr->n[1] + 1) * es > 0x7fffffffll) return 0;
   int ty = p->precision == SURF_F64 ? COL_TY64 : COL_TY;
   int chunks = (gr->n[1] + ty - 1) / ty;
   *strips = (gr->n[0] + COL_OUT - 1) / COL_OUT;
@@ -407,19 +410,18 @@ int col2d_impl(surf_ctx* c, const void* vof_next, const void* const* u, const vo
     a.diag = (c->gtiles[0] % 8) == 0 ? 1 : 0;
     {
       Timed tm(c, 1);
-      const dim3 gc((c->ngtiles + 3) / 4), gl(GEO_LIVE_GRID);
-      if (a.ksweeps <= 8)
+      // pass 2 grid: at most GEO_LIVE_CAP tiles per workgroup even if every
+      // tile is live
+      int nl = GEO_LIVE_GRID;
+      while ((long long)nl * GEO_LIVE_CAP < c->ngtiles) nl *= 2;
+      const dim3 gc((c->ngtiles + 3) / 4), gl(nl);
+      if (a.ksweeps <= 8) {
         hipLaunchKernelGGL((k_geo_classify<R, 8>), gc, dim3(256), 0, c->stream, a);
-      else
+        hipLaunchKernelGGL((k_geo_live<R, 8>), gl, dim3(GEO_WG), 0, c->stream, a);
+      } else {
         hipLaunchKernelGGL((k_geo_classify<R, 16>), gc, dim3(256), 0, c->stream, a);
-      hipLaunchKernelGGL(k_geo_list, dim3(1), dim3(GEO_LIST_THREADS), 0, c->stream,
-                         (const uint8_t*)a.q_out, c->ngtiles, c->live);
-      if (a.ksweeps <= 8)
-        hipLaunchKernelGGL((k_geo_live<R, 8>), gl, dim3(GEO_WG), 0, c->stream, a,
-                           (const int*)c->live);
-      else
-        hipLaunchKernelGGL((k_geo_live<R, 16>), gl, dim3(GEO_WG), 0, c->stream, a,
-                           (const int*)c->live);
+        hipLaunchKernelGGL((k_geo_live<R, 16>), gl, dim3(GEO_WG), 0, c->stream, a);
+      }
     }
     c->chi_cur = 1 - c->chi_cur;
     c->materialized = true;
@@ -672,10 +674,7 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   b += align_up((size_t)npart * NPART * sizeof(double));
   b += 3 * align_up(n * es);
   b += 2 * align_up((size_t)flag_count(grid, params) + 1);
-  {
-    int tg[2];
-    b += align_up((size_t)(geo_tiles(grid, params, tg) + 1) * sizeof(int));
-  }
+
 
   if (params->adjoint) {
     b += 4 * align_up(n * es);
@@ -732,8 +731,7 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
   p += align_up((size_t)c->nflags + 1);
   c->q[1] = (uint8_t*)p;
   p += align_up((size_t)c->nflags + 1);
-  c->live = (int*)p;
-  p += align_up((size_t)(c->ngtiles + 1) * sizeof(int));
+
 
   for (int i = 0; i < 4; ++i) {
     c->adj[i] = params->adjoint ? (void*)p : nullptr;

@@ -74,6 +74,29 @@ __device__ __forceinline__ double wshift(double v) {
 template <typename R> __device__ __forceinline__ R from_right(R v) { return wshift<DPP_WF_SL1>(v); }
 template <typename R> __device__ __forceinline__ R from_left(R v) { return wshift<DPP_WF_SR1>(v); }
 
+// Buffer-resource access: the base address lives in scalar registers and
+// each lane adds a 32-bit byte offset; reads past num_records return 0 and
+// writes past it are dropped.  Word 3 of the descriptor is the raw
+// (untyped, 32-bit) format of gfx9-class GPUs.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, long long bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename R> __device__ __forceinline__ R bload(rsrc_t r, int voff, int soff);
+template <> __device__ __forceinline__ float bload<float>(rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ double bload<double>(rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(float v, rsrc_t r, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(double v, rsrc_t r, int voff, int soff) {
+  using w64 = unsigned int __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(w64, v), r, voff, soff, 0);
+}
+
 // minmod(a, b) is the median of (a, b, 0): 0 for opposite signs, else the
 // argument of smaller magnitude
 template <typename R> __device__ __forceinline__ R mm(R a, R b) { return minmod<R>(a, b); }
@@ -103,9 +126,10 @@ struct ColAcc {
   int nbad;
 };
 
-// One wave: strip x0, rows y0 .. y0 + TY - 1 (y0 < ny).  INT: the strip and
-// every row it reads lie inside the box, away from all sides.
-template <typename R, int TY, bool HU, bool BULK, bool INT>
+// One wave: strip x0, rows y0 .. y0 + TY - 1 (y0 < ny).  IX: every column
+// the strip reads lies inside the box away from the x sides; IY: the same
+// for the rows and the y sides.
+template <typename R, int TY, bool HU, bool BULK, bool IX, bool IY>
 __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, const int y0,
                                            const int lane, ColAcc<R>& acc) {
   constexpr int NR3 = TY + 6;  // state rows y0-3 .. y0+TY+2
@@ -124,7 +148,7 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
   const int xs = x0 - 3 + lane;
   int mx = xs, fxm = xs + 1;
   bool gcell_x = false, xf_lo = false, xf_hi = false, xf_out = false;
-  if constexpr (!INT) {
+  if constexpr (!IX) {
     mx = map_axis(xs, nx, g.bc[0][0], g.bc[0][1]);
     gcell_x = !px && (xs < 0 || xs >= nx);
     const int fx = xs + 1;  // the lane's right face
@@ -133,47 +157,70 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
     xf_out = !px && (fx < 0 || fx > nx);
     if (px) fxm = ((fx % nx) + nx) % nx;
   }
-  const bool out_lane = lane >= 3 && lane < 3 + COL_OUT && (INT || xs < nx);
+  const bool out_lane = lane >= 3 && lane < 3 + COL_OUT && (IX || xs < nx);
+  // lane constants of the x sides
+  const bool x_side = xf_lo || xf_hi;
+  const bool x_lo_open = xf_lo && ox_lo, x_hi_open = xf_hi && ox_hi;
+  const double wlo = (!IX && !px && xs == 0 && ox_lo) ? -1.0 : 0.0;
+  const double whi = (!IX && !px && xs == nx - 1 && ox_hi) ? 1.0 : 0.0;
 
   // ---- loads, in the order of use: group k holds state row k (F, psi),
   // y face k-3 and level-set / x-face row k-4; iteration i consumes group i,
   // and group i + LOOKAHEAD is issued before iteration i computes
+  constexpr int ES = (int)sizeof(R);
+  const long long ncell = (long long)nx * ny;
+  const rsrc_t bF = make_rsrc(a.F, BULK ? ncell * ES : 0), bP = make_rsrc(a.psi, ncell * ES);
+  const rsrc_t bC = make_rsrc(a.chi, ncell * ES);
+  const rsrc_t bUx = make_rsrc(a.u[0], HU ? (long long)(nx + 1) * ny * ES : 0);
+  const rsrc_t bUy = make_rsrc(a.u[1], HU ? (long long)nx * (ny + 1) * ES : 0);
+  const int vmx = mx * ES, vfx = fxm * ES;  // per-lane byte offsets
   R rF[NR3], rP[NR3], rC[NR1], rUx[NR1], rUy[NFY];
   auto load_group = [&](const int k) {
     if (k < NR3) {
-      const int my = INT ? y0 - 3 + k : map_axis(y0 - 3 + k, ny, g.bc[1][0], g.bc[1][1]);
-      const long long row = (long long)nx * my;
-      rF[k] = BULK ? a.F[row + mx] : R(0);
-      rP[k] = a.psi[row + mx];
+      const int my = IY ? y0 - 3 + k : map_axis(y0 - 3 + k, ny, g.bc[1][0], g.bc[1][1]);
+      const int row = nx * my * ES;
+      rF[k] = BULK ? bload<R>(bF, vmx, row) : R(0);
+      rP[k] = bload<R>(bP, vmx, row);
     }
     if (k >= 3 && k - 3 < NFY) {
       const int i = k - 3;
       rUy[i] = R(0);
       if (HU) {
         int j = y0 - 1 + i;
-        bool ok = true;
-        if (!INT) {
-          ok = !gcell_x;
-          if (py) j = ((j % ny) + ny) % ny;
-          else ok = ok && j >= 0 && j <= ny;
+        bool ok = IX || !gcell_x;
+        if (!IY) {
+          if (py) {
+            while (j < 0) j += ny;
+            while (j >= ny) j -= ny;
+          } else if (j < 0 || j > ny) {
+            j = 0;
+            ok = false;
+          }
         }
-        if (ok) rUy[i] = a.u[1][(long long)nx * j + mx];
+        const R v = bload<R>(bUy, vmx, nx * j * ES);
+        rUy[i] = ok ? v : R(0);
       }
     }
     if (k >= 4 && k - 4 < NR1) {
       const int i = k - 4;
       const int ys = y0 - 1 + i;
-      const int my = INT ? ys : map_axis(ys, ny, g.bc[1][0], g.bc[1][1]);
-      rC[i] = a.chi[(long long)nx * my + mx];
+      const int my = IY ? ys : map_axis(ys, ny, g.bc[1][0], g.bc[1][1]);
+      rC[i] = bload<R>(bC, vmx, nx * my * ES);
       rUx[i] = R(0);
       if (HU) {
-        const bool ok = INT || (!xf_out && !(!py && (ys < 0 || ys >= ny)));
-        if (ok) rUx[i] = a.u[0][(long long)(nx + 1) * my + fxm];
+        const bool ok = (IX || !xf_out) && (IY || py || (ys >= 0 && ys < ny));
+        const R v = bload<R>(bUx, vfx, (nx + 1) * my * ES);
+        rUx[i] = ok ? v : R(0);
       }
     }
   };
 #pragma unroll
   for (int k = 0; k < 3 + COL_LOOKAHEAD && k < NR3; ++k) load_group(k);
+
+  const rsrc_t bFo = make_rsrc(a.Fo, BULK ? ncell * ES : 0), bPo = make_rsrc(a.Po, ncell * ES);
+  const rsrc_t bS = make_rsrc(a.sig, a.sig ? ncell * ES : 0);
+  const int vxs = xs * ES;
+  const R kl = p.kin == KIN_LANGMUIR ? R(1) : R(0);
 
   // ---- values carried from row to row
   R dF2 = rF[1] - rF[0], dP2 = rP[1] - rP[0];  // y differences below rows s-1 and s
@@ -201,7 +248,7 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
       const R uf = rUy[i - 3];
       nyF = BULK ? bcg_face<R>(uf, rF[i - 2], rF[i - 1], dF2, dF1, dF0, hcfl) : R(0);
       nyP = bcg_face<R>(uf, rP[i - 2], rP[i - 1], dP2, dP1, dP0, hcfl);
-      if (!INT) {
+      if (!IY) {
         if (!py && j == 0) {
           nyF = (BULK && oy_lo) ? uf * rF[i - 1] : R(0);
           nyP = oy_lo ? uf * rP[i - 1] : R(0);
@@ -212,7 +259,10 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
           nyF = R(0);
           nyP = R(0);
         }
-        if (gcell_x) { nyF = R(0); nyP = R(0); }
+      }
+      if (!IX) {
+        nyF = gcell_x ? R(0) : nyF;
+        nyP = gcell_x ? R(0) : nyP;
       }
     }
     dF2 = dF1; dP2 = dP1;
@@ -222,7 +272,7 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
       // ---- row s: advected state, phase field, c*, Gamma*
       const int s = y0 - 5 + i;
       const int k1 = i - 4;
-      const bool grow = !INT && !py && (s < 0 || s >= ny);
+      const bool grow = !IY && !py && (s < 0 || s >= ny);
       const R xF = rF[i - 2], xP = rP[i - 2];
       R Fs = xF, Ps = xP;
       R fxF = R(0), fxP = R(0), fxLF = R(0), fxLP = R(0);
@@ -236,23 +286,26 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
         const R ePl = from_left(eP), ePr = from_right(eP);
         fxF = BULK ? bcg_face<R>(ux, xF, xFr, eFl, eF, eFr, hcfl) : R(0);
         fxP = bcg_face<R>(ux, xP, xPr, ePl, eP, ePr, hcfl);
-        if (!INT) {
-          if (xf_lo) {
-            fxF = (BULK && ox_lo) ? ux * xFr : R(0);
-            fxP = ox_lo ? ux * xPr : R(0);
-          }
-          if (xf_hi) {
-            fxF = (BULK && ox_hi) ? ux * xF : R(0);
-            fxP = ox_hi ? ux * xP : R(0);
-          }
-          if (xf_out || grow) { fxF = R(0); fxP = R(0); }
+        if (!IX || !IY) {
+          // lane-constant selects: an open side carries the interior cell,
+          // a wall nothing, faces beyond a side and rows outside nothing
+          const R oF = x_lo_open ? ux * xFr : (x_hi_open ? ux * xF : R(0));
+          const R oP = x_lo_open ? ux * xPr : (x_hi_open ? ux * xP : R(0));
+          fxF = x_side ? (BULK ? oF : R(0)) : fxF;
+          fxP = x_side ? oP : fxP;
+          fxF = (xf_out || grow) ? R(0) : fxF;
+          fxP = (xf_out || grow) ? R(0) : fxP;
         }
         fxLF = from_left(fxF);
         fxLP = from_left(fxP);
         Fs = xF - cfl * ((fxF - fxLF) + (nyF - gyF));
         Ps = xP - cfl * ((fxP - fxLP) + (nyP - gyP));
       }
-      if (!INT && (gcell_x || grow)) { Fs = R(0); Ps = R(0); }
+      if (!IX || !IY) {
+        const bool ghost = gcell_x || grow;
+        Fs = ghost ? R(0) : Fs;
+        Ps = ghost ? R(0) : Ps;
+      }
       if (!BULK) Fs = R(0);
       R ph, om, de;
       phase<R>(rC[k1], p, ph, om, de);
@@ -264,29 +317,31 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
       const R phr = from_right(ph), der = from_right(de);
       const R csr = from_right(cs), Gsr = from_right(Gs);
       R wxF = (ph + phr) * (csr - cs), wxP = (de + der) * (Gsr - Gs);
-      if (!INT && (xf_lo || xf_hi)) { wxF = R(0); wxP = R(0); }
+      if (!IX) {
+        wxF = x_side ? R(0) : wxF;
+        wxP = x_side ? R(0) : wxP;
+      }
       const R axF = wxF - from_left(wxF), axP = wxP - from_left(wxP);
       R wyF = (pPh + ph) * (cs - pC), wyP = (pDe + de) * (Gs - pG);
-      if (!INT && !py && (s == 0 || s == ny)) { wyF = R(0); wyP = R(0); }
+      if (!IY && !py && (s == 0 || s == ny)) { wyF = R(0); wyP = R(0); }
       const R uxL = from_left(ux);
 
       if (i >= 6) {
         // ---- row o = s-1: update, source, sigma, reduction terms
         const int o = s - 1;
-        if (out_lane && (INT || o < ny)) {
+        if (out_lane && (IY || o < ny)) {
           const R divF = dcoef * (pAxF + (wyF - pWyF));
           const R divP = scoef * (pAxP + (wyP - pWyP));
-          R q = R(0);
-          if (BULK)
-            q = p.kin == KIN_LANGMUIR ? p.ka * pC * (p.ginf * pDe - pPs) - p.kd * pPs
-                                      : p.ka * pC * p.ginf * pDe - p.kd * pPs;
+          // Langmuir k_a c (Gamma_inf delta - psi) - k_d psi; Henry drops the
+          // psi in the adsorption term (kl = 0)
+          const R q = BULK ? p.ka * pC * (p.ginf * pDe - kl * pPs) - p.kd * pPs : R(0);
           const R Fn = BULK ? pFs + a.dt * (divF - q) : R(0);
           const R Pn = pPs + a.dt * (divP + q);
           const R sg = eos<R>(quot<R>(Pn, pDe + p.eta_eps, pIP), p);
-          const long long row = (long long)nx * o;
-          if (BULK) a.Fo[row + xs] = Fn;
-          a.Po[row + xs] = Pn;
-          if (a.sig) a.sig[row + xs] = sg;
+          const int row = nx * o * ES;
+          if (BULK) bstore(Fn, bFo, vxs, row);
+          bstore(Pn, bPo, vxs, row);
+          if (a.sig) bstore(sg, bS, vxs, row);
           acc.sF += (double)Fn;
           acc.sP += (double)Pn;
           acc.sD += (double)pDe;
@@ -300,15 +355,15 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
           if (HU) {
             // cell-mean velocities (the literal upper face of a periodic axis)
             R uxh = pUx, uyl = rUy[i - 5], uyh = rUy[i - 4];
-            if (!INT) {
-              if (px && xs == nx - 1) uxh = a.u[0][(long long)(nx + 1) * o + nx];
-              if (py && o == ny - 1) uyh = a.u[1][(long long)nx * ny + xs];
-            }
+            if (!IX && px && xs == nx - 1) uxh = a.u[0][(long long)(nx + 1) * o + nx];
+            if (!IY && py && o == ny - 1) uyh = a.u[1][(long long)nx * ny + xs];
             acc.usum = fmax(acc.usum, fabs(R(0.5) * (pUxL + uxh)) + fabs(R(0.5) * (uyl + uyh)));
-            if (!INT) {
-              // open-side budget of the faces of this cell
-              if (!px && xs == 0 && ox_lo) acc.out -= (double)(a.area_dt * (pFxLF + pFxLP));
-              if (!px && xs == nx - 1 && ox_hi) acc.out += (double)(a.area_dt * (pFxF + pFxP));
+            // open-side budget of the faces of this cell (lane weights
+            // -1 / 0 / +1 for the x sides, uniform branches for the y sides)
+            if (!IX)
+              acc.out += wlo * (double)(a.area_dt * (pFxLF + pFxLP)) +
+                         whi * (double)(a.area_dt * (pFxF + pFxP));
+            if (!IY) {
               if (!py && o == 0 && oy_lo) acc.out -= (double)(a.area_dt * (pGyF + pGyP));
               if (!py && o == ny - 1 && oy_hi) acc.out += (double)(a.area_dt * (gyF + gyP));
             }
@@ -331,14 +386,18 @@ __global__ void __launch_bounds__(64 * COL_WAVES) k_col2d(ColArgs<R> a) {
   const int wg = (b & 7) * a.per_xcd + (b >> 3);  // banded over the XCDs
   if (wg >= a.nwg) return;  // uniform per workgroup: no barrier is skipped by part of it
   const int nx = a.g.n[0], ny = a.g.n[1];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // the wave index is uniform over the wave: say so, so that row offsets
+  // stay in scalar registers
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int sx = wg / a.groups, cg = wg - sx * a.groups;
   const int x0 = sx * COL_OUT, y0 = (cg * COL_WAVES + wv) * TY;
   ColAcc<R> acc{0.0, 0.0, 0.0, 0.0, 0.0, R(0), R(-INFINITY), R(INFINITY), R(INFINITY), 0};
   if (y0 < ny) {  // chunks past the last row only join the reduction
-    const bool interior = x0 >= 3 && x0 + 62 <= nx && y0 >= 3 && y0 + TY + 3 <= ny;
-    if (interior) col2d_wave<R, TY, HU, BULK, true>(a, x0, y0, lane, acc);
-    else col2d_wave<R, TY, HU, BULK, false>(a, x0, y0, lane, acc);
+    const bool ix = x0 >= 3 && x0 + 62 <= nx, iy = y0 >= 3 && y0 + TY + 3 <= ny;
+    if (ix && iy) col2d_wave<R, TY, HU, BULK, true, true>(a, x0, y0, lane, acc);
+    else if (iy) col2d_wave<R, TY, HU, BULK, false, true>(a, x0, y0, lane, acc);
+    else if (ix) col2d_wave<R, TY, HU, BULK, true, false>(a, x0, y0, lane, acc);
+    else col2d_wave<R, TY, HU, BULK, false, false>(a, x0, y0, lane, acc);
   }
   double v[NPART];
   v[P_SUM_F] = acc.sF;

@@ -779,46 +779,71 @@ __global__ void __launch_bounds__(256) k_geo_classify(Step2dArgs<R> a) {
   if (lane == 0) a.q_out[t] = (uint8_t)want;
 }
 
-constexpr int GEO_LIST_THREADS = 1024;
-// live[0] = count, live[1 + r] = the r-th live tile in tile order
-__global__ void __launch_bounds__(GEO_LIST_THREADS) k_geo_list(const uint8_t* __restrict__ q,
-                                                               int ntiles, int* __restrict__ live) {
-  __shared__ int sWave[GEO_LIST_THREADS / 64];
-  __shared__ int sBase;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid == 0) sBase = 0;
-  __syncthreads();
-  for (int base = 0; base < ntiles; base += GEO_LIST_THREADS) {
-    const int t = base + tid;
-    const bool todo = t < ntiles && q[t] == Q_TODO;
-    const unsigned long long m = __ballot(todo);
-    const int below = __popcll(m & ((1ull << lane) - 1ull));
-    if (lane == 0) sWave[wv] = __popcll(m);
-    __syncthreads();
-    int off = sBase;
-    for (int w = 0; w < wv; ++w) off += sWave[w];
-    if (todo) live[1 + off + below] = t;
-    __syncthreads();
-    if (tid == 0) {
-      int tot = 0;
-      for (int w = 0; w < GEO_LIST_THREADS / 64; ++w) tot += sWave[w];
-      sBase += tot;
-    }
-    __syncthreads();
-  }
-  if (tid == 0) live[0] = sBase;
-}
-
-constexpr int GEO_WG = 1024, GEO_LIVE_GRID = 512;
+// Pass 2 ranks the tiles marked by pass 1 itself: each of its 1024 threads
+// reads one 4-byte word of flags, a ballot/LDS prefix gives every marked
+// tile its rank in tile order, and workgroup b takes ranks b, b + G, ...
+constexpr int GEO_WG = 1024, GEO_LIVE_GRID = 512, GEO_LIVE_CAP = 32;
 template <typename R, int KH>
-__global__ void __launch_bounds__(GEO_WG) k_geo_live(Step2dArgs<R> a, const int* __restrict__ live) {
+__global__ void __launch_bounds__(GEO_WG) k_geo_live(Step2dArgs<R> a) {
   using T = Tile2<KH, GEO_T, GEO_T>;
   __shared__ R sChi[T::NC];
   __shared__ R sB[T::NC];
-  const int n = live[0];
-  for (int i = blockIdx.x; i < n; i += gridDim.x) {
-    tile_geometry<R, KH, GEO_WG, GEO_T, GEO_T, true>(a, live[1 + i], sChi, sB, nullptr, true,
-                                                     false, false);
+  __shared__ int sWave[GEO_WG / 64];
+  __shared__ int sMine[GEO_LIVE_CAP];
+  __shared__ int sNum;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nt = a.ntiles;
+  const int G = gridDim.x, b = blockIdx.x;
+  if (tid == 0) sNum = 0;
+  int seen = 0;  // marked tiles in earlier chunks
+  for (int base = 0; base < nt; base += 4 * GEO_WG) {
+    const int t0 = base + 4 * tid;
+    int cnt = 0;
+    uint8_t f[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      f[k] = t0 + k < nt ? a.q_out[t0 + k] : (uint8_t)0;
+      cnt += f[k] == Q_TODO ? 1 : 0;
+    }
+    // inclusive prefix of cnt over the wave (shuffles), then over the waves
+    int inc = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int x = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += x;
+    }
+    if (lane == 63) sWave[wv] = inc;
+    __syncthreads();
+    int before = seen;
+    for (int w = 0; w < wv; ++w) before += sWave[w];
+    int rank = before + inc - cnt;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (f[k] != Q_TODO) continue;
+      if (rank % G == b) {
+        const int m = atomicAdd(&sNum, 1);  // LDS counter; order restored below
+        if (m < GEO_LIVE_CAP) sMine[m] = t0 + k;
+      }
+      ++rank;
+    }
+    int total = 0;
+    for (int w = 0; w < GEO_WG / 64; ++w) total += sWave[w];
+    seen += total;
+    __syncthreads();
+  }
+  const int mine = min(sNum, GEO_LIVE_CAP);
+  if (tid == 0) {
+    for (int i = 1; i < mine; ++i) {
+      const int v = sMine[i];
+      int j = i - 1;
+      while (j >= 0 && sMine[j] > v) { sMine[j + 1] = sMine[j]; --j; }
+      sMine[j + 1] = v;
+    }
+  }
+  __syncthreads();
+  for (int i = 0; i < mine; ++i) {
+    tile_geometry<R, KH, GEO_WG, GEO_T, GEO_T, true>(a, sMine[i], sChi, sB, nullptr, true, false,
+                                                     false);
     __syncthreads();
   }
 }
