@@ -1,6 +1,6 @@
 """Surfactant-step throughput on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c1i|c2|c0]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c1i|c0|c2|c3|c4]
 
 A step is one pass of the whole path (redistancing of the moving interface,
 the fused transport kernel, the FP64 reductions) over the workload's grid.
@@ -15,6 +15,14 @@ Timed regions:
      events: average duration of the fused transport kernel -> `roofline`.
 The FP64 CPU oracle is timed on a bounded sample of the same workload on the
 host (`cpu_baseline`).
+
+Other workloads (one JSON line each, not the default):
+  c2  the 256^3 translating sphere (inputs generated on the GPU, all steps
+      resident before the timed region);
+  c3  the 64-instance ensemble in the batched form (one persistent launch
+      per step, HIP-graph replay), against the same instances stepped one by
+      one with the plain path;
+  c4  the 128^3 adjoint sphere: forward steps and checkpointed adjoint steps.
 """
 from __future__ import annotations
 
@@ -35,7 +43,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c1i", "c2"])
+    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c1i", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -136,6 +144,10 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
+    if args.workload == "c3":
+        return bench_batch(args)
+    if args.workload == "c4":
+        return bench_adjoint(args)
     import numpy as np
     import torch
     from paper_2605_27534_amd import surf as S
@@ -154,14 +166,17 @@ def main():
         s = S.Surf(prob, cfg["dt"], prec)
         tens = s.tensor
         print("# generating inputs: %s, %d steps" % (cfg["name"], W + K), file=sys.stderr, flush=True)
-        vof0 = tens(cfg["vof0"]())
+        dev_gen = cfg.get("vof_seq_dev") is not None
+        vof0 = tens(cfg["vof0_dev"](dev)) if dev_gen else tens(cfg["vof0"]())
         vofs = None
         if cfg.get("vof_seq"):
-            vofs = [tens(cfg["vof_seq"](k)) for k in range(W + K)]
+            vofs = [tens(cfg["vof_seq_dev"](k, dev)) if dev_gen else tens(cfg["vof_seq"](k))
+                    for k in range(W + K)]
         u_static = [tens(x) for x in cfg["u"]()] if cfg.get("u") else None
         u_list = None
         if cfg.get("u_seq"):
-            u_list = [[tens(x) for x in cfg["u_seq"](k)] for k in range(W + K)]
+            u_list = [[tens(x) for x in (cfg["u_seq_dev"](k, dev) if dev_gen else cfg["u_seq"](k))]
+                      for k in range(W + K)]
         c0 = tens(cfg["c0"]()) if cfg.get("c0") else None
         bulk = prob.get("bulk_enabled", 1)
         bufs = [[s.empty() if bulk else None, s.empty()] for _ in range(2)]
@@ -259,6 +274,124 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """The 64-instance ensemble: batched form against the plain path."""
+    import numpy as np
+    import torch
+    from paper_2605_27534_amd import configs as C
+    from paper_2605_27534_amd import surf as S
+    from paper_2605_27534_amd.batch import Batch
+    K, W = args.steps, args.warmup
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ens = C.c3_ensemble()
+    side = torch.cuda.Stream(dev)
+    cells = sum(int(np.prod(e["prob"]["n"])) for e in ens)
+    print("# generating inputs: 64 instances, %d cells" % cells, file=sys.stderr, flush=True)
+    vofs = [torch.as_tensor(e["vof0"]()).to(dev, torch.float32) for e in ens]
+    with torch.cuda.stream(side):
+        b = Batch([e["prob"] for e in ens], [e["dt"] for e in ens], S.SURF_F32)
+        for i, e in enumerate(ens):
+            b.set_geometry(i, vofs[i].reshape(b.shapes[i]).contiguous())
+            b.init_state(i, None, e["c0_const"], e["gamma0"])
+        choice, times = b.tune()
+        tot = torch.zeros((len(ens), 16), dtype=torch.float64, device=dev)
+        b.step(W, tot)
+        side.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b.step(K, tot)  # records the graphs of K steps from both buffer parities
+        b.step(K, tot)
+        side.synchronize()
+        t0.record(side)
+        b.step(K, tot)  # replays it
+        t1.record(side)
+        side.synchronize()
+        ms_batch = t0.elapsed_time(t1)
+        # plain path: the same instances one after the other, K steps each
+        plain = []
+        for i, e in enumerate(ens):
+            s = S.Surf(e["prob"], e["dt"], S.SURF_F32)
+            s.set_geometry(vofs[i].reshape(b.shapes[i]).contiguous(), full=True)
+            F, P = s.init_state(None, e["c0_const"], e["gamma0"])
+            F2, P2, sg = s.empty(), s.empty(), s.empty()
+            plain.append([s, F, P, F2, P2, sg])
+        side.synchronize()
+
+        def plain_steps(k):
+            for st in plain:
+                s, F, P, F2, P2, sg = st
+                for _ in range(k):
+                    s.step(F, P, F2, P2, sigma_out=sg)
+                    F, F2, P, P2 = F2, F, P2, P
+                st[1:5] = [F, P, F2, P2]
+
+        plain_steps(W)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            plain_steps(K)
+        side.synchronize()
+        t0.record(side)
+        g.replay()
+        t1.record(side)
+        side.synchronize()
+        ms_plain = t0.elapsed_time(t1)
+    value = cells * K / (ms_batch * 1e-3) / 1e9
+    out = {"metric": "surfactant-step Gcell-updates/s (batched form)", "value": round(value, 4),
+           "unit": "Gcell-updates/s", "n_gpus": 1, "steps": K, "warmup": W,
+           "ms_per_step": round(ms_batch / K, 6), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "ensemble of 64 static circles fp32", "cells": cells,
+                      "tuned_choice": choice},
+           "plain": {"value": round(cells * K / (ms_plain * 1e-3) / 1e9, 4),
+                     "ms_per_step": round(ms_plain / K, 6),
+                     "note": "the same 64 instances stepped one after the other with surf_step, "
+                             "replayed from one HIP graph"},
+           "batched_over_plain": round(ms_plain / ms_batch, 3)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(args):
+    """The 128^3 adjoint sphere: forward and checkpointed adjoint steps."""
+    import numpy as np
+    import torch
+    from paper_2605_27534_amd import configs as C
+    from paper_2605_27534_amd import surf as S
+    from paper_2605_27534_amd.adjoint import Rollout
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    cfg = C.c4_adjoint()
+    N, Kc = args.steps, max(1, args.steps // 10)
+    print("# generating inputs: %s" % cfg["name"], file=sys.stderr, flush=True)
+    ro = Rollout(cfg["prob"], cfg["dt"], S.SURF_F32, vof=cfg["vof0"](), u=cfg["u"](),
+                 gamma0=cfg["gamma0"], nsteps=N, checkpoint=Kc)
+    th = torch.tensor(cfg["theta_nominal"], dtype=torch.float64, device=dev)
+    c0 = ro.s.tensor(cfg["c0"]())
+    tg = torch.full((N,), 0.95, dtype=torch.float64, device=dev)
+    ro.forward(th, c0, tg)  # warm-up
+    torch.cuda.synchronize()
+    t0, t1, t2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    t0.record()
+    loss, tot, w, ck = ro.forward(th, c0, tg)
+    t1.record()
+    ro.backward(w, ck)
+    t2.record()
+    torch.cuda.synchronize()
+    ms_f, ms_b = t0.elapsed_time(t1), t1.elapsed_time(t2)
+    cells = int(np.prod(cfg["prob"]["n"]))
+    out = {"metric": "surfactant-step Gcell-updates/s (adjoint form)",
+           "value": round(cells * N / (ms_b * 1e-3) / 1e9, 4), "unit": "Gcell-updates/s",
+           "n_gpus": 1, "steps": N, "warmup": 1, "ms_per_step": round(ms_b / N, 6),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": cfg["name"], "cells": cells, "checkpoint": Kc,
+                      "note": "backward = recomputation of each checkpoint segment + the adjoint "
+                              "steps, launched eagerly"},
+           "forward": {"value": round(cells * N / (ms_f * 1e-3) / 1e9, 4),
+                       "ms_per_step": round(ms_f / N, 6)},
+           "adjoint_over_forward_time": round(ms_b / ms_f, 3)}
     print(json.dumps(out), flush=True)
 
 

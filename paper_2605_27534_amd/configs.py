@@ -2,7 +2,8 @@
 
 Each function returns a dict with the problem (the keys of the library's
 parameter structs), the time step, the step count and callables producing the
-seeded inputs (all FP64 NumPy, from `synth`).  Time steps are fixed numbers
+seeded inputs (FP64 NumPy from `synth`; the 3D sphere also has the same
+inputs generated on a torch device, from `synth_dev`).  Time steps are fixed numbers
 chosen at or below the explicit stability bound of the split step (the bound
 is the library's SURF_T_DT_NEXT; the values below were read from it for the
 analytic velocity fields and rounded down).
@@ -13,7 +14,7 @@ import math
 
 import numpy as np
 
-from . import synth
+from . import synth, synth_dev
 
 
 def c0_static_circle():
@@ -77,6 +78,14 @@ def c2_translating_sphere(n=256):
                                                  period_z=1.0),
                 u_seq=lambda k: synth.u_hadamard((n, n, n), h, cen(k * dt), R, -U, 0.01,
                                                  frame_shift=U, period_z=1.0),
+                # the same inputs generated on a torch device
+                vof_seq_dev=lambda k, dev: synth_dev.vof_ball((n, n, n), h, cen((k + 1) * dt), R,
+                                                              period_z=1.0, device=dev),
+                u_seq_dev=lambda k, dev: synth_dev.u_hadamard((n, n, n), h, cen(k * dt), R, -U,
+                                                              0.01, frame_shift=U, period_z=1.0,
+                                                              device=dev),
+                vof0_dev=lambda dev: synth_dev.vof_ball((n, n, n), h, cen(0.0), R, period_z=1.0,
+                                                        device=dev),
                 c0=None, c0_const=1.0, gamma0=0.0, hj_step=16)
 
 
