@@ -12,6 +12,7 @@
 #include "surf_kernels.hpp"
 #include "surf_step2d.hpp"
 #include "surf_col2d.hpp"
+#include "surf_geo3d.hpp"
 #include "surf_adjoint.hpp"
 
 using namespace surf;
@@ -41,6 +42,10 @@ struct surf_ctx {
   int gtiles[2];
   int ngtiles;
   int nflags;
+  // 3D moving geometry: 16^3 tiles and the live-tile list ([0] count)
+  int g3tiles[3];
+  int ng3;
+  int* live3;
 
 
   int per_xcd;
@@ -223,10 +228,19 @@ int geo_tiles(const surf_grid* gr, const surf_params* p, int* t) {
   return t[0] * t[1];
 }
 
+// Tiles of the 3D moving geometry (0 in 2D).
+int geo3_tiles(const surf_grid* gr, int* t) {
+  t[0] = t[1] = t[2] = 0;
+  if (gr->dim != 3) return 0;
+  for (int d = 0; d < 3; ++d) t[d] = (gr->n[d] + G3 - 1) / G3;
+  return t[0] * t[1] * t[2];
+}
+
 int flag_count(const surf_grid* gr, const surf_params* p) {
-  int t2[2], tg[2];
-  int a = ntiles_2d(gr, t2), b = geo_tiles(gr, p, tg);
-  return a > b ? a : b;
+  int t2[2], tg[2], t3[3];
+  int a = ntiles_2d(gr, t2), b = geo_tiles(gr, p, tg), c = geo3_tiles(gr, t3);
+  a = a > b ? a : b;
+  return a > c ? a : c;
 }
 
 int status_of_launch() {
@@ -383,6 +397,47 @@ FinalArgs final_of(const surf_grid& gr, const surf_params& q, int nblk, double d
 
 template <typename R>
 void finalize(surf_ctx* c, double* totals, int nblk);
+
+// 3D moving geometry: K warm-start sweeps over the tiles near the interface
+// (even K up to the tile edge), the level set of the other tiles at the clamp.
+template <typename R>
+bool geo3_ok(const surf_ctx* c) {
+  const int K = c->prm.hj_iters_step;
+  return c->grid.dim == 3 && c->ng3 > 0 && K >= 2 && K <= G3 && (K % 2) == 0;
+}
+
+template <typename R>
+void geo3_impl(surf_ctx* c, const void* vof) {
+  Geo3Args ga;
+  ga.g = c->g;
+  for (int d = 0; d < 3; ++d) ga.tiles[d] = c->g3tiles[d];
+  ga.ntiles = c->ng3;
+  const Par<R> p = make_par<R>(c);
+  R* chi_in = (R*)c->chi[c->chi_cur];
+  R* chi_out = (R*)c->chi[1 - c->chi_cur];
+  uint8_t* q_in = c->q[c->chi_cur];
+  uint8_t* q_out = c->q[1 - c->chi_cur];
+  {
+    Timed tm(c, 1);
+    hipLaunchKernelGGL(k_geo3_classify<R>, dim3(c->ng3), dim3(G3_THREADS), 0, c->stream, ga, p,
+                       (const R*)vof, (const R*)chi_in, chi_out, (R*)c->g0, (const uint8_t*)q_in,
+                       q_out, c->state);
+    hipLaunchKernelGGL(k_geo3_list, dim3(1), dim3(G3_LIST_THREADS), 0, c->stream,
+                       (const uint8_t*)q_out, c->ng3, c->live3);
+    const int K = c->prm.hj_iters_step;
+    const R dtau = (R)(c->grid.h / 3);
+    for (int k = 1; k <= K; ++k) {
+      // odd sweeps read chi_out and write chi_in, even sweeps the reverse
+      const R* src = (k & 1) ? chi_out : chi_in;
+      R* dst = (k & 1) ? chi_in : chi_out;
+      hipLaunchKernelGGL(k_geo3_sweep<R>, dim3(G3_SWEEP_GRID), dim3(G3_SWEEP_THREADS), 0,
+                         c->stream, ga, p, dtau, src, dst, (const R*)c->g0, q_out,
+                         (const int*)c->live3, k == K ? 1 : 0);
+    }
+  }
+  c->chi_cur = 1 - c->chi_cur;
+  c->materialized = true;
+}
 
 // Weighted form in 2D: the moving geometry as its own tile kernel (every
 // tile writes chi^{n+1}), then the column-streaming transport on the new
@@ -674,6 +729,10 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   b += align_up((size_t)npart * NPART * sizeof(double));
   b += 3 * align_up(n * es);
   b += 2 * align_up((size_t)flag_count(grid, params) + 1);
+  {
+    int t3[3];
+    b += align_up((size_t)(geo3_tiles(grid, t3) + 1) * sizeof(int));
+  }
 
 
   if (params->adjoint) {
@@ -711,6 +770,7 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
   c->ntiles2d = ntiles_2d(grid, c->tiles2d);
   c->per_xcd = (c->ntiles2d + 7) / 8;
   c->ngtiles = geo_tiles(grid, params, c->gtiles);
+  c->ng3 = geo3_tiles(grid, c->g3tiles);
   c->nflags = flag_count(grid, params);
   c->col_nwg = col_shape(grid, params, &c->col_strips, &c->col_groups);
   int npart = c->nblk > c->ntiles2d ? c->nblk : c->ntiles2d;
@@ -731,6 +791,8 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
   p += align_up((size_t)c->nflags + 1);
   c->q[1] = (uint8_t*)p;
   p += align_up((size_t)c->nflags + 1);
+  c->live3 = (int*)p;
+  p += align_up((size_t)(c->ng3 + 1) * sizeof(int));
 
 
   for (int i = 0; i < 4; ++i) {
@@ -813,7 +875,15 @@ int surf_step(surf_ctx* c, const void* vof_next, const void* const* u, const voi
       return step2d_impl<float>(c, vof_next, u, F_in, psi_in, F_out, psi_out, sigma_out,
                                 totals_dev);
     }
-    int rc = surf_set_geometry(c, vof_next, 0);
+    bool banded = false;
+    if (c->prm.precision == SURF_F32 && geo3_ok<float>(c)) {
+      geo3_impl<float>(c, vof_next);
+      banded = true;
+    } else if (c->prm.precision == SURF_F64 && geo3_ok<double>(c)) {
+      geo3_impl<double>(c, vof_next);
+      banded = true;
+    }
+    int rc = banded ? status_of_launch() : surf_set_geometry(c, vof_next, 0);
     if (rc) return rc;
   }
   if (c->prm.precision == SURF_F64)
@@ -1141,6 +1211,7 @@ int surf_batch_set_geometry(surf_batch* b, int32_t i, const void* vof) {
   c.materialized = true;
   c.ntiles2d = 0;
   c.ngtiles = 0;
+  c.ng3 = 0;
   c.nflags = 0;
   c.col_nwg = 0;
   c.profile = false;

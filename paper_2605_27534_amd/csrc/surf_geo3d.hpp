@@ -1,0 +1,258 @@
+// surf_geo3d.hpp -- the moving-interface geometry in 3D (section 2.5):
+// warm-start Jacobi sweeps restricted to the tiles near the interface.
+//
+// The box is cut into 16^3 tiles with one flag each (quiescent at +clamp,
+// quiescent at -clamp, live).  A tile whose VoF is uniform and whose 3x3x3
+// tile neighbourhood was quiescent with the same sign after the previous
+// step keeps the clamp value: every cell it can reach in K <= 16 sweeps is at
+// the clamp, where a Godunov sweep changes nothing.  The other tiles are
+// rebuilt by K sweeps over the live tiles only:
+//   k_geo3_classify  one workgroup per tile: the decision, the clamp value of
+//                    quiescent tiles, and for live tiles the sweep start
+//                    (chi_in copied) and the pin data (Russo-Smereka
+//                    distance of cut cells, signed infinity elsewhere);
+//   k_geo3_list      one workgroup: the live tiles in tile order;
+//   k_geo3_sweep     one Jacobi sweep over the listed tiles (a persistent
+//                    grid); the last sweep also sets the new flags.
+// The sweeps alternate between chi_out and chi_in (whose live tiles the
+// classify pass has already copied).  A quiescent tile holds the clamp in
+// both: in chi_out from the classify pass, in chi_in because its flag after
+// the previous step was that clamp.  K is even, so the result ends in
+// chi_out.
+#pragma once
+#include "surf_common.hpp"
+#include "surf_step2d.hpp"
+
+namespace surf {
+
+constexpr int G3 = 16;                    // tile edge
+constexpr int G3_CELLS = G3 * G3 * G3;    // 4096
+constexpr int G3_THREADS = 256;
+constexpr int G3_CPT = G3_CELLS / G3_THREADS;  // cells per thread (classify)
+
+struct Geo3Args {
+  Grid g;
+  int tiles[3];
+  int ntiles;
+};
+
+__device__ __forceinline__ int geo3_tile_of(const Geo3Args& t, int x, int y, int z) {
+  return (x / G3) + t.tiles[0] * ((y / G3) + t.tiles[1] * (z / G3));
+}
+
+template <typename R>
+__global__ void __launch_bounds__(G3_THREADS) k_geo3_classify(Geo3Args ga, Par<R> p,
+                                                              const R* __restrict__ vof,
+                                                              const R* __restrict__ chi_in,
+                                                              R* __restrict__ chi_out,
+                                                              R* __restrict__ g0,
+                                                              const uint8_t* __restrict__ q_in,
+                                                              uint8_t* __restrict__ q_out,
+                                                              double* __restrict__ state) {
+  __shared__ uint8_t sQ[27];
+  __shared__ int sVote[G3_THREADS / 64];
+  const int t = blockIdx.x;
+  if (t >= ga.ntiles) return;
+  const Grid& g = ga.g;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int tid = threadIdx.x;
+  const int tx = t % ga.tiles[0], ty = (t / ga.tiles[0]) % ga.tiles[1],
+            tz = t / (ga.tiles[0] * ga.tiles[1]);
+  const int x0 = tx * G3, y0 = ty * G3, z0 = tz * G3;
+  // this thread's cells: x = tid % 16, y = tid / 16, z = 0 .. 15
+  const int lx = tid % G3, ly = tid / G3;
+  const int gx = x0 + lx, gy = y0 + ly;
+  const bool colin = gx < nx && gy < ny;
+  bool one = true, zero = true;
+  R f[G3];
+#pragma unroll
+  for (int k = 0; k < G3; ++k) {
+    const int gz = z0 + k;
+    f[k] = R(0.5);
+    if (colin && gz < nz) {
+      f[k] = vof[(long long)gx + (long long)nx * (gy + (long long)ny * gz)];
+      one = one && f[k] == R(1);
+      zero = zero && f[k] == R(0);
+    }
+  }
+  if (tid < 27) {
+    int u[3] = {tx + tid % 3 - 1, ty + (tid / 3) % 3 - 1, tz + tid / 9 - 1};
+    bool ok = true;
+    for (int d = 0; d < 3; ++d) {
+      if (u[d] < 0 || u[d] >= ga.tiles[d]) {
+        if (g.bc[d][u[d] < 0 ? 0 : 1] == BC_PERIODIC) u[d] = (u[d] + ga.tiles[d]) % ga.tiles[d];
+        else ok = false;
+      }
+    }
+    sQ[tid] = ok ? q_in[u[0] + ga.tiles[0] * (u[1] + ga.tiles[1] * u[2])] : (uint8_t)255;
+  }
+  const bool w1 = __all(one), w0 = __all(zero);
+  if ((tid & 63) == 0) sVote[tid >> 6] = (w1 ? 1 : 0) | (w0 ? 2 : 0);
+  __syncthreads();
+  int m = 3;
+#pragma unroll
+  for (int w = 0; w < G3_THREADS / 64; ++w) m &= sVote[w];
+  const int want = (m & 1) ? Q_POS : ((m & 2) ? Q_NEG : -1);
+  bool quiet = true, nb_quiet = true;
+  for (int i = 0; i < 27; ++i) {
+    const uint8_t q = sQ[i];
+    if (q == 255) continue;
+    if ((int)q != want) quiet = false;
+    if (q == Q_LIVE) nb_quiet = false;
+  }
+  if (quiet) {
+    const R v = want == Q_POS ? p.chimax : -p.chimax;
+#pragma unroll
+    for (int k = 0; k < G3; ++k) {
+      const int gz = z0 + k;
+      if (colin && gz < nz) chi_out[(long long)gx + (long long)nx * (gy + (long long)ny * gz)] = v;
+    }
+    if (tid == 0) q_out[t] = (uint8_t)want;
+    return;
+  }
+  if (tid == 0) {
+    q_out[t] = (uint8_t)Q_TODO;
+    // the VoF changed under a tile whose whole neighbourhood was quiescent
+    if (nb_quiet) atomicOr((unsigned*)(state + S_FLAGS), (unsigned)STATUS_GEOM_JUMP);
+  }
+  if (!colin) return;
+  // live: sweep start and pin data of the tile's cells
+  const int mxm = map_axis(gx - 1, nx, g.bc[0][0], g.bc[0][1]);
+  const int mxp = map_axis(gx + 1, nx, g.bc[0][0], g.bc[0][1]);
+  const int mym = map_axis(gy - 1, ny, g.bc[1][0], g.bc[1][1]);
+  const int myp = map_axis(gy + 1, ny, g.bc[1][0], g.bc[1][1]);
+#pragma unroll 4
+  for (int k = 0; k < G3; ++k) {
+    const int gz = z0 + k;
+    if (gz >= nz) break;
+    const long long pl = (long long)nx * ny;
+    const long long c = (long long)gx + (long long)nx * gy + pl * gz;
+    chi_out[c] = chi_in[c];
+    const int mzm = map_axis(gz - 1, nz, g.bc[2][0], g.bc[2][1]);
+    const int mzp = map_axis(gz + 1, nz, g.bc[2][0], g.bc[2][1]);
+    const R x0v = (f[k] - R(0.5)) * p.h;
+    R nb[6];
+    nb[0] = (vof[(long long)mxm + (long long)nx * gy + pl * gz] - R(0.5)) * p.h;
+    nb[1] = (vof[(long long)mxp + (long long)nx * gy + pl * gz] - R(0.5)) * p.h;
+    nb[2] = (vof[(long long)gx + (long long)nx * mym + pl * gz] - R(0.5)) * p.h;
+    nb[3] = (vof[(long long)gx + (long long)nx * myp + pl * gz] - R(0.5)) * p.h;
+    nb[4] = (vof[(long long)gx + (long long)nx * gy + pl * mzm] - R(0.5)) * p.h;
+    nb[5] = (vof[(long long)gx + (long long)nx * gy + pl * mzp] - R(0.5)) * p.h;
+    bool cut = false;
+    R jump = R(0), grad2 = R(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const R xm = nb[2 * d], xp = nb[2 * d + 1];
+      cut = cut || (x0v * xm <= R(0)) || (x0v * xp <= R(0));
+      jump = fmax(jump, fmax(fabs(xm - x0v), fabs(xp - x0v)));
+      const R cd = R(0.5) * (xp - xm);
+      grad2 += cd * cd;
+    }
+    const R Delta = fmax(fmax(rsqrt_<R>(grad2), jump), R(1e-30) * p.h);
+    g0[c] = cut ? p.h * x0v / Delta : (x0v > R(0) ? R(INFINITY) : R(-INFINITY));
+  }
+}
+
+// live[0] = count, live[1 + r] = the r-th live tile in tile order
+constexpr int G3_LIST_THREADS = 1024;
+__global__ void __launch_bounds__(G3_LIST_THREADS) k_geo3_list(const uint8_t* __restrict__ q,
+                                                               int ntiles, int* __restrict__ live) {
+  __shared__ int sWave[G3_LIST_THREADS / 64];
+  __shared__ int sBase;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) sBase = 0;
+  __syncthreads();
+  for (int base = 0; base < ntiles; base += G3_LIST_THREADS) {
+    const int t = base + tid;
+    const bool todo = t < ntiles && q[t] == Q_TODO;
+    const unsigned long long mk = __ballot(todo);
+    const int below = __popcll(mk & ((1ull << lane) - 1ull));
+    if (lane == 0) sWave[wv] = __popcll(mk);
+    __syncthreads();
+    int off = sBase;
+    for (int w = 0; w < wv; ++w) off += sWave[w];
+    if (todo) live[1 + off + below] = t;
+    __syncthreads();
+    if (tid == 0) {
+      int tot = 0;
+      for (int w = 0; w < G3_LIST_THREADS / 64; ++w) tot += sWave[w];
+      sBase += tot;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) live[0] = sBase;
+}
+
+// One Jacobi sweep (Godunov, pinned cut cells, clamp) over the listed
+// tiles; workgroup b takes entries b, b + G, ...  The last sweep also writes
+// each tile's new flag.
+constexpr int G3_SWEEP_THREADS = 1024, G3_SWEEP_GRID = 512;
+template <typename R>
+__global__ void __launch_bounds__(G3_SWEEP_THREADS) k_geo3_sweep(Geo3Args ga, Par<R> p, R dtau,
+                                                                 const R* __restrict__ src,
+                                                                 R* __restrict__ dst,
+                                                                 const R* __restrict__ g0,
+                                                                 uint8_t* __restrict__ q,
+                                                                 const int* __restrict__ live,
+                                                                 int last) {
+  __shared__ int sVote[G3_SWEEP_THREADS / 64];
+  const Grid& g = ga.g;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const long long pl = (long long)nx * ny;
+  const int tid = threadIdx.x;
+  const int n = live[0];
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const int t = live[1 + i];
+    const int tc[3] = {t % ga.tiles[0], (t / ga.tiles[0]) % ga.tiles[1],
+                       t / (ga.tiles[0] * ga.tiles[1])};
+    bool allpos = true, allneg = true;
+#pragma unroll
+    for (int k = 0; k < G3_CELLS / G3_SWEEP_THREADS; ++k) {
+      const int l = tid + k * G3_SWEEP_THREADS;
+      const int c3[3] = {tc[0] * G3 + l % G3, tc[1] * G3 + (l / G3) % G3, tc[2] * G3 + l / (G3 * G3)};
+      if (c3[0] >= nx || c3[1] >= ny || c3[2] >= nz) continue;
+      const long long c = (long long)c3[0] + (long long)nx * c3[1] + pl * c3[2];
+      const R gv = g0[c];
+      R v;
+      if (fabs(gv) < R(INFINITY)) {
+        v = gv;
+      } else {
+        const R x = src[c];
+        const R sgn = gv > R(0) ? R(1) : R(-1);
+        R G2 = R(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          R nbv[2];
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            int m3[3] = {c3[0], c3[1], c3[2]};
+            m3[d] = map_axis(c3[d] + (s ? 1 : -1), g.n[d], g.bc[d][0], g.bc[d][1]);
+            nbv[s] = src[(long long)m3[0] + (long long)nx * m3[1] + pl * m3[2]];
+          }
+          const R a1 = sgn * (x - nbv[0]) * p.inv_h, b1 = sgn * (nbv[1] - x) * p.inv_h;
+          const R t1 = a1 > R(0) ? a1 * a1 : R(0), t2 = b1 < R(0) ? b1 * b1 : R(0);
+          G2 += t1 > t2 ? t1 : t2;
+        }
+        v = x - dtau * sgn * (rsqrt_<R>(G2) - R(1));
+      }
+      v = v > p.chimax ? p.chimax : v;
+      v = v < -p.chimax ? -p.chimax : v;
+      dst[c] = v;
+      allpos = allpos && v == p.chimax;
+      allneg = allneg && v == -p.chimax;
+    }
+    if (last) {
+      const bool wp = __all(allpos), wn = __all(allneg);
+      if ((tid & 63) == 0) sVote[tid >> 6] = (wp ? 1 : 0) | (wn ? 2 : 0);
+    }
+    __syncthreads();
+    if (last && tid == 0) {
+      int m = 3;
+      for (int w = 0; w < G3_SWEEP_THREADS / 64; ++w) m &= sVote[w];
+      q[t] = (m & 1) ? Q_POS : ((m & 2) ? Q_NEG : Q_LIVE);
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace surf
