@@ -66,9 +66,9 @@ def workload(name, K, W):
 def transport_kernel(cfg):
     """Name of the transport kernel the library runs for the workload."""
     p = cfg["prob"]
-    if p["dim"] == 3:
-        return "k_step"
-    return "k_col2d" if p.get("flux_form", 0) == 0 else "k_step2d"
+    if p.get("flux_form", 0) != 0:
+        return "k_step" if p["dim"] == 3 else "k_step2d"
+    return "k_col3d" if p["dim"] == 3 else "k_col2d"
 
 
 def algorithmic_bytes(cfg, es):

@@ -12,6 +12,7 @@
 #include "surf_kernels.hpp"
 #include "surf_step2d.hpp"
 #include "surf_col2d.hpp"
+#include "surf_col3d.hpp"
 #include "surf_geo3d.hpp"
 #include "surf_adjoint.hpp"
 
@@ -51,6 +52,9 @@ struct surf_ctx {
   int per_xcd;
   // 2D weighted-form transport: column-streaming waves
   int col_strips, col_groups, col_nwg;
+  // 3D weighted-form transport: plane-marching workgroups (strips, row
+  // blocks, plane chunks)
+  int c3[3], c3_nwg;
   bool materialized;  // chi[chi_cur] holds explicit values on every tile
   // adjoint scratch: advected state, nu, per-workgroup dtheta partials
   void* adj[4];
@@ -219,6 +223,24 @@ int col_shape(const surf_grid* gr, const surf_params* p, int* strips, int* group
   return *strips * *groups;
 }
 
+// Plane-marching launch shape of the 3D weighted-form transport: strips of
+// COL_OUT columns, blocks of C3_OUT_ROWS rows, chunks of C3_TZ planes (FP32)
+// or C3_TZ64 (FP64).  Returns the workgroup count (0 when the kernel does not
+// apply).
+constexpr int C3_TZ = 16, C3_TZ64 = 8;
+int col3_shape(const surf_grid* gr, const surf_params* p, int* s) {
+  s[0] = s[1] = s[2] = 0;
+  if (gr->dim != 3 || p->flux_form != SURF_FLUX_WEIGHTED) return 0;
+  // 32-bit byte offsets of the buffer-resource access
+  const long long es = p->precision == SURF_F64 ? 8 : 4;
+  if ((long long)(gr->n[0] + 1) * (gr->n[1] + 1) * (gr->n[2] + 1) * es > 0x7fffffffll) return 0;
+  const int tz = p->precision == SURF_F64 ? C3_TZ64 : C3_TZ;
+  s[0] = (gr->n[0] + COL_OUT - 1) / COL_OUT;
+  s[1] = (gr->n[1] + C3_OUT_ROWS - 1) / C3_OUT_ROWS;
+  s[2] = (gr->n[2] + tz - 1) / tz;
+  return s[0] * s[1] * s[2];
+}
+
 // Tiles of the weighted-form geometry kernel (0 when it does not apply).
 int geo_tiles(const surf_grid* gr, const surf_params* p, int* t) {
   t[0] = t[1] = 0;
@@ -364,6 +386,15 @@ void launch_col2d(surf_ctx* c, const ColArgs<R>& a, bool has_u, bool bulk) {
   else if (has_u) hipLaunchKernelGGL((k_col2d<R, TY, true, false>), grid, block, 0, c->stream, a);
   else if (bulk) hipLaunchKernelGGL((k_col2d<R, TY, false, true>), grid, block, 0, c->stream, a);
   else hipLaunchKernelGGL((k_col2d<R, TY, false, false>), grid, block, 0, c->stream, a);
+}
+
+template <typename R, int TZ>
+void launch_col3d(surf_ctx* c, const Col3Args<R>& a, bool has_u, bool bulk) {
+  const dim3 grid(8 * a.per_xcd), block(64 * C3_WAVES);
+  if (has_u && bulk) hipLaunchKernelGGL((k_col3d<R, TZ, true, true>), grid, block, 0, c->stream, a);
+  else if (has_u) hipLaunchKernelGGL((k_col3d<R, TZ, true, false>), grid, block, 0, c->stream, a);
+  else if (bulk) hipLaunchKernelGGL((k_col3d<R, TZ, false, true>), grid, block, 0, c->stream, a);
+  else hipLaunchKernelGGL((k_col3d<R, TZ, false, false>), grid, block, 0, c->stream, a);
 }
 
 template <typename R, int KH>
@@ -569,6 +600,36 @@ int step_impl(surf_ctx* c, const void* const* u, const void* F_in, const void* p
   if (c->grid.dim == 2)
     return step2d_impl<R>(c, nullptr, u, F_in, psi_in, F_out, psi_out, sigma_out, totals);
   materialize<R>(c);
+  if (c->c3_nwg > 0) {
+    // weighted form in 3D: plane-marching transport, then the reduction
+    Col3Args<R> a;
+    a.g = c->g;
+    a.p = make_par<R>(c);
+    a.chi = (const R*)c->chi[c->chi_cur];
+    const bool has_u = u && u[0];
+    const bool bulk = c->prm.bulk_enabled != 0;
+    for (int d = 0; d < 3; ++d) a.u[d] = has_u ? (const R*)u[d] : nullptr;
+    a.F = (const R*)F_in;
+    a.psi = (const R*)psi_in;
+    a.Fo = (R*)F_out;
+    a.Po = (R*)psi_out;
+    a.sig = (R*)sigma_out;
+    a.part = c->part;
+    a.dt = (R)c->dt;
+    a.area_dt = (R)(c->grid.h * c->grid.h * c->dt);
+    a.strips = c->c3[0];
+    a.yblocks = c->c3[1];
+    a.zchunks = c->c3[2];
+    a.nwg = c->c3_nwg;
+    a.per_xcd = (c->c3_nwg + 7) / 8;
+    {
+      Timed tm(c, 0);
+      if constexpr (sizeof(R) == 4) launch_col3d<R, C3_TZ>(c, a, has_u, bulk);
+      else launch_col3d<R, C3_TZ64>(c, a, has_u, bulk);
+    }
+    finalize<R>(c, totals, c->c3_nwg);
+    return status_of_launch();
+  }
   StepArgs<R> a;
   a.g = c->g;
   a.p = make_par<R>(c);
@@ -721,8 +782,11 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   int n2 = ntiles_2d(grid, t2);
   int cs, cg;
   int ncol = col_shape(grid, params, &cs, &cg);
+  int c3s[3];
+  int nc3 = col3_shape(grid, params, c3s);
   int npart = nblk > n2 ? nblk : n2;
   npart = ncol > npart ? ncol : npart;
+  npart = nc3 > npart ? nc3 : npart;
   size_t n = (size_t)grid->n[0] * grid->n[1] * grid->n[2];
   size_t es = esize(params);
   size_t b = align_up(NSTATE * sizeof(double));
@@ -773,8 +837,10 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
   c->ng3 = geo3_tiles(grid, c->g3tiles);
   c->nflags = flag_count(grid, params);
   c->col_nwg = col_shape(grid, params, &c->col_strips, &c->col_groups);
+  c->c3_nwg = col3_shape(grid, params, c->c3);
   int npart = c->nblk > c->ntiles2d ? c->nblk : c->ntiles2d;
   npart = c->col_nwg > npart ? c->col_nwg : npart;
+  npart = c->c3_nwg > npart ? c->c3_nwg : npart;
   size_t es = esize(params);
   char* p = c->ws;
   c->state = (double*)p;
@@ -864,7 +930,7 @@ int surf_step(surf_ctx* c, const void* vof_next, const void* const* u, const voi
   if (!c->has_chi) return SURF_ESTATE;
   if (vof_next) {
     // 2D: the redistancing sweeps run inside tile kernels when they fit
-    if (c->col_nwg > 0) {
+    if (c->grid.dim == 2 && c->col_nwg > 0) {
       if (c->prm.precision == SURF_F32 && geom2d_ok<float>(c))
         return col2d_impl<float>(c, vof_next, u, F_in, psi_in, F_out, psi_out, sigma_out,
                                  totals_dev);
@@ -1214,6 +1280,7 @@ int surf_batch_set_geometry(surf_batch* b, int32_t i, const void* vof) {
   c.ng3 = 0;
   c.nflags = 0;
   c.col_nwg = 0;
+  c.c3_nwg = 0;
   c.profile = false;
   int rc = c.prm.precision == SURF_F64 ? geometry_impl<double>(&c, vof, 1)
                                        : geometry_impl<float>(&c, vof, 1);

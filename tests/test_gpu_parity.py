@@ -153,6 +153,35 @@ def test_step_variants_3d(case, prec):
     compare(o, g, prec, fields=fields)
 
 
+CASES_3D_BLOCKS = [
+    ("open-periodicz", ((2, 2), (2, 2), (1, 1))),
+    ("periodicx-walls", ((1, 1), (0, 0), (2, 0))),
+    ("walls-periodicy", ((0, 2), (1, 1), (0, 0))),
+]
+
+
+@pytest.mark.parametrize("prec", [F64, F32])
+@pytest.mark.parametrize("case", CASES_3D_BLOCKS, ids=[c[0] for c in CASES_3D_BLOCKS])
+def test_step_3d_interior_and_side_blocks(case, prec):
+    # 130 x 47 x 23: three x strips (the middle one away from both x sides,
+    # the last ragged), four row blocks (two away from the y sides, the last
+    # ragged) and ragged plane chunks, so the 3D transport runs both its
+    # interior and its side variants; the flow crosses every open side
+    name, bc = case
+    n = (130, 47, 23)
+    h = 1.0 / 130
+    prob = dict(dim=3, n=n, h=h, bc=bc, eos=1, eos_E=0.3, D_b=1e-2, D_s=2e-3, k_a=1.5, k_d=0.7)
+    cen = (0.46, 0.19, 0.09)
+    vof = synth.vof_ball(n, h, cen, 0.07, 3)
+    u = synth.u_hadamard(n, h, cen, 0.07, -0.4, 0.01)
+    u = [u[0] + 0.25, u[1] - 0.15, u[2]]
+    c0 = synth.uniform_field(n, 9, 0.8, 1.2)
+    dt = 0.1 * h * h / 1e-2
+    o = run_oracle(prob, vof, 6, dt, u=u, c0=c0, gamma0=0.4)
+    g = run_gpu(prob, vof, 6, dt, prec, u=u, c0=c0, gamma0=0.4)
+    compare(o, g, prec)
+
+
 @pytest.mark.parametrize("prec", [F64, F32])
 def test_moving_interface_expanding_circle(prec):
     # the expanding-circle workload at 192^2: VoF recomputed at t^{n+1} every
