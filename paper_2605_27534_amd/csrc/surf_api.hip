@@ -315,10 +315,13 @@ void materialize(surf_ctx* c) {
   c->materialized = true;
 }
 
+// After a full-box level-set pass neither buffer's tiles are known to hold
+// the clamp: both flag arrays say live.
 void flags_live(surf_ctx* c) {
   if (c->nflags == 0) return;
-  hipLaunchKernelGGL(k_fill_u8, dim3((c->nflags + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, c->stream,
-                     c->q[c->chi_cur], (uint8_t)Q_LIVE, c->nflags);
+  for (int b = 0; b < 2; ++b)
+    hipLaunchKernelGGL(k_fill_u8, dim3((c->nflags + BLOCK - 1) / BLOCK), dim3(BLOCK), 0,
+                       c->stream, c->q[b], (uint8_t)Q_LIVE, c->nflags);
 }
 
 template <typename R>
@@ -437,36 +440,37 @@ bool geo3_ok(const surf_ctx* c) {
   return c->grid.dim == 3 && c->ng3 > 0 && K >= 2 && K <= G3 && (K % 2) == 0;
 }
 
+// The level set stays in chi[chi_cur] (R); chi[1 - chi_cur] (S) is the
+// sweeps' partner and its flag array also carries this step's live marks.
 template <typename R>
 void geo3_impl(surf_ctx* c, const void* vof) {
   Geo3Args ga;
   ga.g = c->g;
   for (int d = 0; d < 3; ++d) ga.tiles[d] = c->g3tiles[d];
   ga.ntiles = c->ng3;
+  ga.per_xcd = (c->ng3 + 7) / 8;
   const Par<R> p = make_par<R>(c);
-  R* chi_in = (R*)c->chi[c->chi_cur];
-  R* chi_out = (R*)c->chi[1 - c->chi_cur];
-  uint8_t* q_in = c->q[c->chi_cur];
-  uint8_t* q_out = c->q[1 - c->chi_cur];
+  R* chiR = (R*)c->chi[c->chi_cur];
+  R* chiS = (R*)c->chi[1 - c->chi_cur];
+  uint8_t* qR = c->q[c->chi_cur];
+  uint8_t* qS = c->q[1 - c->chi_cur];
+  const int K = c->prm.hj_iters_step;
   {
     Timed tm(c, 1);
-    hipLaunchKernelGGL(k_geo3_classify<R>, dim3(c->ng3), dim3(G3_THREADS), 0, c->stream, ga, p,
-                       (const R*)vof, (const R*)chi_in, chi_out, (R*)c->g0, (const uint8_t*)q_in,
-                       q_out, c->state);
+    hipLaunchKernelGGL(k_geo3_classify<R>, dim3(8 * ga.per_xcd), dim3(G3_THREADS), 0, c->stream,
+                       ga, p, (const R*)vof, chiS, (R*)c->g0, (const uint8_t*)qR, qS, c->state);
     hipLaunchKernelGGL(k_geo3_list, dim3(1), dim3(G3_LIST_THREADS), 0, c->stream,
-                       (const uint8_t*)q_out, c->ng3, c->live3);
-    const int K = c->prm.hj_iters_step;
+                       (const uint8_t*)qS, c->ng3, c->live3);
     const R dtau = (R)(c->grid.h / 3);
     for (int k = 1; k <= K; ++k) {
-      // odd sweeps read chi_out and write chi_in, even sweeps the reverse
-      const R* src = (k & 1) ? chi_out : chi_in;
-      R* dst = (k & 1) ? chi_in : chi_out;
+      // odd sweeps R -> S, even sweeps S -> R
+      const R* src = (k & 1) ? chiR : chiS;
+      R* dst = (k & 1) ? chiS : chiR;
       hipLaunchKernelGGL(k_geo3_sweep<R>, dim3(G3_SWEEP_GRID), dim3(G3_SWEEP_THREADS), 0,
-                         c->stream, ga, p, dtau, src, dst, (const R*)c->g0, q_out,
+                         c->stream, ga, p, dtau, src, dst, (const R*)c->g0, qR,
                          (const int*)c->live3, k == K ? 1 : 0);
     }
   }
-  c->chi_cur = 1 - c->chi_cur;
   c->materialized = true;
 }
 

@@ -6,19 +6,19 @@
 // tile neighbourhood was quiescent with the same sign after the previous
 // step keeps the clamp value: every cell it can reach in K <= 16 sweeps is at
 // the clamp, where a Godunov sweep changes nothing.  The other tiles are
-// rebuilt by K sweeps over the live tiles only:
-//   k_geo3_classify  one workgroup per tile: the decision, the clamp value of
-//                    quiescent tiles, and for live tiles the sweep start
-//                    (chi_in copied) and the pin data (Russo-Smereka
-//                    distance of cut cells, signed infinity elsewhere);
+// rebuilt by K sweeps over the live tiles only.  The level set stays in one
+// buffer (R); the other (S) is the sweeps' ping-pong partner.  Both hold the
+// clamp on every quiescent tile, each with a flag array saying so, so that a
+// sweep reads its neighbours from one buffer without looking at flags:
+//   k_geo3_classify  one workgroup per tile: the decision; a quiescent tile
+//                    writes the clamp into S only if S's flag says S does not
+//                    hold it yet, a live tile its pin data (Russo-Smereka
+//                    distance of cut cells, signed infinity elsewhere); the
+//                    decision goes to S's flags (live = Q_TODO);
 //   k_geo3_list      one workgroup: the live tiles in tile order;
-//   k_geo3_sweep     one Jacobi sweep over the listed tiles (a persistent
-//                    grid); the last sweep also sets the new flags.
-// The sweeps alternate between chi_out and chi_in (whose live tiles the
-// classify pass has already copied).  A quiescent tile holds the clamp in
-// both: in chi_out from the classify pass, in chi_in because its flag after
-// the previous step was that clamp.  K is even, so the result ends in
-// chi_out.
+//   k_geo3_sweep     one Jacobi sweep over the listed tiles, R -> S or
+//                    S -> R (K even, so the result ends in R); the last one
+//                    writes R's flags.
 #pragma once
 #include "surf_common.hpp"
 #include "surf_step2d.hpp"
@@ -34,6 +34,7 @@ struct Geo3Args {
   Grid g;
   int tiles[3];
   int ntiles;
+  int per_xcd;  // ceil(ntiles / 8): tiles per XCD band of the classify grid
 };
 
 __device__ __forceinline__ int geo3_tile_of(const Geo3Args& t, int x, int y, int z) {
@@ -43,15 +44,16 @@ __device__ __forceinline__ int geo3_tile_of(const Geo3Args& t, int x, int y, int
 template <typename R>
 __global__ void __launch_bounds__(G3_THREADS) k_geo3_classify(Geo3Args ga, Par<R> p,
                                                               const R* __restrict__ vof,
-                                                              const R* __restrict__ chi_in,
-                                                              R* __restrict__ chi_out,
+                                                              R* __restrict__ chiS,
                                                               R* __restrict__ g0,
                                                               const uint8_t* __restrict__ q_in,
                                                               uint8_t* __restrict__ q_out,
                                                               double* __restrict__ state) {
   __shared__ uint8_t sQ[27];
   __shared__ int sVote[G3_THREADS / 64];
-  const int t = blockIdx.x;
+  // consecutive tiles (x neighbours, sharing cache lines) on one XCD
+  const int b = blockIdx.x;
+  const int t = (b & 7) * ga.per_xcd + (b >> 3);
   if (t >= ga.ntiles) return;
   const Grid& g = ga.g;
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
@@ -63,6 +65,7 @@ __global__ void __launch_bounds__(G3_THREADS) k_geo3_classify(Geo3Args ga, Par<R
   const int lx = tid % G3, ly = tid / G3;
   const int gx = x0 + lx, gy = y0 + ly;
   const bool colin = gx < nx && gy < ny;
+  const uint8_t qs_old = q_out[t];  // read before thread 0 rewrites it
   bool one = true, zero = true;
   R f[G3];
 #pragma unroll
@@ -100,12 +103,14 @@ __global__ void __launch_bounds__(G3_THREADS) k_geo3_classify(Geo3Args ga, Par<R
     if ((int)q != want) quiet = false;
     if (q == Q_LIVE) nb_quiet = false;
   }
-  if (quiet) {
-    const R v = want == Q_POS ? p.chimax : -p.chimax;
+  if (quiet) {  // R already holds the clamp here; S gets it unless it has it
+    if ((int)qs_old != want) {
+      const R v = want == Q_POS ? p.chimax : -p.chimax;
 #pragma unroll
-    for (int k = 0; k < G3; ++k) {
-      const int gz = z0 + k;
-      if (colin && gz < nz) chi_out[(long long)gx + (long long)nx * (gy + (long long)ny * gz)] = v;
+      for (int k = 0; k < G3; ++k) {
+        const int gz = z0 + k;
+        if (colin && gz < nz) chiS[(long long)gx + (long long)nx * (gy + (long long)ny * gz)] = v;
+      }
     }
     if (tid == 0) q_out[t] = (uint8_t)want;
     return;
@@ -116,7 +121,7 @@ __global__ void __launch_bounds__(G3_THREADS) k_geo3_classify(Geo3Args ga, Par<R
     if (nb_quiet) atomicOr((unsigned*)(state + S_FLAGS), (unsigned)STATUS_GEOM_JUMP);
   }
   if (!colin) return;
-  // live: sweep start and pin data of the tile's cells
+  // live: pin data of the tile's cells
   const int mxm = map_axis(gx - 1, nx, g.bc[0][0], g.bc[0][1]);
   const int mxp = map_axis(gx + 1, nx, g.bc[0][0], g.bc[0][1]);
   const int mym = map_axis(gy - 1, ny, g.bc[1][0], g.bc[1][1]);
@@ -127,7 +132,6 @@ __global__ void __launch_bounds__(G3_THREADS) k_geo3_classify(Geo3Args ga, Par<R
     if (gz >= nz) break;
     const long long pl = (long long)nx * ny;
     const long long c = (long long)gx + (long long)nx * gy + pl * gz;
-    chi_out[c] = chi_in[c];
     const int mzm = map_axis(gz - 1, nz, g.bc[2][0], g.bc[2][1]);
     const int mzp = map_axis(gz + 1, nz, g.bc[2][0], g.bc[2][1]);
     const R x0v = (f[k] - R(0.5)) * p.h;
@@ -183,16 +187,31 @@ __global__ void __launch_bounds__(G3_LIST_THREADS) k_geo3_list(const uint8_t* __
   if (tid == 0) live[0] = sBase;
 }
 
-// One Jacobi sweep (Godunov, pinned cut cells, clamp) over the listed
-// tiles; workgroup b takes entries b, b + G, ...  The last sweep also writes
-// each tile's new flag.
-constexpr int G3_SWEEP_THREADS = 1024, G3_SWEEP_GRID = 512;
+// map_axis written with selects only (no branches), for the uniform z
+// coordinates and the per-thread x, y neighbours
+__device__ __forceinline__ int map_axis_sel(int q, int n, int lo_bc, int hi_bc) {
+  const int lo = lo_bc == BC_PERIODIC ? q + n : -1 - q;
+  const int hi = hi_bc == BC_PERIODIC ? q - n : 2 * n - 1 - q;
+  int r = q < 0 ? lo : (q >= n ? hi : q);
+  r = r < 0 ? 0 : r;
+  return r >= n ? n - 1 : r;
+}
+
+// One Jacobi sweep (Godunov, pinned cut cells, clamp) over the listed tiles.
+// Thread (x, y) of a 256-thread workgroup owns the tile's z-column at
+// (x, y): it loads the column with one cell beyond each end, the four x and
+// y neighbour columns and the pin data, every load issued before any is
+// used, then updates its 16 cells.  Neighbours come from src everywhere:
+// quiescent tiles hold the clamp in both buffers.  Persistent grid (a
+// multiple of 8 workgroups).  The last sweep also writes each tile's new
+// flag.
+constexpr int G3_SWEEP_THREADS = G3 * G3, G3_SWEEP_GRID = 1024;
 template <typename R>
 __global__ void __launch_bounds__(G3_SWEEP_THREADS) k_geo3_sweep(Geo3Args ga, Par<R> p, R dtau,
                                                                  const R* __restrict__ src,
                                                                  R* __restrict__ dst,
                                                                  const R* __restrict__ g0,
-                                                                 uint8_t* __restrict__ q,
+                                                                 uint8_t* __restrict__ qr,
                                                                  const int* __restrict__ live,
                                                                  int last) {
   __shared__ int sVote[G3_SWEEP_THREADS / 64];
@@ -200,58 +219,71 @@ __global__ void __launch_bounds__(G3_SWEEP_THREADS) k_geo3_sweep(Geo3Args ga, Pa
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const long long pl = (long long)nx * ny;
   const int tid = threadIdx.x;
+  const int lx = tid % G3, ly = tid / G3;
+  // XCD k (workgroups b with b % 8 == k) takes the k-th eighth of the list,
+  // so that neighbouring tiles, which share cache lines, meet in one L2
   const int n = live[0];
-  for (int i = blockIdx.x; i < n; i += gridDim.x) {
-    const int t = live[1 + i];
-    const int tc[3] = {t % ga.tiles[0], (t / ga.tiles[0]) % ga.tiles[1],
-                       t / (ga.tiles[0] * ga.tiles[1])};
+  const int per = (n + 7) / 8, xcd = blockIdx.x & 7, slots = gridDim.x >> 3;
+  const int lo = xcd * per, hi = min(n, lo + per);
+  for (int it = lo + (blockIdx.x >> 3); it < hi; it += slots) {
+    const int t = live[1 + it];
+    const int x0 = (t % ga.tiles[0]) * G3, y0 = ((t / ga.tiles[0]) % ga.tiles[1]) * G3,
+              z0 = (t / (ga.tiles[0] * ga.tiles[1])) * G3;
+    const int gx = x0 + lx, gy = y0 + ly;
+    const bool colin = gx < nx && gy < ny;
+    // columns past the box edge read a valid column and store nothing
+    const int cx = colin ? gx : nx - 1, cy = colin ? gy : ny - 1;
+    const long long cxy = (long long)cx + (long long)nx * cy;
+    const long long cxm = (long long)map_axis_sel(cx - 1, nx, g.bc[0][0], g.bc[0][1]) + (long long)nx * cy;
+    const long long cxp = (long long)map_axis_sel(cx + 1, nx, g.bc[0][0], g.bc[0][1]) + (long long)nx * cy;
+    const long long cym = (long long)cx + (long long)nx * map_axis_sel(cy - 1, ny, g.bc[1][0], g.bc[1][1]);
+    const long long cyp = (long long)cx + (long long)nx * map_axis_sel(cy + 1, ny, g.bc[1][0], g.bc[1][1]);
+    R col[G3 + 2], xm[G3], xp[G3], ym[G3], yp[G3], gv[G3];
+#pragma unroll
+    for (int z = -1; z <= G3; ++z) {
+      const long long pz = pl * map_axis_sel(z0 + z, nz, g.bc[2][0], g.bc[2][1]);
+      col[z + 1] = src[cxy + pz];
+      if (z >= 0 && z < G3) {
+        xm[z] = src[cxm + pz];
+        xp[z] = src[cxp + pz];
+        ym[z] = src[cym + pz];
+        yp[z] = src[cyp + pz];
+        gv[z] = g0[cxy + pz];
+      }
+    }
     bool allpos = true, allneg = true;
 #pragma unroll
-    for (int k = 0; k < G3_CELLS / G3_SWEEP_THREADS; ++k) {
-      const int l = tid + k * G3_SWEEP_THREADS;
-      const int c3[3] = {tc[0] * G3 + l % G3, tc[1] * G3 + (l / G3) % G3, tc[2] * G3 + l / (G3 * G3)};
-      if (c3[0] >= nx || c3[1] >= ny || c3[2] >= nz) continue;
-      const long long c = (long long)c3[0] + (long long)nx * c3[1] + pl * c3[2];
-      const R gv = g0[c];
-      R v;
-      if (fabs(gv) < R(INFINITY)) {
-        v = gv;
-      } else {
-        const R x = src[c];
-        const R sgn = gv > R(0) ? R(1) : R(-1);
-        R G2 = R(0);
+    for (int z = 0; z < G3; ++z) {
+      const R v = col[z + 1], gk = gv[z];
+      const R sgn = gk > R(0) ? R(1) : R(-1);
+      const R nb[6] = {xm[z], xp[z], ym[z], yp[z], col[z], col[z + 2]};
+      R G2 = R(0);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          R nbv[2];
-#pragma unroll
-          for (int s = 0; s < 2; ++s) {
-            int m3[3] = {c3[0], c3[1], c3[2]};
-            m3[d] = map_axis(c3[d] + (s ? 1 : -1), g.n[d], g.bc[d][0], g.bc[d][1]);
-            nbv[s] = src[(long long)m3[0] + (long long)nx * m3[1] + pl * m3[2]];
-          }
-          const R a1 = sgn * (x - nbv[0]) * p.inv_h, b1 = sgn * (nbv[1] - x) * p.inv_h;
-          const R t1 = a1 > R(0) ? a1 * a1 : R(0), t2 = b1 < R(0) ? b1 * b1 : R(0);
-          G2 += t1 > t2 ? t1 : t2;
-        }
-        v = x - dtau * sgn * (rsqrt_<R>(G2) - R(1));
+      for (int d = 0; d < 3; ++d) {
+        const R a1 = sgn * (v - nb[2 * d]) * p.inv_h, b1 = sgn * (nb[2 * d + 1] - v) * p.inv_h;
+        const R t1 = a1 > R(0) ? a1 * a1 : R(0), t2 = b1 < R(0) ? b1 * b1 : R(0);
+        G2 += t1 > t2 ? t1 : t2;
       }
-      v = v > p.chimax ? p.chimax : v;
-      v = v < -p.chimax ? -p.chimax : v;
-      dst[c] = v;
-      allpos = allpos && v == p.chimax;
-      allneg = allneg && v == -p.chimax;
+      R nv = fabs(gk) < R(INFINITY) ? gk : v - dtau * sgn * (rsqrt_<R>(G2) - R(1));
+      nv = nv > p.chimax ? p.chimax : nv;
+      nv = nv < -p.chimax ? -p.chimax : nv;
+      if (colin && z0 + z < nz) {
+        dst[cxy + pl * (z0 + z)] = nv;
+        allpos = allpos && nv == p.chimax;
+        allneg = allneg && nv == -p.chimax;
+      }
     }
     if (last) {
       const bool wp = __all(allpos), wn = __all(allneg);
       if ((tid & 63) == 0) sVote[tid >> 6] = (wp ? 1 : 0) | (wn ? 2 : 0);
+      __syncthreads();
+      if (tid == 0) {
+        int m = 3;
+        for (int w = 0; w < G3_SWEEP_THREADS / 64; ++w) m &= sVote[w];
+        qr[t] = (m & 1) ? Q_POS : ((m & 2) ? Q_NEG : Q_LIVE);
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    if (last && tid == 0) {
-      int m = 3;
-      for (int w = 0; w < G3_SWEEP_THREADS / 64; ++w) m &= sVote[w];
-      q[t] = (m & 1) ? Q_POS : ((m & 2) ? Q_NEG : Q_LIVE);
-    }
-    __syncthreads();
   }
 }
 
