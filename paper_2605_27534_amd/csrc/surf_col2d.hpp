@@ -74,27 +74,15 @@ __device__ __forceinline__ double wshift(double v) {
 template <typename R> __device__ __forceinline__ R from_right(R v) { return wshift<DPP_WF_SL1>(v); }
 template <typename R> __device__ __forceinline__ R from_left(R v) { return wshift<DPP_WF_SR1>(v); }
 
-// Buffer-resource access: the base address lives in scalar registers and
-// each lane adds a 32-bit byte offset; reads past num_records return 0 and
-// writes past it are dropped.  Word 3 of the descriptor is the raw
-// (untyped, 32-bit) format of gfx9-class GPUs.
-using rsrc_t = __amdgpu_buffer_rsrc_t;
-__device__ __forceinline__ rsrc_t make_rsrc(const void* p, long long bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+// Plain global access: a 64-bit scalar base and a 32-bit byte offset.  Every
+// index passed here is mapped into its array by the caller.
+template <typename R>
+__device__ __forceinline__ R gld(const R* base, int voff, int soff) {
+  return *(const R*)((const char*)base + (unsigned)(voff + soff));
 }
-template <typename R> __device__ __forceinline__ R bload(rsrc_t r, int voff, int soff);
-template <> __device__ __forceinline__ float bload<float>(rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-template <> __device__ __forceinline__ double bload<double>(rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-}
-__device__ __forceinline__ void bstore(float v, rsrc_t r, int voff, int soff) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
-}
-__device__ __forceinline__ void bstore(double v, rsrc_t r, int voff, int soff) {
-  using w64 = unsigned int __attribute__((ext_vector_type(2)));
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(w64, v), r, voff, soff, 0);
+template <typename R>
+__device__ __forceinline__ void gst(R v, R* base, int voff, int soff) {
+  *(R*)((char*)base + (unsigned)(voff + soff)) = v;
 }
 
 // minmod(a, b) is the median of (a, b, 0): 0 for opposite signs, else the
@@ -155,7 +143,9 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
     xf_lo = !px && fx == 0;
     xf_hi = !px && fx == nx;
     xf_out = !px && (fx < 0 || fx > nx);
-    if (px) fxm = ((fx % nx) + nx) % nx;
+    // the face column read by the lane, always inside the face array (the
+    // value of a face beyond a side is discarded below)
+    fxm = px ? ((fx % nx) + nx) % nx : (xf_out ? 0 : fx);
   }
   const bool out_lane = lane >= 3 && lane < 3 + COL_OUT && (IX || xs < nx);
   // lane constants of the x sides
@@ -168,19 +158,19 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
   // y face k-3 and level-set / x-face row k-4; iteration i consumes group i,
   // and group i + LOOKAHEAD is issued before iteration i computes
   constexpr int ES = (int)sizeof(R);
-  const long long ncell = (long long)nx * ny;
-  const rsrc_t bF = make_rsrc(a.F, BULK ? ncell * ES : 0), bP = make_rsrc(a.psi, ncell * ES);
-  const rsrc_t bC = make_rsrc(a.chi, ncell * ES);
-  const rsrc_t bUx = make_rsrc(a.u[0], HU ? (long long)(nx + 1) * ny * ES : 0);
-  const rsrc_t bUy = make_rsrc(a.u[1], HU ? (long long)nx * (ny + 1) * ES : 0);
+  const R* const bF = a.F;
+  const R* const bP = a.psi;
+  const R* const bC = a.chi;
+  const R* const bUx = a.u[0];
+  const R* const bUy = a.u[1];
   const int vmx = mx * ES, vfx = fxm * ES;  // per-lane byte offsets
   R rF[NR3], rP[NR3], rC[NR1], rUx[NR1], rUy[NFY];
   auto load_group = [&](const int k) {
     if (k < NR3) {
       const int my = IY ? y0 - 3 + k : map_axis(y0 - 3 + k, ny, g.bc[1][0], g.bc[1][1]);
       const int row = nx * my * ES;
-      rF[k] = BULK ? bload<R>(bF, vmx, row) : R(0);
-      rP[k] = bload<R>(bP, vmx, row);
+      rF[k] = BULK ? gld<R>(bF, vmx, row) : R(0);
+      rP[k] = gld<R>(bP, vmx, row);
     }
     if (k >= 3 && k - 3 < NFY) {
       const int i = k - 3;
@@ -197,7 +187,7 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
             ok = false;
           }
         }
-        const R v = bload<R>(bUy, vmx, nx * j * ES);
+        const R v = gld<R>(bUy, vmx, nx * j * ES);
         rUy[i] = ok ? v : R(0);
       }
     }
@@ -205,11 +195,11 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
       const int i = k - 4;
       const int ys = y0 - 1 + i;
       const int my = IY ? ys : map_axis(ys, ny, g.bc[1][0], g.bc[1][1]);
-      rC[i] = bload<R>(bC, vmx, nx * my * ES);
+      rC[i] = gld<R>(bC, vmx, nx * my * ES);
       rUx[i] = R(0);
       if (HU) {
         const bool ok = (IX || !xf_out) && (IY || py || (ys >= 0 && ys < ny));
-        const R v = bload<R>(bUx, vfx, (nx + 1) * my * ES);
+        const R v = gld<R>(bUx, vfx, (nx + 1) * my * ES);
         rUx[i] = ok ? v : R(0);
       }
     }
@@ -217,8 +207,9 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
 #pragma unroll
   for (int k = 0; k < 3 + COL_LOOKAHEAD && k < NR3; ++k) load_group(k);
 
-  const rsrc_t bFo = make_rsrc(a.Fo, BULK ? ncell * ES : 0), bPo = make_rsrc(a.Po, ncell * ES);
-  const rsrc_t bS = make_rsrc(a.sig, a.sig ? ncell * ES : 0);
+  R* const bFo = a.Fo;
+  R* const bPo = a.Po;
+  R* const bS = a.sig;
   const int vxs = xs * ES;
   const R kl = p.kin == KIN_LANGMUIR ? R(1) : R(0);
 
@@ -339,9 +330,9 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
           const R Pn = pPs + a.dt * (divP + q);
           const R sg = eos<R>(quot<R>(Pn, pDe + p.eta_eps, pIP), p);
           const int row = nx * o * ES;
-          if (BULK) bstore(Fn, bFo, vxs, row);
-          bstore(Pn, bPo, vxs, row);
-          if (a.sig) bstore(sg, bS, vxs, row);
+          if (BULK) gst(Fn, bFo, vxs, row);
+          gst(Pn, bPo, vxs, row);
+          if (a.sig) gst(sg, bS, vxs, row);
           acc.sF += (double)Fn;
           acc.sP += (double)Pn;
           acc.sD += (double)pDe;

@@ -35,15 +35,6 @@ constexpr int C3_XI_ROWS = C3_WAVES + 4;
 constexpr int C3_LOOKAHEAD = 2;       // planes of loads in flight ahead of the arithmetic
 
 template <typename R>
-__device__ __forceinline__ R gld(const R* base, int voff, int soff) {
-  return *(const R*)((const char*)base + (unsigned)(voff + soff));
-}
-template <typename R>
-__device__ __forceinline__ void gst(R v, R* base, int voff, int soff) {
-  *(R*)((char*)base + (unsigned)(voff + soff)) = v;
-}
-
-template <typename R>
 struct Col3Lds {
   R xF[C3_XI_ROWS][64], xP[C3_XI_ROWS][64];  // advected inputs of plane s, rows y0-3 .. y0+16
   R ph[C3_WAVES][64], de[C3_WAVES][64];      // phi, delta of plane s, rows y0-1 .. y0+14

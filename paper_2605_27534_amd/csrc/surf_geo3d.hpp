@@ -37,6 +37,16 @@ struct Geo3Args {
   int per_xcd;  // ceil(ntiles / 8): tiles per XCD band of the classify grid
 };
 
+// map_axis written with selects only (no branches), for the uniform z
+// coordinates and the per-thread x, y neighbours
+__device__ __forceinline__ int map_axis_sel(int q, int n, int lo_bc, int hi_bc) {
+  const int lo = lo_bc == BC_PERIODIC ? q + n : -1 - q;
+  const int hi = hi_bc == BC_PERIODIC ? q - n : 2 * n - 1 - q;
+  int r = q < 0 ? lo : (q >= n ? hi : q);
+  r = r < 0 ? 0 : r;
+  return r >= n ? n - 1 : r;
+}
+
 __device__ __forceinline__ int geo3_tile_of(const Geo3Args& t, int x, int y, int z) {
   return (x / G3) + t.tiles[0] * ((y / G3) + t.tiles[1] * (z / G3));
 }
@@ -61,22 +71,27 @@ __global__ void __launch_bounds__(G3_THREADS) k_geo3_classify(Geo3Args ga, Par<R
   const int tx = t % ga.tiles[0], ty = (t / ga.tiles[0]) % ga.tiles[1],
             tz = t / (ga.tiles[0] * ga.tiles[1]);
   const int x0 = tx * G3, y0 = ty * G3, z0 = tz * G3;
-  // this thread's cells: x = tid % 16, y = tid / 16, z = 0 .. 15
+  // this thread's cells: x = tid % 16, y = tid / 16, z = 0 .. 15.  The
+  // loads go to mapped (always valid) cells and are all issued before any
+  // is used; only the cells inside the box take part in the vote.  Columns
+  // past the box edge read a valid column and store nothing.
   const int lx = tid % G3, ly = tid / G3;
   const int gx = x0 + lx, gy = y0 + ly;
   const bool colin = gx < nx && gy < ny;
+  const int cx = colin ? gx : nx - 1, cy = colin ? gy : ny - 1;
+  const long long pl = (long long)nx * ny;
+  const long long cxy = (long long)cx + (long long)nx * cy;
   const uint8_t qs_old = q_out[t];  // read before thread 0 rewrites it
   bool one = true, zero = true;
   R f[G3];
 #pragma unroll
+  for (int k = 0; k < G3; ++k)
+    f[k] = vof[cxy + pl * map_axis_sel(z0 + k, nz, g.bc[2][0], g.bc[2][1])];
+#pragma unroll
   for (int k = 0; k < G3; ++k) {
-    const int gz = z0 + k;
-    f[k] = R(0.5);
-    if (colin && gz < nz) {
-      f[k] = vof[(long long)gx + (long long)nx * (gy + (long long)ny * gz)];
-      one = one && f[k] == R(1);
-      zero = zero && f[k] == R(0);
-    }
+    const bool in = colin && z0 + k < nz;
+    one = one && (!in || f[k] == R(1));
+    zero = zero && (!in || f[k] == R(0));
   }
   if (tid < 27) {
     int u[3] = {tx + tid % 3 - 1, ty + (tid / 3) % 3 - 1, tz + tid / 9 - 1};
@@ -121,39 +136,48 @@ __global__ void __launch_bounds__(G3_THREADS) k_geo3_classify(Geo3Args ga, Par<R
     if (nb_quiet) atomicOr((unsigned*)(state + S_FLAGS), (unsigned)STATUS_GEOM_JUMP);
   }
   if (!colin) return;
-  // live: pin data of the tile's cells
-  const int mxm = map_axis(gx - 1, nx, g.bc[0][0], g.bc[0][1]);
-  const int mxp = map_axis(gx + 1, nx, g.bc[0][0], g.bc[0][1]);
-  const int mym = map_axis(gy - 1, ny, g.bc[1][0], g.bc[1][1]);
-  const int myp = map_axis(gy + 1, ny, g.bc[1][0], g.bc[1][1]);
-#pragma unroll 4
-  for (int k = 0; k < G3; ++k) {
-    const int gz = z0 + k;
-    if (gz >= nz) break;
-    const long long pl = (long long)nx * ny;
-    const long long c = (long long)gx + (long long)nx * gy + pl * gz;
-    const int mzm = map_axis(gz - 1, nz, g.bc[2][0], g.bc[2][1]);
-    const int mzp = map_axis(gz + 1, nz, g.bc[2][0], g.bc[2][1]);
-    const R x0v = (f[k] - R(0.5)) * p.h;
-    R nb[6];
-    nb[0] = (vof[(long long)mxm + (long long)nx * gy + pl * gz] - R(0.5)) * p.h;
-    nb[1] = (vof[(long long)mxp + (long long)nx * gy + pl * gz] - R(0.5)) * p.h;
-    nb[2] = (vof[(long long)gx + (long long)nx * mym + pl * gz] - R(0.5)) * p.h;
-    nb[3] = (vof[(long long)gx + (long long)nx * myp + pl * gz] - R(0.5)) * p.h;
-    nb[4] = (vof[(long long)gx + (long long)nx * gy + pl * mzm] - R(0.5)) * p.h;
-    nb[5] = (vof[(long long)gx + (long long)nx * gy + pl * mzp] - R(0.5)) * p.h;
-    bool cut = false;
-    R jump = R(0), grad2 = R(0);
+  // live: pin data of the tile's cells, in two halves of 8 planes; the
+  // neighbour columns of each half are loaded before any is used
+  const long long cxm = (long long)map_axis_sel(cx - 1, nx, g.bc[0][0], g.bc[0][1]) + (long long)nx * cy;
+  const long long cxp = (long long)map_axis_sel(cx + 1, nx, g.bc[0][0], g.bc[0][1]) + (long long)nx * cy;
+  const long long cym = (long long)cx + (long long)nx * map_axis_sel(cy - 1, ny, g.bc[1][0], g.bc[1][1]);
+  const long long cyp = (long long)cx + (long long)nx * map_axis_sel(cy + 1, ny, g.bc[1][0], g.bc[1][1]);
+  const R zlo = vof[cxy + pl * map_axis_sel(z0 - 1, nz, g.bc[2][0], g.bc[2][1])];
+  const R zhi = vof[cxy + pl * map_axis_sel(z0 + G3, nz, g.bc[2][0], g.bc[2][1])];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const R xm = nb[2 * d], xp = nb[2 * d + 1];
-      cut = cut || (x0v * xm <= R(0)) || (x0v * xp <= R(0));
-      jump = fmax(jump, fmax(fabs(xm - x0v), fabs(xp - x0v)));
-      const R cd = R(0.5) * (xp - xm);
-      grad2 += cd * cd;
+  for (int half = 0; half < 2; ++half) {
+    R nxm[G3 / 2], nxp[G3 / 2], nym[G3 / 2], nyp[G3 / 2];
+#pragma unroll
+    for (int j = 0; j < G3 / 2; ++j) {
+      const long long pz = pl * map_axis_sel(z0 + half * (G3 / 2) + j, nz, g.bc[2][0], g.bc[2][1]);
+      nxm[j] = vof[cxm + pz];
+      nxp[j] = vof[cxp + pz];
+      nym[j] = vof[cym + pz];
+      nyp[j] = vof[cyp + pz];
     }
-    const R Delta = fmax(fmax(rsqrt_<R>(grad2), jump), R(1e-30) * p.h);
-    g0[c] = cut ? p.h * x0v / Delta : (x0v > R(0) ? R(INFINITY) : R(-INFINITY));
+#pragma unroll
+    for (int j = 0; j < G3 / 2; ++j) {
+      const int k = half * (G3 / 2) + j;
+      const int gz = z0 + k;
+      const R x0v = (f[k] - R(0.5)) * p.h;
+      const R nb[6] = {(nxm[j] - R(0.5)) * p.h, (nxp[j] - R(0.5)) * p.h,
+                       (nym[j] - R(0.5)) * p.h, (nyp[j] - R(0.5)) * p.h,
+                       ((k > 0 ? f[k - 1] : zlo) - R(0.5)) * p.h,
+                       ((k < G3 - 1 ? f[k + 1] : zhi) - R(0.5)) * p.h};
+      bool cut = false;
+      R jump = R(0), grad2 = R(0);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const R xm = nb[2 * d], xp = nb[2 * d + 1];
+        cut = cut || (x0v * xm <= R(0)) || (x0v * xp <= R(0));
+        jump = fmax(jump, fmax(fabs(xm - x0v), fabs(xp - x0v)));
+        const R cd = R(0.5) * (xp - xm);
+        grad2 += cd * cd;
+      }
+      const R Delta = fmax(fmax(rsqrt_<R>(grad2), jump), R(1e-30) * p.h);
+      if (colin && gz < nz)
+        g0[cxy + pl * gz] = cut ? p.h * x0v / Delta : (x0v > R(0) ? R(INFINITY) : R(-INFINITY));
+    }
   }
 }
 
@@ -185,16 +209,6 @@ __global__ void __launch_bounds__(G3_LIST_THREADS) k_geo3_list(const uint8_t* __
     __syncthreads();
   }
   if (tid == 0) live[0] = sBase;
-}
-
-// map_axis written with selects only (no branches), for the uniform z
-// coordinates and the per-thread x, y neighbours
-__device__ __forceinline__ int map_axis_sel(int q, int n, int lo_bc, int hi_bc) {
-  const int lo = lo_bc == BC_PERIODIC ? q + n : -1 - q;
-  const int hi = hi_bc == BC_PERIODIC ? q - n : 2 * n - 1 - q;
-  int r = q < 0 ? lo : (q >= n ? hi : q);
-  r = r < 0 ? 0 : r;
-  return r >= n ? n - 1 : r;
 }
 
 // One Jacobi sweep (Godunov, pinned cut cells, clamp) over the listed tiles.
