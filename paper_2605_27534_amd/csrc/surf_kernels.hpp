@@ -456,13 +456,26 @@ __device__ __forceinline__ void finalize_body(const FinalArgs& f, const double* 
   v[P_MAX_C] = -INFINITY;
   v[P_MIN_F] = INFINITY;
   v[P_MIN_PSI] = INFINITY;
-  for (int b = threadIdx.x; b < f.nblk; b += FIN_BLOCK) {
-    const double* q = part + (long long)b * NPART;
+  // records b = tid, tid + FIN_BLOCK, ... combined in that order; four of
+  // them are loaded (from valid records) before any is combined
+  constexpr int U = 4;
+  for (int b0 = threadIdx.x; b0 < f.nblk; b0 += U * FIN_BLOCK) {
+    double r[U][NPART];
 #pragma unroll
-    for (int s = 0; s < NPART; ++s) {
-      if (s == P_MAX_USUM || s == P_MAX_C) v[s] = fmax(v[s], q[s]);
-      else if (s == P_MIN_F || s == P_MIN_PSI) v[s] = fmin(v[s], q[s]);
-      else v[s] += q[s];
+    for (int u = 0; u < U; ++u) {
+      const int b = min(b0 + u * FIN_BLOCK, f.nblk - 1);
+#pragma unroll
+      for (int s = 0; s < NPART; ++s) r[u][s] = part[(long long)b * NPART + s];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (b0 + u * FIN_BLOCK >= f.nblk) break;
+#pragma unroll
+      for (int s = 0; s < NPART; ++s) {
+        if (s == P_MAX_USUM || s == P_MAX_C) v[s] = fmax(v[s], r[u][s]);
+        else if (s == P_MIN_F || s == P_MIN_PSI) v[s] = fmin(v[s], r[u][s]);
+        else v[s] += r[u][s];
+      }
     }
   }
   __shared__ double tot[NPART];

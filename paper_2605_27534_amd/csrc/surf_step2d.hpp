@@ -234,16 +234,16 @@ __device__ __forceinline__ bool tile_geometry(const Step2dArgs<R>& a, const int 
   }
   {
     R rv[IC], rc[IC];
+    // every load goes to a mapped (valid) cell, also for the threads past the
+    // region, so that none waits behind a branch
 #pragma unroll
     for (int it = 0; it < IC; ++it) {
-      if (cl[it] < NC) {
-        int gx = x0 + cx[it] - HC, gy = y0 + cy[it] - HC;
-        int mx = map_axis(gx, nx, g.bc[0][0], g.bc[0][1]);
-        int my = map_axis(gy, ny, g.bc[1][0], g.bc[1][1]);
-        rv[it] = a.vof[(long long)mx + (long long)nx * my];
-        if constexpr (DECIDED) rc[it] = a.chi_in[(long long)mx + (long long)nx * my];
-        else rc[it] = chi_at_tile<R, KH, TX, TY>(a, sQ, tx, ty, gx, gy);
-      }
+      int gx = x0 + cx[it] - HC, gy = y0 + cy[it] - HC;
+      int mx = map_axis(gx, nx, g.bc[0][0], g.bc[0][1]);
+      int my = map_axis(gy, ny, g.bc[1][0], g.bc[1][1]);
+      rv[it] = a.vof[(long long)mx + (long long)nx * my];
+      if constexpr (DECIDED) rc[it] = a.chi_in[(long long)mx + (long long)nx * my];
+      else if (cl[it] < NC) rc[it] = chi_at_tile<R, KH, TX, TY>(a, sQ, tx, ty, gx, gy);
     }
 #pragma unroll
     for (int it = 0; it < IC; ++it) {
@@ -704,20 +704,21 @@ __global__ void __launch_bounds__(NT) k_step2d(Step2dArgs<R> a) {
 }
 
 // The moving-interface geometry alone (the step then runs the transport on
-// chi_out): every tile writes its chi^{n+1}, quiescent tiles the clamp value,
-// so that chi_out holds explicit values everywhere.  Small tiles (GEO_T x
-// GEO_T) spread the sweeps of the interface band over many CUs.
+// chi_out): every tile of chi_out ends with its chi^{n+1}, quiescent tiles
+// the clamp value, so that chi_out holds explicit values everywhere.  Small
+// tiles (GEO_T x GEO_T) spread the sweeps of the interface band over many
+// CUs.
 constexpr int GEO_T = 16, GEO_THREADS = 256;
-// The weighted-form moving geometry in three launches, none with a
+// The weighted-form moving geometry in two launches, neither with a
 // device-wide atomic (those serialise across the XCDs):
 //  1. k_geo_classify: one wave per tile decides from the tile's VoF and the
-//     neighbour flags of the previous step whether it stays quiescent (clamp
-//     value and flag written) or is live (flag Q_TODO);
-//  2. k_geo_list: one workgroup compacts the live tiles, in tile order, into
-//     a list and a count;
-//  3. k_geo_live: a fixed grid takes list entries w, w + G, ... and rebuilds
-//     each with tile_geometry (1024 threads: 16 waves overlap each sweep's
-//     LDS and barrier latency).
+//     neighbour flags of the previous step whether it stays quiescent (flag
+//     written; the clamp too unless chi_out's flag says the tile already
+//     holds it) or is live (flag Q_TODO);
+//  2. k_geo_live: a fixed grid; every workgroup ranks the Q_TODO flags (one
+//     coalesced pass and a prefix sum) and rebuilds the live tiles of rank
+//     b, b + G, ... with tile_geometry (1024 threads: 16 waves overlap each
+//     sweep's LDS and barrier latency).
 template <typename R, int KH>
 __global__ void __launch_bounds__(256) k_geo_classify(Step2dArgs<R> a) {
   using T = Tile2<KH, GEO_T, GEO_T>;
@@ -729,20 +730,27 @@ __global__ void __launch_bounds__(256) k_geo_classify(Step2dArgs<R> a) {
   const int nx = a.g.n[0], ny = a.g.n[1];
   const int tx = t % a.tiles[0], ty = t / a.tiles[0];
   const int x0 = tx * GEO_T, y0 = ty * GEO_T;
+  // the flag of the output buffer: its tile already holds the clamp when
+  // the flag equals this step's quiescent sign
+  const uint8_t q_had = a.q_out[t];
+  // loads from cells clamped into the box, all issued before any is used;
+  // only the cells inside the box vote
   bool one = true, zero = true;
   long long ci[CPL];
   bool in[CPL];
+  R f[CPL];
 #pragma unroll
   for (int k = 0; k < CPL; ++k) {
     const int c = lane + 64 * k;
     const int gx = x0 + c % GEO_T, gy = y0 + c / GEO_T;
     in[k] = gx < nx && gy < ny;
-    ci[k] = (long long)gx + (long long)nx * gy;
-    if (in[k]) {
-      const R f = a.vof[ci[k]];
-      one = one && f == R(1);
-      zero = zero && f == R(0);
-    }
+    ci[k] = (long long)min(gx, nx - 1) + (long long)nx * min(gy, ny - 1);
+    f[k] = a.vof[ci[k]];
+  }
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) {
+    one = one && (!in[k] || f[k] == R(1));
+    zero = zero && (!in[k] || f[k] == R(0));
   }
   int q = 255;
   if (lane < T::QN) {
@@ -772,10 +780,12 @@ __global__ void __launch_bounds__(256) k_geo_classify(Step2dArgs<R> a) {
     }
     return;
   }
-  const R v = want == Q_POS ? a.p.chimax : -a.p.chimax;
+  if ((int)q_had != want) {
+    const R v = want == Q_POS ? a.p.chimax : -a.p.chimax;
 #pragma unroll
-  for (int k = 0; k < CPL; ++k)
-    if (in[k]) a.chi_out[ci[k]] = v;
+    for (int k = 0; k < CPL; ++k)
+      if (in[k]) a.chi_out[ci[k]] = v;
+  }
   if (lane == 0) a.q_out[t] = (uint8_t)want;
 }
 
@@ -800,11 +810,17 @@ __global__ void __launch_bounds__(GEO_WG) k_geo_live(Step2dArgs<R> a) {
     const int t0 = base + 4 * tid;
     int cnt = 0;
     uint8_t f[4];
+    if (t0 + 3 < nt) {
+      // four flags in one aligned word (t0 is a multiple of 4)
+      const unsigned w = *(const unsigned*)(a.q_out + t0);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      f[k] = t0 + k < nt ? a.q_out[t0 + k] : (uint8_t)0;
-      cnt += f[k] == Q_TODO ? 1 : 0;
+      for (int k = 0; k < 4; ++k) f[k] = (uint8_t)(w >> (8 * k));
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) f[k] = t0 + k < nt ? a.q_out[t0 + k] : (uint8_t)0;
     }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cnt += f[k] == Q_TODO ? 1 : 0;
     // inclusive prefix of cnt over the wave (shuffles), then over the waves
     int inc = cnt;
 #pragma unroll
