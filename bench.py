@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c1i", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="2D moving interface: run each step's geometry on the step's own "
+                         "stream instead of preparing it during the previous transport")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain copy kernel of MIB MiB (counter calibration)")
@@ -196,18 +199,29 @@ def main():
             v = vofs[k] if vofs is not None else None
             s.step(a[0], a[1], b[0], b[1], u=u, vof_next=v, sigma_out=sig, totals=hist[k])
 
+        # 2D moving interface: step k+1's geometry is prepared on `aux` while
+        # step k's transport runs on `side`; every run of steps ends with no
+        # geometry pending
+        pipelined = (vofs is not None and prob["dim"] == 2 and prob.get("flux_form", 0) == 0
+                     and not args.no_pipeline)
+        aux = torch.cuda.Stream(dev)
+
+        def run_steps(k0, k1):
+            for k in range(k0, k1):
+                do_step(k)
+                if pipelined and k + 1 < k1:
+                    s.prepare_geometry(vofs[k + 1], aux)
+
         # ---- region 1: graph replay of K steps
         reset()
-        for k in range(W):
-            do_step(k)
-        side.synchronize()
+        run_steps(0, W)
+        torch.cuda.synchronize()
         graph = None
         if not args.no_graph:
             graph = torch.cuda.CUDAGraph()
             with torch.cuda.graph(graph, stream=side):
-                for k in range(W, W + K):
-                    do_step(k)
-        side.synchronize()
+                run_steps(W, W + K)
+        torch.cuda.synchronize()
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         wall0 = time.perf_counter()
@@ -215,8 +229,7 @@ def main():
         if graph is not None:
             graph.replay()
         else:
-            for k in range(W, W + K):
-                do_step(k)
+            run_steps(W, W + K)
         t1.record(side)
         side.synchronize()
         wall = time.perf_counter() - wall0
@@ -227,22 +240,33 @@ def main():
 
         # ---- region 2: eager K steps with per-launch events
         reset()
-        for k in range(W):
-            do_step(k)
+        run_steps(0, W)
+        torch.cuda.synchronize()
         s.profile_read()
         s.profile(True)
-        for k in range(W, W + K):
-            do_step(k)
-        side.synchronize()
+        run_steps(W, W + K)
+        torch.cuda.synchronize()
         step_ms, step_n, geom_ms, geom_n = s.profile_read()
         s.profile(False)
         h2 = hist.cpu().numpy()
+
+        # ---- region 3: the transport kernel alone, a burst of back-to-back
+        # launches between two HIP events (an event pair around one launch
+        # also counts the launch's dispatch latency, about 3 us)
+        burst_ms, burst_reps = None, 0
+        if prob.get("flux_form", 0) == 0:
+            burst_reps = 200 if ncell <= (1 << 22) else 40
+            a, b = bufs[(W + K) % 2], bufs[(W + K + 1) % 2]
+            u = u_list[W + K - 1] if u_list is not None else u_static
+            burst_ms = s.time_transport(a[0], a[1], b[0], b[1], u=u, sigma_out=sig,
+                                        reps=burst_reps)
 
     ms_per_step = ms_total / K
     traffic = measured_traffic(cfg["name"])
     value = ncell * K / (ms_total * 1e-3) / 1e9
     kbytes, sbytes = algorithmic_bytes(cfg, es)
-    k_avg_ms = step_ms / max(step_n, 1)
+    k_step_ms = step_ms / max(step_n, 1)
+    k_avg_ms = burst_ms if burst_ms is not None else k_step_ms
     achieved = kbytes * ncell / (k_avg_ms * 1e-3) / 1e9
     step_gbs = sbytes * ncell / (ms_per_step * 1e-3) / 1e9
     out = {
@@ -260,12 +284,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["name"], "cells": ncell, "dt": cfg["dt"],
                    "hj_sweeps_per_step": prob["hj_iters_step"] if vofs is not None else 0,
-                   "graph": graph is not None},
+                   "graph": graph is not None, "pipelined_geometry": pipelined},
         "roofline": {
             "bound": "hbm", "kernel": transport_kernel(cfg),
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_cell": kbytes, "avg_launch_us": round(k_avg_ms * 1e3, 3),
+            "launch_timing": ("%d back-to-back launches between HIP events" % burst_reps
+                              if burst_ms is not None else "HIP events around each launch"),
+            "avg_launch_us_in_steps": round(k_step_ms * 1e3, 3),
             "step_bytes_per_cell": sbytes, "step_frac": round(step_gbs / HBM_PEAK_GBS, 4),
             "geometry_us_per_step": round(geom_ms / K * 1e3, 3),
         },

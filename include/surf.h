@@ -166,6 +166,41 @@ int surf_step(surf_ctx* ctx, const void* vof_next, const void* const* u,
               const void* F_in, const void* psi_in, void* F_out, void* psi_out,
               void* sigma_out, double* totals_dev);
 
+/* Pipelined moving interface (2D, weighted flux form).  The geometry of a
+ * step, chi^{n+1} from the VoF at t^{n+1} (section 2.5, as surf_step does it),
+ * depends only on that VoF and chi^n, not on the transported state, so it
+ * can run while the previous step's transport runs.  This call enqueues it
+ * on aux_stream (a HIP stream other than the context's, at the default
+ * priority) after the last transport enqueued on the context's stream has
+ * consumed the level-set buffer it overwrites; the next surf_step, which
+ * must receive the same vof_next pointer, then runs only the transport, on
+ * the context's stream, after the prepared geometry.  Typical order:
+ * surf_step(vof_1); then for n >= 1: surf_prepare_geometry(vof_{n+1}),
+ * surf_step(vof_{n+1}).  Results equal those of plain surf_step calls.
+ *   vof_next  VoF at t^{n+1}; the caller makes it ready with respect to
+ *             aux_stream and keeps it unchanged until that surf_step.
+ * Errors: SURF_EINVAL for a 3D or paper-form context, more than 16 sweeps
+ * per step, a grid below 2 (K + 2) cells per axis, null arguments or a
+ * misaligned vof_next; SURF_ESTATE without a level set or with a prepared
+ * geometry still pending.  While one is pending only surf_step (with that
+ * vof_next), surf_set_dt and the status calls are accepted; the level-set,
+ * state, force and adjoint calls return SURF_ESTATE. */
+int surf_prepare_geometry(surf_ctx* ctx, const void* vof_next, void* aux_stream);
+
+/* Measurement aid: runs only the transport kernel of surf_step (weighted
+ * form: advection, substep 2, source, equation of state and the
+ * per-workgroup reduction records; no reduction to totals, no change of the
+ * running time or status) `reps` times back to back on the context's stream
+ * with the cached level set and the same inputs, and returns the mean time
+ * of one launch between two HIP events (synchronous).  Arguments as in
+ * surf_step (without vof_next); F_out, psi_out and sigma_out are
+ * overwritten.  SURF_EINVAL for the paper flux form (which has no separate
+ * transport kernel) or reps < 1; SURF_ESTATE without a level set or with a
+ * prepared geometry pending. */
+int surf_time_transport(surf_ctx* ctx, const void* const* u, const void* F_in,
+                        const void* psi_in, void* F_out, void* psi_out, void* sigma_out,
+                        int32_t reps, double* ms_per_launch);
+
 /* Marangoni face force (section 2.4) from sigma (cell field) and the cached
  * chi: on each face along d, delta_face [ (grad sigma)_d - n_d (n . grad
  * sigma) ] with n = grad chi/|grad chi| from the face gradient (compact normal

@@ -43,6 +43,7 @@ struct surf_ctx {
   int gtiles[2];
   int ngtiles;
   int nflags;
+  uint8_t* mark;  // 2D weighted-form moving geometry: live-tile marks
   // 3D moving geometry: 16^3 tiles and the live-tile list ([0] count)
   int g3tiles[3];
   int ng3;
@@ -55,6 +56,12 @@ struct surf_ctx {
   // 3D weighted-form transport: plane-marching workgroups (strips, row
   // blocks, plane chunks)
   int c3[3], c3_nwg;
+  // pipelined moving interface (2D weighted form): the next step's geometry
+  // prepared on an auxiliary stream while this step's transport runs
+  hipEvent_t ev_pre = nullptr;     // context stream, just before a transport
+  hipEvent_t ev_geo = nullptr;     // auxiliary stream, after a prepared geometry
+  bool pre_valid = false;          // ev_pre recorded since the last prepare
+  const void* prepared = nullptr;  // VoF of the prepared geometry, or null
   bool materialized;  // chi[chi_cur] holds explicit values on every tile
   // adjoint scratch: advected state, nu, per-workgroup dtheta partials
   void* adj[4];
@@ -287,17 +294,18 @@ hipEvent_t take_event(surf_ctx* c) {
 struct Timed {
   surf_ctx* c;
   int kind;
+  hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
-  Timed(surf_ctx* cc, int k) : c(cc), kind(k) {
+  Timed(surf_ctx* cc, int k, hipStream_t s = nullptr) : c(cc), kind(k), st(s ? s : cc->stream) {
     if (c->profile) {
       a = take_event(c);
       b = take_event(c);
-      if (a) (void)hipEventRecord(a, c->stream);
+      if (a) (void)hipEventRecord(a, st);
     }
   }
   ~Timed() {
     if (c->profile && a && b) {
-      (void)hipEventRecord(b, c->stream);
+      (void)hipEventRecord(b, st);
       c->marks.push_back({a, b, kind});
     }
   }
@@ -474,50 +482,10 @@ void geo3_impl(surf_ctx* c, const void* vof) {
   c->materialized = true;
 }
 
-// Weighted form in 2D: the moving geometry as its own tile kernel (every
-// tile writes chi^{n+1}), then the column-streaming transport on the new
-// level set, then the reduction.
+// The 2D weighted-form transport kernel alone, on the context's stream.
 template <typename R>
-int col2d_impl(surf_ctx* c, const void* vof_next, const void* const* u, const void* F_in,
-               const void* psi_in, void* F_out, void* psi_out, void* sigma_out,
-               double* totals) {
-  if (vof_next) {
-    Step2dArgs<R> a{};
-    a.g = c->g;
-    a.p = make_par<R>(c);
-    a.vof = (const R*)vof_next;
-    a.chi_in = (const R*)c->chi[c->chi_cur];
-    a.chi_out = (R*)c->chi[1 - c->chi_cur];
-    a.q_in = c->q[c->chi_cur];
-    a.q_out = c->q[1 - c->chi_cur];
-    a.state = c->state;
-    a.dtau = (R)(c->grid.h / 2);
-    a.ksweeps = c->prm.hj_iters_step;
-    a.tiles[0] = c->gtiles[0];
-    a.tiles[1] = c->gtiles[1];
-    a.ntiles = c->ngtiles;
-    a.per_xcd = (c->ngtiles + 7) / 8;
-    a.diag = (c->gtiles[0] % 8) == 0 ? 1 : 0;
-    {
-      Timed tm(c, 1);
-      // pass 2 grid: at most GEO_LIVE_CAP tiles per workgroup even if every
-      // tile is live
-      int nl = GEO_LIVE_GRID;
-      while ((long long)nl * GEO_LIVE_CAP < c->ngtiles) nl *= 2;
-      const dim3 gc((c->ngtiles + 3) / 4), gl(nl);
-      if (a.ksweeps <= 8) {
-        hipLaunchKernelGGL((k_geo_classify<R, 8>), gc, dim3(256), 0, c->stream, a);
-        hipLaunchKernelGGL((k_geo_live<R, 8>), gl, dim3(GEO_WG), 0, c->stream, a);
-      } else {
-        hipLaunchKernelGGL((k_geo_classify<R, 16>), gc, dim3(256), 0, c->stream, a);
-        hipLaunchKernelGGL((k_geo_live<R, 16>), gl, dim3(GEO_WG), 0, c->stream, a);
-      }
-    }
-    c->chi_cur = 1 - c->chi_cur;
-    c->materialized = true;
-  } else {
-    materialize<R>(c);
-  }
+void col2d_transport(surf_ctx* c, const void* const* u, const void* F_in, const void* psi_in,
+                     void* F_out, void* psi_out, void* sigma_out) {
   ColArgs<R> a;
   a.g = c->g;
   a.p = make_par<R>(c);
@@ -538,10 +506,98 @@ int col2d_impl(surf_ctx* c, const void* vof_next, const void* const* u, const vo
   a.groups = c->col_groups;
   a.nwg = c->col_nwg;
   a.per_xcd = (c->col_nwg + 7) / 8;
+  if constexpr (sizeof(R) == 4) launch_col2d<R, COL_TY>(c, a, has_u, bulk);
+  else launch_col2d<R, COL_TY64>(c, a, has_u, bulk);
+}
+
+// The 3D weighted-form transport kernel alone, on the context's stream.
+template <typename R>
+void col3d_transport(surf_ctx* c, const void* const* u, const void* F_in, const void* psi_in,
+                     void* F_out, void* psi_out, void* sigma_out) {
+  Col3Args<R> a;
+  a.g = c->g;
+  a.p = make_par<R>(c);
+  a.chi = (const R*)c->chi[c->chi_cur];
+  const bool has_u = u && u[0];
+  const bool bulk = c->prm.bulk_enabled != 0;
+  for (int d = 0; d < 3; ++d) a.u[d] = has_u ? (const R*)u[d] : nullptr;
+  a.F = (const R*)F_in;
+  a.psi = (const R*)psi_in;
+  a.Fo = (R*)F_out;
+  a.Po = (R*)psi_out;
+  a.sig = (R*)sigma_out;
+  a.part = c->part;
+  a.dt = (R)c->dt;
+  a.area_dt = (R)(c->grid.h * c->grid.h * c->dt);
+  a.strips = c->c3[0];
+  a.yblocks = c->c3[1];
+  a.zchunks = c->c3[2];
+  a.nwg = c->c3_nwg;
+  a.per_xcd = (c->c3_nwg + 7) / 8;
+  if constexpr (sizeof(R) == 4) launch_col3d<R, C3_TZ>(c, a, has_u, bulk);
+  else launch_col3d<R, C3_TZ64>(c, a, has_u, bulk);
+}
+
+// Weighted-form moving geometry in 2D on `st`: the classify pass, then the
+// live tiles (every tile of chi_out ends with chi^{n+1}); chi_out becomes the
+// current level set.
+template <typename R>
+void geo2d_launch(surf_ctx* c, const void* vof_next, hipStream_t st) {
+  Step2dArgs<R> a{};
+  a.g = c->g;
+  a.p = make_par<R>(c);
+  a.vof = (const R*)vof_next;
+  a.chi_in = (const R*)c->chi[c->chi_cur];
+  a.chi_out = (R*)c->chi[1 - c->chi_cur];
+  a.q_in = c->q[c->chi_cur];
+  a.q_out = c->q[1 - c->chi_cur];
+  a.mark = c->mark;
+  a.state = c->state;
+  a.dtau = (R)(c->grid.h / 2);
+  a.ksweeps = c->prm.hj_iters_step;
+  a.tiles[0] = c->gtiles[0];
+  a.tiles[1] = c->gtiles[1];
+  a.ntiles = c->ngtiles;
+  a.per_xcd = (c->ngtiles + 7) / 8;
+  a.diag = (c->gtiles[0] % 8) == 0 ? 1 : 0;
+  // live-tile grid: at most GEO_LIVE_CAP tiles per workgroup even if every
+  // tile is live
+  int nl = GEO_LIVE_GRID;
+  while ((long long)nl * GEO_LIVE_CAP < c->ngtiles) nl *= 2;
+  const dim3 gc((c->ngtiles + 3) / 4), gl(nl);
+  if (a.ksweeps <= 8) {
+    hipLaunchKernelGGL((k_geo_classify<R, 8>), gc, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_geo_live<R, 8>), gl, dim3(GEO_WG), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_geo_classify<R, 16>), gc, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_geo_live<R, 16>), gl, dim3(GEO_WG), 0, st, a);
+  }
+  c->chi_cur = 1 - c->chi_cur;
+  c->materialized = true;
+}
+
+// Weighted form in 2D: the moving geometry (unless a prepared one is already
+// current), then the column-streaming transport on the new level set, then
+// the reduction.
+template <typename R>
+int col2d_impl(surf_ctx* c, const void* vof_next, const void* const* u, const void* F_in,
+               const void* psi_in, void* F_out, void* psi_out, void* sigma_out,
+               double* totals, bool geometry_ready = false) {
+  if (vof_next && !geometry_ready) {
+    Timed tm(c, 1);
+    geo2d_launch<R>(c, vof_next, c->stream);
+  } else if (!vof_next) {
+    materialize<R>(c);
+  }
+  // the point after which a geometry for the next step may overwrite the
+  // other level-set buffer: the previous transport is done
+  if (c->ev_pre) {
+    (void)hipEventRecord(c->ev_pre, c->stream);
+    c->pre_valid = true;
+  }
   {
     Timed tm(c, 0);
-    if constexpr (sizeof(R) == 4) launch_col2d<R, COL_TY>(c, a, has_u, bulk);
-    else launch_col2d<R, COL_TY64>(c, a, has_u, bulk);
+    col2d_transport<R>(c, u, F_in, psi_in, F_out, psi_out, sigma_out);
   }
   finalize<R>(c, totals, c->col_nwg);
   return status_of_launch();
@@ -562,6 +618,7 @@ int step2d_impl(surf_ctx* c, const void* vof_next, const void* const* u, const v
   a.chi_out = (R*)c->chi[1 - c->chi_cur];
   a.q_in = c->q[c->chi_cur];
   a.q_out = c->q[1 - c->chi_cur];
+  a.mark = nullptr;
   a.has_u = (u && u[0]) ? 1 : 0;
   a.u[0] = a.has_u ? (const R*)u[0] : nullptr;
   a.u[1] = a.has_u ? (const R*)u[1] : nullptr;
@@ -606,30 +663,9 @@ int step_impl(surf_ctx* c, const void* const* u, const void* F_in, const void* p
   materialize<R>(c);
   if (c->c3_nwg > 0) {
     // weighted form in 3D: plane-marching transport, then the reduction
-    Col3Args<R> a;
-    a.g = c->g;
-    a.p = make_par<R>(c);
-    a.chi = (const R*)c->chi[c->chi_cur];
-    const bool has_u = u && u[0];
-    const bool bulk = c->prm.bulk_enabled != 0;
-    for (int d = 0; d < 3; ++d) a.u[d] = has_u ? (const R*)u[d] : nullptr;
-    a.F = (const R*)F_in;
-    a.psi = (const R*)psi_in;
-    a.Fo = (R*)F_out;
-    a.Po = (R*)psi_out;
-    a.sig = (R*)sigma_out;
-    a.part = c->part;
-    a.dt = (R)c->dt;
-    a.area_dt = (R)(c->grid.h * c->grid.h * c->dt);
-    a.strips = c->c3[0];
-    a.yblocks = c->c3[1];
-    a.zchunks = c->c3[2];
-    a.nwg = c->c3_nwg;
-    a.per_xcd = (c->c3_nwg + 7) / 8;
     {
       Timed tm(c, 0);
-      if constexpr (sizeof(R) == 4) launch_col3d<R, C3_TZ>(c, a, has_u, bulk);
-      else launch_col3d<R, C3_TZ64>(c, a, has_u, bulk);
+      col3d_transport<R>(c, u, F_in, psi_in, F_out, psi_out, sigma_out);
     }
     finalize<R>(c, totals, c->c3_nwg);
     return status_of_launch();
@@ -796,7 +832,7 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   size_t b = align_up(NSTATE * sizeof(double));
   b += align_up((size_t)npart * NPART * sizeof(double));
   b += 3 * align_up(n * es);
-  b += 2 * align_up((size_t)flag_count(grid, params) + 1);
+  b += 3 * align_up((size_t)flag_count(grid, params) + 1);
   {
     int t3[3];
     b += align_up((size_t)(geo3_tiles(grid, t3) + 1) * sizeof(int));
@@ -861,6 +897,8 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
   p += align_up((size_t)c->nflags + 1);
   c->q[1] = (uint8_t*)p;
   p += align_up((size_t)c->nflags + 1);
+  c->mark = (uint8_t*)p;
+  p += align_up((size_t)c->nflags + 1);
   c->live3 = (int*)p;
   p += align_up((size_t)(c->ng3 + 1) * sizeof(int));
 
@@ -879,6 +917,7 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
 }
 
 int surf_set_geometry(surf_ctx* c, const void* vof, int full_rebuild) {
+  if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !vof) return SURF_EINVAL;
   if (!full_rebuild && !c->has_chi) return SURF_ESTATE;
   if (c->prm.precision == SURF_F64) return geometry_impl<double>(c, vof, full_rebuild);
@@ -886,6 +925,7 @@ int surf_set_geometry(surf_ctx* c, const void* vof, int full_rebuild) {
 }
 
 int surf_set_levelset(surf_ctx* c, const void* chi) {
+  if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !chi) return SURF_EINVAL;
   size_t bytes = (size_t)c->ncell * esize(&c->prm);
   if (hipMemcpyAsync(c->chi[c->chi_cur], chi, bytes, hipMemcpyDeviceToDevice, c->stream) !=
@@ -898,6 +938,7 @@ int surf_set_levelset(surf_ctx* c, const void* chi) {
 }
 
 int surf_get_levelset(surf_ctx* c, void* chi_out) {
+  if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !chi_out) return SURF_EINVAL;
   if (!c->has_chi) return SURF_ESTATE;
   if (c->prm.precision == SURF_F64) materialize<double>(c);
@@ -911,6 +952,7 @@ int surf_get_levelset(surf_ctx* c, void* chi_out) {
 
 int surf_init_state(surf_ctx* c, const void* c0, double c0_const, double gamma0, void* F_out,
                     void* psi_out) {
+  if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !psi_out) return SURF_EINVAL;
   if (c->prm.bulk_enabled && !F_out) return SURF_EINVAL;
   if (!c->has_chi) return SURF_ESTATE;
@@ -932,6 +974,17 @@ int surf_step(surf_ctx* c, const void* vof_next, const void* const* u, const voi
   size_t es = esize(&c->prm);
   if (!aligned(psi_in, es) || !aligned(psi_out, es)) return SURF_EINVAL;
   if (!c->has_chi) return SURF_ESTATE;
+  if (c->prepared) {
+    // the geometry of this step was prepared on the auxiliary stream
+    if (vof_next != c->prepared) return SURF_ESTATE;
+    c->prepared = nullptr;
+    if (hipStreamWaitEvent(c->stream, c->ev_geo, 0) != hipSuccess) return SURF_EDEVICE;
+    if (c->prm.precision == SURF_F32)
+      return col2d_impl<float>(c, vof_next, u, F_in, psi_in, F_out, psi_out, sigma_out,
+                               totals_dev, true);
+    return col2d_impl<double>(c, vof_next, u, F_in, psi_in, F_out, psi_out, sigma_out,
+                              totals_dev, true);
+  }
   if (vof_next) {
     // 2D: the redistancing sweeps run inside tile kernels when they fit
     if (c->grid.dim == 2 && c->col_nwg > 0) {
@@ -961,7 +1014,82 @@ int surf_step(surf_ctx* c, const void* vof_next, const void* const* u, const voi
   return step_impl<float>(c, u, F_in, psi_in, F_out, psi_out, sigma_out, totals_dev);
 }
 
+int surf_time_transport(surf_ctx* c, const void* const* u, const void* F_in,
+                        const void* psi_in, void* F_out, void* psi_out, void* sigma_out,
+                        int32_t reps, double* ms_per_launch) {
+  if (!c || !psi_in || !psi_out || !ms_per_launch || reps < 1) return SURF_EINVAL;
+  const bool bulk = c->prm.bulk_enabled != 0;
+  if (bulk && (!F_in || !F_out)) return SURF_EINVAL;
+  if (psi_in == psi_out || (bulk && (F_in == F_out || F_in == psi_out || psi_in == F_out)))
+    return SURF_EINVAL;
+  if (u && u[0])
+    for (int d = 0; d < c->grid.dim; ++d)
+      if (!u[d]) return SURF_EINVAL;
+  const bool two = c->grid.dim == 2 && c->col_nwg > 0, three = c->grid.dim == 3 && c->c3_nwg > 0;
+  if (!two && !three) return SURF_EINVAL;
+  if (!c->has_chi || c->prepared) return SURF_ESTATE;
+  const bool f32 = c->prm.precision == SURF_F32;
+  if (f32) materialize<float>(c);
+  else materialize<double>(c);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return SURF_EDEVICE;
+  }
+  int rc = SURF_OK;
+  if (hipEventRecord(e0, c->stream) != hipSuccess) rc = SURF_EDEVICE;
+  for (int r = 0; r < reps && rc == SURF_OK; ++r) {
+    if (two) {
+      if (f32) col2d_transport<float>(c, u, F_in, psi_in, F_out, psi_out, sigma_out);
+      else col2d_transport<double>(c, u, F_in, psi_in, F_out, psi_out, sigma_out);
+    } else {
+      if (f32) col3d_transport<float>(c, u, F_in, psi_in, F_out, psi_out, sigma_out);
+      else col3d_transport<double>(c, u, F_in, psi_in, F_out, psi_out, sigma_out);
+    }
+  }
+  if (rc == SURF_OK) rc = status_of_launch();
+  float ms = 0.f;
+  if (rc == SURF_OK &&
+      (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+       hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    rc = SURF_EDEVICE;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == SURF_OK) *ms_per_launch = (double)ms / reps;
+  return rc;
+}
+
+int surf_prepare_geometry(surf_ctx* c, const void* vof_next, void* aux_stream) {
+  if (!c || !vof_next || !aux_stream) return SURF_EINVAL;
+  if (c->grid.dim != 2 || c->col_nwg == 0) return SURF_EINVAL;
+  if (c->prm.precision == SURF_F32 ? !geom2d_ok<float>(c) : !geom2d_ok<double>(c))
+    return SURF_EINVAL;
+  if (!c->has_chi || c->prepared) return SURF_ESTATE;
+  if (!aligned(vof_next, esize(&c->prm))) return SURF_EINVAL;
+  if (!c->ev_pre) {
+    if (hipEventCreateWithFlags(&c->ev_pre, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_geo, hipEventDisableTiming) != hipSuccess)
+      return SURF_EDEVICE;
+    c->pre_valid = false;
+  }
+  hipStream_t aux = (hipStream_t)aux_stream;
+  // the other level-set buffer is free once the transport that read it is
+  // done: the point recorded before the latest transport, or else now
+  if (!c->pre_valid && hipEventRecord(c->ev_pre, c->stream) != hipSuccess) return SURF_EDEVICE;
+  c->pre_valid = false;
+  if (hipStreamWaitEvent(aux, c->ev_pre, 0) != hipSuccess) return SURF_EDEVICE;
+  {
+    Timed tm(c, 1, aux);
+    if (c->prm.precision == SURF_F32) geo2d_launch<float>(c, vof_next, aux);
+    else geo2d_launch<double>(c, vof_next, aux);
+  }
+  if (hipEventRecord(c->ev_geo, aux) != hipSuccess) return SURF_EDEVICE;
+  c->prepared = vof_next;
+  return status_of_launch();
+}
+
 int surf_force(surf_ctx* c, const void* sigma, void* const* force) {
+  if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !sigma || !force) return SURF_EINVAL;
   for (int d = 0; d < c->grid.dim; ++d)
     if (!force[d]) return SURF_EINVAL;
@@ -1016,6 +1144,7 @@ int surf_loss_weights(surf_ctx* c, const double* tot, int64_t stride, const doub
 }
 
 int surf_adjoint_seed(surf_ctx* c, const void* psi, const double* w, void* lF, void* lP) {
+  if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !psi || !w || !lP) return SURF_EINVAL;
   if (!c->prm.adjoint) return SURF_ESTATE;
   if (!c->has_chi) return SURF_ESTATE;
@@ -1037,6 +1166,7 @@ int surf_adjoint_seed(surf_ctx* c, const void* psi, const double* w, void* lF, v
 int surf_adjoint_step(surf_ctx* c, const void* const* u, const void* F, const void* psi,
                       const void* mF, const void* mP, const double* w, void* lF, void* lP,
                       double* dtheta) {
+  if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !psi || !mP || !lP || !dtheta) return SURF_EINVAL;
   if (!c->prm.adjoint || c->prm.flux_form != SURF_FLUX_WEIGHTED) return SURF_ESTATE;
   if (!c->has_chi) return SURF_ESTATE;
@@ -1052,6 +1182,7 @@ int surf_adjoint_step(surf_ctx* c, const void* const* u, const void* F, const vo
 }
 
 int surf_adjoint_c0(surf_ctx* c, const void* lF0, void* gc0) {
+  if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !lF0 || !gc0) return SURF_EINVAL;
   if (!c->has_chi) return SURF_ESTATE;
   long long n = c->ncell;
@@ -1441,6 +1572,8 @@ int surf_destroy(surf_ctx* c) {
     (void)hipEventDestroy(m.b);
   }
   for (auto e : c->pool) (void)hipEventDestroy(e);
+  if (c->ev_pre) (void)hipEventDestroy(c->ev_pre);
+  if (c->ev_geo) (void)hipEventDestroy(c->ev_geo);
   delete c;
   return SURF_OK;
 }

@@ -32,6 +32,9 @@ struct Step2dArgs {
   R* chi_out;        // moving geometry: buffer receiving chi^{n+1}
   const uint8_t* q_in;
   uint8_t* q_out;
+  uint8_t* mark;     // weighted-form moving geometry: 1 for the live tiles of
+                     // this step (read by every live-tile workgroup; never
+                     // rewritten while they scan it), 0 otherwise
   const R* u[2];
   const R* F;
   const R* psi;
@@ -714,11 +717,13 @@ constexpr int GEO_T = 16, GEO_THREADS = 256;
 //  1. k_geo_classify: one wave per tile decides from the tile's VoF and the
 //     neighbour flags of the previous step whether it stays quiescent (flag
 //     written; the clamp too unless chi_out's flag says the tile already
-//     holds it) or is live (flag Q_TODO);
-//  2. k_geo_live: a fixed grid; every workgroup ranks the Q_TODO flags (one
+//     holds it) or is live (mark 1; its flag is left to pass 2);
+//  2. k_geo_live: a fixed grid; every workgroup ranks the live marks (one
 //     coalesced pass and a prefix sum) and rebuilds the live tiles of rank
 //     b, b + G, ... with tile_geometry (1024 threads: 16 waves overlap each
-//     sweep's LDS and barrier latency).
+//     sweep's LDS and barrier latency), which writes their flags.  The marks
+//     live apart from the flags: workgroups that start late (the pass may
+//     share the GPU with a transport) must rank the same marks as the first.
 template <typename R, int KH>
 __global__ void __launch_bounds__(256) k_geo_classify(Step2dArgs<R> a) {
   using T = Tile2<KH, GEO_T, GEO_T>;
@@ -776,7 +781,7 @@ __global__ void __launch_bounds__(256) k_geo_classify(Step2dArgs<R> a) {
       // the VoF changed under a tile whose whole neighbourhood was
       // quiescent: the interface moved farther than the clamp in one step
       if (nb_quiet) atomicOr((unsigned*)(a.state + S_FLAGS), (unsigned)STATUS_GEOM_JUMP);
-      a.q_out[t] = (uint8_t)Q_TODO;
+      a.mark[t] = 1;  // its flag in q_out is written by the live-tile pass
     }
     return;
   }
@@ -786,7 +791,10 @@ __global__ void __launch_bounds__(256) k_geo_classify(Step2dArgs<R> a) {
     for (int k = 0; k < CPL; ++k)
       if (in[k]) a.chi_out[ci[k]] = v;
   }
-  if (lane == 0) a.q_out[t] = (uint8_t)want;
+  if (lane == 0) {
+    a.q_out[t] = (uint8_t)want;
+    a.mark[t] = 0;
+  }
 }
 
 // Pass 2 ranks the tiles marked by pass 1 itself: each of its 1024 threads
@@ -811,16 +819,16 @@ __global__ void __launch_bounds__(GEO_WG) k_geo_live(Step2dArgs<R> a) {
     int cnt = 0;
     uint8_t f[4];
     if (t0 + 3 < nt) {
-      // four flags in one aligned word (t0 is a multiple of 4)
-      const unsigned w = *(const unsigned*)(a.q_out + t0);
+      // four marks in one aligned word (t0 is a multiple of 4)
+      const unsigned w = *(const unsigned*)(a.mark + t0);
 #pragma unroll
       for (int k = 0; k < 4; ++k) f[k] = (uint8_t)(w >> (8 * k));
     } else {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) f[k] = t0 + k < nt ? a.q_out[t0 + k] : (uint8_t)0;
+      for (int k = 0; k < 4; ++k) f[k] = t0 + k < nt ? a.mark[t0 + k] : (uint8_t)0;
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) cnt += f[k] == Q_TODO ? 1 : 0;
+    for (int k = 0; k < 4; ++k) cnt += f[k] == 1 ? 1 : 0;
     // inclusive prefix of cnt over the wave (shuffles), then over the waves
     int inc = cnt;
 #pragma unroll
@@ -835,7 +843,7 @@ __global__ void __launch_bounds__(GEO_WG) k_geo_live(Step2dArgs<R> a) {
     int rank = before + inc - cnt;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (f[k] != Q_TODO) continue;
+      if (f[k] != 1) continue;
       if (rank % G == b) {
         const int m = atomicAdd(&sNum, 1);  // LDS counter; order restored below
         if (m < GEO_LIVE_CAP) sMine[m] = t0 + k;

@@ -31,7 +31,8 @@ ERRORS = {0: "ok", -1: "invalid argument", -2: "workspace too small",
 
 EXPORTS = [
     "surf_workspace_bytes", "surf_init", "surf_set_geometry", "surf_set_levelset",
-    "surf_get_levelset", "surf_init_state", "surf_step", "surf_force", "surf_set_dt",
+    "surf_get_levelset", "surf_init_state", "surf_step", "surf_prepare_geometry",
+    "surf_time_transport", "surf_force", "surf_set_dt",
     "surf_get_status", "surf_clear_status", "surf_destroy", "surf_strerror", "surf_version",
     "surf_profile_enable", "surf_profile_read", "surf_set_kinetics", "surf_loss_weights",
     "surf_adjoint_seed", "surf_adjoint_step", "surf_adjoint_c0",
@@ -86,6 +87,9 @@ def lib():
         L.surf_init_state.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp]
         L.surf_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.surf_force.argtypes = [vp, vp, vp]
+        L.surf_prepare_geometry.argtypes = [vp, vp, vp]
+        L.surf_time_transport.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_double)]
         L.surf_set_dt.argtypes = [vp, ctypes.c_double]
         L.surf_get_status.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
         L.surf_clear_status.argtypes = [vp]
@@ -242,6 +246,27 @@ class Surf:
                                      _ptr(self._cell(psi_out, "psi_out")),
                                      _ptr(self._cell(sigma_out, "sigma_out")), _ptr(totals)),
                     "surf_step")
+
+    def prepare_geometry(self, vof_next, stream):
+        """Enqueues the next step's geometry on `stream` (a torch stream other
+        than the context's); the next step() must get the same vof_next."""
+        self._check(self.L.surf_prepare_geometry(self.ctx, _ptr(self._cell(vof_next, "vof_next")),
+                                                 ctypes.c_void_p(stream.cuda_stream)),
+                    "surf_prepare_geometry")
+
+    def time_transport(self, F_in, psi_in, F_out, psi_out, u=None, sigma_out=None, reps=100):
+        """Mean milliseconds of one transport-kernel launch over `reps`
+        back-to-back launches (outputs overwritten; state untouched)."""
+        ua = self._faces(u, "u")
+        ms = ctypes.c_double(0.0)
+        self._check(self.L.surf_time_transport(self.ctx, ua, _ptr(self._cell(F_in, "F_in")),
+                                               _ptr(self._cell(psi_in, "psi_in")),
+                                               _ptr(self._cell(F_out, "F_out")),
+                                               _ptr(self._cell(psi_out, "psi_out")),
+                                               _ptr(self._cell(sigma_out, "sigma_out")),
+                                               int(reps), ctypes.byref(ms)),
+                    "surf_time_transport")
+        return ms.value
 
     def force(self, sigma):
         out = [torch.empty(self.face_shape(d), dtype=self.dtype, device=self.device)
