@@ -180,7 +180,8 @@ def main():
         if cfg.get("u_seq"):
             u_list = [[tens(x) for x in (cfg["u_seq_dev"](k, dev) if dev_gen else cfg["u_seq"](k))]
                       for k in range(W + K)]
-        c0 = tens(cfg["c0"]()) if cfg.get("c0") else None
+        c0v = cfg["c0"]() if cfg.get("c0") else None  # None: constant c0 (or no bulk)
+        c0 = tens(c0v) if c0v is not None else None
         bulk = prob.get("bulk_enabled", 1)
         bufs = [[s.empty() if bulk else None, s.empty()] for _ in range(2)]
         sig = s.empty()
