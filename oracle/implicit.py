@@ -1,0 +1,171 @@
+"""FP64 oracle of the implicit substep 2 (section 3, second substep of the
+split; Appendix C), weighted flux form.
+
+TEST INFRASTRUCTURE ONLY: the tests and the CPU-baseline leg of the
+benchmark may import this module; the product path never does.  It shares no
+code with the HIP library; it reuses the C oracle (``oracle.py``) for the
+cell geometry and the explicit advection of substep 1.
+
+The step (section 3: Lie split; Appendix C: implicit Euler for substep 2):
+
+    xi*     = advection of xi^n over dt                         (substep 1)
+    (xi^{n+1} - xi*) / dt = div(flux(xi^{n+1})) +/- q^{n+1}     (substep 2)
+
+with the weighted-form flux through a face, D wbar (r_R - r_L) / h, where
+r = xi / (w + eta_w) is the carrier quotient (c = F/(phi + eta) for the
+bulk, Gamma = psi/(delta + eta/eps) for the interface), wbar the mean of w
+over the face (w = phi or delta), and no diffusive flux through walls and
+open sides.  In terms of r the flux divergence is -K r with K the symmetric
+face-weighted graph Laplacian
+
+    K[L,L] += k, K[R,R] += k, K[L,R] -= k, K[R,L] -= k,  k = D wbar / h^2
+
+for every face that carries flux.  The source q = k_a c (Gamma_inf delta -
+psi) - k_d psi (Langmuir; Henry drops psi in the adsorption term) couples the
+two fields; Appendix C recasts each equation as a linear elliptic problem
+whose reaction coefficient holds the other field at t^{n+1}.  Those two
+problems are solved alternately (Picard sweeps, the interfacial one first):
+
+    interface:  [ (delta+eta/eps)(1/dt + kl k_a c + k_d) + K_s ] Gamma
+                    = psi*/dt + k_a c Gamma_inf delta
+    bulk:       [ (phi+eta)/dt + k_a (Gamma_inf delta - kl psi) + K_b ] c
+                    = F*/dt + k_d psi
+
+(kl = 1 Langmuir, 0 Henry), starting from c = c*.  Each linear problem is
+solved exactly (a sparse direct solve).  After `picard` sweeps:
+F = (phi+eta) c, psi = (delta+eta/eps) Gamma, sigma = sigma(psi/(delta+eta/eps)).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import oracle as O
+
+
+def laplacian(q, w, D):
+    """K (N x N, CSR) for face weights w (cell field, [nz][ny][nx])."""
+    nx, ny, nz = q["n"]
+    N = nx * ny * nz
+    idx = np.arange(N).reshape(nz, ny, nx)
+    rows, cols, vals = [], [], []
+    bc = list(q["bc"]) + [(0, 0)] * (3 - len(q["bc"]))
+    for d in range(q["dim"]):
+        ax = 2 - d  # numpy axis of grid axis d
+        per = bc[d][0] == O.BC_PERIODIC
+        L = idx
+        R = np.roll(idx, -1, axis=ax)  # right neighbour (wrapped)
+        wL = w
+        wR = np.roll(w, -1, axis=ax)
+        k = D * 0.5 * (wL + wR) / (q["h"] ** 2)
+        if not per:
+            # the face between the last cell and the wrapped first one is a
+            # side: no flux
+            sl = [slice(None)] * 3
+            sl[ax] = slice(0, q["n"][d] - 1)
+            L, R, k = L[tuple(sl)], R[tuple(sl)], k[tuple(sl)]
+        L, R, k = L.ravel(), R.ravel(), k.ravel()
+        rows += [L, R, L, R]
+        cols += [L, R, R, L]
+        vals += [k, k, -k, -k]
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = np.concatenate(vals)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
+
+
+def implicit_step(prob, chi, u, F, psi, dt, picard=3, totals=None):
+    """One step with substep 2 implicit.  Returns (F, psi, sigma, totals);
+    totals follow the explicit step's layout, with the next stable dt taken
+    from the advective bound only (substep 2 has none)."""
+    q = O.full(prob)
+    assert q["flux_form"] == 0, "the weighted flux form"
+    shp = O.shape(prob)
+    N = int(np.prod(shp))
+    phi, om, de = O.cell_geometry(prob, chi)
+    bulk = bool(q["bulk_enabled"])
+    if u is not None:
+        Fs, outF = O.advect(prob, u, F, dt) if bulk else (np.array(F, dtype=np.float64), 0.0)
+        Ps, outP = O.advect(prob, u, psi, dt)
+    else:
+        Fs, outF = np.array(F, dtype=np.float64), 0.0
+        Ps, outP = np.array(psi, dtype=np.float64), 0.0
+    dF = phi + q["eta"]
+    dP = de + q["eta"] / q["eps"]
+    kl = 1.0 if q["kinetics"] == 0 else 0.0
+    ka, kd, ginf = (q["k_a"], q["k_d"], q["gamma_inf"]) if bulk else (0.0, 0.0, 0.0)
+    Kb = laplacian(q, phi, q["D_b"])
+    Ks = laplacian(q, de, q["D_s"])
+    c = (Fs / dF).ravel()
+    G = (Ps / dP).ravel()
+    dFv, dPv, dev = dF.ravel(), dP.ravel(), de.ravel()
+    Fsv, Psv = Fs.ravel(), Ps.ravel()
+    for _ in range(max(1, picard) if bulk else 1):
+        # interfacial problem with c at its latest value
+        A = Ks + sp.diags(dPv * (1.0 / dt + kl * ka * c + kd))
+        G = spla.spsolve(A.tocsc(), Psv / dt + ka * c * ginf * dev)
+        if not bulk:
+            break
+        psi_new = dPv * G
+        # bulk problem with the new psi
+        A = Kb + sp.diags(dFv / dt + ka * (ginf * dev - kl * psi_new))
+        c = spla.spsolve(A.tocsc(), Fsv / dt + kd * psi_new)
+    Fo = (dFv * c).reshape(shp) if bulk else np.array(F, dtype=np.float64)
+    Po = (dPv * G).reshape(shp)
+    S = O.eos(prob, Po / dP)
+    tot = np.zeros(16) if totals is None else np.array(totals, dtype=np.float64)
+    vol = q["h"] ** q["dim"]
+    mb = math.fsum((Fo * vol).ravel()) if bulk else 0.0
+    ms = math.fsum((Po * vol).ravel())
+    sd = math.fsum((de * vol).ravel())
+    ssd = math.fsum((S * de * vol).ravel())
+    su = 0.0
+    if u is not None:
+        s = np.zeros(shp)
+        for d in range(q["dim"]):
+            ud = np.asarray(u[d], dtype=np.float64)
+            ax = 2 - d
+            lo = [slice(None)] * 3
+            hi = [slice(None)] * 3
+            lo[ax] = slice(0, q["n"][d])
+            hi[ax] = slice(1, q["n"][d] + 1)
+            s += np.abs(0.5 * (ud[tuple(lo)] + ud[tuple(hi)]))
+        su = float(s.max())
+    out = outF + outP
+    outcum = tot[O.T_OUTCUM] + out
+    dta = q["cfl_adv"] * q["h"] / su if su > 0 else math.inf
+    cc = Fo / dF
+    tot[O.T_MB] = mb
+    tot[O.T_MS] = ms
+    tot[O.T_OUT] = out
+    tot[O.T_OUTCUM] = outcum
+    tot[O.T_SDELTA] = sd
+    tot[O.T_SSIGD] = ssd
+    tot[O.T_SU] = su
+    tot[O.T_DTNEXT] = dta
+    tot[O.T_MINF] = float(Fo.min()) if bulk else 0.0
+    tot[O.T_MINPSI] = float(Po.min())
+    tot[O.T_NBAD] = float(np.count_nonzero(~np.isfinite(Fo) | ~np.isfinite(Po) | ~np.isfinite(S)))
+    tot[O.T_T] = tot[O.T_T] + dt
+    tot[O.T_GAVG] = ms / sd
+    tot[O.T_SAVG] = ssd / sd
+    tot[O.T_MTOT] = mb + ms + outcum
+    tot[O.T_CMAX] = float(cc.max()) if bulk else 0.0
+    return Fo, Po, S, tot
+
+
+def run(prob, chi, u, F, psi, dt, nsteps, vof_seq=None, hj_iters=8, picard=3):
+    """nsteps implicit steps (the level set warm-started from vof_seq(n)
+    before step n when given).  Returns (chi, F, psi, sigma, totals history)."""
+    tot = np.zeros(16)
+    hist = []
+    S = None
+    for n in range(nsteps):
+        if vof_seq is not None:
+            chi = O.geometry(prob, vof_seq(n), hj_iters, chi=chi)
+        F, psi, S, tot = implicit_step(prob, chi, u, F, psi, dt, picard=picard, totals=tot)
+        hist.append(tot.copy())
+    return chi, F, psi, S, np.array(hist)
