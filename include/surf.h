@@ -59,6 +59,11 @@ enum { SURF_F32 = 0, SURF_F64 = 1 };
 /* substep-2 flux: weighted form D wbar grad(xi/w) (default) or the paper's
  * centred-diffusion + upwind anti-diffusion form (section 3.2) */
 enum { SURF_FLUX_WEIGHTED = 0, SURF_FLUX_PAPER = 1 };
+/* substep 2 in time: explicit Euler from the advected state (default), or
+ * implicit Euler (section 3, Appendix C; weighted flux form only), with the
+ * interfacial and bulk problems solved alternately by Jacobi-preconditioned
+ * conjugate gradients in FP64 */
+enum { SURF_SUBSTEP2_EXPLICIT = 0, SURF_SUBSTEP2_IMPLICIT = 1 };
 /* exchange law: Langmuir J = k_a c (Gamma_inf - Gamma) - k_d Gamma
  * (section 2.6) or constant adsorption flux J = k_a c Gamma_inf - k_d Gamma
  * (section 4.3.1) */
@@ -123,6 +128,12 @@ typedef struct {
   double chi_max_eps;   /* distance clamp |chi| <= chi_max_eps * eps; 0: 12 */
   double cfl_adv, cfl_diff; /* safety factors of SURF_T_DT_NEXT; 0: 0.5, 0.8 */
   double dt;            /* time step used by surf_step (> 0)              */
+  int32_t substep2;     /* SURF_SUBSTEP2_*                                */
+  int32_t picard_iters; /* implicit: interfacial + bulk solve sweeps per step (0: 3) */
+  int32_t cg_max_iters; /* implicit: CG iterations per linear solve at most (0: 400) */
+  int32_t pad2_;
+  double cg_tol;        /* implicit: ||M^-1 r|| <= cg_tol ||x|| ends a solve,
+                         * M the Jacobi diagonal (0: 1e-12)               */
 } surf_params;
 
 /* Bytes of device workspace a context needs. */

@@ -15,6 +15,7 @@
 #include "surf_col3d.hpp"
 #include "surf_geo3d.hpp"
 #include "surf_adjoint.hpp"
+#include "surf_implicit.hpp"
 
 using namespace surf;
 
@@ -56,6 +57,9 @@ struct surf_ctx {
   // 3D weighted-form transport: plane-marching workgroups (strips, row
   // blocks, plane chunks)
   int c3[3], c3_nwg;
+  // implicit substep 2: FP64 work arrays and records
+  ImpBuf imp{};
+  int imp_nblk = 0;
   // pipelined moving interface (2D weighted form): the next step's geometry
   // prepared on an auxiliary stream while this step's transport runs
   hipEvent_t ev_pre = nullptr;     // context stream, just before a transport
@@ -144,6 +148,11 @@ int check_grid_params(const surf_grid* gr, const surf_params* p) {
   if (!(p->gamma_inf > 0)) return SURF_EINVAL;
   if (!(p->dt > 0) || !std::isfinite(p->dt)) return SURF_EINVAL;
   if (p->hj_iters_init < 0 || p->hj_iters_step < 0) return SURF_EINVAL;
+  if (p->substep2 < 0 || p->substep2 > 1) return SURF_EINVAL;
+  if (p->substep2 == SURF_SUBSTEP2_IMPLICIT &&
+      (p->flux_form != SURF_FLUX_WEIGHTED || p->adjoint || p->picard_iters < 0 ||
+       p->cg_max_iters < 0 || !(p->cg_tol >= 0)))
+    return SURF_EINVAL;
   return SURF_OK;
 }
 
@@ -154,6 +163,9 @@ surf_params with_defaults(const surf_params* in, int dim) {
   if (p.cfl_adv == 0) p.cfl_adv = 0.5;
   if (p.cfl_diff == 0) p.cfl_diff = 0.8;
   if (p.hj_iters_step == 0) p.hj_iters_step = 8;
+  if (p.picard_iters == 0) p.picard_iters = 3;
+  if (p.cg_max_iters == 0) p.cg_max_iters = 400;
+  if (p.cg_tol == 0) p.cg_tol = 1e-12;
   return p;
 }
 
@@ -434,6 +446,7 @@ FinalArgs final_of(const surf_grid& gr, const surf_params& q, int nblk, double d
                    : Dmax * (2.0 * nd / (h * h) + std::sqrt(nd) / (eps * h));
   if (f.bulk) lam += q.k_a * q.gamma_inf / eps + q.k_d;
   f.lam0 = lam;
+  f.implicit = q.substep2 == SURF_SUBSTEP2_IMPLICIT ? 1 : 0;
   return f;
 }
 
@@ -705,6 +718,70 @@ void finalize(surf_ctx* c, double* totals, int nblk) {
                      c->state, totals);
 }
 
+// Implicit substep 2 (weighted form): advection, then `picard_iters` sweeps
+// of the interfacial and bulk problems, each by Jacobi-CG, then the outputs,
+// the records and the reduction.
+template <typename R>
+void cg_solve(surf_ctx* c, const ImpArgs<R>& a, int field) {
+  const dim3 gr(c->imp_nblk), bl(IMP_BLOCK);
+  hipLaunchKernelGGL(k_cg_init<R>, gr, bl, 0, c->stream, a, field);
+  hipLaunchKernelGGL(k_cg_scal, dim3(1), dim3(CG_SCAL_THREADS), 0, c->stream, c->imp.sc,
+                     (const double*)c->imp.cgp, c->imp_nblk, 0, a.tol);
+  for (int it = 0; it < c->prm.cg_max_iters; ++it) {
+    const int pin = it & 1;
+    hipLaunchKernelGGL(k_cg_apply<R>, gr, bl, 0, c->stream, a, field, pin);
+    hipLaunchKernelGGL(k_cg_scal, dim3(1), dim3(CG_SCAL_THREADS), 0, c->stream, c->imp.sc,
+                       (const double*)c->imp.cgp, c->imp_nblk, 1, a.tol);
+    hipLaunchKernelGGL(k_cg_update<R>, gr, bl, 0, c->stream, a, field, pin ^ 1);
+    hipLaunchKernelGGL(k_cg_scal, dim3(1), dim3(CG_SCAL_THREADS), 0, c->stream, c->imp.sc,
+                       (const double*)c->imp.cgp, c->imp_nblk, 2, a.tol);
+  }
+}
+
+template <typename R>
+int implicit_impl(surf_ctx* c, const void* const* u, const void* F_in, const void* psi_in,
+                  void* F_out, void* psi_out, void* sigma_out, double* totals) {
+  materialize<R>(c);
+  ImpArgs<R> a;
+  a.g = c->g;
+  a.p = make_par<R>(c);
+  a.B = c->imp;
+  const surf_params& q = c->prm;
+  const bool bulk = q.bulk_enabled != 0;
+  a.dt = c->dt;
+  a.eta = q.eta;
+  a.eta_eps = q.eta / q.eps;
+  a.ka = bulk ? q.k_a : 0.0;
+  a.kd = bulk ? q.k_d : 0.0;
+  a.ginf = q.gamma_inf;
+  a.kl = q.kinetics == SURF_KIN_LANGMUIR ? 1.0 : 0.0;
+  a.tol = q.cg_tol;
+  a.inv_h2 = 1.0 / (c->grid.h * c->grid.h);
+  a.Db = q.D_b;
+  a.Ds = q.D_s;
+  a.bulk = bulk ? 1 : 0;
+  a.ncell = c->ncell;
+  const bool has_u = u && u[0];
+  const R area_dt = (R)((c->grid.dim == 3 ? c->grid.h * c->grid.h : c->grid.h) * c->dt);
+  const dim3 gr(c->imp_nblk), bl(IMP_BLOCK);
+  {
+    Timed tm(c, 0);
+    hipLaunchKernelGGL(k_imp_adv<R>, gr, bl, 0, c->stream, a, (const R*)c->chi[c->chi_cur],
+                       has_u ? (const R*)u[0] : nullptr, has_u ? (const R*)u[1] : nullptr,
+                       (has_u && c->grid.dim == 3) ? (const R*)u[2] : nullptr,
+                       (const R*)F_in, (const R*)psi_in, area_dt);
+    const int sweeps = bulk ? q.picard_iters : 1;
+    for (int s = 0; s < sweeps; ++s) {
+      cg_solve<R>(c, a, 0);
+      if (bulk) cg_solve<R>(c, a, 1);
+    }
+    hipLaunchKernelGGL(k_imp_final<R>, gr, bl, 0, c->stream, a, (R*)F_out, (R*)psi_out,
+                       (R*)sigma_out, c->part);
+  }
+  finalize<R>(c, totals, c->imp_nblk);
+  return status_of_launch();
+}
+
 template <typename R>
 int init_impl(surf_ctx* c, const void* c0, double c0_const, double gamma0, void* F, void* psi) {
   materialize<R>(c);
@@ -828,6 +905,9 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   npart = ncol > npart ? ncol : npart;
   npart = nc3 > npart ? nc3 : npart;
   size_t n = (size_t)grid->n[0] * grid->n[1] * grid->n[2];
+  const bool imp = params->substep2 == SURF_SUBSTEP2_IMPLICIT;
+  const int nimp = imp ? (int)((n + IMP_BLOCK - 1) / IMP_BLOCK) : 0;
+  npart = nimp > npart ? nimp : npart;
   size_t es = esize(params);
   size_t b = align_up(NSTATE * sizeof(double));
   b += align_up((size_t)npart * NPART * sizeof(double));
@@ -842,6 +922,10 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   if (params->adjoint) {
     b += 4 * align_up(n * es);
     b += align_up((size_t)((n + BLOCK - 1) / BLOCK) * NADJ * sizeof(double));
+  }
+  if (imp) {
+    b += IMP_FIELDS * align_up(n * sizeof(double));
+    b += align_up((size_t)nimp * 6 * sizeof(double)) + align_up(SC_N * sizeof(double));
   }
   *bytes = b;
   return SURF_OK;
@@ -881,6 +965,9 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
   int npart = c->nblk > c->ntiles2d ? c->nblk : c->ntiles2d;
   npart = c->col_nwg > npart ? c->col_nwg : npart;
   npart = c->c3_nwg > npart ? c->c3_nwg : npart;
+  const bool imp = params->substep2 == SURF_SUBSTEP2_IMPLICIT;
+  c->imp_nblk = imp ? (int)((c->ncell + IMP_BLOCK - 1) / IMP_BLOCK) : 0;
+  npart = c->imp_nblk > npart ? c->imp_nblk : npart;
   size_t es = esize(params);
   char* p = c->ws;
   c->state = (double*)p;
@@ -908,6 +995,21 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
     if (params->adjoint) p += align_up(c->ncell * es);
   }
   c->adj_part = params->adjoint ? (double*)p : nullptr;
+  if (params->adjoint) p += align_up((size_t)((c->ncell + BLOCK - 1) / BLOCK) * NADJ * sizeof(double));
+  if (imp) {
+    double** f[IMP_FIELDS] = {&c->imp.Fs, &c->imp.Ps, &c->imp.wF, &c->imp.wP, &c->imp.xF,
+                              &c->imp.xP, &c->imp.dg, &c->imp.minv, &c->imp.r, &c->imp.z,
+                              &c->imp.p[0], &c->imp.p[1], &c->imp.q};
+    for (auto a : f) {
+      *a = (double*)p;
+      p += align_up((size_t)c->ncell * sizeof(double));
+    }
+    c->imp.adv = (double*)p;
+    c->imp.cgp = c->imp.adv + 2 * (size_t)c->imp_nblk;
+    p += align_up((size_t)c->imp_nblk * 6 * sizeof(double));
+    c->imp.sc = (double*)p;
+    p += align_up(SC_N * sizeof(double));
+  }
   c->materialized = true;
   c->chi_cur = 0;
   c->has_chi = false;
@@ -974,6 +1076,27 @@ int surf_step(surf_ctx* c, const void* vof_next, const void* const* u, const voi
   size_t es = esize(&c->prm);
   if (!aligned(psi_in, es) || !aligned(psi_out, es)) return SURF_EINVAL;
   if (!c->has_chi) return SURF_ESTATE;
+  if (c->prm.substep2 == SURF_SUBSTEP2_IMPLICIT) {
+    if (vof_next) {
+      // the level set of the new interface, as in the explicit path
+      if (c->grid.dim == 2 && c->col_nwg > 0 &&
+          (c->prm.precision == SURF_F32 ? geom2d_ok<float>(c) : geom2d_ok<double>(c))) {
+        Timed tm(c, 1);
+        if (c->prm.precision == SURF_F32) geo2d_launch<float>(c, vof_next, c->stream);
+        else geo2d_launch<double>(c, vof_next, c->stream);
+      } else if (c->prm.precision == SURF_F32 && geo3_ok<float>(c)) {
+        geo3_impl<float>(c, vof_next);
+      } else if (c->prm.precision == SURF_F64 && geo3_ok<double>(c)) {
+        geo3_impl<double>(c, vof_next);
+      } else {
+        int rc = surf_set_geometry(c, vof_next, 0);
+        if (rc) return rc;
+      }
+    }
+    if (c->prm.precision == SURF_F64)
+      return implicit_impl<double>(c, u, F_in, psi_in, F_out, psi_out, sigma_out, totals_dev);
+    return implicit_impl<float>(c, u, F_in, psi_in, F_out, psi_out, sigma_out, totals_dev);
+  }
   if (c->prepared) {
     // the geometry of this step was prepared on the auxiliary stream
     if (vof_next != c->prepared) return SURF_ESTATE;
@@ -1026,7 +1149,7 @@ int surf_time_transport(surf_ctx* c, const void* const* u, const void* F_in,
     for (int d = 0; d < c->grid.dim; ++d)
       if (!u[d]) return SURF_EINVAL;
   const bool two = c->grid.dim == 2 && c->col_nwg > 0, three = c->grid.dim == 3 && c->c3_nwg > 0;
-  if (!two && !three) return SURF_EINVAL;
+  if ((!two && !three) || c->prm.substep2 != SURF_SUBSTEP2_EXPLICIT) return SURF_EINVAL;
   if (!c->has_chi || c->prepared) return SURF_ESTATE;
   const bool f32 = c->prm.precision == SURF_F32;
   if (f32) materialize<float>(c);
@@ -1061,7 +1184,8 @@ int surf_time_transport(surf_ctx* c, const void* const* u, const void* F_in,
 
 int surf_prepare_geometry(surf_ctx* c, const void* vof_next, void* aux_stream) {
   if (!c || !vof_next || !aux_stream) return SURF_EINVAL;
-  if (c->grid.dim != 2 || c->col_nwg == 0) return SURF_EINVAL;
+  if (c->grid.dim != 2 || c->col_nwg == 0 || c->prm.substep2 != SURF_SUBSTEP2_EXPLICIT)
+    return SURF_EINVAL;
   if (c->prm.precision == SURF_F32 ? !geom2d_ok<float>(c) : !geom2d_ok<double>(c))
     return SURF_EINVAL;
   if (!c->has_chi || c->prepared) return SURF_ESTATE;

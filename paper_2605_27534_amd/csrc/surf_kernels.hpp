@@ -442,6 +442,7 @@ struct FinalArgs {
   int dim, bulk;
   double h, ka, cfl_a, cfl_d, dt;
   double lam0;  // stability rate of substep 2 without the c_max term
+  int implicit; // substep 2 implicit: only the advective bound applies
 };
 
 constexpr int FIN_BLOCK = 256;
@@ -495,8 +496,8 @@ __device__ __forceinline__ void finalize_body(const FinalArgs& f, const double* 
   double lam = f.lam0;
   if (f.bulk) lam += f.ka * (cmax > 0 ? cmax : 0.0);
   double dta = su > 0 ? f.cfl_a * f.h / su : INFINITY;
-  double dtd = f.cfl_d / lam;
-  double bound = fmin(su > 0 ? f.h / su : INFINITY, 1.0 / lam);
+  double dtd = f.implicit ? INFINITY : f.cfl_d / lam;
+  double bound = fmin(su > 0 ? f.h / su : INFINITY, f.implicit ? INFINITY : 1.0 / lam);
   unsigned status = (unsigned)state[S_STATUS] | *(const unsigned*)(state + S_FLAGS);
   if (tot[P_NBAD] > 0) status |= 1u;
   if ((f.bulk && tot[P_MIN_F] < 0) || tot[P_MIN_PSI] < 0) status |= 2u;

@@ -16,6 +16,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsurf.so")
 
 SURF_F32, SURF_F64 = 0, 1
+SURF_SUBSTEP2_EXPLICIT, SURF_SUBSTEP2_IMPLICIT = 0, 1
 FLUX_WEIGHTED, FLUX_PAPER = 0, 1
 KIN_LANGMUIR, KIN_HENRY = 0, 1
 EOS_LINEAR, EOS_LANGMUIR, EOS_TANH = 0, 1, 2
@@ -64,7 +65,10 @@ class Params(ctypes.Structure):
                 ("gamma_inf", ctypes.c_double), ("sigma0", ctypes.c_double),
                 ("eos_E", ctypes.c_double), ("eta", ctypes.c_double),
                 ("chi_max_eps", ctypes.c_double), ("cfl_adv", ctypes.c_double),
-                ("cfl_diff", ctypes.c_double), ("dt", ctypes.c_double)]
+                ("cfl_diff", ctypes.c_double), ("dt", ctypes.c_double),
+                ("substep2", ctypes.c_int32), ("picard_iters", ctypes.c_int32),
+                ("cg_max_iters", ctypes.c_int32), ("pad2_", ctypes.c_int32),
+                ("cg_tol", ctypes.c_double)]
 
 
 _lib = None
@@ -112,7 +116,8 @@ def lib():
 DEFAULTS = dict(flux_form=0, kinetics=0, eos=0, bulk_enabled=1, D_b=1e-2, D_s=1e-3,
                 k_a=1.0, k_d=1.0, gamma_inf=1.0, sigma0=1.0, eos_E=0.5, eta=1e-12,
                 chi_max_eps=12.0, cfl_adv=0.5, cfl_diff=0.8, hj_iters_init=0,
-                hj_iters_step=0, adjoint=0)
+                hj_iters_step=0, adjoint=0, substep2=0, picard_iters=0, cg_max_iters=0,
+                cg_tol=0.0)
 
 
 def make_structs(prob: dict, dt: float, precision: int):
@@ -132,10 +137,10 @@ def make_structs(prob: dict, dt: float, precision: int):
     p = Params()
     p.precision = precision
     for k in ("flux_form", "kinetics", "eos", "bulk_enabled", "hj_iters_init", "hj_iters_step",
-              "adjoint"):
+              "adjoint", "substep2", "picard_iters", "cg_max_iters"):
         setattr(p, k, int(q[k]))
     for k in ("D_b", "D_s", "k_a", "k_d", "gamma_inf", "sigma0", "eos_E", "eta",
-              "chi_max_eps", "cfl_adv", "cfl_diff"):
+              "chi_max_eps", "cfl_adv", "cfl_diff", "cg_tol"):
         setattr(p, k, float(q[k]))
     p.eps = float(q.get("eps", 1.5 * q["h"]))
     p.dt = float(dt)
