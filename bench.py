@@ -22,7 +22,11 @@ Other workloads (one JSON line each, not the default):
   c3  the 64-instance ensemble in the batched form (one persistent launch
       per step, HIP-graph replay), against the same instances stepped one by
       one with the plain path;
-  c4  the 128^3 adjoint sphere: forward steps and checkpointed adjoint steps.
+  c4  the 128^3 adjoint sphere: forward steps and checkpointed adjoint steps;
+  c1m the 1024^2 soluble expanding circle with substep 2 implicit (48 times
+      the explicit step): steps launched eagerly and replayed from a graph,
+      the CG iteration kernel timed in a burst (`roofline`), the iterations
+      of every linear solve, and the implicit oracle on a 256^2 sample.
 """
 from __future__ import annotations
 
@@ -43,7 +47,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c1", choices=["c0", "c1", "c1i", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c1",
+                    choices=["c0", "c1", "c1i", "c1m", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-pipeline", action="store_true",
@@ -151,6 +156,8 @@ def main():
         return bench_batch(args)
     if args.workload == "c4":
         return bench_adjoint(args)
+    if args.workload == "c1m":
+        return bench_implicit(args)
     import numpy as np
     import torch
     from paper_2605_27534_amd import surf as S
@@ -421,6 +428,160 @@ def bench_adjoint(args):
                        "ms_per_step": round(ms_f / N, 6)},
            "adjoint_over_forward_time": round(ms_b / ms_f, 3)}
     print(json.dumps(out), flush=True)
+
+
+CG_ITER_BYTES_PER_CELL = 13 * 8  # reads x p r w z minv dg w_face, writes x p r w z
+
+
+def bench_implicit(args):
+    """The 1024^2 soluble expanding circle with substep 2 implicit."""
+    import numpy as np
+    import torch
+    from paper_2605_27534_amd import configs as C
+    from paper_2605_27534_amd import surf as S
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    side = torch.cuda.Stream(dev)
+    K, W = args.steps, args.warmup
+    cfg = C.c1_implicit()
+    prob = dict(cfg["prob"])
+    prob["hj_iters_step"] = cfg["hj_step"]
+    ncell = int(np.prod(prob["n"]))
+    print("# generating inputs: %s, %d steps" % (cfg["name"], W + K), file=sys.stderr, flush=True)
+    with torch.cuda.stream(side):
+        s = S.Surf(prob, cfg["dt"], S.SURF_F32)
+        T = s.tensor
+        vof0 = T(cfg["vof0"]())
+        vofs = [T(cfg["vof_seq"](k)) for k in range(W + K)]
+        u = [T(x) for x in cfg["u"]()]
+        c0 = T(cfg["c0"]())
+        bufs = [[s.empty(), s.empty()] for _ in range(2)]
+        sig = s.empty()
+        hist = torch.zeros((W + K, 16), dtype=torch.float64, device=dev)
+
+        def reset():
+            s.set_geometry(vof0, full=True)
+            F, P = s.init_state(c0, 1.0, cfg["gamma0"])
+            bufs[0][0].copy_(F)
+            bufs[0][1].copy_(P)
+
+        def do_step(k):
+            a, b = bufs[k % 2], bufs[(k + 1) % 2]
+            s.step(a[0], a[1], b[0], b[1], u=u, vof_next=vofs[k], sigma_out=sig, totals=hist[k])
+
+        reset()
+        warm_iters = []
+        for k in range(W):
+            do_step(k)
+            warm_iters.append(s.solver_iterations())
+        torch.cuda.synchronize()
+        print("# warm-up solves (iterations per solve): %s" % warm_iters, file=sys.stderr, flush=True)
+        # ---- region 1: K steps launched eagerly
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        wall0 = time.perf_counter()
+        t0.record(side)
+        for k in range(W, W + K):
+            do_step(k)
+        t1.record(side)
+        side.synchronize()
+        wall = time.perf_counter() - wall0
+        ms_eager = t0.elapsed_time(t1)
+        last_iters = s.solver_iterations()
+        h1 = hist.cpu().numpy()
+        assert np.all(np.isfinite(h1[W:W + K, S.T_MTOT])), "non-finite totals"
+        status = s.status()
+        print("# eager: %.3f ms/step, status %d" % (ms_eager / K, status), file=sys.stderr,
+              flush=True)
+        # ---- region 2: the same K steps replayed from a HIP graph
+        ms_graph = None
+        if not args.no_graph:
+            reset()
+            for k in range(W):
+                do_step(k)
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=side):
+                for k in range(W, W + K):
+                    do_step(k)
+            torch.cuda.synchronize()
+            t0.record(side)
+            graph.replay()
+            t1.record(side)
+            side.synchronize()
+            ms_graph = t0.elapsed_time(t1)
+            status |= s.status()
+            del graph
+            print("# graph: %.3f ms/step" % (ms_graph / K), file=sys.stderr, flush=True)
+        # ---- region 3: the CG iteration kernel alone (bulk problem)
+        reps = 200
+        it_ms = s.time_solver(1, reps)
+    ms_total = min(ms_eager, ms_graph) if ms_graph is not None else ms_eager
+    achieved = CG_ITER_BYTES_PER_CELL * ncell / (it_ms * 1e-3) / 1e9
+    out = {
+        "metric": "surfactant-step Gcell-updates/s (+ % HBM roofline)",
+        "value": round(ncell * K / (ms_total * 1e-3) / 1e9, 4),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(ms_total / K, 6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 state, f64 solver", "data": "synthetic",
+        "config": {"workload": cfg["name"], "cells": ncell, "dt": cfg["dt"],
+                   "picard_sweeps": prob["picard_iters"], "cg_tol": prob["cg_tol"],
+                   "cg_max_iters": prob["cg_max_iters"],
+                   "timing": "graph replay" if ms_total == ms_graph else "eager launches"},
+        "ms_per_step_eager": round(ms_eager / K, 6),
+        "ms_per_step_graph": round(ms_graph / K, 6) if ms_graph is not None else None,
+        "simulated_time_per_s": round(cfg["dt"] * K / (ms_total * 1e-3), 6),
+        "solve_iterations_last_step": last_iters,
+        "solve_iterations_warmup": warm_iters,
+        "roofline": {
+            "bound": "hbm", "kernel": "k_cg_iter", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None, "bytes_per_cell": CG_ITER_BYTES_PER_CELL,
+            "avg_launch_us": round(it_ms * 1e3, 3),
+            "launch_timing": "%d back-to-back iteration launches between HIP events" % reps,
+            "cg_share_of_step": round(sum(last_iters) * it_ms / (ms_total / K), 4),
+        },
+        "status": status,
+        "wall_s": round(wall, 4),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_implicit(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_implicit(seconds):
+    """The implicit FP64 oracle (sparse direct solves), one host thread, on
+    the same workload at 256^2 (the 1024^2 factorizations take minutes)."""
+    import math
+    import numpy as np
+    from oracle import implicit as I
+    from oracle import oracle as O
+    from paper_2605_27534_amd import configs as C
+    cfg = C.c1_implicit(n=256)
+    prob = dict(cfg["prob"])
+    q = O.full(prob)
+    ncell = int(np.prod(q["n"]))
+    iters = 2 * int(math.ceil(q["chi_max_eps"] * q["eps"] / (q["h"] / q["dim"]) - 1e-9))
+    chi = O.geometry(prob, cfg["vof0"](), iters)
+    F, P = O.init_state(prob, chi, c0=cfg["c0"](), gamma0=cfg["gamma0"])
+    u = cfg["u"]()
+    tot = np.zeros(16)
+    el, k = 0.0, 0
+    while el < seconds and k < 50:
+        vk = cfg["vof_seq"](k)
+        t = time.perf_counter()
+        chi = O.geometry(prob, vk, cfg["hj_step"], chi=chi)
+        F, P, _, tot = I.implicit_step(prob, chi, u, F, P, cfg["dt"], picard=prob["picard_iters"],
+                                       totals=tot)
+        el += time.perf_counter() - t
+        k += 1
+    return {"value": round(ncell * k / el / 1e9, 6), "unit": "Gcell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "first %d steps of the same workload at 256^2 (geometry warm start + "
+                      "implicit step with sparse direct solves), FP64, one host thread, %.1f s"
+                      % (k, el)}
 
 
 def cpu_baseline(cfg, seconds):

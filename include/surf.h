@@ -54,6 +54,13 @@ extern "C" {
 #define SURF_STATUS_NONFINITE 1u /* a non-finite F, psi or sigma was produced */
 #define SURF_STATUS_NEGATIVE 2u  /* a negative F or psi was produced          */
 #define SURF_STATUS_UNSTABLE 4u  /* dt exceeded the explicit stability bound  */
+#define SURF_STATUS_GEOMETRY 8u  /* the VoF changed under a tile whose whole
+                                  * neighbourhood was outside the band: the
+                                  * interface moved farther than the clamp
+                                  * distance in one step (level set stale)   */
+#define SURF_STATUS_SOLVE 16u    /* implicit substep 2: a linear solve ended at
+                                  * cg_max_iters without meeting its test, or
+                                  * broke down (matrix not positive definite) */
 
 enum { SURF_F32 = 0, SURF_F64 = 1 };
 /* substep-2 flux: weighted form D wbar grad(xi/w) (default) or the paper's
@@ -129,8 +136,11 @@ typedef struct {
   double cfl_adv, cfl_diff; /* safety factors of SURF_T_DT_NEXT; 0: 0.5, 0.8 */
   double dt;            /* time step used by surf_step (> 0)              */
   int32_t substep2;     /* SURF_SUBSTEP2_*                                */
-  int32_t picard_iters; /* implicit: interfacial + bulk solve sweeps per step (0: 3) */
-  int32_t cg_max_iters; /* implicit: CG iterations per linear solve at most (0: 400) */
+  int32_t picard_iters; /* implicit: interfacial + bulk solve sweeps per step
+                         * (0: 3; at most 32)                            */
+  int32_t cg_max_iters; /* implicit: CG iterations per linear solve at most
+                         * (0: 400); each is one kernel launch, those after
+                         * the test is met return at once               */
   int32_t pad2_;
   double cg_tol;        /* implicit: ||M^-1 r|| <= cg_tol ||x|| ends a solve,
                          * M the Jacobi diagonal (0: 1e-12)               */
@@ -172,7 +182,12 @@ int surf_init_state(surf_ctx* ctx, const void* c0, double c0_const, double gamma
  *             u == NULL / u[0] == NULL for no flow (substep 1 skipped).
  *   sigma_out cell field or NULL; totals_dev 16 doubles (device) or NULL.
  * Inputs and outputs must not alias (ping-pong buffers).  F_in/F_out are
- * ignored (may be NULL) when the bulk is disabled. */
+ * ignored (may be NULL) when the bulk is disabled.
+ * With substep2 = SURF_SUBSTEP2_IMPLICIT (section 3, Appendix C) the step
+ * advects, then takes substep 2 by implicit Euler: picard_iters sweeps of
+ * the interfacial problem for Gamma and the bulk problem for c, each solved
+ * by CG (see cg_tol, cg_max_iters); SURF_T_DT_NEXT then holds the advective
+ * bound only and SURF_STATUS_UNSTABLE tests only that bound. */
 int surf_step(surf_ctx* ctx, const void* vof_next, const void* const* u,
               const void* F_in, const void* psi_in, void* F_out, void* psi_out,
               void* sigma_out, double* totals_dev);
@@ -212,6 +227,16 @@ int surf_time_transport(surf_ctx* ctx, const void* const* u, const void* F_in,
                         const void* psi_in, void* F_out, void* psi_out, void* sigma_out,
                         int32_t reps, double* ms_per_launch);
 
+/* Measurement aid for implicit substep 2: sets up the linear problem of
+ * `field` (0 interface, 1 bulk) from the last implicit step's advected state
+ * and iterates, and returns the mean time of `reps` back-to-back CG
+ * iteration launches between two HIP events, the stop test switched off so
+ * that every launch iterates.  It overwrites only solver work arrays: the
+ * next surf_step is unaffected.  Waits for the stream.  SURF_EINVAL for an
+ * explicit context, field 1 without a bulk or reps < 1; SURF_ESTATE before
+ * the first implicit step. */
+int surf_time_solver(surf_ctx* ctx, int32_t field, int32_t reps, double* ms_per_launch);
+
 /* Marangoni face force (section 2.4) from sigma (cell field) and the cached
  * chi: on each face along d, delta_face [ (grad sigma)_d - n_d (n . grad
  * sigma) ] with n = grad chi/|grad chi| from the face gradient (compact normal
@@ -225,6 +250,14 @@ int surf_set_dt(surf_ctx* ctx, double dt);
 /* Reads (synchronously: waits for the stream) and clears the status word. */
 int surf_get_status(surf_ctx* ctx, uint32_t* bits);
 int surf_clear_status(surf_ctx* ctx);
+
+/* Implicit substep 2: the CG iterations of each linear solve of the last
+ * surf_step, in the order they ran (interface, bulk, interface, bulk, ...;
+ * interface only without a bulk).  Writes min(cap, *count) counts to iters
+ * (host memory), *count the number of solves.  Waits for the context's
+ * stream.  SURF_EINVAL for an explicit context or null arguments,
+ * SURF_ESTATE before the first implicit step. */
+int surf_solver_iterations(surf_ctx* ctx, int32_t* iters, int32_t cap, int32_t* count);
 
 int surf_destroy(surf_ctx* ctx);
 const char* surf_strerror(int code);

@@ -32,7 +32,7 @@ def c0_static_circle():
                 vof_seq=None, u=None, c0=None, c0_const=1.0, gamma0=0.0, hj_step=8)
 
 
-def c1_expanding_circle(n=1024, soluble=True):
+def c1_expanding_circle(n=1024, soluble=True, dt=None, extra=None, name=None):
     """1024^2 FP32, open box, circle R(t) = sqrt(R0^2 + Q t / pi), R0 = 0.1,
     Q = 0.05, centred, under the 2D source flow (core radius 0.02); VoF at
     t^{n+1} each step; Gamma0 = 0.5; c0 ~ U[0.8, 1.2] (seed 1) in the liquid;
@@ -44,15 +44,32 @@ def c1_expanding_circle(n=1024, soluble=True):
                 k_a=1.0, k_d=1.0, gamma_inf=1.0, D_b=1e-2, D_s=1e-3,
                 bulk_enabled=1 if soluble else 0)
     # explicit bound at 1024^2: substep 2 limits (soluble 1.776e-5, insoluble 1.803e-4)
-    dt = (1.77e-5 if soluble else 1.80e-4) * (1024.0 / n) ** 2
+    if dt is None:
+        dt = (1.77e-5 if soluble else 1.80e-4) * (1024.0 / n) ** 2
+    prob.update(extra or {})
     Rt = lambda t: math.sqrt(R0 ** 2 + Q * t / math.pi)
-    return dict(name="expanding circle %d^2 fp32 %s" % (n, "soluble" if soluble else "insoluble"),
+    return dict(name=name or "expanding circle %d^2 fp32 %s" % (n, "soluble" if soluble else "insoluble"),
                 prob=prob, precision=0, dt=dt, steps=2000, R=Rt,
                 vof0=lambda: synth.vof_ball((n, n), h, (0.5, 0.5, 0), R0, 2),
                 vof_seq=lambda k: synth.vof_ball((n, n), h, (0.5, 0.5, 0), Rt((k + 1) * dt), 2),
                 u=lambda: synth.u_source2d((n, n), h, (0.5, 0.5, 0), Q),
                 c0=lambda: synth.uniform_field((n, n), 1, 0.8, 1.2) if soluble else None,
                 c0_const=1.0, gamma0=0.5, hj_step=8)
+
+
+def c1_implicit(n=1024, steps=100):
+    """The soluble expanding circle with substep 2 implicit (section 3,
+    Appendix C): dt = 8.5e-4 at 1024^2 (48 times the explicit step; the
+    advective bound 0.5 h / S_u with S_u = 0.562 is 8.69e-4), 3 Picard sweeps,
+    each linear solve to ||M^-1 r|| <= 1e-9 ||x||, at most 400 CG iterations;
+    100 steps."""
+    dt = 8.5e-4 * (1024.0 / n)
+    cfg = c1_expanding_circle(n, soluble=True, dt=dt,
+                              extra=dict(substep2=1, picard_iters=3, cg_tol=1e-9,
+                                         cg_max_iters=400),
+                              name="expanding circle %d^2 fp32 soluble implicit" % n)
+    cfg["steps"] = steps
+    return cfg
 
 
 def c2_translating_sphere(n=256):

@@ -60,6 +60,9 @@ struct surf_ctx {
   // implicit substep 2: FP64 work arrays and records
   ImpBuf imp{};
   int imp_nblk = 0;
+  int imp_nsolves = 0;  // linear solves of the last implicit step
+  unsigned long long* hprog = nullptr;  // CG progress words (pinned host memory)
+  unsigned long long solve_serial = 0;
   // pipelined moving interface (2D weighted form): the next step's geometry
   // prepared on an auxiliary stream while this step's transport runs
   hipEvent_t ev_pre = nullptr;     // context stream, just before a transport
@@ -151,7 +154,8 @@ int check_grid_params(const surf_grid* gr, const surf_params* p) {
   if (p->substep2 < 0 || p->substep2 > 1) return SURF_EINVAL;
   if (p->substep2 == SURF_SUBSTEP2_IMPLICIT &&
       (p->flux_form != SURF_FLUX_WEIGHTED || p->adjoint || p->picard_iters < 0 ||
-       p->cg_max_iters < 0 || !(p->cg_tol >= 0)))
+       p->picard_iters > IMP_MAX_PICARD || p->cg_max_iters < 0 || !(p->cg_tol >= 0) ||
+       ncell >= 2147483648.0))
     return SURF_EINVAL;
   return SURF_OK;
 }
@@ -721,27 +725,103 @@ void finalize(surf_ctx* c, double* totals, int nblk) {
 // Implicit substep 2 (weighted form): advection, then `picard_iters` sweeps
 // of the interfacial and bulk problems, each by Jacobi-CG, then the outputs,
 // the records and the reduction.
+//
+// CG tiling: 64 x 32-cell tiles of one z-plane; at most CG_MAXWG workgroups,
+// each taking a run of per_wg consecutive tiles.
+void cg_shape(const surf_grid* g, int* tiles, int* ntiles, int* nwg, int* per_wg) {
+  tiles[0] = (g->n[0] + CG_TX - 1) / CG_TX;
+  tiles[1] = (g->n[1] + CG_TY - 1) / CG_TY;
+  tiles[2] = g->dim == 3 ? g->n[2] : 1;
+  *ntiles = tiles[0] * tiles[1] * tiles[2];
+  int w = *ntiles < CG_MAXWG ? *ntiles : CG_MAXWG;
+  *per_wg = (*ntiles + w - 1) / w;
+  *nwg = (*ntiles + *per_wg - 1) / *per_wg;
+}
+
 template <typename R>
-void cg_solve(surf_ctx* c, const ImpArgs<R>& a, int field) {
-  const dim3 gr(c->imp_nblk), bl(IMP_BLOCK);
-  hipLaunchKernelGGL(k_cg_init<R>, gr, bl, 0, c->stream, a, field);
-  hipLaunchKernelGGL(k_cg_scal, dim3(1), dim3(CG_SCAL_THREADS), 0, c->stream, c->imp.sc,
-                     (const double*)c->imp.cgp, c->imp_nblk, 0, a.tol);
-  for (int it = 0; it < c->prm.cg_max_iters; ++it) {
-    const int pin = it & 1;
-    hipLaunchKernelGGL(k_cg_apply<R>, gr, bl, 0, c->stream, a, field, pin);
-    hipLaunchKernelGGL(k_cg_scal, dim3(1), dim3(CG_SCAL_THREADS), 0, c->stream, c->imp.sc,
-                       (const double*)c->imp.cgp, c->imp_nblk, 1, a.tol);
-    hipLaunchKernelGGL(k_cg_update<R>, gr, bl, 0, c->stream, a, field, pin ^ 1);
-    hipLaunchKernelGGL(k_cg_scal, dim3(1), dim3(CG_SCAL_THREADS), 0, c->stream, c->imp.sc,
-                       (const double*)c->imp.cgp, c->imp_nblk, 2, a.tol);
+CgArgs cg_args(surf_ctx* c, const ImpArgs<R>& a, int field) {
+  CgArgs k{};
+  k.g = c->g;
+  const bool bulk_field = field == 1;
+  k.fw = bulk_field ? c->imp.wF : c->imp.wP;
+  k.kc = 0.5 * (bulk_field ? a.Db : a.Ds) * a.inv_h2;
+  k.tol2 = a.tol * a.tol;
+  k.x = bulk_field ? c->imp.xF : c->imp.xP;
+  k.p = c->imp.p;
+  for (int i = 0; i < 2; ++i) {
+    k.r[i] = c->imp.r[i];
+    k.w[i] = c->imp.w[i];
+    k.z[i] = c->imp.z[i];
+  }
+  k.minv = c->imp.minv;
+  k.dg = c->imp.dg;
+  k.part = c->imp.part;
+  k.sc = c->imp.sc;
+  cg_shape(&c->grid, k.tiles, &k.ntiles, &k.nwg, &k.per_wg);
+  return k;
+}
+
+void cg_iter_launch(surf_ctx* c, const CgArgs& k, int it) {
+  const dim3 gr(k.nwg), bl(CG_WG);
+  if (c->grid.dim == 3) hipLaunchKernelGGL(k_cg_iter<3>, gr, bl, 0, c->stream, k, it);
+  else hipLaunchKernelGGL(k_cg_iter<2>, gr, bl, 0, c->stream, k, it);
+}
+
+// Host-paced iteration launches: chunks of CG_CHUNK, enqueued once the device
+// has started the launch CG_LEAD before the end of the queue.
+constexpr int CG_CHUNK = 4, CG_LEAD = 8;
+
+bool stream_capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+// Waits until solve `id` has met its test (1) or its device progress
+// reached `target` launches (0), or the stream ran dry (0: everything
+// enqueued has run); SURF_EDEVICE on a stream error.
+int cg_wait(surf_ctx* c, unsigned long long id, int target) {
+  volatile unsigned long long* hp = c->hprog;
+  for (unsigned spin = 0;; ++spin) {
+    if (hp[1] >= id) return 1;
+    const unsigned long long pr = hp[0];
+    if ((pr >> 32) == id && (long long)(pr & 0xffffffffull) >= target) return 0;
+    if ((spin & 63) == 63) {
+      const hipError_t q = hipStreamQuery(c->stream);
+      if (q == hipSuccess) return 0;
+      if (q != hipErrorNotReady) return SURF_EDEVICE;
+    }
   }
 }
 
 template <typename R>
-int implicit_impl(surf_ctx* c, const void* const* u, const void* F_in, const void* psi_in,
-                  void* F_out, void* psi_out, void* sigma_out, double* totals) {
-  materialize<R>(c);
+int cg_solve(surf_ctx* c, const ImpArgs<R>& a, int field, int solve, bool paced) {
+  CgArgs k = cg_args(c, a, field);
+  k.hp = c->hprog;
+  k.solve_id = ++c->solve_serial;
+  hipLaunchKernelGGL(k_cg_setup<R>, dim3(k.nwg), dim3(CG_WG), 0, c->stream, a, k, field);
+  cg_iter_launch(c, k, -1);
+  const int cap = c->prm.cg_max_iters;
+  if (!paced) {
+    for (int it = 0; it < cap; ++it) cg_iter_launch(c, k, it);
+  } else {
+    int enq = 0;
+    while (enq < cap) {
+      const int n = cap - enq < CG_CHUNK ? cap - enq : CG_CHUNK;
+      for (int j = 0; j < n; ++j) cg_iter_launch(c, k, enq + j);
+      enq += n;
+      if (enq >= cap) break;
+      const int rc = cg_wait(c, k.solve_id, enq - CG_LEAD);
+      if (rc < 0) return rc;
+      if (rc == 1) break;
+    }
+  }
+  hipLaunchKernelGGL(k_cg_end, dim3(1), dim3(CG_WG), 0, c->stream, k, cap, c->imp.rec + solve,
+                     c->state);
+  return SURF_OK;
+}
+
+template <typename R>
+ImpArgs<R> imp_args(surf_ctx* c) {
   ImpArgs<R> a;
   a.g = c->g;
   a.p = make_par<R>(c);
@@ -761,6 +841,16 @@ int implicit_impl(surf_ctx* c, const void* const* u, const void* F_in, const voi
   a.Ds = q.D_s;
   a.bulk = bulk ? 1 : 0;
   a.ncell = c->ncell;
+  return a;
+}
+
+template <typename R>
+int implicit_impl(surf_ctx* c, const void* const* u, const void* F_in, const void* psi_in,
+                  void* F_out, void* psi_out, void* sigma_out, double* totals) {
+  materialize<R>(c);
+  const ImpArgs<R> a = imp_args<R>(c);
+  const surf_params& q = c->prm;
+  const bool bulk = q.bulk_enabled != 0;
   const bool has_u = u && u[0];
   const R area_dt = (R)((c->grid.dim == 3 ? c->grid.h * c->grid.h : c->grid.h) * c->dt);
   const dim3 gr(c->imp_nblk), bl(IMP_BLOCK);
@@ -771,15 +861,53 @@ int implicit_impl(surf_ctx* c, const void* const* u, const void* F_in, const voi
                        (has_u && c->grid.dim == 3) ? (const R*)u[2] : nullptr,
                        (const R*)F_in, (const R*)psi_in, area_dt);
     const int sweeps = bulk ? q.picard_iters : 1;
+    c->imp_nsolves = bulk ? 2 * sweeps : 1;
+    // outside graph capture the host paces the iteration launches
+    const bool paced = !stream_capturing(c->stream);
+    if (paced && !c->hprog) {
+      void* hp = nullptr;
+      if (hipHostMalloc(&hp, 64, hipHostMallocCoherent) == hipSuccess) {
+        std::memset(hp, 0, 64);
+        c->hprog = (unsigned long long*)hp;
+      }
+    }
     for (int s = 0; s < sweeps; ++s) {
-      cg_solve<R>(c, a, 0);
-      if (bulk) cg_solve<R>(c, a, 1);
+      int rc = cg_solve<R>(c, a, 0, 2 * s, paced && c->hprog);
+      if (rc == SURF_OK && bulk) rc = cg_solve<R>(c, a, 1, 2 * s + 1, paced && c->hprog);
+      if (rc != SURF_OK) return rc;
     }
     hipLaunchKernelGGL(k_imp_final<R>, gr, bl, 0, c->stream, a, (R*)F_out, (R*)psi_out,
                        (R*)sigma_out, c->part);
   }
   finalize<R>(c, totals, c->imp_nblk);
   return status_of_launch();
+}
+
+template <typename R>
+int time_solver_impl(surf_ctx* c, int field, int reps, double* ms_per_launch) {
+  const ImpArgs<R> a = imp_args<R>(c);
+  CgArgs k = cg_args(c, a, field);
+  k.tol2 = 0.0;  // no stop test: every launch iterates
+  hipLaunchKernelGGL(k_cg_setup<R>, dim3(k.nwg), dim3(CG_WG), 0, c->stream, a, k, field);
+  cg_iter_launch(c, k, -1);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return SURF_EDEVICE;
+  }
+  int rc = SURF_OK;
+  if (hipEventRecord(e0, c->stream) != hipSuccess) rc = SURF_EDEVICE;
+  for (int it = 0; it < reps && rc == SURF_OK; ++it) cg_iter_launch(c, k, it);
+  if (rc == SURF_OK) rc = status_of_launch();
+  float ms = 0.f;
+  if (rc == SURF_OK &&
+      (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+       hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    rc = SURF_EDEVICE;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == SURF_OK) *ms_per_launch = (double)ms / reps;
+  return rc;
 }
 
 template <typename R>
@@ -925,7 +1053,9 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   }
   if (imp) {
     b += IMP_FIELDS * align_up(n * sizeof(double));
-    b += align_up((size_t)nimp * 6 * sizeof(double)) + align_up(SC_N * sizeof(double));
+    b += align_up((size_t)nimp * 2 * sizeof(double));
+    b += align_up((size_t)2 * CG_MAXWG * CT_N * sizeof(double));
+    b += align_up(SC_N * sizeof(double)) + align_up(IMP_MAX_SOLVES * sizeof(double));
   }
   *bytes = b;
   return SURF_OK;
@@ -997,18 +1127,22 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
   c->adj_part = params->adjoint ? (double*)p : nullptr;
   if (params->adjoint) p += align_up((size_t)((c->ncell + BLOCK - 1) / BLOCK) * NADJ * sizeof(double));
   if (imp) {
-    double** f[IMP_FIELDS] = {&c->imp.Fs, &c->imp.Ps, &c->imp.wF, &c->imp.wP, &c->imp.xF,
-                              &c->imp.xP, &c->imp.dg, &c->imp.minv, &c->imp.r, &c->imp.z,
-                              &c->imp.p[0], &c->imp.p[1], &c->imp.q};
+    double** f[IMP_FIELDS] = {&c->imp.Fs,   &c->imp.Ps,   &c->imp.wF,   &c->imp.wP,
+                              &c->imp.xF,   &c->imp.xP,   &c->imp.dg,   &c->imp.minv,
+                              &c->imp.p,    &c->imp.r[0], &c->imp.r[1], &c->imp.w[0],
+                              &c->imp.w[1], &c->imp.z[0], &c->imp.z[1]};
     for (auto a : f) {
       *a = (double*)p;
       p += align_up((size_t)c->ncell * sizeof(double));
     }
     c->imp.adv = (double*)p;
-    c->imp.cgp = c->imp.adv + 2 * (size_t)c->imp_nblk;
-    p += align_up((size_t)c->imp_nblk * 6 * sizeof(double));
+    p += align_up((size_t)c->imp_nblk * 2 * sizeof(double));
+    c->imp.part = (double*)p;
+    p += align_up((size_t)2 * CG_MAXWG * CT_N * sizeof(double));
     c->imp.sc = (double*)p;
     p += align_up(SC_N * sizeof(double));
+    c->imp.rec = (double*)p;
+    p += align_up(IMP_MAX_SOLVES * sizeof(double));
   }
   c->materialized = true;
   c->chi_cur = 0;
@@ -1182,6 +1316,15 @@ int surf_time_transport(surf_ctx* c, const void* const* u, const void* F_in,
   return rc;
 }
 
+int surf_time_solver(surf_ctx* c, int32_t field, int32_t reps, double* ms_per_launch) {
+  if (!c || !ms_per_launch || reps < 1 || field < 0 || field > 1) return SURF_EINVAL;
+  if (c->prm.substep2 != SURF_SUBSTEP2_IMPLICIT) return SURF_EINVAL;
+  if (field == 1 && !c->prm.bulk_enabled) return SURF_EINVAL;
+  if (c->imp_nsolves == 0 || c->prepared) return SURF_ESTATE;
+  if (c->prm.precision == SURF_F64) return time_solver_impl<double>(c, field, reps, ms_per_launch);
+  return time_solver_impl<float>(c, field, reps, ms_per_launch);
+}
+
 int surf_prepare_geometry(surf_ctx* c, const void* vof_next, void* aux_stream) {
   if (!c || !vof_next || !aux_stream) return SURF_EINVAL;
   if (c->grid.dim != 2 || c->col_nwg == 0 || c->prm.substep2 != SURF_SUBSTEP2_EXPLICIT)
@@ -1236,6 +1379,20 @@ int surf_get_status(surf_ctx* c, uint32_t* bits) {
     return SURF_EDEVICE;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return SURF_EDEVICE;
   *bits = (uint32_t)s;
+  return SURF_OK;
+}
+
+int surf_solver_iterations(surf_ctx* c, int32_t* iters, int32_t cap, int32_t* count) {
+  if (!c || !count || cap < 0 || (cap > 0 && !iters)) return SURF_EINVAL;
+  if (c->prm.substep2 != SURF_SUBSTEP2_IMPLICIT) return SURF_EINVAL;
+  if (c->imp_nsolves == 0) return SURF_ESTATE;
+  double rec[IMP_MAX_SOLVES];
+  if (hipMemcpyAsync(rec, c->imp.rec, c->imp_nsolves * sizeof(double), hipMemcpyDeviceToHost,
+                     c->stream) != hipSuccess)
+    return SURF_EDEVICE;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return SURF_EDEVICE;
+  *count = c->imp_nsolves;
+  for (int i = 0; i < c->imp_nsolves && i < cap; ++i) iters[i] = (int32_t)rec[i];
   return SURF_OK;
 }
 
@@ -1698,6 +1855,12 @@ int surf_destroy(surf_ctx* c) {
   for (auto e : c->pool) (void)hipEventDestroy(e);
   if (c->ev_pre) (void)hipEventDestroy(c->ev_pre);
   if (c->ev_geo) (void)hipEventDestroy(c->ev_geo);
+  if (c->hprog) {
+    // the context's kernels may still write the progress words (the
+    // stream itself may already be gone)
+    (void)hipDeviceSynchronize();
+    (void)hipHostFree(c->hprog);
+  }
   delete c;
   return SURF_OK;
 }

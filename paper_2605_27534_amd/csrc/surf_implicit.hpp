@@ -16,41 +16,67 @@
 //   bulk:       [ (phi+eta)/dt + k_a (Gamma_inf delta - kl psi) + K_b ] c
 //                   = F*/dt + k_d psi
 //
-// Each matrix is symmetric positive definite; each problem is solved by
-// Jacobi-preconditioned conjugate gradients in FP64, matrix-free, one cell
-// per thread:
+// Each matrix is symmetric; it is positive definite while its reaction
+// diagonal is positive (always for the interfacial one; for the bulk one
+// while k_a kl psi < (phi + eta)/dt + k_a Gamma_inf delta).  Each problem is
+// solved by Jacobi-preconditioned conjugate gradients in FP64, matrix-free,
+// in the Chronopoulos-Gear arrangement (one global reduction per iteration,
+// Chronopoulos and Gear, J. Comput. Appl. Math. 25, 1989):
+//
+//   r0 = b - A x0, u0 = M^-1 r0, w0 = A u0
+//   iteration i:  gamma = (r, u), delta = (w, u),
+//                 beta = gamma / gamma_prev (0 at i = 0),
+//                 alpha = gamma / (delta - beta gamma / alpha_prev)
+//                 z = w + beta z,  p = u + beta p,  x += alpha p,
+//                 r -= alpha z,  u = M^-1 r,  w = A u
+//
+// so that one kernel launch per iteration does all vector work, including
+// the matrix-vector product with the next u, which it forms at the
+// neighbours from their r, w and z.  The kernels:
 //   k_imp_adv    substep 1 into FP64 arrays, phi and delta, the starting
 //                iterates, and per-block records of the open-side outflow
 //                and the largest cell-mean velocity sum;
-//   k_cg_init    reaction diagonal, right-hand side, r = b - A x, z = M^-1 r,
-//                p = z, partial sums of r.z, z.z and x.x;
-//   k_cg_apply   p <- z + beta p and q = A p in one pass (p ping-pongs
-//                between two buffers so that neighbours read the old p),
-//                partial sums of p.q;
-//   k_cg_update  x += alpha p, r -= alpha q, z = M^-1 r, partial sums of r.z,
-//                z.z and x.x;
-//   k_cg_scal    one workgroup: the scalars alpha, beta and the convergence
-//                flag, after which every later kernel of that solve returns
-//                at once.
+//   k_cg_setup   reaction diagonal, inverse Jacobi diagonal, r0 = b - A x0;
+//   k_cg_iter    one iteration: every workgroup first reduces the previous
+//                launch's per-workgroup partial sums (the same sums in the
+//                same order, so every workgroup gets the same scalars), then
+//                updates its tiles and leaves the partial sums of gamma,
+//                delta, (u, u) and (x, x) for the next launch.  Launch -1 is
+//                the start (alpha = beta = 0 gives u0 and w0);
+//   k_cg_end     the solve's iteration count, and the status bit when it
+//                ended without meeting the test;
 //
-// The solve ends when ||M^-1 r|| <= tol ||x|| (M the Jacobi diagonal).  The
+// Each iteration launch also publishes its progress, and the end of the
+// solve, to a word of pinned host memory.  Outside graph capture the host
+// enqueues the iterations a few launches ahead of the device and stops once
+// the test is met, instead of enqueuing cg_max_iters launches of which those
+// after convergence return at once; which launches run is decided on the
+// device either way, so the results are the same.
+//   k_imp_final  F, psi, sigma and the step's reduction records.
+//
+// A solve ends when ||M^-1 r|| <= tol ||x|| (M the Jacobi diagonal).  The
 // diagonal spans many orders of magnitude (delta + eta/eps and phi + eta
 // vanish away from the interface and the liquid), so a test on ||r|| would
 // leave the cells with a small diagonal unconverged; both matrices are
 // strictly diagonally dominant, and then M^-1 r bounds the error cell by cell
-// (|e| <= |M^-1 r| / (1 - rho), rho < 1 the largest off-diagonal row sum
-// over the diagonal).
-//   k_imp_final  F, psi, sigma and the step's reduction records.
+// (|e| <= |M^-1 r| / (1 - rho), rho < 1 the largest off-diagonal row sum over
+// the diagonal).  After the test is met (or on a breakdown) every later
+// launch of that solve returns at once.
+//
+// Layout: tiles of 64 x 32 cells of one z-plane, one tile row of 64 cells
+// per wave lane set, four rows per lane held in registers with the rows
+// above and below; x-neighbours by wave shifts, the tile's edge columns
+// loaded by eight lanes and passed on; z-neighbours loaded.  Workgroups take
+// contiguous runs of tiles, consecutive runs on the same XCD.
 #pragma once
-#include "surf_kernels.hpp"
+#include "surf_col2d.hpp"
 
 namespace surf {
 
 constexpr int IMP_BLOCK = 256;
-constexpr int IMP_FIELDS = 13;  // FP64 cell arrays of ImpBuf
-constexpr int CG_SCAL_THREADS = 1024;
-enum { CG_RZ = 0, CG_ZZ, CG_XX, CG_PQ };                            // partial-sum slots
-enum { SC_RZ = 0, SC_ZZ, SC_XX, SC_ALPHA, SC_BETA, SC_DONE, SC_ITERS, SC_N = 8 };
+constexpr int IMP_FIELDS = 15;      // FP64 cell arrays of ImpBuf
+constexpr int IMP_MAX_PICARD = 32;  // Picard sweeps per step at most
+constexpr int IMP_MAX_SOLVES = 2 * IMP_MAX_PICARD;
 
 // FP64 arrays of the implicit path (one value per cell) and its records
 struct ImpBuf {
@@ -58,10 +84,11 @@ struct ImpBuf {
   double *wF, *wP;          // phi and delta: face weights and carrier denominators
   double *xF, *xP;          // c and Gamma: Picard iterates and solutions
   double *dg, *minv;        // reaction diagonal, inverse Jacobi diagonal
-  double *r, *z, *p[2], *q;
+  double *p, *r[2], *w[2], *z[2];  // CG vectors (r, w, z ping-pong by iteration)
   double* adv;              // [nblk][2]: outflow, largest velocity sum
-  double* cgp;              // [nblk][4]: CG partial sums
-  double* sc;               // [SC_N]: CG scalars
+  double* part;             // [2][CG_MAXWG][4]: CG partial sums
+  double* sc;               // CG scalars and control words
+  double* rec;              // [IMP_MAX_SOLVES]: iterations of the last step's solves
 };
 
 template <typename R>
@@ -79,20 +106,6 @@ __device__ __forceinline__ void imp_coords(const Grid& g, long long c, int* x) {
   x[0] = (int)(c % g.n[0]);
   x[1] = (int)((c / g.n[0]) % g.n[1]);
   x[2] = (int)(c / ((long long)g.n[0] * g.n[1]));
-}
-
-// The neighbour across the face on side s (-1 lo, +1 hi) along d, or -1 when
-// the face is a wall or open side (no diffusive flux).
-__device__ __forceinline__ long long imp_nbr(const Grid& g, const int* x, int d, int s) {
-  const bool per = g.bc[d][0] == BC_PERIODIC;
-  int v = x[d] + s;
-  if (v < 0 || v >= g.n[d]) {
-    if (!per) return -1;
-    v = v < 0 ? v + g.n[d] : v - g.n[d];
-  }
-  int y[3] = {x[0], x[1], x[2]};
-  y[d] = v;
-  return cell_index(g, y[0], y[1], y[2]);
 }
 
 template <int NT>
@@ -206,165 +219,306 @@ __global__ void __launch_bounds__(IMP_BLOCK) k_imp_adv(ImpArgs<R> a, const R* __
 }
 
 // ---------------------------------------------------------------- CG
-// the field's face weight, diffusivity and unknown
-struct ImpField {
-  const double* w;
-  double D;
-  double* x;
+constexpr int CG_WAVES = 8, CG_WG = 64 * CG_WAVES;  // 512 threads
+constexpr int CG_ROWS = 4;                           // rows per lane
+constexpr int CG_TX = 64, CG_TY = CG_WAVES * CG_ROWS;  // tile 64 x 32
+constexpr int CG_MAXWG = 512;  // workgroups at most: each one reduces every partial
+enum { CT_GAMMA = 0, CT_DELTA, CT_UU, CT_XX, CT_N = 4 };  // partial sums
+// scalars: (gamma, alpha) of the last two iterations by parity, control words
+enum { SC_GA = 0, SC_DONE = 4, SC_ITER = 5, SC_FAIL = 6, SC_N = 8 };
+enum { STATUS_SOLVE = 16 };  // a linear solve ended without meeting its test
+
+struct CgArgs {
+  Grid g;
+  const double* fw;  // face weight of the field (delta or phi)
+  double kc;         // D / (2 h^2): a face's coefficient is kc (w_L + w_R)
+  double tol2;
+  double* x;         // the unknown (Gamma or c)
+  double* p;
+  double* r[2];
+  double* w[2];
+  double* z[2];
+  double* minv;
+  double* dg;
+  double* part;      // [2][CG_MAXWG][CT_N]
+  double* sc;        // [SC_N]
+  // host-visible progress words (pinned host memory) or null: [0] the
+  // solve's id << 32 | launches started, [1] the id of the last solve that
+  // met its test
+  unsigned long long* hp;
+  unsigned long long solve_id;
+  int tiles[3];      // tiles along x, y, z
+  int ntiles, nwg, per_wg;
 };
 
-template <typename R>
-__device__ __forceinline__ ImpField imp_field(const ImpArgs<R>& a, int field) {
-  if (field == 0) return ImpField{a.B.wP, a.Ds, a.B.xP};
-  return ImpField{a.B.wF, a.Db, a.B.xF};
+__device__ __forceinline__ void cg_publish(unsigned long long* hp, int slot,
+                                           unsigned long long v) {
+  __hip_atomic_store(hp + slot, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// field 0: the interfacial problem, 1: the bulk problem
+__device__ __forceinline__ int cg_wrap(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+__device__ __forceinline__ int cg_clamp(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
+__device__ __forceinline__ int cg_map(int v, int n, bool per) {
+  return per ? cg_wrap(v, n) : cg_clamp(v, n);
+}
+
+// the workgroup's run of tiles: hardware workgroup b runs on XCD b mod 8;
+// the workgroups of one XCD take consecutive runs
+__device__ __forceinline__ int cg_logical_wg(int b, int nwg) {
+  const int q = nwg >> 3, rem = nwg & 7, k = b & 7;
+  return k * q + (k < rem ? k : rem) + (b >> 3);
+}
+
+// the reaction diagonal and right-hand side of cell c (field 0: interface,
+// 1: bulk), from the advected state and the other field's latest iterate
 template <typename R>
-__global__ void __launch_bounds__(IMP_BLOCK) k_cg_init(ImpArgs<R> a, int field) {
-  const long long c = (long long)blockIdx.x * IMP_BLOCK + threadIdx.x;
-  const Grid& g = a.g;
-  const ImpField fd = imp_field(a, field);
-  double v[3] = {0.0, 0.0, 0.0};
-  if (c < a.ncell) {
-    const ImpBuf& B = a.B;
-    const double inv_h2 = a.inv_h2;
-    double dg, rhs;
-    if (field == 0) {
-      const double dP = B.wP[c] + a.eta_eps, cF = a.bulk ? B.xF[c] : 0.0;
-      dg = dP * (1.0 / a.dt + a.kl * a.ka * cF + a.kd);
-      rhs = B.Ps[c] / a.dt + a.ka * cF * a.ginf * B.wP[c];
-    } else {
-      const double dF = B.wF[c] + a.eta, ps = (B.wP[c] + a.eta_eps) * B.xP[c];
-      dg = dF / a.dt + a.ka * (a.ginf * B.wP[c] - a.kl * ps);
-      rhs = B.Fs[c] / a.dt + a.kd * ps;
+__device__ __forceinline__ void cg_row(const ImpArgs<R>& a, int field, int c, double& dg,
+                                       double& rhs) {
+  const ImpBuf& B = a.B;
+  if (field == 0) {
+    const double dP = B.wP[c] + a.eta_eps, cF = a.bulk ? B.xF[c] : 0.0;
+    dg = dP * (1.0 / a.dt + a.kl * a.ka * cF + a.kd);
+    rhs = B.Ps[c] / a.dt + a.ka * cF * a.ginf * B.wP[c];
+  } else {
+    const double dF = B.wF[c] + a.eta, ps = (B.wP[c] + a.eta_eps) * B.xP[c];
+    dg = dF / a.dt + a.ka * (a.ginf * B.wP[c] - a.kl * ps);
+    rhs = B.Fs[c] / a.dt + a.kd * ps;
+  }
+}
+
+// diagonal, inverse Jacobi diagonal and r0 = b - A x0 into r[1]; p, w[1] and
+// z[0] cleared for the start launch; control words reset
+template <typename R>
+__global__ void __launch_bounds__(CG_WG) k_cg_setup(ImpArgs<R> a, CgArgs c, int field) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c.sc[SC_DONE] = 0.0;
+    c.sc[SC_ITER] = 0.0;
+    c.sc[SC_FAIL] = 0.0;
+  }
+  const Grid& g = c.g;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const bool per[3] = {g.bc[0][0] == BC_PERIODIC, g.bc[1][0] == BC_PERIODIC,
+                       g.dim == 3 && g.bc[2][0] == BC_PERIODIC};
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int L = cg_logical_wg(blockIdx.x, c.nwg);
+  const int t1 = min((L + 1) * c.per_wg, c.ntiles);
+  for (int t = L * c.per_wg; t < t1; ++t) {
+    const int tx = t % c.tiles[0], ty = (t / c.tiles[0]) % c.tiles[1];
+    const int tz = t / (c.tiles[0] * c.tiles[1]);
+    const int x = tx * CG_TX + lane;
+    for (int j = 0; j < CG_ROWS; ++j) {
+      const int y = ty * CG_TY + wv * CG_ROWS + j;
+      if (x >= nx || y >= ny) continue;
+      const int q[3] = {x, y, tz};
+      const int n = x + nx * (y + ny * tz);
+      double dg, rhs;
+      cg_row(a, field, n, dg, rhs);
+      const double xc = c.x[n], wc = c.fw[n];
+      double ax = dg * xc, m = dg;
+      for (int d = 0; d < g.dim; ++d)
+        for (int s = -1; s <= 1; s += 2) {
+          const int v = q[d] + s;
+          if (!per[d] && (v < 0 || v >= g.n[d])) continue;  // wall or open side
+          int e[3] = {q[0], q[1], q[2]};
+          e[d] = cg_wrap(v, g.n[d]);
+          const int nb = e[0] + nx * (e[1] + ny * e[2]);
+          const double k = c.kc * (wc + c.fw[nb]);
+          ax += k * (xc - c.x[nb]);
+          m += k;
+        }
+      (void)nz;
+      c.dg[n] = dg;
+      // m > 0 unless the reaction diagonal is negative enough to make the
+      // matrix indefinite; the iterations then flag a breakdown
+      c.minv[n] = 1.0 / m;
+      c.r[1][n] = rhs - ax;
+      c.p[n] = 0.0;
+      c.w[1][n] = 0.0;
+      c.z[0][n] = 0.0;
     }
-    int x[3];
-    imp_coords(g, c, x);
-    const double xc = fd.x[c], wc = fd.w[c];
-    double ax = dg * xc, m = dg;
-    for (int d = 0; d < g.dim; ++d)
-      for (int s = -1; s <= 1; s += 2) {
-        const long long nb = imp_nbr(g, x, d, s);
-        if (nb < 0) continue;
-        const double k = fd.D * 0.5 * (wc + fd.w[nb]) * inv_h2;
-        ax += k * (xc - fd.x[nb]);
-        m += k;
+  }
+}
+
+// one iteration (it >= 0) or the start launch (it = -1)
+template <int DIM>
+__global__ void __launch_bounds__(CG_WG) k_cg_iter(CgArgs c, int it) {
+  if (it >= 0 && c.sc[SC_DONE] != 0.0) return;  // uniform over the grid
+  if (c.hp && blockIdx.x == 0 && threadIdx.x == 0)
+    cg_publish(c.hp, 0, (c.solve_id << 32) | (unsigned long long)(it + 1));
+  const int par = it & 1;
+  double alpha = 0.0, beta = 0.0;
+  if (it >= 0) {
+    const double* P = c.part + (size_t)par * CG_MAXWG * CT_N;
+    double v[CT_N] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < c.nwg; b += CG_WG)
+      for (int k = 0; k < CT_N; ++k) v[k] += P[b * CT_N + k];
+    __shared__ double tot[CT_N];
+    block_sums<CG_WG>(v, CT_N, tot);
+    __syncthreads();
+    const double gam = tot[CT_GAMMA], del = tot[CT_DELTA];
+    bool done = tot[CT_UU] <= c.tol2 * tot[CT_XX];
+    bool fail = false;
+    if (!done) {
+      double den = del;
+      if (it > 0) {
+        const double* prev = c.sc + SC_GA + 2 * ((it - 1) & 1);
+        beta = gam / prev[0];
+        den = del - beta * gam / prev[1];
       }
-    const double r = rhs - ax, mi = 1.0 / m, z = r * mi;
-    B.dg[c] = dg;
-    B.minv[c] = mi;
-    B.r[c] = r;
-    B.z[c] = z;
-    B.p[0][c] = z;
-    v[CG_RZ] = r * z;
-    v[CG_ZZ] = z * z;
-    v[CG_XX] = xc * xc;
-  }
-  __shared__ double out[4];
-  block_sums<IMP_BLOCK>(v, 3, out);
-  if (threadIdx.x < 3) a.B.cgp[4 * blockIdx.x + threadIdx.x] = out[threadIdx.x];
-}
-
-// mode 0: after init; 1: after apply (alpha); 2: after update (beta, test)
-__global__ void __launch_bounds__(CG_SCAL_THREADS) k_cg_scal(double* __restrict__ sc,
-                                                            const double* __restrict__ cgp,
-                                                            int nblk, int mode, double tol) {
-  if (mode != 0 && sc[SC_DONE] != 0.0) return;  // uniform
-  double v[3] = {0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nblk; b += CG_SCAL_THREADS) {
-    if (mode == 1) {
-      v[0] += cgp[4 * b + CG_PQ];
-    } else {
-      v[0] += cgp[4 * b + CG_RZ];
-      v[1] += cgp[4 * b + CG_ZZ];
-      v[2] += cgp[4 * b + CG_XX];
+      alpha = gam / den;
+      fail = !(gam > 0.0) || !(den > 0.0) || !isfinite(alpha) || !isfinite(beta);
+    }
+    if (done || fail) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c.sc[SC_DONE] = 1.0;
+        c.sc[SC_ITER] = (double)it;
+        c.sc[SC_FAIL] = fail ? 1.0 : 0.0;
+        if (c.hp) cg_publish(c.hp, 1, c.solve_id);
+      }
+      return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      c.sc[SC_GA + 2 * par] = gam;
+      c.sc[SC_GA + 2 * par + 1] = alpha;
     }
   }
-  __shared__ double tot[4];
-  block_sums<CG_SCAL_THREADS>(v, 3, tot);
+  const double* __restrict__ r_in = c.r[par];
+  const double* __restrict__ w_in = c.w[par];
+  const double* __restrict__ z_in = c.z[par ^ 1];
+  double* __restrict__ r_out = c.r[par ^ 1];
+  double* __restrict__ w_out = c.w[par ^ 1];
+  double* __restrict__ z_out = c.z[par];
+  const double* __restrict__ minv = c.minv;
+  const double* __restrict__ fw = c.fw;
+  const Grid& g = c.g;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const bool perx = g.bc[0][0] == BC_PERIODIC, pery = g.bc[1][0] == BC_PERIODIC;
+  const bool perz = DIM == 3 && g.bc[2][0] == BC_PERIODIC;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double kc = c.kc;
+  // u of the next iteration at cell n: M^-1 (r - alpha (w + beta z))
+  auto unew = [&](int n) { return minv[n] * (r_in[n] - alpha * (w_in[n] + beta * z_in[n])); };
+  double acc[CT_N] = {0.0, 0.0, 0.0, 0.0};
+  const int L = cg_logical_wg(blockIdx.x, c.nwg);
+  const int t1 = min((L + 1) * c.per_wg, c.ntiles);
+  for (int t = L * c.per_wg; t < t1; ++t) {
+    const int tx = t % c.tiles[0], ty = (t / c.tiles[0]) % c.tiles[1];
+    const int zc = t / (c.tiles[0] * c.tiles[1]);
+    const int x0 = tx * CG_TX, x = x0 + lane, xm = min(x, nx - 1);
+    const int y0 = ty * CG_TY + wv * CG_ROWS;  // the lane's first row
+    const int zoff = ny * zc;
+    // register rows y0-1 .. y0+CG_ROWS (wrapped or clamped into the grid)
+    double u[CG_ROWS + 2], fr[CG_ROWS + 2];
+    double rold[CG_ROWS], mio[CG_ROWS], zo[CG_ROWS], ro[CG_ROWS];
+#pragma unroll
+    for (int k = 0; k < CG_ROWS + 2; ++k) {
+      const int ym = cg_map(y0 - 1 + k, ny, pery);
+      const int n = xm + nx * (ym + zoff);
+      const double r_ = r_in[n], mi = minv[n];
+      const double s = w_in[n] + beta * z_in[n];
+      const double rn = r_ - alpha * s;
+      u[k] = mi * rn;
+      fr[k] = fw[n];
+      if (k >= 1 && k <= CG_ROWS) {
+        rold[k - 1] = r_;
+        mio[k - 1] = mi;
+        zo[k - 1] = s;
+        ro[k - 1] = rn;
+      }
+    }
+    // the tile's edge columns: lane 2j fetches row j's left neighbour
+    // column, lane 2j + 1 its right one
+    const int rl = min(63, nx - 1 - x0);  // the tile's last lane inside the grid
+    const bool lex = x0 > 0 || perx, rex = x0 + CG_TX < nx || perx;
+    double ue = 0.0, fe = 0.0;
+    if (lane < 2 * CG_ROWS) {
+      const int col = (lane & 1) ? (x0 + CG_TX < nx ? x0 + CG_TX : 0) : (x0 > 0 ? x0 - 1 : nx - 1);
+      const int ym = cg_map(y0 + (lane >> 1), ny, pery);
+      const int n = col + nx * (ym + zoff);
+      ue = unew(n);
+      fe = fw[n];
+    }
+#pragma unroll
+    for (int j = 0; j < CG_ROWS; ++j) {
+      const int k = j + 1, y = y0 + j;
+      const double uc = u[k], fc = fr[k];
+      double uL = from_left(uc), fL = from_left(fc);
+      double uR = from_right(uc), fR = from_right(fc);
+      const double ueL = __shfl(ue, 2 * j), feL = __shfl(fe, 2 * j);
+      const double ueR = __shfl(ue, 2 * j + 1), feR = __shfl(fe, 2 * j + 1);
+      if (lane == 0) {
+        uL = ueL;
+        fL = feL;
+      }
+      if (lane == rl) {
+        uR = ueR;
+        fR = feR;
+      }
+      const int ym = min(y, ny - 1);
+      const int n = xm + nx * (ym + zoff);
+      const double dgc = c.dg[n], xo = c.x[n], po = c.p[n];
+      double Au = dgc * uc;
+      if (lane > 0 || lex) Au += kc * (fc + fL) * (uc - uL);
+      if (lane < rl || rex) Au += kc * (fc + fR) * (uc - uR);
+      if (y > 0 || pery) Au += kc * (fc + fr[k - 1]) * (uc - u[k - 1]);
+      if (y + 1 < ny || pery) Au += kc * (fc + fr[k + 1]) * (uc - u[k + 1]);
+      if (DIM == 3) {
+#pragma unroll
+        for (int s = -1; s <= 1; s += 2) {
+          const int zz = zc + s;
+          const int nb = xm + nx * (ym + ny * cg_map(zz, nz, perz));
+          const double un = unew(nb), fn = fw[nb];
+          if ((zz >= 0 && zz < nz) || perz) Au += kc * (fc + fn) * (uc - un);
+        }
+      }
+      const double pn = mio[j] * rold[j] + beta * po;
+      const double xn = xo + alpha * pn;
+      if (x < nx && y < ny) {
+        c.x[n] = xn;
+        c.p[n] = pn;
+        r_out[n] = ro[j];
+        z_out[n] = zo[j];
+        w_out[n] = Au;
+        acc[CT_GAMMA] += ro[j] * uc;
+        acc[CT_DELTA] += Au * uc;
+        acc[CT_UU] += uc * uc;
+        acc[CT_XX] += xn * xn;
+      }
+    }
+  }
+  __shared__ double out[CT_N];
+  block_sums<CG_WG>(acc, CT_N, out);
+  if (threadIdx.x < CT_N)
+    c.part[(size_t)(par ^ 1) * CG_MAXWG * CT_N + (size_t)L * CT_N + threadIdx.x] = out[threadIdx.x];
+}
+
+// after the solve's last launch: its iteration count into rec; the status
+// bit when it neither met the test nor stopped on it
+__global__ void __launch_bounds__(CG_WG) k_cg_end(CgArgs c, int iters, double* rec,
+                                                  double* state) {
+  const double done = c.sc[SC_DONE];
+  double v[CT_N] = {0.0, 0.0, 0.0, 0.0};
+  if (done == 0.0) {
+    const double* P = c.part + (size_t)(iters & 1) * CG_MAXWG * CT_N;
+    for (int b = threadIdx.x; b < c.nwg; b += CG_WG)
+      for (int k = 0; k < CT_N; ++k) v[k] += P[b * CT_N + k];
+  }
+  __shared__ double tot[CT_N];
+  block_sums<CG_WG>(v, CT_N, tot);
   __syncthreads();
   if (threadIdx.x != 0) return;
-  const double tol2 = tol * tol;
-  if (mode == 0) {
-    sc[SC_RZ] = tot[0];
-    sc[SC_ZZ] = tot[1];
-    sc[SC_XX] = tot[2];
-    sc[SC_BETA] = 0.0;
-    sc[SC_ALPHA] = 0.0;
-    sc[SC_ITERS] = 0.0;
-    sc[SC_DONE] = (tot[1] <= tol2 * tot[2]) ? 1.0 : 0.0;
-  } else if (mode == 1) {
-    if (tot[0] > 0.0) {
-      sc[SC_ALPHA] = sc[SC_RZ] / tot[0];
-    } else {
-      sc[SC_DONE] = 1.0;  // p = 0: nothing left to reduce
-    }
+  bool ok;
+  if (done != 0.0) {
+    *rec = c.sc[SC_ITER];
+    ok = c.sc[SC_FAIL] == 0.0;
   } else {
-    sc[SC_BETA] = sc[SC_RZ] != 0.0 ? tot[0] / sc[SC_RZ] : 0.0;
-    sc[SC_RZ] = tot[0];
-    sc[SC_ZZ] = tot[1];
-    sc[SC_XX] = tot[2];
-    sc[SC_ITERS] += 1.0;
-    if (tot[1] <= tol2 * tot[2]) sc[SC_DONE] = 1.0;
+    *rec = (double)iters;
+    ok = tot[CT_UU] <= c.tol2 * tot[CT_XX];
   }
-}
-
-template <typename R>
-__global__ void __launch_bounds__(IMP_BLOCK) k_cg_apply(ImpArgs<R> a, int field, int pin) {
-  if (a.B.sc[SC_DONE] != 0.0) return;  // uniform over the grid
-  const long long c = (long long)blockIdx.x * IMP_BLOCK + threadIdx.x;
-  const Grid& g = a.g;
-  const ImpField fd = imp_field(a, field);
-  const ImpBuf& B = a.B;
-  const double* po = B.p[pin];
-  double* pn = B.p[pin ^ 1];
-  const double beta = B.sc[SC_BETA];
-  double v[1] = {0.0};
-  if (c < a.ncell) {
-    const double inv_h2 = a.inv_h2;
-    int x[3];
-    imp_coords(g, c, x);
-    const double pc = B.z[c] + beta * po[c], wc = fd.w[c];
-    double q = B.dg[c] * pc;
-    for (int d = 0; d < g.dim; ++d)
-      for (int s = -1; s <= 1; s += 2) {
-        const long long nb = imp_nbr(g, x, d, s);
-        if (nb < 0) continue;
-        const double k = fd.D * 0.5 * (wc + fd.w[nb]) * inv_h2;
-        q += k * (pc - (B.z[nb] + beta * po[nb]));
-      }
-    pn[c] = pc;
-    B.q[c] = q;
-    v[0] = pc * q;
-  }
-  __shared__ double out[4];
-  block_sums<IMP_BLOCK>(v, 1, out);
-  if (threadIdx.x == 0) B.cgp[4 * blockIdx.x + CG_PQ] = out[0];
-}
-
-template <typename R>
-__global__ void __launch_bounds__(IMP_BLOCK) k_cg_update(ImpArgs<R> a, int field, int pcur) {
-  if (a.B.sc[SC_DONE] != 0.0) return;  // uniform over the grid
-  const long long c = (long long)blockIdx.x * IMP_BLOCK + threadIdx.x;
-  const ImpField fd = imp_field(a, field);
-  const ImpBuf& B = a.B;
-  const double alpha = B.sc[SC_ALPHA];
-  double v[3] = {0.0, 0.0, 0.0};
-  if (c < a.ncell) {
-    const double x = fd.x[c] + alpha * B.p[pcur][c];
-    const double r = B.r[c] - alpha * B.q[c];
-    const double z = r * B.minv[c];
-    fd.x[c] = x;
-    B.r[c] = r;
-    B.z[c] = z;
-    v[CG_RZ] = r * z;
-    v[CG_ZZ] = z * z;
-    v[CG_XX] = x * x;
-  }
-  __shared__ double out[4];
-  block_sums<IMP_BLOCK>(v, 3, out);
-  if (threadIdx.x < 3) B.cgp[4 * blockIdx.x + threadIdx.x] = out[threadIdx.x];
+  if (!ok) atomicOr((unsigned*)(state + S_FLAGS), (unsigned)STATUS_SOLVE);
 }
 
 // ---------------------------------------------------------------- output

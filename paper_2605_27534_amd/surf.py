@@ -21,7 +21,7 @@ FLUX_WEIGHTED, FLUX_PAPER = 0, 1
 KIN_LANGMUIR, KIN_HENRY = 0, 1
 EOS_LINEAR, EOS_LANGMUIR, EOS_TANH = 0, 1, 2
 BC_WALL, BC_PERIODIC, BC_OPEN = 0, 1, 2
-STATUS_NONFINITE, STATUS_NEGATIVE, STATUS_UNSTABLE = 1, 2, 4
+STATUS_NONFINITE, STATUS_NEGATIVE, STATUS_UNSTABLE, STATUS_GEOMETRY, STATUS_SOLVE = 1, 2, 4, 8, 16
 
 # totals slots
 T_MB, T_MS, T_OUT, T_OUTCUM, T_SDELTA, T_SSIGD, T_SU, T_DTNEXT = range(8)
@@ -34,7 +34,8 @@ EXPORTS = [
     "surf_workspace_bytes", "surf_init", "surf_set_geometry", "surf_set_levelset",
     "surf_get_levelset", "surf_init_state", "surf_step", "surf_prepare_geometry",
     "surf_time_transport", "surf_force", "surf_set_dt",
-    "surf_get_status", "surf_clear_status", "surf_destroy", "surf_strerror", "surf_version",
+    "surf_get_status", "surf_clear_status", "surf_solver_iterations", "surf_time_solver",
+    "surf_destroy", "surf_strerror", "surf_version",
     "surf_profile_enable", "surf_profile_read", "surf_set_kinetics", "surf_loss_weights",
     "surf_adjoint_seed", "surf_adjoint_step", "surf_adjoint_c0",
     "surf_batch_workspace_bytes", "surf_batch_create", "surf_batch_set_geometry",
@@ -97,6 +98,9 @@ def lib():
         L.surf_set_dt.argtypes = [vp, ctypes.c_double]
         L.surf_get_status.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
         L.surf_clear_status.argtypes = [vp]
+        L.surf_time_solver.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double)]
+        L.surf_solver_iterations.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), i32,
+                                             ctypes.POINTER(ctypes.c_int32)]
         L.surf_destroy.argtypes = [vp]
         L.surf_strerror.argtypes = [i32]
         L.surf_strerror.restype = ctypes.c_char_p
@@ -292,6 +296,21 @@ class Surf:
 
     def clear_status(self):
         self._check(self.L.surf_clear_status(self.ctx), "surf_clear_status")
+
+    def time_solver(self, field, reps):
+        """Mean ms of one CG iteration launch (implicit contexts)."""
+        ms = ctypes.c_double(0.0)
+        self._check(self.L.surf_time_solver(self.ctx, int(field), int(reps), ctypes.byref(ms)),
+                    "surf_time_solver")
+        return ms.value
+
+    def solver_iterations(self):
+        """CG iterations of each linear solve of the last implicit step."""
+        buf = (ctypes.c_int32 * 64)()
+        n = ctypes.c_int32(0)
+        self._check(self.L.surf_solver_iterations(self.ctx, buf, 64, ctypes.byref(n)),
+                    "surf_solver_iterations")
+        return [int(buf[i]) for i in range(n.value)]
 
     # -- adjoint
     def set_kinetics(self, k_a, k_d, D_b, D_s):
