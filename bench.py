@@ -24,7 +24,8 @@ Other workloads (one JSON line each, not the default):
       one with the plain path;
   c4  the 128^3 adjoint sphere: forward steps and checkpointed adjoint steps;
   c1m the 1024^2 soluble expanding circle with substep 2 implicit (48 times
-      the explicit step): steps launched eagerly and replayed from a graph,
+      the explicit step, at most 100 steps): steps launched eagerly (the host
+      paces the CG launches; --implicit-graph adds a graph replay),
       the CG iteration kernel timed in a burst (`roofline`), the iterations
       of every linear solve, and the implicit oracle on a 256^2 sample.
 """
@@ -51,6 +52,9 @@ def parse():
                     choices=["c0", "c1", "c1i", "c1m", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--implicit-graph", action="store_true",
+                    help="c1m: also replay the steps from a HIP graph (every capped CG launch "
+                         "is captured; eagerly the host stops enqueuing once a solve converged)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="2D moving interface: run each step's geometry on the step's own "
                          "stream instead of preparing it during the previous transport")
@@ -95,26 +99,37 @@ def algorithmic_bytes(cfg, es):
     return words * es, step_words * es
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_col2d_expanding_circle_1024_traffic.md")
-KERNEL_SOURCES = ("surf_common.hpp", "surf_kernels.hpp", "surf_col2d.hpp")
+# committed counter summaries (rocprofv3 FETCH_SIZE / WRITE_SIZE): the
+# workload, the file and the sources of the kernel they were taken on
+TRAFFIC = {
+    "expanding circle 1024^2 fp32 soluble": (
+        "k_col2d_expanding_circle_1024_traffic.md",
+        ("surf_common.hpp", "surf_kernels.hpp", "surf_col2d.hpp")),
+    "expanding circle 1024^2 fp32 soluble implicit": (
+        "k_cg_iter_expanding_circle_implicit_1024_traffic.md",
+        ("surf_common.hpp", "surf_kernels.hpp", "surf_col2d.hpp", "surf_implicit.hpp")),
+}
 
 
-def kernel_source_digest():
+def kernel_source_digest(sources):
     import hashlib
     hs = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2605_27534_amd", "csrc", f), "rb") as fh:
             hs.update(fh.read())
     return hs.hexdigest()[:16]
 
 
 def measured_traffic(workload_name):
-    """HBM-side bytes per launch of the fused kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or
-    None when there is none for this workload or the kernel source changed
-    since the counters were taken."""
+    """HBM-side bytes per launch of the workload's dominant kernel from the
+    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE,
+    copy-calibrated), or None when there is none for this workload or the
+    kernel source changed since the counters were taken."""
+    if workload_name not in TRAFFIC:
+        return None
+    fname, sources = TRAFFIC[workload_name]
     try:
-        txt = open(TRAFFIC_FILE).read()
+        txt = open(os.path.join(ROOT, "profiles", fname)).read()
     except OSError:
         return None
     kv = {}
@@ -122,7 +137,8 @@ def measured_traffic(workload_name):
         if line.startswith("- ") and ": " in line:
             k, v = line[2:].split(": ", 1)
             kv[k.strip()] = v.strip().strip("`")
-    if kv.get("workload") != workload_name or kv.get("kernel_source_digest") != kernel_source_digest():
+    if (kv.get("workload") != workload_name
+            or kv.get("kernel_source_digest") != kernel_source_digest(sources)):
         return None
     try:
         return float(kv["traffic_bytes_per_launch"])
@@ -442,8 +458,8 @@ def bench_implicit(args):
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     side = torch.cuda.Stream(dev)
-    K, W = args.steps, args.warmup
     cfg = C.c1_implicit()
+    K, W = min(args.steps, cfg["steps"]), args.warmup
     prob = dict(cfg["prob"])
     prob["hj_iters_step"] = cfg["hj_step"]
     ncell = int(np.prod(prob["n"]))
@@ -495,7 +511,7 @@ def bench_implicit(args):
               flush=True)
         # ---- region 2: the same K steps replayed from a HIP graph
         ms_graph = None
-        if not args.no_graph:
+        if args.implicit_graph:
             reset()
             for k in range(W):
                 do_step(k)
@@ -538,7 +554,7 @@ def bench_implicit(args):
         "roofline": {
             "bound": "hbm", "kernel": "k_cg_iter", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None, "bytes_per_cell": CG_ITER_BYTES_PER_CELL,
+            "traffic": measured_traffic(cfg["name"]), "bytes_per_cell": CG_ITER_BYTES_PER_CELL,
             "avg_launch_us": round(it_ms * 1e3, 3),
             "launch_timing": "%d back-to-back iteration launches between HIP events" % reps,
             "cg_share_of_step": round(sum(last_iters) * it_ms / (ms_total / K), 4),
