@@ -127,6 +127,14 @@ def u_rotation(n, h, centre, omega, origin=(0.0, 0.0, 0.0)):
     return [ux, uy]
 
 
+def u_uniform(n, dim, U):
+    """The same velocity U[d] on every face along d."""
+    out = zeros_faces(n, dim)
+    for d in range(dim):
+        out[d][...] = U[d]
+    return out
+
+
 def face_centres_shape(n, d):
     nx, ny, nz = (list(n) + [1, 1])[:3]
     m = [nz, ny, nx]
