@@ -25,7 +25,14 @@ build's readings too):
   unit vector of the face gradient of s: normal component (s_R - s_L)/h, each
   transverse component the mean of the two cells' centred differences (ghost
   cells mirror at walls and open sides, wrap on periodic axes),
-  n = g / max(|g|, 1e-6);
+  n = g / max(|g|, 1/2).  Continuously phi (1 - phi) grad s = eps grad phi, so
+  the flux is zeta eps grad phi (1 - 1/|grad s|): diffusion where the profile
+  is too thin, anti-diffusion where it is too wide, nothing at the equilibrium
+  |grad s| = 1.  Where s flattens (the tails, and the plateau the level-set
+  clamp leaves), a unit normal would make that anti-diffusion unbounded and
+  turn rounding into exponentially growing noise; the bound 1/2 caps it at
+  zeta eps |grad phi|, the size of the diffusion, and leaves every profile up
+  to twice the equilibrium width unchanged;
 * no regularization flux through walls and open sides;
 * s is evaluated on phi clamped into [0, 1] (so that it stays finite when
   rounding leaves phi a little outside);
@@ -109,7 +116,7 @@ def regularization_fluxes(prob, phi, zeta, vareps=VAREPS):
                 continue
             gt = 0.5 * (cd[t] + _nb(cd[t], d, 1, per[d], n[d]))
             g2 = g2 + gt * gt
-        nd = gn / np.maximum(np.sqrt(g2), 1e-6)
+        nd = gn / np.maximum(np.sqrt(g2), 0.5)
         T = np.tanh(0.5 * (s + sR) / (2.0 * eps))
         Gd = zeta * (eps * (phR - phi) / h - 0.25 * (1.0 - T * T) * nd)
         if not per[d]:
