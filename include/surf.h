@@ -71,6 +71,11 @@ enum { SURF_FLUX_WEIGHTED = 0, SURF_FLUX_PAPER = 1 };
  * interfacial and bulk problems solved alternately by Jacobi-preconditioned
  * conjugate gradients in FP64 */
 enum { SURF_SUBSTEP2_EXPLICIT = 0, SURF_SUBSTEP2_IMPLICIT = 1 };
+/* the interface: the level set rebuilt from the VoF given to every moving
+ * step (default), or the phase field phi evolved by ACDI (section 2.5, the
+ * Phase-Field method) and re-initialized from a VoF field only when one is
+ * given */
+enum { SURF_IFACE_VOF = 0, SURF_IFACE_ACDI = 1 };
 /* exchange law: Langmuir J = k_a c (Gamma_inf - Gamma) - k_d Gamma
  * (section 2.6) or constant adsorption flux J = k_a c Gamma_inf - k_d Gamma
  * (section 4.3.1) */
@@ -144,6 +149,12 @@ typedef struct {
   int32_t pad2_;
   double cg_tol;        /* implicit: ||M^-1 r|| <= cg_tol ||x|| ends a solve,
                          * M the Jacobi diagonal (0: 1e-12)               */
+  int32_t interface;    /* SURF_IFACE_*                                   */
+  int32_t pad3_;
+  double acdi_zeta;     /* ACDI velocity scale (> 0; the paper takes 1.1
+                         * times the largest speed)                      */
+  double acdi_vareps;   /* ACDI: s = eps ln((phi + ve)/(1 - phi + ve))
+                         * (0: 1e-6)                                      */
 } surf_params;
 
 /* Bytes of device workspace a context needs. */
@@ -167,6 +178,11 @@ int surf_set_levelset(surf_ctx* ctx, const void* chi);
 /* Copies the cached signed distance into chi_out (cell field). */
 int surf_get_levelset(surf_ctx* ctx, void* chi_out);
 
+/* ACDI interface: copies the phase field phi (cell field, 0 in fluid 1, 1 in
+ * the liquid) into phi_out on the context's stream.  SURF_EINVAL for a
+ * context without ACDI, SURF_ESTATE before a level set is set. */
+int surf_get_phase(surf_ctx* ctx, void* phi_out);
+
 /* Initial state F = c0 phi, psi = gamma0 delta (section 2.6, f = Gamma delta).
  * c0 is a cell field or NULL for the constant c0_const.  Resets the running
  * time, the cumulative outflow and the status word.  F_out may be NULL when
@@ -183,6 +199,16 @@ int surf_init_state(surf_ctx* ctx, const void* c0, double c0_const, double gamma
  *   sigma_out cell field or NULL; totals_dev 16 doubles (device) or NULL.
  * Inputs and outputs must not alias (ping-pong buffers).  F_in/F_out are
  * ignored (may be NULL) when the bulk is disabled.
+ * With interface = SURF_IFACE_ACDI (section 2.5) the step first advances
+ * the phase field phi by one ACDI step (advection by u, then the
+ * regularization flux zeta [eps grad phi - 1/4 (1 - tanh^2(s/2eps)) grad s/|grad s|],
+ * s = eps ln((phi+ve)/(1-phi+ve))) and runs the transport on chi = -s(phi)
+ * clamped to |chi| <= chi_max; a vof_next instead re-initializes: chi
+ * warm-started from the current one with hj_iters_step sweeps, then
+ * phi = 1/(1 + e^{chi/eps}).  The caller chooses the re-initialization
+ * frequency by passing vof_next.  The regularization is explicit:
+ * SURF_T_DT_NEXT and SURF_STATUS_UNSTABLE include its bound
+ * 1/(zeta (2 dim eps/h^2 + sqrt(dim)/h)).
  * With substep2 = SURF_SUBSTEP2_IMPLICIT (section 3, Appendix C) the step
  * advects, then takes substep 2 by implicit Euler: picard_iters sweeps of
  * the interfacial problem for Gamma and the bulk problem for c, each solved

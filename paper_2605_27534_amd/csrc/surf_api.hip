@@ -16,6 +16,7 @@
 #include "surf_geo3d.hpp"
 #include "surf_adjoint.hpp"
 #include "surf_implicit.hpp"
+#include "surf_acdi.hpp"
 
 using namespace surf;
 
@@ -61,6 +62,7 @@ struct surf_ctx {
   ImpBuf imp{};
   int imp_nblk = 0;
   int imp_nsolves = 0;  // linear solves of the last implicit step
+  void* acdi[3] = {nullptr, nullptr, nullptr};  // ACDI: phi, phi*, s (cell fields)
   unsigned long long* hprog = nullptr;  // CG progress words (pinned host memory)
   unsigned long long solve_serial = 0;
   // pipelined moving interface (2D weighted form): the next step's geometry
@@ -152,6 +154,11 @@ int check_grid_params(const surf_grid* gr, const surf_params* p) {
   if (!(p->dt > 0) || !std::isfinite(p->dt)) return SURF_EINVAL;
   if (p->hj_iters_init < 0 || p->hj_iters_step < 0) return SURF_EINVAL;
   if (p->substep2 < 0 || p->substep2 > 1) return SURF_EINVAL;
+  if (p->interface < 0 || p->interface > 1) return SURF_EINVAL;
+  if (p->interface == SURF_IFACE_ACDI &&
+      (!(p->acdi_zeta > 0) || !std::isfinite(p->acdi_zeta) || !(p->acdi_vareps >= 0) ||
+       p->acdi_vareps >= 0.5 || p->adjoint))
+    return SURF_EINVAL;
   if (p->substep2 == SURF_SUBSTEP2_IMPLICIT &&
       (p->flux_form != SURF_FLUX_WEIGHTED || p->adjoint || p->picard_iters < 0 ||
        p->picard_iters > IMP_MAX_PICARD || p->cg_max_iters < 0 || !(p->cg_tol >= 0) ||
@@ -170,6 +177,7 @@ surf_params with_defaults(const surf_params* in, int dim) {
   if (p.picard_iters == 0) p.picard_iters = 3;
   if (p.cg_max_iters == 0) p.cg_max_iters = 400;
   if (p.cg_tol == 0) p.cg_tol = 1e-12;
+  if (p.acdi_vareps == 0) p.acdi_vareps = 1e-6;
   return p;
 }
 
@@ -348,6 +356,15 @@ void flags_live(surf_ctx* c) {
                        c->stream, c->q[b], (uint8_t)Q_LIVE, c->nflags);
 }
 
+// ACDI: phi from the current level set
+template <typename R>
+void acdi_init(surf_ctx* c) {
+  if (c->prm.interface != SURF_IFACE_ACDI) return;
+  const long long n = c->ncell;
+  hipLaunchKernelGGL(k_acdi_init<R>, dim3(grid1d(n)), dim3(BLOCK), 0, c->stream, c->g,
+                     make_par<R>(c), (const R*)c->chi[c->chi_cur], (R*)c->acdi[0], n);
+}
+
 template <typename R>
 int geometry_impl(surf_ctx* c, const void* vof, int full) {
   Par<R> p = make_par<R>(c);
@@ -375,6 +392,36 @@ int geometry_impl(surf_ctx* c, const void* vof, int full) {
   c->has_chi = true;
   c->materialized = true;
   flags_live(c);
+  acdi_init<R>(c);
+  return status_of_launch();
+}
+
+// ACDI interface: a VoF field re-initializes phi (the level set warm-started
+// from the current one, then phi from it); without one phi advances by one
+// ACDI step, which also writes the level set the transport reads.
+template <typename R>
+int acdi_geometry(surf_ctx* c, const void* vof, const void* const* u) {
+  if (vof) return geometry_impl<R>(c, vof, 0);
+  AcdiArgs<R> a;
+  a.g = c->g;
+  a.p = make_par<R>(c);
+  a.dt = (R)c->dt;
+  a.cfl = (R)(c->dt / c->grid.h);
+  a.zeta = (R)c->prm.acdi_zeta;
+  a.ve = (R)c->prm.acdi_vareps;
+  a.ncell = c->ncell;
+  const bool has_u = u && u[0];
+  const long long n = c->ncell;
+  Timed tm(c, 1);
+  hipLaunchKernelGGL(k_acdi_adv<R>, dim3(grid1d(n)), dim3(BLOCK), 0, c->stream, a,
+                     (const R*)c->acdi[0], has_u ? (const R*)u[0] : nullptr,
+                     has_u ? (const R*)u[1] : nullptr,
+                     (has_u && c->grid.dim == 3) ? (const R*)u[2] : nullptr, (R*)c->acdi[1],
+                     (R*)c->acdi[2]);
+  hipLaunchKernelGGL(k_acdi_reg<R>, dim3(grid1d(n)), dim3(BLOCK), 0, c->stream, a,
+                     (const R*)c->acdi[1], (const R*)c->acdi[2], (R*)c->acdi[0],
+                     (R*)c->chi[c->chi_cur]);
+  c->materialized = true;
   return status_of_launch();
 }
 
@@ -451,6 +498,11 @@ FinalArgs final_of(const surf_grid& gr, const surf_params& q, int nblk, double d
   if (f.bulk) lam += q.k_a * q.gamma_inf / eps + q.k_d;
   f.lam0 = lam;
   f.implicit = q.substep2 == SURF_SUBSTEP2_IMPLICIT ? 1 : 0;
+  // ACDI: its regularization is explicit, a diffusion zeta eps plus a
+  // transport at speed up to zeta (the same form as the paper-form bound)
+  f.lam_acdi = q.interface == SURF_IFACE_ACDI
+                   ? q.acdi_zeta * (2.0 * nd * eps / (h * h) + std::sqrt(nd) / h)
+                   : 0.0;
   return f;
 }
 
@@ -1051,6 +1103,7 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
     b += 4 * align_up(n * es);
     b += align_up((size_t)((n + BLOCK - 1) / BLOCK) * NADJ * sizeof(double));
   }
+  if (params->interface == SURF_IFACE_ACDI) b += 3 * align_up(n * es);
   if (imp) {
     b += IMP_FIELDS * align_up(n * sizeof(double));
     b += align_up((size_t)nimp * 2 * sizeof(double));
@@ -1126,6 +1179,11 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
   }
   c->adj_part = params->adjoint ? (double*)p : nullptr;
   if (params->adjoint) p += align_up((size_t)((c->ncell + BLOCK - 1) / BLOCK) * NADJ * sizeof(double));
+  if (params->interface == SURF_IFACE_ACDI)
+    for (int i = 0; i < 3; ++i) {
+      c->acdi[i] = p;
+      p += align_up(c->ncell * es);
+    }
   if (imp) {
     double** f[IMP_FIELDS] = {&c->imp.Fs,   &c->imp.Ps,   &c->imp.wF,   &c->imp.wP,
                               &c->imp.xF,   &c->imp.xP,   &c->imp.dg,   &c->imp.minv,
@@ -1170,7 +1228,20 @@ int surf_set_levelset(surf_ctx* c, const void* chi) {
   c->has_chi = true;
   c->materialized = true;
   flags_live(c);
+  if (c->prm.precision == SURF_F64) acdi_init<double>(c);
+  else acdi_init<float>(c);
   return status_of_launch();
+}
+
+int surf_get_phase(surf_ctx* c, void* phi_out) {
+  if (!c || !phi_out) return SURF_EINVAL;
+  if (c->prm.interface != SURF_IFACE_ACDI) return SURF_EINVAL;
+  if (!c->has_chi) return SURF_ESTATE;
+  size_t bytes = (size_t)c->ncell * esize(&c->prm);
+  if (hipMemcpyAsync(phi_out, c->acdi[0], bytes, hipMemcpyDeviceToDevice, c->stream) !=
+      hipSuccess)
+    return SURF_EDEVICE;
+  return SURF_OK;
 }
 
 int surf_get_levelset(surf_ctx* c, void* chi_out) {
@@ -1210,6 +1281,12 @@ int surf_step(surf_ctx* c, const void* vof_next, const void* const* u, const voi
   size_t es = esize(&c->prm);
   if (!aligned(psi_in, es) || !aligned(psi_out, es)) return SURF_EINVAL;
   if (!c->has_chi) return SURF_ESTATE;
+  if (c->prm.interface == SURF_IFACE_ACDI) {
+    const int rc = c->prm.precision == SURF_F64 ? acdi_geometry<double>(c, vof_next, u)
+                                                : acdi_geometry<float>(c, vof_next, u);
+    if (rc) return rc;
+    vof_next = nullptr;  // the transport runs on the level set just written
+  }
   if (c->prm.substep2 == SURF_SUBSTEP2_IMPLICIT) {
     if (vof_next) {
       // the level set of the new interface, as in the explicit path
@@ -1327,7 +1404,8 @@ int surf_time_solver(surf_ctx* c, int32_t field, int32_t reps, double* ms_per_la
 
 int surf_prepare_geometry(surf_ctx* c, const void* vof_next, void* aux_stream) {
   if (!c || !vof_next || !aux_stream) return SURF_EINVAL;
-  if (c->grid.dim != 2 || c->col_nwg == 0 || c->prm.substep2 != SURF_SUBSTEP2_EXPLICIT)
+  if (c->grid.dim != 2 || c->col_nwg == 0 || c->prm.substep2 != SURF_SUBSTEP2_EXPLICIT ||
+      c->prm.interface != SURF_IFACE_VOF)
     return SURF_EINVAL;
   if (c->prm.precision == SURF_F32 ? !geom2d_ok<float>(c) : !geom2d_ok<double>(c))
     return SURF_EINVAL;

@@ -443,6 +443,7 @@ struct FinalArgs {
   double h, ka, cfl_a, cfl_d, dt;
   double lam0;  // stability rate of substep 2 without the c_max term
   int implicit; // substep 2 implicit: only the advective bound applies
+  double lam_acdi;  // stability rate of the ACDI regularization (0 without ACDI)
 };
 
 constexpr int FIN_BLOCK = 256;
@@ -498,6 +499,10 @@ __device__ __forceinline__ void finalize_body(const FinalArgs& f, const double* 
   double dta = su > 0 ? f.cfl_a * f.h / su : INFINITY;
   double dtd = f.implicit ? INFINITY : f.cfl_d / lam;
   double bound = fmin(su > 0 ? f.h / su : INFINITY, f.implicit ? INFINITY : 1.0 / lam);
+  if (f.lam_acdi > 0) {
+    dtd = fmin(dtd, f.cfl_d / f.lam_acdi);
+    bound = fmin(bound, 1.0 / f.lam_acdi);
+  }
   unsigned status = (unsigned)state[S_STATUS] | *(const unsigned*)(state + S_FLAGS);
   if (tot[P_NBAD] > 0) status |= 1u;
   if ((f.bulk && tot[P_MIN_F] < 0) || tot[P_MIN_PSI] < 0) status |= 2u;

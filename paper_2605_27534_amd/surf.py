@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_PKG, "libsurf.so")
 
 SURF_F32, SURF_F64 = 0, 1
 SURF_SUBSTEP2_EXPLICIT, SURF_SUBSTEP2_IMPLICIT = 0, 1
+SURF_IFACE_VOF, SURF_IFACE_ACDI = 0, 1
 FLUX_WEIGHTED, FLUX_PAPER = 0, 1
 KIN_LANGMUIR, KIN_HENRY = 0, 1
 EOS_LINEAR, EOS_LANGMUIR, EOS_TANH = 0, 1, 2
@@ -32,7 +33,7 @@ ERRORS = {0: "ok", -1: "invalid argument", -2: "workspace too small",
 
 EXPORTS = [
     "surf_workspace_bytes", "surf_init", "surf_set_geometry", "surf_set_levelset",
-    "surf_get_levelset", "surf_init_state", "surf_step", "surf_prepare_geometry",
+    "surf_get_levelset", "surf_get_phase", "surf_init_state", "surf_step", "surf_prepare_geometry",
     "surf_time_transport", "surf_force", "surf_set_dt",
     "surf_get_status", "surf_clear_status", "surf_solver_iterations", "surf_time_solver",
     "surf_destroy", "surf_strerror", "surf_version",
@@ -69,7 +70,9 @@ class Params(ctypes.Structure):
                 ("cfl_diff", ctypes.c_double), ("dt", ctypes.c_double),
                 ("substep2", ctypes.c_int32), ("picard_iters", ctypes.c_int32),
                 ("cg_max_iters", ctypes.c_int32), ("pad2_", ctypes.c_int32),
-                ("cg_tol", ctypes.c_double)]
+                ("cg_tol", ctypes.c_double), ("interface", ctypes.c_int32),
+                ("pad3_", ctypes.c_int32), ("acdi_zeta", ctypes.c_double),
+                ("acdi_vareps", ctypes.c_double)]
 
 
 _lib = None
@@ -89,6 +92,7 @@ def lib():
         L.surf_set_geometry.argtypes = [vp, vp, i32]
         L.surf_set_levelset.argtypes = [vp, vp]
         L.surf_get_levelset.argtypes = [vp, vp]
+        L.surf_get_phase.argtypes = [vp, vp]
         L.surf_init_state.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp]
         L.surf_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.surf_force.argtypes = [vp, vp, vp]
@@ -121,7 +125,7 @@ DEFAULTS = dict(flux_form=0, kinetics=0, eos=0, bulk_enabled=1, D_b=1e-2, D_s=1e
                 k_a=1.0, k_d=1.0, gamma_inf=1.0, sigma0=1.0, eos_E=0.5, eta=1e-12,
                 chi_max_eps=12.0, cfl_adv=0.5, cfl_diff=0.8, hj_iters_init=0,
                 hj_iters_step=0, adjoint=0, substep2=0, picard_iters=0, cg_max_iters=0,
-                cg_tol=0.0)
+                cg_tol=0.0, interface=0, acdi_zeta=0.0, acdi_vareps=0.0)
 
 
 def make_structs(prob: dict, dt: float, precision: int):
@@ -141,10 +145,10 @@ def make_structs(prob: dict, dt: float, precision: int):
     p = Params()
     p.precision = precision
     for k in ("flux_form", "kinetics", "eos", "bulk_enabled", "hj_iters_init", "hj_iters_step",
-              "adjoint", "substep2", "picard_iters", "cg_max_iters"):
+              "adjoint", "substep2", "picard_iters", "cg_max_iters", "interface"):
         setattr(p, k, int(q[k]))
     for k in ("D_b", "D_s", "k_a", "k_d", "gamma_inf", "sigma0", "eos_E", "eta",
-              "chi_max_eps", "cfl_adv", "cfl_diff", "cg_tol"):
+              "chi_max_eps", "cfl_adv", "cfl_diff", "cg_tol", "acdi_zeta", "acdi_vareps"):
         setattr(p, k, float(q[k]))
     p.eps = float(q.get("eps", 1.5 * q["h"]))
     p.dt = float(dt)
@@ -228,6 +232,12 @@ class Surf:
     def set_levelset(self, chi):
         self._check(self.L.surf_set_levelset(self.ctx, _ptr(self._cell(chi, "chi"))),
                     "surf_set_levelset")
+
+    def phase(self):
+        """The ACDI phase field phi (ACDI contexts)."""
+        out = self.empty()
+        self._check(self.L.surf_get_phase(self.ctx, _ptr(out)), "surf_get_phase")
+        return out
 
     def levelset(self):
         out = self.empty()

@@ -120,11 +120,12 @@ def test_batch_workspace_validates_instances():
 
 def test_params_struct_matches_the_header():
     # the binding's surf_params mirrors include/surf.h: 8 int32, 13 doubles,
-    # 4 int32, 1 double, naturally aligned
+    # 4 int32, 1 double, 2 int32, 2 doubles, naturally aligned
     import ctypes
     from paper_2605_27534_amd import surf as S
-    assert ctypes.sizeof(S.Params) == 8 * 4 + 13 * 8 + 4 * 4 + 8
-    assert S.Params.cg_tol.offset == ctypes.sizeof(S.Params) - 8
+    assert ctypes.sizeof(S.Params) == 8 * 4 + 13 * 8 + 4 * 4 + 8 + 2 * 4 + 2 * 8
+    assert S.Params.cg_tol.offset == 8 * 4 + 13 * 8 + 4 * 4
+    assert S.Params.acdi_vareps.offset == ctypes.sizeof(S.Params) - 8
 
 
 def test_implicit_substep2_validation():
@@ -141,5 +142,24 @@ def test_implicit_substep2_validation():
     assert ws_imp >= nb.value + 15 * 32 * 32 * 8  # the FP64 work arrays
     for bad in (dict(flux_form=1), dict(adjoint=1), dict(substep2=2), dict(picard_iters=-1),
                 dict(picard_iters=33), dict(cg_tol=-1.0), dict(cg_max_iters=-1)):
+        g, p, _ = S.make_structs(dict(base, **bad), 1e-3, S.SURF_F32)
+        assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == -1, bad
+
+
+def test_acdi_validation():
+    import ctypes
+    from paper_2605_27534_amd import surf as S
+    L = S.lib()
+    nb = ctypes.c_size_t(0)
+    base = dict(dim=2, n=(32, 32), h=1 / 32, bc=((0, 0), (0, 0)), interface=1, acdi_zeta=0.5)
+    g, p, _ = S.make_structs(base, 1e-3, S.SURF_F32)
+    assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == 0
+    ws_acdi = nb.value
+    g, p, _ = S.make_structs(dict(base, interface=0), 1e-3, S.SURF_F32)
+    assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == 0
+    assert ws_acdi >= nb.value + 3 * 32 * 32 * 4  # phi, phi* and s
+    for bad in (dict(acdi_zeta=0.0), dict(acdi_zeta=-1.0), dict(acdi_zeta=float("inf")),
+                dict(acdi_vareps=-1e-6), dict(acdi_vareps=0.5), dict(interface=2),
+                dict(adjoint=1)):
         g, p, _ = S.make_structs(dict(base, **bad), 1e-3, S.SURF_F32)
         assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == -1, bad
