@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c1",
-                    choices=["c0", "c1", "c1i", "c1m", "c2", "c3", "c4"])
+                    choices=["c0", "c1", "c1i", "c1a", "c1m", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--implicit-graph", action="store_true",
@@ -72,6 +72,8 @@ def workload(name, K, W):
         return C.c1_expanding_circle(soluble=True)
     if name == "c1i":
         return C.c1_expanding_circle(soluble=False)
+    if name == "c1a":
+        return C.c1_acdi()
     return C.c2_translating_sphere()
 
 
@@ -195,8 +197,10 @@ def main():
         dev_gen = cfg.get("vof_seq_dev") is not None
         vof0 = tens(cfg["vof0_dev"](dev)) if dev_gen else tens(cfg["vof0"]())
         vofs = None
+        reinit = cfg.get("reinit_every")  # ACDI: a VoF field only every `reinit` steps
         if cfg.get("vof_seq"):
-            vofs = [tens(cfg["vof_seq_dev"](k, dev)) if dev_gen else tens(cfg["vof_seq"](k))
+            vofs = [None if reinit and (k + 1) % reinit else
+                    tens(cfg["vof_seq_dev"](k, dev)) if dev_gen else tens(cfg["vof_seq"](k))
                     for k in range(W + K)]
         u_static = [tens(x) for x in cfg["u"]()] if cfg.get("u") else None
         u_list = None
@@ -227,7 +231,7 @@ def main():
         # step k's transport runs on `side`; every run of steps ends with no
         # geometry pending
         pipelined = (vofs is not None and prob["dim"] == 2 and prob.get("flux_form", 0) == 0
-                     and not args.no_pipeline)
+                     and not args.no_pipeline and not reinit)
         aux = torch.cuda.Stream(dev)
 
         def run_steps(k0, k1):
@@ -284,6 +288,7 @@ def main():
             u = u_list[W + K - 1] if u_list is not None else u_static
             burst_ms = s.time_transport(a[0], a[1], b[0], b[1], u=u, sigma_out=sig,
                                         reps=burst_reps)
+        acdi_ms = s.time_acdi(u=u_static, reps=200) if reinit else None
 
     ms_per_step = ms_total / K
     traffic = measured_traffic(cfg["name"])
@@ -323,6 +328,15 @@ def main():
         "status": status,
         "wall_s": round(wall, 4),
     }
+    if acdi_ms is not None:
+        ab = ACDI_WORDS_PER_CELL * es
+        out["config"]["acdi_reinit_every"] = reinit
+        out["acdi"] = {
+            "kernels": "k_acdi_adv + k_acdi_reg", "avg_step_us": round(acdi_ms * 1e3, 3),
+            "timing": "200 back-to-back ACDI steps between HIP events",
+            "bytes_per_cell": ab, "achieved": round(ab * ncell / (acdi_ms * 1e-3) / 1e9, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ab * ncell / (acdi_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -446,6 +460,9 @@ def bench_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
+# ACDI: k_acdi_adv reads phi and the d face velocities, writes phi* and s;
+# k_acdi_reg reads phi* and s, writes phi and chi (2D: 5 + 4 words)
+ACDI_WORDS_PER_CELL = 9
 CG_ITER_BYTES_PER_CELL = 13 * 8  # reads x p r w z minv dg w_face, writes x p r w z
 
 
@@ -602,15 +619,15 @@ def cpu_baseline_implicit(seconds):
 
 def cpu_baseline(cfg, seconds):
     """The FP64 oracle as it stands, single-threaded, on a bounded sample of
-    the same workload: the first S steps (geometry warm start + step), S
-    chosen from a one-step probe to take about `seconds`."""
+    the same workload: the first S steps (the interface step + the surfactant
+    step), S chosen from a one-step probe to take about `seconds`."""
+    import math
     import numpy as np
     from oracle import oracle as O
     prob = dict(cfg["prob"])
     q = O.full(prob)
     ncell = int(np.prod(q["n"]))
     vof0 = cfg["vof0"]()
-    import math
     iters = 2 * int(math.ceil(q["chi_max_eps"] * q["eps"] / (q["h"] / q["dim"]) - 1e-9))
     chi = O.geometry(prob, vof0, iters)
     c0 = cfg["c0"]() if cfg.get("c0") else None
@@ -618,33 +635,50 @@ def cpu_baseline(cfg, seconds):
                         gamma0=cfg.get("gamma0", 0.0))
     u = cfg["u"]() if cfg.get("u") else None
     hj = cfg.get("hj_step", 8)
+    reinit = cfg.get("reinit_every")
+    st = {"chi": chi}
+    if reinit:
+        from oracle import acdi as A
+        st["phi"] = A.phi_of_chi(prob, chi)
 
-    def one(k, chi, F, P, tot):
-        if cfg.get("vof_seq"):
-            chi = O.geometry(prob, cfg["vof_seq"](k), hj, chi=chi)
+    def inputs(k):
+        # inputs of step k, generated outside the timed part
+        vk = None
+        if cfg.get("vof_seq") and (not reinit or (k + 1) % reinit == 0):
+            vk = cfg["vof_seq"](k)
         uk = cfg["u_seq"](k) if cfg.get("u_seq") else u
-        F, P, _, tot = O.step(prob, chi, uk, F, P, cfg["dt"], tot)
-        return chi, F, P, tot
+        return vk, uk
+
+    def one(vk, uk, F, P, tot):
+        if reinit:
+            if vk is not None:
+                st["chi"] = O.geometry(prob, vk, hj, chi=st["chi"])
+                st["phi"] = A.phi_of_chi(prob, st["chi"])
+            else:
+                st["phi"] = A.acdi_step(prob, st["phi"], uk, cfg["dt"], prob["acdi_zeta"])
+                st["chi"] = A.chi_of_phi(prob, st["phi"])
+        elif vk is not None:
+            st["chi"] = O.geometry(prob, vk, hj, chi=st["chi"])
+        F, P, _, tot = O.step(prob, st["chi"], uk, F, P, cfg["dt"], tot)
+        return F, P, tot
 
     tot = np.zeros(16)
+    vk, uk = inputs(0)
     t = time.perf_counter()
-    chi, F, P, tot = one(0, chi, F, P, tot)
+    F, P, tot = one(vk, uk, F, P, tot)
     probe = time.perf_counter() - t
     nsteps = max(1, min(200, int(seconds / max(probe, 1e-6))))
     el = 0.0
     for k in range(1, nsteps + 1):
-        # inputs of the next step are generated outside the timed part
-        vk = cfg["vof_seq"](k) if cfg.get("vof_seq") else None
-        uk = cfg["u_seq"](k) if cfg.get("u_seq") else u
+        vk, uk = inputs(k)
         t = time.perf_counter()
-        if vk is not None:
-            chi = O.geometry(prob, vk, hj, chi=chi)
-        F, P, _, tot = O.step(prob, chi, uk, F, P, cfg["dt"], tot)
+        F, P, tot = one(vk, uk, F, P, tot)
         el += time.perf_counter() - t
+    what = "ACDI step" if reinit else "geometry warm start"
     return {"value": round(ncell * nsteps / el / 1e9, 6), "unit": "Gcell-updates/s", "cores": 1,
             "kind": "oracle",
-            "sample": "first %d steps of the same workload (geometry warm start + step), "
-                      "FP64, one host thread, %.1f s" % (nsteps, el)}
+            "sample": "first %d steps of the same workload (%s + step), FP64, one host thread, "
+                      "%.1f s" % (nsteps, what, el)}
 
 
 if __name__ == "__main__":

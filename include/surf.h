@@ -263,6 +263,14 @@ int surf_time_transport(surf_ctx* ctx, const void* const* u, const void* F_in,
  * the first implicit step. */
 int surf_time_solver(surf_ctx* ctx, int32_t field, int32_t reps, double* ms_per_launch);
 
+/* Measurement aid for the ACDI interface: `reps` ACDI steps (advection and
+ * regularization of phi by u, as surf_step runs them) back to back from the
+ * current phase field, their results written to scratch so that the
+ * context's state is unchanged; returns the mean time of one step (both
+ * kernels) between two HIP events.  Waits for the stream.  SURF_EINVAL for a
+ * context without ACDI or reps < 1; SURF_ESTATE without a level set. */
+int surf_time_acdi(surf_ctx* ctx, const void* const* u, int32_t reps, double* ms_per_step);
+
 /* Marangoni face force (section 2.4) from sigma (cell field) and the cached
  * chi: on each face along d, delta_face [ (grad sigma)_d - n_d (n . grad
  * sigma) ] with n = grad chi/|grad chi| from the face gradient (compact normal

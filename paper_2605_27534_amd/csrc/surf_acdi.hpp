@@ -47,11 +47,22 @@ __device__ __forceinline__ R acdi_s(R phi, R eps, R ve) {
   return eps * rlog<R>(rdiv<R>(q + ve, R(1) - q + ve));
 }
 
-template <typename R>
-__device__ __forceinline__ void acdi_coords(const Grid& g, long long c, int* x) {
-  x[0] = (int)(c % g.n[0]);
-  x[1] = (int)((c / g.n[0]) % g.n[1]);
-  x[2] = (int)(c / ((long long)g.n[0] * g.n[1]));
+// Launch shape of the per-cell ACDI kernels: each workgroup takes ACDI_TX
+// cells of one row (y, z); the row and the offset in it come from the
+// workgroup index by scalar arithmetic, so no thread divides.
+constexpr int ACDI_TX = 256;
+
+__host__ __device__ __forceinline__ int acdi_xblocks(int nx) { return (nx + ACDI_TX - 1) / ACDI_TX; }
+
+// the cell of this thread; false past the end of its row
+__device__ __forceinline__ bool acdi_cell(const Grid& g, int* x, long long& c) {
+  const int xb = acdi_xblocks(g.n[0]);
+  const int row = (int)blockIdx.x / xb;  // uniform: y + ny z
+  x[0] = ((int)blockIdx.x - row * xb) * ACDI_TX + (int)threadIdx.x;
+  x[1] = row % g.n[1];
+  x[2] = row / g.n[1];
+  c = (long long)row * g.n[0] + x[0];
+  return x[0] < g.n[0];
 }
 
 // phi from the level set (initial state and re-initialization)
@@ -65,111 +76,137 @@ __global__ void __launch_bounds__(BLOCK) k_acdi_init(Grid g, Par<R> p, const R* 
   phi[c] = ph;
 }
 
-// substep 1 for phi, and s of the result
-template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_acdi_adv(AcdiArgs<R> a, const R* __restrict__ phi,
-                                                    const R* __restrict__ u0,
-                                                    const R* __restrict__ u1,
-                                                    const R* __restrict__ u2,
-                                                    R* __restrict__ phs, R* __restrict__ s) {
-  const long long c = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  if (c >= a.ncell) return;
+// substep 1 for phi, and s of the result.  Every load (the 5-cell stencil
+// along each axis, both face velocities) is issued up front from indices
+// mapped into the grid; the boundary cases only select among the results.
+template <typename R, int DIM>
+__global__ void __launch_bounds__(ACDI_TX) k_acdi_adv(AcdiArgs<R> a, const R* __restrict__ phi,
+                                                      const R* __restrict__ u0,
+                                                      const R* __restrict__ u1,
+                                                      const R* __restrict__ u2,
+                                                      R* __restrict__ phs, R* __restrict__ s) {
   const Grid& g = a.g;
-  R st = phi[c];
+  int x[3];
+  long long c;
+  if (!acdi_cell(g, x, c)) return;
+  const R pc = phi[c];
+  R st = pc;
   if (u0) {
     const R* u[3] = {u0, u1, u2};
-    int x[3];
-    acdi_coords<R>(g, c, x);
-    R div = R(0);
-    for (int d = 0; d < g.dim; ++d) {
-      const bool per = g.bc[d][0] == BC_PERIODIC;
+    R v[DIM][5], ul[DIM], uh[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
       const int nd = g.n[d];
-      for (int sd = 0; sd < 2; ++sd) {
-        const int fidx = x[d] + sd;
-        const bool blo = !per && fidx == 0, bhi = !per && fidx == nd;
-        int y[3] = {x[0], x[1], x[2]};
-        y[d] = (per && fidx == nd) ? 0 : fidx;
-        const R uf = u[d][face_index(g, d, y[0], y[1], y[2])];
-        R fl;
-        if (blo) {
-          fl = g.bc[d][0] == BC_OPEN ? uf * phi[c] : R(0);
-        } else if (bhi) {
-          fl = g.bc[d][1] == BC_OPEN ? uf * phi[c] : R(0);
-        } else {
-          const int off = sd == 0 ? -1 : 0;
-          auto at = [&](int o) {
-            int w[3] = {x[0], x[1], x[2]};
-            w[d] = map_axis(x[d] + o, nd, g.bc[d][0], g.bc[d][1]);
-            return phi[cell_index(g, w[0], w[1], w[2])];
-          };
-          fl = adv_flux<R>(uf, at(off - 1), at(off), at(off + 1), at(off + 2), a.cfl);
-        }
-        div += sd == 0 ? -fl : fl;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        int w[3] = {x[0], x[1], x[2]};
+        w[d] = map_axis(x[d] + k - 2, nd, g.bc[d][0], g.bc[d][1]);
+        v[d][k] = phi[cell_index(g, w[0], w[1], w[2])];
       }
+      int y[3] = {x[0], x[1], x[2]};
+      ul[d] = u[d][face_index(g, d, y[0], y[1], y[2])];
+      const bool per = g.bc[d][0] == BC_PERIODIC;
+      y[d] = (per && x[d] + 1 == nd) ? 0 : x[d] + 1;
+      uh[d] = u[d][face_index(g, d, y[0], y[1], y[2])];
     }
-    st = phi[c] - a.cfl * div;
+    R div = R(0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const bool per = g.bc[d][0] == BC_PERIODIC;
+      const bool blo = !per && x[d] == 0, bhi = !per && x[d] + 1 == g.n[d];
+      const R flo_i = adv_flux<R>(ul[d], v[d][0], v[d][1], v[d][2], v[d][3], a.cfl);
+      const R fhi_i = adv_flux<R>(uh[d], v[d][1], v[d][2], v[d][3], v[d][4], a.cfl);
+      const R flo = blo ? (g.bc[d][0] == BC_OPEN ? ul[d] * pc : R(0)) : flo_i;
+      const R fhi = bhi ? (g.bc[d][1] == BC_OPEN ? uh[d] * pc : R(0)) : fhi_i;
+      div += -flo;
+      div += fhi;
+    }
+    st = pc - a.cfl * div;
   }
   phs[c] = st;
   s[c] = acdi_s<R>(st, a.p.eps, a.ve);
 }
 
-// G through the face between cell xl and its neighbour along +d (wrapped on
-// a periodic axis); the caller checks that the face carries flux
-template <typename R>
-__device__ __forceinline__ R acdi_face(const AcdiArgs<R>& a, const R* __restrict__ phs,
-                                       const R* __restrict__ s, const int* xl, int d) {
+// The regularization substep, then the level set of the new phi.  s on the
+// 3^DIM block around the cell and phi* on the cell and its face neighbours
+// are loaded up front (indices mapped into the grid); each face flux is then
+// formed from registers.  A face's flux is computed by both of its cells from
+// the same values in the same order.
+template <typename R, int DIM>
+__global__ void __launch_bounds__(ACDI_TX) k_acdi_reg(AcdiArgs<R> a, const R* __restrict__ phs,
+                                                      const R* __restrict__ s,
+                                                      R* __restrict__ phi_out,
+                                                      R* __restrict__ chi_out) {
   const Grid& g = a.g;
   const Par<R>& p = a.p;
-  int xr[3] = {xl[0], xl[1], xl[2]};
-  xr[d] = xl[d] + 1 == g.n[d] ? 0 : xl[d] + 1;
-  const long long L = cell_index(g, xl[0], xl[1], xl[2]);
-  const long long Rc = cell_index(g, xr[0], xr[1], xr[2]);
-  const R sL = s[L], sR = s[Rc];
-  const R gn = (sR - sL) * p.inv_h;
-  R g2 = gn * gn;
-  for (int t = 0; t < g.dim; ++t) {
-    if (t == d) continue;
-    R cd[2];
-    for (int k = 0; k < 2; ++k) {
-      const int* q = k == 0 ? xl : xr;
-      int hi[3] = {q[0], q[1], q[2]}, lo[3] = {q[0], q[1], q[2]};
-      hi[t] = map_axis(q[t] + 1, g.n[t], g.bc[t][0], g.bc[t][1]);
-      lo[t] = map_axis(q[t] - 1, g.n[t], g.bc[t][0], g.bc[t][1]);
-      cd[k] = (s[cell_index(g, hi[0], hi[1], hi[2])] - s[cell_index(g, lo[0], lo[1], lo[2])]) *
-              (R(0.5) * p.inv_h);
-    }
-    const R gt = R(0.5) * (cd[0] + cd[1]);
-    g2 += gt * gt;
-  }
-  const R nd = rdiv<R>(gn, fmax(rsqrt_<R>(g2), R(0.5)));
-  const R T = rtanh<R>(R(0.5) * (sL + sR) * (R(0.5) * p.inv_eps));
-  return a.zeta * (p.eps * (phs[Rc] - phs[L]) * p.inv_h - R(0.25) * (R(1) - T * T) * nd);
-}
-
-// the regularization substep, then the level set of the new phi
-template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_acdi_reg(AcdiArgs<R> a, const R* __restrict__ phs,
-                                                    const R* __restrict__ s,
-                                                    R* __restrict__ phi_out,
-                                                    R* __restrict__ chi_out) {
-  const long long c = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  if (c >= a.ncell) return;
-  const Grid& g = a.g;
   int x[3];
-  acdi_coords<R>(g, c, x);
-  R acc = R(0);
-  for (int d = 0; d < g.dim; ++d) {
-    const bool per = g.bc[d][0] == BC_PERIODIC;
-    R Ghi = R(0), Glo = R(0);
-    if (per || x[d] + 1 < g.n[d]) Ghi = acdi_face<R>(a, phs, s, x, d);
-    if (per || x[d] > 0) {
-      int xl[3] = {x[0], x[1], x[2]};
-      xl[d] = x[d] > 0 ? x[d] - 1 : g.n[d] - 1;
-      Glo = acdi_face<R>(a, phs, s, xl, d);
-    }
-    acc += Ghi - Glo;
+  long long c;
+  if (!acdi_cell(g, x, c)) return;
+  constexpr int NZ = DIM == 3 ? 3 : 1;
+  int m[3][3];  // m[d][k]: the cell coordinate x[d] + k - 1, mapped
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      m[d][k] = d < DIM ? map_axis(x[d] + k - 1, g.n[d], g.bc[d][0], g.bc[d][1]) : x[d];
+  R S[NZ][3][3];
+#pragma unroll
+  for (int kz = 0; kz < NZ; ++kz)
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx)
+        S[kz][ky][kx] = s[cell_index(g, m[0][kx], m[1][ky], DIM == 3 ? m[2][kz] : x[2])];
+  R P[DIM][3];  // phi* at offsets -1, 0, +1 along each axis
+  const R pc = phs[c];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    int lo[3] = {x[0], x[1], x[2]}, hi[3] = {x[0], x[1], x[2]};
+    lo[d] = m[d][0];
+    hi[d] = m[d][2];
+    P[d][0] = phs[cell_index(g, lo[0], lo[1], lo[2])];
+    P[d][1] = pc;
+    P[d][2] = phs[cell_index(g, hi[0], hi[1], hi[2])];
   }
-  const R phn = phs[c] + a.cfl * acc;
+  // s at the block offsets (k0, k1, k2) along axes 0, 1, 2 (each 0..2)
+  auto sat = [&](int k0, int k1, int k2) { return S[DIM == 3 ? k2 : 0][k1][k0]; };
+  R acc = R(0);
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const bool per = g.bc[d][0] == BC_PERIODIC;
+    R G[2];
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const int kL = sd, kR = sd + 1;  // the face's cells along d
+      int oL[3] = {1, 1, 1}, oR[3] = {1, 1, 1};
+      oL[d] = kL;
+      oR[d] = kR;
+      const R sL = sat(oL[0], oL[1], oL[2]), sR = sat(oR[0], oR[1], oR[2]);
+      const R gn = (sR - sL) * p.inv_h;
+      R g2 = gn * gn;
+#pragma unroll
+      for (int t = 0; t < DIM; ++t) {
+        if (t == d) continue;
+        int lp[3] = {oL[0], oL[1], oL[2]}, lm[3] = {oL[0], oL[1], oL[2]};
+        int rp[3] = {oR[0], oR[1], oR[2]}, rm[3] = {oR[0], oR[1], oR[2]};
+        lp[t] = 2;
+        lm[t] = 0;
+        rp[t] = 2;
+        rm[t] = 0;
+        const R cdL = (sat(lp[0], lp[1], lp[2]) - sat(lm[0], lm[1], lm[2])) * (R(0.5) * p.inv_h);
+        const R cdR = (sat(rp[0], rp[1], rp[2]) - sat(rm[0], rm[1], rm[2])) * (R(0.5) * p.inv_h);
+        const R gt = R(0.5) * (cdL + cdR);
+        g2 += gt * gt;
+      }
+      const R nd = rdiv<R>(gn, fmax(rsqrt_<R>(g2), R(0.5)));
+      const R T = rtanh<R>(R(0.5) * (sL + sR) * (R(0.5) * p.inv_eps));
+      const R f = a.zeta * (p.eps * (P[d][kR] - P[d][kL]) * p.inv_h - R(0.25) * (R(1) - T * T) * nd);
+      const bool has = per || (sd == 0 ? x[d] > 0 : x[d] + 1 < g.n[d]);
+      G[sd] = has ? f : R(0);
+    }
+    acc += G[1] - G[0];
+  }
+  const R phn = pc + a.cfl * acc;
   phi_out[c] = phn;
   const R chi = -acdi_s<R>(phn, a.p.eps, a.ve);
   chi_out[c] = fmin(fmax(chi, -a.p.chimax), a.p.chimax);

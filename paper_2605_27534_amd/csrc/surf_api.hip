@@ -399,9 +399,10 @@ int geometry_impl(surf_ctx* c, const void* vof, int full) {
 // ACDI interface: a VoF field re-initializes phi (the level set warm-started
 // from the current one, then phi from it); without one phi advances by one
 // ACDI step, which also writes the level set the transport reads.
+// One ACDI step from the phase field: phi* and s into the context's scratch
+// fields, the new phi and its level set into phi_out and chi_out.
 template <typename R>
-int acdi_geometry(surf_ctx* c, const void* vof, const void* const* u) {
-  if (vof) return geometry_impl<R>(c, vof, 0);
+void acdi_launch(surf_ctx* c, const void* const* u, R* phi_out, R* chi_out) {
   AcdiArgs<R> a;
   a.g = c->g;
   a.p = make_par<R>(c);
@@ -411,18 +412,58 @@ int acdi_geometry(surf_ctx* c, const void* vof, const void* const* u) {
   a.ve = (R)c->prm.acdi_vareps;
   a.ncell = c->ncell;
   const bool has_u = u && u[0];
-  const long long n = c->ncell;
-  Timed tm(c, 1);
-  hipLaunchKernelGGL(k_acdi_adv<R>, dim3(grid1d(n)), dim3(BLOCK), 0, c->stream, a,
-                     (const R*)c->acdi[0], has_u ? (const R*)u[0] : nullptr,
-                     has_u ? (const R*)u[1] : nullptr,
-                     (has_u && c->grid.dim == 3) ? (const R*)u[2] : nullptr, (R*)c->acdi[1],
-                     (R*)c->acdi[2]);
-  hipLaunchKernelGGL(k_acdi_reg<R>, dim3(grid1d(n)), dim3(BLOCK), 0, c->stream, a,
-                     (const R*)c->acdi[1], (const R*)c->acdi[2], (R*)c->acdi[0],
-                     (R*)c->chi[c->chi_cur]);
+  const dim3 gr(acdi_xblocks(c->grid.n[0]) * c->grid.n[1] * c->grid.n[2]);
+  const R* u0 = has_u ? (const R*)u[0] : nullptr;
+  const R* u1 = has_u ? (const R*)u[1] : nullptr;
+  const R* u2 = (has_u && c->grid.dim == 3) ? (const R*)u[2] : nullptr;
+  if (c->grid.dim == 3) {
+    hipLaunchKernelGGL((k_acdi_adv<R, 3>), gr, dim3(ACDI_TX), 0, c->stream, a,
+                       (const R*)c->acdi[0], u0, u1, u2, (R*)c->acdi[1], (R*)c->acdi[2]);
+    hipLaunchKernelGGL((k_acdi_reg<R, 3>), gr, dim3(ACDI_TX), 0, c->stream, a,
+                       (const R*)c->acdi[1], (const R*)c->acdi[2], phi_out, chi_out);
+  } else {
+    hipLaunchKernelGGL((k_acdi_adv<R, 2>), gr, dim3(ACDI_TX), 0, c->stream, a,
+                       (const R*)c->acdi[0], u0, u1, u2, (R*)c->acdi[1], (R*)c->acdi[2]);
+    hipLaunchKernelGGL((k_acdi_reg<R, 2>), gr, dim3(ACDI_TX), 0, c->stream, a,
+                       (const R*)c->acdi[1], (const R*)c->acdi[2], phi_out, chi_out);
+  }
+}
+
+template <typename R>
+int acdi_geometry(surf_ctx* c, const void* vof, const void* const* u) {
+  if (vof) return geometry_impl<R>(c, vof, 0);
+  {
+    Timed tm(c, 1);
+    acdi_launch<R>(c, u, (R*)c->acdi[0], (R*)c->chi[c->chi_cur]);
+  }
   c->materialized = true;
   return status_of_launch();
+}
+
+// Measurement aid: `reps` ACDI steps back to back from the current phase
+// field, the new phi and level set written to free scratch (the pin-data
+// buffer and the idle level-set buffer), so the context's state is unchanged.
+template <typename R>
+int time_acdi_impl(surf_ctx* c, const void* const* u, int reps, double* ms_per_step) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return SURF_EDEVICE;
+  }
+  int rc = SURF_OK;
+  if (hipEventRecord(e0, c->stream) != hipSuccess) rc = SURF_EDEVICE;
+  for (int r = 0; r < reps && rc == SURF_OK; ++r)
+    acdi_launch<R>(c, u, (R*)c->g0, (R*)c->chi[1 - c->chi_cur]);
+  if (rc == SURF_OK) rc = status_of_launch();
+  float ms = 0.f;
+  if (rc == SURF_OK &&
+      (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+       hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    rc = SURF_EDEVICE;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == SURF_OK) *ms_per_step = (double)ms / reps;
+  return rc;
 }
 
 template <typename R, int DIM, int TX, int TY, int TZ>
@@ -1391,6 +1432,17 @@ int surf_time_transport(surf_ctx* c, const void* const* u, const void* F_in,
   (void)hipEventDestroy(e1);
   if (rc == SURF_OK) *ms_per_launch = (double)ms / reps;
   return rc;
+}
+
+int surf_time_acdi(surf_ctx* c, const void* const* u, int32_t reps, double* ms_per_step) {
+  if (!c || !ms_per_step || reps < 1) return SURF_EINVAL;
+  if (c->prm.interface != SURF_IFACE_ACDI) return SURF_EINVAL;
+  if (u && u[0])
+    for (int d = 0; d < c->grid.dim; ++d)
+      if (!u[d]) return SURF_EINVAL;
+  if (!c->has_chi) return SURF_ESTATE;
+  if (c->prm.precision == SURF_F64) return time_acdi_impl<double>(c, u, reps, ms_per_step);
+  return time_acdi_impl<float>(c, u, reps, ms_per_step);
 }
 
 int surf_time_solver(surf_ctx* c, int32_t field, int32_t reps, double* ms_per_launch) {

@@ -35,7 +35,7 @@ EXPORTS = [
     "surf_workspace_bytes", "surf_init", "surf_set_geometry", "surf_set_levelset",
     "surf_get_levelset", "surf_get_phase", "surf_init_state", "surf_step", "surf_prepare_geometry",
     "surf_time_transport", "surf_force", "surf_set_dt",
-    "surf_get_status", "surf_clear_status", "surf_solver_iterations", "surf_time_solver",
+    "surf_get_status", "surf_clear_status", "surf_solver_iterations", "surf_time_solver", "surf_time_acdi",
     "surf_destroy", "surf_strerror", "surf_version",
     "surf_profile_enable", "surf_profile_read", "surf_set_kinetics", "surf_loss_weights",
     "surf_adjoint_seed", "surf_adjoint_step", "surf_adjoint_c0",
@@ -103,6 +103,7 @@ def lib():
         L.surf_get_status.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
         L.surf_clear_status.argtypes = [vp]
         L.surf_time_solver.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double)]
+        L.surf_time_acdi.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double)]
         L.surf_solver_iterations.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), i32,
                                              ctypes.POINTER(ctypes.c_int32)]
         L.surf_destroy.argtypes = [vp]
@@ -306,6 +307,13 @@ class Surf:
 
     def clear_status(self):
         self._check(self.L.surf_clear_status(self.ctx), "surf_clear_status")
+
+    def time_acdi(self, u=None, reps=100):
+        """Mean ms of one ACDI step (both kernels), the state unchanged."""
+        ms = ctypes.c_double(0.0)
+        self._check(self.L.surf_time_acdi(self.ctx, self._faces(u, "u"), int(reps), ctypes.byref(ms)),
+                    "surf_time_acdi")
+        return ms.value
 
     def time_solver(self, field, reps):
         """Mean ms of one CG iteration launch (implicit contexts)."""

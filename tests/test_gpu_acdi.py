@@ -185,3 +185,32 @@ def test_acdi_errors():
     s2 = S.Surf(dict(dim=2, n=n, h=h, bc=((0, 0), (0, 0))), 1e-4, S.SURF_F32)
     with pytest.raises(S.SurfError):
         s2.phase()  # not an ACDI context
+
+
+def test_time_acdi_leaves_the_state_alone():
+    # the measurement entry writes its ACDI steps to scratch: a step after it
+    # equals the same step of a context that never called it
+    import torch
+    n = (150, 131)
+    h = 1.0 / 150
+    cen = (0.5, 0.46, 0)
+    u = synth.u_source2d(n, h, cen, 0.05)
+    prob = dict(dim=2, n=n, h=h, bc=((2, 2), (2, 0)), eos=1, eos_E=0.2, interface=1,
+                acdi_zeta=1.1 * max_speed(u))
+    dt = 0.15 * h * h / 1e-2
+    outs = []
+    for timed in (True, False):
+        s = S.Surf(prob, dt, S.SURF_F32)
+        T = s.tensor
+        s.set_geometry(T(synth.vof_ball(n, h, cen, 0.15, 2)), full=True)
+        F, P = s.init_state(T(synth.uniform_field(n, 3, 0.8, 1.2)), 1.0, 0.4)
+        ud = [T(x) for x in u]
+        F2, P2, sig = s.empty(), s.empty(), s.empty()
+        s.step(F, P, F2, P2, u=ud, sigma_out=sig)
+        if timed:
+            assert s.time_acdi(u=ud, reps=5) > 0
+        s.step(F2, P2, F, P, u=ud, sigma_out=sig)
+        torch.cuda.synchronize()
+        outs.append([x.clone() for x in (F, P, sig, s.phase(), s.levelset())])
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
