@@ -25,9 +25,11 @@
  *   ip[0] dim  ip[1..3] nx ny nz  ip[4..9] bc x-lo x-hi y-lo y-hi z-lo z-hi
  *   ip[10] flux form (0 weighted, 1 paper)  ip[11] kinetics (0 Langmuir,
  *   1 Henry)  ip[12] EoS (0 linear, 1 Langmuir, 2 tanh)  ip[13] bulk on
+ *   ip[14] axisymmetric (2D only: x is the radius r, y the axis z)
  *   dp[0] h  dp[1] eps  dp[2] D_b  dp[3] D_s  dp[4] k_a  dp[5] k_d
  *   dp[6] Gamma_inf  dp[7] sigma0  dp[8] E  dp[9] eta  dp[10] chi_max/eps
  *   dp[11] advective safety factor  dp[12] diffusive safety factor
+ *   dp[13] radius of the low x side (axisymmetric)
  * Boundary codes: 0 wall, 1 periodic, 2 open.
  */
 #include <math.h>
@@ -47,8 +49,8 @@ enum {
 
 typedef struct {
   int dim, n[3], bc[3][2];
-  int form, kin, eos, bulk;
-  double h, eps, Db, Ds, ka, kd, ginf, sigma0, E, eta, chimax, cfl_a, cfl_d;
+  int form, kin, eos, bulk, axi;
+  double h, eps, Db, Ds, ka, kd, ginf, sigma0, E, eta, chimax, cfl_a, cfl_d, r0;
   long ncell;
 } Prob;
 
@@ -59,10 +61,11 @@ static Prob unpack(const int* ip, const double* dp) {
   p.bc[0][0] = ip[4]; p.bc[0][1] = ip[5];
   p.bc[1][0] = ip[6]; p.bc[1][1] = ip[7];
   p.bc[2][0] = ip[8]; p.bc[2][1] = ip[9];
-  p.form = ip[10]; p.kin = ip[11]; p.eos = ip[12]; p.bulk = ip[13];
+  p.form = ip[10]; p.kin = ip[11]; p.eos = ip[12]; p.bulk = ip[13]; p.axi = ip[14];
   p.h = dp[0]; p.eps = dp[1]; p.Db = dp[2]; p.Ds = dp[3];
   p.ka = dp[4]; p.kd = dp[5]; p.ginf = dp[6]; p.sigma0 = dp[7]; p.E = dp[8];
   p.eta = dp[9]; p.chimax = dp[10] * dp[1]; p.cfl_a = dp[11]; p.cfl_d = dp[12];
+  p.r0 = dp[13];
   p.ncell = (long)p.n[0] * p.n[1] * p.n[2];
   return p;
 }
@@ -86,6 +89,35 @@ static long nbr(const Prob* p, int i, int j, int k, int d, int s) {
   }
   c[d] = q;
   return cell(p, c[0], c[1], c[2]);
+}
+
+/* Axisymmetric geometry (Appendix B): cell (i, j) is the ring between radii
+ * r_{i-1/2} = r0 + i h and r_{i+1/2} = r0 + (i+1) h, of volume
+ * pi (r_{i+1/2}^2 - r_{i-1/2}^2) h = 2 pi r_i h^2 with r_i its mid radius.
+ * Dividing the finite-volume balance by the volume, a flux through a radial
+ * face enters with the weight r_face / r_i, an axial one with 1.  The
+ * Cartesian case has every weight 1 and volume h^dim. */
+static const double PI = 3.14159265358979323846;
+static double r_face(const Prob* p, int i) { return p->r0 + i * p->h; }
+static double r_mid(const Prob* p, int i) { return p->r0 + (i + 0.5) * p->h; }
+static double cell_volume(const Prob* p, int i) {
+  return p->axi ? 2.0 * PI * r_mid(p, i) * p->h * p->h : pow(p->h, p->dim);
+}
+/* area of face (i, j, k) along d: radial faces 2 pi r_face h, axial faces
+ * 2 pi r_i h (Cartesian: h^(dim-1)) */
+static double face_area(const Prob* p, int d, int i) {
+  if (!p->axi) return pow(p->h, p->dim - 1);
+  return 2.0 * PI * (d == 0 ? r_face(p, i) : r_mid(p, i)) * p->h;
+}
+/* the weights of the low and high faces of cell i along d in its balance */
+static void div_weights(const Prob* p, int d, int i, double* wm, double* wp) {
+  if (p->axi && d == 0) {
+    *wm = r_face(p, i) / r_mid(p, i);
+    *wp = r_face(p, i + 1) / r_mid(p, i);
+  } else {
+    *wm = 1.0;
+    *wp = 1.0;
+  }
 }
 
 /* number of faces along axis d and the linear index of face (i,j,k) where
@@ -275,7 +307,7 @@ static void advect_faces(const Prob* p, int d, const double* u, const double* xi
                          double dt, double* flux, double* out) {
   int m[3] = {p->n[0], p->n[1], p->n[2]};
   m[d] += 1;
-  double h = p->h, area = pow(p->h, p->dim - 1);
+  double h = p->h;
   for (int k = 0; k < m[2]; ++k)
     for (int j = 0; j < m[1]; ++j)
       for (int i = 0; i < m[0]; ++i) {
@@ -293,7 +325,7 @@ static void advect_faces(const Prob* p, int d, const double* u, const double* xi
           ci[d] = hi_bnd ? nd - 1 : 0;
           double v = u[fi] * xi[cell(p, ci[0], ci[1], ci[2])];
           flux[fi] = v;
-          out[0] += dt * area * (hi_bnd ? v : -v);
+          out[0] += dt * face_area(p, d, i) * (hi_bnd ? v : -v);
           continue;
         }
         /* interior (or periodic face 0): left cell L, right cell R */
@@ -327,7 +359,8 @@ static void advect_faces(const Prob* p, int d, const double* u, const double* xi
         }
 }
 
-/* xi* = xi - dt/h * sum_d (flux_{+1/2} - flux_{-1/2}) */
+/* xi* = xi - dt/h * sum_d (w_+ flux_{+1/2} - w_- flux_{-1/2}), the weights
+ * 1 except on radial faces in the axisymmetric case */
 int or_advect(const int* ip, const double* dp, const double* ux, const double* uy,
               const double* uz, const double* xi, double dt, double* xs,
               double* outflow) {
@@ -351,7 +384,9 @@ int or_advect(const int* ip, const double* dp, const double* ux, const double* u
           long fm = face(&p, d, a[0], a[1], a[2]);
           a[d] += 1;
           long fp = face(&p, d, a[0], a[1], a[2]);
-          div += fl[d][fp] - fl[d][fm];
+          double wm, wp;
+          div_weights(&p, d, i, &wm, &wp);
+          div += wp * fl[d][fp] - wm * fl[d][fm];
         }
         xs[c] = xi[c] - dt / p.h * div;
       }
@@ -497,7 +532,9 @@ int or_step(const int* ip, const double* dp, const double* chi,
             long fm = face(&p, d, a[0], a[1], a[2]);
             a[d] += 1;
             long fp = face(&p, d, a[0], a[1], a[2]);
-            div[cell(&p, i, j, k)] += (fl[fp] - fl[fm]) / p.h;
+            double wm, wp;
+            div_weights(&p, d, i, &wm, &wp);
+            div[cell(&p, i, j, k)] += (wp * fl[fp] - wm * fl[fm]) / p.h;
           }
     }
     free(fl);
@@ -527,10 +564,10 @@ int or_step(const int* ip, const double* dp, const double* chi,
 
   /* totals (FP64, compensated sums in cell order) */
   if (totals) {
-    double vol = pow(p.h, p.dim);
     Kahan mb = {0, 0}, ms = {0, 0}, sd = {0, 0}, ssd = {0, 0};
     double minF = INFINITY, minP = INFINITY, cmax = -INFINITY, nbad = 0, su = 0.0;
     for (long c = 0; c < N; ++c) {
+      double vol = cell_volume(&p, (int)(c % p.n[0]));
       double sg = sigma ? sigma[c] : eos(&p, psiout[c] / (del[c] + p.eta / p.eps));
       kadd(&mb, Fout[c] * vol);
       kadd(&ms, psiout[c] * vol);
@@ -553,7 +590,10 @@ int or_step(const int* ip, const double* dp, const double* chi,
               double um = u[d][face(&p, d, a[0], a[1], a[2])];
               a[d] += 1;
               double up = u[d][face(&p, d, a[0], a[1], a[2])];
-              s += fabs(0.5 * (um + up));
+              /* axisymmetric: the radial mean weights each face by r_face/r_i */
+              double wm, wp;
+              div_weights(&p, d, i, &wm, &wp);
+              s += fabs(0.5 * (wm * um + wp * up));
             }
             if (s > su) su = s;
           }

@@ -135,6 +135,18 @@ def u_uniform(n, dim, U):
     return out
 
 
+def u_axisym_strain(n, h, a, z0, origin=(0.0, 0.0, 0.0)):
+    """Axisymmetric straining flow on an (r, z) grid (x the radius): u_r = a r,
+    u_z = -2 a (z - z0), at the face centres.  r_face u_r differences over a
+    ring balance the axial ones exactly, so the field is discretely
+    divergence free in the axisymmetric sense."""
+    X, Y, _ = face_centres(n, h, 0, origin)
+    ur = np.broadcast_to(a * X + 0 * Y, face_centres_shape(n, 0)).copy()
+    X, Y, _ = face_centres(n, h, 1, origin)
+    uz = np.broadcast_to(-2.0 * a * (Y - z0) + 0 * X, face_centres_shape(n, 1)).copy()
+    return [ur, uz]
+
+
 def face_centres_shape(n, d):
     nx, ny, nz = (list(n) + [1, 1])[:3]
     m = [nz, ny, nx]
