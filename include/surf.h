@@ -110,15 +110,24 @@ enum {
 typedef struct surf_ctx surf_ctx;
 typedef struct surf_batch surf_batch;
 
-/* The domain (section 3.2 and Appendix A: uniform Cartesian cells). */
+/* The domain (section 3.2 and Appendix A: uniform Cartesian cells; with
+ * axisym, the rings of Appendix B). */
 typedef struct {
   int32_t dim;       /* 2 or 3                                     */
   int32_t n[3];      /* cells per axis; n[2] = 1 in 2D              */
   int32_t bc[3][2];  /* SURF_BC_* per box face (lo, hi); periodic
                         axes must be periodic on both sides          */
-  int32_t pad_;
+  int32_t axisym;    /* 1: axisymmetric (r, z), Appendix B: 2D, x the
+                        radius (the low x side at r = origin[0] >= 0,
+                        not periodic), y the axis; cell (i, j) is the
+                        ring of volume 2 pi r_i h^2, radial fluxes enter
+                        with r_face / r_i and every total is a volume
+                        or area integral over the rings.  Weighted flux
+                        form, explicit substep 2, VoF interface, no
+                        adjoint, no batch.  0: Cartesian            */
   double h;          /* cell size (cubic cells)                    */
-  double origin[3];  /* position of the lower box corner (informative) */
+  double origin[3];  /* position of the lower box corner (axisym: the
+                        radius of the low x side; else informative)  */
 } surf_grid;
 
 /* The problem's parameters (sections 2.3-2.6, Appendix C). */

@@ -155,6 +155,12 @@ int check_grid_params(const surf_grid* gr, const surf_params* p) {
   if (p->hj_iters_init < 0 || p->hj_iters_step < 0) return SURF_EINVAL;
   if (p->substep2 < 0 || p->substep2 > 1) return SURF_EINVAL;
   if (p->interface < 0 || p->interface > 1) return SURF_EINVAL;
+  if (gr->axisym < 0 || gr->axisym > 1) return SURF_EINVAL;
+  if (gr->axisym &&
+      (gr->dim != 2 || gr->bc[0][0] == SURF_BC_PERIODIC || !(gr->origin[0] >= 0) ||
+       !std::isfinite(gr->origin[0]) || p->flux_form != SURF_FLUX_WEIGHTED ||
+       p->substep2 != SURF_SUBSTEP2_EXPLICIT || p->interface != SURF_IFACE_VOF || p->adjoint))
+    return SURF_EINVAL;
   if (p->interface == SURF_IFACE_ACDI &&
       (!(p->acdi_zeta > 0) || !std::isfinite(p->acdi_zeta) || !(p->acdi_vareps >= 0) ||
        p->acdi_vareps >= 0.5 || p->adjoint))
@@ -497,6 +503,13 @@ bool geom2d_ok(const surf_ctx* c) {
 template <typename R, int TY>
 void launch_col2d(surf_ctx* c, const ColArgs<R>& a, bool has_u, bool bulk) {
   const dim3 grid(8 * a.per_xcd), block(64 * COL_WAVES);
+  if (c->grid.axisym) {
+    if (has_u && bulk) hipLaunchKernelGGL((k_col2d<R, TY, true, true, true>), grid, block, 0, c->stream, a);
+    else if (has_u) hipLaunchKernelGGL((k_col2d<R, TY, true, false, true>), grid, block, 0, c->stream, a);
+    else if (bulk) hipLaunchKernelGGL((k_col2d<R, TY, false, true, true>), grid, block, 0, c->stream, a);
+    else hipLaunchKernelGGL((k_col2d<R, TY, false, false, true>), grid, block, 0, c->stream, a);
+    return;
+  }
   if (has_u && bulk) hipLaunchKernelGGL((k_col2d<R, TY, true, true>), grid, block, 0, c->stream, a);
   else if (has_u) hipLaunchKernelGGL((k_col2d<R, TY, true, false>), grid, block, 0, c->stream, a);
   else if (bulk) hipLaunchKernelGGL((k_col2d<R, TY, false, true>), grid, block, 0, c->stream, a);
@@ -612,6 +625,7 @@ void col2d_transport(surf_ctx* c, const void* const* u, const void* F_in, const 
   a.part = c->part;
   a.dt = (R)c->dt;
   a.area_dt = (R)(c->grid.h * c->dt);
+  a.r0 = c->grid.origin[0];
   a.strips = c->col_strips;
   a.groups = c->col_groups;
   a.nwg = c->col_nwg;
@@ -1120,6 +1134,7 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   int n2 = ntiles_2d(grid, t2);
   int cs, cg;
   int ncol = col_shape(grid, params, &cs, &cg);
+  if (grid->axisym && ncol == 0) return SURF_EINVAL;  // the rings run on k_col2d only
   int c3s[3];
   int nc3 = col3_shape(grid, params, c3s);
   int npart = nblk > n2 ? nblk : n2;
@@ -1630,6 +1645,7 @@ int batch_layout(int32_t n, const surf_grid* grids, const surf_params* prm, Batc
   L->chi.resize(n);
   L->q.resize(n);
   for (int i = 0; i < n; ++i) {
+    if (grids[i].axisym) return SURF_EINVAL;  // the batch kernel is Cartesian
     int rc = check_grid_params(&grids[i], &prm[i]);
     if (rc) return rc;
     if (grids[i].dim != 2 || prm[i].precision != prm[0].precision) return SURF_EINVAL;

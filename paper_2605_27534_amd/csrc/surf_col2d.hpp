@@ -50,6 +50,7 @@ struct ColArgs {
   double* part;     // [workgroups][NPART]
   R dt;
   R area_dt;        // h dt: face length times the step
+  double r0;        // axisymmetric: the radius of the low x side
   int strips;       // ceil(nx / 58)
   int groups;       // ceil(chunks / 4): row-chunk groups per strip
   int nwg;          // strips * groups
@@ -117,7 +118,7 @@ struct ColAcc {
 // One wave: strip x0, rows y0 .. y0 + TY - 1 (y0 < ny).  IX: every column
 // the strip reads lies inside the box away from the x sides; IY: the same
 // for the rows and the y sides.
-template <typename R, int TY, bool HU, bool BULK, bool IX, bool IY>
+template <typename R, int TY, bool HU, bool BULK, bool IX, bool IY, bool AXI>
 __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, const int y0,
                                            const int lane, ColAcc<R>& acc) {
   constexpr int NR3 = TY + 6;  // state rows y0-3 .. y0+TY+2
@@ -151,8 +152,24 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
   // lane constants of the x sides
   const bool x_side = xf_lo || xf_hi;
   const bool x_lo_open = xf_lo && ox_lo, x_hi_open = xf_hi && ox_hi;
-  const double wlo = (!IX && !px && xs == 0 && ox_lo) ? -1.0 : 0.0;
-  const double whi = (!IX && !px && xs == nx - 1 && ox_hi) ? 1.0 : 0.0;
+  double wlo = (!IX && !px && xs == 0 && ox_lo) ? -1.0 : 0.0;
+  double whi = (!IX && !px && xs == nx - 1 && ox_hi) ? 1.0 : 0.0;
+  // axisymmetric rings (Appendix B): the lane's column is the ring between
+  // r_lo and r_hi (the mapped column for ghost lanes, whose values are never
+  // used); radial face fluxes enter its balance with r_face / r_mid, its
+  // volume is 2 pi r_mid h^2 (the reduction counts 2 pi r_mid per cell, the
+  // finalize multiplies by h^2) and its faces' areas 2 pi r h
+  R a_lo = R(1), a_hi = R(1);
+  double w_mid = 1.0;
+  if constexpr (AXI) {
+    const double rl = a.r0 + (double)mx * (double)p.h, rh = rl + (double)p.h;
+    const double rm = rl + 0.5 * (double)p.h;
+    a_lo = (R)(rl / rm);
+    a_hi = (R)(rh / rm);
+    w_mid = 2.0 * M_PI * rm;
+    wlo *= 2.0 * M_PI * rl;
+    whi *= 2.0 * M_PI * rh;
+  }
 
   // ---- loads, in the order of use: group k holds state row k (F, psi),
   // y face k-3 and level-set / x-face row k-4; iteration i consumes group i,
@@ -289,8 +306,13 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
         }
         fxLF = from_left(fxF);
         fxLP = from_left(fxP);
-        Fs = xF - cfl * ((fxF - fxLF) + (nyF - gyF));
-        Ps = xP - cfl * ((fxP - fxLP) + (nyP - gyP));
+        if constexpr (AXI) {
+          Fs = xF - cfl * ((a_hi * fxF - a_lo * fxLF) + (nyF - gyF));
+          Ps = xP - cfl * ((a_hi * fxP - a_lo * fxLP) + (nyP - gyP));
+        } else {
+          Fs = xF - cfl * ((fxF - fxLF) + (nyF - gyF));
+          Ps = xP - cfl * ((fxP - fxLP) + (nyP - gyP));
+        }
       }
       if (!IX || !IY) {
         const bool ghost = gcell_x || grow;
@@ -312,7 +334,14 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
         wxF = x_side ? R(0) : wxF;
         wxP = x_side ? R(0) : wxP;
       }
-      const R axF = wxF - from_left(wxF), axP = wxP - from_left(wxP);
+      R axF, axP;
+      if constexpr (AXI) {
+        axF = a_hi * wxF - a_lo * from_left(wxF);
+        axP = a_hi * wxP - a_lo * from_left(wxP);
+      } else {
+        axF = wxF - from_left(wxF);
+        axP = wxP - from_left(wxP);
+      }
       R wyF = (pPh + ph) * (cs - pC), wyP = (pDe + de) * (Gs - pG);
       if (!IY && !py && (s == 0 || s == ny)) { wyF = R(0); wyP = R(0); }
       const R uxL = from_left(ux);
@@ -333,10 +362,17 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
           if (BULK) gst(Fn, bFo, vxs, row);
           gst(Pn, bPo, vxs, row);
           if (a.sig) gst(sg, bS, vxs, row);
-          acc.sF += (double)Fn;
-          acc.sP += (double)Pn;
-          acc.sD += (double)pDe;
-          acc.sSD += (double)(sg * pDe);
+          if constexpr (AXI) {
+            acc.sF += w_mid * (double)Fn;
+            acc.sP += w_mid * (double)Pn;
+            acc.sD += w_mid * (double)pDe;
+            acc.sSD += w_mid * (double)(sg * pDe);
+          } else {
+            acc.sF += (double)Fn;
+            acc.sP += (double)Pn;
+            acc.sD += (double)pDe;
+            acc.sSD += (double)(sg * pDe);
+          }
           if (BULK) {
             acc.mxC = fmax(acc.mxC, quot<R>(Fn, pPh + p.eta, pIF));
             acc.mnF = fmin(acc.mnF, Fn);
@@ -348,15 +384,19 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
             R uxh = pUx, uyl = rUy[i - 5], uyh = rUy[i - 4];
             if (!IX && px && xs == nx - 1) uxh = a.u[0][(long long)(nx + 1) * o + nx];
             if (!IY && py && o == ny - 1) uyh = a.u[1][(long long)nx * ny + xs];
-            acc.usum = fmax(acc.usum, fabs(R(0.5) * (pUxL + uxh)) + fabs(R(0.5) * (uyl + uyh)));
+            if constexpr (AXI)
+              acc.usum = fmax(acc.usum, fabs(R(0.5) * (a_lo * pUxL + a_hi * uxh)) +
+                                            fabs(R(0.5) * (uyl + uyh)));
+            else
+              acc.usum = fmax(acc.usum, fabs(R(0.5) * (pUxL + uxh)) + fabs(R(0.5) * (uyl + uyh)));
             // open-side budget of the faces of this cell (lane weights
             // -1 / 0 / +1 for the x sides, uniform branches for the y sides)
             if (!IX)
               acc.out += wlo * (double)(a.area_dt * (pFxLF + pFxLP)) +
                          whi * (double)(a.area_dt * (pFxF + pFxP));
             if (!IY) {
-              if (!py && o == 0 && oy_lo) acc.out -= (double)(a.area_dt * (pGyF + pGyP));
-              if (!py && o == ny - 1 && oy_hi) acc.out += (double)(a.area_dt * (gyF + gyP));
+              if (!py && o == 0 && oy_lo) acc.out -= w_mid * (double)(a.area_dt * (pGyF + pGyP));
+              if (!py && o == ny - 1 && oy_hi) acc.out += w_mid * (double)(a.area_dt * (gyF + gyP));
             }
           }
         }
@@ -371,7 +411,7 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
   }
 }
 
-template <typename R, int TY, bool HU, bool BULK>
+template <typename R, int TY, bool HU, bool BULK, bool AXI = false>
 __global__ void __launch_bounds__(64 * COL_WAVES) k_col2d(ColArgs<R> a) {
   const int b = blockIdx.x;
   const int wg = (b & 7) * a.per_xcd + (b >> 3);  // banded over the XCDs
@@ -385,10 +425,10 @@ __global__ void __launch_bounds__(64 * COL_WAVES) k_col2d(ColArgs<R> a) {
   ColAcc<R> acc{0.0, 0.0, 0.0, 0.0, 0.0, R(0), R(-INFINITY), R(INFINITY), R(INFINITY), 0};
   if (y0 < ny) {  // chunks past the last row only join the reduction
     const bool ix = x0 >= 3 && x0 + 62 <= nx, iy = y0 >= 3 && y0 + TY + 3 <= ny;
-    if (ix && iy) col2d_wave<R, TY, HU, BULK, true, true>(a, x0, y0, lane, acc);
-    else if (iy) col2d_wave<R, TY, HU, BULK, false, true>(a, x0, y0, lane, acc);
-    else if (ix) col2d_wave<R, TY, HU, BULK, true, false>(a, x0, y0, lane, acc);
-    else col2d_wave<R, TY, HU, BULK, false, false>(a, x0, y0, lane, acc);
+    if (ix && iy) col2d_wave<R, TY, HU, BULK, true, true, AXI>(a, x0, y0, lane, acc);
+    else if (iy) col2d_wave<R, TY, HU, BULK, false, true, AXI>(a, x0, y0, lane, acc);
+    else if (ix) col2d_wave<R, TY, HU, BULK, true, false, AXI>(a, x0, y0, lane, acc);
+    else col2d_wave<R, TY, HU, BULK, false, false, AXI>(a, x0, y0, lane, acc);
   }
   double v[NPART];
   v[P_SUM_F] = acc.sF;

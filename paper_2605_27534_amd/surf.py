@@ -53,7 +53,7 @@ class SurfError(RuntimeError):
 
 class Grid(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3),
-                ("bc", (ctypes.c_int32 * 2) * 3), ("pad_", ctypes.c_int32),
+                ("bc", (ctypes.c_int32 * 2) * 3), ("axisym", ctypes.c_int32),
                 ("h", ctypes.c_double), ("origin", ctypes.c_double * 3)]
 
 
@@ -140,6 +140,7 @@ def make_structs(prob: dict, dt: float, precision: int):
         g.n[d] = int(n[d])
         g.bc[d][0], g.bc[d][1] = bc[d]
     g.h = q["h"]
+    g.axisym = int(q.get("axisym", 0))
     org = q.get("origin", (0.0, 0.0, 0.0))
     for d in range(3):
         g.origin[d] = org[d] if d < len(org) else 0.0

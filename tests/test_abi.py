@@ -163,3 +163,18 @@ def test_acdi_validation():
                 dict(adjoint=1)):
         g, p, _ = S.make_structs(dict(base, **bad), 1e-3, S.SURF_F32)
         assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == -1, bad
+
+
+def test_axisym_validation():
+    import ctypes
+    from paper_2605_27534_amd import surf as S
+    L = S.lib()
+    nb = ctypes.c_size_t(0)
+    base = dict(dim=2, n=(64, 64), h=1 / 64, bc=((0, 2), (0, 0)), axisym=1)
+    g, p, _ = S.make_structs(base, 1e-3, S.SURF_F32)
+    assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == 0
+    for bad in (dict(axisym=2), dict(bc=((1, 1), (0, 0))), dict(flux_form=1), dict(substep2=1),
+                dict(interface=1, acdi_zeta=0.5), dict(adjoint=1), dict(origin=(-0.1, 0.0, 0.0)),
+                dict(dim=3, n=(64, 64, 8), bc=((0, 2), (0, 0), (0, 0)))):
+        g, p, _ = S.make_structs(dict(base, **bad), 1e-3, S.SURF_F32)
+        assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == -1, bad
