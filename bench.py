@@ -23,6 +23,11 @@ Other workloads (one JSON line each, not the default):
       per step, HIP-graph replay), against the same instances stepped one by
       one with the plain path;
   c4  the 128^3 adjoint sphere: forward steps and checkpointed adjoint steps;
+  c1a the 1024^2 soluble expanding circle on the ACDI interface (phi advanced
+      by ACDI, re-initialized from the VoF every 50 steps), with the ACDI
+      steps timed in a burst (`acdi`);
+  c2x the translating sphere of c2 on axisymmetric rings, 512 x 1024 (run it
+      with --steps 100: its inputs are generated on the host);
   c1m the 1024^2 soluble expanding circle with substep 2 implicit (48 times
       the explicit step, at most 100 steps): steps launched eagerly (the host
       paces the CG launches; --implicit-graph adds a graph replay),
@@ -49,7 +54,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c1",
-                    choices=["c0", "c1", "c1i", "c1a", "c1m", "c2", "c3", "c4"])
+                    choices=["c0", "c1", "c1i", "c1a", "c1m", "c2", "c2x", "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--implicit-graph", action="store_true",
@@ -74,6 +79,8 @@ def workload(name, K, W):
         return C.c1_expanding_circle(soluble=False)
     if name == "c1a":
         return C.c1_acdi()
+    if name == "c2x":
+        return C.c2_axisymmetric()
     return C.c2_translating_sphere()
 
 

@@ -119,6 +119,37 @@ def c2_translating_sphere(n=256):
                 c0=None, c0_const=1.0, gamma0=0.0, hj_step=16)
 
 
+def c2_axisymmetric(nr=512, nz=1024):
+    """The translating sphere of C2 on axisymmetric rings (Appendix B): r in
+    [0, 0.5] (wall on the axis, open outside), z in [0, 1] periodic, h = 1/1024,
+    FP32; sphere R = 0.15 on the axis at z = 0.25 + U t, U = 0.5, VoF each
+    step; the Hadamard-Rybczynski flow plus U along z, nearest periodic image;
+    the bubble-scaled parameters of C2; 1000 steps at dt = 1.2e-3 (256/1024)^2."""
+    h = 1.0 / nz
+    U, R, d = 0.5, 0.15, 0.3
+    prob = dict(dim=2, n=(nr, nz), h=h, bc=((0, 2), (1, 1)), axisym=1, eos=1, eos_E=0.3,
+                sigma0=1.0, gamma_inf=1.0, D_b=U * d / 100, D_s=U * d / 1000,
+                k_d=1.0 * U / d, k_a=0.1 * U / d, hj_iters_step=16)
+    dt = 1.2e-3 * (256.0 / nz) ** 2
+    zc = lambda t: (0.25 + U * t) % 1.0
+    n = (nr, nz)
+
+    def vof(t):
+        # the meridional disc of the sphere and its periodic images in z
+        f = synth.vof_ball(n, h, (0.0, zc(t), 0), R, 2)
+        for s in (-1.0, 1.0):
+            f = np.maximum(f, synth.vof_ball(n, h, (0.0, zc(t) + s, 0), R, 2))
+        return f
+
+    return dict(name="translating sphere axisymmetric %dx%d fp32" % (nr, nz), prob=prob,
+                precision=0, dt=dt, steps=1000,
+                vof0=lambda: vof(0.0),
+                vof_seq=lambda k: vof((k + 1) * dt),
+                u_seq=lambda k: synth.u_hadamard_axi(n, h, zc(k * dt), R, -U, 0.01,
+                                                     frame_shift=U, period_z=1.0),
+                c0=None, c0_const=1.0, gamma0=0.0, hj_step=16)
+
+
 def c3_ensemble(seed=3, count=64):
     """64 independent 2D static-circle instances: n ~ choice{128, 256, 512,
     1024}, R ~ U[0.15, 0.3] centred, Bi, Da ~ 10^U[-2, 2] (drawn in the order

@@ -239,6 +239,24 @@ def u_hadamard(n, h, centre, a, V, lam, frame_shift=0.0, origin=(0.0, 0.0, 0.0),
     return out
 
 
+def u_hadamard_axi(n, h, zc, a, V, lam, frame_shift=0.0, origin=(0.0, 0.0, 0.0),
+                   period_z=None):
+    """The Hadamard-Rybczynski flow of `u_hadamard` on an axisymmetric (r, z)
+    grid (x the radius from origin[0], y the axis), the sphere on the axis at
+    z = zc: u_r on the radial faces, u_z (+ frame_shift) on the axial faces."""
+    out = []
+    for d in range(2):
+        X, Y, _ = face_centres(n, h, d, origin)
+        shp = face_centres_shape(n, d)
+        R = np.broadcast_to(X, shp)
+        Zc = np.broadcast_to(Y - zc, shp)
+        if period_z is not None:
+            Zc = Zc - period_z * np.round(Zc / period_z)
+        ur, _, uz = _hr_velocity(R, np.zeros(shp), Zc, a, V, lam)
+        out.append(np.ascontiguousarray(ur if d == 0 else uz + frame_shift))
+    return out
+
+
 def smooth_modes(n, h, seed, nmodes=8, kmax=3, dim=3, origin=(0.0, 0.0, 0.0)):
     """Sum of `nmodes` cosine modes with integer wave vectors |k|_inf <= kmax
     and random phases, normalised to max |s| = 1 (seeded)."""
