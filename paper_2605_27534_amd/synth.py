@@ -79,6 +79,28 @@ def vof_ball(n, h, centre, R, dim, sub=8, origin=(0.0, 0.0, 0.0), period_z=None)
     return f
 
 
+def vof_disc(n, h, centre, R, samples=256, origin=(0.0, 0.0, 0.0)):
+    """2D fraction of each cell inside a circle, integrated along x with the
+    midpoint rule (`samples` points per cell) over the exact covered length
+    in y: relative errors of order (1/samples)^2, against 1/64 for the
+    subcell count of vof_ball (what curvature from volume fractions needs)."""
+    nx, ny = n[0], n[1]
+    x0 = origin[0] + np.arange(nx) * h
+    y0 = origin[1] + np.arange(ny) * h
+    t = (np.arange(samples) + 0.5) / samples * h
+    f = np.zeros((1, ny, nx))
+    for i in range(nx):
+        xs = x0[i] + t - centre[0]
+        s = np.sqrt(np.maximum(R * R - xs * xs, 0.0))
+        lo = np.maximum(y0[:, None], centre[1] - s[None, :])
+        hi = np.minimum(y0[:, None] + h, centre[1] + s[None, :])
+        f[0, :, i] = np.mean(np.clip(hi - lo, 0.0, h), axis=1) / h
+    # full and empty cells exactly (the sums above round)
+    f[f > 1.0 - 1e-13] = 1.0
+    f[f < 1e-13] = 0.0
+    return f
+
+
 def vof_flat(n, h, y0, origin=(0.0, 0.0, 0.0)):
     """Flat interface at y = y0, fluid 1 below: f = fraction of the cell
     below y0 (exact)."""
