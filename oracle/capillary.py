@@ -84,40 +84,44 @@ def levelset_curvature(prob, chi, j, i):
     return kc / (1.0 - c(0, 0) * kc)
 
 
-def curvature(prob, vof, chi):
-    """kappa in every cell with 0 < c < 1 (0 elsewhere), 2D."""
+def cell_curvature(prob, vof, chi, j, i):
+    """kappa of cell (j, i) (assumed interfacial), 2D."""
     q = O.full(prob)
     per = _axes(q)
     h = q["h"]
+    v = np.asarray(vof, dtype=np.float64)[0]
+    mx, my = youngs_normal(v, j, i, q, per)
+    vert = abs(my) >= abs(mx)  # columns along y
+    out = my if vert else mx   # the normal's component along the columns
+    H = []
+    ok = True
+    for kk in (-1, 0, 1):
+        col = []
+        for l in range(-3, 4):
+            col.append(_at(v, j + l, i + kk, q, per) if vert else
+                       _at(v, j + kk, i + l, q, per))
+        # fluid 1 lies against the normal: at the low end when the normal
+        # points to +, at the high end otherwise
+        full, empty = (col[0], col[-1]) if out > 0 else (col[-1], col[0])
+        if not (full >= 1.0 - CUT and empty <= CUT):
+            ok = False
+        H.append(sum(col))
+    if ok:
+        d1 = 0.5 * (H[2] - H[0])
+        d2 = (H[2] - 2.0 * H[1] + H[0]) / h
+        return d2 / (1.0 + d1 * d1) ** 1.5
+    return levelset_curvature(prob, chi, j, i)
+
+
+def curvature(prob, vof, chi):
+    """kappa in every cell with 0 < c < 1 (0 elsewhere), 2D."""
     v = np.asarray(vof, dtype=np.float64)[0]
     ny, nx = v.shape
     k = np.zeros_like(v)
     for j in range(ny):
         for i in range(nx):
-            if not interfacial(v[j, i]):
-                continue
-            mx, my = youngs_normal(v, j, i, q, per)
-            vert = abs(my) >= abs(mx)  # columns along y
-            out = my if vert else mx   # the normal's component along the columns
-            H = []
-            ok = True
-            for kk in (-1, 0, 1):
-                col = []
-                for l in range(-3, 4):
-                    col.append(_at(v, j + l, i + kk, q, per) if vert else
-                               _at(v, j + kk, i + l, q, per))
-                # fluid 1 lies against the normal: at the low end when the
-                # normal points to +, at the high end otherwise
-                full, empty = (col[0], col[-1]) if out > 0 else (col[-1], col[0])
-                if not (full >= 1.0 - CUT and empty <= CUT):
-                    ok = False
-                H.append(sum(col))
-            if ok:
-                d1 = 0.5 * (H[2] - H[0])
-                d2 = (H[2] - 2.0 * H[1] + H[0]) / h
-                k[j, i] = d2 / (1.0 + d1 * d1) ** 1.5
-            else:
-                k[j, i] = levelset_curvature(prob, chi, j, i)
+            if interfacial(v[j, i]):
+                k[j, i] = cell_curvature(prob, vof, chi, j, i)
     return k[None]
 
 
@@ -197,25 +201,34 @@ def youngs_normal(vof, j, i, q, per):
     return mx, my
 
 
-def marangoni_delta(prob, vof):
-    """delta_m = A_f / V_c per cell (2D)."""
+def cell_delta(prob, vof, j, i):
+    """delta_m = A_f / V_c of cell (j, i), 2D (0 unless interfacial)."""
     q = O.full(prob)
     per = _axes(q)
+    v = np.asarray(vof, dtype=np.float64)[0]
+    c = v[j, i]
+    if not interfacial(c):
+        return 0.0
+    return plic_chord(youngs_normal(v, j, i, q, per), c) / q["h"]
+
+
+def marangoni_delta(prob, vof):
+    """delta_m = A_f / V_c per cell (2D)."""
     v = np.asarray(vof, dtype=np.float64)[0]
     ny, nx = v.shape
     out = np.zeros_like(v)
     for j in range(ny):
         for i in range(nx):
-            c = v[j, i]
-            if interfacial(c):
-                m = youngs_normal(v, j, i, q, per)
-                out[j, i] = plic_chord(m, c) / q["h"]
+            if interfacial(v[j, i]):
+                out[j, i] = cell_delta(prob, vof, j, i)
     return out[None]
 
 
-def forces(prob, vof, chi, sigma):
-    """(capillary [fx, fy], Marangoni [fx, fy]) on the faces (2D, face
-    layouts [ny][nx+1] and [ny+1][nx])."""
+def face_force(prob, vof, chi, sigma, d, j, i, kap=None, dm=None):
+    """(capillary, Marangoni) on face (j, i) of the faces along d (layouts
+    [ny][nx+1] and [ny+1][nx]).  kap and dm: the per-cell curvature and
+    delta_m fields when already computed, else the two cells' values are
+    computed here."""
     q = O.full(prob)
     per = _axes(q)
     h = q["h"]
@@ -223,8 +236,58 @@ def forces(prob, vof, chi, sigma):
     v = np.asarray(vof, dtype=np.float64)[0]
     ch = np.asarray(chi, dtype=np.float64)[0]
     sg = np.asarray(sigma, dtype=np.float64)[0]
-    kap = curvature(prob, vof, chi)[0]
-    dm = marangoni_delta(prob, vof)[0]
+    f = (i, j)[d]
+    nd = (nx, ny)[d]
+    if (f == 0 or f == nd) and not per[d]:
+        return 0.0, 0.0
+    # cells L and R of the face (the last face of a periodic axis is the first)
+    if d == 0:
+        iR, jR = i % nx, j
+        iL, jL = (i - 1) % nx, j
+    else:
+        iR, jR = i, j % ny
+        iL, jL = i, (j - 1) % ny
+    cutL = interfacial(v[jL, iL])
+    cutR = interfacial(v[jR, iR])
+    kapc = (lambda jj, ii: kap[0][jj, ii]) if kap is not None else \
+        (lambda jj, ii: cell_curvature(prob, vof, chi, jj, ii))
+    dmc = (lambda jj, ii: dm[0][jj, ii]) if dm is not None else \
+        (lambda jj, ii: cell_delta(prob, vof, jj, ii))
+    sf = 0.5 * (sg[jL, iL] + sg[jR, iR])
+    if cutL and cutR:
+        kf = 0.5 * (kapc(jL, iL) + kapc(jR, iR))
+    else:
+        kf = kapc(jL, iL) if cutL else (kapc(jR, iR) if cutR else 0.0)
+    cap = -sf * kf * (v[jR, iR] - v[jL, iL]) / h
+
+    def face_grad(a):
+        g = [0.0, 0.0]
+        g[d] = (a[jR, iR] - a[jL, iL]) / h
+        t = 1 - d
+        dl = [0, 0]
+        dl[t] = 1
+        for (jj, ii) in ((jL, iL), (jR, iR)):
+            g[t] += 0.5 * (_at(a, jj + dl[1], ii + dl[0], q, per) -
+                           _at(a, jj - dl[1], ii - dl[0], q, per)) / (2 * h)
+        return g
+    gs = face_grad(sg)
+    gc = face_grad(ch)
+    nrm = max(math.hypot(gc[0], gc[1]), 1e-6)
+    n = (gc[0] / nrm, gc[1] / nrm)
+    ndot = n[0] * gs[0] + n[1] * gs[1]
+    dL = dmc(jL, iL) if cutL else 0.0
+    dR = dmc(jR, iR) if cutR else 0.0
+    dmf = 0.5 * (dL + dR)
+    return cap, dmf * (gs[d] - n[d] * ndot)
+
+
+def forces(prob, vof, chi, sigma):
+    """(capillary [fx, fy], Marangoni [fx, fy]) on the faces (2D, face
+    layouts [ny][nx+1] and [ny+1][nx])."""
+    q = O.full(prob)
+    nx, ny = q["n"][0], q["n"][1]
+    kap = curvature(prob, vof, chi)
+    dm = marangoni_delta(prob, vof)
     cap = [np.zeros((1, ny, nx + 1)), np.zeros((1, ny + 1, nx))]
     ma = [np.zeros((1, ny, nx + 1)), np.zeros((1, ny + 1, nx))]
     for d in range(2):
@@ -232,51 +295,6 @@ def forces(prob, vof, chi, sigma):
         m[d] += 1
         for j in range(m[1]):
             for i in range(m[0]):
-                f = (i, j)[d]
-                nd = (nx, ny)[d]
-                if (f == 0 or f == nd) and not per[d]:
-                    continue
-                # cells L and R of the face
-                iR, jR = i, j
-                if d == 0:
-                    iR = i % nx
-                    iL, jL = (i - 1) % nx, j
-                else:
-                    jR = j % ny
-                    iL, jL = i, (j - 1) % ny
-                sf = 0.5 * (sg[jL, iL] + sg[jR, iR])
-                cutL = interfacial(v[jL, iL])
-                cutR = interfacial(v[jR, iR])
-                if cutL and cutR:
-                    kf = 0.5 * (kap[jL, iL] + kap[jR, iR])
-                else:
-                    kf = kap[jL, iL] if cutL else (kap[jR, iR] if cutR else 0.0)
-                cap[d][0, j, i] = -sf * kf * (v[jR, iR] - v[jL, iL]) / h
-
-                def face_grad(a):
-                    g = [0.0, 0.0]
-                    g[d] = (a[jR, iR] - a[jL, iL]) / h
-                    t = 1 - d
-                    dl = [0, 0]
-                    dl[t] = 1
-                    for (jj, ii) in ((jL, iL), (jR, iR)):
-                        g[t] += 0.5 * (_at(a, jj + dl[1], ii + dl[0], q, per) -
-                                       _at(a, jj - dl[1], ii - dl[0], q, per)) / (2 * h)
-                    return g
-                gs = face_grad(sg)
-                gc = face_grad(ch)
-                nrm = max(math.hypot(gc[0], gc[1]), 1e-6)
-                n = (gc[0] / nrm, gc[1] / nrm)
-                ndot = n[0] * gs[0] + n[1] * gs[1]
-                dmf = 0.5 * (dm[jL, iL] + dm[jR, iR])
-                ma[d][0, j, i] = dmf * (gs[d] - n[d] * ndot)
-    # periodic: the last face is the first face
-    for d in range(2):
-        if per[d]:
-            if d == 0:
-                cap[0][..., nx] = cap[0][..., 0]
-                ma[0][..., nx] = ma[0][..., 0]
-            else:
-                cap[1][:, ny, :] = cap[1][:, 0, :]
-                ma[1][:, ny, :] = ma[1][:, 0, :]
+                cap[d][0, j, i], ma[d][0, j, i] = face_force(prob, vof, chi, sigma, d, j, i,
+                                                             kap, dm)
     return cap, ma
