@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c1",
-                    choices=["c0", "c1", "c1i", "c1a", "c1m", "c2", "c2x", "c3", "c4"])
+                    choices=["c0", "c1", "c1i", "c1a", "c1f", "c1m", "c2", "c2x", "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--implicit-graph", action="store_true",
@@ -79,6 +79,8 @@ def workload(name, K, W):
         return C.c1_expanding_circle(soluble=False)
     if name == "c1a":
         return C.c1_acdi()
+    if name == "c1f":
+        return C.c1_forces()
     if name == "c2x":
         return C.c2_axisymmetric()
     return C.c2_translating_sphere()
@@ -220,6 +222,10 @@ def main():
         bufs = [[s.empty() if bulk else None, s.empty()] for _ in range(2)]
         sig = s.empty()
         hist = torch.zeros((W + K, 16), dtype=torch.float64, device=dev)
+        forces = None
+        if cfg.get("forces"):  # capillary and Marangoni face arrays
+            forces = tuple([torch.empty(s.face_shape(d), dtype=s.dtype, device=dev)
+                            for d in range(2)] for _ in range(2))
 
         def reset():
             s.set_geometry(vof0, full=True)
@@ -233,6 +239,8 @@ def main():
             u = u_list[k] if u_list is not None else u_static
             v = vofs[k] if vofs is not None else None
             s.step(a[0], a[1], b[0], b[1], u=u, vof_next=v, sigma_out=sig, totals=hist[k])
+            if forces is not None:
+                s.interface_force(v if v is not None else vof0, sig, out=forces)
 
         # 2D moving interface: step k+1's geometry is prepared on `aux` while
         # step k's transport runs on `side`; every run of steps ends with no
@@ -296,6 +304,19 @@ def main():
             burst_ms = s.time_transport(a[0], a[1], b[0], b[1], u=u, sigma_out=sig,
                                         reps=burst_reps)
         acdi_ms = s.time_acdi(u=u_static, reps=200) if reinit else None
+        force_ms = None
+        if forces is not None:  # the force kernel alone, back to back
+            v_last = vofs[W + K - 1] if vofs is not None else vof0
+            for _ in range(10):
+                s.interface_force(v_last, sig, out=forces)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(side)
+            for _ in range(FORCE_REPS):
+                s.interface_force(v_last, sig, out=forces)
+            e1.record(side)
+            side.synchronize()
+            force_ms = e0.elapsed_time(e1) / FORCE_REPS
 
     ms_per_step = ms_total / K
     traffic = measured_traffic(cfg["name"])
@@ -344,6 +365,15 @@ def main():
             "bytes_per_cell": ab, "achieved": round(ab * ncell / (acdi_ms * 1e-3) / 1e9, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ab * ncell / (acdi_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if force_ms is not None:
+        fb = FORCE_WORDS_PER_CELL * es
+        out["config"]["interface_forces"] = True
+        out["iface"] = {
+            "kernel": "k_iface_force", "avg_launch_us": round(force_ms * 1e3, 3),
+            "timing": "%d back-to-back launches between HIP events" % FORCE_REPS,
+            "bytes_per_cell": fb, "achieved": round(fb * ncell / (force_ms * 1e-3) / 1e9, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(fb * ncell / (force_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -470,6 +500,11 @@ def bench_adjoint(args):
 # ACDI: k_acdi_adv reads phi and the d face velocities, writes phi* and s;
 # k_acdi_reg reads phi* and s, writes phi and chi (2D: 5 + 4 words)
 ACDI_WORDS_PER_CELL = 9
+# interfacial forces (2D): read the VoF and sigma, write the capillary and
+# Marangoni forces on the x and y faces (about one face per cell and axis);
+# the level set is read only round the interface
+FORCE_WORDS_PER_CELL = 6
+FORCE_REPS = 200
 CG_ITER_BYTES_PER_CELL = 13 * 8  # reads x p r w z minv dg w_face, writes x p r w z
 
 
@@ -498,6 +533,10 @@ def bench_implicit(args):
         bufs = [[s.empty(), s.empty()] for _ in range(2)]
         sig = s.empty()
         hist = torch.zeros((W + K, 16), dtype=torch.float64, device=dev)
+        forces = None
+        if cfg.get("forces"):  # capillary and Marangoni face arrays
+            forces = tuple([torch.empty(s.face_shape(d), dtype=s.dtype, device=dev)
+                            for d in range(2)] for _ in range(2))
 
         def reset():
             s.set_geometry(vof0, full=True)
@@ -666,25 +705,34 @@ def cpu_baseline(cfg, seconds):
                 st["chi"] = A.chi_of_phi(prob, st["phi"])
         elif vk is not None:
             st["chi"] = O.geometry(prob, vk, hj, chi=st["chi"])
-        F, P, _, tot = O.step(prob, st["chi"], uk, F, P, cfg["dt"], tot)
+        F, P, S, tot = O.step(prob, st["chi"], uk, F, P, cfg["dt"], tot)
+        if cfg.get("forces"):
+            K.forces(prob, vk if vk is not None else vof0, st["chi"], S)
         return F, P, tot
 
+    if cfg.get("forces"):
+        from oracle import capillary as K
     tot = np.zeros(16)
     vk, uk = inputs(0)
     t = time.perf_counter()
     F, P, tot = one(vk, uk, F, P, tot)
     probe = time.perf_counter() - t
-    nsteps = max(1, min(200, int(seconds / max(probe, 1e-6))))
-    el = 0.0
-    for k in range(1, nsteps + 1):
-        vk, uk = inputs(k)
-        t = time.perf_counter()
-        F, P, tot = one(vk, uk, F, P, tot)
-        el += time.perf_counter() - t
-    what = "ACDI step" if reinit else "geometry warm start"
+    if probe >= seconds:  # one step is already the sample
+        nsteps, el = 1, probe
+    else:
+        nsteps = max(1, min(200, int(seconds / max(probe, 1e-6))))
+        el = 0.0
+        for k in range(1, nsteps + 1):
+            vk, uk = inputs(k)
+            t = time.perf_counter()
+            F, P, tot = one(vk, uk, F, P, tot)
+            el += time.perf_counter() - t
+    what = ("ACDI step" if reinit else "geometry warm start") + " + step"
+    if cfg.get("forces"):
+        what += " + interfacial forces"
     return {"value": round(ncell * nsteps / el / 1e9, 6), "unit": "Gcell-updates/s", "cores": 1,
             "kind": "oracle",
-            "sample": "first %d steps of the same workload (%s + step), FP64, one host thread, "
+            "sample": "first %d steps of the same workload (%s), FP64, one host thread, "
                       "%.1f s" % (nsteps, what, el)}
 
 

@@ -287,6 +287,33 @@ int surf_time_acdi(surf_ctx* ctx, const void* const* u, int32_t reps, double* ms
  * face layout of u.  Faces on walls and open boundaries get 0. */
 int surf_force(surf_ctx* ctx, const void* sigma, void* const* force);
 
+/* The interfacial forces of the coupling to a flow solver (section 2.4, the
+ * capillary force and the Marangoni force with delta_m = A_f / V_c), 2D
+ * Cartesian, on the faces of u.  Inputs (device, context precision, cell
+ * layout): vof, the VoF fraction of fluid 1, and sigma, the surface tension
+ * (e.g. surf_step's sigma_out); the context's cached level set supplies the
+ * normal and the curvature fallback.  Outputs (device, caller-owned):
+ * f_cap[0..1] and f_ma[0..1], the x- and y-face arrays ([ny][nx+1] and
+ * [ny+1][nx]) of
+ *   capillary  -sigma_f kappa_f (c_R - c_L)/h, kappa by height functions
+ *              (seven-cell columns along the larger component of the Youngs
+ *              normal; the level-set curvature where a column does not
+ *              close) in cells with 1e-6 < c < 1 - 1e-6, on a face the mean
+ *              over its interfacial cells, sigma_f the mean of both;
+ *   Marangoni  delta_m,f (grad sigma - n (n . grad sigma)), delta_m the
+ *              length of the PLIC line (Youngs normal, closed-form plane
+ *              constant) in each interfacial cell over h, on a face the
+ *              mean of both cells; grad sigma and n from the face gradients
+ *              of sigma and chi as in surf_force.
+ * Either array pair may be NULL (not both).  Faces on walls and open sides
+ * get 0; on a periodic axis the last face repeats the first.  Enqueued on
+ * the context's stream.  SURF_EINVAL for a 3D or axisymmetric grid, an axis
+ * under 4 cells, (nx+1)(ny+1) >= 2^30, NULL inputs or a NULL array in a
+ * given pair; SURF_ESTATE without a level set or with a prepared geometry
+ * pending. */
+int surf_interface_force(surf_ctx* ctx, const void* vof, const void* sigma, void* const* f_cap,
+                         void* const* f_ma);
+
 /* Changes the time step used by the following steps. */
 int surf_set_dt(surf_ctx* ctx, double dt);
 

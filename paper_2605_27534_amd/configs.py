@@ -85,6 +85,17 @@ def c1_acdi(n=1024, reinit_every=50):
     return cfg
 
 
+def c1_forces(n=1024):
+    """The soluble expanding circle with the interfacial forces of the flow
+    coupling (section 2.4) evaluated after every step: capillary and Marangoni
+    forces on the faces from the step's VoF and the sigma it returns; the rest
+    as C1."""
+    cfg = c1_expanding_circle(n, soluble=True,
+                              name="expanding circle %d^2 fp32 soluble forces" % n)
+    cfg["forces"] = True
+    return cfg
+
+
 def c2_translating_sphere(n=256):
     """256^3 FP32, periodic in z, open in x and y; sphere R = 0.15 with centre
     (0.5, 0.5, 0.25 + U t), U = 0.5, VoF each step; lab-frame

@@ -17,6 +17,7 @@
 #include "surf_adjoint.hpp"
 #include "surf_implicit.hpp"
 #include "surf_acdi.hpp"
+#include "surf_capillary.hpp"
 
 using namespace surf;
 
@@ -1041,6 +1042,25 @@ int force_impl(surf_ctx* c, const void* sigma, void* const* force) {
   return status_of_launch();
 }
 
+template <typename R>
+int iface_force_impl(surf_ctx* c, const void* vof, const void* sigma, void* const* cap,
+                     void* const* ma) {
+  materialize<R>(c);
+  IfaceArgs<R> a;
+  a.g = c->g;
+  a.p = make_par<R>(c);
+  a.vof = (const R*)vof;
+  a.chi = (const R*)c->chi[c->chi_cur];
+  a.sig = (const R*)sigma;
+  a.h = c->grid.h;
+  const unsigned tiles =
+      (unsigned)iface_tiles_x(c->grid.n[0]) * (unsigned)iface_tiles_y(c->grid.n[1]);
+  hipLaunchKernelGGL(k_iface_force<R>, dim3(tiles), dim3(IF_THREADS), 0, c->stream, a,
+                     cap ? (R*)cap[0] : nullptr, cap ? (R*)cap[1] : nullptr,
+                     ma ? (R*)ma[0] : nullptr, ma ? (R*)ma[1] : nullptr);
+  return status_of_launch();
+}
+
 bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
 // ---------------------------------------------------------------- batches
@@ -1508,6 +1528,20 @@ int surf_force(surf_ctx* c, const void* sigma, void* const* force) {
   if (!c->has_chi) return SURF_ESTATE;
   if (c->prm.precision == SURF_F64) return force_impl<double>(c, sigma, force);
   return force_impl<float>(c, sigma, force);
+}
+
+int surf_interface_force(surf_ctx* c, const void* vof, const void* sigma, void* const* f_cap,
+                         void* const* f_ma) {
+  if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
+  if (!c || !vof || !sigma || (!f_cap && !f_ma)) return SURF_EINVAL;
+  if (c->grid.dim != 2 || c->grid.axisym) return SURF_EINVAL;
+  if (c->grid.n[0] < 4 || c->grid.n[1] < 4) return SURF_EINVAL;
+  if ((long long)(c->grid.n[0] + 1) * (c->grid.n[1] + 1) >= (1ll << 30)) return SURF_EINVAL;
+  for (int d = 0; d < 2; ++d)
+    if ((f_cap && !f_cap[d]) || (f_ma && !f_ma[d])) return SURF_EINVAL;
+  if (!c->has_chi) return SURF_ESTATE;
+  if (c->prm.precision == SURF_F64) return iface_force_impl<double>(c, vof, sigma, f_cap, f_ma);
+  return iface_force_impl<float>(c, vof, sigma, f_cap, f_ma);
 }
 
 int surf_set_dt(surf_ctx* c, double dt) {

@@ -34,7 +34,7 @@ ERRORS = {0: "ok", -1: "invalid argument", -2: "workspace too small",
 EXPORTS = [
     "surf_workspace_bytes", "surf_init", "surf_set_geometry", "surf_set_levelset",
     "surf_get_levelset", "surf_get_phase", "surf_init_state", "surf_step", "surf_prepare_geometry",
-    "surf_time_transport", "surf_force", "surf_set_dt",
+    "surf_time_transport", "surf_force", "surf_interface_force", "surf_set_dt",
     "surf_get_status", "surf_clear_status", "surf_solver_iterations", "surf_time_solver", "surf_time_acdi",
     "surf_destroy", "surf_strerror", "surf_version",
     "surf_profile_enable", "surf_profile_read", "surf_set_kinetics", "surf_loss_weights",
@@ -96,6 +96,7 @@ def lib():
         L.surf_init_state.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp]
         L.surf_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.surf_force.argtypes = [vp, vp, vp]
+        L.surf_interface_force.argtypes = [vp, vp, vp, vp, vp]
         L.surf_prepare_geometry.argtypes = [vp, vp, vp]
         L.surf_time_transport.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_double)]
@@ -296,6 +297,20 @@ class Surf:
                                       for d in range(3)])
         self._check(self.L.surf_force(self.ctx, _ptr(self._cell(sigma, "sigma")), arr),
                     "surf_force")
+        return out
+
+    def interface_force(self, vof, sigma, cap=True, ma=True, out=None):
+        """(capillary [fx, fy], Marangoni [fx, fy]) on the faces, 2D; a pair
+        not asked for is None.  `out` = (cap, ma) reuses caller arrays."""
+        if out is None:
+            mk = lambda: [torch.empty(self.face_shape(d), dtype=self.dtype, device=self.device)
+                          for d in range(2)]
+            out = (mk() if cap else None, mk() if ma else None)
+        arrs = [None if o is None else self._faces(o, "force") for o in out]
+        self._check(self.L.surf_interface_force(self.ctx, _ptr(self._cell(vof, "vof")),
+                                                _ptr(self._cell(sigma, "sigma")), arrs[0],
+                                                arrs[1]),
+                    "surf_interface_force")
         return out
 
     def set_dt(self, dt):

@@ -178,3 +178,43 @@ def test_axisym_validation():
                 dict(dim=3, n=(64, 64, 8), bc=((0, 2), (0, 0), (0, 0)))):
         g, p, _ = S.make_structs(dict(base, **bad), 1e-3, S.SURF_F32)
         assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == -1, bad
+
+
+def test_interface_force_validation():
+    """surf_interface_force rejects 3D and axisymmetric grids, missing
+    inputs and half-given output pairs before touching the device, and asks
+    for a level set first."""
+    import ctypes
+    from paper_2605_27534_amd import surf as S
+    L = S.lib()
+
+    def ctx_of(prob):
+        g, p, _ = S.make_structs(prob, 1e-3, S.SURF_F32)
+        nb = ctypes.c_size_t(0)
+        assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == 0
+        buf = ctypes.create_string_buffer(nb.value + 512)
+        base = (ctypes.addressof(buf) + 255) // 256 * 256
+        ctx = ctypes.c_void_p()
+        assert L.surf_init(ctypes.byref(ctx), ctypes.byref(g), ctypes.byref(p),
+                           ctypes.c_void_p(base), nb, None) == 0
+        return ctx, buf, base
+
+    two = dict(dim=2, n=(32, 24), h=1.0 / 32, bc=((0, 0), (1, 1)))
+    ctx, buf, base = ctx_of(two)
+    p = ctypes.c_void_p(base)
+    pair = (ctypes.c_void_p * 2)(base, base)
+    half = (ctypes.c_void_p * 2)(base, None)
+    assert L.surf_interface_force(ctx, p, p, pair, pair) == -4  # no level set
+    assert L.surf_interface_force(ctx, p, p, pair, None) == -4
+    assert L.surf_interface_force(ctx, p, p, None, None) == -1
+    assert L.surf_interface_force(ctx, None, p, pair, pair) == -1
+    assert L.surf_interface_force(ctx, p, None, pair, pair) == -1
+    assert L.surf_interface_force(ctx, p, p, half, pair) == -1
+    assert L.surf_interface_force(ctx, p, p, pair, half) == -1
+    assert L.surf_interface_force(None, p, p, pair, pair) == -1
+    assert L.surf_destroy(ctx) == 0
+    for bad in (dict(dim=3, n=(16, 16, 16), bc=((0, 0), (0, 0), (0, 0))),
+                dict(axisym=1, bc=((0, 2), (0, 0)))):
+        ctx, buf, base = ctx_of(dict(two, **bad))
+        assert L.surf_interface_force(ctx, p, p, pair, pair) == -1, bad
+        assert L.surf_destroy(ctx) == 0
