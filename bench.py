@@ -131,14 +131,24 @@ def kernel_source_digest(sources):
     return hs.hexdigest()[:16]
 
 
-def measured_traffic(workload_name):
-    """HBM-side bytes per launch of the workload's dominant kernel from the
-    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE,
-    copy-calibrated), or None when there is none for this workload or the
-    kernel source changed since the counters were taken."""
-    if workload_name not in TRAFFIC:
+# the same for the interfacial-force kernel of the c1f workload
+IFACE_TRAFFIC = {
+    "expanding circle 1024^2 fp32 soluble forces": (
+        "k_iface_force_expanding_circle_forces_1024_traffic.md",
+        ("surf_common.hpp", "surf_kernels.hpp", "surf_capillary.hpp")),
+}
+
+
+def measured_traffic(workload_name, table=None):
+    """HBM-side bytes per launch of the workload's dominant kernel (or of the
+    kernel `table` covers) from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is none
+    for this workload or the kernel source changed since the counters were
+    taken."""
+    table = TRAFFIC if table is None else table
+    if workload_name not in table:
         return None
-    fname, sources = TRAFFIC[workload_name]
+    fname, sources = table[workload_name]
     try:
         txt = open(os.path.join(ROOT, "profiles", fname)).read()
     except OSError:
@@ -373,7 +383,8 @@ def main():
             "timing": "%d back-to-back launches between HIP events" % FORCE_REPS,
             "bytes_per_cell": fb, "achieved": round(fb * ncell / (force_ms * 1e-3) / 1e9, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(fb * ncell / (force_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "frac": round(fb * ncell / (force_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(cfg["name"], IFACE_TRAFFIC)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -500,10 +511,10 @@ def bench_adjoint(args):
 # ACDI: k_acdi_adv reads phi and the d face velocities, writes phi* and s;
 # k_acdi_reg reads phi* and s, writes phi and chi (2D: 5 + 4 words)
 ACDI_WORDS_PER_CELL = 9
-# interfacial forces (2D): read the VoF and sigma, write the capillary and
-# Marangoni forces on the x and y faces (about one face per cell and axis);
-# the level set is read only round the interface
-FORCE_WORDS_PER_CELL = 6
+# interfacial forces (2D): read the VoF, write the capillary and Marangoni
+# forces on the x and y faces (about one face per cell and axis); the level
+# set and sigma are read only in tiles that hold interface
+FORCE_WORDS_PER_CELL = 5
 FORCE_REPS = 200
 CG_ITER_BYTES_PER_CELL = 13 * 8  # reads x p r w z minv dg w_face, writes x p r w z
 
