@@ -35,7 +35,7 @@ BC_WALL, BC_PERIODIC, BC_OPEN = 0, 1, 2
 DEFAULTS = dict(
     flux_form=0, kinetics=0, eos=0, bulk_enabled=1, D_b=1e-2, D_s=1e-3,
     k_a=1.0, k_d=1.0, gamma_inf=1.0, sigma0=1.0, eos_E=0.5, eta=1e-12,
-    chi_max_eps=12.0, cfl_adv=0.5, cfl_diff=0.8, axisym=0,
+    chi_max_eps=12.0, cfl_adv=0.5, cfl_diff=0.8, axisym=0, limiter=0, bcg_transverse=0,
 )
 
 
@@ -82,7 +82,8 @@ def pack(prob: dict):
         assert (b[0] == BC_PERIODIC) == (b[1] == BC_PERIODIC), "periodic axes wrap on both sides"
     ip = np.array([q["dim"], *q["n"], bc[0][0], bc[0][1], bc[1][0], bc[1][1],
                    bc[2][0], bc[2][1], q["flux_form"], q["kinetics"], q["eos"],
-                   q["bulk_enabled"], int(q["axisym"]), 0], dtype=np.int32)
+                   q["bulk_enabled"], int(q["axisym"]), int(q["limiter"]),
+                   int(q["bcg_transverse"])], dtype=np.int32)
     r0 = float(q.get("origin", (0.0, 0.0, 0.0))[0])
     dp = np.array([q["h"], q["eps"], q["D_b"], q["D_s"], q["k_a"], q["k_d"],
                    q["gamma_inf"], q["sigma0"], q["eos_E"], q["eta"],

@@ -26,6 +26,8 @@
  *   ip[10] flux form (0 weighted, 1 paper)  ip[11] kinetics (0 Langmuir,
  *   1 Henry)  ip[12] EoS (0 linear, 1 Langmuir, 2 tanh)  ip[13] bulk on
  *   ip[14] axisymmetric (2D only: x is the radius r, y the axis z)
+ *   ip[15] slope limiter of substep 1 (0 minmod, 1 monotonized central)
+ *   ip[16] BCG transverse term in substep 1 (0 off, 1 on)
  *   dp[0] h  dp[1] eps  dp[2] D_b  dp[3] D_s  dp[4] k_a  dp[5] k_d
  *   dp[6] Gamma_inf  dp[7] sigma0  dp[8] E  dp[9] eta  dp[10] chi_max/eps
  *   dp[11] advective safety factor  dp[12] diffusive safety factor
@@ -49,7 +51,7 @@ enum {
 
 typedef struct {
   int dim, n[3], bc[3][2];
-  int form, kin, eos, bulk, axi;
+  int form, kin, eos, bulk, axi, lim, trans;
   double h, eps, Db, Ds, ka, kd, ginf, sigma0, E, eta, chimax, cfl_a, cfl_d, r0;
   long ncell;
 } Prob;
@@ -62,6 +64,7 @@ static Prob unpack(const int* ip, const double* dp) {
   p.bc[1][0] = ip[6]; p.bc[1][1] = ip[7];
   p.bc[2][0] = ip[8]; p.bc[2][1] = ip[9];
   p.form = ip[10]; p.kin = ip[11]; p.eos = ip[12]; p.bulk = ip[13]; p.axi = ip[14];
+  p.lim = ip[15]; p.trans = ip[16];
   p.h = dp[0]; p.eps = dp[1]; p.Db = dp[2]; p.Ds = dp[3];
   p.ka = dp[4]; p.kd = dp[5]; p.ginf = dp[6]; p.sigma0 = dp[7]; p.E = dp[8];
   p.eta = dp[9]; p.chimax = dp[10] * dp[1]; p.cfl_a = dp[11]; p.cfl_d = dp[12];
@@ -293,7 +296,9 @@ int or_init_state(const int* ip, const double* dp, const double* chi,
 
 /* ------------------------------------------------------------------ */
 /* Substep 1: explicit advection (section 3.1, BCG-type upwind face    */
-/* values with a minmod-limited slope and the normal predictor)        */
+/* values: the upwind cell's value carried to the half-step foot of    */
+/* the characteristic with a limited slope; optionally the transverse  */
+/* part of the unsplit BCG predictor)                                  */
 /* ------------------------------------------------------------------ */
 
 static double minmod(double a, double b) {
@@ -301,10 +306,34 @@ static double minmod(double a, double b) {
   return fabs(a) < fabs(b) ? a : b;
 }
 
+/* Monotonized central limiter (van Leer, J. Comput. Phys. 23, 1977): the
+ * centred slope, bounded by twice each one-sided slope, 0 at extrema. */
+static double mc_limit(double a, double b) {
+  if (a * b <= 0.0) return 0.0;
+  double c = 0.5 * (a + b), m = fabs(c);
+  if (2.0 * fabs(a) < m) m = 2.0 * fabs(a);
+  if (2.0 * fabs(b) < m) m = 2.0 * fabs(b);
+  return a > 0.0 ? m : -m;
+}
+
+static double slope(const Prob* p, double a, double b) {
+  return p->lim == 1 ? mc_limit(a, b) : minmod(a, b);
+}
+
+/* Velocity of cell (c) along axis t: the mean of its two t faces. */
+static double cell_velocity(const Prob* p, const double* ut, int t, const int* c) {
+  int a[3] = {c[0], c[1], c[2]};
+  double lo = ut[face(p, t, a[0], a[1], a[2])];
+  a[t] += 1;
+  double hi = ut[face(p, t, a[0], a[1], a[2])];
+  return 0.5 * (lo + hi);
+}
+
 /* Advective flux u * xi_face through every face along axis d.  out[0] gets
  * the amount leaving the box through open faces (dt * area * flux). */
-static void advect_faces(const Prob* p, int d, const double* u, const double* xi,
+static void advect_faces(const Prob* p, int d, const double* const* uall, const double* xi,
                          double dt, double* flux, double* out) {
+  const double* u = uall[d];
   int m[3] = {p->n[0], p->n[1], p->n[2]};
   m[d] += 1;
   double h = p->h;
@@ -341,8 +370,19 @@ static void advect_faces(const Prob* p, int d, const double* u, const double* xi
         long U = cell(p, Uc[0], Uc[1], Uc[2]);
         double xm = xi[nbr(p, Uc[0], Uc[1], Uc[2], d, -1)];
         double xp = xi[nbr(p, Uc[0], Uc[1], Uc[2], d, +1)];
-        double g = minmod((xi[U] - xm) / h, (xp - xi[U]) / h);
+        double g = slope(p, (xi[U] - xm) / h, (xp - xi[U]) / h);
         double xf = xi[U] + sg * 0.5 * (h - fabs(uf) * dt) * g;
+        /* unsplit BCG: minus dt/2 times v_t d(xi)/dx_t at the upwind cell for
+         * each transverse axis t, v_t the cell's mean velocity and the
+         * derivative the one-sided difference on its upwind side */
+        if (p->trans)
+          for (int t = 0; t < p->dim; ++t) {
+            if (t == d) continue;
+            double vt = cell_velocity(p, uall[t], t, Uc);
+            double dxt = vt > 0.0 ? xi[U] - xi[nbr(p, Uc[0], Uc[1], Uc[2], t, -1)]
+                                  : xi[nbr(p, Uc[0], Uc[1], Uc[2], t, +1)] - xi[U];
+            xf -= 0.5 * dt * vt * dxt / h;
+          }
         (void)L;
         flux[fi] = uf * xf;
       }
@@ -372,7 +412,7 @@ int or_advect(const int* ip, const double* dp, const double* ux, const double* u
     long nf = p.ncell / p.n[d] * (p.n[d] + 1);
     fl[d] = malloc(nf * sizeof(double));
     if (!fl[d]) return -2;
-    advect_faces(&p, d, u[d], xi, dt, fl[d], &out);
+    advect_faces(&p, d, u, xi, dt, fl[d], &out);
   }
   for (int k = 0; k < p.n[2]; ++k)
     for (int j = 0; j < p.n[1]; ++j)
