@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c1",
-                    choices=["c0", "c1", "c1i", "c1a", "c1f", "c1m", "c2", "c2x", "c3", "c4"])
+                    choices=["c0", "c1", "c1i", "c1a", "c1f", "c1m", "c1v", "c2", "c2x", "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--implicit-graph", action="store_true",
@@ -81,6 +81,8 @@ def workload(name, K, W):
         return C.c1_acdi()
     if name == "c1f":
         return C.c1_forces()
+    if name == "c1v":
+        return C.c1_variants()
     if name == "c2x":
         return C.c2_axisymmetric()
     return C.c2_translating_sphere()

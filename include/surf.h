@@ -76,6 +76,9 @@ enum { SURF_SUBSTEP2_EXPLICIT = 0, SURF_SUBSTEP2_IMPLICIT = 1 };
  * Phase-Field method) and re-initialized from a VoF field only when one is
  * given */
 enum { SURF_IFACE_VOF = 0, SURF_IFACE_ACDI = 1 };
+/* slope limiter of the substep-1 face values (section 3.1): minmod (default)
+ * or the monotonized central limiter of van Leer (1977) */
+enum { SURF_LIMITER_MINMOD = 0, SURF_LIMITER_MC = 1 };
 /* exchange law: Langmuir J = k_a c (Gamma_inf - Gamma) - k_d Gamma
  * (section 2.6) or constant adsorption flux J = k_a c Gamma_inf - k_d Gamma
  * (section 4.3.1) */
@@ -164,6 +167,17 @@ typedef struct {
                          * times the largest speed)                      */
   double acdi_vareps;   /* ACDI: s = eps ln((phi + ve)/(1 - phi + ve))
                          * (0: 1e-6)                                      */
+  int32_t limiter;      /* substep 1 slope limiter (section 3.1, BCG face
+                         * values): SURF_LIMITER_MINMOD (0) or
+                         * SURF_LIMITER_MC, the monotonized central limiter */
+  int32_t transverse;   /* 1: the transverse term of the unsplit BCG
+                         * predictor in substep 1: each face value less
+                         * dt/2 times the upwind cell's mean transverse
+                         * velocity times its one-sided transverse
+                         * difference on the upwind side.  Either variant
+                         * needs a 2D Cartesian grid, the weighted flux
+                         * form, explicit substep 2, the VoF interface and
+                         * no adjoint (SURF_EINVAL otherwise)            */
 } surf_params;
 
 /* Bytes of device workspace a context needs. */

@@ -320,11 +320,13 @@ static double slope(const Prob* p, double a, double b) {
   return p->lim == 1 ? mc_limit(a, b) : minmod(a, b);
 }
 
-/* Velocity of cell (c) along axis t: the mean of its two t faces. */
+/* Velocity of cell (c) along axis t: the mean of its two t faces (on a
+ * periodic axis face n_t is face 0, as in the fluxes). */
 static double cell_velocity(const Prob* p, const double* ut, int t, const int* c) {
   int a[3] = {c[0], c[1], c[2]};
   double lo = ut[face(p, t, a[0], a[1], a[2])];
   a[t] += 1;
+  if (a[t] == p->n[t] && p->bc[t][0] == BC_PERIODIC) a[t] = 0;
   double hi = ut[face(p, t, a[0], a[1], a[2])];
   return 0.5 * (lo + hi);
 }

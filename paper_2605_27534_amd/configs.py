@@ -85,6 +85,14 @@ def c1_acdi(n=1024, reinit_every=50):
     return cfg
 
 
+def c1_variants(n=1024):
+    """The soluble expanding circle with the substep-1 variants of the unsplit
+    BCG scheme (section 3.1): the monotonized central limiter and the
+    transverse term of the predictor; the rest as C1."""
+    return c1_expanding_circle(n, soluble=True, extra=dict(limiter=1, bcg_transverse=1),
+                               name="expanding circle %d^2 fp32 soluble mc-transverse" % n)
+
+
 def c1_forces(n=1024):
     """The soluble expanding circle with the interfacial forces of the flow
     coupling (section 2.4) evaluated after every step: capillary and Marangoni

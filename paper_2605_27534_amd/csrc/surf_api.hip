@@ -166,6 +166,12 @@ int check_grid_params(const surf_grid* gr, const surf_params* p) {
       (!(p->acdi_zeta > 0) || !std::isfinite(p->acdi_zeta) || !(p->acdi_vareps >= 0) ||
        p->acdi_vareps >= 0.5 || p->adjoint))
     return SURF_EINVAL;
+  if (p->limiter < 0 || p->limiter > 1 || p->transverse < 0 || p->transverse > 1)
+    return SURF_EINVAL;
+  if ((p->limiter || p->transverse) &&
+      (gr->dim != 2 || gr->axisym || p->flux_form != SURF_FLUX_WEIGHTED ||
+       p->substep2 != SURF_SUBSTEP2_EXPLICIT || p->interface != SURF_IFACE_VOF || p->adjoint))
+    return SURF_EINVAL;
   if (p->substep2 == SURF_SUBSTEP2_IMPLICIT &&
       (p->flux_form != SURF_FLUX_WEIGHTED || p->adjoint || p->picard_iters < 0 ||
        p->picard_iters > IMP_MAX_PICARD || p->cg_max_iters < 0 || !(p->cg_tol >= 0) ||
@@ -509,6 +515,20 @@ void launch_col2d(surf_ctx* c, const ColArgs<R>& a, bool has_u, bool bulk) {
     else if (has_u) hipLaunchKernelGGL((k_col2d<R, TY, true, false, true>), grid, block, 0, c->stream, a);
     else if (bulk) hipLaunchKernelGGL((k_col2d<R, TY, false, true, true>), grid, block, 0, c->stream, a);
     else hipLaunchKernelGGL((k_col2d<R, TY, false, false, true>), grid, block, 0, c->stream, a);
+    return;
+  }
+  if (has_u && (c->prm.limiter || c->prm.transverse)) {
+    // substep-1 variants (the scheme only matters with a flow)
+    const int v = (c->prm.limiter ? 1 : 0) + (c->prm.transverse ? 2 : 0);
+    if (bulk) {
+      if (v == 1) hipLaunchKernelGGL((k_col2d<R, TY, true, true, false, 1, false>), grid, block, 0, c->stream, a);
+      else if (v == 2) hipLaunchKernelGGL((k_col2d<R, TY, true, true, false, 0, true>), grid, block, 0, c->stream, a);
+      else hipLaunchKernelGGL((k_col2d<R, TY, true, true, false, 1, true>), grid, block, 0, c->stream, a);
+    } else {
+      if (v == 1) hipLaunchKernelGGL((k_col2d<R, TY, true, false, false, 1, false>), grid, block, 0, c->stream, a);
+      else if (v == 2) hipLaunchKernelGGL((k_col2d<R, TY, true, false, false, 0, true>), grid, block, 0, c->stream, a);
+      else hipLaunchKernelGGL((k_col2d<R, TY, true, false, false, 1, true>), grid, block, 0, c->stream, a);
+    }
     return;
   }
   if (has_u && bulk) hipLaunchKernelGGL((k_col2d<R, TY, true, true>), grid, block, 0, c->stream, a);
@@ -1155,6 +1175,8 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   int cs, cg;
   int ncol = col_shape(grid, params, &cs, &cg);
   if (grid->axisym && ncol == 0) return SURF_EINVAL;  // the rings run on k_col2d only
+  // so do the substep-1 variants
+  if ((params->limiter || params->transverse) && ncol == 0) return SURF_EINVAL;
   int c3s[3];
   int nc3 = col3_shape(grid, params, c3s);
   int npart = nblk > n2 ? nblk : n2;
@@ -1680,6 +1702,7 @@ int batch_layout(int32_t n, const surf_grid* grids, const surf_params* prm, Batc
   L->q.resize(n);
   for (int i = 0; i < n; ++i) {
     if (grids[i].axisym) return SURF_EINVAL;  // the batch kernel is Cartesian
+    if (prm[i].limiter || prm[i].transverse) return SURF_EINVAL;  // and takes the default scheme
     int rc = check_grid_params(&grids[i], &prm[i]);
     if (rc) return rc;
     if (grids[i].dim != 2 || prm[i].precision != prm[0].precision) return SURF_EINVAL;

@@ -108,6 +108,26 @@ __device__ __forceinline__ R bcg_face(R uf, R x, R xr, R dl, R d, R dr, R half_c
   return uf * ((pos ? x : xr) + (pos ? k : -k) * m);
 }
 
+// Monotonized central slope (van Leer 1977): the centred difference bounded
+// by twice each one-sided difference, 0 at extrema.
+template <typename R>
+__device__ __forceinline__ R mc(R a, R b) {
+  const R m = fmin(fabs(R(0.5) * (a + b)), R(2) * fmin(fabs(a), fabs(b)));
+  return a * b > R(0) ? copysign(m, a) : R(0);
+}
+
+// The face value of the substep-1 variants: the slope limiter LIM (0 minmod,
+// 1 MC), plus tl or tr, the transverse term of the upwind cell (low or high
+// side), when the unsplit predictor is on.
+template <typename R, int LIM>
+__device__ __forceinline__ R bcg_face_v(R uf, R x, R xr, R dl, R d, R dr, R half_cfl, R tl,
+                                        R tr) {
+  const bool pos = uf > R(0);
+  const R k = R(0.5) - fabs(uf) * half_cfl;
+  const R m = LIM == 1 ? mc<R>(pos ? dl : dr, d) : mm<R>(pos ? dl : dr, d);
+  return uf * ((pos ? x : xr) + (pos ? k : -k) * m + (pos ? tl : tr));
+}
+
 template <typename R>
 struct ColAcc {
   double sF, sP, sD, sSD, out;
@@ -118,9 +138,14 @@ struct ColAcc {
 // One wave: strip x0, rows y0 .. y0 + TY - 1 (y0 < ny).  IX: every column
 // the strip reads lies inside the box away from the x sides; IY: the same
 // for the rows and the y sides.
-template <typename R, int TY, bool HU, bool BULK, bool IX, bool IY, bool AXI>
+// LIM and TR select the substep-1 variants (2D Cartesian only): the slope
+// limiter and the transverse term of the unsplit BCG predictor, which needs
+// the x-face velocities of one more row below and above the advected rows.
+template <typename R, int TY, bool HU, bool BULK, bool IX, bool IY, bool AXI, int LIM = 0,
+          bool TR = false>
 __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, const int y0,
                                            const int lane, ColAcc<R>& acc) {
+  constexpr bool VAR = LIM != 0 || TR;
   constexpr int NR3 = TY + 6;  // state rows y0-3 .. y0+TY+2
   constexpr int NR1 = TY + 2;  // rows of the advected state y0-1 .. y0+TY
   constexpr int NFY = TY + 3;  // y faces y0-1 .. y0+TY+1 (face j lies below row j)
@@ -181,7 +206,10 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
   const R* const bUx = a.u[0];
   const R* const bUy = a.u[1];
   const int vmx = mx * ES, vfx = fxm * ES;  // per-lane byte offsets
-  R rF[NR3], rP[NR3], rC[NR1], rUx[NR1], rUy[NFY];
+  // TR: x-face velocities of rows y0-2 .. y0+TY+1 (rUxT[m] is row y0-2+m,
+  // loaded with group m+2); else rows y0-1 .. y0+TY in rUx
+  constexpr int NUX = TR ? TY + 4 : 1;
+  R rF[NR3], rP[NR3], rC[NR1], rUx[TR ? 1 : NR1], rUy[NFY], rUxT[NUX];
   auto load_group = [&](const int k) {
     if (k < NR3) {
       const int my = IY ? y0 - 3 + k : map_axis(y0 - 3 + k, ny, g.bc[1][0], g.bc[1][1]);
@@ -213,11 +241,23 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
       const int ys = y0 - 1 + i;
       const int my = IY ? ys : map_axis(ys, ny, g.bc[1][0], g.bc[1][1]);
       rC[i] = gld<R>(bC, vmx, nx * my * ES);
-      rUx[i] = R(0);
-      if (HU) {
+      if constexpr (!TR) {
+        rUx[i] = R(0);
+        if (HU) {
+          const bool ok = (IX || !xf_out) && (IY || py || (ys >= 0 && ys < ny));
+          const R v = gld<R>(bUx, vfx, (nx + 1) * my * ES);
+          rUx[i] = ok ? v : R(0);
+        }
+      }
+    }
+    if constexpr (TR) {
+      if (k >= 2 && k - 2 < NUX) {
+        const int m = k - 2;
+        const int ys = y0 - 2 + m;
+        const int my = IY ? ys : map_axis(ys, ny, g.bc[1][0], g.bc[1][1]);
         const bool ok = (IX || !xf_out) && (IY || py || (ys >= 0 && ys < ny));
         const R v = gld<R>(bUx, vfx, (nx + 1) * my * ES);
-        rUx[i] = ok ? v : R(0);
+        rUxT[m] = ok ? v : R(0);
       }
     }
   };
@@ -241,6 +281,20 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
   R pWyF = R(0), pWyP = R(0);  // weighted flux through face s-1
   R pFxF = R(0), pFxP = R(0), pFxLF = R(0), pFxLP = R(0);  // advective x fluxes of row s-1
   R pUx = R(0), pUxL = R(0);
+  // TR: the transverse term of the y faces' upwind cells in the row below
+  // the current face (carried from the previous iteration)
+  R tyF = R(0), tyP = R(0);
+  // the y-face transverse term of row r (rF / rP index kr, x-face velocities
+  // rUxT[mr]): minus dt/2h times the cell-mean x velocity times the upwind
+  // x difference
+  auto ty_row = [&](const int kr, const int mr, R& tF, R& tP) {
+    const R uc = R(0.5) * (from_left(rUxT[mr]) + rUxT[mr]);
+    const R eF = from_right(rF[kr]) - rF[kr], eP = from_right(rP[kr]) - rP[kr];
+    const R lF = from_left(eF), lP = from_left(eP);
+    const bool up = uc > R(0);
+    tF = BULK ? -hcfl * uc * (up ? lF : eF) : R(0);
+    tP = -hcfl * uc * (up ? lP : eP);
+  };
 
 #pragma unroll
   for (int i = 3; i < NR3; ++i) {
@@ -254,8 +308,22 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
     R nyF = R(0), nyP = R(0);
     if (HU) {
       const R uf = rUy[i - 3];
-      nyF = BULK ? bcg_face<R>(uf, rF[i - 2], rF[i - 1], dF2, dF1, dF0, hcfl) : R(0);
-      nyP = bcg_face<R>(uf, rP[i - 2], rP[i - 1], dP2, dP1, dP0, hcfl);
+      if constexpr (VAR) {
+        // rows s (index i-2, x velocities rUxT[i-3]) and s+1 (i-1, rUxT[i-2])
+        R tF1 = R(0), tP1 = R(0);
+        if constexpr (TR) {
+          if (i == 3) ty_row(i - 2, i - 3, tyF, tyP);
+          ty_row(i - 1, i - 2, tF1, tP1);
+        }
+        nyF = BULK ? bcg_face_v<R, LIM>(uf, rF[i - 2], rF[i - 1], dF2, dF1, dF0, hcfl, tyF, tF1)
+                   : R(0);
+        nyP = bcg_face_v<R, LIM>(uf, rP[i - 2], rP[i - 1], dP2, dP1, dP0, hcfl, tyP, tP1);
+        tyF = tF1;
+        tyP = tP1;
+      } else {
+        nyF = BULK ? bcg_face<R>(uf, rF[i - 2], rF[i - 1], dF2, dF1, dF0, hcfl) : R(0);
+        nyP = bcg_face<R>(uf, rP[i - 2], rP[i - 1], dP2, dP1, dP0, hcfl);
+      }
       if (!IY) {
         if (!py && j == 0) {
           nyF = (BULK && oy_lo) ? uf * rF[i - 1] : R(0);
@@ -284,7 +352,9 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
       const R xF = rF[i - 2], xP = rP[i - 2];
       R Fs = xF, Ps = xP;
       R fxF = R(0), fxP = R(0), fxLF = R(0), fxLP = R(0);
-      const R ux = rUx[k1];
+      R ux;
+      if constexpr (TR) ux = rUxT[k1 + 1];
+      else ux = rUx[k1];
       if (HU) {
         // the right-face flux of this lane's cell; the left face is the
         // right face of the lane to the left (every shift runs on all lanes)
@@ -292,8 +362,24 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
         const R eF = xFr - xF, eP = xPr - xP;
         const R eFl = from_left(eF), eFr = from_right(eF);
         const R ePl = from_left(eP), ePr = from_right(eP);
-        fxF = BULK ? bcg_face<R>(ux, xF, xFr, eFl, eF, eFr, hcfl) : R(0);
-        fxP = bcg_face<R>(ux, xP, xPr, ePl, eP, ePr, hcfl);
+        if constexpr (VAR) {
+          // the transverse term of this lane's cell from its own column:
+          // minus dt/2h times the mean of its y faces s and s+1 times the
+          // upwind y difference; the right neighbour's by one shift
+          R txF = R(0), txP = R(0);
+          if constexpr (TR) {
+            const R vc = R(0.5) * (rUy[i - 4] + rUy[i - 3]);
+            const bool up = vc > R(0);
+            txF = BULK ? -hcfl * vc * (up ? rF[i - 2] - rF[i - 3] : rF[i - 1] - rF[i - 2]) : R(0);
+            txP = -hcfl * vc * (up ? rP[i - 2] - rP[i - 3] : rP[i - 1] - rP[i - 2]);
+          }
+          const R txFr = TR ? from_right(txF) : R(0), txPr = TR ? from_right(txP) : R(0);
+          fxF = BULK ? bcg_face_v<R, LIM>(ux, xF, xFr, eFl, eF, eFr, hcfl, txF, txFr) : R(0);
+          fxP = bcg_face_v<R, LIM>(ux, xP, xPr, ePl, eP, ePr, hcfl, txP, txPr);
+        } else {
+          fxF = BULK ? bcg_face<R>(ux, xF, xFr, eFl, eF, eFr, hcfl) : R(0);
+          fxP = bcg_face<R>(ux, xP, xPr, ePl, eP, ePr, hcfl);
+        }
         if (!IX || !IY) {
           // lane-constant selects: an open side carries the interior cell,
           // a wall nothing, faces beyond a side and rows outside nothing
@@ -411,7 +497,7 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
   }
 }
 
-template <typename R, int TY, bool HU, bool BULK, bool AXI = false>
+template <typename R, int TY, bool HU, bool BULK, bool AXI = false, int LIM = 0, bool TR = false>
 __global__ void __launch_bounds__(64 * COL_WAVES) k_col2d(ColArgs<R> a) {
   const int b = blockIdx.x;
   const int wg = (b & 7) * a.per_xcd + (b >> 3);  // banded over the XCDs
@@ -425,10 +511,10 @@ __global__ void __launch_bounds__(64 * COL_WAVES) k_col2d(ColArgs<R> a) {
   ColAcc<R> acc{0.0, 0.0, 0.0, 0.0, 0.0, R(0), R(-INFINITY), R(INFINITY), R(INFINITY), 0};
   if (y0 < ny) {  // chunks past the last row only join the reduction
     const bool ix = x0 >= 3 && x0 + 62 <= nx, iy = y0 >= 3 && y0 + TY + 3 <= ny;
-    if (ix && iy) col2d_wave<R, TY, HU, BULK, true, true, AXI>(a, x0, y0, lane, acc);
-    else if (iy) col2d_wave<R, TY, HU, BULK, false, true, AXI>(a, x0, y0, lane, acc);
-    else if (ix) col2d_wave<R, TY, HU, BULK, true, false, AXI>(a, x0, y0, lane, acc);
-    else col2d_wave<R, TY, HU, BULK, false, false, AXI>(a, x0, y0, lane, acc);
+    if (ix && iy) col2d_wave<R, TY, HU, BULK, true, true, AXI, LIM, TR>(a, x0, y0, lane, acc);
+    else if (iy) col2d_wave<R, TY, HU, BULK, false, true, AXI, LIM, TR>(a, x0, y0, lane, acc);
+    else if (ix) col2d_wave<R, TY, HU, BULK, true, false, AXI, LIM, TR>(a, x0, y0, lane, acc);
+    else col2d_wave<R, TY, HU, BULK, false, false, AXI, LIM, TR>(a, x0, y0, lane, acc);
   }
   double v[NPART];
   v[P_SUM_F] = acc.sF;

@@ -72,7 +72,8 @@ class Params(ctypes.Structure):
                 ("cg_max_iters", ctypes.c_int32), ("pad2_", ctypes.c_int32),
                 ("cg_tol", ctypes.c_double), ("interface", ctypes.c_int32),
                 ("pad3_", ctypes.c_int32), ("acdi_zeta", ctypes.c_double),
-                ("acdi_vareps", ctypes.c_double)]
+                ("acdi_vareps", ctypes.c_double), ("limiter", ctypes.c_int32),
+                ("transverse", ctypes.c_int32)]
 
 
 _lib = None
@@ -127,7 +128,8 @@ DEFAULTS = dict(flux_form=0, kinetics=0, eos=0, bulk_enabled=1, D_b=1e-2, D_s=1e
                 k_a=1.0, k_d=1.0, gamma_inf=1.0, sigma0=1.0, eos_E=0.5, eta=1e-12,
                 chi_max_eps=12.0, cfl_adv=0.5, cfl_diff=0.8, hj_iters_init=0,
                 hj_iters_step=0, adjoint=0, substep2=0, picard_iters=0, cg_max_iters=0,
-                cg_tol=0.0, interface=0, acdi_zeta=0.0, acdi_vareps=0.0)
+                cg_tol=0.0, interface=0, acdi_zeta=0.0, acdi_vareps=0.0, limiter=0,
+                bcg_transverse=0)
 
 
 def make_structs(prob: dict, dt: float, precision: int):
@@ -153,6 +155,8 @@ def make_structs(prob: dict, dt: float, precision: int):
     for k in ("D_b", "D_s", "k_a", "k_d", "gamma_inf", "sigma0", "eos_E", "eta",
               "chi_max_eps", "cfl_adv", "cfl_diff", "cg_tol", "acdi_zeta", "acdi_vareps"):
         setattr(p, k, float(q[k]))
+    p.limiter = int(q["limiter"])
+    p.transverse = int(q["bcg_transverse"])
     p.eps = float(q.get("eps", 1.5 * q["h"]))
     p.dt = float(dt)
     return g, p, q

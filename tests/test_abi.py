@@ -120,12 +120,13 @@ def test_batch_workspace_validates_instances():
 
 def test_params_struct_matches_the_header():
     # the binding's surf_params mirrors include/surf.h: 8 int32, 13 doubles,
-    # 4 int32, 1 double, 2 int32, 2 doubles, naturally aligned
+    # 4 int32, 1 double, 2 int32, 2 doubles, 2 int32, naturally aligned
     import ctypes
     from paper_2605_27534_amd import surf as S
-    assert ctypes.sizeof(S.Params) == 8 * 4 + 13 * 8 + 4 * 4 + 8 + 2 * 4 + 2 * 8
+    assert ctypes.sizeof(S.Params) == 8 * 4 + 13 * 8 + 4 * 4 + 8 + 2 * 4 + 2 * 8 + 2 * 4
     assert S.Params.cg_tol.offset == 8 * 4 + 13 * 8 + 4 * 4
-    assert S.Params.acdi_vareps.offset == ctypes.sizeof(S.Params) - 8
+    assert S.Params.acdi_vareps.offset == ctypes.sizeof(S.Params) - 16
+    assert S.Params.transverse.offset == ctypes.sizeof(S.Params) - 4
 
 
 def test_implicit_substep2_validation():
@@ -218,3 +219,26 @@ def test_interface_force_validation():
         ctx, buf, base = ctx_of(dict(two, **bad))
         assert L.surf_interface_force(ctx, p, p, pair, pair) == -1, bad
         assert L.surf_destroy(ctx) == 0
+
+
+def test_advection_variant_validation():
+    """The MC limiter and the transverse term: 2D Cartesian weighted form,
+    explicit substep 2, the VoF interface, no adjoint, no batch."""
+    import ctypes
+    from paper_2605_27534_amd import surf as S
+    L = S.lib()
+    nb = ctypes.c_size_t(0)
+    base = dict(dim=2, n=(64, 48), h=1 / 64, bc=((1, 1), (0, 2)), limiter=1, bcg_transverse=1)
+    for ok in (dict(), dict(limiter=0), dict(bcg_transverse=0)):
+        g, p, _ = S.make_structs(dict(base, **ok), 1e-3, S.SURF_F32)
+        assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == 0, ok
+    for bad in (dict(limiter=2), dict(bcg_transverse=-1), dict(flux_form=1), dict(substep2=1),
+                dict(interface=1, acdi_zeta=0.5), dict(adjoint=1),
+                dict(axisym=1, bc=((0, 2), (0, 0))),
+                dict(dim=3, n=(16, 16, 16), bc=((0, 0), (0, 0), (0, 0)))):
+        g, p, _ = S.make_structs(dict(base, **bad), 1e-3, S.SURF_F32)
+        assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == -1, bad
+    g, p, _ = S.make_structs(base, 1e-3, S.SURF_F32)
+    nbb = ctypes.c_size_t(0)
+    assert L.surf_batch_workspace_bytes(1, ctypes.byref(g), ctypes.byref(p),
+                                        ctypes.byref(nbb)) == -1
