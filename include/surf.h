@@ -262,6 +262,27 @@ int surf_step(surf_ctx* ctx, const void* vof_next, const void* const* u,
  * state, force and adjoint calls return SURF_ESTATE. */
 int surf_prepare_geometry(surf_ctx* ctx, const void* vof_next, void* aux_stream);
 
+/* Pipelined ACDI interface (section 2.5, the Phase-Field method; 2D, weighted
+ * flux form, explicit substep 2).  A step's ACDI step (the advection of phi
+ * by u and the regularization, then chi = -s(phi)) depends only on phi and
+ * u, not on the transported state, so it can run while the previous step's
+ * transport runs.  This call enqueues it on aux_stream (a HIP stream other
+ * than the context's, at the default priority) after the last transport
+ * enqueued on the context's stream has consumed the level-set buffer it
+ * writes; the next surf_step, which must get vof_next = NULL and the same u
+ * (u[0] pointer), then waits for it and runs only the transport.  Results
+ * equal those of plain surf_step calls.  Steps that re-initialize from a VoF
+ * field are not prepared.
+ *   u  the face velocities of that step (as in surf_step; NULL for no flow),
+ *      ready with respect to aux_stream and unchanged until that surf_step.
+ * Errors: SURF_EINVAL for a context without ACDI, a 3D grid, the paper flux
+ * form or the implicit substep, a null aux_stream or u[1] missing;
+ * SURF_ESTATE without a level set or with a prepare still pending.  While
+ * one is pending only surf_step (as above), surf_set_dt and the status calls
+ * are accepted; the level-set, phase, state, force, timing and adjoint calls
+ * return SURF_ESTATE. */
+int surf_prepare_phase(surf_ctx* ctx, const void* const* u, void* aux_stream);
+
 /* Measurement aid: runs only the transport kernel of surf_step (weighted
  * form: advection, substep 2, source, equation of state and the
  * per-workgroup reduction records; no reduction to totals, no change of the

@@ -72,6 +72,10 @@ struct surf_ctx {
   hipEvent_t ev_geo = nullptr;     // auxiliary stream, after a prepared geometry
   bool pre_valid = false;          // ev_pre recorded since the last prepare
   const void* prepared = nullptr;  // VoF of the prepared geometry, or null
+  // ACDI: the next step's phase field prepared on the auxiliary stream
+  // (prepared then points at prepared_phase), with the velocity it took
+  bool prepared_phase = false;
+  const void* prep_u0 = nullptr;
   bool materialized;  // chi[chi_cur] holds explicit values on every tile
   // adjoint scratch: advected state, nu, per-workgroup dtheta partials
   void* adj[4];
@@ -415,7 +419,9 @@ int geometry_impl(surf_ctx* c, const void* vof, int full) {
 // One ACDI step from the phase field: phi* and s into the context's scratch
 // fields, the new phi and its level set into phi_out and chi_out.
 template <typename R>
-void acdi_launch(surf_ctx* c, const void* const* u, R* phi_out, R* chi_out) {
+void acdi_launch(surf_ctx* c, const void* const* u, R* phi_out, R* chi_out,
+                 hipStream_t st = nullptr) {
+  if (!st) st = c->stream;
   AcdiArgs<R> a;
   a.g = c->g;
   a.p = make_par<R>(c);
@@ -430,14 +436,14 @@ void acdi_launch(surf_ctx* c, const void* const* u, R* phi_out, R* chi_out) {
   const R* u1 = has_u ? (const R*)u[1] : nullptr;
   const R* u2 = (has_u && c->grid.dim == 3) ? (const R*)u[2] : nullptr;
   if (c->grid.dim == 3) {
-    hipLaunchKernelGGL((k_acdi_adv<R, 3>), gr, dim3(ACDI_TX), 0, c->stream, a,
+    hipLaunchKernelGGL((k_acdi_adv<R, 3>), gr, dim3(ACDI_TX), 0, st, a,
                        (const R*)c->acdi[0], u0, u1, u2, (R*)c->acdi[1], (R*)c->acdi[2]);
-    hipLaunchKernelGGL((k_acdi_reg<R, 3>), gr, dim3(ACDI_TX), 0, c->stream, a,
+    hipLaunchKernelGGL((k_acdi_reg<R, 3>), gr, dim3(ACDI_TX), 0, st, a,
                        (const R*)c->acdi[1], (const R*)c->acdi[2], phi_out, chi_out);
   } else {
-    hipLaunchKernelGGL((k_acdi_adv<R, 2>), gr, dim3(ACDI_TX), 0, c->stream, a,
+    hipLaunchKernelGGL((k_acdi_adv<R, 2>), gr, dim3(ACDI_TX), 0, st, a,
                        (const R*)c->acdi[0], u0, u1, u2, (R*)c->acdi[1], (R*)c->acdi[2]);
-    hipLaunchKernelGGL((k_acdi_reg<R, 2>), gr, dim3(ACDI_TX), 0, c->stream, a,
+    hipLaunchKernelGGL((k_acdi_reg<R, 2>), gr, dim3(ACDI_TX), 0, st, a,
                        (const R*)c->acdi[1], (const R*)c->acdi[2], phi_out, chi_out);
   }
 }
@@ -1332,6 +1338,7 @@ int surf_set_levelset(surf_ctx* c, const void* chi) {
 }
 
 int surf_get_phase(surf_ctx* c, void* phi_out) {
+  if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !phi_out) return SURF_EINVAL;
   if (c->prm.interface != SURF_IFACE_ACDI) return SURF_EINVAL;
   if (!c->has_chi) return SURF_ESTATE;
@@ -1380,9 +1387,21 @@ int surf_step(surf_ctx* c, const void* vof_next, const void* const* u, const voi
   if (!aligned(psi_in, es) || !aligned(psi_out, es)) return SURF_EINVAL;
   if (!c->has_chi) return SURF_ESTATE;
   if (c->prm.interface == SURF_IFACE_ACDI) {
-    const int rc = c->prm.precision == SURF_F64 ? acdi_geometry<double>(c, vof_next, u)
-                                                : acdi_geometry<float>(c, vof_next, u);
-    if (rc) return rc;
+    if (c->prepared_phase) {
+      // this step's ACDI step ran on the auxiliary stream into the idle
+      // level-set buffer: wait for it and read that buffer
+      const void* u0 = (u && u[0]) ? u[0] : nullptr;
+      if (vof_next || u0 != c->prep_u0) return SURF_ESTATE;
+      c->prepared_phase = false;
+      c->prepared = nullptr;
+      if (hipStreamWaitEvent(c->stream, c->ev_geo, 0) != hipSuccess) return SURF_EDEVICE;
+      c->chi_cur = 1 - c->chi_cur;
+      c->materialized = true;
+    } else {
+      const int rc = c->prm.precision == SURF_F64 ? acdi_geometry<double>(c, vof_next, u)
+                                                  : acdi_geometry<float>(c, vof_next, u);
+      if (rc) return rc;
+    }
     vof_next = nullptr;  // the transport runs on the level set just written
   }
   if (c->prm.substep2 == SURF_SUBSTEP2_IMPLICIT) {
@@ -1497,7 +1516,7 @@ int surf_time_acdi(surf_ctx* c, const void* const* u, int32_t reps, double* ms_p
   if (u && u[0])
     for (int d = 0; d < c->grid.dim; ++d)
       if (!u[d]) return SURF_EINVAL;
-  if (!c->has_chi) return SURF_ESTATE;
+  if (!c->has_chi || c->prepared) return SURF_ESTATE;
   if (c->prm.precision == SURF_F64) return time_acdi_impl<double>(c, u, reps, ms_per_step);
   return time_acdi_impl<float>(c, u, reps, ms_per_step);
 }
@@ -1509,6 +1528,40 @@ int surf_time_solver(surf_ctx* c, int32_t field, int32_t reps, double* ms_per_la
   if (c->imp_nsolves == 0 || c->prepared) return SURF_ESTATE;
   if (c->prm.precision == SURF_F64) return time_solver_impl<double>(c, field, reps, ms_per_launch);
   return time_solver_impl<float>(c, field, reps, ms_per_launch);
+}
+
+int surf_prepare_phase(surf_ctx* c, const void* const* u, void* aux_stream) {
+  if (!c || !aux_stream) return SURF_EINVAL;
+  if (c->prm.interface != SURF_IFACE_ACDI || c->grid.dim != 2 || c->col_nwg == 0 ||
+      c->prm.substep2 != SURF_SUBSTEP2_EXPLICIT)
+    return SURF_EINVAL;
+  if (u && u[0] && !u[1]) return SURF_EINVAL;
+  if (!c->has_chi || c->prepared) return SURF_ESTATE;
+  if (!c->ev_pre) {
+    if (hipEventCreateWithFlags(&c->ev_pre, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_geo, hipEventDisableTiming) != hipSuccess)
+      return SURF_EDEVICE;
+    c->pre_valid = false;
+  }
+  hipStream_t aux = (hipStream_t)aux_stream;
+  // the idle level-set buffer is free once the transport that read it is
+  // done: the point recorded before the latest transport, or else now; the
+  // phase-field buffers are read and written by ACDI steps alone
+  if (!c->pre_valid && hipEventRecord(c->ev_pre, c->stream) != hipSuccess) return SURF_EDEVICE;
+  c->pre_valid = false;
+  if (hipStreamWaitEvent(aux, c->ev_pre, 0) != hipSuccess) return SURF_EDEVICE;
+  {
+    Timed tm(c, 1, aux);
+    if (c->prm.precision == SURF_F32)
+      acdi_launch<float>(c, u, (float*)c->acdi[0], (float*)c->chi[1 - c->chi_cur], aux);
+    else
+      acdi_launch<double>(c, u, (double*)c->acdi[0], (double*)c->chi[1 - c->chi_cur], aux);
+  }
+  if (hipEventRecord(c->ev_geo, aux) != hipSuccess) return SURF_EDEVICE;
+  c->prepared_phase = true;
+  c->prepared = &c->prepared_phase;
+  c->prep_u0 = (u && u[0]) ? u[0] : nullptr;
+  return status_of_launch();
 }
 
 int surf_prepare_geometry(surf_ctx* c, const void* vof_next, void* aux_stream) {

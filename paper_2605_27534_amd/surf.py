@@ -34,6 +34,7 @@ ERRORS = {0: "ok", -1: "invalid argument", -2: "workspace too small",
 EXPORTS = [
     "surf_workspace_bytes", "surf_init", "surf_set_geometry", "surf_set_levelset",
     "surf_get_levelset", "surf_get_phase", "surf_init_state", "surf_step", "surf_prepare_geometry",
+    "surf_prepare_phase",
     "surf_time_transport", "surf_force", "surf_interface_force", "surf_set_dt",
     "surf_get_status", "surf_clear_status", "surf_solver_iterations", "surf_time_solver", "surf_time_acdi",
     "surf_destroy", "surf_strerror", "surf_version",
@@ -99,6 +100,7 @@ def lib():
         L.surf_force.argtypes = [vp, vp, vp]
         L.surf_interface_force.argtypes = [vp, vp, vp, vp, vp]
         L.surf_prepare_geometry.argtypes = [vp, vp, vp]
+        L.surf_prepare_phase.argtypes = [vp, vp, vp]
         L.surf_time_transport.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_double)]
         L.surf_set_dt.argtypes = [vp, ctypes.c_double]
@@ -279,6 +281,14 @@ class Surf:
         self._check(self.L.surf_prepare_geometry(self.ctx, _ptr(self._cell(vof_next, "vof_next")),
                                                  ctypes.c_void_p(stream.cuda_stream)),
                     "surf_prepare_geometry")
+
+    def prepare_phase(self, u, stream):
+        """ACDI: enqueues the next step's ACDI step on `stream` (a torch stream
+        other than the context's); the next step() gets vof_next=None and
+        the same u."""
+        self._check(self.L.surf_prepare_phase(self.ctx, self._faces(u, "u"),
+                                              ctypes.c_void_p(stream.cuda_stream)),
+                    "surf_prepare_phase")
 
     def time_transport(self, F_in, psi_in, F_out, psi_out, u=None, sigma_out=None, reps=100):
         """Mean milliseconds of one transport-kernel launch over `reps`

@@ -242,3 +242,36 @@ def test_advection_variant_validation():
     nbb = ctypes.c_size_t(0)
     assert L.surf_batch_workspace_bytes(1, ctypes.byref(g), ctypes.byref(p),
                                         ctypes.byref(nbb)) == -1
+
+
+def test_prepare_phase_validation():
+    """surf_prepare_phase: ACDI contexts on the 2D weighted-form path only,
+    and a level set first; checked before any device work."""
+    import ctypes
+    from paper_2605_27534_amd import surf as S
+    L = S.lib()
+
+    def ctx_of(prob):
+        g, p, _ = S.make_structs(prob, 1e-3, S.SURF_F32)
+        nb = ctypes.c_size_t(0)
+        assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == 0
+        buf = ctypes.create_string_buffer(nb.value + 512)
+        base = (ctypes.addressof(buf) + 255) // 256 * 256
+        ctx = ctypes.c_void_p()
+        assert L.surf_init(ctypes.byref(ctx), ctypes.byref(g), ctypes.byref(p),
+                           ctypes.c_void_p(base), nb, None) == 0
+        return ctx, buf, base
+
+    fake_stream = ctypes.c_void_p(1)  # never used: every check fails first
+    acdi = dict(dim=2, n=(32, 32), h=1 / 32, bc=((0, 0), (0, 0)), interface=1, acdi_zeta=0.5)
+    ctx, buf, base = ctx_of(acdi)
+    assert L.surf_prepare_phase(ctx, None, None) == -1
+    assert L.surf_prepare_phase(ctx, None, fake_stream) == -4  # no level set yet
+    half = (ctypes.c_void_p * 3)(base, None, None)
+    assert L.surf_prepare_phase(ctx, half, fake_stream) == -1
+    assert L.surf_destroy(ctx) == 0
+    for bad in (dict(interface=0), dict(flux_form=1),
+                dict(dim=3, n=(16, 16, 16), bc=((0, 0), (0, 0), (0, 0)))):
+        ctx, buf, base = ctx_of(dict(acdi, **bad))
+        assert L.surf_prepare_phase(ctx, None, fake_stream) == -1, bad
+        assert L.surf_destroy(ctx) == 0

@@ -214,3 +214,90 @@ def test_time_acdi_leaves_the_state_alone():
         outs.append([x.clone() for x in (F, P, sig, s.phase(), s.levelset())])
     for a, b in zip(*outs):
         assert torch.equal(a, b)
+
+
+def _acdi_run(prec, pipelined, graph=False, nsteps=9, reinit_at=(4,)):
+    """nsteps ACDI steps (a re-initialization from the VoF at the steps in
+    reinit_at), each next ACDI step prepared on a second stream when
+    pipelined; with graph, the steps after the first are captured once and
+    replayed."""
+    import torch
+    n = (150, 131)
+    h = 1.0 / 150
+    R0, Q = 0.15, 0.05
+    cen = (0.5, 0.46, 0)
+    u = synth.u_source2d(n, h, cen, Q)
+    dt = 0.15 * h * h / 1e-2
+    Rt = lambda t: math.sqrt(R0 ** 2 + Q * t / math.pi)
+    prob = dict(dim=2, n=n, h=h, bc=((2, 2), (2, 0)), eos=1, eos_E=0.2, interface=1,
+                acdi_zeta=1.1 * max_speed(u))
+    main = torch.cuda.Stream()
+    aux = torch.cuda.Stream()
+    with torch.cuda.stream(main):
+        s = S.Surf(prob, dt, prec)
+        T = s.tensor
+        s.set_geometry(T(synth.vof_ball(n, h, cen, R0, 2)), full=True)
+        F, P = s.init_state(T(synth.uniform_field(n, 3, 0.8, 1.2)), 1.0, 0.4)
+        ud = [T(x) for x in u]
+        vofs = {k: T(synth.vof_ball(n, h, cen, Rt(k * dt), 2)) for k in reinit_at}
+        bufs = [[F, P], [s.empty(), s.empty()]]
+        sig = s.empty()
+        hist = torch.zeros((nsteps, 16), dtype=torch.float64, device="cuda")
+
+        def run(k0, k1):
+            for k in range(k0, k1):
+                a, b = bufs[k % 2], bufs[(k + 1) % 2]
+                s.step(a[0], a[1], b[0], b[1], u=ud, vof_next=vofs.get(k), sigma_out=sig,
+                       totals=hist[k])
+                if pipelined and k + 1 < k1 and (k + 1) not in vofs:
+                    s.prepare_phase(ud, aux)
+
+        if graph:
+            run(0, 1)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=main):
+                run(1, nsteps)
+            g.replay()
+        else:
+            run(0, nsteps)
+        torch.cuda.synchronize()
+    last = bufs[nsteps % 2]
+    return [x.clone() for x in (last[0], last[1], sig, s.phase(), s.levelset())] + [hist.clone()]
+
+
+@pytest.mark.parametrize("prec", [F64, F32])
+def test_pipelined_acdi_equals_serial(prec):
+    # surf_prepare_phase runs each next ACDI step on a second stream during
+    # the transport; the results are those of plain steps, bit for bit, also
+    # from a captured graph, with a re-initialization in between
+    import torch
+    ref = _acdi_run(prec, False)
+    for graph in (False, True):
+        got = _acdi_run(prec, True, graph=graph)
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), graph
+
+
+def test_prepare_phase_call_order():
+    import torch
+    n = (64, 48)
+    h = 1.0 / 64
+    prob = dict(dim=2, n=n, h=h, bc=((0, 0), (0, 0)), interface=1, acdi_zeta=0.5)
+    s = S.Surf(prob, 1e-4, S.SURF_F32)
+    T = s.tensor
+    aux = torch.cuda.Stream()
+    s.set_geometry(T(synth.vof_ball(n, h, (0.5, 0.4, 0), 0.2, 2)), full=True)
+    F, P = s.init_state(None, 1.0, 0.3)
+    F2, P2 = s.empty(), s.empty()
+    s.prepare_phase(None, aux)
+    for call in (lambda: s.prepare_phase(None, aux), lambda: s.phase(),
+                 lambda: s.levelset(), lambda: s.time_acdi(reps=2),
+                 lambda: s.step(F, P, F2, P2, vof_next=T(synth.vof_ball(n, h, (0.5, 0.4, 0),
+                                                                         0.2, 2)))):
+        with pytest.raises(S.SurfError) as e:
+            call()
+        assert e.value.code == -4
+    s.step(F, P, F2, P2)  # the prepared step, no flow as prepared
+    torch.cuda.synchronize()
+    assert s.phase() is not None
