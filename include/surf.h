@@ -12,6 +12,12 @@
  *              (sections 2.6, 3.1, 3.2, Appendices A and C);
  *   EoS        sigma(Gamma) (sections 2.3, 5, 6);
  * plus the Marangoni face force delta (I - n n) grad sigma (section 2.4).
+ * Options of the same step: substep 2 implicit (section 3.1, Appendix C),
+ * the ACDI phase field in place of the per-step level set (section 2.5),
+ * axisymmetric rings (Appendix B), and the MC limiter and transverse term
+ * of the unsplit BCG advection (section 3.1).  Beside the step: the
+ * capillary and PLIC Marangoni forces for a flow solver (section 2.4), a
+ * batched form for many small instances, and the discrete adjoint.
  *
  * Conventions
  *  - Every function returns SURF_OK (0) or a negative SURF_E* code; no
