@@ -336,3 +336,52 @@ def test_translating_sphere_banded_redistancing(prec, ksweeps):
     g = run_gpu(prob, vof0, 24, dt, prec, u=u, vof_seq=vs, c0=cf, gamma0=0.3, hj_step=ksweeps)
     compare(o, g, prec)
     assert g[5].status() & 8 == 0
+
+
+def test_expanding_circle_full_size_parity():
+    # the 1024^2 expanding circle of the benchmark in its launch
+    # configuration (VoF recomputed every step, 8 warm-start sweeps), FP32,
+    # 4 steps, every cell against the oracle
+    from paper_2605_27534_amd import configs as C
+    cfg = C.c1_expanding_circle()
+    prob = dict(cfg["prob"])
+    vof0, u, c0 = cfg["vof0"](), cfg["u"](), cfg["c0"]()
+    o = run_oracle(prob, vof0, 4, cfg["dt"], u=u, vof_seq=cfg["vof_seq"], c0=c0,
+                   gamma0=cfg["gamma0"])
+    g = run_gpu(prob, vof0, 4, cfg["dt"], F32, u=u, vof_seq=cfg["vof_seq"], c0=c0,
+                gamma0=cfg["gamma0"])
+    print(compare(o, g, F32), flush=True)
+
+
+def test_translating_sphere_full_size_transport():
+    # 256^3: the initial state and one transport step of the 3D benchmark in
+    # its launch configuration, both sides from the level set the library
+    # builds (the oracle's own 108-sweep build at this size would take
+    # minutes on one host thread); every cell compared
+    import torch
+    from paper_2605_27534_amd import configs as C
+    from paper_2605_27534_amd import surf as S
+    from tests.harness import to_np
+    cfg = C.c2_translating_sphere()
+    prob = dict(cfg["prob"])
+    s = S.Surf(prob, cfg["dt"], F32)
+    T = s.tensor
+    s.set_geometry(T(cfg["vof0"]()), full=True)
+    chi = to_np(s.levelset())
+    F, P = s.init_state(None, 1.0, 0.0)
+    u = cfg["u_seq"](0)
+    F2, P2, sig = s.empty(), s.empty(), s.empty()
+    tot = torch.zeros(16, dtype=torch.float64, device="cuda")
+    s.step(F, P, F2, P2, u=[T(x) for x in u], sigma_out=sig, totals=tot)
+    torch.cuda.synchronize()
+    Fo, Po = O.init_state(prob, chi, c0_const=1.0, gamma0=0.0)
+    assert rel_max(to_np(F), Fo) <= TOL[F32]
+    Fn, Pn, Sn, tn = O.step(prob, chi, u, Fo, Po, cfg["dt"])
+    errs = {"F": rel_max(to_np(F2), Fn), "psi": rel_max(to_np(P2), Pn),
+            "sigma": rel_max(to_np(sig), Sn)}
+    print(errs, flush=True)
+    assert all(e <= TOL[F32] for e in errs.values()), errs
+    tg = tot.cpu().numpy()
+    for slot in (O.T_MB, O.T_MS, O.T_SDELTA, O.T_MTOT):
+        assert abs(tg[slot] - tn[slot]) <= TOL[F32] * abs(tn[slot]), (slot, tg[slot], tn[slot])
+    assert s.status() == 0
