@@ -257,7 +257,7 @@ def main():
         # 2D moving interface: step k+1's geometry is prepared on `aux` while
         # step k's transport runs on `side`; every run of steps ends with no
         # geometry pending
-        pipelined = (vofs is not None and prob["dim"] == 2 and prob.get("flux_form", 0) == 0
+        pipelined = (vofs is not None and prob.get("flux_form", 0) == 0
                      and not args.no_pipeline and not reinit)
         # ACDI: each next ACDI step is prepared on `aux` during the transport
         # (steps that re-initialize from a VoF field run it in the step)

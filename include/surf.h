@@ -247,22 +247,25 @@ int surf_step(surf_ctx* ctx, const void* vof_next, const void* const* u,
               const void* F_in, const void* psi_in, void* F_out, void* psi_out,
               void* sigma_out, double* totals_dev);
 
-/* Pipelined moving interface (2D, weighted flux form).  The geometry of a
- * step, chi^{n+1} from the VoF at t^{n+1} (section 2.5, as surf_step does it),
- * depends only on that VoF and chi^n, not on the transported state, so it
- * can run while the previous step's transport runs.  This call enqueues it
- * on aux_stream (a HIP stream other than the context's, at the default
- * priority) after the last transport enqueued on the context's stream has
- * consumed the level-set buffer it overwrites; the next surf_step, which
- * must receive the same vof_next pointer, then runs only the transport, on
- * the context's stream, after the prepared geometry.  Typical order:
+/* Pipelined moving interface (weighted flux form, 2D or 3D).  The geometry
+ * of a step, chi^{n+1} from the VoF at t^{n+1} (section 2.5, as surf_step
+ * does it), depends only on that VoF and chi^n, not on the transported
+ * state, so it can run while the previous step's transport runs.  This call
+ * enqueues it on aux_stream (a HIP stream other than the context's, at the
+ * default priority) after the last transport enqueued on the context's
+ * stream has consumed the level-set buffer it overwrites (in 3D, where the
+ * sweeps rewrite both level-set buffers, a pipelined step's transport reads
+ * a copy of the level set taken at its start; level-set reads and writes
+ * enqueued after that step make the geometry wait for them); the next
+ * surf_step, which must receive the same vof_next pointer, then runs only
+ * the transport, on the context's stream, after the prepared geometry.  Typical order:
  * surf_step(vof_1); then for n >= 1: surf_prepare_geometry(vof_{n+1}),
  * surf_step(vof_{n+1}).  Results equal those of plain surf_step calls.
  *   vof_next  VoF at t^{n+1}; the caller makes it ready with respect to
  *             aux_stream and keeps it unchanged until that surf_step.
- * Errors: SURF_EINVAL for a 3D or paper-form context, more than 16 sweeps
- * per step, a grid below 2 (K + 2) cells per axis, null arguments or a
- * misaligned vof_next; SURF_ESTATE without a level set or with a prepared
+ * Errors: SURF_EINVAL for a paper-form, implicit or ACDI context, more than
+ * 16 sweeps per step (3D: an odd count or under 2), a 2D grid below
+ * 2 (K + 2) cells per axis, null arguments or a misaligned vof_next; SURF_ESTATE without a level set or with a prepared
  * geometry still pending.  While one is pending only surf_step (with that
  * vof_next), surf_set_dt and the status calls are accepted; the level-set,
  * state, force and adjoint calls return SURF_ESTATE. */

@@ -76,6 +76,10 @@ struct surf_ctx {
   // (prepared then points at prepared_phase), with the velocity it took
   bool prepared_phase = false;
   const void* prep_u0 = nullptr;
+  // 3D weighted form: the level set a pipelined step's transport reads,
+  // copied from chi[chi_cur] so that the next step's geometry may rewrite
+  // both level-set buffers meanwhile
+  void* chi_snap = nullptr;
   bool materialized;  // chi[chi_cur] holds explicit values on every tile
   // adjoint scratch: advected state, nu, per-workgroup dtheta partials
   void* adj[4];
@@ -276,6 +280,12 @@ int col_shape(const surf_grid* gr, const surf_params* p, int* strips, int* group
 // or C3_TZ64 (FP64).  Returns the workgroup count (0 when the kernel does not
 // apply).
 constexpr int C3_TZ = 16, C3_TZ64 = 8;
+
+// the 3D pipelined moving interface keeps a snapshot of the level set
+bool snapshot_needed(const surf_grid* gr, const surf_params* p, int nc3) {
+  return gr->dim == 3 && nc3 > 0 && p->substep2 == SURF_SUBSTEP2_EXPLICIT &&
+         p->interface == SURF_IFACE_VOF;
+}
 int col3_shape(const surf_grid* gr, const surf_params* p, int* s) {
   s[0] = s[1] = s[2] = 0;
   if (gr->dim != 3 || p->flux_form != SURF_FLUX_WEIGHTED) return 0;
@@ -601,7 +611,8 @@ bool geo3_ok(const surf_ctx* c) {
 // The level set stays in chi[chi_cur] (R); chi[1 - chi_cur] (S) is the
 // sweeps' partner and its flag array also carries this step's live marks.
 template <typename R>
-void geo3_impl(surf_ctx* c, const void* vof) {
+void geo3_impl(surf_ctx* c, const void* vof, hipStream_t st = nullptr) {
+  if (!st) st = c->stream;
   Geo3Args ga;
   ga.g = c->g;
   for (int d = 0; d < 3; ++d) ga.tiles[d] = c->g3tiles[d];
@@ -614,10 +625,10 @@ void geo3_impl(surf_ctx* c, const void* vof) {
   uint8_t* qS = c->q[1 - c->chi_cur];
   const int K = c->prm.hj_iters_step;
   {
-    Timed tm(c, 1);
-    hipLaunchKernelGGL(k_geo3_classify<R>, dim3(8 * ga.per_xcd), dim3(G3_THREADS), 0, c->stream,
+    Timed tm(c, 1, st);
+    hipLaunchKernelGGL(k_geo3_classify<R>, dim3(8 * ga.per_xcd), dim3(G3_THREADS), 0, st,
                        ga, p, (const R*)vof, chiS, (R*)c->g0, (const uint8_t*)qR, qS, c->state);
-    hipLaunchKernelGGL(k_geo3_list, dim3(1), dim3(G3_LIST_THREADS), 0, c->stream,
+    hipLaunchKernelGGL(k_geo3_list, dim3(1), dim3(G3_LIST_THREADS), 0, st,
                        (const uint8_t*)qS, c->ng3, c->live3);
     const R dtau = (R)(c->grid.h / 3);
     for (int k = 1; k <= K; ++k) {
@@ -625,7 +636,7 @@ void geo3_impl(surf_ctx* c, const void* vof) {
       const R* src = (k & 1) ? chiR : chiS;
       R* dst = (k & 1) ? chiS : chiR;
       hipLaunchKernelGGL(k_geo3_sweep<R>, dim3(G3_SWEEP_GRID), dim3(G3_SWEEP_THREADS), 0,
-                         c->stream, ga, p, dtau, src, dst, (const R*)c->g0, qR,
+                         st, ga, p, dtau, src, dst, (const R*)c->g0, qR,
                          (const int*)c->live3, k == K ? 1 : 0);
     }
   }
@@ -664,11 +675,11 @@ void col2d_transport(surf_ctx* c, const void* const* u, const void* F_in, const 
 // The 3D weighted-form transport kernel alone, on the context's stream.
 template <typename R>
 void col3d_transport(surf_ctx* c, const void* const* u, const void* F_in, const void* psi_in,
-                     void* F_out, void* psi_out, void* sigma_out) {
+                     void* F_out, void* psi_out, void* sigma_out, const void* chi = nullptr) {
   Col3Args<R> a;
   a.g = c->g;
   a.p = make_par<R>(c);
-  a.chi = (const R*)c->chi[c->chi_cur];
+  a.chi = (const R*)(chi ? chi : c->chi[c->chi_cur]);
   const bool has_u = u && u[0];
   const bool bulk = c->prm.bulk_enabled != 0;
   for (int d = 0; d < 3; ++d) a.u[d] = has_u ? (const R*)u[d] : nullptr;
@@ -806,11 +817,31 @@ int step2d_impl(surf_ctx* c, const void* vof_next, const void* const* u, const v
   return status_of_launch();
 }
 
+// A 3D step whose geometry was prepared on the auxiliary stream (the caller
+// has made the context's stream wait for it): the level set is copied to the
+// snapshot, the point after which the next prepared geometry may rewrite the
+// level-set buffers is recorded, and the transport reads the snapshot.
+template <typename R>
+int col3d_prepared_step(surf_ctx* c, const void* const* u, const void* F_in, const void* psi_in,
+                        void* F_out, void* psi_out, void* sigma_out, double* totals) {
+  hipLaunchKernelGGL(k_copy<R>, dim3(grid1d(c->ncell)), dim3(BLOCK), 0, c->stream,
+                     (const R*)c->chi[c->chi_cur], (R*)c->chi_snap, c->ncell);
+  if (hipEventRecord(c->ev_pre, c->stream) != hipSuccess) return SURF_EDEVICE;
+  c->pre_valid = true;
+  {
+    Timed tm(c, 0);
+    col3d_transport<R>(c, u, F_in, psi_in, F_out, psi_out, sigma_out, c->chi_snap);
+  }
+  finalize<R>(c, totals, c->c3_nwg);
+  return status_of_launch();
+}
+
 template <typename R>
 int step_impl(surf_ctx* c, const void* const* u, const void* F_in, const void* psi_in,
               void* F_out, void* psi_out, void* sigma_out, double* totals) {
   if (c->grid.dim == 2)
     return step2d_impl<R>(c, nullptr, u, F_in, psi_in, F_out, psi_out, sigma_out, totals);
+  c->pre_valid = false;  // this transport reads chi[chi_cur] itself
   materialize<R>(c);
   if (c->c3_nwg > 0) {
     // weighted form in 3D: plane-marching transport, then the reduction
@@ -1089,6 +1120,13 @@ int iface_force_impl(surf_ctx* c, const void* vof, const void* sigma, void* cons
 
 bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
+// Work that reads or writes the level set on the context's stream outside a
+// step: a geometry prepared next must wait for all of it, not only for the
+// point recorded before the last transport.
+void touch_levelset(surf_ctx* c) {
+  if (c) c->pre_valid = false;
+}
+
 // ---------------------------------------------------------------- batches
 Grid grid_of(const surf_grid& gr) {
   Grid g;
@@ -1208,6 +1246,7 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
     b += align_up((size_t)((n + BLOCK - 1) / BLOCK) * NADJ * sizeof(double));
   }
   if (params->interface == SURF_IFACE_ACDI) b += 3 * align_up(n * es);
+  if (snapshot_needed(grid, params, nc3)) b += align_up(n * es);
   if (imp) {
     b += IMP_FIELDS * align_up(n * sizeof(double));
     b += align_up((size_t)nimp * 2 * sizeof(double));
@@ -1288,6 +1327,10 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
       c->acdi[i] = p;
       p += align_up(c->ncell * es);
     }
+  if (snapshot_needed(grid, params, c->c3_nwg)) {
+    c->chi_snap = p;
+    p += align_up(c->ncell * es);
+  }
   if (imp) {
     double** f[IMP_FIELDS] = {&c->imp.Fs,   &c->imp.Ps,   &c->imp.wF,   &c->imp.wP,
                               &c->imp.xF,   &c->imp.xP,   &c->imp.dg,   &c->imp.minv,
@@ -1315,6 +1358,7 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
 }
 
 int surf_set_geometry(surf_ctx* c, const void* vof, int full_rebuild) {
+  touch_levelset(c);
   if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !vof) return SURF_EINVAL;
   if (!full_rebuild && !c->has_chi) return SURF_ESTATE;
@@ -1323,6 +1367,7 @@ int surf_set_geometry(surf_ctx* c, const void* vof, int full_rebuild) {
 }
 
 int surf_set_levelset(surf_ctx* c, const void* chi) {
+  touch_levelset(c);
   if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !chi) return SURF_EINVAL;
   size_t bytes = (size_t)c->ncell * esize(&c->prm);
@@ -1338,6 +1383,7 @@ int surf_set_levelset(surf_ctx* c, const void* chi) {
 }
 
 int surf_get_phase(surf_ctx* c, void* phi_out) {
+  touch_levelset(c);
   if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !phi_out) return SURF_EINVAL;
   if (c->prm.interface != SURF_IFACE_ACDI) return SURF_EINVAL;
@@ -1350,6 +1396,7 @@ int surf_get_phase(surf_ctx* c, void* phi_out) {
 }
 
 int surf_get_levelset(surf_ctx* c, void* chi_out) {
+  touch_levelset(c);
   if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !chi_out) return SURF_EINVAL;
   if (!c->has_chi) return SURF_ESTATE;
@@ -1364,6 +1411,7 @@ int surf_get_levelset(surf_ctx* c, void* chi_out) {
 
 int surf_init_state(surf_ctx* c, const void* c0, double c0_const, double gamma0, void* F_out,
                     void* psi_out) {
+  touch_levelset(c);
   if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !psi_out) return SURF_EINVAL;
   if (c->prm.bulk_enabled && !F_out) return SURF_EINVAL;
@@ -1430,6 +1478,13 @@ int surf_step(surf_ctx* c, const void* vof_next, const void* const* u, const voi
     if (vof_next != c->prepared) return SURF_ESTATE;
     c->prepared = nullptr;
     if (hipStreamWaitEvent(c->stream, c->ev_geo, 0) != hipSuccess) return SURF_EDEVICE;
+    if (c->grid.dim == 3) {
+      if (c->prm.precision == SURF_F32)
+        return col3d_prepared_step<float>(c, u, F_in, psi_in, F_out, psi_out, sigma_out,
+                                          totals_dev);
+      return col3d_prepared_step<double>(c, u, F_in, psi_in, F_out, psi_out, sigma_out,
+                                         totals_dev);
+    }
     if (c->prm.precision == SURF_F32)
       return col2d_impl<float>(c, vof_next, u, F_in, psi_in, F_out, psi_out, sigma_out,
                                totals_dev, true);
@@ -1468,6 +1523,7 @@ int surf_step(surf_ctx* c, const void* vof_next, const void* const* u, const voi
 int surf_time_transport(surf_ctx* c, const void* const* u, const void* F_in,
                         const void* psi_in, void* F_out, void* psi_out, void* sigma_out,
                         int32_t reps, double* ms_per_launch) {
+  touch_levelset(c);
   if (!c || !psi_in || !psi_out || !ms_per_launch || reps < 1) return SURF_EINVAL;
   const bool bulk = c->prm.bulk_enabled != 0;
   if (bulk && (!F_in || !F_out)) return SURF_EINVAL;
@@ -1511,6 +1567,7 @@ int surf_time_transport(surf_ctx* c, const void* const* u, const void* F_in,
 }
 
 int surf_time_acdi(surf_ctx* c, const void* const* u, int32_t reps, double* ms_per_step) {
+  touch_levelset(c);
   if (!c || !ms_per_step || reps < 1) return SURF_EINVAL;
   if (c->prm.interface != SURF_IFACE_ACDI) return SURF_EINVAL;
   if (u && u[0])
@@ -1522,6 +1579,7 @@ int surf_time_acdi(surf_ctx* c, const void* const* u, int32_t reps, double* ms_p
 }
 
 int surf_time_solver(surf_ctx* c, int32_t field, int32_t reps, double* ms_per_launch) {
+  touch_levelset(c);
   if (!c || !ms_per_launch || reps < 1 || field < 0 || field > 1) return SURF_EINVAL;
   if (c->prm.substep2 != SURF_SUBSTEP2_IMPLICIT) return SURF_EINVAL;
   if (field == 1 && !c->prm.bulk_enabled) return SURF_EINVAL;
@@ -1566,11 +1624,16 @@ int surf_prepare_phase(surf_ctx* c, const void* const* u, void* aux_stream) {
 
 int surf_prepare_geometry(surf_ctx* c, const void* vof_next, void* aux_stream) {
   if (!c || !vof_next || !aux_stream) return SURF_EINVAL;
-  if (c->grid.dim != 2 || c->col_nwg == 0 || c->prm.substep2 != SURF_SUBSTEP2_EXPLICIT ||
-      c->prm.interface != SURF_IFACE_VOF)
+  if (c->prm.substep2 != SURF_SUBSTEP2_EXPLICIT || c->prm.interface != SURF_IFACE_VOF)
     return SURF_EINVAL;
-  if (c->prm.precision == SURF_F32 ? !geom2d_ok<float>(c) : !geom2d_ok<double>(c))
+  const bool three = c->grid.dim == 3;
+  if (three) {
+    if (!c->chi_snap || (c->prm.precision == SURF_F32 ? !geo3_ok<float>(c) : !geo3_ok<double>(c)))
+      return SURF_EINVAL;
+  } else if (c->col_nwg == 0 ||
+             (c->prm.precision == SURF_F32 ? !geom2d_ok<float>(c) : !geom2d_ok<double>(c))) {
     return SURF_EINVAL;
+  }
   if (!c->has_chi || c->prepared) return SURF_ESTATE;
   if (!aligned(vof_next, esize(&c->prm))) return SURF_EINVAL;
   if (!c->ev_pre) {
@@ -1585,7 +1648,10 @@ int surf_prepare_geometry(surf_ctx* c, const void* vof_next, void* aux_stream) {
   if (!c->pre_valid && hipEventRecord(c->ev_pre, c->stream) != hipSuccess) return SURF_EDEVICE;
   c->pre_valid = false;
   if (hipStreamWaitEvent(aux, c->ev_pre, 0) != hipSuccess) return SURF_EDEVICE;
-  {
+  if (three) {
+    if (c->prm.precision == SURF_F32) geo3_impl<float>(c, vof_next, aux);
+    else geo3_impl<double>(c, vof_next, aux);
+  } else {
     Timed tm(c, 1, aux);
     if (c->prm.precision == SURF_F32) geo2d_launch<float>(c, vof_next, aux);
     else geo2d_launch<double>(c, vof_next, aux);
@@ -1596,6 +1662,7 @@ int surf_prepare_geometry(surf_ctx* c, const void* vof_next, void* aux_stream) {
 }
 
 int surf_force(surf_ctx* c, const void* sigma, void* const* force) {
+  touch_levelset(c);
   if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !sigma || !force) return SURF_EINVAL;
   for (int d = 0; d < c->grid.dim; ++d)
@@ -1607,6 +1674,7 @@ int surf_force(surf_ctx* c, const void* sigma, void* const* force) {
 
 int surf_interface_force(surf_ctx* c, const void* vof, const void* sigma, void* const* f_cap,
                          void* const* f_ma) {
+  touch_levelset(c);
   if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !vof || !sigma || (!f_cap && !f_ma)) return SURF_EINVAL;
   if (c->grid.dim != 2 || c->grid.axisym) return SURF_EINVAL;
@@ -1679,6 +1747,7 @@ int surf_loss_weights(surf_ctx* c, const double* tot, int64_t stride, const doub
 }
 
 int surf_adjoint_seed(surf_ctx* c, const void* psi, const double* w, void* lF, void* lP) {
+  touch_levelset(c);
   if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !psi || !w || !lP) return SURF_EINVAL;
   if (!c->prm.adjoint) return SURF_ESTATE;
@@ -1701,6 +1770,7 @@ int surf_adjoint_seed(surf_ctx* c, const void* psi, const double* w, void* lF, v
 int surf_adjoint_step(surf_ctx* c, const void* const* u, const void* F, const void* psi,
                       const void* mF, const void* mP, const double* w, void* lF, void* lP,
                       double* dtheta) {
+  touch_levelset(c);
   if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !psi || !mP || !lP || !dtheta) return SURF_EINVAL;
   if (!c->prm.adjoint || c->prm.flux_form != SURF_FLUX_WEIGHTED) return SURF_ESTATE;
@@ -1717,6 +1787,7 @@ int surf_adjoint_step(surf_ctx* c, const void* const* u, const void* F, const vo
 }
 
 int surf_adjoint_c0(surf_ctx* c, const void* lF0, void* gc0) {
+  touch_levelset(c);
   if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !lF0 || !gc0) return SURF_EINVAL;
   if (!c->has_chi) return SURF_ESTATE;

@@ -301,4 +301,12 @@ __global__ void __launch_bounds__(G3_SWEEP_THREADS) k_geo3_sweep(Geo3Args ga, Pa
   }
 }
 
+// dst = src over n cells (the level-set snapshot of a pipelined 3D step)
+template <typename R>
+__global__ void __launch_bounds__(BLOCK) k_copy(const R* __restrict__ src, R* __restrict__ dst,
+                                                long long n) {
+  const long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
 }  // namespace surf
