@@ -15,7 +15,7 @@ The paper evolves phi by the Allen-Cahn-type ACDI equation
 with the auxiliary signed-distance-like field s = eps ln((phi + ve) / (1 - phi + ve))
 (the paper calls it psi; here psi is the interfacial carrier), ve = 1e-6, and
 the velocity scale zeta at least the largest speed.  Readings (they are the
-build's readings too):
+HIP library's readings too):
 
 * the same Lie split as the surfactant fields: phi* = the advection of phi by
   the substep-1 scheme (BCG face values with the minmod limiter, flux form),

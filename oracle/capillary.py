@@ -7,7 +7,7 @@ never does.  It shares no code with the HIP library.
 
 Notation: c the VoF fraction of fluid 1, chi the signed distance (> 0 in
 fluid 1), phi the phase field (0 in fluid 1), n = grad phi / |grad phi| the
-unit normal, pointing out of fluid 1.  Readings (the build's too):
+unit normal, pointing out of fluid 1.  Readings (the HIP library takes the same):
 
 * kappa = -div n by height functions (Cummins, Francois and Kothe, Comput.
   Struct. 83, 2005) in each cell with 0 < c < 1: along the axis of the

@@ -1,6 +1,6 @@
 // surf_acdi.hpp -- the phase field phi evolved by ACDI (section 2.5, the
 // Phase-Field method) instead of a level set rebuilt from the VoF at every
-// step.  The paper's ACDI equation, in the build's notation:
+// step.  The paper's ACDI equation, in this library's notation:
 //
 //   d phi/dt + div(u phi) = div( zeta [ eps grad phi
 //                                       - 1/4 (1 - tanh^2(s/(2 eps))) grad s/|grad s| ] )
