@@ -181,9 +181,10 @@ typedef struct {
                          * dt/2 times the upwind cell's mean transverse
                          * velocity times its one-sided transverse
                          * difference on the upwind side.  Either variant
-                         * needs a 2D Cartesian grid, the weighted flux
-                         * form, explicit substep 2, the VoF interface and
-                         * no adjoint (SURF_EINVAL otherwise)            */
+                         * needs a 2D grid (Cartesian or axisymmetric, where
+                         * the face values are the Cartesian ones), the
+                         * weighted flux form, explicit substep 2, the VoF
+                         * interface and no adjoint (SURF_EINVAL otherwise) */
 } surf_params;
 
 /* Bytes of device workspace a context needs. */

@@ -177,7 +177,7 @@ int check_grid_params(const surf_grid* gr, const surf_params* p) {
   if (p->limiter < 0 || p->limiter > 1 || p->transverse < 0 || p->transverse > 1)
     return SURF_EINVAL;
   if ((p->limiter || p->transverse) &&
-      (gr->dim != 2 || gr->axisym || p->flux_form != SURF_FLUX_WEIGHTED ||
+      (gr->dim != 2 || p->flux_form != SURF_FLUX_WEIGHTED ||
        p->substep2 != SURF_SUBSTEP2_EXPLICIT || p->interface != SURF_IFACE_VOF || p->adjoint))
     return SURF_EINVAL;
   if (p->substep2 == SURF_SUBSTEP2_IMPLICIT &&
@@ -527,6 +527,20 @@ template <typename R, int TY>
 void launch_col2d(surf_ctx* c, const ColArgs<R>& a, bool has_u, bool bulk) {
   const dim3 grid(8 * a.per_xcd), block(64 * COL_WAVES);
   if (c->grid.axisym) {
+    if (has_u && (c->prm.limiter || c->prm.transverse)) {
+      // substep-1 variants on the rings: Cartesian face values, ring weights
+      const int v = (c->prm.limiter ? 1 : 0) + (c->prm.transverse ? 2 : 0);
+      if (bulk) {
+        if (v == 1) hipLaunchKernelGGL((k_col2d<R, TY, true, true, true, 1, false>), grid, block, 0, c->stream, a);
+        else if (v == 2) hipLaunchKernelGGL((k_col2d<R, TY, true, true, true, 0, true>), grid, block, 0, c->stream, a);
+        else hipLaunchKernelGGL((k_col2d<R, TY, true, true, true, 1, true>), grid, block, 0, c->stream, a);
+      } else {
+        if (v == 1) hipLaunchKernelGGL((k_col2d<R, TY, true, false, true, 1, false>), grid, block, 0, c->stream, a);
+        else if (v == 2) hipLaunchKernelGGL((k_col2d<R, TY, true, false, true, 0, true>), grid, block, 0, c->stream, a);
+        else hipLaunchKernelGGL((k_col2d<R, TY, true, false, true, 1, true>), grid, block, 0, c->stream, a);
+      }
+      return;
+    }
     if (has_u && bulk) hipLaunchKernelGGL((k_col2d<R, TY, true, true, true>), grid, block, 0, c->stream, a);
     else if (has_u) hipLaunchKernelGGL((k_col2d<R, TY, true, false, true>), grid, block, 0, c->stream, a);
     else if (bulk) hipLaunchKernelGGL((k_col2d<R, TY, false, true, true>), grid, block, 0, c->stream, a);

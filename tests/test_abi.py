@@ -222,8 +222,9 @@ def test_interface_force_validation():
 
 
 def test_advection_variant_validation():
-    """The MC limiter and the transverse term: 2D Cartesian weighted form,
-    explicit substep 2, the VoF interface, no adjoint, no batch."""
+    """The MC limiter and the transverse term: 2D weighted form (Cartesian or
+    axisymmetric), explicit substep 2, the VoF interface, no adjoint, no
+    batch."""
     import ctypes
     from paper_2605_27534_amd import surf as S
     L = S.lib()
@@ -234,10 +235,12 @@ def test_advection_variant_validation():
         assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == 0, ok
     for bad in (dict(limiter=2), dict(bcg_transverse=-1), dict(flux_form=1), dict(substep2=1),
                 dict(interface=1, acdi_zeta=0.5), dict(adjoint=1),
-                dict(axisym=1, bc=((0, 2), (0, 0))),
                 dict(dim=3, n=(16, 16, 16), bc=((0, 0), (0, 0), (0, 0)))):
         g, p, _ = S.make_structs(dict(base, **bad), 1e-3, S.SURF_F32)
         assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == -1, bad
+    # on axisymmetric rings too
+    g, p, _ = S.make_structs(dict(base, axisym=1, bc=((0, 2), (0, 0))), 1e-3, S.SURF_F32)
+    assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == 0
     g, p, _ = S.make_structs(base, 1e-3, S.SURF_F32)
     nbb = ctypes.c_size_t(0)
     assert L.surf_batch_workspace_bytes(1, ctypes.byref(g), ctypes.byref(p),

@@ -84,3 +84,23 @@ def test_axisym_translating_sphere_moving_geometry(prec):
     o = run_oracle(prob, vof, 8, dt, u=u, vof_seq=seq, c0=c0, gamma0=0.4)
     g = run_gpu(prob, vof, 8, dt, prec, u=u, vof_seq=seq, c0=c0, gamma0=0.4)
     compare(o, g, prec)
+
+
+@pytest.mark.parametrize("prec", [F64, F32])
+@pytest.mark.parametrize("variant", [(1, 0), (0, 1), (1, 1)], ids=["mc", "transverse", "mc-transverse"])
+def test_axisym_advection_variants(variant, prec):
+    # the substep-1 variants on the rings (Cartesian face values, ring
+    # weights on the divergence), under the straining flow with open sides
+    lim, tr = variant
+    n = (130, 140)
+    h = 1.0 / 130
+    z0 = 0.55
+    prob = dict(dim=2, n=n, h=h, bc=((0, 2), (2, 2)), axisym=1, eos=0, eos_E=0.2,
+                k_a=1.0, k_d=0.5, limiter=lim, bcg_transverse=tr)
+    vof = synth.vof_ball(n, h, (0.0, z0, 0), 0.25, 2)
+    u = synth.u_axisym_strain(n, h, 0.3, z0)
+    dt = 0.15 * h * h / 1e-2
+    c0 = synth.uniform_field(n, 6, 0.8, 1.2)
+    o = run_oracle(prob, vof, 10, dt, u=u, c0=c0, gamma0=0.4)
+    g = run_gpu(prob, vof, 10, dt, prec, u=u, c0=c0, gamma0=0.4)
+    compare(o, g, prec)
