@@ -176,9 +176,11 @@ int check_grid_params(const surf_grid* gr, const surf_params* p) {
     return SURF_EINVAL;
   if (p->limiter < 0 || p->limiter > 1 || p->transverse < 0 || p->transverse > 1)
     return SURF_EINVAL;
+  // the variants run in the 2D weighted-form transport and in the implicit
+  // path's advection (2D or 3D)
   if ((p->limiter || p->transverse) &&
-      (gr->dim != 2 || p->flux_form != SURF_FLUX_WEIGHTED ||
-       p->substep2 != SURF_SUBSTEP2_EXPLICIT || p->interface != SURF_IFACE_VOF || p->adjoint))
+      (p->flux_form != SURF_FLUX_WEIGHTED || p->interface != SURF_IFACE_VOF || p->adjoint ||
+       (gr->dim != 2 && p->substep2 != SURF_SUBSTEP2_IMPLICIT)))
     return SURF_EINVAL;
   if (p->substep2 == SURF_SUBSTEP2_IMPLICIT &&
       (p->flux_form != SURF_FLUX_WEIGHTED || p->adjoint || p->picard_iters < 0 ||
@@ -1019,6 +1021,8 @@ ImpArgs<R> imp_args(surf_ctx* c) {
   a.Db = q.D_b;
   a.Ds = q.D_s;
   a.bulk = bulk ? 1 : 0;
+  a.lim = c->prm.limiter;
+  a.tr = c->prm.transverse;
   a.ncell = c->ncell;
   return a;
 }
@@ -1233,8 +1237,10 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   int cs, cg;
   int ncol = col_shape(grid, params, &cs, &cg);
   if (grid->axisym && ncol == 0) return SURF_EINVAL;  // the rings run on k_col2d only
-  // so do the substep-1 variants
-  if ((params->limiter || params->transverse) && ncol == 0) return SURF_EINVAL;
+  // so do the explicit substep-1 variants
+  if ((params->limiter || params->transverse) && ncol == 0 &&
+      params->substep2 != SURF_SUBSTEP2_IMPLICIT)
+    return SURF_EINVAL;
   int c3s[3];
   int nc3 = col3_shape(grid, params, c3s);
   int npart = nblk > n2 ? nblk : n2;

@@ -99,6 +99,7 @@ struct ImpArgs {
   double dt, eta, eta_eps, ka, kd, ginf, kl, tol;  // FP64 coefficients
   double inv_h2, Db, Ds;
   int bulk;
+  int lim, tr;  // substep-1 variants: MC limiter, BCG transverse term
   long long ncell;
 };
 
@@ -172,7 +173,38 @@ __global__ void __launch_bounds__(IMP_BLOCK) k_imp_adv(ImpArgs<R> a, const R* __
                 w[d] = map_axis(x[d] + o, nd, g.bc[d][0], g.bc[d][1]);
                 return xi[cell_index(g, w[0], w[1], w[2])];
               };
-              fl = adv_flux<R>(uf, at(off - 1), at(off), at(off + 1), at(off + 2), cfl);
+              if (!a.lim && !a.tr) {
+                fl = adv_flux<R>(uf, at(off - 1), at(off), at(off + 1), at(off + 2), cfl);
+              } else {
+                // the variants: the upwind cell's value, its limited slope
+                // carried to the half-step foot, less dt/2h times its mean
+                // transverse velocity times its upwind transverse difference
+                const bool pos = uf > R(0);
+                const int uo = pos ? off : off + 1;  // the upwind cell along d
+                const R xm = at(uo - 1), xu = at(uo), xp = at(uo + 1);
+                const R k = R(0.5) * (R(1) - fabs(uf) * cfl);
+                const R sl = a.lim ? mc<R>(xu - xm, xp - xu) : minmod<R>(xu - xm, xp - xu);
+                R val = xu + (pos ? k : -k) * sl;
+                if (a.tr) {
+                  int w[3] = {x[0], x[1], x[2]};
+                  w[d] = map_axis(x[d] + uo, nd, g.bc[d][0], g.bc[d][1]);
+                  for (int t = 0; t < g.dim; ++t) {
+                    if (t == d) continue;
+                    int hi[3] = {w[0], w[1], w[2]};
+                    hi[t] = (g.bc[t][0] == BC_PERIODIC && w[t] + 1 == g.n[t]) ? 0 : w[t] + 1;
+                    const R vt = R(0.5) * (u[t][face_index(g, t, w[0], w[1], w[2])] +
+                                           u[t][face_index(g, t, hi[0], hi[1], hi[2])]);
+                    int lo[3] = {w[0], w[1], w[2]}, up[3] = {w[0], w[1], w[2]};
+                    lo[t] = map_axis(w[t] - 1, g.n[t], g.bc[t][0], g.bc[t][1]);
+                    up[t] = map_axis(w[t] + 1, g.n[t], g.bc[t][0], g.bc[t][1]);
+                    const R xc = xi[cell_index(g, w[0], w[1], w[2])];
+                    const R dxt = vt > R(0) ? xc - xi[cell_index(g, lo[0], lo[1], lo[2])]
+                                            : xi[cell_index(g, up[0], up[1], up[2])] - xc;
+                    val -= R(0.5) * cfl * vt * dxt;
+                  }
+                }
+                fl = uf * val;
+              }
             }
             div += s == 0 ? -fl : fl;
           }
