@@ -180,11 +180,12 @@ typedef struct {
                          * predictor in substep 1: each face value less
                          * dt/2 times the upwind cell's mean transverse
                          * velocity times its one-sided transverse
-                         * difference on the upwind side.  Either variant
-                         * needs a 2D grid (Cartesian or axisymmetric, where
-                         * the face values are the Cartesian ones), the
-                         * weighted flux form, explicit substep 2, the VoF
-                         * interface and no adjoint (SURF_EINVAL otherwise) */
+                         * difference on the upwind side (also in the ACDI
+                         * phase field's advection).  Either variant needs
+                         * the weighted flux form and no adjoint, and a 2D
+                         * grid (Cartesian or axisymmetric, where the face
+                         * values are the Cartesian ones) unless substep 2
+                         * is implicit (SURF_EINVAL otherwise)           */
 } surf_params;
 
 /* Bytes of device workspace a context needs. */

@@ -30,6 +30,7 @@
 // sets phi = 1/(1 + e^{chi/eps}) from the level set.
 #pragma once
 #include "surf_kernels.hpp"
+#include "surf_col2d.hpp"  // mc()
 
 namespace surf {
 
@@ -39,7 +40,44 @@ struct AcdiArgs {
   Par<R> p;
   R dt, cfl, zeta, ve;  // time step, dt/h, velocity scale, regularization of s
   long long ncell;
+  int lim, tr;          // substep-1 variants: MC limiter, BCG transverse term
 };
+
+// The advective flux through the face along d on side sd (0 low, 1 high) of
+// cell x with the substep-1 variants: the upwind cell's value and limited
+// slope (v: phi at x[d]-2 .. x[d]+2), less dt/2h times its mean transverse
+// velocity times its upwind transverse difference per transverse axis.
+template <typename R, int DIM>
+__device__ R acdi_flux_var(const AcdiArgs<R>& a, const R* __restrict__ phi,
+                           const R* const* u, const int* x, int d, int sd, R uf, const R* v) {
+  const Grid& g = a.g;
+  const bool pos = uf > R(0);
+  const int k0 = sd == 0 ? (pos ? 1 : 2) : (pos ? 2 : 3);  // the upwind cell in v
+  const R xm = v[k0 - 1], xu = v[k0], xp = v[k0 + 1];
+  const R k = R(0.5) * (R(1) - fabs(uf) * a.cfl);
+  const R sl = a.lim ? mc<R>(xu - xm, xp - xu) : minmod<R>(xu - xm, xp - xu);
+  R val = xu + (pos ? k : -k) * sl;
+  if (a.tr) {
+    int w[3] = {x[0], x[1], x[2]};
+    w[d] = map_axis(x[d] + k0 - 2, g.n[d], g.bc[d][0], g.bc[d][1]);
+#pragma unroll
+    for (int t = 0; t < DIM; ++t) {
+      if (t == d) continue;
+      int hi[3] = {w[0], w[1], w[2]};
+      hi[t] = (g.bc[t][0] == BC_PERIODIC && w[t] + 1 == g.n[t]) ? 0 : w[t] + 1;
+      const R vt = R(0.5) * (u[t][face_index(g, t, w[0], w[1], w[2])] +
+                             u[t][face_index(g, t, hi[0], hi[1], hi[2])]);
+      int lo[3] = {w[0], w[1], w[2]}, up[3] = {w[0], w[1], w[2]};
+      lo[t] = map_axis(w[t] - 1, g.n[t], g.bc[t][0], g.bc[t][1]);
+      up[t] = map_axis(w[t] + 1, g.n[t], g.bc[t][0], g.bc[t][1]);
+      const R xc = phi[cell_index(g, w[0], w[1], w[2])];
+      const R dxt = vt > R(0) ? xc - phi[cell_index(g, lo[0], lo[1], lo[2])]
+                              : phi[cell_index(g, up[0], up[1], up[2])] - xc;
+      val -= R(0.5) * a.cfl * vt * dxt;
+    }
+  }
+  return uf * val;
+}
 
 template <typename R>
 __device__ __forceinline__ R acdi_s(R phi, R eps, R ve) {
@@ -114,8 +152,14 @@ __global__ void __launch_bounds__(ACDI_TX) k_acdi_adv(AcdiArgs<R> a, const R* __
     for (int d = 0; d < DIM; ++d) {
       const bool per = g.bc[d][0] == BC_PERIODIC;
       const bool blo = !per && x[d] == 0, bhi = !per && x[d] + 1 == g.n[d];
-      const R flo_i = adv_flux<R>(ul[d], v[d][0], v[d][1], v[d][2], v[d][3], a.cfl);
-      const R fhi_i = adv_flux<R>(uh[d], v[d][1], v[d][2], v[d][3], v[d][4], a.cfl);
+      R flo_i, fhi_i;
+      if (a.lim || a.tr) {  // uniform
+        flo_i = acdi_flux_var<R, DIM>(a, phi, u, x, d, 0, ul[d], v[d]);
+        fhi_i = acdi_flux_var<R, DIM>(a, phi, u, x, d, 1, uh[d], v[d]);
+      } else {
+        flo_i = adv_flux<R>(ul[d], v[d][0], v[d][1], v[d][2], v[d][3], a.cfl);
+        fhi_i = adv_flux<R>(uh[d], v[d][1], v[d][2], v[d][3], v[d][4], a.cfl);
+      }
       const R flo = blo ? (g.bc[d][0] == BC_OPEN ? ul[d] * pc : R(0)) : flo_i;
       const R fhi = bhi ? (g.bc[d][1] == BC_OPEN ? uh[d] * pc : R(0)) : fhi_i;
       div += -flo;

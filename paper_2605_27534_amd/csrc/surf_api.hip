@@ -179,7 +179,7 @@ int check_grid_params(const surf_grid* gr, const surf_params* p) {
   // the variants run in the 2D weighted-form transport and in the implicit
   // path's advection (2D or 3D)
   if ((p->limiter || p->transverse) &&
-      (p->flux_form != SURF_FLUX_WEIGHTED || p->interface != SURF_IFACE_VOF || p->adjoint ||
+      (p->flux_form != SURF_FLUX_WEIGHTED || p->adjoint ||
        (gr->dim != 2 && p->substep2 != SURF_SUBSTEP2_IMPLICIT)))
     return SURF_EINVAL;
   if (p->substep2 == SURF_SUBSTEP2_IMPLICIT &&
@@ -442,6 +442,8 @@ void acdi_launch(surf_ctx* c, const void* const* u, R* phi_out, R* chi_out,
   a.zeta = (R)c->prm.acdi_zeta;
   a.ve = (R)c->prm.acdi_vareps;
   a.ncell = c->ncell;
+  a.lim = c->prm.limiter;
+  a.tr = c->prm.transverse;
   const bool has_u = u && u[0];
   const dim3 gr(acdi_xblocks(c->grid.n[0]) * c->grid.n[1] * c->grid.n[2]);
   const R* u0 = has_u ? (const R*)u[0] : nullptr;

@@ -301,3 +301,24 @@ def test_prepare_phase_call_order():
     s.step(F, P, F2, P2)  # the prepared step, no flow as prepared
     torch.cuda.synchronize()
     assert s.phase() is not None
+
+
+@pytest.mark.parametrize("prec", [F64, F32])
+@pytest.mark.parametrize("implicit", [0, 1], ids=["explicit", "implicit"])
+def test_acdi_with_unsplit_bcg(implicit, prec):
+    # the paper's full method on the ACDI interface: the phase field and the
+    # surfactant fields advected by the unsplit BCG scheme (MC limiter,
+    # transverse term), then the regularization and substep 2
+    n = (150, 131)
+    h = 1.0 / 150
+    cen = (0.5, 0.46, 0)
+    u = synth.u_rotation(n, h, cen, 0.8)
+    u = [u[0] + 0.15, u[1] - 0.1]
+    dt = 0.15 * h * h / 1e-2 * (1.5 if implicit else 1)  # below the ACDI bound
+    prob = dict(dim=2, n=n, h=h, bc=((2, 2), (1, 1)), eos=1, eos_E=0.2,
+                acdi_zeta=1.1 * max_speed(u), limiter=1, bcg_transverse=1)
+    if implicit:
+        prob.update(substep2=1, cg_tol=1e-15 if prec == F64 else 1e-9, cg_max_iters=1500)
+    o, g = run_both(prob, synth.vof_ball(n, h, cen, 0.17, 2), 6, dt, prec, u=u,
+                    c0=synth.uniform_field(n, 3, 0.8, 1.2))
+    compare(o, g, prec, 1.5 * h)
