@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(BLOCK) k_acdi_init(Grid g, Par<R> p, const R* 
 // substep 1 for phi, and s of the result.  Every load (the 5-cell stencil
 // along each axis, both face velocities) is issued up front from indices
 // mapped into the grid; the boundary cases only select among the results.
-template <typename R, int DIM>
+template <typename R, int DIM, bool VAR = false>
 __global__ void __launch_bounds__(ACDI_TX) k_acdi_adv(AcdiArgs<R> a, const R* __restrict__ phi,
                                                       const R* __restrict__ u0,
                                                       const R* __restrict__ u1,
@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(ACDI_TX) k_acdi_adv(AcdiArgs<R> a, const R* __
       const bool per = g.bc[d][0] == BC_PERIODIC;
       const bool blo = !per && x[d] == 0, bhi = !per && x[d] + 1 == g.n[d];
       R flo_i, fhi_i;
-      if (a.lim || a.tr) {  // uniform
+      if constexpr (VAR) {  // the substep-1 variants (a separate instantiation)
         flo_i = acdi_flux_var<R, DIM>(a, phi, u, x, d, 0, ul[d], v[d]);
         fhi_i = acdi_flux_var<R, DIM>(a, phi, u, x, d, 1, uh[d], v[d]);
       } else {

@@ -449,14 +449,23 @@ void acdi_launch(surf_ctx* c, const void* const* u, R* phi_out, R* chi_out,
   const R* u0 = has_u ? (const R*)u[0] : nullptr;
   const R* u1 = has_u ? (const R*)u[1] : nullptr;
   const R* u2 = (has_u && c->grid.dim == 3) ? (const R*)u[2] : nullptr;
+  const bool var = c->prm.limiter || c->prm.transverse;
   if (c->grid.dim == 3) {
-    hipLaunchKernelGGL((k_acdi_adv<R, 3>), gr, dim3(ACDI_TX), 0, st, a,
-                       (const R*)c->acdi[0], u0, u1, u2, (R*)c->acdi[1], (R*)c->acdi[2]);
+    if (var)
+      hipLaunchKernelGGL((k_acdi_adv<R, 3, true>), gr, dim3(ACDI_TX), 0, st, a,
+                         (const R*)c->acdi[0], u0, u1, u2, (R*)c->acdi[1], (R*)c->acdi[2]);
+    else
+      hipLaunchKernelGGL((k_acdi_adv<R, 3>), gr, dim3(ACDI_TX), 0, st, a,
+                         (const R*)c->acdi[0], u0, u1, u2, (R*)c->acdi[1], (R*)c->acdi[2]);
     hipLaunchKernelGGL((k_acdi_reg<R, 3>), gr, dim3(ACDI_TX), 0, st, a,
                        (const R*)c->acdi[1], (const R*)c->acdi[2], phi_out, chi_out);
   } else {
-    hipLaunchKernelGGL((k_acdi_adv<R, 2>), gr, dim3(ACDI_TX), 0, st, a,
-                       (const R*)c->acdi[0], u0, u1, u2, (R*)c->acdi[1], (R*)c->acdi[2]);
+    if (var)
+      hipLaunchKernelGGL((k_acdi_adv<R, 2, true>), gr, dim3(ACDI_TX), 0, st, a,
+                         (const R*)c->acdi[0], u0, u1, u2, (R*)c->acdi[1], (R*)c->acdi[2]);
+    else
+      hipLaunchKernelGGL((k_acdi_adv<R, 2>), gr, dim3(ACDI_TX), 0, st, a,
+                         (const R*)c->acdi[0], u0, u1, u2, (R*)c->acdi[1], (R*)c->acdi[2]);
     hipLaunchKernelGGL((k_acdi_reg<R, 2>), gr, dim3(ACDI_TX), 0, st, a,
                        (const R*)c->acdi[1], (const R*)c->acdi[2], phi_out, chi_out);
   }
