@@ -1705,7 +1705,10 @@ int surf_force(surf_ctx* c, const void* sigma, void* const* force) {
 
 int surf_interface_force(surf_ctx* c, const void* vof, const void* sigma, void* const* f_cap,
                          void* const* f_ma) {
-  touch_levelset(c);
+  // the force kernel only reads the current level set, which a geometry
+  // prepared next leaves alone (it writes the other buffer); filling in the
+  // current buffer from its compact form does write it
+  if (c && !c->materialized) touch_levelset(c);
   if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !vof || !sigma || (!f_cap && !f_ma)) return SURF_EINVAL;
   if (c->grid.dim != 2 || c->grid.axisym) return SURF_EINVAL;

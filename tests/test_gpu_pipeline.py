@@ -64,14 +64,19 @@ class Runner:
             self.bufs[0][1].copy_(P)
         torch.cuda.synchronize()
 
-    def steps(self, k0, k1, pipelined):
-        """Steps k0 .. k1-1 on the context's stream (current stream = main)."""
+    def steps(self, k0, k1, pipelined, forces=None):
+        """Steps k0 .. k1-1 on the context's stream (current stream = main);
+        with `forces` (a list), the interfacial forces of each step are taken
+        between the step and the next prepared geometry and appended."""
         for k in range(k0, k1):
             a, b = self.bufs[k % 2], self.bufs[(k + 1) % 2]
             # with pipelined, the geometry of step k > k0 was prepared on the
             # auxiliary stream during step k-1
             self.s.step(a[0], a[1], b[0], b[1], u=self.u, vof_next=self.vofs[k],
                         sigma_out=self.sig, totals=self.hist[k])
+            if forces is not None:
+                cap, ma = self.s.interface_force(self.vofs[k], self.sig)
+                forces.append(cap + ma)
             if pipelined and k + 1 < k1:
                 self.s.prepare_geometry(self.vofs[k + 1], self.aux)
 
@@ -104,6 +109,32 @@ def test_pipelined_equals_plain(prec):
         pipe.steps(0, K, pipelined=True)
     assert_same(pipe.result(K), ref)
     assert pipe.s.status() == plain.s.status() == 0
+
+
+@pytest.mark.parametrize("prec", [F32, F64])
+def test_interface_forces_between_pipelined_steps(prec):
+    # the force kernel reads the current level set while the next step's
+    # geometry is prepared into the other buffer: forces and fields equal
+    # those of the unpipelined run bit for bit
+    import torch
+    case = circle_case((150, 131), prec)
+    K = 12
+    runs = []
+    for pipelined in (False, True):
+        r = Runner(case, prec)
+        r.reset()
+        f = []
+        with torch.cuda.stream(r.main):
+            r.steps(0, K, pipelined=pipelined, forces=f)
+        runs.append((r.result(K), [[to_np(x) for x in fk] for fk in f], r.s.status()))
+    (ref, fref, st0), (got, fgot, st1) = runs
+    assert_same(got, ref)
+    assert st0 == st1 == 0
+    assert len(fgot) == len(fref) == K
+    for k in range(K):
+        for x, y in zip(fgot[k], fref[k]):
+            assert np.array_equal(x, y), k
+    assert max(np.max(np.abs(x)) for x in fref[-1]) > 0
 
 
 def test_pipelined_equals_plain_full_size():
