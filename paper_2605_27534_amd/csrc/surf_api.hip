@@ -1693,7 +1693,9 @@ int surf_prepare_geometry(surf_ctx* c, const void* vof_next, void* aux_stream) {
 }
 
 int surf_force(surf_ctx* c, const void* sigma, void* const* force) {
-  touch_levelset(c);
+  // in 2D the force kernel reads only the current level set, which a geometry
+  // prepared next leaves alone; in 3D that geometry rewrites both buffers
+  if (c && (c->grid.dim == 3 || !c->materialized)) touch_levelset(c);
   if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !sigma || !force) return SURF_EINVAL;
   for (int d = 0; d < c->grid.dim; ++d)

@@ -76,7 +76,7 @@ class Runner:
                         sigma_out=self.sig, totals=self.hist[k])
             if forces is not None:
                 cap, ma = self.s.interface_force(self.vofs[k], self.sig)
-                forces.append(cap + ma)
+                forces.append(cap + ma + self.s.force(self.sig))
             if pipelined and k + 1 < k1:
                 self.s.prepare_geometry(self.vofs[k + 1], self.aux)
 
@@ -113,9 +113,10 @@ def test_pipelined_equals_plain(prec):
 
 @pytest.mark.parametrize("prec", [F32, F64])
 def test_interface_forces_between_pipelined_steps(prec):
-    # the force kernel reads the current level set while the next step's
-    # geometry is prepared into the other buffer: forces and fields equal
-    # those of the unpipelined run bit for bit
+    # the force kernels (interfacial, and the Marangoni force from the level
+    # set) read the current level set while the next step's geometry is
+    # prepared into the other buffer: forces and fields equal those of the
+    # unpipelined run bit for bit
     import torch
     case = circle_case((150, 131), prec)
     K = 12
