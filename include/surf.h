@@ -258,7 +258,9 @@ int surf_step(surf_ctx* ctx, const void* vof_next, const void* const* u,
  * stream has consumed the level-set buffer it overwrites (in 3D, where the
  * sweeps rewrite both level-set buffers, a pipelined step's transport reads
  * a copy of the level set taken at its start; level-set reads and writes
- * enqueued after that step make the geometry wait for them); the next
+ * enqueued after that step make the geometry wait for them; in 2D only the
+ * calls that write the level set do, while surf_force and
+ * surf_interface_force, which read the current buffer, run beside it); the next
  * surf_step, which must receive the same vof_next pointer, then runs only
  * the transport, on the context's stream, after the prepared geometry.  Typical order:
  * surf_step(vof_1); then for n >= 1: surf_prepare_geometry(vof_{n+1}),
