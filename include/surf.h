@@ -63,7 +63,12 @@ extern "C" {
 #define SURF_STATUS_GEOMETRY 8u  /* the VoF changed under a tile whose whole
                                   * neighbourhood was outside the band: the
                                   * interface moved farther than the clamp
-                                  * distance in one step (level set stale)   */
+                                  * distance in one step (level set stale).
+                                  * A geometry prepared on a second stream
+                                  * (surf_prepare_geometry) raises it when it
+                                  * runs, so under pipelining it can show in
+                                  * the status of the step before the one
+                                  * that consumes that geometry             */
 #define SURF_STATUS_SOLVE 16u    /* implicit substep 2: a linear solve ended at
                                   * cg_max_iters without meeting its test, or
                                   * broke down (matrix not positive definite) */
@@ -291,9 +296,11 @@ int surf_prepare_geometry(surf_ctx* ctx, const void* vof_next, void* aux_stream)
  * Errors: SURF_EINVAL for a context without ACDI, a 3D grid, the paper flux
  * form or the implicit substep, a null aux_stream or u[1] missing;
  * SURF_ESTATE without a level set or with a prepare still pending.  While
- * one is pending only surf_step (as above), surf_set_dt and the status calls
- * are accepted; the level-set, phase, state, force, timing and adjoint calls
- * return SURF_ESTATE. */
+ * one is pending only surf_step (as above), surf_set_dt with the dt the
+ * prepared step took (any other dt returns SURF_ESTATE: the phase field has
+ * already advanced with it) and the status calls are accepted; the
+ * level-set, phase, state, force, timing and adjoint calls return
+ * SURF_ESTATE. */
 int surf_prepare_phase(surf_ctx* ctx, const void* const* u, void* aux_stream);
 
 /* Measurement aid: runs only the transport kernel of surf_step (weighted
@@ -362,7 +369,10 @@ int surf_force(surf_ctx* ctx, const void* sigma, void* const* force);
 int surf_interface_force(surf_ctx* ctx, const void* vof, const void* sigma, void* const* f_cap,
                          void* const* f_ma);
 
-/* Changes the time step used by the following steps. */
+/* Changes the time step used by the following steps.  SURF_EINVAL for a dt
+ * that is not positive and finite; SURF_ESTATE for a different dt while an
+ * ACDI step is prepared (surf_prepare_phase), which has already used the
+ * current one. */
 int surf_set_dt(surf_ctx* ctx, double dt);
 
 /* Reads (synchronously: waits for the stream) and clears the status word. */

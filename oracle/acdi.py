@@ -157,6 +157,11 @@ def run(prob, chi, u, F, psi, dt, nsteps, zeta, vof_seq=None, hj_iters=8, totals
     ACDI.  Returns (chi, phi, F, psi, sigma, totals history)."""
     from . import implicit as I
     tot = np.zeros(16) if totals is None else totals
+    # the regularization step is explicit: a diffusion of coefficient
+    # zeta eps and a transport at speed up to zeta, whose explicit bound
+    # (2 dim zeta eps/h^2 + zeta sqrt(dim)/h) joins the next stable step
+    q = O.full(prob)
+    lam = zeta * (2.0 * q["dim"] * q["eps"] / q["h"] ** 2 + math.sqrt(q["dim"]) / q["h"])
     phi = phi_of_chi(prob, chi)
     hist = []
     S = None
@@ -172,6 +177,7 @@ def run(prob, chi, u, F, psi, dt, nsteps, zeta, vof_seq=None, hj_iters=8, totals
             F, psi, S, tot = I.implicit_step(prob, chi, u, F, psi, dt, picard=picard, totals=tot)
         else:
             F, psi, S, tot = O.step(prob, chi, u, F, psi, dt, tot)
+        tot[O.T_DTNEXT] = min(tot[O.T_DTNEXT], q["cfl_diff"] / lam)
         hist.append(tot.copy())
     return chi, phi, F, psi, S, np.array(hist)
 

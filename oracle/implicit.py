@@ -132,7 +132,15 @@ def implicit_step(prob, chi, u, F, psi, dt, picard=3, totals=None):
             hi = [slice(None)] * 3
             lo[ax] = slice(0, q["n"][d])
             hi[ax] = slice(1, q["n"][d] + 1)
-            s += np.abs(0.5 * (ud[tuple(lo)] + ud[tuple(hi)]))
+            uh = ud[tuple(hi)].copy()
+            if q["bc"][d][1] == O.BC_PERIODIC:
+                # face n_d of a periodic axis is face 0
+                last = [slice(None)] * 3
+                last[ax] = slice(q["n"][d] - 1, q["n"][d])
+                first = [slice(None)] * 3
+                first[ax] = slice(0, 1)
+                uh[tuple(last)] = ud[tuple(first)]
+            s += np.abs(0.5 * (ud[tuple(lo)] + uh))
         su = float(s.max())
     out = outF + outP
     outcum = tot[O.T_OUTCUM] + out

@@ -7,6 +7,9 @@
  * the benchmark do.  It shares no source, header, table or helper with the
  * HIP library; it is written from the paper's equations, one stage at a
  * time, in the paper's order, with full temporary arrays and no fusion.
+ * Loops whose cells or faces are independent run over OpenMP threads; every
+ * sum (the outflow budget, the divergences, the totals) keeps one serial
+ * order, so the results do not depend on the thread count.
  *
  * Notation (paper -> names used here):
  *   VoF fraction of fluid 1 (bubble)        c   -> vof
@@ -142,10 +145,12 @@ static long face(const Prob* p, int d, int i, int j, int k) {
 static void pin_data(const Prob* p, const double* vof, double* chi0,
                      signed char* sgn, unsigned char* pinned, double* D) {
   long N = p->ncell;
+  #pragma omp parallel for schedule(static)
   for (long c = 0; c < N; ++c) {
     chi0[c] = (vof[c] - 0.5) * p->h;
     sgn[c] = chi0[c] > 0 ? 1 : (chi0[c] < 0 ? -1 : 0);
   }
+  #pragma omp parallel for collapse(2) schedule(static)
   for (int k = 0; k < p->n[2]; ++k)
     for (int j = 0; j < p->n[1]; ++j)
       for (int i = 0; i < p->n[0]; ++i) {
@@ -176,6 +181,7 @@ static void hj_sweep(const Prob* p, const signed char* sgn,
                      const unsigned char* pinned, const double* D,
                      const double* src, double* dst) {
   double h = p->h, dtau = p->h / p->dim;
+  #pragma omp parallel for collapse(2) schedule(static)
   for (int k = 0; k < p->n[2]; ++k)
     for (int j = 0; j < p->n[1]; ++j)
       for (int i = 0; i < p->n[0]; ++i) {
@@ -220,10 +226,16 @@ int or_geometry(const int* ip, const double* dp, const double* vof, double* chi,
   if (!chi0 || !D || !tmp || !sgn || !pin) return -2;
   pin_data(&p, vof, chi0, sgn, pin, D);
   if (!warm) memcpy(chi, chi0, N * sizeof(double));
+  /* Jacobi sweeps between two buffers; the last one's result ends in chi */
+  double* src = chi;
+  double* dst = tmp;
   for (int it = 0; it < iters; ++it) {
-    hj_sweep(&p, sgn, pin, D, chi, tmp);
-    memcpy(chi, tmp, N * sizeof(double));
+    hj_sweep(&p, sgn, pin, D, src, dst);
+    double* t = src;
+    src = dst;
+    dst = t;
   }
+  if (src != chi) memcpy(chi, src, N * sizeof(double));
   free(chi0); free(D); free(tmp); free(sgn); free(pin);
   return 0;
 }
@@ -248,6 +260,7 @@ int or_pin_data(const int* ip, const double* dp, const double* vof,
 int or_cell_geometry(const int* ip, const double* dp, const double* chi,
                      double* phi, double* omega, double* delta) {
   Prob p = unpack(ip, dp);
+  #pragma omp parallel for schedule(static)
   for (long c = 0; c < p.ncell; ++c) {
     double ph = 1.0 / (1.0 + exp(chi[c] / p.eps));
     double om = 1.0 / (1.0 + exp(-chi[c] / p.eps));
@@ -286,6 +299,7 @@ int or_init_state(const int* ip, const double* dp, const double* chi,
   double* del = malloc(p.ncell * sizeof(double));
   if (!phi || !del) return -2;
   or_cell_geometry(ip, dp, chi, phi, NULL, del);
+  #pragma omp parallel for schedule(static)
   for (long c = 0; c < p.ncell; ++c) {
     F[c] = (c0 ? c0[c] : c0_const) * phi[c];
     psi[c] = gamma0 * del[c];
@@ -339,6 +353,7 @@ static void advect_faces(const Prob* p, int d, const double* const* uall, const 
   int m[3] = {p->n[0], p->n[1], p->n[2]};
   m[d] += 1;
   double h = p->h;
+  #pragma omp parallel for collapse(2) schedule(static)
   for (int k = 0; k < m[2]; ++k)
     for (int j = 0; j < m[1]; ++j)
       for (int i = 0; i < m[0]; ++i) {
@@ -354,9 +369,7 @@ static void advect_faces(const Prob* p, int d, const double* const* uall, const 
           /* open: the interior cell's value, either flow direction */
           int ci[3] = {i, j, k};
           ci[d] = hi_bnd ? nd - 1 : 0;
-          double v = u[fi] * xi[cell(p, ci[0], ci[1], ci[2])];
-          flux[fi] = v;
-          out[0] += dt * face_area(p, d, i) * (hi_bnd ? v : -v);
+          flux[fi] = u[fi] * xi[cell(p, ci[0], ci[1], ci[2])];
           continue;
         }
         /* interior (or periodic face 0): left cell L, right cell R */
@@ -388,6 +401,16 @@ static void advect_faces(const Prob* p, int d, const double* const* uall, const 
         (void)L;
         flux[fi] = uf * xf;
       }
+  /* what leaves through open faces, summed in face order */
+  for (int k = 0; k < m[2]; ++k)
+    for (int j = 0; j < m[1]; ++j)
+      for (int i = 0; i < m[0]; ++i) {
+        int c[3] = {i, j, k};
+        int hi_bnd = c[d] == p->n[d];
+        if ((c[d] != 0 && !hi_bnd) || p->bc[d][hi_bnd] != BC_OPEN) continue;
+        double v = flux[face(p, d, i, j, k)];
+        out[0] += dt * face_area(p, d, i) * (hi_bnd ? v : -v);
+      }
   /* periodic: the last face is the first face */
   if (p->bc[d][0] == BC_PERIODIC)
     for (int k = 0; k < m[2]; ++k)
@@ -416,6 +439,7 @@ int or_advect(const int* ip, const double* dp, const double* ux, const double* u
     if (!fl[d]) return -2;
     advect_faces(&p, d, u, xi, dt, fl[d], &out);
   }
+  #pragma omp parallel for collapse(2) schedule(static)
   for (int k = 0; k < p.n[2]; ++k)
     for (int j = 0; j < p.n[1]; ++j)
       for (int i = 0; i < p.n[0]; ++i) {
@@ -455,6 +479,7 @@ static void substep2_faces(const Prob* p, int d, int is_bulk, const double* xs,
   m[d] += 1;
   double h = p->h, D = is_bulk ? p->Db : p->Ds;
   (void)omega;
+  #pragma omp parallel for collapse(2) schedule(static)
   for (int k = 0; k < m[2]; ++k)
     for (int j = 0; j < m[1]; ++j)
       for (int i = 0; i < m[0]; ++i) {
@@ -494,6 +519,7 @@ static void substep2_faces(const Prob* p, int d, int is_bulk, const double* xs,
 static void paper_B(const Prob* p, int d, int is_bulk, const double* chi,
                     const double* phi, const double* omega, double* B) {
   double D = is_bulk ? p->Db : p->Ds;
+  #pragma omp parallel for collapse(2) schedule(static)
   for (int k = 0; k < p->n[2]; ++k)
     for (int j = 0; j < p->n[1]; ++j)
       for (int i = 0; i < p->n[0]; ++i) {
@@ -567,6 +593,7 @@ int or_step(const int* ip, const double* dp, const double* chi,
       if (p.form == FORM_PAPER) paper_B(&p, d, is_bulk, chi, phi, om, B);
       substep2_faces(&p, d, is_bulk, is_bulk ? Fs : Ps, phi, om, del, B, fl);
       double* div = is_bulk ? divF : divP;
+      #pragma omp parallel for collapse(2) schedule(static)
       for (int k = 0; k < p.n[2]; ++k)
         for (int j = 0; j < p.n[1]; ++j)
           for (int i = 0; i < p.n[0]; ++i) {
@@ -587,6 +614,7 @@ int or_step(const int* ip, const double* dp, const double* chi,
    * written with psi = Gamma delta as k_a c (Gamma_inf delta - psi) - k_d psi;
    * the Henry (constant adsorption flux) law of section 4.3.1 drops the
    * saturation factor: k_a c Gamma_inf delta - k_d psi. */
+  #pragma omp parallel for schedule(static)
   for (long c = 0; c < N; ++c) {
     if (!p.bulk) { q[c] = 0.0; continue; }
     double cs = Fs[c] / (phi[c] + p.eta);
@@ -597,6 +625,7 @@ int or_step(const int* ip, const double* dp, const double* chi,
   }
 
   /* update and equation of state */
+  #pragma omp parallel for schedule(static)
   for (long c = 0; c < N; ++c) {
     Fout[c] = p.bulk ? Fs[c] + dt * (divF[c] - q[c]) : F[c];
     psiout[c] = Ps[c] + dt * (divP[c] + q[c]);
@@ -608,8 +637,11 @@ int or_step(const int* ip, const double* dp, const double* chi,
   if (totals) {
     Kahan mb = {0, 0}, ms = {0, 0}, sd = {0, 0}, ssd = {0, 0};
     double minF = INFINITY, minP = INFINITY, cmax = -INFINITY, nbad = 0, su = 0.0;
+    double* colvol = malloc(p.n[0] * sizeof(double)); /* cell volume by column */
+    if (!colvol) return -2;
+    for (int i = 0; i < p.n[0]; ++i) colvol[i] = cell_volume(&p, i);
     for (long c = 0; c < N; ++c) {
-      double vol = cell_volume(&p, (int)(c % p.n[0]));
+      double vol = colvol[c % p.n[0]];
       double sg = sigma ? sigma[c] : eos(&p, psiout[c] / (del[c] + p.eta / p.eps));
       kadd(&mb, Fout[c] * vol);
       kadd(&ms, psiout[c] * vol);
@@ -621,8 +653,10 @@ int or_step(const int* ip, const double* dp, const double* chi,
       if (cc > cmax) cmax = cc;
       if (!isfinite(Fout[c]) || !isfinite(psiout[c]) || !isfinite(sg)) nbad += 1;
     }
+    free(colvol);
     if (ux) {
       const double* u[3] = {ux, uy, uz};
+      #pragma omp parallel for collapse(2) schedule(static) reduction(max : su)
       for (int k = 0; k < p.n[2]; ++k)
         for (int j = 0; j < p.n[1]; ++j)
           for (int i = 0; i < p.n[0]; ++i) {
@@ -631,6 +665,7 @@ int or_step(const int* ip, const double* dp, const double* chi,
               int a[3] = {i, j, k};
               double um = u[d][face(&p, d, a[0], a[1], a[2])];
               a[d] += 1;
+              if (p.bc[d][1] == BC_PERIODIC && a[d] == p.n[d]) a[d] = 0; /* face n_d is face 0 */
               double up = u[d][face(&p, d, a[0], a[1], a[2])];
               /* axisymmetric: the radial mean weights each face by r_face/r_i */
               double wm, wp;
@@ -706,6 +741,7 @@ int or_force(const int* ip, const double* dp, const double* chi,
   for (int d = 0; d < p.dim; ++d) {
     int m[3] = {p.n[0], p.n[1], p.n[2]};
     m[d] += 1;
+    #pragma omp parallel for collapse(2) schedule(static)
     for (int k = 0; k < m[2]; ++k)
       for (int j = 0; j < m[1]; ++j)
         for (int i = 0; i < m[0]; ++i) {
@@ -952,6 +988,7 @@ int or_loss_grad(const int* ip, const double* dp, const double* chi, const doubl
   double* del = malloc(p.ncell * sizeof(double));
   if (!del) return -2;
   or_cell_geometry(ip, dp, chi, NULL, NULL, del);
+  #pragma omp parallel for schedule(static)
   for (long c = 0; c < p.ncell; ++c) {
     double e = del[c] + p.eta / p.eps;
     gP[c] = w * eos_prime(&p, psi[c] / e) * del[c] / e;

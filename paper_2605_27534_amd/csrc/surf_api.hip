@@ -1725,6 +1725,8 @@ int surf_interface_force(surf_ctx* c, const void* vof, const void* sigma, void* 
 
 int surf_set_dt(surf_ctx* c, double dt) {
   if (!c || !(dt > 0) || !std::isfinite(dt)) return SURF_EINVAL;
+  // a prepared ACDI step has advanced the phase field with the current dt
+  if (c->prepared_phase && dt != c->dt) return SURF_ESTATE;
   c->dt = dt;
   return SURF_OK;
 }

@@ -466,10 +466,9 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
           acc.mnP = fmin(acc.mnP, Pn);
           acc.nbad += isfinite(Pn + sg + Fn) ? 0 : 1;
           if (HU) {
-            // cell-mean velocities (the literal upper face of a periodic axis)
+            // cell-mean velocities (on a periodic axis the upper face of the
+            // last cell is face 0, as in the fluxes)
             R uxh = pUx, uyl = rUy[i - 5], uyh = rUy[i - 4];
-            if (!IX && px && xs == nx - 1) uxh = a.u[0][(long long)(nx + 1) * o + nx];
-            if (!IY && py && o == ny - 1) uyh = a.u[1][(long long)nx * ny + xs];
             if constexpr (AXI)
               acc.usum = fmax(acc.usum, fabs(R(0.5) * (a_lo * pUxL + a_hi * uxh)) +
                                             fabs(R(0.5) * (uyl + uyh)));

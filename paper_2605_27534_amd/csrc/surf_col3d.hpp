@@ -346,14 +346,10 @@ __device__ __forceinline__ void col3d_wg(const Col3Args<R>& a, Col3Lds<R>& L, co
       if (!pz && (s == 0 || s == nz)) { wzF = R(0); wzP = R(0); }
       const R uxL = from_left(ux);  // every lane takes part in the shift
       if (HU && out_lane && out_row && s >= z0 && s < z0 + TZ && s < nz) {
-        // cell-mean velocities of the output cells of plane s (the literal
-        // upper face of a periodic axis) and the open-side budget of their faces
+        // cell-mean velocities of the output cells of plane s (on a periodic
+        // axis the upper face of the last cell is face 0, as in the fluxes)
+        // and the open-side budget of their faces
         R uxh = ux, uyh = rUyh[k1], uzl = rUz[i - 4], uzh = rUz[i - 3];
-        if (!IX && px && xs == nx - 1)
-          uxh = a.u[0][(long long)(nx + 1) * (ny * (long long)s + ys) + nx];
-        if (!IY && py && ys == ny - 1)
-          uyh = a.u[1][(long long)nx * ((ny + 1) * (long long)s + ny) + xs];
-        if (pz && s == nz - 1) uzh = a.u[2][(long long)nx * ny * nz + (long long)nx * ys + xs];
         acc.usum = fmax(acc.usum, fabs(R(0.5) * (uxL + uxh)) + fabs(R(0.5) * (rUyl[k1] + uyh)) +
                                       fabs(R(0.5) * (uzl + uzh)));
         if constexpr (!IX) {

@@ -211,12 +211,14 @@ __global__ void __launch_bounds__(IMP_BLOCK) k_imp_adv(ImpArgs<R> a, const R* __
         }
         st[f] = xi[c] - cfl * div;
       }
-      // cell-mean velocity sum (the literal upper face on a periodic axis)
+      // cell-mean velocity sum (on a periodic axis the upper face of the
+      // last cell is face 0, as in the fluxes)
       R s = R(0);
       for (int d = 0; d < g.dim; ++d) {
         int y[3] = {x[0], x[1], x[2]};
         const R ulo = u[d][face_index(g, d, y[0], y[1], y[2])];
         y[d] += 1;
+        if (y[d] == g.n[d] && g.bc[d][1] == BC_PERIODIC) y[d] = 0;
         const R uhi = u[d][face_index(g, d, y[0], y[1], y[2])];
         s += fabs(R(0.5) * (ulo + uhi));
       }

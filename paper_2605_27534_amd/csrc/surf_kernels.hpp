@@ -321,7 +321,8 @@ __global__ void __launch_bounds__(BLOCK) k_step(StepArgs<R> a) {
           }
           if (interior) {
             int fl[3] = {m[0], m[1], m[2]};
-            fl[d] = m[d] + 1;  // literal upper face for the cell-mean velocity
+            fl[d] = m[d] + 1;  // upper face for the cell-mean velocity: face 0
+            if (fl[d] == g.n[d] && g.bc[d][1] == BC_PERIODIC) fl[d] = 0;  // on a periodic axis
             R uup = a.u[d][face_index(g, d, fl[0], fl[1], fl[2])];
             usum += fabs((double)(R(0.5) * (ulo + uup)));
           }

@@ -587,11 +587,9 @@ __device__ __forceinline__ void step2d_tile(const Step2dArgs<R>& a, const int t)
         Fs = Fs - cfl * dF;
         Ps = Ps - cfl * dP;
         if (lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && gx < nx && gy < ny) {
-          // cell-mean velocity magnitudes (the literal upper face of a
-          // periodic axis)
+          // cell-mean velocity magnitudes (on a periodic axis the upper
+          // face of the last cell is face 0, as in the fluxes)
           R uxl = sUx[xl], uxh = sUx[xl + 1], uyl = sUy[yl], uyh = sUy[yl + EX1];
-          if (px && gx == nx - 1) uxh = a.u[0][(long long)nx + (long long)(nx + 1) * gy];
-          if (py && gy == ny - 1) uyh = a.u[1][(long long)gx + (long long)nx * ny];
           double us = fabs((double)(R(0.5) * (uxl + uxh))) + fabs((double)(R(0.5) * (uyl + uyh)));
           acc[P_MAX_USUM] = fmax(acc[P_MAX_USUM], us);
         }

@@ -69,3 +69,26 @@ def run_gpu(prob, vof0, nsteps, dt, precision, u=None, u_seq=None, vof_seq=None,
     out = (chi_out, None if F is None else to_np(F), to_np(P), to_np(sig),
            hist.cpu().numpy()[:nsteps], s)
     return out
+
+
+def compare_totals(tg, to, tt, F_o, P_o):
+    """Every slot of one step's totals against the oracle's: the sums, the
+    interface averages, the stable step and the largest cell-mean speed
+    relative to themselves; the open-side budget relative to the total
+    surfactant; the minima relative to their field's max-norm (a minimum
+    near zero has no relative size of its own); the count of non-finite
+    values exactly."""
+    for slot in (O.T_MB, O.T_MS, O.T_SDELTA, O.T_SSIGD, O.T_MTOT, O.T_GAVG, O.T_SAVG,
+                 O.T_SU, O.T_DTNEXT, O.T_CMAX):
+        a, b = tg[slot], to[slot]
+        assert abs(a - b) <= tt * max(abs(b), 1e-300), (slot, a, b)
+    scale = abs(to[O.T_MB]) + abs(to[O.T_MS])
+    for slot in (O.T_OUT, O.T_OUTCUM):
+        assert abs(tg[slot] - to[slot]) <= tt * scale, (slot, tg[slot], to[slot])
+    if F_o is not None:
+        Fs = np.max(np.abs(F_o))
+        assert abs(tg[O.T_MINF] - to[O.T_MINF]) <= tt * Fs, (tg[O.T_MINF], to[O.T_MINF])
+    Ps = np.max(np.abs(P_o))
+    assert abs(tg[O.T_MINPSI] - to[O.T_MINPSI]) <= tt * Ps, (tg[O.T_MINPSI], to[O.T_MINPSI])
+    assert tg[O.T_NBAD] == to[O.T_NBAD]
+    assert abs(tg[O.T_T] - to[O.T_T]) <= 1e-14 * abs(to[O.T_T])
