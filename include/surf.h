@@ -369,6 +369,40 @@ int surf_force(surf_ctx* ctx, const void* sigma, void* const* force);
 int surf_interface_force(surf_ctx* ctx, const void* vof, const void* sigma, void* const* f_cap,
                          void* const* f_ma);
 
+/* Allocation-free step, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): one surf_step of the weighted flux form with explicit substep
+ * 2 on a given level set, with no context and no workspace.  The running
+ * state and the per-workgroup records of the reduction live in a
+ * file-scope device array of the library (NSTATE + 4096 x 10 doubles,
+ * 320 KiB, held on every device the library runs on until the process
+ * ends); the call allocates nothing, host or device.
+ *   grid, params  as for surf_init (flux_form SURF_FLUX_WEIGHTED, substep2
+ *                 SURF_SUBSTEP2_EXPLICIT, interface SURF_IFACE_VOF);
+ *                 params->dt is ignored, dt is the step;
+ *   chi           the level set of the interface at t^{n+1} (cell layout,
+ *                 context precision), e.g. from surf_get_levelset;
+ *   u, F_in, psi_in, F_out, psi_out, sigma_out  as for surf_step;
+ *   totals_dev    16 doubles (device) or NULL: read first for the running
+ *                 time (slot SURF_T_TIME) and the cumulative outflow (slot
+ *                 SURF_T_OUTFLOW_CUM) of the previous step, then rewritten with
+ *                 this step's totals; NULL starts from time 0 and writes
+ *                 nothing;
+ *   hip_stream    the stream every launch is enqueued on.
+ * Results equal those of surf_step on a context holding the same level set
+ * (the same kernels).  The status word is not kept: the totals carry the
+ * non-finite count, the minima and the stable step.  Every call on a device
+ * shares that device's array, so calls that overlap on one device race.
+ * Errors: SURF_EINVAL as for surf_init and surf_step, or another flux form,
+ * substep or interface; SURF_ENOMEM for a grid of more than 4096 transport
+ * workgroups (2D: ceil(nx/58) ceil(ceil(ny/8)/4); 3D: ceil(nx/58)
+ * ceil(ny/14) ceil(nz/16) in FP32, ceil(nz/8) in FP64); SURF_EDEVICE for a
+ * HIP error. */
+int surf_step_static(const surf_grid* grid, const surf_params* params, double dt,
+                     const void* chi, const void* const* u, const void* F_in,
+                     const void* psi_in, void* F_out, void* psi_out, void* sigma_out,
+                     double* totals_dev, void* hip_stream);
+
 /* Changes the time step used by the following steps.  SURF_EINVAL for a dt
  * that is not positive and finite; SURF_ESTATE for a different dt while an
  * ACDI step is prepared (surf_prepare_phase), which has already used the

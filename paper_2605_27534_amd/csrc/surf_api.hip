@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -2228,6 +2229,118 @@ int surf_destroy(surf_ctx* c) {
   }
   delete c;
   return SURF_OK;
+}
+
+// ------------------------------------------------------------------
+// Allocation-free step: the running state and the per-workgroup records of
+// the reduction in a file-scope device array instead of a workspace.
+// ------------------------------------------------------------------
+
+}  // extern "C"
+
+namespace {
+
+// at most this many transport workgroups (2D: 58-column strips of 32-row
+// groups, about 1.9 M cells per 1000; 3D: 58 x 14 x 16 blocks, about
+// 13 M cells per 1000)
+constexpr int STATIC_MAX_WG = 4096;
+constexpr long long STATIC_DOUBLES = NSTATE + (long long)STATIC_MAX_WG * NPART;
+__device__ __align__(256) double scratch[STATIC_DOUBLES];
+
+constexpr int STATIC_MAX_DEVICES = 64;
+double* scratch_dev[STATIC_MAX_DEVICES] = {};
+std::mutex scratch_mu;
+
+// The device address of `scratch` on the current device, looked up once per
+// device (each device holds its own copy of the array).
+int static_scratch(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= STATIC_MAX_DEVICES)
+    return SURF_EDEVICE;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SURF_EDEVICE;
+    scratch_dev[dev] = (double*)p;
+  }
+  *out = scratch_dev[dev];
+  return SURF_OK;
+}
+
+// The running state of one call: time and cumulative outflow from the
+// caller's totals (zero without them), status and flags cleared.
+__global__ void k_static_state(double* __restrict__ state, const double* __restrict__ totals) {
+  if (threadIdx.x >= NSTATE) return;
+  double v = 0.0;
+  if (totals && threadIdx.x == S_TIME) v = totals[11];
+  if (totals && threadIdx.x == S_OUTCUM) v = totals[3];
+  state[threadIdx.x] = v;
+}
+
+}  // namespace
+
+extern "C" {
+
+int surf_step_static(const surf_grid* grid, const surf_params* params, double dt,
+                     const void* chi, const void* const* u, const void* F_in,
+                     const void* psi_in, void* F_out, void* psi_out, void* sigma_out,
+                     double* totals_dev, void* hip_stream) {
+  int rc = check_grid_params(grid, params);
+  if (rc) return rc;
+  if (!(dt > 0) || !std::isfinite(dt) || !chi || !psi_in || !psi_out) return SURF_EINVAL;
+  if (params->flux_form != SURF_FLUX_WEIGHTED || params->substep2 != SURF_SUBSTEP2_EXPLICIT ||
+      params->interface != SURF_IFACE_VOF)
+    return SURF_EINVAL;
+  const bool bulk = params->bulk_enabled != 0;
+  if (bulk && (!F_in || !F_out)) return SURF_EINVAL;
+  if (psi_in == psi_out || (bulk && (F_in == F_out || F_in == psi_out || psi_in == F_out)))
+    return SURF_EINVAL;
+  if (u && u[0])
+    for (int d = 0; d < grid->dim; ++d)
+      if (!u[d]) return SURF_EINVAL;
+  const size_t es = esize(params);
+  if (!aligned(chi, es) || !aligned(psi_in, es) || !aligned(psi_out, es)) return SURF_EINVAL;
+  surf_ctx c;  // host-side description only: nothing here allocates
+  c.grid = *grid;
+  c.prm = with_defaults(params, grid->dim);
+  c.g.dim = grid->dim;
+  for (int d = 0; d < 3; ++d) {
+    c.g.n[d] = grid->n[d];
+    c.g.bc[d][0] = d < grid->dim ? grid->bc[d][0] : 0;
+    c.g.bc[d][1] = d < grid->dim ? grid->bc[d][1] : 0;
+  }
+  c.stream = (hipStream_t)hip_stream;
+  c.ncell = (long long)grid->n[0] * grid->n[1] * grid->n[2];
+  c.col_nwg = col_shape(grid, params, &c.col_strips, &c.col_groups);
+  c.c3_nwg = col3_shape(grid, params, c.c3);
+  const int nwg = grid->dim == 2 ? c.col_nwg : c.c3_nwg;
+  if (nwg == 0) return SURF_EINVAL;  // beyond the 32-bit offsets of the transport kernels
+  if (nwg > STATIC_MAX_WG) return SURF_ENOMEM;
+  double* base = nullptr;
+  rc = static_scratch(&base);
+  if (rc) return rc;
+  c.state = base;
+  c.part = base + NSTATE;
+  c.chi[0] = const_cast<void*>(chi);
+  c.chi[1] = nullptr;
+  c.chi_cur = 0;
+  c.has_chi = true;
+  c.materialized = true;
+  c.dt = dt;
+  c.profile = false;
+  hipLaunchKernelGGL(k_static_state, dim3(1), dim3(64), 0, c.stream, c.state,
+                     (const double*)totals_dev);
+  const bool f32 = params->precision == SURF_F32;
+  if (grid->dim == 2) {
+    if (f32) col2d_transport<float>(&c, u, F_in, psi_in, F_out, psi_out, sigma_out);
+    else col2d_transport<double>(&c, u, F_in, psi_in, F_out, psi_out, sigma_out);
+  } else {
+    if (f32) col3d_transport<float>(&c, u, F_in, psi_in, F_out, psi_out, sigma_out);
+    else col3d_transport<double>(&c, u, F_in, psi_in, F_out, psi_out, sigma_out);
+  }
+  if (f32) finalize<float>(&c, totals_dev, nwg);
+  else finalize<double>(&c, totals_dev, nwg);
+  return status_of_launch();
 }
 
 }  // extern "C"

@@ -42,7 +42,7 @@ EXPORTS = [
     "surf_adjoint_seed", "surf_adjoint_step", "surf_adjoint_c0",
     "surf_batch_workspace_bytes", "surf_batch_create", "surf_batch_set_geometry",
     "surf_batch_init_state", "surf_batch_step", "surf_batch_parity", "surf_batch_tune",
-    "surf_batch_destroy",
+    "surf_batch_destroy", "surf_step_static",
 ]
 
 
@@ -122,6 +122,8 @@ def lib():
         L.surf_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.surf_adjoint_c0.argtypes = [vp, vp, vp]
         L.surf_profile_read.argtypes = [vp, vp, vp, vp, vp]
+        L.surf_step_static.argtypes = [vp, vp, ctypes.c_double, vp, vp, vp, vp, vp, vp, vp, vp,
+                                       vp]
         _lib = L
     return _lib
 
@@ -429,3 +431,23 @@ class Surf:
             F, F2 = F2, F
             psi, P2 = P2, psi
         return F, psi, S
+
+
+def step_static(prob: dict, dt: float, precision: int, chi, F_in, psi_in, F_out, psi_out,
+                u=None, sigma_out=None, totals=None, stream=None):
+    """surf_step_static: one step with no context and no workspace (the
+    library's file-scope device array holds the reduction records).  Tensors
+    are device buffers of the problem's precision; totals (16 float64) is
+    read for the running time and outflow and rewritten.  Returns the
+    library's return code (0 on success)."""
+    L = lib()
+    g, p, _ = make_structs(prob, dt, precision)
+    ua = None
+    if u is not None:
+        arr = (ctypes.c_void_p * 3)(*([ctypes.c_void_p(x.data_ptr()) for x in u] +
+                                      [None] * (3 - len(u))))
+        ua = ctypes.cast(arr, ctypes.c_void_p)
+    st = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+    return int(L.surf_step_static(ctypes.byref(g), ctypes.byref(p), float(dt), _ptr(chi), ua,
+                                  _ptr(F_in), _ptr(psi_in), _ptr(F_out), _ptr(psi_out),
+                                  _ptr(sigma_out), _ptr(totals), ctypes.c_void_p(st)))
