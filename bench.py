@@ -395,7 +395,7 @@ def main():
             "frac": round(fb * ncell / (force_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(cfg["name"], IFACE_TRAFFIC)}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baselines(cpu_baseline, cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
@@ -461,6 +461,8 @@ def bench_batch(args):
         side.synchronize()
         ms_plain = t0.elapsed_time(t1)
     value = cells * K / (ms_batch * 1e-3) / 1e9
+    kern_us = times[choice] if 0 <= choice < len(times) else None
+    bpc = 24  # FP32, no flow: reads chi, F, psi; writes F, psi, sigma
     out = {"metric": "surfactant-step Gcell-updates/s (batched form)", "value": round(value, 4),
            "unit": "Gcell-updates/s", "n_gpus": 1, "steps": K, "warmup": W,
            "ms_per_step": round(ms_batch / K, 6), "higher_is_better": True, "scaling": "weak",
@@ -472,7 +474,49 @@ def bench_batch(args):
                      "note": "the same 64 instances stepped one after the other with surf_step, "
                              "replayed from one HIP graph"},
            "batched_over_plain": round(ms_plain / ms_batch, 3)}
+    if kern_us:
+        ach = bpc * cells / (kern_us * 1e-6) / 1e9
+        out["roofline"] = {"bound": "hbm", "kernel": "k_batch_col2d", "achieved": round(ach, 1),
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                           "traffic": None, "bytes_per_cell": bpc,
+                           "avg_launch_us": round(kern_us, 3),
+                           "launch_timing": "3 back-to-back launches between HIP events (the "
+                                            "tuner's measurement of its choice)",
+                           "tuner_times_us": [round(t, 2) for t in times if t > 0]}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baselines(cpu_baseline_ensemble, ens, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_ensemble(ens, seconds):
+    """The oracle on one instance of each grid size of the ensemble, the same
+    number of steps each (about `seconds` in all), scaled by cell count."""
+    import math
+    import numpy as np
+    from oracle import oracle as O
+    picked = {}
+    for e in ens:
+        picked.setdefault(e["prob"]["n"][0], e)
+    insts = [picked[k] for k in sorted(picked)]
+    state = []
+    for e in insts:
+        prob = e["prob"]
+        q = O.full(prob)
+        iters = 2 * int(math.ceil(q["chi_max_eps"] * q["eps"] / (q["h"] / q["dim"]) - 1e-9))
+        chi = O.geometry(prob, e["vof0"](), iters)
+        F, P = O.init_state(prob, chi, c0_const=e["c0_const"], gamma0=e["gamma0"])
+        state.append([chi, F, P, np.zeros(16)])
+    cells = sum(int(np.prod(e["prob"]["n"])) for e in insts)
+    el, k = 0.0, 0
+    while (el < seconds or k == 0) and k < 200:
+        t = time.perf_counter()
+        for e, st in zip(insts, state):
+            st[1], st[2], _, st[3] = O.step(e["prob"], st[0], None, st[1], st[2], e["dt"], st[3])
+        el += time.perf_counter() - t
+        k += 1
+    return {"value": round(cells * k / el / 1e9, 6), "unit": "Gcell-updates/s", "kind": "oracle",
+            "sample": "one instance of each size (%s), %d steps each, FP64, %.1f s"
+                      % (", ".join("%d^2" % n for n in sorted(picked)), k, el)}
 
 
 def bench_adjoint(args):
@@ -503,6 +547,26 @@ def bench_adjoint(args):
     torch.cuda.synchronize()
     ms_f, ms_b = t0.elapsed_time(t1), t1.elapsed_time(t2)
     cells = int(np.prod(cfg["prob"]["n"]))
+    # one adjoint step alone, a burst of back-to-back calls between HIP
+    # events (same inputs; the dtheta accumulator only grows)
+    s = ro.s
+    F0, P0 = ck[0]
+    lF, lP, nF, nP = s.empty(), s.empty(), s.empty(), s.empty()
+    lF.zero_()
+    lP.fill_(1e-3)
+    dth = torch.zeros(4, dtype=torch.float64, device=dev)
+    reps = 50
+    for _ in range(3):
+        s.adjoint_step(F0, P0, lF, lP, nF, nP, dth, u=ro.u, w=w[0:1])
+    torch.cuda.synchronize()
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a0.record()
+    for _ in range(reps):
+        s.adjoint_step(F0, P0, lF, lP, nF, nP, dth, u=ro.u, w=w[0:1])
+    a1.record()
+    torch.cuda.synchronize()
+    adj_us = a0.elapsed_time(a1) / reps * 1e3
+    bpc = 40  # reads chi, u (3), F, psi, lambda (2); writes lambda (2): FP32
     out = {"metric": "surfactant-step Gcell-updates/s (adjoint form)",
            "value": round(cells * N / (ms_b * 1e-3) / 1e9, 4), "unit": "Gcell-updates/s",
            "n_gpus": 1, "steps": N, "warmup": 1, "ms_per_step": round(ms_b / N, 6),
@@ -514,7 +578,45 @@ def bench_adjoint(args):
            "forward": {"value": round(cells * N / (ms_f * 1e-3) / 1e9, 4),
                        "ms_per_step": round(ms_f / N, 6)},
            "adjoint_over_forward_time": round(ms_b / ms_f, 3)}
+    ach = bpc * cells / (adj_us * 1e-6) / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": "adjoint step (k_adv_star, k_adj_src, "
+                                                 "k_adj_adv, k_adj_final)",
+                       "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                       "bytes_per_cell": bpc, "avg_launch_us": round(adj_us, 3),
+                       "launch_timing": "%d back-to-back adjoint steps between HIP events" % reps}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baselines(cpu_baseline_adjoint, cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_adjoint(cfg, seconds):
+    """The oracle's forward and adjoint steps on the 128^3 sphere (the first
+    S forward steps, then S adjoint steps back over them)."""
+    import numpy as np
+    from oracle import oracle as O
+    prob = cfg["prob"]
+    chi = O.geometry(prob, cfg["vof0"](), 108)
+    u = cfg["u"]()
+    q = O.with_theta(prob, cfg["theta_nominal"])
+    F, P = O.init_state(q, chi, c0=cfg["c0"](), gamma0=cfg["gamma0"])
+    cells = int(np.prod(prob["n"]))
+    states, el, k = [(F, P)], 0.0, 0
+    while (el < 0.25 * seconds or k == 0) and k < 20:
+        t = time.perf_counter()
+        F, P, _, _ = O.step(q, chi, u, F, P, cfg["dt"])
+        el += time.perf_counter() - t
+        states.append((F, P))
+        k += 1
+    lF, lP = np.zeros_like(F), np.full_like(P, 1e-3)
+    ea = 0.0
+    for n in range(k - 1, -1, -1):
+        t = time.perf_counter()
+        lF, lP, _ = O.adjoint_step(q, chi, u, states[n][0], states[n][1], cfg["dt"], lF, lP)
+        ea += time.perf_counter() - t
+    return {"value": round(cells * k / ea / 1e9, 6), "unit": "Gcell-updates/s", "kind": "oracle",
+            "sample": "%d forward steps (%.1f s, %.4f Gcell-updates/s), then %d adjoint steps "
+                      "(%.1f s; the value), FP64" % (k, el, cells * k / el / 1e9, k, ea)}
 
 
 # ACDI: k_acdi_adv reads phi and the d face velocities, writes phi* and s;
@@ -646,13 +748,13 @@ def bench_implicit(args):
         "wall_s": round(wall, 4),
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline_implicit(args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baselines(cpu_baseline_implicit, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
 def cpu_baseline_implicit(seconds):
-    """The implicit FP64 oracle (sparse direct solves), one host thread, on
-    the same workload at 256^2 (the 1024^2 factorizations take minutes)."""
+    """The implicit FP64 oracle (sparse direct solves) on the same workload at
+    256^2 (the 1024^2 factorizations take minutes)."""
     import math
     import numpy as np
     from oracle import implicit as I
@@ -676,17 +778,31 @@ def cpu_baseline_implicit(seconds):
                                        totals=tot)
         el += time.perf_counter() - t
         k += 1
-    return {"value": round(ncell * k / el / 1e9, 6), "unit": "Gcell-updates/s", "cores": 1,
+    return {"value": round(ncell * k / el / 1e9, 6), "unit": "Gcell-updates/s",
             "kind": "oracle",
             "sample": "first %d steps of the same workload at 256^2 (geometry warm start + "
-                      "implicit step with sparse direct solves), FP64, one host thread, %.1f s"
-                      % (k, el)}
+                      "implicit step with sparse direct solves), FP64, %.1f s" % (k, el)}
+
+
+def cpu_baselines(fn, *args):
+    """The oracle's rate on all host cores (`cpu_baseline`), with the
+    single-core rate of the same sample beside it."""
+    from oracle import oracle as O
+    cores = O.set_threads(None)
+    O.set_threads(cores)
+    allc = fn(*args)
+    allc["cores"] = cores
+    O.set_threads(1)
+    one = fn(*args)
+    O.set_threads(None)
+    allc["one_core"] = {"value": one["value"], "sample": one["sample"]}
+    return allc
 
 
 def cpu_baseline(cfg, seconds):
-    """The FP64 oracle as it stands, single-threaded, on a bounded sample of
-    the same workload: the first S steps (the interface step + the surfactant
-    step), S chosen from a one-step probe to take about `seconds`."""
+    """The FP64 oracle as it stands on a bounded sample of the same workload:
+    the first S steps (the interface step + the surfactant step), S chosen
+    from a one-step probe to take about `seconds`."""
     import math
     import numpy as np
     from oracle import oracle as O
@@ -750,10 +866,10 @@ def cpu_baseline(cfg, seconds):
     what = ("ACDI step" if reinit else "geometry warm start") + " + step"
     if cfg.get("forces"):
         what += " + interfacial forces"
-    return {"value": round(ncell * nsteps / el / 1e9, 6), "unit": "Gcell-updates/s", "cores": 1,
+    return {"value": round(ncell * nsteps / el / 1e9, 6), "unit": "Gcell-updates/s",
             "kind": "oracle",
-            "sample": "first %d steps of the same workload (%s), FP64, one host thread, "
-                      "%.1f s" % (nsteps, what, el)}
+            "sample": "first %d steps of the same workload (%s), FP64, %.1f s"
+                      % (nsteps, what, el)}
 
 
 if __name__ == "__main__":

@@ -56,9 +56,13 @@ _gomp = None
 _max_threads = None
 
 
+_forced_threads = None
+
+
 def _threads_for(ncell):
     """One thread for small grids (a parallel region costs more than their
-    loops), all of them otherwise; the arithmetic does not depend on it."""
+    loops), all of them otherwise, unless set_threads fixed the count; the
+    arithmetic does not depend on it."""
     global _gomp, _max_threads
     if _gomp is None:
         try:
@@ -67,7 +71,20 @@ def _threads_for(ncell):
         except OSError:
             _gomp = False
     if _gomp:
-        _gomp.omp_set_num_threads(1 if ncell < 65536 else _max_threads)
+        if _forced_threads:
+            _gomp.omp_set_num_threads(_forced_threads)
+        else:
+            _gomp.omp_set_num_threads(1 if ncell < 65536 else _max_threads)
+
+
+def set_threads(n=None):
+    """Run every following call on n threads (None: the size rule above).
+    Returns the thread count the oracle then uses on a large grid."""
+    global _forced_threads
+    lib()
+    _threads_for(0)
+    _forced_threads = int(n) if n else None
+    return _forced_threads or (_max_threads if _gomp else 1)
 
 
 def lib():

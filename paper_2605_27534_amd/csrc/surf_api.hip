@@ -5,8 +5,12 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/surf.h"
@@ -115,8 +119,19 @@ struct surf_batch {
   std::vector<int> host_first;
   std::vector<void*> F, P, S;
   int parity = 0;
-  int nt = 512;      // threads per workgroup
-  int grid = 0;      // persistent workgroups
+  int nt = 512;      // tile kernel (paper-form instances): threads per workgroup
+  int grid = 0;      // tile kernel: persistent workgroups
+  // column kernel (weighted-form instances): row-chunk height, persistent
+  // workgroups (a multiple of 8), its work-list length and record count
+  int ty = 8;
+  int col_grid = 0;
+  int ncol_q = 0;
+  int col_records = 0;  // records reserved for column entries (row chunks of 8)
+  void* col_inst = nullptr;
+  int2* col_queue = nullptr;
+  std::vector<char> host_col_inst;
+  std::vector<int2> host_col_queue;
+  std::string tune_key;
   struct Graph {
     int nsteps, parity;
     double* totals;
@@ -1851,10 +1866,21 @@ namespace {
 
 struct BatchLayout {
   size_t total = 0;
-  size_t states, part, inst, queue, fargs, first, scratch0, scratch1;
+  size_t states, part, inst, col_inst, queue, col_queue, fargs, first, scratch0, scratch1;
   std::vector<size_t> chi, q;
-  int total_tiles = 0;
+  int total_tiles = 0;  // tile entries of the paper-form instances
+  int col_records = 0;  // column entries of the weighted-form instances (row chunks of 8)
 };
+
+// Weighted-form instances run on the column-streaming kernel; the paper
+// form keeps the LDS tile kernel.
+bool batch_col(const surf_params& q) { return q.flux_form == SURF_FLUX_WEIGHTED; }
+
+// workgroups of the column kernel for one instance with row chunks of ty rows
+int batch_col_wgs(const surf_grid& gr, int ty) {
+  const int chunks = (gr.n[1] + ty - 1) / ty;
+  return ((gr.n[0] + COL_OUT - 1) / COL_OUT) * ((chunks + COL_WAVES - 1) / COL_WAVES);
+}
 
 int batch_layout(int32_t n, const surf_grid* grids, const surf_params* prm, BatchLayout* L) {
   if (n <= 0 || !grids || !prm) return SURF_EINVAL;
@@ -1870,15 +1896,26 @@ int batch_layout(int32_t n, const surf_grid* grids, const surf_params* prm, Batc
     if (rc) return rc;
     if (grids[i].dim != 2 || prm[i].precision != prm[0].precision) return SURF_EINVAL;
     int t2[2];
-    tt += ntiles_2d(&grids[i], t2);
+    if (batch_col(prm[i])) {
+      // 32-bit byte offsets of the column kernel's loads
+      const long long es = prm[i].precision == SURF_F64 ? 8 : 4;
+      if ((long long)(grids[i].n[0] + 1) * (grids[i].n[1] + 1) * es > 0x7fffffffll)
+        return SURF_EINVAL;
+      L->col_records += batch_col_wgs(grids[i], 8);
+    } else {
+      tt += ntiles_2d(&grids[i], t2);
+    }
     size_t nc = (size_t)grids[i].n[0] * grids[i].n[1];
     if (nc > maxcell) maxcell = nc;
   }
   size_t inst_bytes = prm[0].precision == SURF_F64 ? sizeof(Step2dArgs<double>) : sizeof(Step2dArgs<float>);
+  size_t col_bytes = prm[0].precision == SURF_F64 ? sizeof(ColArgs<double>) : sizeof(ColArgs<float>);
   L->states = off; off += align_up((size_t)n * NSTATE * sizeof(double));
-  L->part = off; off += align_up((size_t)tt * NPART * sizeof(double));
+  L->part = off; off += align_up((size_t)(tt + L->col_records) * NPART * sizeof(double));
   L->inst = off; off += align_up((size_t)n * inst_bytes);
-  L->queue = off; off += align_up((size_t)tt * sizeof(int2));
+  L->col_inst = off; off += align_up((size_t)n * col_bytes);
+  L->queue = off; off += align_up((size_t)(tt > 0 ? tt : 1) * sizeof(int2));
+  L->col_queue = off; off += align_up((size_t)(L->col_records > 0 ? L->col_records : 1) * sizeof(int2));
   L->fargs = off; off += align_up((size_t)n * sizeof(FinalArgs));
   L->first = off; off += align_up((size_t)n * sizeof(int));
   L->scratch0 = off; off += align_up(maxcell * es);
@@ -1894,9 +1931,35 @@ int batch_layout(int32_t n, const surf_grid* grids, const surf_params* prm, Batc
   return SURF_OK;
 }
 
+// Column entries for row chunks of ty rows (ty in {8, 16}: never more
+// entries than the records reserved for 8).
+template <typename R>
+void batch_col_tables(surf_batch* b) {
+  b->host_col_queue.clear();
+  int rec = 0;
+  for (int i = 0; i < b->n; ++i) {
+    if (!batch_col(b->prm[i])) continue;
+    const int nw = batch_col_wgs(b->grids[i], b->ty);
+    ColArgs<R> a;
+    std::memcpy(&a, b->host_col_inst.data() + sizeof(a) * i, sizeof(a));
+    a.groups = (((b->grids[i].n[1] + b->ty - 1) / b->ty) + COL_WAVES - 1) / COL_WAVES;
+    a.strips = (b->grids[i].n[0] + COL_OUT - 1) / COL_OUT;
+    a.nwg = nw;
+    a.per_xcd = (nw + 7) / 8;
+    std::memcpy(b->host_col_inst.data() + sizeof(a) * i, &a, sizeof(a));
+    b->host_first[i] = rec;
+    for (int w = 0; w < nw; ++w) b->host_col_queue.push_back(make_int2(i, w));
+    rec += nw;
+    FinalArgs f = final_of(b->grids[i], b->prm[i], nw, b->prm[i].dt);
+    std::memcpy(b->host_fargs.data() + sizeof(f) * i, &f, sizeof(f));
+  }
+  b->ncol_q = rec;
+}
+
 template <typename R>
 void batch_tables(surf_batch* b) {
   b->host_inst.resize(sizeof(Step2dArgs<R>) * b->n);
+  b->host_col_inst.resize(sizeof(ColArgs<R>) * b->n);
   b->host_fargs.resize(sizeof(FinalArgs) * b->n);
   b->host_first.resize(b->n);
   b->host_queue.clear();
@@ -1931,28 +1994,66 @@ void batch_tables(surf_batch* b) {
     a.per_xcd = (a.ntiles + 7) / 8;
     a.diag = 0;
     std::memcpy(b->host_inst.data() + sizeof(a) * i, &a, sizeof(a));
-    b->host_first[i] = (int)b->host_queue.size();
+    ColArgs<R> c{};
+    c.g = a.g;
+    c.p = a.p;
+    c.chi = a.chi_in;
+    c.u[0] = c.u[1] = nullptr;
+    c.F = a.F;
+    c.psi = a.psi;
+    c.Fo = a.Fo;
+    c.Po = a.Po;
+    c.sig = a.sig;
+    c.part = nullptr;
+    c.dt = a.dt;
+    c.area_dt = a.area_dt;
+    c.r0 = 0.0;
+    std::memcpy(b->host_col_inst.data() + sizeof(c) * i, &c, sizeof(c));
+    if (batch_col(q)) continue;  // column entries: batch_col_tables
+    // tile entries of the paper-form instances: records after the column ones
+    b->host_first[i] = b->col_records + (int)b->host_queue.size();
     for (int t = 0; t < a.ntiles; ++t) b->host_queue.push_back(make_int2(i, t));
     FinalArgs f = final_of(gr, q, a.ntiles, q.dt);
     std::memcpy(b->host_fargs.data() + sizeof(f) * i, &f, sizeof(f));
   }
+  batch_col_tables<R>(b);
+}
+
+template <typename R>
+void batch_launch_col(surf_batch* b, int ty, int grid, int parity) {
+  if (b->ncol_q == 0) return;
+  if (ty == 16)
+    hipLaunchKernelGGL((k_batch_col2d<R, 16>), dim3(grid), dim3(64 * COL_WAVES), 0, b->stream,
+                       (const ColArgs<R>*)b->col_inst, (const int2*)b->col_queue, b->ncol_q,
+                       (const int*)b->first, parity, b->part);
+  else
+    hipLaunchKernelGGL((k_batch_col2d<R, 8>), dim3(grid), dim3(64 * COL_WAVES), 0, b->stream,
+                       (const ColArgs<R>*)b->col_inst, (const int2*)b->col_queue, b->ncol_q,
+                       (const int*)b->first, parity, b->part);
 }
 
 template <typename R>
 void batch_launch_step(surf_batch* b, int nt, int grid, int parity) {
+  if (b->total_tiles == 0) return;
+  double* part = b->part + (size_t)b->col_records * NPART;
   if (nt == 256)
     hipLaunchKernelGGL((k_batch2d<R, 256>), dim3(grid), dim3(256), 0, b->stream,
                        (const Step2dArgs<R>*)b->inst_tab, (const int2*)b->queue, b->total_tiles,
-                       parity, b->part);
+                       parity, part);
   else
     hipLaunchKernelGGL((k_batch2d<R, 512>), dim3(grid), dim3(512), 0, b->stream,
                        (const Step2dArgs<R>*)b->inst_tab, (const int2*)b->queue, b->total_tiles,
-                       parity, b->part);
+                       parity, part);
 }
 
 void batch_step_kernels(surf_batch* b, int parity, double* totals) {
-  if (b->prec == SURF_F64) batch_launch_step<double>(b, b->nt, b->grid, parity);
-  else batch_launch_step<float>(b, b->nt, b->grid, parity);
+  if (b->prec == SURF_F64) {
+    batch_launch_col<double>(b, b->ty, b->col_grid, parity);
+    batch_launch_step<double>(b, b->nt, b->grid, parity);
+  } else {
+    batch_launch_col<float>(b, b->ty, b->col_grid, parity);
+    batch_launch_step<float>(b, b->nt, b->grid, parity);
+  }
   hipLaunchKernelGGL(k_batch_final, dim3(b->n), dim3(FIN_BLOCK), 0, b->stream,
                      (const FinalArgs*)b->fargs, (const int*)b->first, (const double*)b->part,
                      b->states, totals);
@@ -1964,6 +2065,76 @@ void batch_drop_graphs(surf_batch* b) {
     (void)hipGraphDestroy(g.g);
   }
   b->graphs.clear();
+}
+
+// persistent grid of the column kernel: every entry in flight at once up to
+// 2048 workgroups (8 per CU), a multiple of 8
+int batch_col_default_grid(int nq) {
+  int g = nq < 2048 ? nq : 2048;
+  return ((g + 7) / 8) * 8 > 0 ? ((g + 7) / 8) * 8 : 8;
+}
+
+int batch_upload(surf_batch* b) {
+  bool ok = hipMemcpyAsync(b->inst_tab, b->host_inst.data(), b->host_inst.size(),
+                           hipMemcpyHostToDevice, b->stream) == hipSuccess &&
+            hipMemcpyAsync(b->col_inst, b->host_col_inst.data(), b->host_col_inst.size(),
+                           hipMemcpyHostToDevice, b->stream) == hipSuccess &&
+            hipMemcpyAsync(b->fargs, b->host_fargs.data(), b->host_fargs.size(),
+                           hipMemcpyHostToDevice, b->stream) == hipSuccess &&
+            hipMemcpyAsync(b->first, b->host_first.data(), b->host_first.size() * sizeof(int),
+                           hipMemcpyHostToDevice, b->stream) == hipSuccess;
+  if (ok && !b->host_queue.empty())
+    ok = hipMemcpyAsync(b->queue, b->host_queue.data(), b->host_queue.size() * sizeof(int2),
+                        hipMemcpyHostToDevice, b->stream) == hipSuccess;
+  if (ok && !b->host_col_queue.empty())
+    ok = hipMemcpyAsync(b->col_queue, b->host_col_queue.data(),
+                        b->host_col_queue.size() * sizeof(int2), hipMemcpyHostToDevice,
+                        b->stream) == hipSuccess;
+  // the host tables are pageable: wait before they may change
+  if (!ok || hipStreamSynchronize(b->stream) != hipSuccess) return SURF_EDEVICE;
+  return SURF_OK;
+}
+
+// Tuned launch shapes, keyed by the device and the instances' precision,
+// sizes, flux forms and bulk switches; kept for the process and, when the
+// environment variable SURF_TUNE_CACHE names a file, in that file (one line
+// per key: the key, then ty, col_grid, nt, grid).
+struct TuneChoice { int ty, col_grid, nt, grid; };
+std::mutex tune_mu;
+std::map<std::string, TuneChoice>& tune_cache() {
+  static std::map<std::string, TuneChoice> m;
+  static bool loaded = false;
+  if (!loaded) {
+    loaded = true;
+    const char* path = std::getenv("SURF_TUNE_CACHE");
+    if (path) {
+      if (FILE* f = std::fopen(path, "r")) {
+        char key[4096];
+        TuneChoice c;
+        while (std::fscanf(f, "%4095s %d %d %d %d", key, &c.ty, &c.col_grid, &c.nt, &c.grid) == 5)
+          if ((c.ty == 8 || c.ty == 16) && c.col_grid > 0 && c.col_grid % 8 == 0 &&
+              (c.nt == 256 || c.nt == 512) && c.grid > 0)
+            m[key] = c;
+        std::fclose(f);
+      }
+    }
+  }
+  return m;
+}
+
+std::string batch_tune_key(const surf_batch* b) {
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  std::string name = "gpu";
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) name = prop.gcnArchName;
+  for (auto& ch : name)
+    if (ch == ' ' || ch == ':') ch = '_';
+  std::string k = name + "/p" + std::to_string(b->prec);
+  for (int i = 0; i < b->n; ++i)
+    k += "/" + std::to_string(b->grids[i].n[0]) + "x" + std::to_string(b->grids[i].n[1]) +
+         (batch_col(b->prm[i]) ? "w" : "p") + (b->prm[i].bulk_enabled ? "b" : "i");
+  return k;
 }
 
 }  // namespace
@@ -2005,7 +2176,10 @@ int surf_batch_create(surf_batch** out, int32_t n, const surf_grid* grids,
   b->states = (double*)(base + L.states);
   b->part = (double*)(base + L.part);
   b->inst_tab = base + L.inst;
+  b->col_inst = base + L.col_inst;
   b->queue = (int2*)(base + L.queue);
+  b->col_queue = (int2*)(base + L.col_queue);
+  b->col_records = L.col_records;
   b->fargs = base + L.fargs;
   b->first = (int*)(base + L.first);
   b->scratch[0] = base + L.scratch0;
@@ -2021,18 +2195,23 @@ int surf_batch_create(surf_batch** out, int32_t n, const surf_grid* grids,
   }
   if (sigma)
     for (int i = 0; i < n; ++i) b->S.push_back(sigma[i]);
+  b->tune_key = batch_tune_key(b);
+  {
+    // a choice tuned before for the same instances on this device
+    std::lock_guard<std::mutex> lock(tune_mu);
+    auto it = tune_cache().find(b->tune_key);
+    if (it != tune_cache().end()) {
+      b->ty = it->second.ty;
+      b->col_grid = it->second.col_grid;
+      b->nt = it->second.nt;
+      b->grid = it->second.grid;
+    }
+  }
   if (b->prec == SURF_F64) batch_tables<double>(b);
   else batch_tables<float>(b);
-  b->grid = b->total_tiles < 2048 ? b->total_tiles : 2048;
-  bool ok = hipMemcpyAsync(b->inst_tab, b->host_inst.data(), b->host_inst.size(),
-                           hipMemcpyHostToDevice, b->stream) == hipSuccess &&
-            hipMemcpyAsync(b->queue, b->host_queue.data(), b->host_queue.size() * sizeof(int2),
-                           hipMemcpyHostToDevice, b->stream) == hipSuccess &&
-            hipMemcpyAsync(b->fargs, b->host_fargs.data(), b->host_fargs.size(),
-                           hipMemcpyHostToDevice, b->stream) == hipSuccess &&
-            hipMemcpyAsync(b->first, b->host_first.data(), b->host_first.size() * sizeof(int),
-                           hipMemcpyHostToDevice, b->stream) == hipSuccess;
-  if (!ok || hipStreamSynchronize(b->stream) != hipSuccess) {
+  if (b->grid == 0) b->grid = b->total_tiles < 2048 ? b->total_tiles : 2048;
+  if (b->col_grid == 0) b->col_grid = batch_col_default_grid(b->ncol_q);
+  if (batch_upload(b) != SURF_OK) {
     delete b;
     return SURF_EDEVICE;
   }
@@ -2135,41 +2314,100 @@ int surf_batch_parity(surf_batch* b) { return b ? b->parity : SURF_EINVAL; }
 
 int surf_batch_tune(surf_batch* b, int32_t* choice, double* times_us, int32_t max_times) {
   if (!b) return SURF_EINVAL;
-  const int T = b->total_tiles;
-  const int cand[][2] = {{256, T}, {512, T}, {512, T < 512 ? T : 512},
-                         {512, T < 1024 ? T : 1024}, {256, T < 2048 ? T : 2048},
-                         {512, T < 2048 ? T : 2048}};
-  const int nc = (int)(sizeof(cand) / sizeof(cand[0]));
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SURF_EDEVICE;
-  int best = 0;
-  double best_t = 1e300;
-  for (int k = 0; k < nc; ++k) {
-    // reads the current buffers and writes the other ones: the state is
-    // untouched and the next step overwrites the scratch results
-    auto run = [&]() {
-      if (b->prec == SURF_F64) batch_launch_step<double>(b, cand[k][0], cand[k][1], b->parity);
-      else batch_launch_step<float>(b, cand[k][0], cand[k][1], b->parity);
-    };
+  // each candidate reads the current buffers and writes the other ones: the
+  // state is untouched and the next step overwrites the scratch results
+  auto timed = [&](auto run) -> double {
     run();
     (void)hipEventRecord(e0, b->stream);
     for (int r = 0; r < 3; ++r) run();
     (void)hipEventRecord(e1, b->stream);
-    if (hipEventSynchronize(e1) != hipSuccess) return SURF_EDEVICE;
+    if (hipEventSynchronize(e1) != hipSuccess) return -1.0;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    double us = ms * 1e3 / 3;
-    if (times_us && k < max_times) times_us[k] = us;
-    if (us < best_t) {
-      best_t = us;
-      best = k;
+    return ms * 1e3 / 3;
+  };
+  int k_out = 0, best = -1;
+  // column kernel: row-chunk height (FP32 8 or 16 rows; FP64 8) by
+  // persistent grid
+  if (b->ncol_q > 0) {
+    const int tys[2] = {8, 16};
+    const int nty = b->prec == SURF_F64 ? 1 : 2;
+    double best_t = 1e300;
+    int best_ty = b->ty, best_grid = b->col_grid;
+    for (int t = 0; t < nty; ++t) {
+      b->ty = tys[t];
+      if (b->prec == SURF_F64) batch_col_tables<double>(b);
+      else batch_col_tables<float>(b);
+      if (batch_upload(b) != SURF_OK) return SURF_EDEVICE;
+      const int nq = b->ncol_q;
+      const int grids[4] = {batch_col_default_grid(nq < 1024 ? nq : 1024),
+                            batch_col_default_grid(nq), ((nq < 4096 ? nq : 4096) + 7) / 8 * 8,
+                            (nq + 7) / 8 * 8};
+      for (int g = 0; g < 4; ++g) {
+        const int grid = grids[g];
+        double us = timed([&]() {
+          if (b->prec == SURF_F64) batch_launch_col<double>(b, b->ty, grid, b->parity);
+          else batch_launch_col<float>(b, b->ty, grid, b->parity);
+        });
+        if (us < 0) return SURF_EDEVICE;
+        if (times_us && k_out < max_times) times_us[k_out] = us;
+        if (us < best_t) {
+          best_t = us;
+          best_ty = b->ty;
+          best_grid = grid;
+          best = k_out;
+        }
+        ++k_out;
+      }
     }
+    b->ty = best_ty;
+    b->col_grid = best_grid;
+    if (b->prec == SURF_F64) batch_col_tables<double>(b);
+    else batch_col_tables<float>(b);
+    if (batch_upload(b) != SURF_OK) return SURF_EDEVICE;
+  }
+  // tile kernel (paper-form instances): threads per workgroup by grid
+  if (b->total_tiles > 0) {
+    const int T = b->total_tiles;
+    const int cand[][2] = {{256, T}, {512, T}, {512, T < 512 ? T : 512},
+                           {512, T < 1024 ? T : 1024}, {256, T < 2048 ? T : 2048},
+                           {512, T < 2048 ? T : 2048}};
+    const int nc = (int)(sizeof(cand) / sizeof(cand[0]));
+    double best_t = 1e300;
+    int bk = 0;
+    for (int k = 0; k < nc; ++k) {
+      double us = timed([&]() {
+        if (b->prec == SURF_F64) batch_launch_step<double>(b, cand[k][0], cand[k][1], b->parity);
+        else batch_launch_step<float>(b, cand[k][0], cand[k][1], b->parity);
+      });
+      if (us < 0) return SURF_EDEVICE;
+      if (times_us && k_out < max_times) times_us[k_out] = us;
+      if (us < best_t) {
+        best_t = us;
+        bk = k;
+      }
+      if (b->ncol_q == 0 && best_t == us) best = k_out;
+      ++k_out;
+    }
+    b->nt = cand[bk][0];
+    b->grid = cand[bk][1];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  b->nt = cand[best][0];
-  b->grid = cand[best][1];
   batch_drop_graphs(b);
+  {
+    std::lock_guard<std::mutex> lock(tune_mu);
+    tune_cache()[b->tune_key] = TuneChoice{b->ty, b->col_grid, b->nt, b->grid};
+    if (const char* path = std::getenv("SURF_TUNE_CACHE")) {
+      if (FILE* f = std::fopen(path, "a")) {
+        std::fprintf(f, "%s %d %d %d %d\n", b->tune_key.c_str(), b->ty, b->col_grid, b->nt,
+                     b->grid);
+        std::fclose(f);
+      }
+    }
+  }
   if (choice) *choice = best;
   return status_of_launch();
 }

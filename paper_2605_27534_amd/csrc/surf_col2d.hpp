@@ -529,4 +529,71 @@ __global__ void __launch_bounds__(64 * COL_WAVES) k_col2d(ColArgs<R> a) {
   block_partials<R, 64 * COL_WAVES>(v, a.part + (long long)wg * NPART);
 }
 
+// Batched form on the column-streaming transport: one persistent launch over
+// the flattened work list of every weighted-form instance of a batch, one
+// entry per workgroup of that instance's single-problem launch (a strip and
+// a group of COL_WAVES row chunks of TY rows).  inst[i] holds instance i's
+// arguments for parity 0 (reading F, psi and writing Fo, Po); parity 1
+// swaps the two buffers.  Entry (i, w) leaves its record in
+// part[first[i] + w], so each instance's records are contiguous and in the
+// order of the single-problem launch.  The entries are dealt to the eight
+// XCDs in contiguous bands (workgroup b runs on XCD b mod 8), so that the
+// vertically adjacent chunks of a strip, which share halo rows, meet in one
+// L2.  The grid is a multiple of 8.
+template <typename R, int TY>
+__global__ void __launch_bounds__(64 * COL_WAVES) k_batch_col2d(
+    const ColArgs<R>* __restrict__ inst, const int2* __restrict__ queue, int nqueue,
+    const int* __restrict__ first, int parity, double* __restrict__ part) {
+  const int b = blockIdx.x;
+  const int per_xcd = (nqueue + 7) / 8;
+  const int stride = gridDim.x >> 3;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int k = b >> 3; k < per_xcd; k += stride) {
+    const int q = (b & 7) * per_xcd + k;
+    if (q >= nqueue) break;  // uniform over the workgroup; later k only grow
+    const int2 e = queue[q];
+    ColArgs<R> a = inst[e.x];
+    if (parity) {
+      const R* f = a.F;
+      a.F = a.Fo;
+      a.Fo = (R*)f;
+      const R* ps = a.psi;
+      a.psi = a.Po;
+      a.Po = (R*)ps;
+    }
+    const int wg = e.y;
+    const int nx = a.g.n[0], ny = a.g.n[1];
+    const int sx = wg / a.groups, cg = wg - sx * a.groups;
+    const int x0 = sx * COL_OUT, y0 = (cg * COL_WAVES + wv) * TY;
+    ColAcc<R> acc{0.0, 0.0, 0.0, 0.0, 0.0, R(0), R(-INFINITY), R(INFINITY), R(INFINITY), 0};
+    if (y0 < ny) {
+      const bool ix = x0 >= 3 && x0 + 62 <= nx, iy = y0 >= 3 && y0 + TY + 3 <= ny;
+      if (a.p.bulk) {
+        if (ix && iy) col2d_wave<R, TY, false, true, true, true, false>(a, x0, y0, lane, acc);
+        else if (iy) col2d_wave<R, TY, false, true, false, true, false>(a, x0, y0, lane, acc);
+        else if (ix) col2d_wave<R, TY, false, true, true, false, false>(a, x0, y0, lane, acc);
+        else col2d_wave<R, TY, false, true, false, false, false>(a, x0, y0, lane, acc);
+      } else {
+        if (ix && iy) col2d_wave<R, TY, false, false, true, true, false>(a, x0, y0, lane, acc);
+        else if (iy) col2d_wave<R, TY, false, false, false, true, false>(a, x0, y0, lane, acc);
+        else if (ix) col2d_wave<R, TY, false, false, true, false, false>(a, x0, y0, lane, acc);
+        else col2d_wave<R, TY, false, false, false, false, false>(a, x0, y0, lane, acc);
+      }
+    }
+    double v[NPART];
+    v[P_SUM_F] = acc.sF;
+    v[P_SUM_PSI] = acc.sP;
+    v[P_SUM_DELTA] = acc.sD;
+    v[P_SUM_SIGDELTA] = acc.sSD;
+    v[P_OUTFLOW] = acc.out;
+    v[P_MAX_USUM] = (double)acc.usum;
+    v[P_MAX_C] = (double)acc.mxC;
+    v[P_MIN_F] = (double)acc.mnF;
+    v[P_MIN_PSI] = (double)acc.mnP;
+    v[P_NBAD] = (double)acc.nbad;
+    block_partials<R, 64 * COL_WAVES>(v, part + (long long)(first[e.x] + wg) * NPART);
+    __syncthreads();  // the record's LDS is reused by the next entry
+  }
+}
+
 }  // namespace surf
