@@ -245,6 +245,15 @@ int surf_init_state(surf_ctx* ctx, const void* c0, double c0_const, double gamma
  * frequency by passing vof_next.  The regularization is explicit:
  * SURF_T_DT_NEXT and SURF_STATUS_UNSTABLE include its bound
  * 1/(zeta (2 dim eps/h^2 + sqrt(dim)/h)).
+ * FP32 contexts (weighted flux form, explicit substep 2) store the new F and
+ * psi with stochastic rounding: each value is one of the two floats
+ * neighbouring the exact update, with the probability of its closeness, so
+ * that increments below half an ulp are kept on average (round-to-nearest
+ * drops them every step, and over thousands of steps a smooth field drifts
+ * by tens of ulps).  The random numbers are a hash of the cell and of the
+ * running time the step starts from (surf_set_time): a run repeated from
+ * the same state and time gives the same bits.  FP64 contexts add exactly
+ * as written.
  * With substep2 = SURF_SUBSTEP2_IMPLICIT (section 3, Appendix C) the step
  * advects, then takes substep 2 by implicit Euler: picard_iters sweeps of
  * the interfacial problem for Gamma and the bulk problem for c, each solved
@@ -408,6 +417,16 @@ int surf_step_static(const surf_grid* grid, const surf_params* params, double dt
  * ACDI step is prepared (surf_prepare_phase), which has already used the
  * current one. */
 int surf_set_dt(surf_ctx* ctx, double dt);
+
+/* Sets the running time of the context (the time a step starts from,
+ * SURF_T_TIME of the previous step's totals) from one device double,
+ * enqueued on the context's stream; time_dev NULL sets it to 0.  In FP32
+ * the time also keys the stochastic rounding of the stored state (see
+ * surf_step), so a run replayed from a stored state with that state's time
+ * reproduces the original steps bit for bit (the adjoint's recomputation
+ * from checkpoints does this).  SURF_ESTATE while a prepared step is
+ * pending. */
+int surf_set_time(surf_ctx* ctx, const double* time_dev);
 
 /* Reads (synchronously: waits for the stream) and clears the status word. */
 int surf_get_status(surf_ctx* ctx, uint32_t* bits);

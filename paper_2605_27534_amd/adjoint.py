@@ -57,8 +57,10 @@ class Rollout:
         s.loss_weights(tot, target.to(torch.float64).contiguous(), w, loss)
         return loss[0], tot, w, ck
 
-    def backward(self, w, ck):
-        """dL/dtheta (4, float64) and dL/dc0 (field) from the checkpoints."""
+    def backward(self, w, ck, tot=None):
+        """dL/dtheta (4, float64) and dL/dc0 (field) from the checkpoints; tot
+        (the forward's totals) restores each segment's starting time, so that
+        the recomputed states are the forward's bit for bit."""
         s = self.s
         dth = torch.zeros(4, dtype=torch.float64, device=s.device)
         FN, PN = ck[self.N]
@@ -71,6 +73,7 @@ class Rollout:
             s1 = min(s0 + self.K, self.N)
             states = [ck[s0]]
             F, P = ck[s0]
+            s.set_time(tot[s0 - 1, 11:12] if (tot is not None and s0 > 0) else None)
             for n in range(s0, s1 - 1):
                 F, P = self._step(F, P, scratch)
                 states.append((F, P))
@@ -91,14 +94,14 @@ class SurfRollout(torch.autograd.Function):
     def forward(ctx, theta, c0, rollout, target):
         loss, tot, w, ck = rollout.forward(theta, c0, target)
         ctx.rollout = rollout
-        ctx.saved = (w, ck)
+        ctx.saved = (w, ck, tot)
         ctx.c0_dtype = c0.dtype
         ctx.theta_dtype = theta.dtype
         return loss.clone()
 
     @staticmethod
     def backward(ctx, g):
-        w, ck = ctx.saved
-        dth, gc0 = ctx.rollout.backward(w, ck)
+        w, ck, tot = ctx.saved
+        dth, gc0 = ctx.rollout.backward(w, ck, tot)
         g = g.to(torch.float64)
         return (dth * g).to(ctx.theta_dtype), (gc0.to(torch.float64) * g).to(ctx.c0_dtype), None, None

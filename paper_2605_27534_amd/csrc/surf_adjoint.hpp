@@ -41,63 +41,73 @@ struct AdjArgs {
   long long ncell;
 };
 
-__device__ __forceinline__ void cell_coords(const Grid& g, long long c, int* x) {
-  x[0] = (int)(c % g.n[0]);
-  long long r = c / g.n[0];
-  x[1] = (int)(r % g.n[1]);
-  x[2] = (int)(r / g.n[1]);
+// Launch shape of the three per-cell adjoint kernels: 64 x 4 cells of one
+// plane per 256-thread workgroup, grid (ceil(nx/64), ceil(ny/4), nz), so
+// that a cell's coordinates come from the workgroup and thread indices (no
+// integer division); cell indices are 32-bit (grids under 2^31 cells).
+constexpr int ADJ_TX = 64, ADJ_TY = 4;
+
+__device__ __forceinline__ bool adj_cell(const Grid& g, int* x) {
+  x[0] = blockIdx.x * ADJ_TX + (int)(threadIdx.x % ADJ_TX);
+  x[1] = blockIdx.y * ADJ_TY + (int)(threadIdx.x / ADJ_TX);
+  x[2] = blockIdx.z;
+  return x[0] < g.n[0] && x[1] < g.n[1];
 }
 
-template <typename R>
-__device__ __forceinline__ long long nb_index(const Grid& g, const int* x, int d, int s) {
-  int y[3] = {x[0], x[1], x[2]};
-  y[d] = map_axis(x[d] + s, g.n[d], g.bc[d][0], g.bc[d][1]);
-  return cell_index(g, y[0], y[1], y[2]);
+// stride of axis d in the cell layout
+__device__ __forceinline__ int axis_stride(const Grid& g, int d) {
+  return d == 0 ? 1 : (d == 1 ? g.n[0] : g.n[0] * g.n[1]);
 }
 
-// advective face value slope-limited as in the forward step, per cell
+// 32-bit face index along d (the d coordinate runs 0..n_d)
+__device__ __forceinline__ int face_index32(const Grid& g, int d, const int* y) {
+  const int mx = g.n[0] + (d == 0), my = g.n[1] + (d == 1);
+  return y[0] + mx * (y[1] + my * y[2]);
+}
+
+// the advected state xi* = xi - dt/h sum_d (flux_hi - flux_lo), fluxes as in
+// the forward step (BCG-minmod face values); per axis the five cells c-2 ..
+// c+2 (mapped) are loaded once and serve both faces
 template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_adv_star(AdjArgs<R> a) {
-  long long c = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  if (c >= a.ncell) return;
+__global__ void __launch_bounds__(ADJ_TX * ADJ_TY) k_adv_star(AdjArgs<R> a) {
+  int x[3];
+  if (!adj_cell(a.g, x)) return;
   const Grid& g = a.g;
   const Par<R>& p = a.p;
-  int x[3];
-  cell_coords(g, c, x);
+  const int c = x[0] + g.n[0] * (x[1] + g.n[1] * x[2]);
   const R cfl = a.dt * p.inv_h;
-  for (int f = 0; f < 2; ++f) {
-    if (f == 0 && !p.bulk) continue;
-    const R* xi = f == 0 ? a.F : a.psi;
-    R div = R(0);
-    for (int d = 0; d < g.dim; ++d) {
-      const bool per = g.bc[d][0] == BC_PERIODIC;
-      const int nd = g.n[d];
-      // lo face (index x[d]) and hi face (index x[d] + 1)
-      for (int s = 0; s < 2; ++s) {
-        int fidx = x[d] + s;
-        bool blo = !per && fidx == 0, bhi = !per && fidx == nd;
-        int fw = (per && fidx == nd) ? 0 : fidx;
-        int y[3] = {x[0], x[1], x[2]};
-        y[d] = fw;
-        R uf = a.u[d][face_index(g, d, y[0], y[1], y[2])];
-        R fl;
-        if (blo) {
-          fl = g.bc[d][0] == BC_OPEN ? uf * xi[c] : R(0);
-        } else if (bhi) {
-          fl = g.bc[d][1] == BC_OPEN ? uf * xi[c] : R(0);
-        } else {
-          // cells L = fidx - 1 and R = fidx along d (mapped), and their outer neighbours
-          int off = s == 0 ? -1 : 0;  // offset of L from this cell
-          R xLm = xi[nb_index<R>(g, x, d, off - 1)], xL = xi[nb_index<R>(g, x, d, off)];
-          R xR = xi[nb_index<R>(g, x, d, off + 1)], xRp = xi[nb_index<R>(g, x, d, off + 2)];
-          fl = adv_flux<R>(uf, xLm, xL, xR, xRp, cfl);
-        }
-        div += s == 0 ? -fl : fl;
+  R divF = R(0), divP = R(0);
+  for (int d = 0; d < g.dim; ++d) {
+    const bool per = g.bc[d][0] == BC_PERIODIC;
+    const int nd = g.n[d], st = axis_stride(g, d);
+    int idx[5];
+#pragma unroll
+    for (int o = -2; o <= 2; ++o)
+      idx[o + 2] = c + (map_axis(x[d] + o, nd, g.bc[d][0], g.bc[d][1]) - x[d]) * st;
+    int ylo[3] = {x[0], x[1], x[2]}, yhi[3] = {x[0], x[1], x[2]};
+    yhi[d] = (per && x[d] + 1 == nd) ? 0 : x[d] + 1;
+    const R ulo = a.u[d][face_index32(g, d, ylo)], uhi = a.u[d][face_index32(g, d, yhi)];
+    const bool blo = !per && x[d] == 0, bhi = !per && x[d] == nd - 1;
+    for (int f = 0; f < 2; ++f) {
+      if (f == 0 && !p.bulk) continue;
+      const R* xi = f == 0 ? a.F : a.psi;
+      const R v0 = xi[idx[0]], v1 = xi[idx[1]], v2 = xi[idx[2]], v3 = xi[idx[3]],
+              v4 = xi[idx[4]];
+      const R flo = blo ? (g.bc[d][0] == BC_OPEN ? ulo * v2 : R(0))
+                        : adv_flux<R>(ulo, v0, v1, v2, v3, cfl);
+      const R fhi = bhi ? (g.bc[d][1] == BC_OPEN ? uhi * v2 : R(0))
+                        : adv_flux<R>(uhi, v1, v2, v3, v4, cfl);
+      if (f == 0) {
+        divF += -flo;
+        divF += fhi;
+      } else {
+        divP += -flo;
+        divP += fhi;
       }
     }
-    R v = xi[c] - cfl * div;
-    if (f == 0) ((R*)a.Fs)[c] = v; else ((R*)a.Ps)[c] = v;
   }
+  if (p.bulk) ((R*)a.Fs)[c] = a.F[c] - cfl * divF;
+  ((R*)a.Ps)[c] = a.psi[c] - cfl * divP;
 }
 
 template <int NT>
@@ -121,14 +131,13 @@ __device__ __forceinline__ void block_sum4(double* v, double* out) {
 // D M diag(1/w) with M the symmetric face-weighted graph Laplacian, so
 // (L^T mu)_i = D sum_f wbar_f (mu_nb - mu_i) / (w_i h^2).
 template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_adj_src(AdjArgs<R> a) {
-  long long c = (long long)blockIdx.x * BLOCK + threadIdx.x;
+__global__ void __launch_bounds__(ADJ_TX * ADJ_TY) k_adj_src(AdjArgs<R> a) {
   double acc[NADJ] = {0.0, 0.0, 0.0, 0.0};
-  if (c < a.ncell) {
+  int x[3];
+  if (adj_cell(a.g, x)) {
     const Grid& g = a.g;
     const Par<R>& p = a.p;
-    int x[3];
-    cell_coords(g, c, x);
+    const int c = x[0] + g.n[0] * (x[1] + g.n[1] * x[2]);
     R ph, om, de;
     phase<R>(a.chi[c], p, ph, om, de);
     const R wF = ph + p.eta, wP = de + p.eta_eps;
@@ -136,11 +145,12 @@ __global__ void __launch_bounds__(BLOCK) k_adj_src(AdjArgs<R> a) {
     const R cF = p.bulk ? a.Fs[c] / wF : R(0), cP = a.Ps[c] / wP;
     R LtF = R(0), LtP = R(0), SF = R(0), SP = R(0);
     for (int d = 0; d < g.dim; ++d) {
+      const int st = axis_stride(g, d);
       for (int s = -1; s <= 1; s += 2) {
         bool bnd = (s < 0 && x[d] == 0 && g.bc[d][0] != BC_PERIODIC) ||
                    (s > 0 && x[d] == g.n[d] - 1 && g.bc[d][1] != BC_PERIODIC);
         if (bnd) continue;
-        long long o = nb_index<R>(g, x, d, s);
+        const int o = c + (map_axis(x[d] + s, g.n[d], g.bc[d][0], g.bc[d][1]) - x[d]) * st;
         R pho, omo, deo;
         phase<R>(a.chi[o], p, pho, omo, deo);
         R fbar = R(0.5) * (ph + pho), dbar = R(0.5) * (de + deo);
@@ -181,7 +191,8 @@ __global__ void __launch_bounds__(BLOCK) k_adj_src(AdjArgs<R> a) {
     a.nF[c] = nuF;
     a.nP[c] = nuP;
   }
-  block_sum4<BLOCK>(acc, a.part + (long long)blockIdx.x * NADJ);
+  const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  block_sum4<ADJ_TX * ADJ_TY>(acc, a.part + (long long)blk * NADJ);
 }
 
 // derivative of the equation of state
@@ -199,67 +210,90 @@ __device__ __forceinline__ R eos_prime(R G, const Par<R>& p) {
 
 // lambda_j = nu_j + (dt/h) sum_f dflux_f/dxi_j (nu_R(f) - nu_L(f)), over the
 // faces f whose (mirrored or wrapped) stencil holds j: along each axis the
-// faces j-3/2 .. j+3/2
+// faces j-1/2 .. j+5/2 (face k lies between cells j+k-1 and j+k), whose
+// stencils reach the cells j-3 .. j+3; per axis those cells' xi (7), their
+// nu (5 of them) and the four face velocities are loaded once
 template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_adj_adv(AdjArgs<R> a) {
-  long long c = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  if (c >= a.ncell) return;
+__global__ void __launch_bounds__(ADJ_TX * ADJ_TY) k_adj_adv(AdjArgs<R> a) {
+  int x[3];
+  if (!adj_cell(a.g, x)) return;
   const Grid& g = a.g;
   const Par<R>& p = a.p;
-  int x[3];
-  cell_coords(g, c, x);
+  const int c = x[0] + g.n[0] * (x[1] + g.n[1] * x[2]);
   R lamF = a.nF[c], lamP = a.nP[c];
   if (a.has_u) {
     const R cfl = a.dt * p.inv_h;
     for (int d = 0; d < g.dim; ++d) {
       const bool per = g.bc[d][0] == BC_PERIODIC;
-      const int nd = g.n[d];
+      const int nd = g.n[d], st = axis_stride(g, d);
+      // mapped neighbours along d at offsets -3 .. 3: index and whether it is
+      // this cell (a mirrored stencil can reach it twice)
+      int idx[7];
+      bool me[7];
+#pragma unroll
+      for (int o = -3; o <= 3; ++o) {
+        const int m = map_axis(x[d] + o, nd, g.bc[d][0], g.bc[d][1]);
+        idx[o + 3] = c + (m - x[d]) * st;
+        me[o + 3] = m == x[d];
+      }
+      R uf[4];
+      bool skip[4], blo[4], bhi[4];
+#pragma unroll
       for (int k = -1; k <= 2; ++k) {
         int fidx = x[d] + k;  // face between cells fidx-1 and fidx
+        skip[k + 1] = false;
         if (per) {
-          fidx = ((fidx % nd) + nd) % nd;  // face nd is face 0
+          fidx = fidx < 0 ? fidx + nd : (fidx >= nd ? fidx - nd : fidx);  // face nd is face 0
         } else if (fidx < 0 || fidx > nd) {
-          continue;
+          skip[k + 1] = true;
+          fidx = 0;
         }
         int y[3] = {x[0], x[1], x[2]};
         y[d] = fidx;
-        R uf = a.u[d][face_index(g, d, y[0], y[1], y[2])];
-        bool blo = !per && fidx == 0, bhi = !per && fidx == nd;
-        // the face's left/right cells relative to this cell: offsets k-1, k
-        for (int f = 0; f < 2; ++f) {
-          if (f == 0 && !p.bulk) continue;
-          const R* xi = f == 0 ? a.F : a.psi;
-          const R* nu = f == 0 ? a.nF : a.nP;
+        uf[k + 1] = a.u[d][face_index32(g, d, y)];
+        blo[k + 1] = !per && fidx == 0;
+        bhi[k + 1] = !per && fidx == nd;
+      }
+      for (int f = 0; f < 2; ++f) {
+        if (f == 0 && !p.bulk) continue;
+        const R* xi = f == 0 ? a.F : a.psi;
+        const R* nu = f == 0 ? a.nF : a.nP;
+        R v[7], w5[5];
+#pragma unroll
+        for (int o = 0; o < 7; ++o) v[o] = xi[idx[o]];
+#pragma unroll
+        for (int o = 0; o < 5; ++o) w5[o] = nu[idx[o + 1]];  // offsets -2 .. 2
+#pragma unroll
+        for (int k = -1; k <= 2; ++k) {
+          if (skip[k + 1]) continue;
+          const R u = uf[k + 1];
           R gsum = R(0);
-          if (blo || bhi) {
-            // open boundary: flux = u xi_interior, interior cell is this one only
-            int bc = blo ? g.bc[d][0] : g.bc[d][1];
-            if (bc == BC_OPEN && ((blo && x[d] == 0) || (bhi && x[d] == nd - 1))) {
-              R gdiff = blo ? nu[c] : -nu[c];
-              gsum = uf * gdiff;
+          if (blo[k + 1] || bhi[k + 1]) {
+            // open boundary: flux = u xi_interior, the interior cell only
+            const int bc = blo[k + 1] ? g.bc[d][0] : g.bc[d][1];
+            if (bc == BC_OPEN && ((blo[k + 1] && x[d] == 0) || (bhi[k + 1] && x[d] == nd - 1))) {
+              const R gdiff = blo[k + 1] ? nu[c] : -nu[c];
+              gsum = u * gdiff;
             }
           } else {
-            long long L = nb_index<R>(g, x, d, k - 1), Rr = nb_index<R>(g, x, d, k);
-            bool pos = uf > R(0);
-            // upwind cell b and its neighbours along d (mapped)
-            int ob = pos ? k - 1 : k;
-            long long ib = nb_index<R>(g, x, d, ob);
-            int yb[3] = {x[0], x[1], x[2]};
-            yb[d] = map_axis(x[d] + ob, nd, g.bc[d][0], g.bc[d][1]);
-            long long im = nb_index<R>(g, yb, d, -1), iq = nb_index<R>(g, yb, d, +1);
-            R s1 = xi[ib] - xi[im], s2 = xi[iq] - xi[ib];
+            // L at offset k-1, R at k; the upwind cell b and its neighbours
+            const bool pos = u > R(0);
+            const int ob = pos ? k - 1 : k;
+            const R xb = v[ob + 3], xm = v[ob + 2], xq = v[ob + 4];
+            const R s1 = xb - xm, s2 = xq - xb;
             R sel1 = R(0), sel2 = R(0);
-            bool same = (s1 > R(0) && s2 > R(0)) || (s1 < R(0) && s2 < R(0));
+            const bool same = (s1 > R(0) && s2 > R(0)) || (s1 < R(0) && s2 < R(0));
             if (same) {
               if (fabs(s1) < fabs(s2)) sel1 = R(1); else sel2 = R(1);
             }
-            R kk = (pos ? R(1) : R(-1)) * R(0.5) * (R(1) - fabs(uf) * cfl);
-            R wm = uf * (-kk * sel1), wb = uf * (R(1) + kk * sel1 - kk * sel2), wq = uf * kk * sel2;
+            const R kk = (pos ? R(1) : R(-1)) * R(0.5) * (R(1) - fabs(u) * cfl);
+            const R wm = u * (-kk * sel1), wb = u * (R(1) + kk * sel1 - kk * sel2),
+                    wq = u * kk * sel2;
             R w = R(0);
-            if (im == c) w += wm;
-            if (ib == c) w += wb;
-            if (iq == c) w += wq;
-            gsum = w * (nu[Rr] - nu[L]);
+            if (me[ob + 2]) w += wm;
+            if (me[ob + 3]) w += wb;
+            if (me[ob + 4]) w += wq;
+            gsum = w * (w5[k + 2] - w5[k + 1]);
           }
           if (f == 0) lamF += cfl * gsum; else lamP += cfl * gsum;
         }

@@ -198,6 +198,11 @@ int check_grid_params(const surf_grid* gr, const surf_params* p) {
       (p->flux_form != SURF_FLUX_WEIGHTED || p->adjoint ||
        (gr->dim != 2 && p->substep2 != SURF_SUBSTEP2_IMPLICIT)))
     return SURF_EINVAL;
+  // the adjoint kernels index cells and faces in 32 bits and launch a grid of
+  // (nx/64, ny/4, nz) workgroups
+  if (p->adjoint && ((double)(gr->n[0] + 1) * (gr->n[1] + 1) * (gr->n[2] + 1) >= 2147483648.0 ||
+                     (gr->n[1] + 3) / 4 > 65535 || gr->n[2] > 65535))
+    return SURF_EINVAL;
   if (p->substep2 == SURF_SUBSTEP2_IMPLICIT &&
       (p->flux_form != SURF_FLUX_WEIGHTED || p->adjoint || p->picard_iters < 0 ||
        p->picard_iters > IMP_MAX_PICARD || p->cg_max_iters < 0 || !(p->cg_tol >= 0) ||
@@ -332,6 +337,12 @@ int geo3_tiles(const surf_grid* gr, int* t) {
   if (gr->dim != 3) return 0;
   for (int d = 0; d < 3; ++d) t[d] = (gr->n[d] + G3 - 1) / G3;
   return t[0] * t[1] * t[2];
+}
+
+// workgroups of the adjoint kernels (64 x 4 cells of one plane each)
+long long adj_blocks(const surf_grid* gr) {
+  return (long long)((gr->n[0] + ADJ_TX - 1) / ADJ_TX) * ((gr->n[1] + ADJ_TY - 1) / ADJ_TY) *
+         gr->n[2];
 }
 
 int flag_count(const surf_grid* gr, const surf_params* p) {
@@ -704,6 +715,7 @@ void col2d_transport(surf_ctx* c, const void* const* u, const void* F_in, const 
   a.Po = (R*)psi_out;
   a.sig = (R*)sigma_out;
   a.part = c->part;
+  a.state = c->state;
   a.dt = (R)c->dt;
   a.area_dt = (R)(c->grid.h * c->dt);
   a.r0 = c->grid.origin[0];
@@ -732,6 +744,7 @@ void col3d_transport(surf_ctx* c, const void* const* u, const void* F_in, const 
   a.Po = (R*)psi_out;
   a.sig = (R*)sigma_out;
   a.part = c->part;
+  a.state = c->state;
   a.dt = (R)c->dt;
   a.area_dt = (R)(c->grid.h * c->grid.h * c->dt);
   a.strips = c->c3[0];
@@ -1136,10 +1149,20 @@ template <typename R>
 int force_impl(surf_ctx* c, const void* sigma, void* const* force) {
   materialize<R>(c);
   Par<R> p = make_par<R>(c);
-  for (int d = 0; d < c->grid.dim; ++d) {
-    long long nf = c->ncell / c->grid.n[d] * (c->grid.n[d] + 1);
-    hipLaunchKernelGGL(k_force<R>, dim3(grid1d(nf)), dim3(BLOCK), 0, c->stream, c->g, p,
-                       (const R*)c->chi[c->chi_cur], (const R*)sigma, (R*)force[d], d, nf);
+  const R* chi = (const R*)c->chi[c->chi_cur];
+  const int nx = c->grid.n[0], ny = c->grid.n[1], nz = c->grid.n[2];
+  if (c->grid.dim == 2) {
+    constexpr int TX = 64, TY = 8;
+    const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
+    hipLaunchKernelGGL((k_force<R, 2, TX, TY, 1>), dim3(tx * ty), dim3(TX * TY), 0, c->stream,
+                       c->g, p, chi, (const R*)sigma, (R*)force[0], (R*)force[1], (R*)nullptr,
+                       tx, ty);
+  } else {
+    constexpr int TX = 32, TY = 8, TZ = 2;
+    const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY, tz = (nz + TZ - 1) / TZ;
+    hipLaunchKernelGGL((k_force<R, 3, TX, TY, TZ>), dim3(tx * ty * tz), dim3(TX * TY * TZ), 0,
+                       c->stream, c->g, p, chi, (const R*)sigma, (R*)force[0], (R*)force[1],
+                       (R*)force[2], tx, ty);
   }
   return status_of_launch();
 }
@@ -1218,9 +1241,12 @@ int adjoint_step_impl(surf_ctx* c, const void* const* u, const void* F, const vo
   a.part = c->adj_part;
   a.dt = (R)c->dt;
   a.ncell = c->ncell;
-  unsigned nb = grid1d(c->ncell);
+  const dim3 agrid((c->grid.n[0] + ADJ_TX - 1) / ADJ_TX, (c->grid.n[1] + ADJ_TY - 1) / ADJ_TY,
+                   c->grid.n[2]);
+  const dim3 ablock(ADJ_TX * ADJ_TY);
+  const int nb = (int)(agrid.x * agrid.y * agrid.z);
   if (a.has_u) {
-    hipLaunchKernelGGL(k_adv_star<R>, dim3(nb), dim3(BLOCK), 0, c->stream, a);
+    hipLaunchKernelGGL(k_adv_star<R>, agrid, ablock, 0, c->stream, a);
   } else {
     size_t bytes = (size_t)c->ncell * sizeof(R);
     if (c->prm.bulk_enabled &&
@@ -1229,10 +1255,10 @@ int adjoint_step_impl(surf_ctx* c, const void* const* u, const void* F, const vo
     if (hipMemcpyAsync(c->adj[1], psi, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
       return SURF_EDEVICE;
   }
-  hipLaunchKernelGGL(k_adj_src<R>, dim3(nb), dim3(BLOCK), 0, c->stream, a);
-  hipLaunchKernelGGL(k_adj_adv<R>, dim3(nb), dim3(BLOCK), 0, c->stream, a);
+  hipLaunchKernelGGL(k_adj_src<R>, agrid, ablock, 0, c->stream, a);
+  hipLaunchKernelGGL(k_adj_adv<R>, agrid, ablock, 0, c->stream, a);
   hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(FIN_BLOCK), 0, c->stream,
-                     (const double*)c->adj_part, (int)nb, dtheta);
+                     (const double*)c->adj_part, nb, dtheta);
   return status_of_launch();
 }
 
@@ -1290,7 +1316,7 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
 
   if (params->adjoint) {
     b += 4 * align_up(n * es);
-    b += align_up((size_t)((n + BLOCK - 1) / BLOCK) * NADJ * sizeof(double));
+    b += align_up((size_t)adj_blocks(grid) * NADJ * sizeof(double));
   }
   if (params->interface == SURF_IFACE_ACDI) b += 3 * align_up(n * es);
   if (snapshot_needed(grid, params, nc3)) b += align_up(n * es);
@@ -1368,7 +1394,7 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
     if (params->adjoint) p += align_up(c->ncell * es);
   }
   c->adj_part = params->adjoint ? (double*)p : nullptr;
-  if (params->adjoint) p += align_up((size_t)((c->ncell + BLOCK - 1) / BLOCK) * NADJ * sizeof(double));
+  if (params->adjoint) p += align_up((size_t)adj_blocks(grid) * NADJ * sizeof(double));
   if (params->interface == SURF_IFACE_ACDI)
     for (int i = 0; i < 3; ++i) {
       c->acdi[i] = p;
@@ -1747,6 +1773,13 @@ int surf_set_dt(surf_ctx* c, double dt) {
   return SURF_OK;
 }
 
+int surf_set_time(surf_ctx* c, const double* time_dev) {
+  if (!c) return SURF_EINVAL;
+  if (c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
+  hipLaunchKernelGGL(k_set_time, dim3(1), dim3(64), 0, c->stream, c->state, time_dev);
+  return status_of_launch();
+}
+
 int surf_get_status(surf_ctx* c, uint32_t* bits) {
   if (!c || !bits) return SURF_EINVAL;
   double s = 0;
@@ -2005,6 +2038,7 @@ void batch_tables(surf_batch* b) {
     c.Po = a.Po;
     c.sig = a.sig;
     c.part = nullptr;
+    c.state = b->states + (size_t)i * NSTATE;
     c.dt = a.dt;
     c.area_dt = a.area_dt;
     c.r0 = 0.0;

@@ -48,6 +48,7 @@ struct ColArgs {
   R* Po;
   R* sig;           // may be nullptr
   double* part;     // [workgroups][NPART]
+  const double* state;  // running state: the time keys the FP32 stochastic rounding
   R dt;
   R area_dt;        // h dt: face length times the step
   double r0;        // axisymmetric: the radius of the low x side
@@ -144,7 +145,8 @@ struct ColAcc {
 template <typename R, int TY, bool HU, bool BULK, bool IX, bool IY, bool AXI, int LIM = 0,
           bool TR = false>
 __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, const int y0,
-                                           const int lane, ColAcc<R>& acc) {
+                                           const int lane, ColAcc<R>& acc, const unsigned tkey) {
+  constexpr bool SRND = sizeof(R) == 4;  // FP32: stochastically rounded state
   constexpr bool VAR = LIM != 0 || TR;
   constexpr int NR3 = TY + 6;  // state rows y0-3 .. y0+TY+2
   constexpr int NR1 = TY + 2;  // rows of the advected state y0-1 .. y0+TY
@@ -277,6 +279,9 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
   R pGyF = R(0), pGyP = R(0);  // advective flux through face s-1
   R pFs = R(0), pPs = R(0), pC = R(0), pPh = R(0), pDe = R(0), pIF = R(1), pIP = R(1);
   R pG = R(0);
+  // FP32: the old state and the advective increment of row s-1, added to
+  // the substep-2 increment in one stochastically rounded update
+  R pXF = R(0), pXP = R(0), pAF = R(0), pAP = R(0);
   R pAxF = R(0), pAxP = R(0);  // x part of the weighted divergence of row s-1
   R pWyF = R(0), pWyP = R(0);  // weighted flux through face s-1
   R pFxF = R(0), pFxP = R(0), pFxLF = R(0), pFxLP = R(0);  // advective x fluxes of row s-1
@@ -351,6 +356,7 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
       const bool grow = !IY && !py && (s < 0 || s >= ny);
       const R xF = rF[i - 2], xP = rP[i - 2];
       R Fs = xF, Ps = xP;
+      R aF = R(0), aP = R(0);  // FP32: the advective increments
       R fxF = R(0), fxP = R(0), fxLF = R(0), fxLP = R(0);
       R ux;
       if constexpr (TR) ux = rUxT[k1 + 1];
@@ -392,7 +398,17 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
         }
         fxLF = from_left(fxF);
         fxLP = from_left(fxP);
-        if constexpr (AXI) {
+        if constexpr (SRND) {
+          if constexpr (AXI) {
+            aF = -cfl * ((a_hi * fxF - a_lo * fxLF) + (nyF - gyF));
+            aP = -cfl * ((a_hi * fxP - a_lo * fxLP) + (nyP - gyP));
+          } else {
+            aF = -cfl * ((fxF - fxLF) + (nyF - gyF));
+            aP = -cfl * ((fxP - fxLP) + (nyP - gyP));
+          }
+          Fs = xF + aF;
+          Ps = xP + aP;
+        } else if constexpr (AXI) {
           Fs = xF - cfl * ((a_hi * fxF - a_lo * fxLF) + (nyF - gyF));
           Ps = xP - cfl * ((a_hi * fxP - a_lo * fxLP) + (nyP - gyP));
         } else {
@@ -441,8 +457,16 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
           // Langmuir k_a c (Gamma_inf delta - psi) - k_d psi; Henry drops the
           // psi in the adsorption term (kl = 0)
           const R q = BULK ? p.ka * pC * (p.ginf * pDe - kl * pPs) - p.kd * pPs : R(0);
-          const R Fn = BULK ? pFs + a.dt * (divF - q) : R(0);
-          const R Pn = pPs + a.dt * (divP + q);
+          R Fn, Pn;
+          if constexpr (SRND) {
+            // one random word per cell and step: 16 bits for each field
+            const unsigned rk = fmix32((unsigned)(nx * o + xs) ^ tkey);
+            Fn = BULK ? upd<R>(pXF, pAF + a.dt * (divF - q), rk) : R(0);
+            Pn = upd<R>(pXP, pAP + a.dt * (divP + q), rk >> 16);
+          } else {
+            Fn = BULK ? pFs + a.dt * (divF - q) : R(0);
+            Pn = pPs + a.dt * (divP + q);
+          }
           const R sg = eos<R>(quot<R>(Pn, pDe + p.eta_eps, pIP), p);
           const int row = nx * o * ES;
           if (BULK) gst(Fn, bFo, vxs, row);
@@ -487,6 +511,7 @@ __device__ __forceinline__ void col2d_wave(const ColArgs<R>& a, const int x0, co
         }
       }
       pFs = Fs; pPs = Ps; pC = cs; pG = Gs; pPh = ph; pDe = de; pIF = iF; pIP = iP;
+      if constexpr (SRND) { pXF = xF; pXP = xP; pAF = aF; pAP = aP; }
       pAxF = axF; pAxP = axP; pWyF = wyF; pWyP = wyP;
       pFxF = fxF; pFxP = fxP; pFxLF = fxLF; pFxLP = fxLP;
       pUx = ux; pUxL = uxL;
@@ -508,12 +533,13 @@ __global__ void __launch_bounds__(64 * COL_WAVES) k_col2d(ColArgs<R> a) {
   const int sx = wg / a.groups, cg = wg - sx * a.groups;
   const int x0 = sx * COL_OUT, y0 = (cg * COL_WAVES + wv) * TY;
   ColAcc<R> acc{0.0, 0.0, 0.0, 0.0, 0.0, R(0), R(-INFINITY), R(INFINITY), R(INFINITY), 0};
+  const unsigned tk = sizeof(R) == 4 ? step_key(a.state[S_TIME]) : 0u;
   if (y0 < ny) {  // chunks past the last row only join the reduction
     const bool ix = x0 >= 3 && x0 + 62 <= nx, iy = y0 >= 3 && y0 + TY + 3 <= ny;
-    if (ix && iy) col2d_wave<R, TY, HU, BULK, true, true, AXI, LIM, TR>(a, x0, y0, lane, acc);
-    else if (iy) col2d_wave<R, TY, HU, BULK, false, true, AXI, LIM, TR>(a, x0, y0, lane, acc);
-    else if (ix) col2d_wave<R, TY, HU, BULK, true, false, AXI, LIM, TR>(a, x0, y0, lane, acc);
-    else col2d_wave<R, TY, HU, BULK, false, false, AXI, LIM, TR>(a, x0, y0, lane, acc);
+    if (ix && iy) col2d_wave<R, TY, HU, BULK, true, true, AXI, LIM, TR>(a, x0, y0, lane, acc, tk);
+    else if (iy) col2d_wave<R, TY, HU, BULK, false, true, AXI, LIM, TR>(a, x0, y0, lane, acc, tk);
+    else if (ix) col2d_wave<R, TY, HU, BULK, true, false, AXI, LIM, TR>(a, x0, y0, lane, acc, tk);
+    else col2d_wave<R, TY, HU, BULK, false, false, AXI, LIM, TR>(a, x0, y0, lane, acc, tk);
   }
   double v[NPART];
   v[P_SUM_F] = acc.sF;
@@ -566,18 +592,19 @@ __global__ void __launch_bounds__(64 * COL_WAVES) k_batch_col2d(
     const int sx = wg / a.groups, cg = wg - sx * a.groups;
     const int x0 = sx * COL_OUT, y0 = (cg * COL_WAVES + wv) * TY;
     ColAcc<R> acc{0.0, 0.0, 0.0, 0.0, 0.0, R(0), R(-INFINITY), R(INFINITY), R(INFINITY), 0};
+    const unsigned tk = sizeof(R) == 4 ? step_key(a.state[S_TIME]) : 0u;
     if (y0 < ny) {
       const bool ix = x0 >= 3 && x0 + 62 <= nx, iy = y0 >= 3 && y0 + TY + 3 <= ny;
       if (a.p.bulk) {
-        if (ix && iy) col2d_wave<R, TY, false, true, true, true, false>(a, x0, y0, lane, acc);
-        else if (iy) col2d_wave<R, TY, false, true, false, true, false>(a, x0, y0, lane, acc);
-        else if (ix) col2d_wave<R, TY, false, true, true, false, false>(a, x0, y0, lane, acc);
-        else col2d_wave<R, TY, false, true, false, false, false>(a, x0, y0, lane, acc);
+        if (ix && iy) col2d_wave<R, TY, false, true, true, true, false>(a, x0, y0, lane, acc, tk);
+        else if (iy) col2d_wave<R, TY, false, true, false, true, false>(a, x0, y0, lane, acc, tk);
+        else if (ix) col2d_wave<R, TY, false, true, true, false, false>(a, x0, y0, lane, acc, tk);
+        else col2d_wave<R, TY, false, true, false, false, false>(a, x0, y0, lane, acc, tk);
       } else {
-        if (ix && iy) col2d_wave<R, TY, false, false, true, true, false>(a, x0, y0, lane, acc);
-        else if (iy) col2d_wave<R, TY, false, false, false, true, false>(a, x0, y0, lane, acc);
-        else if (ix) col2d_wave<R, TY, false, false, true, false, false>(a, x0, y0, lane, acc);
-        else col2d_wave<R, TY, false, false, false, false, false>(a, x0, y0, lane, acc);
+        if (ix && iy) col2d_wave<R, TY, false, false, true, true, false>(a, x0, y0, lane, acc, tk);
+        else if (iy) col2d_wave<R, TY, false, false, false, true, false>(a, x0, y0, lane, acc, tk);
+        else if (ix) col2d_wave<R, TY, false, false, true, false, false>(a, x0, y0, lane, acc, tk);
+        else col2d_wave<R, TY, false, false, false, false, false>(a, x0, y0, lane, acc, tk);
       }
     }
     double v[NPART];

@@ -53,6 +53,7 @@ struct Col3Args {
   R* Po;
   R* sig;
   double* part;
+  const double* state;  // running state: the time keys the FP32 stochastic rounding
   R dt;
   R area_dt;   // h^2 dt
   int strips;  // ceil(nx / 58)
@@ -68,7 +69,8 @@ struct Col3Args {
 template <typename R, int TZ, bool HU, bool BULK, bool IX, bool IY>
 __device__ __forceinline__ void col3d_wg(const Col3Args<R>& a, Col3Lds<R>& L, const int x0,
                                          const int y0, const int z0, const int lane,
-                                         const int wv, ColAcc<R>& acc) {
+                                         const int wv, ColAcc<R>& acc, const unsigned tkey) {
+  constexpr bool SRND = sizeof(R) == 4;  // FP32: stochastically rounded state
   R (&sXF)[C3_XI_ROWS][64] = L.xF;
   R (&sXP)[C3_XI_ROWS][64] = L.xP;
   R (&sPh)[C3_WAVES][64] = L.ph;
@@ -200,6 +202,9 @@ __device__ __forceinline__ void col3d_wg(const Col3Args<R>& a, Col3Lds<R>& L, co
   R gzF = R(0), gzP = R(0);       // advective z flux below plane s
   R pFs = R(0), pPs = R(0), pC = R(0), pG = R(0), pPh = R(0), pDe = R(0), pIF = R(1), pIP = R(1);
   R pDivF = R(0), pDivP = R(0);   // x + y weighted divergence of plane s-1
+  // FP32: the old state and the advective increment of plane s-1, added to
+  // the substep-2 increment in one stochastically rounded update
+  R pXF = R(0), pXP = R(0), pAF = R(0), pAP = R(0);
   R pWzF = R(0), pWzP = R(0);     // weighted flux through z face s-1
 
 #pragma unroll
@@ -241,6 +246,7 @@ __device__ __forceinline__ void col3d_wg(const Col3Args<R>& a, Col3Lds<R>& L, co
       }
       __syncthreads();
       R Fs = xF, Ps = xP;
+      R aF = R(0), aP = R(0);  // FP32: the advective increments
       R fxF = R(0), fxP = R(0), fxLF = R(0), fxLP = R(0);
       R fyLF = R(0), fyLP = R(0), fyHF = R(0), fyHP = R(0);
       const R ux = rUx[k1];
@@ -296,8 +302,15 @@ __device__ __forceinline__ void col3d_wg(const Col3Args<R>& a, Col3Lds<R>& L, co
           fyHP = gx ? R(0) : fyHP;
         }
         if (gz) { fyLF = R(0); fyLP = R(0); fyHF = R(0); fyHP = R(0); }
-        Fs = xF - cfl * (((fxF - fxLF) + (fyHF - fyLF)) + (nzF - gzF));
-        Ps = xP - cfl * (((fxP - fxLP) + (fyHP - fyLP)) + (nzP - gzP));
+        if constexpr (SRND) {
+          aF = -cfl * (((fxF - fxLF) + (fyHF - fyLF)) + (nzF - gzF));
+          aP = -cfl * (((fxP - fxLP) + (fyHP - fyLP)) + (nzP - gzP));
+          Fs = xF + aF;
+          Ps = xP + aP;
+        } else {
+          Fs = xF - cfl * (((fxF - fxLF) + (fyHF - fyLF)) + (nzF - gzF));
+          Ps = xP - cfl * (((fxP - fxLP) + (fyHP - fyLP)) + (nzP - gzP));
+        }
       }
       if constexpr (!IX) {
         Fs = gx ? R(0) : Fs;
@@ -369,8 +382,16 @@ __device__ __forceinline__ void col3d_wg(const Col3Args<R>& a, Col3Lds<R>& L, co
           const R divF = dcoef * (pDivF + (wzF - pWzF));
           const R divP = scoef * (pDivP + (wzP - pWzP));
           const R q = BULK ? p.ka * pC * (p.ginf * pDe - kl * pPs) - p.kd * pPs : R(0);
-          const R Fn = BULK ? pFs + a.dt * (divF - q) : R(0);
-          const R Pn = pPs + a.dt * (divP + q);
+          R Fn, Pn;
+          if constexpr (SRND) {
+            // one random word per cell and step: 16 bits for each field
+            const unsigned rk = fmix32((unsigned)(nx * (ny * o + ys) + xs) ^ tkey);
+            Fn = BULK ? upd<R>(pXF, pAF + a.dt * (divF - q), rk) : R(0);
+            Pn = upd<R>(pXP, pAP + a.dt * (divP + q), rk >> 16);
+          } else {
+            Fn = BULK ? pFs + a.dt * (divF - q) : R(0);
+            Pn = pPs + a.dt * (divP + q);
+          }
           const R sg = eos<R>(quot<R>(Pn, pDe + p.eta_eps, pIP), p);
           const int off = (nx * ny * o + nx * ys) * ES;
           if (BULK) gst(Fn, bFo, vxs, off);
@@ -389,6 +410,7 @@ __device__ __forceinline__ void col3d_wg(const Col3Args<R>& a, Col3Lds<R>& L, co
         }
       }
       pFs = Fs; pPs = Ps; pC = cs; pG = Gs; pPh = ph; pDe = de; pIF = iF; pIP = iP;
+      if constexpr (SRND) { pXF = xF; pXP = xP; pAF = aF; pAP = aP; }
       pDivF = axF + ayF; pDivP = axP + ayP; pWzF = wzF; pWzP = wzP;
     }
     gzF = nzF; gzP = nzP;
@@ -410,8 +432,9 @@ __global__ void __launch_bounds__(64 * C3_WAVES) k_col3d(Col3Args<R> a) {
   const int x0 = sx * COL_OUT, y0 = yb * C3_OUT_ROWS, z0 = zc * TZ;
   ColAcc<R> acc{0.0, 0.0, 0.0, 0.0, 0.0, R(0), R(-INFINITY), R(INFINITY), R(INFINITY), 0};
   const bool ix = x0 >= 3 && x0 + 62 <= nx, iy = y0 >= 3 && y0 + 17 <= ny;
-  if (ix && iy) col3d_wg<R, TZ, HU, BULK, true, true>(a, L, x0, y0, z0, lane, wv, acc);
-  else col3d_wg<R, TZ, HU, BULK, false, false>(a, L, x0, y0, z0, lane, wv, acc);
+  const unsigned tk = sizeof(R) == 4 ? step_key(a.state[S_TIME]) : 0u;
+  if (ix && iy) col3d_wg<R, TZ, HU, BULK, true, true>(a, L, x0, y0, z0, lane, wv, acc, tk);
+  else col3d_wg<R, TZ, HU, BULK, false, false>(a, L, x0, y0, z0, lane, wv, acc, tk);
   double v[NPART];
   v[P_SUM_F] = acc.sF;
   v[P_SUM_PSI] = acc.sP;

@@ -88,6 +88,47 @@ template <> __device__ __forceinline__ double rsqrt_<double>(double x) { return 
 template <typename R> __device__ __forceinline__ R rdiv(R a, R b) { return a * rrcp<R>(b); }
 template <> __device__ __forceinline__ double rdiv<double>(double a, double b) { return a / b; }
 
+// The 32-bit finalizer of MurmurHash3 (Appleby, public domain): a bijective
+// mix of the bits of x.
+__device__ __forceinline__ unsigned fmix32(unsigned x) {
+  x ^= x >> 16;
+  x *= 0x85ebca6bu;
+  x ^= x >> 13;
+  x *= 0xc2b2ae35u;
+  x ^= x >> 16;
+  return x;
+}
+
+// The key of a step: a mix of the bits of the running time the step starts
+// from (device state), so that every step draws other numbers and a run
+// replayed from the same state draws the same ones.
+__device__ __forceinline__ unsigned step_key(double t) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(t);
+  return fmix32((unsigned)b ^ fmix32((unsigned)(b >> 32)));
+}
+
+// The state update a + b stored in the context precision.  FP32 rounds
+// stochastically: the exact sum (two floats added in FP64) is raised by a
+// random fraction of an FP32 ulp (the 16 bits of r16 on the 29 bits below
+// the FP32 mantissa) and truncated, so that each of the two neighbouring
+// floats comes out with the probability of its closeness and the stored
+// state is unbiased.  Round-to-nearest drops every increment below half an
+// ulp, and a smooth field whose per-step changes are that small stops
+// evolving.  FP64 adds.
+template <typename R>
+__device__ __forceinline__ R upd(R a, R b, unsigned r16);
+template <>
+__device__ __forceinline__ float upd<float>(float a, float b, unsigned r16) {
+  const double x = (double)a + (double)b;
+  unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  u = (u + ((unsigned long long)(r16 & 0xffffu) << 13)) & ~0x1fffffffull;
+  return (float)__longlong_as_double((long long)u);
+}
+template <>
+__device__ __forceinline__ double upd<double>(double a, double b, unsigned) {
+  return a + b;
+}
+
 // phi = 1/(1+e^{chi/eps}) (0 in fluid 1, 1 in the liquid), omega = 1 - phi
 // evaluated without cancellation, delta = phi omega / eps.
 template <typename R>

@@ -553,62 +553,125 @@ __global__ void k_reset_state(double* state) {
   if (threadIdx.x < NSTATE) state[threadIdx.x] = 0.0;
 }
 
-// ---------------------------------------------------------------- force
-template <typename R>
-__device__ __forceinline__ void face_grad(const Grid& g, const Par<R>& p, const R* __restrict__ v,
-                                          int d, const int* cL, const int* cR, long long L,
-                                          long long Rr, R* out) {
-  for (int e = 0; e < g.dim; ++e) {
-    if (e == d) {
-      out[e] = (v[Rr] - v[L]) * p.inv_h;
-    } else {
-      int a[3] = {cL[0], cL[1], cL[2]}, b[3] = {cL[0], cL[1], cL[2]};
-      a[e] = map_axis(cL[e] + 1, g.n[e], g.bc[e][0], g.bc[e][1]);
-      b[e] = map_axis(cL[e] - 1, g.n[e], g.bc[e][0], g.bc[e][1]);
-      R tl = v[cell_index(g, a[0], a[1], a[2])] - v[cell_index(g, b[0], b[1], b[2])];
-      int c[3] = {cR[0], cR[1], cR[2]}, dd[3] = {cR[0], cR[1], cR[2]};
-      c[e] = map_axis(cR[e] + 1, g.n[e], g.bc[e][0], g.bc[e][1]);
-      dd[e] = map_axis(cR[e] - 1, g.n[e], g.bc[e][0], g.bc[e][1]);
-      R tr = v[cell_index(g, c[0], c[1], c[2])] - v[cell_index(g, dd[0], dd[1], dd[2])];
-      out[e] = (tl + tr) * (R(0.25) * p.inv_h);
-    }
-  }
+// the running time from a device value (0 without one)
+__global__ void k_set_time(double* state, const double* t) {
+  if (threadIdx.x == 0) state[S_TIME] = t ? *t : 0.0;
 }
 
-template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_force(Grid g, Par<R> p, const R* __restrict__ chi,
-                                                 const R* __restrict__ sig, R* __restrict__ out,
-                                                 int d, long long nface) {
-  long long fi = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  if (fi >= nface) return;
-  int m[3] = {g.n[0], g.n[1], g.n[2]};
-  m[d] += 1;
-  int c[3] = {(int)(fi % m[0]), (int)((fi / m[0]) % m[1]), (int)(fi / ((long long)m[0] * m[1]))};
-  int fd = c[d], nd = g.n[d];
-  if ((fd == 0 || fd == nd) && g.bc[d][fd == nd] != BC_PERIODIC) {
-    out[fi] = R(0);
-    return;
-  }
-  int cR[3] = {c[0], c[1], c[2]};
-  if (fd == nd) cR[d] = 0;
-  int cL[3] = {cR[0], cR[1], cR[2]};
-  cL[d] = cR[d] - 1 < 0 ? nd - 1 : cR[d] - 1;
-  long long Rr = cell_index(g, cR[0], cR[1], cR[2]);
-  long long L = cell_index(g, cL[0], cL[1], cL[2]);
+// ---------------------------------------------------------------- force
+// Marangoni face force (section 2.4), F_d = dbar (grad sigma - n (n . grad
+// sigma))_d on every face, n = grad chi / max(|grad chi|, 1e-6); the face
+// gradient of a cell field takes the compact difference across the face for
+// its normal component and the centred transverse differences of the two
+// cells, averaged, for the others; dbar is the mean delta of the two cells.
+//
+// Work unit: a tile of TX x TY (x TZ) cells, one thread per cell; chi, sigma
+// and delta of the tile and a one-cell halo (corners included: the
+// transverse differences of the cell across the face) are staged in LDS,
+// with mirrored ghosts at walls and open sides and wrapped ones on periodic
+// axes.  Each thread writes the low face of its cell along every axis; the
+// last cell along an axis also writes the high face (zero on a wall or open
+// side, on a periodic axis the value of face 0, computed from the same two
+// cells in the same order).  Tile and cell indices are 32-bit (no 64-bit
+// division).
+template <typename R, int DIM, int TX, int TY, int TZ>
+struct ForceLds {
+  static constexpr int HX = TX + 2, HY = TY + 2, HZ = DIM == 3 ? TZ + 2 : 1;
+  R chi[HZ][HY][HX], sig[HZ][HY][HX], del[HZ][HY][HX];
+};
+
+template <typename R, int DIM, int TX, int TY, int TZ>
+__device__ __forceinline__ R force_face(const ForceLds<R, DIM, TX, TY, TZ>& L, const Par<R>& p,
+                                        const int d, const int lx, const int ly, const int lz) {
+  // cells L (low side) and R (high side) of the face along d, in LDS coordinates
+  int rl[3] = {lx, ly, lz};
+  int ll[3] = {lx, ly, lz};
+  ll[d] -= 1;
   R gn[3] = {R(0), R(0), R(0)}, gs[3] = {R(0), R(0), R(0)};
-  face_grad<R>(g, p, chi, d, cL, cR, L, Rr, gn);
-  face_grad<R>(g, p, sig, d, cL, cR, L, Rr, gs);
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) {
+    if (e == d) {
+      gn[e] = (L.chi[rl[2]][rl[1]][rl[0]] - L.chi[ll[2]][ll[1]][ll[0]]) / p.h;
+      gs[e] = (L.sig[rl[2]][rl[1]][rl[0]] - L.sig[ll[2]][ll[1]][ll[0]]) / p.h;
+    } else {
+      int a[3] = {ll[0], ll[1], ll[2]}, b[3] = {ll[0], ll[1], ll[2]};
+      int c[3] = {rl[0], rl[1], rl[2]}, q[3] = {rl[0], rl[1], rl[2]};
+      a[e] += 1;
+      b[e] -= 1;
+      c[e] += 1;
+      q[e] -= 1;
+      const R tln = L.chi[a[2]][a[1]][a[0]] - L.chi[b[2]][b[1]][b[0]];
+      const R trn = L.chi[c[2]][c[1]][c[0]] - L.chi[q[2]][q[1]][q[0]];
+      const R tls = L.sig[a[2]][a[1]][a[0]] - L.sig[b[2]][b[1]][b[0]];
+      const R trs = L.sig[c[2]][c[1]][c[0]] - L.sig[q[2]][q[1]][q[0]];
+      gn[e] = (tln + trn) / (R(4) * p.h);
+      gs[e] = (tls + trs) / (R(4) * p.h);
+    }
+  }
   R nrm = R(0);
-  for (int e = 0; e < g.dim; ++e) nrm += gn[e] * gn[e];
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) nrm += gn[e] * gn[e];
   nrm = rsqrt_<R>(nrm);
   nrm = nrm < R(1e-6) ? R(1e-6) : nrm;
   R ndot = R(0);
-  for (int e = 0; e < g.dim; ++e) ndot += gn[e] / nrm * gs[e];
-  R phL, omL, deL, phR, omR, deR;
-  phase<R>(chi[L], p, phL, omL, deL);
-  phase<R>(chi[Rr], p, phR, omR, deR);
-  R dbar = R(0.5) * (deL + deR);
-  out[fi] = dbar * (gs[d] - gn[d] / nrm * ndot);
+#pragma unroll
+  for (int e = 0; e < DIM; ++e) ndot += gn[e] / nrm * gs[e];
+  const R dbar = R(0.5) * (L.del[ll[2]][ll[1]][ll[0]] + L.del[rl[2]][rl[1]][rl[0]]);
+  return dbar * (gs[d] - gn[d] / nrm * ndot);
+}
+
+template <typename R, int DIM, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(TX * TY * TZ) k_force(Grid g, Par<R> p,
+                                                        const R* __restrict__ chi,
+                                                        const R* __restrict__ sig,
+                                                        R* __restrict__ fx, R* __restrict__ fy,
+                                                        R* __restrict__ fz, int tiles_x,
+                                                        int tiles_y) {
+  using Lds = ForceLds<R, DIM, TX, TY, TZ>;
+  constexpr int NT = TX * TY * TZ, HX = Lds::HX, HY = Lds::HY, HZ = Lds::HZ;
+  __shared__ Lds L;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int b = blockIdx.x;
+  const int bx = b % tiles_x, r = b / tiles_x;
+  const int by = r % tiles_y, bz = r / tiles_y;
+  const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+  for (int l = threadIdx.x; l < HX * HY * HZ; l += NT) {
+    const int lx = l % HX, ly = (l / HX) % HY, lz = l / (HX * HY);
+    const int gx = map_axis(x0 - 1 + lx, nx, g.bc[0][0], g.bc[0][1]);
+    const int gy = map_axis(y0 - 1 + ly, ny, g.bc[1][0], g.bc[1][1]);
+    const int gz = DIM == 3 ? map_axis(z0 - 1 + lz, nz, g.bc[2][0], g.bc[2][1]) : 0;
+    const long long ci = cell_index(g, gx, gy, gz);
+    const R c = chi[ci];
+    R ph, om, de;
+    phase<R>(c, p, ph, om, de);
+    L.chi[lz][ly][lx] = c;
+    L.sig[lz][ly][lx] = sig[ci];
+    L.del[lz][ly][lx] = de;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = threadIdx.x / (TX * TY);
+  const int cx = x0 + tx, cy = y0 + ty, cz = z0 + tz;
+  if (cx >= nx || cy >= ny || cz >= nz) return;
+  const int lx = tx + 1, ly = ty + 1, lz = DIM == 3 ? tz + 1 : 0;
+  const int cc[3] = {cx, cy, cz};
+  R* const out[3] = {fx, fy, fz};
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const bool per = g.bc[d][0] == BC_PERIODIC;
+    const int nd = g.n[d];
+    int fi[3] = {cx, cy, cz};
+    // low face of the cell
+    R v = (cc[d] == 0 && !per) ? R(0) : force_face<R, DIM, TX, TY, TZ>(L, p, d, lx, ly, lz);
+    out[d][face_index(g, d, fi[0], fi[1], fi[2])] = v;
+    if (cc[d] == nd - 1) {
+      // high face: the face between this cell and the next one along d
+      int hl[3] = {lx, ly, lz};
+      hl[d] += 1;
+      R w = per ? force_face<R, DIM, TX, TY, TZ>(L, p, d, hl[0], hl[1], hl[2]) : R(0);
+      fi[d] = nd;
+      out[d][face_index(g, d, fi[0], fi[1], fi[2])] = w;
+    }
+  }
 }
 
 }  // namespace surf

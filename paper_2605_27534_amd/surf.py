@@ -42,7 +42,7 @@ EXPORTS = [
     "surf_adjoint_seed", "surf_adjoint_step", "surf_adjoint_c0",
     "surf_batch_workspace_bytes", "surf_batch_create", "surf_batch_set_geometry",
     "surf_batch_init_state", "surf_batch_step", "surf_batch_parity", "surf_batch_tune",
-    "surf_batch_destroy", "surf_step_static",
+    "surf_batch_destroy", "surf_step_static", "surf_set_time",
 ]
 
 
@@ -104,6 +104,7 @@ def lib():
         L.surf_time_transport.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_double)]
         L.surf_set_dt.argtypes = [vp, ctypes.c_double]
+        L.surf_set_time.argtypes = [vp, vp]
         L.surf_get_status.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
         L.surf_clear_status.argtypes = [vp]
         L.surf_time_solver.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double)]
@@ -306,9 +307,10 @@ class Surf:
                     "surf_time_transport")
         return ms.value
 
-    def force(self, sigma):
-        out = [torch.empty(self.face_shape(d), dtype=self.dtype, device=self.device)
-               for d in range(self.dim)]
+    def force(self, sigma, out=None):
+        if out is None:
+            out = [torch.empty(self.face_shape(d), dtype=self.dtype, device=self.device)
+                   for d in range(self.dim)]
         arr = (ctypes.c_void_p * 3)(*[out[d].data_ptr() if d < self.dim else None
                                       for d in range(3)])
         self._check(self.L.surf_force(self.ctx, _ptr(self._cell(sigma, "sigma")), arr),
@@ -331,6 +333,12 @@ class Surf:
 
     def set_dt(self, dt):
         self._check(self.L.surf_set_dt(self.ctx, float(dt)), "surf_set_dt")
+
+    def set_time(self, t=None):
+        """Running time from a one-element float64 device tensor (None: 0)."""
+        if t is not None and (t.dtype != torch.float64 or t.device != self.device):
+            raise ValueError("time: a float64 device tensor")
+        self._check(self.L.surf_set_time(self.ctx, _ptr(t)), "surf_set_time")
 
     def status(self):
         b = ctypes.c_uint32(0)

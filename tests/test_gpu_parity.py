@@ -220,7 +220,7 @@ def test_force_parity(prec, dim):
     s.set_levelset(s.tensor(chi))
     fg = s.force(s.tensor(sig))
     for d in range(dim):
-        assert rel_max(fg[d].double().cpu().numpy(), fo[d]) <= TOL[prec] * 5, d
+        assert rel_max(fg[d].double().cpu().numpy(), fo[d]) <= TOL[prec], (d, rel_max(fg[d].double().cpu().numpy(), fo[d]))
 
 
 def test_deterministic_bitwise():

@@ -180,6 +180,7 @@ def test_pipelined_graph_replays():
     # the level set and state after K0 steps, to restart each replay from
     chi0 = r.s.levelset().clone()
     F0, P0 = [x.clone() for x in r.bufs[K0 % 2]]
+    t0 = r.hist[K0 - 1, S.T_T:S.T_T + 1].clone()  # the running time after K0 steps
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=r.main):
         r.steps(K0, K0 + K, pipelined=True)
@@ -187,9 +188,11 @@ def test_pipelined_graph_replays():
     for rep in range(3):
         with torch.cuda.stream(r.main):
             r.s.set_levelset(chi0)
-            # the replay starts from the level set after K0 steps; the
-            # context's running time and totals restart with it
+            # the replay starts from the level set, the state and the running
+            # time after K0 steps (the time keys the FP32 stochastic
+            # rounding); the cumulative totals restart
             r.s.init_state(r.c0, 1.0, 0.3)
+            r.s.set_time(t0)
             r.bufs[K0 % 2][0].copy_(F0)
             r.bufs[K0 % 2][1].copy_(P0)
             r.hist.zero_()
