@@ -19,6 +19,9 @@ host (`cpu_baseline`).
 Other workloads (one JSON line each, not the default):
   c2  the 256^3 translating sphere (inputs generated on the GPU, all steps
       resident before the timed region);
+  c2a the sphere of c2 on the ACDI interface (phi advanced by ACDI, each
+      next ACDI step prepared during the transport, re-initialized from the
+      VoF every 50 steps; the ACDI bound sets dt = 3.5e-4);
   c3  the 64-instance ensemble in the batched form (one persistent launch
       per step, HIP-graph replay), against the same instances stepped one by
       one with the plain path;
@@ -54,7 +57,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c1",
-                    choices=["c0", "c1", "c1i", "c1a", "c1f", "c1m", "c1v", "c2", "c2x", "c3", "c4"])
+                    choices=["c0", "c1", "c1i", "c1a", "c1f", "c1m", "c1v", "c2", "c2a", "c2x", "c3",
+                             "c4"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--implicit-graph", action="store_true",
@@ -85,6 +89,8 @@ def workload(name, K, W):
         return C.c1_variants()
     if name == "c2x":
         return C.c2_axisymmetric()
+    if name == "c2a":
+        return C.c2_acdi()
     return C.c2_translating_sphere()
 
 
@@ -261,7 +267,7 @@ def main():
                      and not args.no_pipeline and not reinit)
         # ACDI: each next ACDI step is prepared on `aux` during the transport
         # (steps that re-initialize from a VoF field run it in the step)
-        pipelined_acdi = (bool(reinit) and prob["dim"] == 2 and prob.get("flux_form", 0) == 0
+        pipelined_acdi = (bool(reinit) and prob.get("flux_form", 0) == 0
                           and not args.no_pipeline)
         aux = torch.cuda.Stream(dev)
 
@@ -321,7 +327,10 @@ def main():
             u = u_list[W + K - 1] if u_list is not None else u_static
             burst_ms = s.time_transport(a[0], a[1], b[0], b[1], u=u, sigma_out=sig,
                                         reps=burst_reps)
-        acdi_ms = s.time_acdi(u=u_static, reps=200) if reinit else None
+        acdi_ms, acdi_reps = None, 200 if ncell <= (1 << 22) else 40
+        if reinit:
+            acdi_ms = s.time_acdi(u=u_static if u_list is None else u_list[W + K - 1],
+                                  reps=acdi_reps)
         # the Marangoni face force (surf_force) on the last step's sigma, a
         # burst of back-to-back calls between HIP events
         mforce_ms = None
@@ -405,7 +414,7 @@ def main():
         out["config"]["acdi_reinit_every"] = reinit
         out["acdi"] = {
             "kernels": "k_acdi_adv + k_acdi_reg", "avg_step_us": round(acdi_ms * 1e3, 3),
-            "timing": "200 back-to-back ACDI steps between HIP events",
+            "timing": "%d back-to-back ACDI steps between HIP events" % acdi_reps,
             "bytes_per_cell": ab, "achieved": round(ab * ncell / (acdi_ms * 1e-3) / 1e9, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ab * ncell / (acdi_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}

@@ -289,8 +289,8 @@ int surf_step(surf_ctx* ctx, const void* vof_next, const void* const* u,
  * state, force and adjoint calls return SURF_ESTATE. */
 int surf_prepare_geometry(surf_ctx* ctx, const void* vof_next, void* aux_stream);
 
-/* Pipelined ACDI interface (section 2.5, the Phase-Field method; 2D, weighted
- * flux form, explicit substep 2).  A step's ACDI step (the advection of phi
+/* Pipelined ACDI interface (section 2.5, the Phase-Field method; 2D or 3D,
+ * weighted flux form, explicit substep 2).  A step's ACDI step (the advection of phi
  * by u and the regularization, then chi = -s(phi)) depends only on phi and
  * u, not on the transported state, so it can run while the previous step's
  * transport runs.  This call enqueues it on aux_stream (a HIP stream other
@@ -302,8 +302,8 @@ int surf_prepare_geometry(surf_ctx* ctx, const void* vof_next, void* aux_stream)
  * field are not prepared.
  *   u  the face velocities of that step (as in surf_step; NULL for no flow),
  *      ready with respect to aux_stream and unchanged until that surf_step.
- * Errors: SURF_EINVAL for a context without ACDI, a 3D grid, the paper flux
- * form or the implicit substep, a null aux_stream or u[1] missing;
+ * Errors: SURF_EINVAL for a context without ACDI, the paper flux form or
+ * the implicit substep, a null aux_stream or u[1] (3D: u[2]) missing;
  * SURF_ESTATE without a level set or with a prepare still pending.  While
  * one is pending only surf_step (as above), surf_set_dt with the dt the
  * prepared step took (any other dt returns SURF_ESTATE: the phase field has

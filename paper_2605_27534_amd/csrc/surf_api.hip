@@ -897,8 +897,15 @@ int step_impl(surf_ctx* c, const void* const* u, const void* F_in, const void* p
               void* F_out, void* psi_out, void* sigma_out, double* totals) {
   if (c->grid.dim == 2)
     return step2d_impl<R>(c, nullptr, u, F_in, psi_in, F_out, psi_out, sigma_out, totals);
-  c->pre_valid = false;  // this transport reads chi[chi_cur] itself
   materialize<R>(c);
+  if (c->ev_pre && c->prm.interface == SURF_IFACE_ACDI && c->c3_nwg > 0) {
+    // an ACDI step prepared next writes only the other level-set buffer: it
+    // may start once the transports before this one are done
+    if (hipEventRecord(c->ev_pre, c->stream) != hipSuccess) return SURF_EDEVICE;
+    c->pre_valid = true;
+  } else {
+    c->pre_valid = false;  // this transport reads chi[chi_cur] itself
+  }
   if (c->c3_nwg > 0) {
     // weighted form in 3D: plane-marching transport, then the reduction
     {
@@ -1663,9 +1670,10 @@ int surf_time_solver(surf_ctx* c, int32_t field, int32_t reps, double* ms_per_la
 
 int surf_prepare_phase(surf_ctx* c, const void* const* u, void* aux_stream) {
   if (!c || !aux_stream) return SURF_EINVAL;
-  if (c->prm.interface != SURF_IFACE_ACDI || c->grid.dim != 2 || c->col_nwg == 0 ||
-      c->prm.substep2 != SURF_SUBSTEP2_EXPLICIT)
+  if (c->prm.interface != SURF_IFACE_ACDI || c->prm.substep2 != SURF_SUBSTEP2_EXPLICIT ||
+      !((c->grid.dim == 2 && c->col_nwg > 0) || (c->grid.dim == 3 && c->c3_nwg > 0)))
     return SURF_EINVAL;
+  if (c->grid.dim == 3 && u && u[0] && !u[2]) return SURF_EINVAL;
   if (u && u[0] && !u[1]) return SURF_EINVAL;
   if (!c->has_chi || c->prepared) return SURF_ESTATE;
   if (!c->ev_pre) {

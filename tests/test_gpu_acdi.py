@@ -277,6 +277,63 @@ def test_pipelined_acdi_equals_serial(prec):
             assert torch.equal(a, b), graph
 
 
+@pytest.mark.parametrize("prec", [F64, F32])
+def test_pipelined_acdi_3d_equals_serial(prec):
+    # the same in 3D: a sphere carried by the Hadamard-Rybczynski flow on a
+    # ragged 70 x 48 x 40 grid, open x and y, periodic z, 7 steps with a
+    # re-initialization at step 3; eager and from a captured graph
+    import torch
+    n = (70, 48, 40)
+    h = 1.0 / 70
+    cen = (0.5, 0.35, 0.3)
+    u = synth.u_hadamard(n, h, cen, 0.15, -0.4, 0.01, frame_shift=0.4, period_z=40 * h)
+    dt = 0.1 * h * h / 1e-2
+    prob = dict(dim=3, n=n, h=h, bc=((2, 2), (2, 2), (1, 1)), eos=1, eos_E=0.3, interface=1,
+                acdi_zeta=1.1 * max_speed(u))
+    vof = lambda k: synth.vof_ball(n, h, (cen[0], cen[1], cen[2] + 0.4 * k * dt), 0.15, 3,
+                                   period_z=40 * h)
+
+    def run(pipelined, graph):
+        main, aux = torch.cuda.Stream(), torch.cuda.Stream()
+        with torch.cuda.stream(main):
+            s = S.Surf(prob, dt, prec)
+            T = s.tensor
+            s.set_geometry(T(vof(0)), full=True)
+            F, P = s.init_state(T(synth.uniform_field(n, 3, 0.8, 1.2)), 1.0, 0.4)
+            ud = [T(x) for x in u]
+            vofs = {3: T(vof(3))}
+            bufs = [[F, P], [s.empty(), s.empty()]]
+            sig = s.empty()
+            hist = torch.zeros((7, 16), dtype=torch.float64, device="cuda")
+
+            def steps(k0, k1):
+                for k in range(k0, k1):
+                    a, b = bufs[k % 2], bufs[(k + 1) % 2]
+                    s.step(a[0], a[1], b[0], b[1], u=ud, vof_next=vofs.get(k), sigma_out=sig,
+                           totals=hist[k])
+                    if pipelined and k + 1 < k1 and (k + 1) not in vofs:
+                        s.prepare_phase(ud, aux)
+
+            if graph:
+                steps(0, 1)
+                torch.cuda.synchronize()
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=main):
+                    steps(1, 7)
+                g.replay()
+            else:
+                steps(0, 7)
+            torch.cuda.synchronize()
+        last = bufs[7 % 2]
+        return [x.clone() for x in (last[0], last[1], sig, s.phase(), s.levelset(), hist)]
+
+    ref = run(False, False)
+    for graph in (False, True):
+        got = run(True, graph)
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), graph
+
+
 def test_prepare_phase_call_order():
     import torch
     n = (64, 48)
