@@ -253,8 +253,9 @@ def test_advection_variant_validation():
 
 
 def test_prepare_phase_validation():
-    """surf_prepare_phase: ACDI contexts on the 2D weighted-form path only,
-    and a level set first; checked before any device work."""
+    """surf_prepare_phase: ACDI contexts on the weighted-form explicit path
+    (2D or 3D), every velocity component, and a level set first; checked
+    before any device work."""
     import ctypes
     from paper_2605_27534_amd import surf as S
     L = S.lib()
@@ -278,8 +279,14 @@ def test_prepare_phase_validation():
     half = (ctypes.c_void_p * 3)(base, None, None)
     assert L.surf_prepare_phase(ctx, half, fake_stream) == -1
     assert L.surf_destroy(ctx) == 0
-    for bad in (dict(interface=0), dict(flux_form=1),
-                dict(dim=3, n=(16, 16, 16), bc=((0, 0), (0, 0), (0, 0)))):
+    cube = dict(dim=3, n=(16, 16, 16), bc=((0, 0), (0, 0), (0, 0)))
+    ctx, buf, base = ctx_of(dict(acdi, **cube))
+    assert L.surf_prepare_phase(ctx, None, fake_stream) == -4  # no level set yet
+    two = (ctypes.c_void_p * 3)(base, base, None)
+    assert L.surf_prepare_phase(ctx, two, fake_stream) == -1  # no z velocity
+    assert L.surf_destroy(ctx) == 0
+    for bad in (dict(interface=0), dict(flux_form=1), dict(cube, flux_form=1),
+                dict(substep2=1)):
         ctx, buf, base = ctx_of(dict(acdi, **bad))
         assert L.surf_prepare_phase(ctx, None, fake_stream) == -1, bad
         assert L.surf_destroy(ctx) == 0
