@@ -49,6 +49,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector issue peak in VALU lane operations per second: 157.3 TFLOP/s
+# (256 CUs at 2.4 GHz) counts an FMA as two flops; one lane of one VALU
+# instruction is one lane operation
+VALU_PEAK_LANE_OPS = 157.3e12 / 2
 
 
 def parse():
@@ -122,8 +126,11 @@ def algorithmic_bytes(cfg, es):
 # workload, the file and the sources of the kernel they were taken on
 TRAFFIC = {
     "expanding circle 1024^2 fp32 soluble": (
-        "k_col2d_expanding_circle_1024_traffic.md",
+        "k_col2d_expanding_circle_1024_counters.md",
         ("surf_common.hpp", "surf_kernels.hpp", "surf_col2d.hpp")),
+    "translating sphere 256^3 fp32": (
+        "k_col3d_translating_sphere_256_counters.md",
+        ("surf_common.hpp", "surf_kernels.hpp", "surf_col2d.hpp", "surf_col3d.hpp")),
     "expanding circle 1024^2 fp32 soluble implicit": (
         "k_cg_iter_expanding_circle_implicit_1024_traffic.md",
         ("surf_common.hpp", "surf_kernels.hpp", "surf_col2d.hpp", "surf_implicit.hpp")),
@@ -139,12 +146,70 @@ def kernel_source_digest(sources):
     return hs.hexdigest()[:16]
 
 
+# the same for the Marangoni face force (surf_force)
+FORCE_COUNTERS = {
+    "expanding circle 1024^2 fp32 soluble": (
+        "k_force_expanding_circle_1024_counters.md", ("surf_common.hpp", "surf_kernels.hpp")),
+    "translating sphere 256^3 fp32": (
+        "k_force_translating_sphere_256_counters.md", ("surf_common.hpp", "surf_kernels.hpp")),
+}
+
 # the same for the interfacial-force kernel of the c1f workload
 IFACE_TRAFFIC = {
     "expanding circle 1024^2 fp32 soluble forces": (
         "k_iface_force_expanding_circle_forces_1024_traffic.md",
         ("surf_common.hpp", "surf_kernels.hpp", "surf_capillary.hpp")),
 }
+
+
+def kernel_counters(workload_name, table=None):
+    """The machine-readable fields of the committed rocprofv3 counter summary
+    of the workload's dominant kernel (or of the kernel `table` covers), or
+    {} when there is none for this workload or the kernel source changed
+    since the counters were taken."""
+    table = TRAFFIC if table is None else table
+    if workload_name not in table:
+        return {}
+    fname, sources = table[workload_name]
+    try:
+        txt = open(os.path.join(ROOT, "profiles", fname)).read()
+    except OSError:
+        return {}
+    kv = {}
+    for line in txt.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            kv[k.strip()] = v.strip().strip("`")
+    if (kv.get("workload") != workload_name
+            or kv.get("kernel_source_digest") != kernel_source_digest(sources)):
+        return {}
+    return kv
+
+
+def roofline_of(kernel, alg_bytes, launch_ms, ctr):
+    """The roofline of one launch: the algorithmic bytes against 8 TB/s, and,
+    with a counter summary, the counted VALU lane operations against the
+    FP32 vector issue peak; the larger of the two floors (the time each
+    would take at its peak) names the bound.  Without counters the bound is
+    the HBM one."""
+    t = launch_ms * 1e-3
+    hbm_ach = alg_bytes / t / 1e9
+    hbm = {"achieved": round(hbm_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(hbm_ach / HBM_PEAK_GBS, 4)}
+    traffic = float(ctr["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in ctr else None
+    out = {"bound": "hbm", "kernel": kernel, **hbm, "traffic": traffic}
+    if "valu_insts_per_launch" in ctr:
+        lane_ops = float(ctr["valu_insts_per_launch"]) * 64
+        v_ach = lane_ops / t / 1e12
+        valu = {"achieved": round(v_ach, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2),
+                "unit": "Tlane-op/s", "frac": round(v_ach * 1e12 / VALU_PEAK_LANE_OPS, 4),
+                "lane_ops_per_launch": lane_ops}
+        if lane_ops / VALU_PEAK_LANE_OPS > alg_bytes / (HBM_PEAK_GBS * 1e9):
+            out.update({"bound": "alu", "achieved": valu["achieved"], "peak": valu["peak"],
+                        "unit": valu["unit"], "frac": valu["frac"]})
+        out["hbm"] = hbm
+        out["valu"] = valu
+    return out
 
 
 def measured_traffic(workload_name, table=None):
@@ -363,12 +428,10 @@ def main():
             force_ms = e0.elapsed_time(e1) / FORCE_REPS
 
     ms_per_step = ms_total / K
-    traffic = measured_traffic(cfg["name"])
     value = ncell * K / (ms_total * 1e-3) / 1e9
     kbytes, sbytes = algorithmic_bytes(cfg, es)
     k_step_ms = step_ms / max(step_n, 1)
     k_avg_ms = burst_ms if burst_ms is not None else k_step_ms
-    achieved = kbytes * ncell / (k_avg_ms * 1e-3) / 1e9
     step_gbs = sbytes * ncell / (ms_per_step * 1e-3) / 1e9
     out = {
         "metric": "surfactant-step Gcell-updates/s (+ % HBM roofline)",
@@ -388,9 +451,8 @@ def main():
                    "graph": graph is not None,
                    "pipelined_geometry": pipelined or pipelined_acdi},
         "roofline": {
-            "bound": "hbm", "kernel": transport_kernel(cfg),
-            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            **roofline_of(transport_kernel(cfg), kbytes * ncell, k_avg_ms,
+                          kernel_counters(cfg["name"])),
             "bytes_per_cell": kbytes, "avg_launch_us": round(k_avg_ms * 1e3, 3),
             "launch_timing": ("%d back-to-back launches between HIP events" % burst_reps
                               if burst_ms is not None else "HIP events around each launch"),
@@ -403,12 +465,12 @@ def main():
     }
     if mforce_ms is not None:
         fbpc = (2 + prob["dim"]) * es  # reads chi, sigma; writes the dim face arrays
-        fach = fbpc * ncell / (mforce_ms * 1e-3) / 1e9
         out["force"] = {
-            "kernel": "k_force", "avg_launch_us": round(mforce_ms * 1e3, 3),
+            **roofline_of("k_force", fbpc * ncell, mforce_ms,
+                          kernel_counters(cfg["name"], FORCE_COUNTERS)),
+            "avg_launch_us": round(mforce_ms * 1e3, 3),
             "timing": "back-to-back surf_force calls between HIP events",
-            "bytes_per_cell": fbpc, "achieved": round(fach, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(fach / HBM_PEAK_GBS, 4)}
+            "bytes_per_cell": fbpc}
     if acdi_ms is not None:
         ab = ACDI_WORDS_PER_CELL * es
         out["config"]["acdi_reinit_every"] = reinit
