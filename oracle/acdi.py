@@ -41,7 +41,11 @@ HIP library's readings too):
 * the level set the surfactant transport sees: chi = -s(phi), clamped to
   |chi| <= chi_max (the transport's own phi of it is then (phi + ve)/(1 + 2 ve));
 * re-initialization from a VoF field: the warm-started level set (hj sweeps
-  from the current chi), then phi from it.
+  from the current chi), then phi from it;
+* on axisymmetric rings (Appendix B) the fluxes are the same expressions in
+  (r, z) (the azimuthal component vanishes by symmetry), and the balance of
+  ring i, divided by its volume 2 pi r_i h^2, takes a radial face's flux
+  with the weight r_face / r_i, as the surfactant fields do.
 """
 from __future__ import annotations
 
@@ -140,7 +144,14 @@ def regularize(prob, phi, dt, zeta, vareps=VAREPS):
             sl = [slice(None)] * 3
             sl[2 - d] = slice(0, 1)
             Glo[tuple(sl)] = 0.0  # the low side of the box
-        div = div + (G[d] - Glo)
+        if q["axisym"] and d == 0:
+            # ring i between r_lo = r0 + i h and r_hi = r_lo + h, mid radius r_i
+            r0 = float(q.get("origin", (0.0, 0.0, 0.0))[0])
+            r_lo = r0 + np.arange(n[0], dtype=np.float64) * q["h"]
+            r_mid = r_lo + 0.5 * q["h"]
+            div = div + (G[d] * ((r_lo + q["h"]) / r_mid) - Glo * (r_lo / r_mid))
+        else:
+            div = div + (G[d] - Glo)
     return phi + dt * div / q["h"]
 
 
@@ -180,6 +191,16 @@ def run(prob, chi, u, F, psi, dt, nsteps, zeta, vof_seq=None, hj_iters=8, totals
         tot[O.T_DTNEXT] = min(tot[O.T_DTNEXT], q["cfl_diff"] / lam)
         hist.append(tot.copy())
     return chi, phi, F, psi, S, np.array(hist)
+
+
+def ring_volumes(prob):
+    """The cell volumes: h^dim, or 2 pi r_i h^2 on axisymmetric rings."""
+    q = O.full(prob)
+    if not q["axisym"]:
+        return np.full(O.shape(prob), q["h"] ** q["dim"])
+    r0 = float(q.get("origin", (0.0, 0.0, 0.0))[0])
+    r = r0 + (np.arange(q["n"][0], dtype=np.float64) + 0.5) * q["h"]
+    return np.broadcast_to(2.0 * math.pi * r * q["h"] ** 2, O.shape(prob)).copy()
 
 
 def profile_thickness(prob, phi):

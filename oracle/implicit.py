@@ -34,6 +34,12 @@ problems are solved alternately (Picard sweeps, the interfacial one first):
 (kl = 1 Langmuir, 0 Henry), starting from c = c*.  Each linear problem is
 solved exactly (a sparse direct solve).  After `picard` sweeps:
 F = (phi+eta) c, psi = (delta+eta/eps) Gamma, sigma = sigma(psi/(delta+eta/eps)).
+
+On axisymmetric rings (Appendix B) the balance of cell i is divided by its
+volume 2 pi r_i h^2, so a radial face's flux enters cell i with the weight
+r_face / r_i (an axial face's with 1): face f between L and R adds
+k r_f / r_L to row L and k r_f / r_R to row R, and the totals integrate over
+the ring volumes.
 """
 from __future__ import annotations
 
@@ -46,13 +52,35 @@ import scipy.sparse.linalg as spla
 from . import oracle as O
 
 
+def radii(q):
+    """Axisymmetric rings: (r_i, r_{i+1/2}) of every cell as [nz][ny][nx]
+    arrays (the mid radius and the radius of the high radial face)."""
+    nx, ny, nz = q["n"]
+    r0 = float(q.get("origin", (0.0, 0.0, 0.0))[0])
+    i = np.arange(nx, dtype=np.float64)
+    rmid = np.broadcast_to(r0 + (i + 0.5) * q["h"], (nz, ny, nx))
+    rhi = np.broadcast_to(r0 + (i + 1.0) * q["h"], (nz, ny, nx))
+    return rmid, rhi
+
+
+def cell_volumes(q):
+    """h^dim, or 2 pi r_i h^2 on axisymmetric rings."""
+    if q["axisym"]:
+        rmid, _ = radii(q)
+        return 2.0 * math.pi * rmid * q["h"] ** 2
+    return np.full(O.shape(q), q["h"] ** q["dim"])
+
+
 def laplacian(q, w, D):
-    """K (N x N, CSR) for face weights w (cell field, [nz][ny][nx])."""
+    """K (N x N, CSR) for face weights w (cell field, [nz][ny][nx]): each
+    face's coefficient k enters its two cells' rows with their divergence
+    weights (1, or r_face / r_i for a radial face of a ring)."""
     nx, ny, nz = q["n"]
     N = nx * ny * nz
     idx = np.arange(N).reshape(nz, ny, nx)
     rows, cols, vals = [], [], []
     bc = list(q["bc"]) + [(0, 0)] * (3 - len(q["bc"]))
+    rmid, rhi = radii(q) if q["axisym"] else (None, None)
     for d in range(q["dim"]):
         ax = 2 - d  # numpy axis of grid axis d
         per = bc[d][0] == O.BC_PERIODIC
@@ -61,16 +89,23 @@ def laplacian(q, w, D):
         wL = w
         wR = np.roll(w, -1, axis=ax)
         k = D * 0.5 * (wL + wR) / (q["h"] ** 2)
+        if q["axisym"] and d == 0:
+            # the face is the high face of L and the low face of R
+            kL = k * rhi / rmid
+            kR = k * rhi / np.roll(rmid, -1, axis=ax)
+        else:
+            kL, kR = k, k
         if not per:
             # the face between the last cell and the wrapped first one is a
             # side: no flux
             sl = [slice(None)] * 3
             sl[ax] = slice(0, q["n"][d] - 1)
-            L, R, k = L[tuple(sl)], R[tuple(sl)], k[tuple(sl)]
-        L, R, k = L.ravel(), R.ravel(), k.ravel()
+            L, R = L[tuple(sl)], R[tuple(sl)]
+            kL, kR = kL[tuple(sl)], kR[tuple(sl)]
+        L, R, kL, kR = L.ravel(), R.ravel(), kL.ravel(), kR.ravel()
         rows += [L, R, L, R]
         cols += [L, R, R, L]
-        vals += [k, k, -k, -k]
+        vals += [kL, kR, -kL, -kR]
     rows = np.concatenate(rows)
     cols = np.concatenate(cols)
     vals = np.concatenate(vals)
@@ -117,7 +152,7 @@ def implicit_step(prob, chi, u, F, psi, dt, picard=3, totals=None):
     Po = (dPv * G).reshape(shp)
     S = O.eos(prob, Po / dP)
     tot = np.zeros(16) if totals is None else np.array(totals, dtype=np.float64)
-    vol = q["h"] ** q["dim"]
+    vol = cell_volumes(q)
     mb = math.fsum((Fo * vol).ravel()) if bulk else 0.0
     ms = math.fsum((Po * vol).ravel())
     sd = math.fsum((de * vol).ravel())
@@ -140,7 +175,13 @@ def implicit_step(prob, chi, u, F, psi, dt, picard=3, totals=None):
                 first = [slice(None)] * 3
                 first[ax] = slice(0, 1)
                 uh[tuple(last)] = ud[tuple(first)]
-            s += np.abs(0.5 * (ud[tuple(lo)] + uh))
+            ul = ud[tuple(lo)]
+            if q["axisym"] and d == 0:
+                # the radial mean weights each face by r_face / r_i
+                rmid, rhi = radii(q)
+                ul = ul * (rhi - q["h"]) / rmid
+                uh = uh * rhi / rmid
+            s += np.abs(0.5 * (ul + uh))
         su = float(s.max())
     out = outF + outP
     outcum = tot[O.T_OUTCUM] + out

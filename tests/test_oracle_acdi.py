@@ -13,7 +13,11 @@ facts it must reproduce, none of them a retyping of its flux:
   measure sum phi (1 - phi)/eps h -> 1 per unit length);
 - phi stays in [0, 1], up to the regularization constant 1e-6 that keeps s
   finite, over a full period of translation with zeta >= |u|, and returns
-  close to its start."""
+  close to its start;
+- on axisymmetric rings (Appendix B): the integral of phi over the ring
+  volumes is conserved exactly with walls and a periodic axis, and a
+  profile that varies along the axis only (no radial flux) takes the same
+  step as on the Cartesian grid."""
 import math
 
 import numpy as np
@@ -165,3 +169,47 @@ def test_tilted_equilibrium_profile_is_steady():
     assert tilted < 3.0 * aligned, (tilted, aligned)
     # the size of one term alone, for scale
     assert aligned < 1e-2 * np.max(np.abs(ph1 * (1 - ph1))) / eps / h
+
+
+@pytest.mark.parametrize("r0", [0.0, 0.3])
+def test_axisymmetric_conserves_the_ring_integral(r0):
+    # a sphere on the axis (r0 = 0) or a torus about it (r0 = 0.3), walls on
+    # both radial sides, periodic along the axis; a flow with a radial part
+    n = (40, 48)
+    h = 1.0 / 40
+    prob = dict(dim=2, n=n, h=h, bc=((0, 0), (1, 1)), eps=1.5 * h, axisym=1,
+                origin=(r0, 0.0, 0.0))
+    vof = synth.vof_ball(n, h, (0.0 if r0 == 0 else 0.35, 0.5, 0), 0.25, 2)
+    phi = A.phi_of_chi(prob, O.geometry(prob, vof, 60))
+    u = synth.u_source2d(n, h, (0.5, 0.5, 0), 0.05)
+    # ring volumes written out from the geometry of the rings
+    r = r0 + (np.arange(n[0]) + 0.5) * h
+    vol = (2.0 * math.pi * r * h * h)[None, None, :]
+    out = phi
+    for _ in range(5):
+        out = A.acdi_step(prob, out, u, 0.2 * h, 0.6)
+    before, after = math.fsum((phi * vol).ravel()), math.fsum((out * vol).ravel())
+    assert abs(after - before) <= 1e-13 * before, (before, after)
+    assert not np.allclose(out, phi)
+    # without the ring weights the same step does not conserve it
+    cart = dict(prob, axisym=0)
+    outc = phi
+    for _ in range(5):
+        outc = A.acdi_step(cart, outc, u, 0.2 * h, 0.6)
+    assert abs(math.fsum((outc * vol).ravel()) - before) > 1e-9 * before
+
+
+def test_axisymmetric_axial_profile_matches_the_cartesian_step():
+    # phi varies along the axis only: radial fluxes vanish, the axial faces
+    # carry weight 1, so the rings step as the Cartesian grid does
+    n = (24, 48)
+    h = 1.0 / 48
+    z = (np.arange(n[1]) + 0.5) * h
+    phi = 1.0 / (1.0 + np.exp((z - 0.37) / (2.0 * h)))
+    phi = np.broadcast_to(phi[None, :, None], (1, n[1], n[0])).copy()
+    for bc in (((0, 2), (0, 0)), ((0, 0), (1, 1))):
+        prob = dict(dim=2, n=n, h=h, bc=bc, eps=1.5 * h, axisym=1, origin=(0.1, 0.0, 0.0))
+        a = A.acdi_step(prob, phi, None, 0.2 * h, 0.8)
+        b = A.acdi_step(dict(prob, axisym=0), phi, None, 0.2 * h, 0.8)
+        assert np.max(np.abs(a - phi)) > 1e-6
+        assert np.max(np.abs(a - b)) == 0.0
