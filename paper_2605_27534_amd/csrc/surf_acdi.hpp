@@ -27,7 +27,9 @@
 // Each face flux is evaluated by both of its cells with the same arithmetic
 // in the same order, so the update conserves sum(phi) exactly.  s is taken of
 // phi clamped into [0, 1]; re-initialization from a VoF field (k_acdi_init)
-// sets phi = 1/(1 + e^{chi/eps}) from the level set.
+// sets phi = 1/(1 + e^{chi/eps}) from the level set.  On axisymmetric rings
+// (Appendix B) the fluxes are the same expressions in (r, z), and a radial
+// face's flux enters ring i with the weight r_face / r_i (both substeps).
 #pragma once
 #include "surf_kernels.hpp"
 #include "surf_col2d.hpp"  // mc()
@@ -41,7 +43,22 @@ struct AcdiArgs {
   R dt, cfl, zeta, ve;  // time step, dt/h, velocity scale, regularization of s
   long long ncell;
   int lim, tr;          // substep-1 variants: MC limiter, BCG transverse term
+  int axi;              // axisymmetric rings: x is the radius, from r0
+  double r0, h;
 };
+
+// the weights of ring x0's low and high radial faces, r_face / r_i (1, 1 on
+// a Cartesian grid)
+template <typename R>
+__device__ __forceinline__ void acdi_ring_weights(const AcdiArgs<R>& a, int x0, R& wlo, R& whi) {
+  wlo = R(1);
+  whi = R(1);
+  if (a.axi) {
+    const double rl = a.r0 + (double)x0 * a.h, rm = rl + 0.5 * a.h;
+    wlo = (R)(rl / rm);
+    whi = (R)((rl + a.h) / rm);
+  }
+}
 
 // The advective flux through the face along d on side sd (0 low, 1 high) of
 // cell x with the substep-1 variants: the upwind cell's value and limited
@@ -147,6 +164,8 @@ __global__ void __launch_bounds__(ACDI_TX) k_acdi_adv(AcdiArgs<R> a, const R* __
       y[d] = (per && x[d] + 1 == nd) ? 0 : x[d] + 1;
       uh[d] = u[d][face_index(g, d, y[0], y[1], y[2])];
     }
+    R wlo, whi;
+    acdi_ring_weights(a, x[0], wlo, whi);
     R div = R(0);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
@@ -162,8 +181,8 @@ __global__ void __launch_bounds__(ACDI_TX) k_acdi_adv(AcdiArgs<R> a, const R* __
       }
       const R flo = blo ? (g.bc[d][0] == BC_OPEN ? ul[d] * pc : R(0)) : flo_i;
       const R fhi = bhi ? (g.bc[d][1] == BC_OPEN ? uh[d] * pc : R(0)) : fhi_i;
-      div += -flo;
-      div += fhi;
+      div += -((d == 0 ? wlo : R(1)) * flo);
+      div += (d == 0 ? whi : R(1)) * fhi;
     }
     st = pc - a.cfl * div;
   }
@@ -214,6 +233,8 @@ __global__ void __launch_bounds__(ACDI_TX) k_acdi_reg(AcdiArgs<R> a, const R* __
   }
   // s at the block offsets (k0, k1, k2) along axes 0, 1, 2 (each 0..2)
   auto sat = [&](int k0, int k1, int k2) { return S[DIM == 3 ? k2 : 0][k1][k0]; };
+  R wlo, whi;
+  acdi_ring_weights(a, x[0], wlo, whi);
   R acc = R(0);
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
@@ -248,7 +269,7 @@ __global__ void __launch_bounds__(ACDI_TX) k_acdi_reg(AcdiArgs<R> a, const R* __
       const bool has = per || (sd == 0 ? x[d] > 0 : x[d] + 1 < g.n[d]);
       G[sd] = has ? f : R(0);
     }
-    acc += G[1] - G[0];
+    acc += d == 0 ? whi * G[1] - wlo * G[0] : G[1] - G[0];
   }
   const R phn = pc + a.cfl * acc;
   phi_out[c] = phn;

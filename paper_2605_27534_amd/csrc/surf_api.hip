@@ -183,8 +183,7 @@ int check_grid_params(const surf_grid* gr, const surf_params* p) {
   if (gr->axisym < 0 || gr->axisym > 1) return SURF_EINVAL;
   if (gr->axisym &&
       (gr->dim != 2 || gr->bc[0][0] == SURF_BC_PERIODIC || !(gr->origin[0] >= 0) ||
-       !std::isfinite(gr->origin[0]) || p->flux_form != SURF_FLUX_WEIGHTED ||
-       p->substep2 != SURF_SUBSTEP2_EXPLICIT || p->interface != SURF_IFACE_VOF || p->adjoint))
+       !std::isfinite(gr->origin[0]) || p->flux_form != SURF_FLUX_WEIGHTED || p->adjoint))
     return SURF_EINVAL;
   if (p->interface == SURF_IFACE_ACDI &&
       (!(p->acdi_zeta > 0) || !std::isfinite(p->acdi_zeta) || !(p->acdi_vareps >= 0) ||
@@ -471,6 +470,9 @@ void acdi_launch(surf_ctx* c, const void* const* u, R* phi_out, R* chi_out,
   a.ncell = c->ncell;
   a.lim = c->prm.limiter;
   a.tr = c->prm.transverse;
+  a.axi = c->grid.axisym ? 1 : 0;
+  a.r0 = c->grid.origin[0];
+  a.h = c->grid.h;
   const bool has_u = u && u[0];
   const dim3 gr(acdi_xblocks(c->grid.n[0]) * c->grid.n[1] * c->grid.n[2]);
   const R* u0 = has_u ? (const R*)u[0] : nullptr;
@@ -985,6 +987,9 @@ CgArgs cg_args(surf_ctx* c, const ImpArgs<R>& a, int field) {
   k.dg = c->imp.dg;
   k.part = c->imp.part;
   k.sc = c->imp.sc;
+  k.axi = a.axi;
+  k.r0 = a.r0;
+  k.h = a.h;
   cg_shape(&c->grid, k.tiles, &k.ntiles, &k.nwg, &k.per_wg);
   return k;
 }
@@ -1070,6 +1075,9 @@ ImpArgs<R> imp_args(surf_ctx* c) {
   a.bulk = bulk ? 1 : 0;
   a.lim = c->prm.limiter;
   a.tr = c->prm.transverse;
+  a.axi = c->grid.axisym ? 1 : 0;
+  a.r0 = c->grid.origin[0];
+  a.h = c->grid.h;
   a.ncell = c->ncell;
   return a;
 }

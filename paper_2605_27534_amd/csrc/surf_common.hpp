@@ -144,9 +144,13 @@ __device__ __forceinline__ R eos(R G, const Par<R>& p) {
   R x = G * p.inv_ginf;
   if (p.eos == EOS_LIN) return p.sigma0 * (R(1) - p.E * x);
   if (p.eos == EOS_LANG) {
+    // x bounded to [0, 1 - 1e-6], written as 1 - x bounded below by the
+    // FP64 value of 1 - (1 - 1e-6): the same bound in FP64, and in FP32 one
+    // that 1 - 1e-6 (not a float) would miss by 1.3%
+    constexpr double OM_MIN = 1.0 - (1.0 - 1e-6);
     x = x < R(0) ? R(0) : x;
-    x = x > R(1) - R(1e-6) ? R(1) - R(1e-6) : x;
-    return p.sigma0 * (R(1) + p.E * rlog<R>(R(1) - x));
+    const R om = R(1) - x;  // NaN stays NaN
+    return p.sigma0 * (R(1) + p.E * rlog<R>(om < R(OM_MIN) ? R(OM_MIN) : om));
   }
   return p.sigma0 * (R(1) - rtanh<R>(p.E * x));
 }

@@ -63,6 +63,15 @@
 // the diagonal).  After the test is met (or on a breakdown) every later
 // launch of that solve returns at once.
 //
+// On axisymmetric rings (Appendix B) every cell's balance is multiplied by
+// its mid radius r_i (the volume 2 pi r_i h^2 up to a constant): a radial
+// face's coefficient takes its radius r_face, an axial face's the ring's
+// r_i, and the reaction diagonal and right-hand side r_i.  The matrix stays
+// symmetric (each face has one coefficient), its solution is that of the
+// divided balance, and the stop test on M^-1 r does not see the scaling.
+// Substep 1 takes the radial fluxes with r_face / r_i, the outflow with the
+// face areas 2 pi r h, and the records with the ring volumes.
+//
 // Layout: tiles of 64 x 32 cells of one z-plane, one tile row of 64 cells
 // per wave lane set, four rows per lane held in registers with the rows
 // above and below; x-neighbours by wave shifts, the tile's edge columns
@@ -100,8 +109,22 @@ struct ImpArgs {
   double inv_h2, Db, Ds;
   int bulk;
   int lim, tr;  // substep-1 variants: MC limiter, BCG transverse term
+  int axi;      // axisymmetric rings: x is the radius, from r0
+  double r0, h; // the low radius and the cell size in FP64
   long long ncell;
 };
+
+// Ring radii of column i (axisymmetric): low face, high face, middle
+struct Rings {
+  double lo, hi, mid;
+};
+__device__ __forceinline__ Rings rings_of(double r0, double h, int i) {
+  Rings r;
+  r.lo = r0 + (double)i * h;
+  r.hi = r.lo + h;
+  r.mid = r.lo + 0.5 * h;
+  return r;
+}
 
 __device__ __forceinline__ void imp_coords(const Grid& g, long long c, int* x) {
   x[0] = (int)(c % g.n[0]);
@@ -145,6 +168,18 @@ __global__ void __launch_bounds__(IMP_BLOCK) k_imp_adv(ImpArgs<R> a, const R* __
     phase<R>(chi[c], p, ph, om, de);
     const R cfl = (R)a.dt * p.inv_h;
     R st[2] = {a.bulk ? F[c] : R(0), psi[c]};
+    // axisymmetric: the radial faces' weights r_face / r_i in the balance,
+    // and 2 pi r over the face areas of the outflow (Cartesian: 1)
+    R wr[2] = {R(1), R(1)};
+    double ar[3] = {1.0, 1.0, 1.0};  // radial low, radial high, axial
+    if (a.axi) {
+      const Rings r = rings_of(a.r0, a.h, x[0]);
+      wr[0] = (R)(r.lo / r.mid);
+      wr[1] = (R)(r.hi / r.mid);
+      ar[0] = 2.0 * M_PI * r.lo;
+      ar[1] = 2.0 * M_PI * r.hi;
+      ar[2] = 2.0 * M_PI * r.mid;
+    }
     if (u0) {
       for (int f = 0; f < 2; ++f) {
         if (f == 0 && !a.bulk) continue;
@@ -160,12 +195,13 @@ __global__ void __launch_bounds__(IMP_BLOCK) k_imp_adv(ImpArgs<R> a, const R* __
             y[d] = (per && fidx == nd) ? 0 : fidx;
             const R uf = u[d][face_index(g, d, y[0], y[1], y[2])];
             R fl;
+            const double af = d == 0 ? ar[s] : ar[2];
             if (blo) {
               fl = g.bc[d][0] == BC_OPEN ? uf * xi[c] : R(0);
-              out -= (double)(area_dt * fl);
+              out -= af * (double)(area_dt * fl);
             } else if (bhi) {
               fl = g.bc[d][1] == BC_OPEN ? uf * xi[c] : R(0);
-              out += (double)(area_dt * fl);
+              out += af * (double)(area_dt * fl);
             } else {
               const int off = s == 0 ? -1 : 0;
               auto at = [&](int o) {
@@ -206,7 +242,8 @@ __global__ void __launch_bounds__(IMP_BLOCK) k_imp_adv(ImpArgs<R> a, const R* __
                 fl = uf * val;
               }
             }
-            div += s == 0 ? -fl : fl;
+            const R wf = d == 0 ? wr[s] : R(1);
+            div += s == 0 ? -(wf * fl) : wf * fl;
           }
         }
         st[f] = xi[c] - cfl * div;
@@ -220,7 +257,8 @@ __global__ void __launch_bounds__(IMP_BLOCK) k_imp_adv(ImpArgs<R> a, const R* __
         y[d] += 1;
         if (y[d] == g.n[d] && g.bc[d][1] == BC_PERIODIC) y[d] = 0;
         const R uhi = u[d][face_index(g, d, y[0], y[1], y[2])];
-        s += fabs(R(0.5) * (ulo + uhi));
+        // the radial mean weights each face by r_face / r_i
+        s += d == 0 ? fabs(R(0.5) * (wr[0] * ulo + wr[1] * uhi)) : fabs(R(0.5) * (ulo + uhi));
       }
       usum = (double)s;
     }
@@ -283,6 +321,8 @@ struct CgArgs {
   unsigned long long solve_id;
   int tiles[3];      // tiles along x, y, z
   int ntiles, nwg, per_wg;
+  int axi;           // axisymmetric rings: rows scaled by r_i, faces by their radius
+  double r0, h;
 };
 
 __device__ __forceinline__ void cg_publish(unsigned long long* hp, int slot,
@@ -350,6 +390,16 @@ __global__ void __launch_bounds__(CG_WG) k_cg_setup(ImpArgs<R> a, CgArgs c, int 
       const int n = x + nx * (y + ny * tz);
       double dg, rhs;
       cg_row(a, field, n, dg, rhs);
+      // face radii (low, high radial face; axial faces) and the row scale
+      double rf[3] = {1.0, 1.0, 1.0};
+      if (c.axi) {
+        const Rings r = rings_of(c.r0, c.h, x);
+        rf[0] = r.lo;
+        rf[1] = r.hi;
+        rf[2] = r.mid;
+        dg *= r.mid;
+        rhs *= r.mid;
+      }
       const double xc = c.x[n], wc = c.fw[n];
       double ax = dg * xc, m = dg;
       for (int d = 0; d < g.dim; ++d)
@@ -359,7 +409,7 @@ __global__ void __launch_bounds__(CG_WG) k_cg_setup(ImpArgs<R> a, CgArgs c, int 
           int e[3] = {q[0], q[1], q[2]};
           e[d] = cg_wrap(v, g.n[d]);
           const int nb = e[0] + nx * (e[1] + ny * e[2]);
-          const double k = c.kc * (wc + c.fw[nb]);
+          const double k = c.kc * (wc + c.fw[nb]) * (d == 0 ? rf[s > 0 ? 1 : 0] : rf[2]);
           ax += k * (xc - c.x[nb]);
           m += k;
         }
@@ -444,6 +494,14 @@ __global__ void __launch_bounds__(CG_WG) k_cg_iter(CgArgs c, int it) {
     const int x0 = tx * CG_TX, x = x0 + lane, xm = min(x, nx - 1);
     const int y0 = ty * CG_TY + wv * CG_ROWS;  // the lane's first row
     const int zoff = ny * zc;
+    // face radii of the lane's column (axisymmetric; else 1)
+    double rlo = 1.0, rhi = 1.0, rmid = 1.0;
+    if (c.axi) {
+      const Rings r = rings_of(c.r0, c.h, xm);
+      rlo = r.lo;
+      rhi = r.hi;
+      rmid = r.mid;
+    }
     // register rows y0-1 .. y0+CG_ROWS (wrapped or clamped into the grid)
     double u[CG_ROWS + 2], fr[CG_ROWS + 2];
     double rold[CG_ROWS], mio[CG_ROWS], zo[CG_ROWS], ro[CG_ROWS];
@@ -495,10 +553,10 @@ __global__ void __launch_bounds__(CG_WG) k_cg_iter(CgArgs c, int it) {
       const int n = xm + nx * (ym + zoff);
       const double dgc = c.dg[n], xo = c.x[n], po = c.p[n];
       double Au = dgc * uc;
-      if (lane > 0 || lex) Au += kc * (fc + fL) * (uc - uL);
-      if (lane < rl || rex) Au += kc * (fc + fR) * (uc - uR);
-      if (y > 0 || pery) Au += kc * (fc + fr[k - 1]) * (uc - u[k - 1]);
-      if (y + 1 < ny || pery) Au += kc * (fc + fr[k + 1]) * (uc - u[k + 1]);
+      if (lane > 0 || lex) Au += kc * (fc + fL) * rlo * (uc - uL);
+      if (lane < rl || rex) Au += kc * (fc + fR) * rhi * (uc - uR);
+      if (y > 0 || pery) Au += kc * (fc + fr[k - 1]) * rmid * (uc - u[k - 1]);
+      if (y + 1 < ny || pery) Au += kc * (fc + fr[k + 1]) * rmid * (uc - u[k + 1]);
       if (DIM == 3) {
 #pragma unroll
         for (int s = -1; s <= 1; s += 2) {
@@ -579,10 +637,17 @@ __global__ void __launch_bounds__(IMP_BLOCK) k_imp_final(ImpArgs<R> a, R* __rest
     if (a.bulk) Fo[c] = Fn;
     Po[c] = Pn;
     if (sig) sig[c] = sg;
-    v[P_SUM_F] = (double)Fn;
-    v[P_SUM_PSI] = (double)Pn;
-    v[P_SUM_DELTA] = (double)de;
-    v[P_SUM_SIGDELTA] = (double)(sg * de);
+    // axisymmetric: each ring counts 2 pi r_i (the finalize multiplies by h^2)
+    double wv = 1.0;
+    if (a.axi) {
+      int x[3];
+      imp_coords(a.g, c, x);
+      wv = 2.0 * M_PI * rings_of(a.r0, a.h, x[0]).mid;
+    }
+    v[P_SUM_F] = wv * (double)Fn;
+    v[P_SUM_PSI] = wv * (double)Pn;
+    v[P_SUM_DELTA] = wv * (double)de;
+    v[P_SUM_SIGDELTA] = wv * (double)(sg * de);
     if (a.bulk) {
       v[P_MAX_C] = (double)rdiv<R>(Fn, ph + p.eta);
       v[P_MIN_F] = (double)Fn;
