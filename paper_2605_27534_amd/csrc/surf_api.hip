@@ -191,11 +191,9 @@ int check_grid_params(const surf_grid* gr, const surf_params* p) {
     return SURF_EINVAL;
   if (p->limiter < 0 || p->limiter > 1 || p->transverse < 0 || p->transverse > 1)
     return SURF_EINVAL;
-  // the variants run in the 2D weighted-form transport and in the implicit
-  // path's advection (2D or 3D)
-  if ((p->limiter || p->transverse) &&
-      (p->flux_form != SURF_FLUX_WEIGHTED || p->adjoint ||
-       (gr->dim != 2 && p->substep2 != SURF_SUBSTEP2_IMPLICIT)))
+  // the variants run in the 2D weighted-form transport, in the 3D tile
+  // transport (k_step) and in the implicit path's advection (2D or 3D)
+  if ((p->limiter || p->transverse) && (p->flux_form != SURF_FLUX_WEIGHTED || p->adjoint))
     return SURF_EINVAL;
   // the adjoint kernels index cells and faces in 32 bits and launch a grid of
   // (nx/64, ny/4, nz) workgroups
@@ -311,6 +309,8 @@ bool snapshot_needed(const surf_grid* gr, const surf_params* p, int nc3) {
 int col3_shape(const surf_grid* gr, const surf_params* p, int* s) {
   s[0] = s[1] = s[2] = 0;
   if (gr->dim != 3 || p->flux_form != SURF_FLUX_WEIGHTED) return 0;
+  // the substep-1 variants run in the tile transport (k_step)
+  if (p->limiter || p->transverse) return 0;
   // 32-bit byte offsets of the buffer-resource access
   const long long es = p->precision == SURF_F64 ? 8 : 4;
   if ((long long)(gr->n[0] + 1) * (gr->n[1] + 1) * (gr->n[2] + 1) * es > 0x7fffffffll) return 0;
@@ -922,6 +922,8 @@ int step_impl(surf_ctx* c, const void* const* u, const void* F_in, const void* p
   a.p = make_par<R>(c);
   a.chi = (const R*)c->chi[c->chi_cur];
   a.has_u = (u && u[0]) ? 1 : 0;
+  a.lim = c->prm.limiter;
+  a.tr = c->prm.transverse;
   for (int d = 0; d < 3; ++d) a.u[d] = (a.has_u && d < c->grid.dim) ? (const R*)u[d] : nullptr;
   a.F = (const R*)F_in;
   a.psi = (const R*)psi_in;
@@ -1305,8 +1307,8 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   int cs, cg;
   int ncol = col_shape(grid, params, &cs, &cg);
   if (grid->axisym && ncol == 0) return SURF_EINVAL;  // the rings run on k_col2d only
-  // so do the explicit substep-1 variants
-  if ((params->limiter || params->transverse) && ncol == 0 &&
+  // so do the explicit substep-1 variants in 2D (3D: the tile transport)
+  if ((params->limiter || params->transverse) && grid->dim == 2 && ncol == 0 &&
       params->substep2 != SURF_SUBSTEP2_IMPLICIT)
     return SURF_EINVAL;
   int c3s[3];

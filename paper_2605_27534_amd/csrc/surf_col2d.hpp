@@ -109,14 +109,6 @@ __device__ __forceinline__ R bcg_face(R uf, R x, R xr, R dl, R d, R dr, R half_c
   return uf * ((pos ? x : xr) + (pos ? k : -k) * m);
 }
 
-// Monotonized central slope (van Leer 1977): the centred difference bounded
-// by twice each one-sided difference, 0 at extrema.
-template <typename R>
-__device__ __forceinline__ R mc(R a, R b) {
-  const R m = fmin(fabs(R(0.5) * (a + b)), R(2) * fmin(fabs(a), fabs(b)));
-  return a * b > R(0) ? copysign(m, a) : R(0);
-}
-
 // The face value of the substep-1 variants: the slope limiter LIM (0 minmod,
 // 1 MC), plus tl or tr, the transverse term of the upwind cell (low or high
 // side), when the unsplit predictor is on.

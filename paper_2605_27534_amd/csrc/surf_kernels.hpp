@@ -130,6 +130,7 @@ struct StepArgs {
   R area_dt;   // h^(dim-1) * dt, for the open-boundary budget
   int has_u;
   int tiles[3];
+  int lim, tr;  // substep-1 variants: MC limiter, BCG transverse term
 };
 
 // Advective flux u xi_f through a face (section 3.1): xi_f is the upwind
@@ -143,6 +144,14 @@ __device__ __forceinline__ R adv_flux(R uf, R xLm, R xL, R xR, R xRp, R cfl_scal
   const R c = pos ? xR : xL;    // downwind cell
   const R k = R(0.5) * (R(1) - fabs(uf) * cfl_scale);
   return uf * (b + k * minmod<R>(b - a, c - b));
+}
+
+// Monotonized central slope (van Leer 1977): the centred difference bounded
+// by twice each one-sided difference, 0 at extrema.
+template <typename R>
+__device__ __forceinline__ R mc(R a, R b) {
+  const R m = fmin(fabs(R(0.5) * (a + b)), R(2) * fmin(fabs(a), fabs(b)));
+  return a * b > R(0) ? copysign(m, a) : R(0);
 }
 
 // Paper-form anti-diffusion coefficient of a cell along d (section 3.2,
@@ -196,6 +205,45 @@ __device__ __forceinline__ void block_partials(double* v, double* out) {
     }
     out[s] = x;
   }
+}
+
+// The advective flux through an interior face with the substep-1 variants
+// (section 3.1): the upwind cell's value and its slope (MC or minmod)
+// carried to the half-step foot, less dt/2h times its mean transverse
+// velocity times its upwind transverse difference for each transverse axis
+// (the unsplit BCG predictor).  x: a field in LDS with strides s3, lL the
+// face's low cell there and gL its coordinates in the box (the high cell is
+// one step along d; both are cells of the box, a periodic wrap included).
+template <typename R, int DIM>
+__device__ R step_flux_var(const StepArgs<R>& a, const R* x, int lL, const int* s3, int d,
+                           const int* gL, R uf, R cfl) {
+  const Grid& g = a.g;
+  const int st = s3[d];
+  const bool pos = uf > R(0);
+  const int lU = pos ? lL : lL + st;  // the upwind cell
+  const R xm = x[lU - st], xu = x[lU], xp = x[lU + st];
+  const R k = R(0.5) * (R(1) - fabs(uf) * cfl);
+  const R sl = a.lim ? mc<R>(xu - xm, xp - xu) : minmod<R>(xu - xm, xp - xu);
+  R val = xu + (pos ? k : -k) * sl;
+  if (a.tr) {
+    int w[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const int q = gL[e] + (e == d && !pos ? 1 : 0);
+      w[e] = e < DIM ? map_axis(q, g.n[e], g.bc[e][0], g.bc[e][1]) : 0;
+    }
+#pragma unroll
+    for (int t = 0; t < DIM; ++t) {
+      if (t == d) continue;
+      int hi[3] = {w[0], w[1], w[2]};
+      hi[t] = (g.bc[t][0] == BC_PERIODIC && w[t] + 1 == g.n[t]) ? 0 : w[t] + 1;
+      const R vt = R(0.5) * (a.u[t][face_index(g, t, w[0], w[1], w[2])] +
+                             a.u[t][face_index(g, t, hi[0], hi[1], hi[2])]);
+      const R dxt = vt > R(0) ? xu - x[lU - s3[t]] : x[lU + s3[t]] - xu;
+      val -= R(0.5) * cfl * vt * dxt;
+    }
+  }
+  return uf * val;
 }
 
 // Fused step on one tile of TX x TY (x TZ) cells.  LDS holds the old state
@@ -303,13 +351,20 @@ __global__ void __launch_bounds__(BLOCK) k_step(StepArgs<R> a) {
             if (f == 0 && !bulk) continue;
             const R* x = sA + f * N3;
             R Flo, Fhi;
+            const bool var = a.lim || a.tr;
             if (blo) {
               Flo = g.bc[d][0] == BC_OPEN ? ulo * x[l3] : R(0);
+            } else if (var) {
+              int gL[3] = {gc[0], gc[1], gc[2]};
+              gL[d] -= 1;
+              Flo = step_flux_var<R, DIM>(a, x, l3 - st, s3, d, gL, ulo, cfl);
             } else {
               Flo = adv_flux<R>(ulo, x[l3 - 2 * st], x[l3 - st], x[l3], x[l3 + st], cfl);
             }
             if (bhi) {
               Fhi = g.bc[d][1] == BC_OPEN ? uhi * x[l3] : R(0);
+            } else if (var) {
+              Fhi = step_flux_var<R, DIM>(a, x, l3, s3, d, gc, uhi, cfl);
             } else {
               Fhi = adv_flux<R>(uhi, x[l3 - st], x[l3], x[l3 + st], x[l3 + 2 * st], cfl);
             }

@@ -228,8 +228,8 @@ def test_interface_force_validation():
 
 def test_advection_variant_validation():
     """The MC limiter and the transverse term: the weighted form, no adjoint,
-    no batch; explicit substep 2 in 2D (Cartesian or axisymmetric, the VoF or
-    the ACDI interface), implicit substep 2 in 2D or 3D."""
+    no batch; either substep 2 in 2D (Cartesian or axisymmetric, the VoF or
+    the ACDI interface) and in 3D."""
     import ctypes
     from paper_2605_27534_amd import surf as S
     L = S.lib()
@@ -238,14 +238,15 @@ def test_advection_variant_validation():
     for ok in (dict(), dict(limiter=0), dict(bcg_transverse=0)):
         g, p, _ = S.make_structs(dict(base, **ok), 1e-3, S.SURF_F32)
         assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == 0, ok
-    for ok in (dict(substep2=1), dict(substep2=1, dim=3, n=(16, 16, 16),
-                                      bc=((1, 1), (0, 2), (0, 0)))):
+    cube = dict(dim=3, n=(16, 16, 16), bc=((1, 1), (0, 2), (0, 0)))
+    for ok in (dict(substep2=1), dict(cube, substep2=1), cube,
+               dict(cube, interface=1, acdi_zeta=0.5)):
         g, p, _ = S.make_structs(dict(base, **ok), 1e-3, S.SURF_F32)
         assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == 0, ok
     g, p, _ = S.make_structs(dict(base, interface=1, acdi_zeta=0.5), 1e-3, S.SURF_F32)
     assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == 0
     for bad in (dict(limiter=2), dict(bcg_transverse=-1), dict(flux_form=1), dict(adjoint=1),
-                dict(dim=3, n=(16, 16, 16), bc=((0, 0), (0, 0), (0, 0)))):
+                dict(cube, flux_form=1)):
         g, p, _ = S.make_structs(dict(base, **bad), 1e-3, S.SURF_F32)
         assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == -1, bad
     # on axisymmetric rings too
