@@ -1,5 +1,5 @@
 """FP64 oracle of the implicit substep 2 (section 3, second substep of the
-split; Appendix C), weighted flux form.
+split; Appendix C), in the weighted flux form and in the paper's own form.
 
 TEST INFRASTRUCTURE ONLY: the tests and the CPU-baseline leg of the
 benchmark may import this module; the product path never does.  It shares no
@@ -40,6 +40,21 @@ volume 2 pi r_i h^2, so a radial face's flux enters cell i with the weight
 r_face / r_i (an axial face's with 1): face f between L and R adds
 k r_f / r_L to row L and k r_f / r_R to row R, and the totals integrate over
 the ring volumes.
+
+In the paper's form (sections 2.6, 3.2, Appendix A) the unknowns are F and
+psi themselves and the flux through a face is D (xi_R - xi_L)/h + Bbar xi_up:
+the centred diffusion plus the anti-diffusive transport at velocity -B, B
+the face mean of the cell values B_F = -D_b (1 - phi) n_d / eps (bulk) and
+B_psi = -D_s (1 - 2 phi) n_d / eps (carrier), n = -grad chi / |grad chi|
+from centred differences (|grad chi| bounded below by 1e-6), xi_up the cell
+upwind of -Bbar (L when Bbar < 0).  Its divergence is -P xi with P a
+non-symmetric matrix, and the two problems read
+
+    interface:  [ 1/dt + kl k_a c + k_d + P_s ] psi = psi*/dt + k_a c Gamma_inf delta
+    bulk:       [ 1/dt + k_a (Gamma_inf delta - kl psi)/(phi + eta) + P_b ] F
+                    = F*/dt + k_d psi
+
+with c = F/(phi + eta) at its latest value.
 """
 from __future__ import annotations
 
@@ -112,12 +127,77 @@ def laplacian(q, w, D):
     return sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
 
 
+def _nbr(a, d, off, per, n):
+    """a shifted so that entry i holds a[i + off] along grid axis d: wrapped
+    on a periodic axis, mirrored about the boundary face otherwise."""
+    ax = 2 - d
+    idx = np.arange(n) + off
+    if per:
+        idx = np.mod(idx, n)
+    else:
+        idx = np.where(idx < 0, -1 - idx, idx)
+        idx = np.where(idx >= n, 2 * n - 1 - idx, idx)
+    return np.take(a, idx, axis=ax)
+
+
+def paper_B(q, chi, phi, om, bulk_field):
+    """The paper-form coefficient of every cell along each axis."""
+    bc = list(q["bc"]) + [(0, 0)] * (3 - len(q["bc"]))
+    per = [bc[d][0] == O.BC_PERIODIC for d in range(3)]
+    n = q["n"]
+    g = [(_nbr(chi, e, 1, per[e], n[e]) - _nbr(chi, e, -1, per[e], n[e])) / (2.0 * q["h"])
+         for e in range(q["dim"])]
+    nrm = np.sqrt(sum(x * x for x in g))
+    nrm = np.maximum(nrm, 1e-6)
+    D = q["D_b"] if bulk_field else q["D_s"]
+    w = om if bulk_field else om - phi
+    return [-D * w / q["eps"] * (-g[d] / nrm) for d in range(q["dim"])]
+
+
+def paper_operator(q, chi, phi, om, bulk_field):
+    """P (N x N, CSR): minus the paper-form flux divergence, -(1/h) sum_d
+    (flux_hi - flux_lo), as a matrix acting on xi."""
+    nx, ny, nz = q["n"]
+    N = nx * ny * nz
+    h = q["h"]
+    D = q["D_b"] if bulk_field else q["D_s"]
+    idx = np.arange(N).reshape(nz, ny, nx)
+    B = paper_B(q, chi, phi, om, bulk_field)
+    bc = list(q["bc"]) + [(0, 0)] * (3 - len(q["bc"]))
+    rows, cols, vals = [], [], []
+    for d in range(q["dim"]):
+        ax = 2 - d
+        per = bc[d][0] == O.BC_PERIODIC
+        L = idx
+        R = np.roll(idx, -1, axis=ax)
+        Bf = 0.5 * (B[d] + np.roll(B[d], -1, axis=ax))
+        if not per:
+            sl = [slice(None)] * 3
+            sl[ax] = slice(0, q["n"][d] - 1)
+            L, R, Bf = L[tuple(sl)], R[tuple(sl)], Bf[tuple(sl)]
+        L, R, Bf = L.ravel(), R.ravel(), Bf.ravel()
+        up = np.where(Bf < 0.0, L, R)
+        # flux = D (xi_R - xi_L)/h + Bf xi_up through the high face of L and
+        # the low face of R: minus the divergence takes -flux/h in row L and
+        # +flux/h in row R
+        k = D / (h * h)
+        rows += [L, L, R, R, L, R]
+        cols += [L, R, R, L, up, up]
+        vals += [np.full(L.size, k), np.full(L.size, -k), np.full(L.size, k),
+                 np.full(L.size, -k), -Bf / h, Bf / h]
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = np.concatenate(vals)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
+
+
 def implicit_step(prob, chi, u, F, psi, dt, picard=3, totals=None):
     """One step with substep 2 implicit.  Returns (F, psi, sigma, totals);
     totals follow the explicit step's layout, with the next stable dt taken
     from the advective bound only (substep 2 has none)."""
     q = O.full(prob)
-    assert q["flux_form"] == 0, "the weighted flux form"
+    paper = q["flux_form"] == 1
+    assert not (paper and q["axisym"]), "the paper form on Cartesian grids"
     shp = O.shape(prob)
     N = int(np.prod(shp))
     phi, om, de = O.cell_geometry(prob, chi)
@@ -132,24 +212,39 @@ def implicit_step(prob, chi, u, F, psi, dt, picard=3, totals=None):
     dP = de + q["eta"] / q["eps"]
     kl = 1.0 if q["kinetics"] == 0 else 0.0
     ka, kd, ginf = (q["k_a"], q["k_d"], q["gamma_inf"]) if bulk else (0.0, 0.0, 0.0)
-    Kb = laplacian(q, phi, q["D_b"])
-    Ks = laplacian(q, de, q["D_s"])
     c = (Fs / dF).ravel()
     G = (Ps / dP).ravel()
     dFv, dPv, dev = dF.ravel(), dP.ravel(), de.ravel()
     Fsv, Psv = Fs.ravel(), Ps.ravel()
-    for _ in range(max(1, picard) if bulk else 1):
-        # interfacial problem with c at its latest value
-        A = Ks + sp.diags(dPv * (1.0 / dt + kl * ka * c + kd))
-        G = spla.spsolve(A.tocsc(), Psv / dt + ka * c * ginf * dev)
-        if not bulk:
-            break
-        psi_new = dPv * G
-        # bulk problem with the new psi
-        A = Kb + sp.diags(dFv / dt + ka * (ginf * dev - kl * psi_new))
-        c = spla.spsolve(A.tocsc(), Fsv / dt + kd * psi_new)
-    Fo = (dFv * c).reshape(shp) if bulk else np.array(F, dtype=np.float64)
-    Po = (dPv * G).reshape(shp)
+    if paper:
+        Pb = paper_operator(q, chi, phi, om, True)
+        Ps_ = paper_operator(q, chi, phi, om, False)
+        Fv, Pv = Fsv.copy(), Psv.copy()
+        for _ in range(max(1, picard) if bulk else 1):
+            cF = Fv / dFv if bulk else np.zeros_like(Fv)
+            A = Ps_ + sp.diags(1.0 / dt + kl * ka * cF + kd)
+            Pv = spla.spsolve(A.tocsc(), Psv / dt + ka * cF * ginf * dev)
+            if not bulk:
+                break
+            A = Pb + sp.diags(1.0 / dt + ka * (ginf * dev - kl * Pv) / dFv)
+            Fv = spla.spsolve(A.tocsc(), Fsv / dt + kd * Pv)
+        Fo = Fv.reshape(shp) if bulk else np.array(F, dtype=np.float64)
+        Po = Pv.reshape(shp)
+    else:
+        Kb = laplacian(q, phi, q["D_b"])
+        Ks = laplacian(q, de, q["D_s"])
+        for _ in range(max(1, picard) if bulk else 1):
+            # interfacial problem with c at its latest value
+            A = Ks + sp.diags(dPv * (1.0 / dt + kl * ka * c + kd))
+            G = spla.spsolve(A.tocsc(), Psv / dt + ka * c * ginf * dev)
+            if not bulk:
+                break
+            psi_new = dPv * G
+            # bulk problem with the new psi
+            A = Kb + sp.diags(dFv / dt + ka * (ginf * dev - kl * psi_new))
+            c = spla.spsolve(A.tocsc(), Fsv / dt + kd * psi_new)
+        Fo = (dFv * c).reshape(shp) if bulk else np.array(F, dtype=np.float64)
+        Po = (dPv * G).reshape(shp)
     S = O.eos(prob, Po / dP)
     tot = np.zeros(16) if totals is None else np.array(totals, dtype=np.float64)
     vol = cell_volumes(q)

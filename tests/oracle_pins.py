@@ -373,3 +373,33 @@ def periodic_last_face_unread():
         assert np.array_equal(x1, x2)
     assert np.array_equal(a[3], b[3]), (a[3], b[3])
     return True
+
+
+# ------------------------------------- implicit substep 2, paper form
+def paper_implicit_residual(I=None, kinetics=1):
+    """The implicit paper-form step (Appendix C with the paper's flux), with
+    the Picard sweeps converged, satisfies its implicit equations when they
+    are evaluated by the explicit C oracle: advancing the result by a tiny
+    dt' with O.step gives (xi' - xi)/dt' = the right-hand side at xi, which
+    must equal (xi - xi*)/dt.  A flipped anti-diffusive term or the wrong
+    upwind cell in the implicit operator leaves a residual of the size of
+    that term.  I: the implicit oracle module (a planted copy in the
+    mutation tests)."""
+    if I is None:
+        from oracle import implicit as I
+    from paper_2605_27534_amd import synth
+    n = (40, 32)
+    h = 1.0 / 40
+    prob = dict(dim=2, n=n, h=h, bc=((0, 0), (1, 1)), kinetics=kinetics, eos=1, eos_E=0.3,
+                D_b=1e-2, D_s=2e-3, k_a=2.0, k_d=0.7, flux_form=1)
+    chi = O.geometry(prob, synth.vof_ball(n, h, (0.48, 0.41, 0), 0.21, 2), 60)
+    F, P = O.init_state(prob, chi, c0=synth.uniform_field(n, 4, 0.8, 1.2), gamma0=0.4)
+    dt = 20 * 0.2 * h * h / 1e-2
+    Fn, Pn, _, _ = I.implicit_step(prob, chi, None, F, P, dt, picard=60)
+    dtp = 1e-3
+    Fe, Pe, _, _ = O.step(prob, chi, None, Fn, Pn, dtp)
+    worst = 0.0
+    for lhs, rhs in (((Fn - F) / dt, (Fe - Fn) / dtp), ((Pn - P) / dt, (Pe - Pn) / dtp)):
+        worst = max(worst, float(np.max(np.abs(lhs - rhs)) / np.max(np.abs(lhs))))
+    assert worst < 1e-9, worst
+    return worst

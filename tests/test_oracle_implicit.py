@@ -39,9 +39,11 @@ def circle_case(n=(40, 32), bc=((0, 0), (1, 1)), kinetics=0, axisym=False):
     return prob, chi, F, P
 
 
-@pytest.mark.parametrize("kinetics,axisym", [(0, False), (1, False), (0, True), (1, True)])
-def test_converged_picard_satisfies_the_implicit_equations(kinetics, axisym):
+@pytest.mark.parametrize("kinetics,axisym,form", [(0, False, 0), (1, False, 0), (0, True, 0),
+                                                  (1, True, 0), (0, False, 1), (1, False, 1)])
+def test_converged_picard_satisfies_the_implicit_equations(kinetics, axisym, form):
     prob, chi, F, P = circle_case(kinetics=kinetics, axisym=axisym)
+    prob["flux_form"] = form
     h = prob["h"]
     dt = 20 * 0.2 * h * h / 1e-2  # twenty times the explicit diffusive step
     Fn, Pn, _, _ = I.implicit_step(prob, chi, None, F, P, dt, picard=60)
@@ -79,9 +81,11 @@ def test_fourier_mode_decays_by_the_implicit_euler_factor():
     assert err < 1e-12, err
 
 
-@pytest.mark.parametrize("kinetics,axisym", [(0, False), (1, False), (0, True), (1, True)])
-def test_total_amount_conserved_with_walls(kinetics, axisym):
+@pytest.mark.parametrize("kinetics,axisym,form", [(0, False, 0), (1, False, 0), (0, True, 0),
+                                                  (1, True, 0), (0, False, 1), (1, False, 1)])
+def test_total_amount_conserved_with_walls(kinetics, axisym, form):
     prob, chi, F, P = circle_case(bc=((0, 0), (0, 0)), kinetics=kinetics, axisym=axisym)
+    prob["flux_form"] = form
     h = prob["h"]
     dt = 50 * 0.2 * h * h / 1e-2
     Fn, Pn, _, tot = I.implicit_step(prob, chi, None, F, P, dt, picard=60)
@@ -99,9 +103,10 @@ def test_total_amount_conserved_with_walls(kinetics, axisym):
     assert abs(tot[O.T_MB] + tot[O.T_MS] - after) <= 1e-12 * abs(after)
 
 
-@pytest.mark.parametrize("axisym", [False, True])
-def test_second_order_agreement_with_the_explicit_step(axisym):
+@pytest.mark.parametrize("axisym,form", [(False, 0), (True, 0), (False, 1)])
+def test_second_order_agreement_with_the_explicit_step(axisym, form):
     prob, chi, F, P = circle_case(bc=((0 if axisym else 2, 2), (1, 1)), axisym=axisym)
+    prob["flux_form"] = form
     h = prob["h"]
     u = synth.u_source2d((40, 32), h, (0.48, 0.41, 0), 0.03)
     errs = []

@@ -62,6 +62,43 @@ GUARDS = {
 }
 
 
+# mistakes planted in the implicit oracle (a Python module), each with the
+# pin that guards it
+PY_MUTANTS = {
+    # the anti-diffusive term with the wrong sign in the implicit operator
+    "implicit-paper-sign": ("oracle/implicit.py",
+                            [("np.full(L.size, -k), -Bf / h, Bf / h]",
+                              "np.full(L.size, -k), Bf / h, -Bf / h]")],
+                            PINS.paper_implicit_residual),
+    # the downwind cell of -B
+    "implicit-paper-downwind": ("oracle/implicit.py",
+                                [("up = np.where(Bf < 0.0, L, R)", "up = np.where(Bf < 0.0, R, L)")],
+                                PINS.paper_implicit_residual),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTANTS))
+def test_python_pin_fails_on_planted_mistake(name):
+    import importlib.util
+    path, edits, check = PY_MUTANTS[name]
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = open(os.path.join(root, path)).read()
+    for a, b in edits:
+        assert src.count(a) == 1, (name, a)
+        src = src.replace(a, b)
+    check()  # holds on the oracle
+    with tempfile.TemporaryDirectory() as d:
+        f = os.path.join(d, "oracle_mutant_%s.py" % name.replace("-", "_"))
+        with open(f, "w") as fh:
+            # the module imports its sibling with a relative import
+            fh.write(src.replace("from . import oracle as O", "from oracle import oracle as O"))
+        spec = importlib.util.spec_from_file_location("oracle_mutant", f)
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        with pytest.raises(AssertionError):
+            check(mod)
+
+
 @contextlib.contextmanager
 def planted(name):
     src = open(O._SRC).read()

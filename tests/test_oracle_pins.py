@@ -41,3 +41,8 @@ def test_force_stencil_exact_for_quadratic_fields(dim):
 
 def test_periodic_last_face_is_never_read():
     PINS.periodic_last_face_unread()
+
+
+@pytest.mark.parametrize("kinetics", [0, 1])
+def test_implicit_paper_form_satisfies_its_equations(kinetics):
+    PINS.paper_implicit_residual(kinetics=kinetics)
