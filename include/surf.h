@@ -78,9 +78,10 @@ enum { SURF_F32 = 0, SURF_F64 = 1 };
  * centred-diffusion + upwind anti-diffusion form (section 3.2) */
 enum { SURF_FLUX_WEIGHTED = 0, SURF_FLUX_PAPER = 1 };
 /* substep 2 in time: explicit Euler from the advected state (default), or
- * implicit Euler (section 3, Appendix C; weighted flux form only), with the
- * interfacial and bulk problems solved alternately by Jacobi-preconditioned
- * conjugate gradients in FP64 */
+ * implicit Euler (section 3, Appendix C), with the interfacial and bulk
+ * problems solved alternately in FP64 by Jacobi-preconditioned conjugate
+ * gradients (weighted form: symmetric matrices) or BiCGSTAB (paper form:
+ * the upwind anti-diffusion makes them non-symmetric) */
 enum { SURF_SUBSTEP2_EXPLICIT = 0, SURF_SUBSTEP2_IMPLICIT = 1 };
 /* the interface: the level set rebuilt from the VoF given to every moving
  * step (default), or the phase field phi evolved by ACDI (section 2.5, the
@@ -166,9 +167,10 @@ typedef struct {
   int32_t substep2;     /* SURF_SUBSTEP2_*                                */
   int32_t picard_iters; /* implicit: interfacial + bulk solve sweeps per step
                          * (0: 3; at most 32)                            */
-  int32_t cg_max_iters; /* implicit: CG iterations per linear solve at most
-                         * (0: 400); each is one kernel launch, those after
-                         * the test is met return at once               */
+  int32_t cg_max_iters; /* implicit: CG (BiCGSTAB) iterations per linear
+                         * solve at most (0: 400); each is one (three)
+                         * kernel launch(es), those after the test is met
+                         * return at once                               */
   int32_t pad2_;
   double cg_tol;        /* implicit: ||M^-1 r|| <= cg_tol ||x|| ends a solve,
                          * M the Jacobi diagonal (0: 1e-12)               */
@@ -256,8 +258,9 @@ int surf_init_state(surf_ctx* ctx, const void* c0, double c0_const, double gamma
  * as written.
  * With substep2 = SURF_SUBSTEP2_IMPLICIT (section 3, Appendix C) the step
  * advects, then takes substep 2 by implicit Euler: picard_iters sweeps of
- * the interfacial problem for Gamma and the bulk problem for c, each solved
- * by CG (see cg_tol, cg_max_iters); SURF_T_DT_NEXT then holds the advective
+ * the interfacial problem for Gamma and the bulk problem for c (paper form:
+ * for psi and F), each solved by CG (paper form: BiCGSTAB; see cg_tol,
+ * cg_max_iters); SURF_T_DT_NEXT then holds the advective
  * bound only and SURF_STATUS_UNSTABLE tests only that bound. */
 int surf_step(surf_ctx* ctx, const void* vof_next, const void* const* u,
               const void* F_in, const void* psi_in, void* F_out, void* psi_out,
@@ -332,8 +335,8 @@ int surf_time_transport(surf_ctx* ctx, const void* const* u, const void* F_in,
  * iteration launches between two HIP events, the stop test switched off so
  * that every launch iterates.  It overwrites only solver work arrays: the
  * next surf_step is unaffected.  Waits for the stream.  SURF_EINVAL for an
- * explicit context, field 1 without a bulk or reps < 1; SURF_ESTATE before
- * the first implicit step. */
+ * explicit or paper-form context, field 1 without a bulk or reps < 1;
+ * SURF_ESTATE before the first implicit step. */
 int surf_time_solver(surf_ctx* ctx, int32_t field, int32_t reps, double* ms_per_launch);
 
 /* Measurement aid for the ACDI interface: `reps` ACDI steps (advection and

@@ -21,6 +21,7 @@
 #include "surf_geo3d.hpp"
 #include "surf_adjoint.hpp"
 #include "surf_implicit.hpp"
+#include "surf_bicgstab.hpp"
 #include "surf_acdi.hpp"
 #include "surf_capillary.hpp"
 
@@ -201,7 +202,7 @@ int check_grid_params(const surf_grid* gr, const surf_params* p) {
                      (gr->n[1] + 3) / 4 > 65535 || gr->n[2] > 65535))
     return SURF_EINVAL;
   if (p->substep2 == SURF_SUBSTEP2_IMPLICIT &&
-      (p->flux_form != SURF_FLUX_WEIGHTED || p->adjoint || p->picard_iters < 0 ||
+      (p->adjoint || p->picard_iters < 0 ||
        p->picard_iters > IMP_MAX_PICARD || p->cg_max_iters < 0 || !(p->cg_tol >= 0) ||
        ncell >= 2147483648.0))
     return SURF_EINVAL;
@@ -1080,8 +1081,57 @@ ImpArgs<R> imp_args(surf_ctx* c) {
   a.axi = c->grid.axisym ? 1 : 0;
   a.r0 = c->grid.origin[0];
   a.h = c->grid.h;
+  a.paper = q.flux_form == SURF_FLUX_PAPER ? 1 : 0;
   a.ncell = c->ncell;
   return a;
+}
+
+// One paper-form linear solve by BiCGSTAB (field 0: psi, 1: F), from the
+// unknown's current values: coefficients, setup, cg_max_iters iterations of
+// three launches (those after the solve stopped return at once), the end.
+template <typename R>
+int bicg_solve(surf_ctx* c, const ImpArgs<R>& a, int field, int solve) {
+  BicgArgs k{};
+  k.g = c->g;
+  k.k = (field == 1 ? a.Db : a.Ds) * a.inv_h2;
+  k.inv_h = 1.0 / c->grid.h;
+  k.tol2 = a.tol * a.tol;
+  k.x = field == 1 ? c->imp.xF : c->imp.xP;
+  k.p[0] = c->imp.p;
+  k.p[1] = c->imp.z[1];
+  k.v[0] = c->imp.w[0];
+  k.v[1] = c->imp.w[1];
+  k.r = c->imp.r[0];
+  k.rh = c->imp.r[1];
+  k.t = c->imp.z[0];
+  k.minv = c->imp.minv;
+  k.dg = c->imp.dg;
+  for (int d = 0; d < 3; ++d) k.B[d] = c->imp.B[d];
+  k.part = c->imp.part;
+  k.sc = c->imp.sc;
+  k.ncell = c->ncell;
+  const long long nb = (c->ncell + BICG_WG - 1) / BICG_WG;
+  k.nwg = (int)(nb < BICG_MAXWG ? nb : BICG_MAXWG);
+  const dim3 gr(k.nwg), bl(BICG_WG);
+  const bool three = c->grid.dim == 3;
+  hipLaunchKernelGGL(k_bicg_coef<R>, gr, bl, 0, c->stream, a, (const R*)c->chi[c->chi_cur], field,
+                     c->imp.B[0], c->imp.B[1], three ? c->imp.B[2] : c->imp.B[1]);
+  if (three) hipLaunchKernelGGL((k_bicg_setup<R, 3>), gr, bl, 0, c->stream, a, k, field);
+  else hipLaunchKernelGGL((k_bicg_setup<R, 2>), gr, bl, 0, c->stream, a, k, field);
+  const int cap = c->prm.cg_max_iters;
+  for (int it = 0; it < cap; ++it) {
+    if (three) {
+      hipLaunchKernelGGL(k_bicg_a<3>, gr, bl, 0, c->stream, k, it);
+      hipLaunchKernelGGL(k_bicg_b<3>, gr, bl, 0, c->stream, k, it);
+    } else {
+      hipLaunchKernelGGL(k_bicg_a<2>, gr, bl, 0, c->stream, k, it);
+      hipLaunchKernelGGL(k_bicg_b<2>, gr, bl, 0, c->stream, k, it);
+    }
+    hipLaunchKernelGGL(k_bicg_c, gr, bl, 0, c->stream, k, it);
+  }
+  hipLaunchKernelGGL(k_bicg_end, dim3(1), bl, 0, c->stream, k, cap, c->imp.rec + solve,
+                     c->state);
+  return SURF_OK;
 }
 
 template <typename R>
@@ -1112,8 +1162,15 @@ int implicit_impl(surf_ctx* c, const void* const* u, const void* F_in, const voi
       }
     }
     for (int s = 0; s < sweeps; ++s) {
-      int rc = cg_solve<R>(c, a, 0, 2 * s, paced && c->hprog);
-      if (rc == SURF_OK && bulk) rc = cg_solve<R>(c, a, 1, 2 * s + 1, paced && c->hprog);
+      int rc;
+      if (a.paper) {
+        // the paper form's non-symmetric problems
+        rc = bicg_solve<R>(c, a, 0, 2 * s);
+        if (rc == SURF_OK && bulk) rc = bicg_solve<R>(c, a, 1, 2 * s + 1);
+      } else {
+        rc = cg_solve<R>(c, a, 0, 2 * s, paced && c->hprog);
+        if (rc == SURF_OK && bulk) rc = cg_solve<R>(c, a, 1, 2 * s + 1, paced && c->hprog);
+      }
       if (rc != SURF_OK) return rc;
     }
     hipLaunchKernelGGL(k_imp_final<R>, gr, bl, 0, c->stream, a, (R*)F_out, (R*)psi_out,
@@ -1340,8 +1397,10 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   if (imp) {
     b += IMP_FIELDS * align_up(n * sizeof(double));
     b += align_up((size_t)nimp * 2 * sizeof(double));
-    b += align_up((size_t)2 * CG_MAXWG * CT_N * sizeof(double));
+    b += align_up((size_t)3 * CG_MAXWG * CT_N * sizeof(double));
     b += align_up(SC_N * sizeof(double)) + align_up(IMP_MAX_SOLVES * sizeof(double));
+    // the paper form's coefficient B per cell and axis
+    if (params->flux_form == SURF_FLUX_PAPER) b += grid->dim * align_up(n * sizeof(double));
   }
   *bytes = b;
   return SURF_OK;
@@ -1433,11 +1492,18 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
     c->imp.adv = (double*)p;
     p += align_up((size_t)c->imp_nblk * 2 * sizeof(double));
     c->imp.part = (double*)p;
-    p += align_up((size_t)2 * CG_MAXWG * CT_N * sizeof(double));
+    p += align_up((size_t)3 * CG_MAXWG * CT_N * sizeof(double));
     c->imp.sc = (double*)p;
     p += align_up(SC_N * sizeof(double));
     c->imp.rec = (double*)p;
     p += align_up(IMP_MAX_SOLVES * sizeof(double));
+    for (int d = 0; d < 3; ++d) {
+      c->imp.B[d] = nullptr;
+      if (params->flux_form == SURF_FLUX_PAPER && d < grid->dim) {
+        c->imp.B[d] = (double*)p;
+        p += align_up((size_t)c->ncell * sizeof(double));
+      }
+    }
   }
   c->materialized = true;
   c->chi_cur = 0;
@@ -1672,6 +1738,7 @@ int surf_time_solver(surf_ctx* c, int32_t field, int32_t reps, double* ms_per_la
   touch_levelset(c);
   if (!c || !ms_per_launch || reps < 1 || field < 0 || field > 1) return SURF_EINVAL;
   if (c->prm.substep2 != SURF_SUBSTEP2_IMPLICIT) return SURF_EINVAL;
+  if (c->prm.flux_form != SURF_FLUX_WEIGHTED) return SURF_EINVAL;  // CG iterations only
   if (field == 1 && !c->prm.bulk_enabled) return SURF_EINVAL;
   if (c->imp_nsolves == 0 || c->prepared) return SURF_ESTATE;
   if (c->prm.precision == SURF_F64) return time_solver_impl<double>(c, field, reps, ms_per_launch);

@@ -98,6 +98,7 @@ struct ImpBuf {
   double* part;             // [2][CG_MAXWG][4]: CG partial sums
   double* sc;               // CG scalars and control words
   double* rec;              // [IMP_MAX_SOLVES]: iterations of the last step's solves
+  double* B[3];             // paper form: the anti-diffusion coefficient per cell and axis
 };
 
 template <typename R>
@@ -111,6 +112,7 @@ struct ImpArgs {
   int lim, tr;  // substep-1 variants: MC limiter, BCG transverse term
   int axi;      // axisymmetric rings: x is the radius, from r0
   double r0, h; // the low radius and the cell size in FP64
+  int paper;    // the paper's flux form: the unknowns are F and psi themselves
   long long ncell;
 };
 
@@ -267,8 +269,13 @@ __global__ void __launch_bounds__(IMP_BLOCK) k_imp_adv(ImpArgs<R> a, const R* __
     a.B.wP[c] = w1;
     a.B.Fs[c] = (double)st[0];
     a.B.Ps[c] = (double)st[1];
-    a.B.xF[c] = a.bulk ? (double)st[0] / (w0 + a.eta) : 0.0;
-    a.B.xP[c] = (double)st[1] / (w1 + a.eta_eps);
+    if (a.paper) {
+      a.B.xF[c] = a.bulk ? (double)st[0] : 0.0;
+      a.B.xP[c] = (double)st[1];
+    } else {
+      a.B.xF[c] = a.bulk ? (double)st[0] / (w0 + a.eta) : 0.0;
+      a.B.xP[c] = (double)st[1] / (w1 + a.eta_eps);
+    }
   }
   // records: outflow (sum), largest velocity sum (max)
   __shared__ double red[IMP_BLOCK / 64][2];
@@ -297,7 +304,7 @@ constexpr int CG_TX = 64, CG_TY = CG_WAVES * CG_ROWS;  // tile 64 x 32
 constexpr int CG_MAXWG = 512;  // workgroups at most: each one reduces every partial
 enum { CT_GAMMA = 0, CT_DELTA, CT_UU, CT_XX, CT_N = 4 };  // partial sums
 // scalars: (gamma, alpha) of the last two iterations by parity, control words
-enum { SC_GA = 0, SC_DONE = 4, SC_ITER = 5, SC_FAIL = 6, SC_N = 8 };
+enum { SC_GA = 0, SC_DONE = 4, SC_ITER = 5, SC_FAIL = 6, SC_N = 16 };
 enum { STATUS_SOLVE = 16 };  // a linear solve ended without meeting its test
 
 struct CgArgs {
@@ -631,8 +638,9 @@ __global__ void __launch_bounds__(IMP_BLOCK) k_imp_final(ImpArgs<R> a, R* __rest
   v[P_MIN_PSI] = INFINITY;
   if (c < a.ncell) {
     const R ph = (R)B.wF[c], de = (R)B.wP[c];
-    const R Fn = a.bulk ? (R)((B.wF[c] + a.eta) * B.xF[c]) : R(0);
-    const R Pn = (R)((B.wP[c] + a.eta_eps) * B.xP[c]);
+    // the unknowns: c and Gamma (weighted form) or F and psi (paper form)
+    const R Fn = a.bulk ? (R)(a.paper ? B.xF[c] : (B.wF[c] + a.eta) * B.xF[c]) : R(0);
+    const R Pn = (R)(a.paper ? B.xP[c] : (B.wP[c] + a.eta_eps) * B.xP[c]);
     const R sg = eos<R>(rdiv<R>(Pn, de + p.eta_eps), p);
     if (a.bulk) Fo[c] = Fn;
     Po[c] = Pn;

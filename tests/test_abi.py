@@ -141,7 +141,11 @@ def test_implicit_substep2_validation():
     g, p, _ = S.make_structs(dict(base, substep2=0), 1e-3, S.SURF_F32)
     assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == 0
     assert ws_imp >= nb.value + 15 * 32 * 32 * 8  # the FP64 work arrays
-    for bad in (dict(flux_form=1), dict(adjoint=1), dict(substep2=2), dict(picard_iters=-1),
+    # the paper form solves by BiCGSTAB, with its coefficient B per axis
+    g, p, _ = S.make_structs(dict(base, flux_form=1), 1e-3, S.SURF_F32)
+    assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == 0
+    assert nb.value >= ws_imp + 2 * 32 * 32 * 8
+    for bad in (dict(adjoint=1), dict(substep2=2), dict(picard_iters=-1),
                 dict(picard_iters=33), dict(cg_tol=-1.0), dict(cg_max_iters=-1)):
         g, p, _ = S.make_structs(dict(base, **bad), 1e-3, S.SURF_F32)
         assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == -1, bad
