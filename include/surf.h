@@ -355,8 +355,8 @@ int surf_time_acdi(surf_ctx* ctx, const void* const* u, int32_t reps, double* ms
 int surf_force(surf_ctx* ctx, const void* sigma, void* const* force);
 
 /* The interfacial forces of the coupling to a flow solver (section 2.4, the
- * capillary force and the Marangoni force with delta_m = A_f / V_c), 2D
- * Cartesian, on the faces of u.  Inputs (device, context precision, cell
+ * capillary force and the Marangoni force with delta_m = A_f / V_c), 2D or
+ * 3D Cartesian, on the faces of u.  Inputs (device, context precision, cell
  * layout): vof, the VoF fraction of fluid 1, and sigma, the surface tension
  * (e.g. surf_step's sigma_out); the context's cached level set supplies the
  * normal and the curvature fallback.  Outputs (device, caller-owned):
@@ -372,11 +372,20 @@ int surf_force(surf_ctx* ctx, const void* sigma, void* const* force);
  *              constant) in each interfacial cell over h, on a face the
  *              mean of both cells; grad sigma and n from the face gradients
  *              of sigma and chi as in surf_force.
- * Either array pair may be NULL (not both).  Faces on walls and open sides
+ * In 3D (f_cap[0..2], f_ma[0..2], the face layouts of u): the Youngs normal
+ * from the 3x3x3 stencil; kappa = (H_bb (1 + H_c^2) + H_cc (1 + H_b^2) -
+ * 2 H_bc H_b H_c)/(1 + H_b^2 + H_c^2)^(3/2) from nine columns of nine cells
+ * along the first axis, in the order of the normal's components, whose
+ * columns all close; a cell where none closes takes the mean height
+ * curvature of the interfacial cells of its 3x3x3 block, or the level-set
+ * curvature moved to the interface; delta_m the area of the PLIC plane in
+ * the cell over h.  The 3D call uses the context's pin-data and idle
+ * level-set buffers as scratch (both free between steps).
+ * Either array set may be NULL (not both).  Faces on walls and open sides
  * get 0; on a periodic axis the last face repeats the first.  Enqueued on
- * the context's stream.  SURF_EINVAL for a 3D or axisymmetric grid, an axis
- * under 4 cells, (nx+1)(ny+1) >= 2^30, NULL inputs or a NULL array in a
- * given pair; SURF_ESTATE without a level set or with a prepared geometry
+ * the context's stream.  SURF_EINVAL for an axisymmetric grid, an axis
+ * under 4 cells, in 2D (nx+1)(ny+1) >= 2^30, NULL inputs or a NULL array in
+ * a given set; SURF_ESTATE without a level set or with a prepared geometry
  * pending. */
 int surf_interface_force(surf_ctx* ctx, const void* vof, const void* sigma, void* const* f_cap,
                          void* const* f_ma);

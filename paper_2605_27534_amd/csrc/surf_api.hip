@@ -24,6 +24,7 @@
 #include "surf_bicgstab.hpp"
 #include "surf_acdi.hpp"
 #include "surf_capillary.hpp"
+#include "surf_capillary3d.hpp"
 
 using namespace surf;
 
@@ -1260,6 +1261,29 @@ int iface_force_impl(surf_ctx* c, const void* vof, const void* sigma, void* cons
   return status_of_launch();
 }
 
+// 3D: the cells pass into two scratch cell arrays (the pin-data buffer and
+// the idle level-set buffer, both free between steps), then the faces pass
+template <typename R>
+int iface3_force_impl(surf_ctx* c, const void* vof, const void* sigma, void* const* cap,
+                      void* const* ma) {
+  materialize<R>(c);
+  Iface3Args<R> a;
+  a.g = c->g;
+  a.vof = (const R*)vof;
+  a.chi = (const R*)c->chi[c->chi_cur];
+  a.sig = (const R*)sigma;
+  a.kh = (R*)c->g0;
+  a.dm = (R*)c->chi[1 - c->chi_cur];
+  a.h = c->grid.h;
+  const dim3 gr(grid1d(c->ncell)), bl(256);
+  hipLaunchKernelGGL(k_iface3_cells<R>, gr, bl, 0, c->stream, a);
+  hipLaunchKernelGGL(k_iface3_faces<R>, gr, bl, 0, c->stream, a, cap ? (R*)cap[0] : nullptr,
+                     cap ? (R*)cap[1] : nullptr, cap ? (R*)cap[2] : nullptr,
+                     ma ? (R*)ma[0] : nullptr, ma ? (R*)ma[1] : nullptr,
+                     ma ? (R*)ma[2] : nullptr);
+  return status_of_launch();
+}
+
 bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
 // Work that reads or writes the level set on the context's stream outside a
@@ -1840,12 +1864,22 @@ int surf_interface_force(surf_ctx* c, const void* vof, const void* sigma, void* 
   if (c && !c->materialized) touch_levelset(c);
   if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !vof || !sigma || (!f_cap && !f_ma)) return SURF_EINVAL;
-  if (c->grid.dim != 2 || c->grid.axisym) return SURF_EINVAL;
-  if (c->grid.n[0] < 4 || c->grid.n[1] < 4) return SURF_EINVAL;
-  if ((long long)(c->grid.n[0] + 1) * (c->grid.n[1] + 1) >= (1ll << 30)) return SURF_EINVAL;
-  for (int d = 0; d < 2; ++d)
+  if (c->grid.axisym) return SURF_EINVAL;
+  const int dim = c->grid.dim;
+  for (int d = 0; d < dim; ++d)
+    if (c->grid.n[d] < 4) return SURF_EINVAL;
+  if (dim == 2 && (long long)(c->grid.n[0] + 1) * (c->grid.n[1] + 1) >= (1ll << 30))
+    return SURF_EINVAL;
+  for (int d = 0; d < dim; ++d)
     if ((f_cap && !f_cap[d]) || (f_ma && !f_ma[d])) return SURF_EINVAL;
   if (!c->has_chi) return SURF_ESTATE;
+  if (dim == 3) {
+    // the cells pass writes the idle level-set buffer: the next geometry
+    // (which writes it too) must wait for it
+    touch_levelset(c);
+    if (c->prm.precision == SURF_F64) return iface3_force_impl<double>(c, vof, sigma, f_cap, f_ma);
+    return iface3_force_impl<float>(c, vof, sigma, f_cap, f_ma);
+  }
   if (c->prm.precision == SURF_F64) return iface_force_impl<double>(c, vof, sigma, f_cap, f_ma);
   return iface_force_impl<float>(c, vof, sigma, f_cap, f_ma);
 }

@@ -318,11 +318,11 @@ class Surf:
         return out
 
     def interface_force(self, vof, sigma, cap=True, ma=True, out=None):
-        """(capillary [fx, fy], Marangoni [fx, fy]) on the faces, 2D; a pair
-        not asked for is None.  `out` = (cap, ma) reuses caller arrays."""
+        """(capillary [fx, fy(, fz)], Marangoni [fx, fy(, fz)]) on the faces;
+        a set not asked for is None.  `out` = (cap, ma) reuses caller arrays."""
         if out is None:
             mk = lambda: [torch.empty(self.face_shape(d), dtype=self.dtype, device=self.device)
-                          for d in range(2)]
+                          for d in range(self.dim)]
             out = (mk() if cap else None, mk() if ma else None)
         arrs = [None if o is None else self._faces(o, "force") for o in out]
         self._check(self.L.surf_interface_force(self.ctx, _ptr(self._cell(vof, "vof")),

@@ -191,9 +191,9 @@ def test_axisym_validation():
 
 
 def test_interface_force_validation():
-    """surf_interface_force rejects 3D and axisymmetric grids, missing
-    inputs and half-given output pairs before touching the device, and asks
-    for a level set first."""
+    """surf_interface_force rejects axisymmetric grids, missing inputs and
+    half-given output sets before touching the device, and asks for a level
+    set first (2D and 3D)."""
     import ctypes
     from paper_2605_27534_amd import surf as S
     L = S.lib()
@@ -223,11 +223,18 @@ def test_interface_force_validation():
     assert L.surf_interface_force(ctx, p, p, pair, half) == -1
     assert L.surf_interface_force(None, p, p, pair, pair) == -1
     assert L.surf_destroy(ctx) == 0
-    for bad in (dict(dim=3, n=(16, 16, 16), bc=((0, 0), (0, 0), (0, 0))),
-                dict(axisym=1, bc=((0, 2), (0, 0)))):
-        ctx, buf, base = ctx_of(dict(two, **bad))
-        assert L.surf_interface_force(ctx, p, p, pair, pair) == -1, bad
-        assert L.surf_destroy(ctx) == 0
+    ctx, buf, base = ctx_of(dict(axisym=1, **dict(two, bc=((0, 2), (0, 0)))))
+    assert L.surf_interface_force(ctx, p, p, pair, pair) == -1
+    assert L.surf_destroy(ctx) == 0
+    cube = dict(dim=3, n=(16, 16, 16), h=1.0 / 16, bc=((0, 0), (0, 0), (1, 1)))
+    ctx, buf, base = ctx_of(cube)
+    trip = (ctypes.c_void_p * 3)(base, base, base)
+    part = (ctypes.c_void_p * 3)(base, base, None)
+    assert L.surf_interface_force(ctx, p, p, trip, trip) == -4  # no level set
+    assert L.surf_interface_force(ctx, p, p, None, trip) == -4
+    assert L.surf_interface_force(ctx, p, p, trip, part) == -1
+    assert L.surf_interface_force(ctx, p, p, None, None) == -1
+    assert L.surf_destroy(ctx) == 0
 
 
 def test_advection_variant_validation():
