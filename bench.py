@@ -19,6 +19,7 @@ host (`cpu_baseline`).
 Other workloads (one JSON line each, not the default):
   c2  the 256^3 translating sphere (inputs generated on the GPU, all steps
       resident before the timed region);
+  c2f the sphere of c2 with the 3D interfacial forces taken every step;
   c2a the sphere of c2 on the ACDI interface (phi advanced by ACDI, each
       next ACDI step prepared during the transport, re-initialized from the
       VoF every 50 steps; the ACDI bound sets dt = 3.5e-4);
@@ -61,8 +62,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c1",
-                    choices=["c0", "c1", "c1i", "c1a", "c1f", "c1m", "c1v", "c2", "c2a", "c2x", "c3",
-                             "c4"])
+                    choices=["c0", "c1", "c1i", "c1a", "c1f", "c1m", "c1v", "c2", "c2a", "c2f", "c2x",
+                             "c3", "c4"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--implicit-graph", action="store_true",
@@ -95,6 +96,8 @@ def workload(name, K, W):
         return C.c2_axisymmetric()
     if name == "c2a":
         return C.c2_acdi()
+    if name == "c2f":
+        return C.c2_forces()
     return C.c2_translating_sphere()
 
 
@@ -308,7 +311,7 @@ def main():
         forces = None
         if cfg.get("forces"):  # capillary and Marangoni face arrays
             forces = tuple([torch.empty(s.face_shape(d), dtype=s.dtype, device=dev)
-                            for d in range(2)] for _ in range(2))
+                            for d in range(prob["dim"])] for _ in range(2))
 
         def reset():
             s.set_geometry(vof0, full=True)
@@ -416,16 +419,17 @@ def main():
         force_ms = None
         if forces is not None:  # the force kernel alone, back to back
             v_last = vofs[W + K - 1] if vofs is not None else vof0
-            for _ in range(10):
+            force_reps = FORCE_REPS if ncell <= (1 << 22) else 20
+            for _ in range(3):
                 s.interface_force(v_last, sig, out=forces)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(side)
-            for _ in range(FORCE_REPS):
+            for _ in range(force_reps):
                 s.interface_force(v_last, sig, out=forces)
             e1.record(side)
             side.synchronize()
-            force_ms = e0.elapsed_time(e1) / FORCE_REPS
+            force_ms = e0.elapsed_time(e1) / force_reps
 
     ms_per_step = ms_total / K
     value = ncell * K / (ms_total * 1e-3) / 1e9
@@ -466,7 +470,7 @@ def main():
     if mforce_ms is not None:
         fbpc = (2 + prob["dim"]) * es  # reads chi, sigma; writes the dim face arrays
         out["force"] = {
-            **roofline_of("k_force", fbpc * ncell, mforce_ms,
+            **roofline_of("k_force%d" % prob["dim"], fbpc * ncell, mforce_ms,
                           kernel_counters(cfg["name"], FORCE_COUNTERS)),
             "avg_launch_us": round(mforce_ms * 1e3, 3),
             "timing": "back-to-back surf_force calls between HIP events",
@@ -481,11 +485,15 @@ def main():
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ab * ncell / (acdi_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if force_ms is not None:
-        fb = FORCE_WORDS_PER_CELL * es
+        three = prob["dim"] == 3
+        # 2D: reads the VoF, writes four face arrays; 3D: reads the VoF, chi
+        # and sigma, writes six
+        fb = (9 if three else FORCE_WORDS_PER_CELL) * es
         out["config"]["interface_forces"] = True
         out["iface"] = {
-            "kernel": "k_iface_force", "avg_launch_us": round(force_ms * 1e3, 3),
-            "timing": "%d back-to-back launches between HIP events" % FORCE_REPS,
+            "kernel": "k_iface3_cells + k_iface3_faces" if three else "k_iface_force",
+            "avg_launch_us": round(force_ms * 1e3, 3),
+            "timing": "%d back-to-back calls between HIP events" % force_reps,
             "bytes_per_cell": fb, "achieved": round(fb * ncell / (force_ms * 1e-3) / 1e9, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(fb * ncell / (force_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -755,7 +763,7 @@ def bench_implicit(args):
         forces = None
         if cfg.get("forces"):  # capillary and Marangoni face arrays
             forces = tuple([torch.empty(s.face_shape(d), dtype=s.dtype, device=dev)
-                            for d in range(2)] for _ in range(2))
+                            for d in range(prob["dim"])] for _ in range(2))
 
         def reset():
             s.set_geometry(vof0, full=True)

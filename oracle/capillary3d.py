@@ -375,3 +375,74 @@ def forces(prob, vof, chi, sigma):
         cap.append(fc)
         ma.append(fm)
     return cap, ma
+
+
+# ---- one face at a time (for sampled comparisons on large boxes)
+def cell_kappa(prob, vof, chi, x):
+    """kappa of interfacial cell x: its height curvature, else the mean of
+    the height curvatures of the interfacial cells of its 3x3x3 block (dz,
+    dy, dx from -1 to 1), else the level-set curvature moved to the
+    interface."""
+    kk = height_curvature(prob, vof, x)
+    if kk is not None:
+        return kk
+    q = O.full(prob)
+    per = _axes(q)
+    v = np.asarray(vof, dtype=np.float64)
+    s, cnt = 0.0, 0
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dx == 0 and dy == 0 and dz == 0:
+                    continue
+                y = [x[0] + dx, x[1] + dy, x[2] + dz]
+                if not interfacial(_at(v, y, q, per)):
+                    continue
+                y = [_map(y[e], q["n"][e], per[e]) for e in range(3)]
+                val = height_curvature(prob, vof, y)
+                if val is not None:
+                    s += val
+                    cnt += 1
+    return s / cnt if cnt else levelset_curvature(prob, chi, x)
+
+
+def face_force(prob, vof, chi, sigma, d, face):
+    """(capillary, Marangoni) on the face along d with index face = (i, j, k)
+    in the face layout (coordinate d runs to n_d), as forces() gives it."""
+    q = O.full(prob)
+    per = _axes(q)
+    h = q["h"]
+    n = q["n"]
+    f = face[d]
+    if (f == 0 or f == n[d]) and not per[d]:
+        return 0.0, 0.0
+    v = np.asarray(vof, dtype=np.float64)
+    sg = np.asarray(sigma, dtype=np.float64)
+    ch = np.asarray(chi, dtype=np.float64)
+    R = list(face)
+    R[d] = f % n[d]
+    L = list(R)
+    L[d] = (f - 1) % n[d]
+    cL, cR = v[L[2], L[1], L[0]], v[R[2], R[1], R[0]]
+    cutL, cutR = interfacial(cL), interfacial(cR)
+    kL = cell_kappa(prob, vof, chi, L) if cutL else 0.0
+    kR = cell_kappa(prob, vof, chi, R) if cutR else 0.0
+    kf = 0.5 * (kL + kR) if cutL and cutR else (kL if cutL else (kR if cutR else 0.0))
+    sf = 0.5 * (sg[L[2], L[1], L[0]] + sg[R[2], R[1], R[0]])
+    cap = -sf * kf * (cR - cL) / h
+
+    def grad(a):
+        g = [0.0, 0.0, 0.0]
+        g[d] = (a[R[2], R[1], R[0]] - a[L[2], L[1], L[0]]) / h
+        for t in range(3):
+            if t != d:
+                for X in (L, R):
+                    g[t] += 0.5 * (_at(a, _off(X, t, 1), q, per) -
+                                   _at(a, _off(X, t, -1), q, per)) / (2 * h)
+        return g
+    gs, gc = grad(sg), grad(ch)
+    nrm = max(math.sqrt(gc[0] ** 2 + gc[1] ** 2 + gc[2] ** 2), 1e-6)
+    nn = [gc[e] / nrm for e in range(3)]
+    ndot = nn[0] * gs[0] + nn[1] * gs[1] + nn[2] * gs[2]
+    dmf = 0.5 * (cell_delta(prob, vof, L) + cell_delta(prob, vof, R))
+    return cap, dmf * (gs[d] - nn[d] * ndot)

@@ -138,6 +138,17 @@ def c2_translating_sphere(n=256):
                 c0=None, c0_const=1.0, gamma0=0.0, hj_step=16)
 
 
+def c2_forces(n=256):
+    """The translating sphere of C2 with the interfacial forces of the flow
+    coupling (section 2.4) evaluated after every step, in 3D: capillary and
+    Marangoni forces on the three face sets from the step's VoF and the sigma
+    it returns; the rest as C2."""
+    cfg = dict(c2_translating_sphere(n))
+    cfg["name"] = "translating sphere %d^3 fp32 forces" % n
+    cfg["forces"] = True
+    return cfg
+
+
 def c2_acdi(n=256, reinit_every=50):
     """The translating sphere of C2 on the ACDI interface (section 2.5): phi
     advanced by one ACDI step per step with zeta = 0.82 (1.1 times the

@@ -1229,13 +1229,12 @@ int force_impl(surf_ctx* c, const void* sigma, void* const* force) {
   if (c->grid.dim == 2) {
     constexpr int TX = 64, TY = 8;
     const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY;
-    hipLaunchKernelGGL((k_force<R, 2, TX, TY, 1>), dim3(tx * ty), dim3(TX * TY), 0, c->stream,
-                       c->g, p, chi, (const R*)sigma, (R*)force[0], (R*)force[1], (R*)nullptr,
-                       tx, ty);
+    hipLaunchKernelGGL((k_force2<R, TX, TY>), dim3(tx * ty), dim3(TX * TY), 0, c->stream, c->g,
+                       p, chi, (const R*)sigma, (R*)force[0], (R*)force[1], tx);
   } else {
-    constexpr int TX = 32, TY = 8, TZ = 2;
-    const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY, tz = (nz + TZ - 1) / TZ;
-    hipLaunchKernelGGL((k_force<R, 3, TX, TY, TZ>), dim3(tx * ty * tz), dim3(TX * TY * TZ), 0,
+    constexpr int TX = 64, TY = 8, ZC = 16;
+    const int tx = (nx + TX - 1) / TX, ty = (ny + TY - 1) / TY, tz = (nz + ZC - 1) / ZC;
+    hipLaunchKernelGGL((k_force3<R, TX, TY, ZC>), dim3(tx * ty * tz), dim3(TX * TY), 0,
                        c->stream, c->g, p, chi, (const R*)sigma, (R*)force[0], (R*)force[1],
                        (R*)force[2], tx, ty);
   }
@@ -1262,7 +1261,11 @@ int iface_force_impl(surf_ctx* c, const void* vof, const void* sigma, void* cons
 }
 
 // 3D: the cells pass into two scratch cell arrays (the pin-data buffer and
-// the idle level-set buffer, both free between steps), then the faces pass
+// the idle level-set buffer), then the faces pass.  The moving geometry
+// rewrites the pin data of its live tiles before it reads them, but it takes
+// the idle buffer to hold the clamp wherever that buffer's flag says so: its
+// flags are set live afterwards, so that the next geometry writes the clamp
+// back into every tile it finds quiescent.
 template <typename R>
 int iface3_force_impl(surf_ctx* c, const void* vof, const void* sigma, void* const* cap,
                       void* const* ma) {
@@ -1275,12 +1278,22 @@ int iface3_force_impl(surf_ctx* c, const void* vof, const void* sigma, void* con
   a.kh = (R*)c->g0;
   a.dm = (R*)c->chi[1 - c->chi_cur];
   a.h = c->grid.h;
-  const dim3 gr(grid1d(c->ncell)), bl(256);
-  hipLaunchKernelGGL(k_iface3_cells<R>, gr, bl, 0, c->stream, a);
-  hipLaunchKernelGGL(k_iface3_faces<R>, gr, bl, 0, c->stream, a, cap ? (R*)cap[0] : nullptr,
+  const int nx = c->grid.n[0], ny = c->grid.n[1], nz = c->grid.n[2];
+  const int tx = (nx + IF3_TX - 1) / IF3_TX, ty = (ny + IF3_TY - 1) / IF3_TY;
+  const long long tiles = (long long)tx * ty * ((nz + IF3_TZ - 1) / IF3_TZ);
+  const int chunks = (nx + 255) / 256;
+  const long long rows = (long long)chunks * ny * nz;
+  if (tiles >= (1ll << 31) || rows >= (1ll << 31)) return SURF_EINVAL;
+  hipLaunchKernelGGL(k_iface3_cells<R>, dim3((unsigned)tiles), dim3(IF3_NT), 0, c->stream, a,
+                     tx, ty);
+  hipLaunchKernelGGL(k_iface3_faces<R>, dim3((unsigned)rows), dim3(256), 0, c->stream, a, chunks,
+                     cap ? (R*)cap[0] : nullptr,
                      cap ? (R*)cap[1] : nullptr, cap ? (R*)cap[2] : nullptr,
                      ma ? (R*)ma[0] : nullptr, ma ? (R*)ma[1] : nullptr,
                      ma ? (R*)ma[2] : nullptr);
+  if (c->nflags > 0)
+    hipLaunchKernelGGL(k_fill_u8, dim3((c->nflags + BLOCK - 1) / BLOCK), dim3(BLOCK), 0,
+                       c->stream, c->q[1 - c->chi_cur], (uint8_t)Q_LIVE, c->nflags);
   return status_of_launch();
 }
 

@@ -24,11 +24,14 @@
 //     unit cube on its side m.x <= alpha, A_f its area inside the cube.  With
 //     the axes reflected so that n = |m| / |m|_1 >= 0 and k the axis of n's
 //     largest component, the plane is z_k = (alpha - L)/n_k over the unit
-//     square of the other two axes, L = n_i x_i + n_j x_j, so the volume below
-//     it is the area of {L <= alpha - n_k} plus the integral of (alpha -
-//     L)/n_k over the band {alpha - n_k <= L <= alpha}, and A_f is the band's
-//     area times |n| / n_k.  Both come from the unit square clipped by
-//     half-planes (no division by a small component); alpha by bisection.
+//     square of the other two axes, L = n_i x_i + n_j x_j.  With G(t) the
+//     area of {L <= t} in the square (piecewise quadratic in t) and I(t) its
+//     integral from 0 (piecewise cubic), the volume below the plane is
+//     (I(alpha) - I(alpha - n_k)) / n_k and A_f = (G(alpha) - G(alpha - n_k))
+//     |n| / n_k: no division by a small component (n_k >= 1/3, and the
+//     pieces of G and I that divide by n_i or n_j are taken only on their
+//     own intervals).  alpha by Newton's method on that volume inside a
+//     shrinking bracket, bisecting when a step leaves it.
 // On a face kappa is the mean over its interfacial cells, delta_m and sigma
 // the means of both; grad_s sigma is the face gradient of sigma (compact
 // normal difference, the two cells' centred transverse differences averaged)
@@ -36,12 +39,17 @@
 // open sides carry no force; on a periodic axis the last face repeats the
 // first.  The geometry runs in FP64 in both precisions.
 //
-// Two launches, one thread per cell: k_iface3_cells leaves every cell's
-// height curvature (NaN where no axis closes, 0 away from the interface)
-// and delta_m in two scratch cell arrays; k_iface3_faces writes the cell's
-// low face along each axis (and the last cell its high face), filling in
-// the curvature of a cell without heights from the first array, which no
-// thread writes.
+// Two launches.  k_iface3_cells takes a 64 x 4 x 2 tile per workgroup, lists
+// the tile's interfacial cells in LDS and gives them to its first threads (a
+// sphere's surface leaves a few dozen per tile, so the heavy work packs into
+// one wave instead of one per row of the tile); it writes each listed cell's
+// height curvature (NaN where no axis closes) and delta_m into two scratch
+// cell arrays, and nothing for the other cells.  k_iface3_faces, one thread
+// per cell, writes the cell's low face along each axis (and the last cell
+// its high face), reading the scratch arrays only at interfacial cells and
+// filling in the curvature of a cell without heights from the first array,
+// which no thread writes.  A face with neither cell interfacial has both
+// forces zero and reads nothing past the two fractions.
 #pragma once
 #include "surf_capillary.hpp"
 
@@ -71,70 +79,29 @@ __device__ __forceinline__ double if3_at(const R* a, const Grid& g, int x, int y
 }
 
 // ---- PLIC area in the unit cube
-struct Poly {
-  double x[8], y[8];
-  int n;
-};
-
-// the part of polygon P where s (a x + b y - t) <= 0 (s = +-1)
-__device__ __forceinline__ void poly_clip(const Poly& P, double a, double b, double t, double s,
-                                          Poly& Q) {
-  Q.n = 0;
-  for (int v = 0; v < P.n; ++v) {
-    const int w = v + 1 == P.n ? 0 : v + 1;
-    const double fa = s * (a * P.x[v] + b * P.y[v] - t);
-    const double fb = s * (a * P.x[w] + b * P.y[w] - t);
-    if (fa <= 0.0) {
-      Q.x[Q.n] = P.x[v];
-      Q.y[Q.n] = P.y[v];
-      ++Q.n;
-    }
-    if ((fa < 0.0 && fb > 0.0) || (fb < 0.0 && fa > 0.0)) {
-      const double u = fa / (fa - fb);
-      Q.x[Q.n] = P.x[v] + u * (P.x[w] - P.x[v]);
-      Q.y[Q.n] = P.y[v] + u * (P.y[w] - P.y[v]);
-      ++Q.n;
-    }
-  }
+// G(t) = area of {a x + b y <= t} in the unit square and I(t) = its integral
+// over [0, t], for 0 <= a <= b: with s = a + b, G is t^2 / (2ab) on [0, a],
+// (t - a/2) / b on [a, b] and symmetric about (s/2, 1/2) (the square's
+// centre), so I(t) = t - s/2 + I(s - t) past s/2.
+__device__ __forceinline__ double plic_G(double a, double b, double t) {
+  const double s = a + b;
+  if (t <= 0.0) return 0.0;
+  if (t >= s) return 1.0;
+  const bool flip = t > 0.5 * s;
+  const double u = flip ? s - t : t;  // in (0, s/2], so u <= b
+  const double g = u <= a ? u * u / (2.0 * a * b) : (u - 0.5 * a) / b;
+  return flip ? 1.0 - g : g;
 }
 
-// area and the integral of a x + b y over a counter-clockwise polygon
-__device__ __forceinline__ void poly_moments(const Poly& P, double a, double b, double& area,
-                                             double& lin) {
-  double s = 0.0, mx = 0.0, my = 0.0;
-  for (int v = 0; v < P.n; ++v) {
-    const int w = v + 1 == P.n ? 0 : v + 1;
-    const double cr = P.x[v] * P.y[w] - P.x[w] * P.y[v];
-    s += cr;
-    mx += (P.x[v] + P.x[w]) * cr;
-    my += (P.y[v] + P.y[w]) * cr;
-  }
-  area = 0.5 * s;
-  lin = (a * mx + b * my) / 6.0;
-}
-
-__device__ __forceinline__ void unit_square(Poly& P) {
-  P.n = 4;
-  P.x[0] = 0.0; P.y[0] = 0.0;
-  P.x[1] = 1.0; P.y[1] = 0.0;
-  P.x[2] = 1.0; P.y[2] = 1.0;
-  P.x[3] = 0.0; P.y[3] = 1.0;
-}
-
-// the volume below the plane L + nk z = alpha in the unit cube, and the area
-// of the band {alpha - nk <= L <= alpha} of the unit square
-__device__ __forceinline__ double plic_vol3(double ni, double nj, double nk, double alpha,
-                                            double& band) {
-  Poly S, lowP, B1, B2;
-  unit_square(S);
-  poly_clip(S, ni, nj, alpha - nk, 1.0, lowP);  // L <= alpha - nk
-  double alow, dummy;
-  poly_moments(lowP, ni, nj, alow, dummy);
-  poly_clip(S, ni, nj, alpha - nk, -1.0, B1);   // L >= alpha - nk
-  poly_clip(B1, ni, nj, alpha, 1.0, B2);        // L <= alpha
-  double lin;
-  poly_moments(B2, ni, nj, band, lin);
-  return alow + (alpha * band - lin) / nk;
+__device__ __forceinline__ double plic_I(double a, double b, double t) {
+  const double s = a + b;
+  if (t <= 0.0) return 0.0;
+  if (t >= s) return t - 0.5 * s;
+  const bool flip = t > 0.5 * s;
+  const double u = flip ? s - t : t;
+  const double v =
+      u <= a ? u * u * u / (6.0 * a * b) : a * a / (6.0 * b) + (u * u - a * u) / (2.0 * b);
+  return flip ? t - 0.5 * s + v : v;
 }
 
 __device__ double plic_area3(double m0, double m1, double m2, double c) {
@@ -148,16 +115,26 @@ __device__ double plic_area3(double m0, double m1, double m2, double c) {
   int k = 2;
   if (n[1] > n[k]) k = 1;
   if (n[0] > n[k]) k = 0;
-  const double nk = n[k], ni = n[k == 0 ? 1 : 0], nj = n[k == 2 ? 1 : 2];
-  double lo = 0.0, hi = 1.0, band = 0.0;
+  const double nk = n[k], p = n[k == 0 ? 1 : 0], q = n[k == 2 ? 1 : 2];
+  const double a = fmin(p, q), b = fmax(p, q);
+  // the plane leaves the same area cutting off 1 - c from the opposite
+  // corner: solve for the smaller volume, where V and G carry no cancellation
+  if (c > 0.5) c = 1.0 - c;
+  // V(alpha) = (I(alpha) - I(alpha - nk)) / nk rises from 0 to 1 on [0, 1]
+  double lo = 0.0, hi = 1.0, al = c;
   for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid == lo || mid == hi) break;
-    if (plic_vol3(ni, nj, nk, mid, band) < c) lo = mid;
-    else hi = mid;
+    const double f = (plic_I(a, b, al) - plic_I(a, b, al - nk)) / nk - c;
+    if (f == 0.0) break;
+    if (f < 0.0) lo = al;
+    else hi = al;
+    const double dv = (plic_G(a, b, al) - plic_G(a, b, al - nk)) / nk;
+    double nx = dv > 0.0 ? al - f / dv : 0.5 * (lo + hi);
+    if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
+    if (nx == al) break;
+    al = nx;
   }
-  (void)plic_vol3(ni, nj, nk, 0.5 * (lo + hi), band);
-  return band * sqrt(ni * ni + nj * nj + nk * nk) / nk;
+  const double band = plic_G(a, b, al) - plic_G(a, b, al - nk);
+  return band * sqrt(nk * nk + a * a + b * b) / nk;
 }
 
 // ---- the cells pass
@@ -233,26 +210,45 @@ __device__ bool if3_heights(const Iface3Args<R>& a, int x, int y, int z, const d
   return false;
 }
 
+constexpr int IF3_TX = 64, IF3_TY = 4, IF3_TZ = 2, IF3_NT = IF3_TX * IF3_TY * IF3_TZ;
+
 template <typename R>
-__global__ void __launch_bounds__(256) k_iface3_cells(Iface3Args<R> a) {
+__global__ void __launch_bounds__(IF3_NT) k_iface3_cells(Iface3Args<R> a, int tiles_x,
+                                                        int tiles_y) {
+  __shared__ int sList[IF3_NT];
+  __shared__ int sWave[IF3_NT / 64];
   const Grid& g = a.g;
-  const long long n = (long long)g.n[0] * g.n[1] * g.n[2];
-  for (long long cl = (long long)blockIdx.x * 256 + threadIdx.x; cl < n;
-       cl += (long long)gridDim.x * 256) {
-    const int x = (int)(cl % g.n[0]);
-    const int y = (int)((cl / g.n[0]) % g.n[1]);
-    const int z = (int)(cl / ((long long)g.n[0] * g.n[1]));
-    const double c = (double)a.vof[cl];
-    double kap = 0.0, dm = 0.0;
-    if (if3_cut(c)) {
-      double m[3];
-      if3_youngs(a, x, y, z, m);
-      if (!if3_heights(a, x, y, z, m, kap)) kap = (double)NAN;
-      dm = plic_area3(m[0], m[1], m[2], c) / a.h;
-    }
-    a.kh[cl] = (R)kap;
-    a.dm[cl] = (R)dm;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int bx = blockIdx.x % tiles_x, r = blockIdx.x / tiles_x;
+  const int x0 = bx * IF3_TX, y0 = (r % tiles_y) * IF3_TY, z0 = (r / tiles_y) * IF3_TZ;
+  int x = x0 + t % IF3_TX, y = y0 + (t / IF3_TX) % IF3_TY, z = z0 + t / (IF3_TX * IF3_TY);
+  const bool cut = x < g.n[0] && y < g.n[1] && z < g.n[2] &&
+                   if3_cut((double)a.vof[cell_index(g, x, y, z)]);
+  // the tile's interfacial cells, in thread order
+  const unsigned long long bal = __ballot(cut);
+  if (lane == 0) sWave[w] = __popcll(bal);
+  __syncthreads();
+  int base = 0, total = 0;
+#pragma unroll
+  for (int v = 0; v < IF3_NT / 64; ++v) {
+    const int cnt = sWave[v];
+    base += v < w ? cnt : 0;
+    total += cnt;
   }
+  if (cut) sList[base + __popcll(bal & ((1ull << lane) - 1ull))] = t;
+  __syncthreads();
+  if (t >= total) return;
+  const int u = sList[t];
+  x = x0 + u % IF3_TX;
+  y = y0 + (u / IF3_TX) % IF3_TY;
+  z = z0 + u / (IF3_TX * IF3_TY);
+  const long long cl = cell_index(g, x, y, z);
+  const double c = (double)a.vof[cl];
+  double m[3], kap = 0.0;
+  if3_youngs(a, x, y, z, m);
+  if (!if3_heights(a, x, y, z, m, kap)) kap = (double)NAN;
+  a.kh[cl] = (R)kap;
+  a.dm[cl] = (R)(plic_area3(m[0], m[1], m[2], c) / a.h);
 }
 
 // ---- the faces pass
@@ -328,6 +324,9 @@ __device__ void if3_face(const Iface3Args<R>& a, int d, const int* L, const int*
   const long long iL = cell_index(a.g, L[0], L[1], L[2]), iR = cell_index(a.g, Rc[0], Rc[1], Rc[2]);
   const double cL = (double)a.vof[iL], cR = (double)a.vof[iR];
   const bool cutL = if3_cut(cL), cutR = if3_cut(cR);
+  cap = ma = 0.0;
+  // kappa and delta_m vanish on both sides: so do both forces
+  if (!cutL && !cutR) return;
   const double kL = cutL ? if3_kappa(a, L[0], L[1], L[2]) : 0.0;
   const double kR = cutR ? if3_kappa(a, Rc[0], Rc[1], Rc[2]) : 0.0;
   const double kf = cutL && cutR ? 0.5 * (kL + kR) : (cutL ? kL : (cutR ? kR : 0.0));
@@ -340,41 +339,40 @@ __device__ void if3_face(const Iface3Args<R>& a, int d, const int* L, const int*
   const double n0 = gc[0] / nrm, n1 = gc[1] / nrm, n2 = gc[2] / nrm;
   const double nd = d == 0 ? n0 : (d == 1 ? n1 : n2);
   const double ndot = n0 * gs[0] + n1 * gs[1] + n2 * gs[2];
-  const double dmf = 0.5 * ((double)a.dm[iL] + (double)a.dm[iR]);
+  const double dmf = 0.5 * ((cutL ? (double)a.dm[iL] : 0.0) + (cutR ? (double)a.dm[iR] : 0.0));
   ma = dmf * (gs[d] - nd * ndot);
 }
 
+// one thread per cell: rows of the box along x in chunks of 256, a workgroup
+// per (chunk, y, z)
 template <typename R>
-__global__ void __launch_bounds__(256) k_iface3_faces(Iface3Args<R> a, R* cx, R* cy, R* cz,
-                                                      R* mx, R* my, R* mz) {
+__global__ void __launch_bounds__(256) k_iface3_faces(Iface3Args<R> a, int chunks_x, R* cx,
+                                                      R* cy, R* cz, R* mx, R* my, R* mz) {
   const Grid& g = a.g;
   R* cap[3] = {cx, cy, cz};
   R* ma[3] = {mx, my, mz};
-  const long long n = (long long)g.n[0] * g.n[1] * g.n[2];
-  for (long long cl = (long long)blockIdx.x * 256 + threadIdx.x; cl < n;
-       cl += (long long)gridDim.x * 256) {
-    const int x = (int)(cl % g.n[0]);
-    const int y = (int)((cl / g.n[0]) % g.n[1]);
-    const int z = (int)(cl / ((long long)g.n[0] * g.n[1]));
-    const int X[3] = {x, y, z};
-    for (int d = 0; d < 3; ++d) {
-      const bool per = g.bc[d][0] == BC_PERIODIC;
-      // the low face of the cell, and the high face for the last cell
-      for (int side = 0; side < (X[d] + 1 == g.n[d] ? 2 : 1); ++side) {
-        const int f = X[d] + side;  // face coordinate along d
-        double fc = 0.0, fm = 0.0;
-        if (per || (f > 0 && f < g.n[d])) {
-          int Rc[3] = {x, y, z}, L[3] = {x, y, z};
-          Rc[d] = f % g.n[d];
-          L[d] = (f - 1 + g.n[d]) % g.n[d];
-          if3_face(a, d, L, Rc, fc, fm);
-        }
-        int F[3] = {x, y, z};
-        F[d] = f;
-        const long long fi = face_index(g, d, F[0], F[1], F[2]);
-        if (cap[d]) cap[d][fi] = (R)fc;
-        if (ma[d]) ma[d][fi] = (R)fm;
+  const int row = blockIdx.x / chunks_x;
+  const int x = (blockIdx.x % chunks_x) * 256 + threadIdx.x;
+  const int y = row % g.n[1], z = row / g.n[1];
+  if (x >= g.n[0]) return;
+  const int X[3] = {x, y, z};
+  for (int d = 0; d < 3; ++d) {
+    const bool per = g.bc[d][0] == BC_PERIODIC;
+    // the low face of the cell, and the high face for the last cell
+    for (int side = 0; side < (X[d] + 1 == g.n[d] ? 2 : 1); ++side) {
+      const int f = X[d] + side;  // face coordinate along d
+      double fc = 0.0, fm = 0.0;
+      if (per || (f > 0 && f < g.n[d])) {
+        int Rc[3] = {x, y, z}, L[3] = {x, y, z};
+        Rc[d] = f % g.n[d];
+        L[d] = (f - 1 + g.n[d]) % g.n[d];
+        if3_face(a, d, L, Rc, fc, fm);
       }
+      int F[3] = {x, y, z};
+      F[d] = f;
+      const long long fi = face_index(g, d, F[0], F[1], F[2]);
+      if (cap[d]) cap[d][fi] = (R)fc;
+      if (ma[d]) ma[d][fi] = (R)fm;
     }
   }
 }

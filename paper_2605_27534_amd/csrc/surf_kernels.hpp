@@ -9,7 +9,7 @@
 //              6) and per-workgroup FP64 partial reductions
 //   k_finalize deterministic reduction of the partials -> totals, status
 //   k_init     F = c0 phi, psi = gamma0 delta
-//   k_force    Marangoni face force (section 2.4)
+//   k_force2/3 Marangoni face force (section 2.4)
 #pragma once
 #include "surf_common.hpp"
 
@@ -619,113 +619,208 @@ __global__ void k_set_time(double* state, const double* t) {
 // gradient of a cell field takes the compact difference across the face for
 // its normal component and the centred transverse differences of the two
 // cells, averaged, for the others; dbar is the mean delta of the two cells.
+// The divisions by h and by the norm are multiplications by reciprocals.
 //
-// Work unit: a tile of TX x TY (x TZ) cells, one thread per cell; chi, sigma
-// and delta of the tile and a one-cell halo (corners included: the
-// transverse differences of the cell across the face) are staged in LDS,
-// with mirrored ghosts at walls and open sides and wrapped ones on periodic
-// axes.  Each thread writes the low face of its cell along every axis; the
+// 2D work unit: a tile of TX x TY cells, one thread per cell; chi, sigma and
+// delta of the tile and a one-cell halo (corners included: the transverse
+// differences of the cell across the face) are staged in LDS, with mirrored
+// ghosts at walls and open sides and wrapped ones on periodic axes.  3D: a
+// TX x TY column tile marching along z over ZC planes, three planes (z - 1,
+// z, z + 1, each with its halo ring) in an LDS ring, so that a plane is
+// loaded and its delta evaluated once per chunk instead of once per tile
+// layer.  Each thread writes the low face of its cell along every axis; the
 // last cell along an axis also writes the high face (zero on a wall or open
 // side, on a periodic axis the value of face 0, computed from the same two
 // cells in the same order).  Tile and cell indices are 32-bit (no 64-bit
 // division).
-template <typename R, int DIM, int TX, int TY, int TZ>
-struct ForceLds {
-  static constexpr int HX = TX + 2, HY = TY + 2, HZ = DIM == 3 ? TZ + 2 : 1;
-  R chi[HZ][HY][HX], sig[HZ][HY][HX], del[HZ][HY][HX];
-};
-
-template <typename R, int DIM, int TX, int TY, int TZ>
-__device__ __forceinline__ R force_face(const ForceLds<R, DIM, TX, TY, TZ>& L, const Par<R>& p,
-                                        const int d, const int lx, const int ly, const int lz) {
-  // cells L (low side) and R (high side) of the face along d, in LDS coordinates
-  int rl[3] = {lx, ly, lz};
-  int ll[3] = {lx, ly, lz};
-  ll[d] -= 1;
-  R gn[3] = {R(0), R(0), R(0)}, gs[3] = {R(0), R(0), R(0)};
-#pragma unroll
-  for (int e = 0; e < DIM; ++e) {
-    if (e == d) {
-      gn[e] = (L.chi[rl[2]][rl[1]][rl[0]] - L.chi[ll[2]][ll[1]][ll[0]]) / p.h;
-      gs[e] = (L.sig[rl[2]][rl[1]][rl[0]] - L.sig[ll[2]][ll[1]][ll[0]]) / p.h;
-    } else {
-      int a[3] = {ll[0], ll[1], ll[2]}, b[3] = {ll[0], ll[1], ll[2]};
-      int c[3] = {rl[0], rl[1], rl[2]}, q[3] = {rl[0], rl[1], rl[2]};
-      a[e] += 1;
-      b[e] -= 1;
-      c[e] += 1;
-      q[e] -= 1;
-      const R tln = L.chi[a[2]][a[1]][a[0]] - L.chi[b[2]][b[1]][b[0]];
-      const R trn = L.chi[c[2]][c[1]][c[0]] - L.chi[q[2]][q[1]][q[0]];
-      const R tls = L.sig[a[2]][a[1]][a[0]] - L.sig[b[2]][b[1]][b[0]];
-      const R trs = L.sig[c[2]][c[1]][c[0]] - L.sig[q[2]][q[1]][q[0]];
-      gn[e] = (tln + trn) / (R(4) * p.h);
-      gs[e] = (tls + trs) / (R(4) * p.h);
-    }
+template <typename R>
+__device__ __forceinline__ R force_finish(const R* gn, const R* gs, int dim, int d, R dbar) {
+  R nrm = R(0), dot = R(0);
+  for (int e = 0; e < dim; ++e) {
+    nrm += gn[e] * gn[e];
+    dot += gn[e] * gs[e];
   }
-  R nrm = R(0);
-#pragma unroll
-  for (int e = 0; e < DIM; ++e) nrm += gn[e] * gn[e];
   nrm = rsqrt_<R>(nrm);
-  nrm = nrm < R(1e-6) ? R(1e-6) : nrm;
-  R ndot = R(0);
-#pragma unroll
-  for (int e = 0; e < DIM; ++e) ndot += gn[e] / nrm * gs[e];
-  const R dbar = R(0.5) * (L.del[ll[2]][ll[1]][ll[0]] + L.del[rl[2]][rl[1]][rl[0]]);
-  return dbar * (gs[d] - gn[d] / nrm * ndot);
+  const R inv = rrcp<R>(nrm < R(1e-6) ? R(1e-6) : nrm);
+  return dbar * (gs[d] - gn[d] * inv * (dot * inv));
 }
 
-template <typename R, int DIM, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(TX * TY * TZ) k_force(Grid g, Par<R> p,
-                                                        const R* __restrict__ chi,
-                                                        const R* __restrict__ sig,
-                                                        R* __restrict__ fx, R* __restrict__ fy,
-                                                        R* __restrict__ fz, int tiles_x,
-                                                        int tiles_y) {
-  using Lds = ForceLds<R, DIM, TX, TY, TZ>;
-  constexpr int NT = TX * TY * TZ, HX = Lds::HX, HY = Lds::HY, HZ = Lds::HZ;
+template <typename R, int TX, int TY>
+struct ForceLds2 {
+  static constexpr int HX = TX + 2, HY = TY + 2;
+  R chi[HY][HX], sig[HY][HX], del[HY][HX];
+};
+
+// 2D: the face along d whose high-side cell is (lx, ly) in LDS coordinates
+template <typename R, int TX, int TY>
+__device__ __forceinline__ R force_face2(const ForceLds2<R, TX, TY>& L, const Par<R>& p,
+                                         const int d, const int lx, const int ly) {
+  const R ih = p.inv_h, iq = R(0.25) * p.inv_h;
+  const int ax = lx - (d == 0), ay = ly - (d == 1);  // the low-side cell
+  const int tx = d == 1, ty = d == 0;                // one step along the other axis
+  R gn[2], gs[2];
+  gn[d] = (L.chi[ly][lx] - L.chi[ay][ax]) * ih;
+  gs[d] = (L.sig[ly][lx] - L.sig[ay][ax]) * ih;
+  gn[1 - d] = ((L.chi[ay + ty][ax + tx] - L.chi[ay - ty][ax - tx]) +
+               (L.chi[ly + ty][lx + tx] - L.chi[ly - ty][lx - tx])) * iq;
+  gs[1 - d] = ((L.sig[ay + ty][ax + tx] - L.sig[ay - ty][ax - tx]) +
+               (L.sig[ly + ty][lx + tx] - L.sig[ly - ty][lx - tx])) * iq;
+  return force_finish<R>(gn, gs, 2, d, R(0.5) * (L.del[ay][ax] + L.del[ly][lx]));
+}
+
+template <typename R, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) k_force2(Grid g, Par<R> p, const R* __restrict__ chi,
+                                                    const R* __restrict__ sig,
+                                                    R* __restrict__ fx, R* __restrict__ fy,
+                                                    int tiles_x) {
+  using Lds = ForceLds2<R, TX, TY>;
+  constexpr int NT = TX * TY, HX = Lds::HX, HY = Lds::HY;
   __shared__ Lds L;
-  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-  const int b = blockIdx.x;
-  const int bx = b % tiles_x, r = b / tiles_x;
-  const int by = r % tiles_y, bz = r / tiles_y;
-  const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
-  for (int l = threadIdx.x; l < HX * HY * HZ; l += NT) {
-    const int lx = l % HX, ly = (l / HX) % HY, lz = l / (HX * HY);
+  const int nx = g.n[0], ny = g.n[1];
+  const int x0 = (blockIdx.x % tiles_x) * TX, y0 = (blockIdx.x / tiles_x) * TY;
+  for (int l = threadIdx.x; l < HX * HY; l += NT) {
+    const int lx = l % HX, ly = l / HX;
     const int gx = map_axis(x0 - 1 + lx, nx, g.bc[0][0], g.bc[0][1]);
     const int gy = map_axis(y0 - 1 + ly, ny, g.bc[1][0], g.bc[1][1]);
-    const int gz = DIM == 3 ? map_axis(z0 - 1 + lz, nz, g.bc[2][0], g.bc[2][1]) : 0;
-    const long long ci = cell_index(g, gx, gy, gz);
+    const long long ci = (long long)gx + (long long)nx * gy;
     const R c = chi[ci];
     R ph, om, de;
     phase<R>(c, p, ph, om, de);
-    L.chi[lz][ly][lx] = c;
-    L.sig[lz][ly][lx] = sig[ci];
-    L.del[lz][ly][lx] = de;
+    L.chi[ly][lx] = c;
+    L.sig[ly][lx] = sig[ci];
+    L.del[ly][lx] = de;
   }
   __syncthreads();
-  const int tx = threadIdx.x % TX, ty = (threadIdx.x / TX) % TY, tz = threadIdx.x / (TX * TY);
-  const int cx = x0 + tx, cy = y0 + ty, cz = z0 + tz;
-  if (cx >= nx || cy >= ny || cz >= nz) return;
-  const int lx = tx + 1, ly = ty + 1, lz = DIM == 3 ? tz + 1 : 0;
-  const int cc[3] = {cx, cy, cz};
-  R* const out[3] = {fx, fy, fz};
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    const bool per = g.bc[d][0] == BC_PERIODIC;
-    const int nd = g.n[d];
-    int fi[3] = {cx, cy, cz};
-    // low face of the cell
-    R v = (cc[d] == 0 && !per) ? R(0) : force_face<R, DIM, TX, TY, TZ>(L, p, d, lx, ly, lz);
-    out[d][face_index(g, d, fi[0], fi[1], fi[2])] = v;
-    if (cc[d] == nd - 1) {
-      // high face: the face between this cell and the next one along d
-      int hl[3] = {lx, ly, lz};
-      hl[d] += 1;
-      R w = per ? force_face<R, DIM, TX, TY, TZ>(L, p, d, hl[0], hl[1], hl[2]) : R(0);
-      fi[d] = nd;
-      out[d][face_index(g, d, fi[0], fi[1], fi[2])] = w;
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int cx = x0 + tx, cy = y0 + ty;
+  if (cx >= nx || cy >= ny) return;
+  const int lx = tx + 1, ly = ty + 1;
+  // x faces: [ny][nx + 1]
+  {
+    const bool per = g.bc[0][0] == BC_PERIODIC;
+    const long long row = (long long)cy * (nx + 1);
+    fx[row + cx] = (cx == 0 && !per) ? R(0) : force_face2<R, TX, TY>(L, p, 0, lx, ly);
+    if (cx == nx - 1) fx[row + nx] = per ? force_face2<R, TX, TY>(L, p, 0, lx + 1, ly) : R(0);
+  }
+  // y faces: [ny + 1][nx]
+  {
+    const bool per = g.bc[1][0] == BC_PERIODIC;
+    fy[(long long)cy * nx + cx] = (cy == 0 && !per) ? R(0) : force_face2<R, TX, TY>(L, p, 1, lx, ly);
+    if (cy == ny - 1)
+      fy[(long long)ny * nx + cx] = per ? force_face2<R, TX, TY>(L, p, 1, lx, ly + 1) : R(0);
+  }
+}
+
+template <typename R, int TX, int TY>
+struct ForceLds3 {
+  static constexpr int HX = TX + 2, HY = TY + 2;
+  R chi[3][HY][HX], sig[3][HY][HX], del[3][HY][HX];
+};
+
+// 3D, a face in the plane (d = 0 or 1): its two cells in plane slot s0, the
+// planes below and above in slots sm and sp; (lx, ly) is the high-side cell
+template <typename R, int TX, int TY>
+__device__ __forceinline__ R force_face3_xy(const ForceLds3<R, TX, TY>& L, const Par<R>& p,
+                                            const int d, const int sm, const int s0,
+                                            const int sp, const int lx, const int ly) {
+  const R ih = p.inv_h, iq = R(0.25) * p.inv_h;
+  const int ax = lx - (d == 0), ay = ly - (d == 1);
+  const int tx = d == 1, ty = d == 0;
+  R gn[3], gs[3];
+  gn[d] = (L.chi[s0][ly][lx] - L.chi[s0][ay][ax]) * ih;
+  gs[d] = (L.sig[s0][ly][lx] - L.sig[s0][ay][ax]) * ih;
+  gn[1 - d] = ((L.chi[s0][ay + ty][ax + tx] - L.chi[s0][ay - ty][ax - tx]) +
+               (L.chi[s0][ly + ty][lx + tx] - L.chi[s0][ly - ty][lx - tx])) * iq;
+  gs[1 - d] = ((L.sig[s0][ay + ty][ax + tx] - L.sig[s0][ay - ty][ax - tx]) +
+               (L.sig[s0][ly + ty][lx + tx] - L.sig[s0][ly - ty][lx - tx])) * iq;
+  gn[2] = ((L.chi[sp][ay][ax] - L.chi[sm][ay][ax]) + (L.chi[sp][ly][lx] - L.chi[sm][ly][lx])) * iq;
+  gs[2] = ((L.sig[sp][ay][ax] - L.sig[sm][ay][ax]) + (L.sig[sp][ly][lx] - L.sig[sm][ly][lx])) * iq;
+  return force_finish<R>(gn, gs, 3, d, R(0.5) * (L.del[s0][ay][ax] + L.del[s0][ly][lx]));
+}
+
+// 3D, the face along z between the cell (lx, ly) of plane slot sl (low side)
+// and of slot sh (high side)
+template <typename R, int TX, int TY>
+__device__ __forceinline__ R force_face3_z(const ForceLds3<R, TX, TY>& L, const Par<R>& p,
+                                           const int sl, const int sh, const int lx,
+                                           const int ly) {
+  const R ih = p.inv_h, iq = R(0.25) * p.inv_h;
+  R gn[3], gs[3];
+  gn[2] = (L.chi[sh][ly][lx] - L.chi[sl][ly][lx]) * ih;
+  gs[2] = (L.sig[sh][ly][lx] - L.sig[sl][ly][lx]) * ih;
+  gn[0] = ((L.chi[sl][ly][lx + 1] - L.chi[sl][ly][lx - 1]) +
+           (L.chi[sh][ly][lx + 1] - L.chi[sh][ly][lx - 1])) * iq;
+  gs[0] = ((L.sig[sl][ly][lx + 1] - L.sig[sl][ly][lx - 1]) +
+           (L.sig[sh][ly][lx + 1] - L.sig[sh][ly][lx - 1])) * iq;
+  gn[1] = ((L.chi[sl][ly + 1][lx] - L.chi[sl][ly - 1][lx]) +
+           (L.chi[sh][ly + 1][lx] - L.chi[sh][ly - 1][lx])) * iq;
+  gs[1] = ((L.sig[sl][ly + 1][lx] - L.sig[sl][ly - 1][lx]) +
+           (L.sig[sh][ly + 1][lx] - L.sig[sh][ly - 1][lx])) * iq;
+  return force_finish<R>(gn, gs, 3, 2, R(0.5) * (L.del[sl][ly][lx] + L.del[sh][ly][lx]));
+}
+
+template <typename R, int TX, int TY, int ZC>
+__global__ void __launch_bounds__(TX * TY) k_force3(Grid g, Par<R> p, const R* __restrict__ chi,
+                                                    const R* __restrict__ sig,
+                                                    R* __restrict__ fx, R* __restrict__ fy,
+                                                    R* __restrict__ fz, int tiles_x,
+                                                    int tiles_y) {
+  using Lds = ForceLds3<R, TX, TY>;
+  constexpr int NT = TX * TY, HX = Lds::HX, HY = Lds::HY;
+  __shared__ Lds L;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int b = blockIdx.x;
+  const int r = b / tiles_x;
+  const int x0 = (b % tiles_x) * TX, y0 = (r % tiles_y) * TY, z0 = (r / tiles_y) * ZC;
+  const int z1 = z0 + ZC < nz ? z0 + ZC : nz;
+  // plane zq (mapped into the box) with its halo ring into slot s
+  auto load = [&](int zq, int s) {
+    const int gz = map_axis(zq, nz, g.bc[2][0], g.bc[2][1]);
+    for (int l = threadIdx.x; l < HX * HY; l += NT) {
+      const int lx = l % HX, ly = l / HX;
+      const int gx = map_axis(x0 - 1 + lx, nx, g.bc[0][0], g.bc[0][1]);
+      const int gy = map_axis(y0 - 1 + ly, ny, g.bc[1][0], g.bc[1][1]);
+      const long long ci = (long long)gx + (long long)nx * (gy + (long long)ny * gz);
+      const R c = chi[ci];
+      R ph, om, de;
+      phase<R>(c, p, ph, om, de);
+      L.chi[s][ly][lx] = c;
+      L.sig[s][ly][lx] = sig[ci];
+      L.del[s][ly][lx] = de;
     }
+  };
+  load(z0 - 1, 0);
+  load(z0, 1);
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int cx = x0 + tx, cy = y0 + ty;
+  const bool in = cx < nx && cy < ny;
+  const int lx = tx + 1, ly = ty + 1;
+  const bool px = g.bc[0][0] == BC_PERIODIC, py = g.bc[1][0] == BC_PERIODIC,
+             pz = g.bc[2][0] == BC_PERIODIC;
+  for (int z = z0; z < z1; ++z) {
+    const int k = z - z0;
+    const int sm = k % 3, s0 = (k + 1) % 3, sp = (k + 2) % 3;
+    load(z + 1, sp);
+    __syncthreads();
+    if (in) {
+      const long long plane = (long long)z * ny;
+      // x faces: [nz][ny][nx + 1]
+      const long long rx = (plane + cy) * (nx + 1);
+      fx[rx + cx] = (cx == 0 && !px) ? R(0) : force_face3_xy<R, TX, TY>(L, p, 0, sm, s0, sp, lx, ly);
+      if (cx == nx - 1)
+        fx[rx + nx] = px ? force_face3_xy<R, TX, TY>(L, p, 0, sm, s0, sp, lx + 1, ly) : R(0);
+      // y faces: [nz][ny + 1][nx]
+      const long long ry = (long long)z * (ny + 1);
+      fy[(ry + cy) * nx + cx] =
+          (cy == 0 && !py) ? R(0) : force_face3_xy<R, TX, TY>(L, p, 1, sm, s0, sp, lx, ly);
+      if (cy == ny - 1)
+        fy[(ry + ny) * nx + cx] = py ? force_face3_xy<R, TX, TY>(L, p, 1, sm, s0, sp, lx, ly + 1) : R(0);
+      // z faces: [nz + 1][ny][nx]
+      fz[(plane + cy) * nx + cx] = (z == 0 && !pz) ? R(0) : force_face3_z<R, TX, TY>(L, p, sm, s0, lx, ly);
+      if (z == nz - 1)
+        fz[((long long)nz * ny + cy) * nx + cx] = pz ? force_face3_z<R, TX, TY>(L, p, s0, sp, lx, ly) : R(0);
+    }
+    __syncthreads();  // the next plane goes into slot sm
   }
 }
 

@@ -79,6 +79,24 @@ def vof_ball(n, h, centre, R, dim, sub=8, origin=(0.0, 0.0, 0.0), period_z=None)
     return f
 
 
+def distance_ball(n, h, centre, R, clamp, origin=(0.0, 0.0, 0.0), period_z=None):
+    """Signed distance R - |x - centre| to a sphere, or a circle for a 2D n
+    (positive inside), cut to [-clamp, clamp], at the cell centres of an
+    (nz, ny, nx) box; `period_z` (box length) takes the nearest periodic
+    image in z."""
+    x, y, z = cell_centres(n, h, origin)
+    dz = z - centre[2] if len(n) == 3 else np.zeros(1)
+    if period_z is not None:
+        dz = dz - period_z * np.round(dz / period_z)
+    dy = y - centre[1]
+    dx = x - centre[0]
+    out = np.empty((len(z), len(y), len(x)))
+    for k in range(len(z)):  # a plane at a time: no full-box temporaries
+        r = np.sqrt(dz[k] ** 2 + dy[:, None] ** 2 + dx[None, :] ** 2)
+        out[k] = np.clip(R - r, -clamp, clamp)
+    return out
+
+
 def vof_disc(n, h, centre, R, samples=256, origin=(0.0, 0.0, 0.0)):
     """2D fraction of each cell inside a circle, integrated along x with the
     midpoint rule (`samples` points per cell) over the exact covered length

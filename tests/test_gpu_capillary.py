@@ -136,8 +136,8 @@ def test_one_pair_only_and_validation():
 @pytest.mark.parametrize("prec", [F32])
 def test_expanding_circle_size_sampled(prec):
     # the 1024^2 expanding-circle workload (the VoF of its first step, 8x8
-    # subsamples per cell) with the level set the library builds from it;
-    # every face next to the interface and random others, against the
+    # subsamples per cell) with the circle's clamped signed distance as the
+    # level set; faces next to the interface and random others, against the
     # oracle face by face
     from paper_2605_27534_amd import configs as C
     import torch
@@ -148,8 +148,10 @@ def test_expanding_circle_size_sampled(prec):
     T = s.tensor
     vof = rounded(cfg["vof0"](), prec)
     sig = rounded(1.0 + 0.2 * synth.smooth_modes(n, prob["h"], 16, dim=2), prec)
-    s.set_geometry(T(vof), full=True)
-    chi = to_np(s.levelset())
+    q = O.full(prob)
+    chi = rounded(synth.distance_ball(n, prob["h"], (0.5, 0.5, 0), 0.1,
+                                      q["chi_max_eps"] * q["eps"]), prec)
+    s.set_levelset(T(chi))
     c, m = s.interface_force(T(vof), T(sig))
     torch.cuda.synchronize()
     cap_g, ma_g = [to_np(x) for x in c], [to_np(x) for x in m]

@@ -147,3 +147,27 @@ def test_capillary_balance_and_laplace_jump():
     for j, k in ((c - 1, c - 1), (c, c - 1), (c - 1, c), (c, c)):
         jump = float(np.sum(cap[0][k, j, c:])) * h
         assert abs(jump + 2 * s0 / R) < 0.05 * 2 * s0 / R, jump
+
+
+def test_face_force_matches_the_whole_box():
+    # the face-by-face form (used on boxes too large for the whole-box one)
+    # gives the same values, bit for bit, on a ragged box with a wall, an open
+    # side and a periodic axis, for the faces next to the interface, the
+    # boundary faces and random others
+    n = (14, 12, 10)
+    h = 1.0 / n[0]
+    prob = dict(dim=3, n=n, h=h, bc=((0, 2), (1, 1), (2, 0)))
+    vof = synth.vof_ball(n, h, (0.45, 0.5 * n[1] * h, 0.4 * n[2] * h), 0.28, 3)
+    chi = O.geometry(prob, vof, 60)
+    sig = 1.0 + 0.2 * synth.smooth_modes(n, h, 31, dim=3)
+    cap, ma = K3.forces(prob, vof, chi, sig)
+    rng = np.random.default_rng(32)
+    for d in range(3):
+        shp = cap[d].shape
+        picks = [tuple(rng.integers(s) for s in shp) for _ in range(60)]
+        kk, jj, ii = np.nonzero(cap[d] != 0.0)
+        picks += list(zip(kk[::3], jj[::3], ii[::3]))
+        picks += [(0, 0, 0), tuple(s - 1 for s in shp)]
+        for (k, j, i) in picks:
+            fc, fm = K3.face_force(prob, vof, chi, sig, d, (int(i), int(j), int(k)))
+            assert fc == cap[d][k, j, i] and fm == ma[d][k, j, i], (d, i, j, k)
