@@ -1327,6 +1327,32 @@ Par<R> par_of(const surf_grid& gr, const surf_params& q) {
 }
 
 
+// the three per-cell adjoint kernels, specialized on the dimension, the bulk
+// switch and the presence of a flow
+template <typename R, int DIM, bool BULK>
+void adj_launch(hipStream_t st, const AdjArgs<R>& a, dim3 grid, dim3 block, int which) {
+  if (which == 0) hipLaunchKernelGGL((k_adv_star<R, DIM, BULK>), grid, block, 0, st, a);
+  else if (which == 1) hipLaunchKernelGGL((k_adj_src<R, DIM, BULK>), grid, block, 0, st, a);
+  else {
+    // interior x tiles plus one workgroup of side columns per row block
+    const dim3 gs(adj_xtiles(a.g.n[0]) + 1, grid.y, grid.z);
+    if (a.has_u) hipLaunchKernelGGL((k_adj_adv<R, DIM, BULK, true>), gs, block, 0, st, a);
+    else hipLaunchKernelGGL((k_adj_adv<R, DIM, BULK, false>), gs, block, 0, st, a);
+  }
+}
+
+template <typename R>
+void adj_launch(hipStream_t st, const AdjArgs<R>& a, int dim, bool bulk, dim3 grid, dim3 block,
+                int which) {
+  if (dim == 2) {
+    if (bulk) adj_launch<R, 2, true>(st, a, grid, block, which);
+    else adj_launch<R, 2, false>(st, a, grid, block, which);
+  } else {
+    if (bulk) adj_launch<R, 3, true>(st, a, grid, block, which);
+    else adj_launch<R, 3, false>(st, a, grid, block, which);
+  }
+}
+
 template <typename R>
 int adjoint_step_impl(surf_ctx* c, const void* const* u, const void* F, const void* psi,
                       const void* mF, const void* mP, const double* w, void* lF, void* lP,
@@ -1357,7 +1383,7 @@ int adjoint_step_impl(surf_ctx* c, const void* const* u, const void* F, const vo
   const dim3 ablock(ADJ_TX * ADJ_TY);
   const int nb = (int)(agrid.x * agrid.y * agrid.z);
   if (a.has_u) {
-    hipLaunchKernelGGL(k_adv_star<R>, agrid, ablock, 0, c->stream, a);
+    adj_launch<R>(c->stream, a, c->grid.dim, c->prm.bulk_enabled != 0, agrid, ablock, 0);
   } else {
     size_t bytes = (size_t)c->ncell * sizeof(R);
     if (c->prm.bulk_enabled &&
@@ -1366,8 +1392,8 @@ int adjoint_step_impl(surf_ctx* c, const void* const* u, const void* F, const vo
     if (hipMemcpyAsync(c->adj[1], psi, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
       return SURF_EDEVICE;
   }
-  hipLaunchKernelGGL(k_adj_src<R>, agrid, ablock, 0, c->stream, a);
-  hipLaunchKernelGGL(k_adj_adv<R>, agrid, ablock, 0, c->stream, a);
+  adj_launch<R>(c->stream, a, c->grid.dim, c->prm.bulk_enabled != 0, agrid, ablock, 1);
+  adj_launch<R>(c->stream, a, c->grid.dim, c->prm.bulk_enabled != 0, agrid, ablock, 2);
   hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(FIN_BLOCK), 0, c->stream,
                      (const double*)c->adj_part, nb, dtheta);
   return status_of_launch();

@@ -211,6 +211,26 @@ __global__ void __launch_bounds__(G3_LIST_THREADS) k_geo3_list(const uint8_t* __
   if (tid == 0) live[0] = sBase;
 }
 
+// The Godunov update of one cell from its value v, pin datum gk (finite on
+// cut cells: the pinned value) and its six neighbours, clamped.
+template <typename R>
+__device__ __forceinline__ R geo3_update(const Par<R>& p, R dtau, R v, R gk, R xm, R xp, R ym,
+                                         R yp, R zm, R zp) {
+  const R sgn = gk > R(0) ? R(1) : R(-1);
+  const R nb[6] = {xm, xp, ym, yp, zm, zp};
+  R G2 = R(0);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const R a1 = sgn * (v - nb[2 * d]) * p.inv_h, b1 = sgn * (nb[2 * d + 1] - v) * p.inv_h;
+    const R t1 = a1 > R(0) ? a1 * a1 : R(0), t2 = b1 < R(0) ? b1 * b1 : R(0);
+    G2 += t1 > t2 ? t1 : t2;
+  }
+  R nv = fabs(gk) < R(INFINITY) ? gk : v - dtau * sgn * (rsqrt_<R>(G2) - R(1));
+  nv = nv > p.chimax ? p.chimax : nv;
+  nv = nv < -p.chimax ? -p.chimax : nv;
+  return nv;
+}
+
 // One Jacobi sweep (Godunov, pinned cut cells, clamp) over the listed tiles.
 // Thread (x, y) of a 256-thread workgroup owns the tile's z-column at
 // (x, y): it loads the column with one cell beyond each end, the four x and
@@ -268,19 +288,8 @@ __global__ void __launch_bounds__(G3_SWEEP_THREADS) k_geo3_sweep(Geo3Args ga, Pa
     bool allpos = true, allneg = true;
 #pragma unroll
     for (int z = 0; z < G3; ++z) {
-      const R v = col[z + 1], gk = gv[z];
-      const R sgn = gk > R(0) ? R(1) : R(-1);
-      const R nb[6] = {xm[z], xp[z], ym[z], yp[z], col[z], col[z + 2]};
-      R G2 = R(0);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const R a1 = sgn * (v - nb[2 * d]) * p.inv_h, b1 = sgn * (nb[2 * d + 1] - v) * p.inv_h;
-        const R t1 = a1 > R(0) ? a1 * a1 : R(0), t2 = b1 < R(0) ? b1 * b1 : R(0);
-        G2 += t1 > t2 ? t1 : t2;
-      }
-      R nv = fabs(gk) < R(INFINITY) ? gk : v - dtau * sgn * (rsqrt_<R>(G2) - R(1));
-      nv = nv > p.chimax ? p.chimax : nv;
-      nv = nv < -p.chimax ? -p.chimax : nv;
+      const R nv = geo3_update<R>(p, dtau, col[z + 1], gv[z], xm[z], xp[z], ym[z], yp[z], col[z],
+                                  col[z + 2]);
       if (colin && z0 + z < nz) {
         dst[cxy + pl * (z0 + z)] = nv;
         allpos = allpos && nv == p.chimax;

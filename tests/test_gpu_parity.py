@@ -348,7 +348,7 @@ def test_interface_jump_raises_status():
     assert s.status() & 8
 
 
-@pytest.mark.parametrize("prec,ksweeps", [(F64, 16), (F32, 16), (F32, 8)])
+@pytest.mark.parametrize("prec,ksweeps", [(F64, 16), (F32, 16), (F32, 8), (F32, 6)])
 def test_translating_sphere_banded_redistancing(prec, ksweeps):
     # 3D moving interface through the band geometry (16^3 tiles, sweeps over
     # the live tiles only) on a ragged 56 x 52 x 60 grid with periodic z: a
@@ -372,6 +372,28 @@ def test_translating_sphere_banded_redistancing(prec, ksweeps):
     g = run_gpu(prob, vof0, 24, dt, prec, u=u, vof_seq=vs, c0=cf, gamma0=0.3, hj_step=ksweeps)
     compare(o, g, prec)
     assert g[5].status() & 8 == 0
+
+
+def test_small_sphere_quiescent_tiles():
+    # an 88 x 80 x 64 box with a sphere of radius 0.1 (8.8 cells): most 16^3
+    # tiles stay quiescent, so the two-sweep launches meet quiescent
+    # neighbours on every side of the live band; 8 steps with 16 sweeps
+    # each, against the oracle's global sweeps
+    n = (88, 80, 64)
+    h = 1.0 / 88
+    dt = 0.08 * h * h / 1e-2
+    w = 0.3 * h / dt
+    prob = dict(dim=3, n=n, h=h, bc=((2, 0), (2, 2), (1, 1)), eos=0, eos_E=0.3,
+                hj_iters_step=16)
+    cen = lambda t: (0.45, 0.41, (0.2 + w * t) % (64 * h))
+    vof0 = synth.vof_ball(n, h, cen(0), 0.1, 3, period_z=64 * h)
+    vs = lambda k: synth.vof_ball(n, h, cen((k + 1) * dt), 0.1, 3, period_z=64 * h)
+    u = [np.zeros(synth.face_centres_shape(n, 0)), np.zeros(synth.face_centres_shape(n, 1)),
+         np.full(synth.face_centres_shape(n, 2), w)]
+    cf = synth.uniform_field(n, 7, 0.8, 1.2)
+    o = run_oracle(prob, vof0, 8, dt, u=u, vof_seq=vs, c0=cf, gamma0=0.3, hj_step=16)
+    g = run_gpu(prob, vof0, 8, dt, F32, u=u, vof_seq=vs, c0=cf, gamma0=0.3, hj_step=16)
+    compare(o, g, F32)
 
 
 def test_expanding_circle_full_size_parity():
