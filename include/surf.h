@@ -272,11 +272,11 @@ int surf_step(surf_ctx* ctx, const void* vof_next, const void* const* u,
  * state, so it can run while the previous step's transport runs.  This call
  * enqueues it on aux_stream (a HIP stream other than the context's, at the
  * default priority) after the last transport enqueued on the context's
- * stream has consumed the level-set buffer it overwrites (in 3D, where the
- * sweeps rewrite both level-set buffers, a pipelined step's transport reads
- * a copy of the level set taken at its start; level-set reads and writes
- * enqueued after that step make the geometry wait for them; in 2D only the
- * calls that write the level set do, while surf_force and
+ * stream has consumed the level-set buffer it overwrites (2D: the other of
+ * the two; 3D: the sweeps alternate between the other two of three buffers
+ * and the consuming step makes the last one current; calls that write the
+ * level set, and surf_interface_force in 3D, which uses the idle buffer as
+ * scratch, make the geometry wait for them, while surf_force and the 2D
  * surf_interface_force, which read the current buffer, run beside it); the next
  * surf_step, which must receive the same vof_next pointer, then runs only
  * the transport, on the context's stream, after the prepared geometry.  Typical order:

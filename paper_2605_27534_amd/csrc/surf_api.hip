@@ -83,10 +83,11 @@ struct surf_ctx {
   // (prepared then points at prepared_phase), with the velocity it took
   bool prepared_phase = false;
   const void* prep_u0 = nullptr;
-  // 3D weighted form: the level set a pipelined step's transport reads,
-  // copied from chi[chi_cur] so that the next step's geometry may rewrite
-  // both level-set buffers meanwhile
+  // 3D weighted form: the third level-set buffer, which a geometry prepared
+  // while a transport reads chi[chi_cur] sweeps into (with chi[1 - chi_cur])
+  // and which the step that consumes it swaps with chi[chi_cur]
   void* chi_snap = nullptr;
+  uint8_t* q_snap = nullptr;  // its per-tile flags (3D moving geometry)
   bool materialized;  // chi[chi_cur] holds explicit values on every tile
   // adjoint scratch: advected state, nu, per-workgroup dtheta partials
   void* adj[4];
@@ -303,7 +304,7 @@ int col_shape(const surf_grid* gr, const surf_params* p, int* strips, int* group
 // apply).
 constexpr int C3_TZ = 16, C3_TZ64 = 8;
 
-// the 3D pipelined moving interface keeps a snapshot of the level set
+// the 3D pipelined moving interface keeps a third level-set buffer
 bool snapshot_needed(const surf_grid* gr, const surf_params* p, int nc3) {
   return gr->dim == 3 && nc3 > 0 && p->substep2 == SURF_SUBSTEP2_EXPLICIT &&
          p->interface == SURF_IFACE_VOF;
@@ -408,9 +409,12 @@ void materialize(surf_ctx* c) {
 // the clamp: both flag arrays say live.
 void flags_live(surf_ctx* c) {
   if (c->nflags == 0) return;
-  for (int b = 0; b < 2; ++b)
-    hipLaunchKernelGGL(k_fill_u8, dim3((c->nflags + BLOCK - 1) / BLOCK), dim3(BLOCK), 0,
-                       c->stream, c->q[b], (uint8_t)Q_LIVE, c->nflags);
+  for (int b = 0; b < 3; ++b) {
+    uint8_t* q = b < 2 ? c->q[b] : c->q_snap;
+    if (q)
+      hipLaunchKernelGGL(k_fill_u8, dim3((c->nflags + BLOCK - 1) / BLOCK), dim3(BLOCK), 0,
+                         c->stream, q, (uint8_t)Q_LIVE, c->nflags);
+  }
 }
 
 // ACDI: phi from the current level set
@@ -668,8 +672,11 @@ bool geo3_ok(const surf_ctx* c) {
 
 // The level set stays in chi[chi_cur] (R); chi[1 - chi_cur] (S) is the
 // sweeps' partner and its flag array also carries this step's live marks.
+// With third = true (a geometry prepared while a transport reads R) the
+// sweeps alternate between S and chi_snap (T) and end in T, which the step
+// that consumes them makes the current buffer.
 template <typename R>
-void geo3_impl(surf_ctx* c, const void* vof, hipStream_t st = nullptr) {
+void geo3_impl(surf_ctx* c, const void* vof, hipStream_t st = nullptr, bool third = false) {
   if (!st) st = c->stream;
   Geo3Args ga;
   ga.g = c->g;
@@ -684,17 +691,23 @@ void geo3_impl(surf_ctx* c, const void* vof, hipStream_t st = nullptr) {
   const int K = c->prm.hj_iters_step;
   {
     Timed tm(c, 1, st);
+    R* chiT = third ? (R*)c->chi_snap : nullptr;
+    uint8_t* qT = third ? c->q_snap : nullptr;
     hipLaunchKernelGGL(k_geo3_classify<R>, dim3(8 * ga.per_xcd), dim3(G3_THREADS), 0, st,
-                       ga, p, (const R*)vof, chiS, (R*)c->g0, (const uint8_t*)qR, qS, c->state);
+                       ga, p, (const R*)vof, chiS, (R*)c->g0, (const uint8_t*)qR, qS, chiT, qT,
+                       c->state);
     hipLaunchKernelGGL(k_geo3_list, dim3(1), dim3(G3_LIST_THREADS), 0, st,
                        (const uint8_t*)qS, c->ng3, c->live3);
     const R dtau = (R)(c->grid.h / 3);
+    // odd sweeps R -> S (T -> S after the first with a third buffer), even
+    // sweeps S -> R (S -> T)
+    R* chiE = third ? chiT : chiR;
+    uint8_t* qE = third ? qT : qR;
     for (int k = 1; k <= K; ++k) {
-      // odd sweeps R -> S, even sweeps S -> R
-      const R* src = (k & 1) ? chiR : chiS;
-      R* dst = (k & 1) ? chiS : chiR;
+      const R* src = (k & 1) ? (k == 1 ? chiR : chiE) : chiS;
+      R* dst = (k & 1) ? chiS : chiE;
       hipLaunchKernelGGL(k_geo3_sweep<R>, dim3(G3_SWEEP_GRID), dim3(G3_SWEEP_THREADS), 0,
-                         st, ga, p, dtau, src, dst, (const R*)c->g0, qR,
+                         st, ga, p, dtau, src, dst, (const R*)c->g0, qE,
                          (const int*)c->live3, k == K ? 1 : 0);
     }
   }
@@ -878,19 +891,20 @@ int step2d_impl(surf_ctx* c, const void* vof_next, const void* const* u, const v
 }
 
 // A 3D step whose geometry was prepared on the auxiliary stream (the caller
-// has made the context's stream wait for it): the level set is copied to the
-// snapshot, the point after which the next prepared geometry may rewrite the
-// level-set buffers is recorded, and the transport reads the snapshot.
+// has made the context's stream wait for it): the prepared level set, in the
+// third buffer, becomes the current one (the old current buffer becomes the
+// third, with its flags), the point after which the next prepared geometry
+// may rewrite the two others is recorded, and the transport reads it.
 template <typename R>
 int col3d_prepared_step(surf_ctx* c, const void* const* u, const void* F_in, const void* psi_in,
                         void* F_out, void* psi_out, void* sigma_out, double* totals) {
-  hipLaunchKernelGGL(k_copy<R>, dim3(grid1d(c->ncell)), dim3(BLOCK), 0, c->stream,
-                     (const R*)c->chi[c->chi_cur], (R*)c->chi_snap, c->ncell);
+  std::swap(c->chi[c->chi_cur], c->chi_snap);
+  std::swap(c->q[c->chi_cur], c->q_snap);
   if (hipEventRecord(c->ev_pre, c->stream) != hipSuccess) return SURF_EDEVICE;
   c->pre_valid = true;
   {
     Timed tm(c, 0);
-    col3d_transport<R>(c, u, F_in, psi_in, F_out, psi_out, sigma_out, c->chi_snap);
+    col3d_transport<R>(c, u, F_in, psi_in, F_out, psi_out, sigma_out);
   }
   finalize<R>(c, totals, c->c3_nwg);
   return status_of_launch();
@@ -1456,7 +1470,8 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
     b += align_up((size_t)adj_blocks(grid) * NADJ * sizeof(double));
   }
   if (params->interface == SURF_IFACE_ACDI) b += 3 * align_up(n * es);
-  if (snapshot_needed(grid, params, nc3)) b += align_up(n * es);
+  if (snapshot_needed(grid, params, nc3))
+    b += align_up(n * es) + align_up((size_t)flag_count(grid, params) + 1);
   if (imp) {
     b += IMP_FIELDS * align_up(n * sizeof(double));
     b += align_up((size_t)nimp * 2 * sizeof(double));
@@ -1542,6 +1557,8 @@ int surf_init(surf_ctx** out, const surf_grid* grid, const surf_params* params, 
   if (snapshot_needed(grid, params, c->c3_nwg)) {
     c->chi_snap = p;
     p += align_up(c->ncell * es);
+    c->q_snap = (uint8_t*)p;
+    p += align_up((size_t)c->nflags + 1);
   }
   if (imp) {
     double** f[IMP_FIELDS] = {&c->imp.Fs,   &c->imp.Ps,   &c->imp.wF,   &c->imp.wP,
@@ -1870,8 +1887,8 @@ int surf_prepare_geometry(surf_ctx* c, const void* vof_next, void* aux_stream) {
   c->pre_valid = false;
   if (hipStreamWaitEvent(aux, c->ev_pre, 0) != hipSuccess) return SURF_EDEVICE;
   if (three) {
-    if (c->prm.precision == SURF_F32) geo3_impl<float>(c, vof_next, aux);
-    else geo3_impl<double>(c, vof_next, aux);
+    if (c->prm.precision == SURF_F32) geo3_impl<float>(c, vof_next, aux, true);
+    else geo3_impl<double>(c, vof_next, aux, true);
   } else {
     Timed tm(c, 1, aux);
     if (c->prm.precision == SURF_F32) geo2d_launch<float>(c, vof_next, aux);
@@ -1883,9 +1900,10 @@ int surf_prepare_geometry(surf_ctx* c, const void* vof_next, void* aux_stream) {
 }
 
 int surf_force(surf_ctx* c, const void* sigma, void* const* force) {
-  // in 2D the force kernel reads only the current level set, which a geometry
-  // prepared next leaves alone; in 3D that geometry rewrites both buffers
-  if (c && (c->grid.dim == 3 || !c->materialized)) touch_levelset(c);
+  // the force kernel reads only the current level set, which a geometry
+  // prepared next leaves alone (2D: it writes the other buffer; 3D: the
+  // other two)
+  if (c && !c->materialized) touch_levelset(c);
   if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !sigma || !force) return SURF_EINVAL;
   for (int d = 0; d < c->grid.dim; ++d)

@@ -9,7 +9,11 @@
 // rebuilt by K sweeps over the live tiles only.  The level set stays in one
 // buffer (R); the other (S) is the sweeps' ping-pong partner.  Both hold the
 // clamp on every quiescent tile, each with a flag array saying so, so that a
-// sweep reads its neighbours from one buffer without looking at flags:
+// sweep reads its neighbours from one buffer without looking at flags.  A
+// geometry prepared while a transport still reads R sweeps between S and a
+// third buffer T instead (R -> S -> T -> S ... -> T), which then becomes R:
+// classify gives T the clamp on quiescent tiles too, and the last sweep
+// writes T's flags.
 //   k_geo3_classify  one workgroup per tile: the decision; a quiescent tile
 //                    writes the clamp into S only if S's flag says S does not
 //                    hold it yet, a live tile its pin data (Russo-Smereka
@@ -58,6 +62,8 @@ __global__ void __launch_bounds__(G3_THREADS) k_geo3_classify(Geo3Args ga, Par<R
                                                               R* __restrict__ g0,
                                                               const uint8_t* __restrict__ q_in,
                                                               uint8_t* __restrict__ q_out,
+                                                              R* __restrict__ chiT,
+                                                              uint8_t* __restrict__ qT,
                                                               double* __restrict__ state) {
   __shared__ uint8_t sQ[27];
   __shared__ int sVote[G3_THREADS / 64];
@@ -82,6 +88,7 @@ __global__ void __launch_bounds__(G3_THREADS) k_geo3_classify(Geo3Args ga, Par<R
   const long long pl = (long long)nx * ny;
   const long long cxy = (long long)cx + (long long)nx * cy;
   const uint8_t qs_old = q_out[t];  // read before thread 0 rewrites it
+  const uint8_t qt_old = qT ? qT[t] : (uint8_t)0;
   bool one = true, zero = true;
   R f[G3];
 #pragma unroll
@@ -118,16 +125,26 @@ __global__ void __launch_bounds__(G3_THREADS) k_geo3_classify(Geo3Args ga, Par<R
     if ((int)q != want) quiet = false;
     if (q == Q_LIVE) nb_quiet = false;
   }
-  if (quiet) {  // R already holds the clamp here; S gets it unless it has it
+  if (quiet) {  // R already holds the clamp here; S (and T) get it unless they have it
+    const R v = want == Q_POS ? p.chimax : -p.chimax;
     if ((int)qs_old != want) {
-      const R v = want == Q_POS ? p.chimax : -p.chimax;
 #pragma unroll
       for (int k = 0; k < G3; ++k) {
         const int gz = z0 + k;
         if (colin && gz < nz) chiS[(long long)gx + (long long)nx * (gy + (long long)ny * gz)] = v;
       }
     }
-    if (tid == 0) q_out[t] = (uint8_t)want;
+    if (qT && (int)qt_old != want) {
+#pragma unroll
+      for (int k = 0; k < G3; ++k) {
+        const int gz = z0 + k;
+        if (colin && gz < nz) chiT[(long long)gx + (long long)nx * (gy + (long long)ny * gz)] = v;
+      }
+    }
+    if (tid == 0) {
+      q_out[t] = (uint8_t)want;
+      if (qT) qT[t] = (uint8_t)want;
+    }
     return;
   }
   if (tid == 0) {
@@ -236,7 +253,7 @@ __device__ __forceinline__ R geo3_update(const Par<R>& p, R dtau, R v, R gk, R x
 // (x, y): it loads the column with one cell beyond each end, the four x and
 // y neighbour columns and the pin data, every load issued before any is
 // used, then updates its 16 cells.  Neighbours come from src everywhere:
-// quiescent tiles hold the clamp in both buffers.  Persistent grid (a
+// quiescent tiles hold the clamp in every buffer a sweep reads.  Persistent grid (a
 // multiple of 8 workgroups).  The last sweep also writes each tile's new
 // flag.
 constexpr int G3_SWEEP_THREADS = G3 * G3, G3_SWEEP_GRID = 1024;
@@ -310,12 +327,5 @@ __global__ void __launch_bounds__(G3_SWEEP_THREADS) k_geo3_sweep(Geo3Args ga, Pa
   }
 }
 
-// dst = src over n cells (the level-set snapshot of a pipelined 3D step)
-template <typename R>
-__global__ void __launch_bounds__(BLOCK) k_copy(const R* __restrict__ src, R* __restrict__ dst,
-                                                long long n) {
-  const long long i = (long long)blockIdx.x * BLOCK + threadIdx.x;
-  if (i < n) dst[i] = src[i];
-}
 
 }  // namespace surf
