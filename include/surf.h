@@ -385,8 +385,8 @@ int surf_force(surf_ctx* ctx, const void* sigma, void* const* force);
  * Either array set may be NULL (not both).  Faces on walls and open sides
  * get 0; on a periodic axis the last face repeats the first.  Enqueued on
  * the context's stream.  SURF_EINVAL for an axisymmetric grid, an axis
- * under 4 cells, in 2D (nx+1)(ny+1) >= 2^30, in 3D ny nz ceil(nx/256) >=
- * 2^31, NULL inputs or a NULL array in
+ * under 4 cells, in 2D (nx+1)(ny+1) >= 2^30, in 3D 2^31 or more 16^3
+ * tiles, NULL inputs or a NULL array in
  * a given set; SURF_ESTATE without a level set or with a prepared geometry
  * pending. */
 int surf_interface_force(surf_ctx* ctx, const void* vof, const void* sigma, void* const* f_cap,

@@ -1292,19 +1292,24 @@ int iface3_force_impl(surf_ctx* c, const void* vof, const void* sigma, void* con
   a.kh = (R*)c->g0;
   a.dm = (R*)c->chi[1 - c->chi_cur];
   a.h = c->grid.h;
+  for (int d = 0; d < 3; ++d) {
+    a.fc[d] = cap ? (R*)cap[d] : nullptr;
+    a.fm[d] = ma ? (R*)ma[d] : nullptr;
+  }
   const int nx = c->grid.n[0], ny = c->grid.n[1], nz = c->grid.n[2];
-  const int tx = (nx + IF3_TX - 1) / IF3_TX, ty = (ny + IF3_TY - 1) / IF3_TY;
-  const long long tiles = (long long)tx * ty * ((nz + IF3_TZ - 1) / IF3_TZ);
-  const int chunks = (nx + 255) / 256;
-  const long long rows = (long long)chunks * ny * nz;
-  if (tiles >= (1ll << 31) || rows >= (1ll << 31)) return SURF_EINVAL;
+  const int tx = (nx + IF3_T - 1) / IF3_T, ty = (ny + IF3_T - 1) / IF3_T;
+  const long long tiles = (long long)tx * ty * ((nz + IF3_T - 1) / IF3_T);
+  if (tiles >= (1ll << 31)) return SURF_EINVAL;
+  for (int d = 0; d < 3; ++d) {
+    const long long nf = c->ncell / c->grid.n[d] * (c->grid.n[d] + 1);
+    for (R* f : {a.fc[d], a.fm[d]})
+      if (f) hipLaunchKernelGGL(k_zero<R>, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0,
+                                c->stream, f, nf);
+  }
   hipLaunchKernelGGL(k_iface3_cells<R>, dim3((unsigned)tiles), dim3(IF3_NT), 0, c->stream, a,
                      tx, ty);
-  hipLaunchKernelGGL(k_iface3_faces<R>, dim3((unsigned)rows), dim3(256), 0, c->stream, a, chunks,
-                     cap ? (R*)cap[0] : nullptr,
-                     cap ? (R*)cap[1] : nullptr, cap ? (R*)cap[2] : nullptr,
-                     ma ? (R*)ma[0] : nullptr, ma ? (R*)ma[1] : nullptr,
-                     ma ? (R*)ma[2] : nullptr);
+  hipLaunchKernelGGL(k_iface3_faces<R>, dim3((unsigned)tiles), dim3(IF3_NT), 0, c->stream, a,
+                     tx, ty);
   if (c->nflags > 0)
     hipLaunchKernelGGL(k_fill_u8, dim3((c->nflags + BLOCK - 1) / BLOCK), dim3(BLOCK), 0,
                        c->stream, c->q[1 - c->chi_cur], (uint8_t)Q_LIVE, c->nflags);

@@ -39,17 +39,16 @@
 // open sides carry no force; on a periodic axis the last face repeats the
 // first.  The geometry runs in FP64 in both precisions.
 //
-// Two launches.  k_iface3_cells takes a 64 x 4 x 2 tile per workgroup, lists
-// the tile's interfacial cells in LDS and gives them to its first threads (a
-// sphere's surface leaves a few dozen per tile, so the heavy work packs into
-// one wave instead of one per row of the tile); it writes each listed cell's
-// height curvature (NaN where no axis closes) and delta_m into two scratch
-// cell arrays, and nothing for the other cells.  k_iface3_faces, one thread
-// per cell, writes the cell's low face along each axis (and the last cell
-// its high face), reading the scratch arrays only at interfacial cells and
-// filling in the curvature of a cell without heights from the first array,
-// which no thread writes.  A face with neither cell interfacial has both
-// forces zero and reads nothing past the two fractions.
+// The face arrays are zeroed (k_zero), then two launches over 16^3 tiles (a
+// thread per z-column).  k_iface3_cells lists the tile's interfacial
+// cells in LDS and gives them to its first threads (a sphere's surface
+// leaves a few dozen to a few hundred per tile, so the heavy work packs into
+// a wave or two); it writes each listed cell's height curvature (NaN where
+// no axis closes) and delta_m into two scratch cell arrays, and nothing for
+// the other cells.  k_iface3_faces lists the faces of all three axes with an
+// interfacial cell on either side and computes those, reading the scratch
+// arrays only at interfacial cells and filling in the curvature of a cell
+// without heights from the first array, which no thread writes.
 #pragma once
 #include "surf_capillary.hpp"
 
@@ -65,17 +64,24 @@ struct Iface3Args {
   const R* sig;
   R* kh;     // height curvature per cell
   R* dm;     // delta_m per cell
+  R* fc[3];  // capillary force per face set (or null)
+  R* fm[3];  // Marangoni force per face set (or null)
   double h;
 };
 
 __device__ __forceinline__ bool if3_cut(double c) { return c > IFACE_CUT && c < 1.0 - IFACE_CUT; }
 
-template <typename R>
-__device__ __forceinline__ double if3_at(const R* a, const Grid& g, int x, int y, int z) {
+// the cell index of (x, y, z) mapped into the box (mirrored or wrapped ghosts)
+__device__ __forceinline__ long long if3_index(const Grid& g, int x, int y, int z) {
   const int i = map_axis(x, g.n[0], g.bc[0][0], g.bc[0][1]);
   const int j = map_axis(y, g.n[1], g.bc[1][0], g.bc[1][1]);
   const int k = map_axis(z, g.n[2], g.bc[2][0], g.bc[2][1]);
-  return (double)a[cell_index(g, i, j, k)];
+  return cell_index(g, i, j, k);
+}
+
+template <typename R>
+__device__ __forceinline__ double if3_at(const R* a, const Grid& g, int x, int y, int z) {
+  return (double)a[if3_index(g, x, y, z)];
 }
 
 // ---- PLIC area in the unit cube
@@ -138,22 +144,25 @@ __device__ double plic_area3(double m0, double m1, double m2, double c) {
 }
 
 // ---- the cells pass
-template <typename R>
-__device__ void if3_youngs(const Iface3Args<R>& a, int x, int y, int z, double* m) {
+// fv(x, y, z): the fraction of cell (x, y, z), ghosts mapped
+template <typename FV>
+__device__ __forceinline__ void if3_youngs(const FV& fv, int x, int y, int z, double* m) {
   const double w[3] = {1.0, 2.0, 1.0};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int b = d == 0 ? 1 : 0, cc = d == 2 ? 1 : 2;
     double s = 0.0;
+#pragma unroll
     for (int p = -1; p <= 1; ++p)
+#pragma unroll
       for (int r = -1; r <= 1; ++r) {
         int o[3] = {0, 0, 0};
         o[b] = p;
         o[cc] = r;
         o[d] = 1;
-        const double hi = if3_at(a.vof, a.g, x + o[0], y + o[1], z + o[2]);
+        const double hi = fv(x + o[0], y + o[1], z + o[2]);
         o[d] = -1;
-        const double lo = if3_at(a.vof, a.g, x + o[0], y + o[1], z + o[2]);
+        const double lo = fv(x + o[0], y + o[1], z + o[2]);
         s += w[p + 1] * w[r + 1] * (hi - lo);
       }
     m[d] = -s;
@@ -161,9 +170,9 @@ __device__ void if3_youngs(const Iface3Args<R>& a, int x, int y, int z, double* 
 }
 
 // kappa by height functions; false when no axis closes
-template <typename R>
-__device__ bool if3_heights(const Iface3Args<R>& a, int x, int y, int z, const double* m,
-                            double& kappa) {
+template <typename FV>
+__device__ __forceinline__ bool if3_heights(const FV& fv, double h, int x, int y, int z,
+                                            const double* m, double& kappa) {
   // axes by |m| descending, ties to the higher axis
   int ord[3] = {2, 1, 0};
   for (int u = 0; u < 3; ++u)
@@ -176,33 +185,34 @@ __device__ bool if3_heights(const Iface3Args<R>& a, int x, int y, int z, const d
   for (int q = 0; q < 3; ++q) {
     const int ax = ord[q];
     if (m[ax] == 0.0) continue;
-    const int b = ax == 0 ? 1 : 0, cc = ax == 2 ? 1 : 2;
-    double H[3][3];
+    const int b = ax == 0 ? 1 : 0;
+    // the offset along axis e of cell l of column (p, r): l along ax, p along
+    // b, r along the third axis (no indexed arrays, so that the 81 loads are
+    // issued together)
+    auto off = [&](int e, int p, int r, int l) { return e == ax ? l : (e == b ? p : r); };
+    double H[9];
     bool ok = true;
-    for (int p = -1; p <= 1; ++p)
-      for (int r = -1; r <= 1; ++r) {
-        double sum = 0.0, lo = 0.0, hi = 0.0;
-        for (int l = -IF3_HL; l <= IF3_HL; ++l) {
-          int o[3] = {0, 0, 0};
-          o[ax] = l;
-          o[b] = p;
-          o[cc] = r;
-          const double c = if3_at(a.vof, a.g, x + o[0], y + o[1], z + o[2]);
-          sum += c;
-          if (l == -IF3_HL) lo = c;
-          if (l == IF3_HL) hi = c;
-        }
-        const double full = m[ax] > 0.0 ? lo : hi, empty = m[ax] > 0.0 ? hi : lo;
-        if (!(full >= 1.0 - IFACE_CUT && empty <= IFACE_CUT)) ok = false;
-        H[p + 1][r + 1] = sum;
-      }
+    for (int pr = 0; pr < 9; ++pr) {  // column (p, r) = (pr / 3 - 1, pr % 3 - 1)
+      const int p = pr / 3 - 1, r = pr % 3 - 1;
+      double col[2 * IF3_HL + 1];  // the column's nine values gathered together
+#pragma unroll
+      for (int l = -IF3_HL; l <= IF3_HL; ++l)
+        col[l + IF3_HL] = fv(x + off(0, p, r, l), y + off(1, p, r, l), z + off(2, p, r, l));
+      double sum = 0.0;
+#pragma unroll
+      for (int l = 0; l <= 2 * IF3_HL; ++l) sum += col[l];
+      const double lo = col[0], hi = col[2 * IF3_HL];
+      const double full = m[ax] > 0.0 ? lo : hi, empty = m[ax] > 0.0 ? hi : lo;
+      if (!(full >= 1.0 - IFACE_CUT && empty <= IFACE_CUT)) ok = false;
+      H[pr] = sum;
+    }
     if (!ok) continue;
-    const double h = a.h;
-    const double Hb = 0.5 * (H[2][1] - H[0][1]);
-    const double Hc = 0.5 * (H[1][2] - H[1][0]);
-    const double Hbb = (H[2][1] - 2.0 * H[1][1] + H[0][1]) / h;
-    const double Hcc = (H[1][2] - 2.0 * H[1][1] + H[1][0]) / h;
-    const double Hbc = (H[2][2] - H[2][0] - H[0][2] + H[0][0]) / (4.0 * h);
+    // H[3 (p + 1) + (r + 1)]
+    const double Hb = 0.5 * (H[7] - H[1]);
+    const double Hc = 0.5 * (H[5] - H[3]);
+    const double Hbb = (H[7] - 2.0 * H[4] + H[1]) / h;
+    const double Hcc = (H[5] - 2.0 * H[4] + H[3]) / h;
+    const double Hbc = (H[8] - H[6] - H[2] + H[0]) / (4.0 * h);
     const double qq = 1.0 + Hb * Hb + Hc * Hc;
     kappa = (Hbb * (1.0 + Hc * Hc) + Hcc * (1.0 + Hb * Hb) - 2.0 * Hbc * Hb * Hc) / (qq * sqrt(qq));
     return true;
@@ -210,51 +220,106 @@ __device__ bool if3_heights(const Iface3Args<R>& a, int x, int y, int z, const d
   return false;
 }
 
-constexpr int IF3_TX = 64, IF3_TY = 4, IF3_TZ = 2, IF3_NT = IF3_TX * IF3_TY * IF3_TZ;
+constexpr int IF3_T = 16, IF3_NT = IF3_T * IF3_T;  // 16^3 tiles, a thread per z-column
+constexpr int IF3_S = IF3_T + 2 * IF3_HL;           // the staged region's edge
+
+// The workgroup's list of this thread's entries (the set bits k of mask,
+// stored as (k << 8) | t | tag, tag above bit 11) after those of the
+// threads before it, in sList; returns the list length.  Two barriers.
+__device__ __forceinline__ int if3_list(unsigned mask, unsigned short* sList, int* sWave,
+                                        unsigned tag = 0) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int cnt = __popc(mask);
+  int inc = cnt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int up = __shfl_up(inc, o);
+    if (lane >= o) inc += up;
+  }
+  if (lane == 63) sWave[w] = inc;
+  __syncthreads();
+  int pos = inc - cnt, total = 0;
+#pragma unroll
+  for (int v = 0; v < IF3_NT / 64; ++v) {
+    pos += v < w ? sWave[v] : 0;
+    total += sWave[v];
+  }
+  for (unsigned m = mask; m; m &= m - 1u)
+    sList[pos++] = (unsigned short)((((__ffs(m) - 1) << 8) | t) | tag);
+  __syncthreads();
+  return total;
+}
+
+// the face index of cell (x, y, z) with coordinate d replaced by f
+__device__ __forceinline__ long long if3_face_index(const Grid& g, int d, int x, int y, int z,
+                                                    int f) {
+  return face_index(g, d, d == 0 ? f : x, d == 1 ? f : y, d == 2 ? f : z);
+}
 
 template <typename R>
 __global__ void __launch_bounds__(IF3_NT) k_iface3_cells(Iface3Args<R> a, int tiles_x,
                                                         int tiles_y) {
-  __shared__ int sList[IF3_NT];
+  __shared__ unsigned short sList[IF3_T * IF3_T * IF3_T];
   __shared__ int sWave[IF3_NT / 64];
+  __shared__ float sV[IF3_S][IF3_S][IF3_S];  // FP32 fractions of the tile and its halo
   const Grid& g = a.g;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int bx = blockIdx.x % tiles_x, r = blockIdx.x / tiles_x;
-  const int x0 = bx * IF3_TX, y0 = (r % tiles_y) * IF3_TY, z0 = (r / tiles_y) * IF3_TZ;
-  int x = x0 + t % IF3_TX, y = y0 + (t / IF3_TX) % IF3_TY, z = z0 + t / (IF3_TX * IF3_TY);
-  const bool cut = x < g.n[0] && y < g.n[1] && z < g.n[2] &&
-                   if3_cut((double)a.vof[cell_index(g, x, y, z)]);
-  // the tile's interfacial cells, in thread order
-  const unsigned long long bal = __ballot(cut);
-  if (lane == 0) sWave[w] = __popcll(bal);
-  __syncthreads();
-  int base = 0, total = 0;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int t = threadIdx.x;
+  const int r = blockIdx.x / tiles_x;
+  const int x0 = (blockIdx.x % tiles_x) * IF3_T, y0 = (r % tiles_y) * IF3_T,
+            z0 = (r / tiles_y) * IF3_T;
+  const int x = x0 + t % IF3_T, y = y0 + t / IF3_T;
+  const long long pl = (long long)nx * ny;
+  // this column's interfacial cells as a bit mask, every load issued first
+  unsigned mask = 0;
+  if (x < nx && y < ny) {
+    const long long cxy = (long long)x + (long long)nx * y;
+    R v[IF3_T];
 #pragma unroll
-  for (int v = 0; v < IF3_NT / 64; ++v) {
-    const int cnt = sWave[v];
-    base += v < w ? cnt : 0;
-    total += cnt;
+    for (int k = 0; k < IF3_T; ++k) v[k] = z0 + k < nz ? a.vof[cxy + pl * (z0 + k)] : R(0);
+#pragma unroll
+    for (int k = 0; k < IF3_T; ++k) mask |= if3_cut((double)v[k]) ? (1u << k) : 0u;
   }
-  if (cut) sList[base + __popcll(bal & ((1ull << lane) - 1ull))] = t;
-  __syncthreads();
-  if (t >= total) return;
-  const int u = sList[t];
-  x = x0 + u % IF3_TX;
-  y = y0 + (u / IF3_TX) % IF3_TY;
-  z = z0 + u / (IF3_TX * IF3_TY);
-  const long long cl = cell_index(g, x, y, z);
-  const double c = (double)a.vof[cl];
-  double m[3], kap = 0.0;
-  if3_youngs(a, x, y, z, m);
-  if (!if3_heights(a, x, y, z, m, kap)) kap = (double)NAN;
-  a.kh[cl] = (R)kap;
-  a.dm[cl] = (R)(plic_area3(m[0], m[1], m[2], c) / a.h);
+  const int total = if3_list(mask, sList, sWave);
+  if (total == 0) return;
+  auto cell = [&](const auto& fv) {
+    for (int i = t; i < total; i += IF3_NT) {
+      const int e = sList[i];
+      const int cx = x0 + (e & 15), cy = y0 + ((e >> 4) & 15), cz = z0 + (e >> 8);
+      const long long cl = (long long)cx + (long long)nx * cy + pl * cz;
+      const double c = (double)a.vof[cl];
+      double m3[3], kap = 0.0;
+      if3_youngs(fv, cx, cy, cz, m3);
+      if (!if3_heights(fv, a.h, cx, cy, cz, m3, kap)) kap = (double)NAN;
+      a.kh[cl] = (R)kap;
+      a.dm[cl] = (R)(plic_area3(m3[0], m3[1], m3[2], c) / a.h);
+    }
+  };
+  if constexpr (sizeof(R) == 4) {
+    // FP32: the tile and IF3_HL cells around it (mapped) staged in LDS, a
+    // column of 24 per thread with its loads issued together
+    for (int q = t; q < IF3_S * IF3_S; q += IF3_NT) {
+      const int sx = q % IF3_S, sy = q / IF3_S;
+      R v[IF3_S];
+#pragma unroll
+      for (int k = 0; k < IF3_S; ++k)
+        v[k] = a.vof[if3_index(g, x0 - IF3_HL + sx, y0 - IF3_HL + sy, z0 - IF3_HL + k)];
+#pragma unroll
+      for (int k = 0; k < IF3_S; ++k) sV[k][sy][sx] = v[k];
+    }
+    __syncthreads();
+    cell([&](int X, int Y, int Z) {
+      return (double)sV[Z - z0 + IF3_HL][Y - y0 + IF3_HL][X - x0 + IF3_HL];
+    });
+  } else {
+    cell([&](int X, int Y, int Z) { return if3_at(a.vof, g, X, Y, Z); });
+  }
 }
 
 // ---- the faces pass
 // the level set's curvature at cell (x, y, z), moved to the interface
 template <typename R>
-__device__ double if3_levelset_kappa(const Iface3Args<R>& a, int x, int y, int z) {
+__device__ __forceinline__ double if3_levelset_kappa(const Iface3Args<R>& a, int x, int y, int z) {
   const double h = a.h;
   auto C = [&](int dx, int dy, int dz) { return if3_at(a.chi, a.g, x + dx, y + dy, z + dz); };
   const double c0 = C(0, 0, 0);
@@ -277,49 +342,56 @@ __device__ double if3_levelset_kappa(const Iface3Args<R>& a, int x, int y, int z
 
 // kappa of an interfacial cell (mapped coordinates)
 template <typename R>
-__device__ double if3_kappa(const Iface3Args<R>& a, int x, int y, int z) {
+__device__ __forceinline__ double if3_kappa(const Iface3Args<R>& a, int x, int y, int z) {
   const double kh = (double)a.kh[cell_index(a.g, x, y, z)];
   if (!isnan(kh)) return kh;
+  // every neighbour's fraction and scratch curvature loaded first (the
+  // curvature is used only where the neighbour is interfacial)
+  R fv[27], kv[27];
+#pragma unroll
+  for (int q = 0; q < 27; ++q) {
+    const long long i = if3_index(a.g, x + q % 3 - 1, y + (q / 3) % 3 - 1, z + q / 9 - 1);
+    fv[q] = a.vof[i];
+    kv[q] = a.kh[i];
+  }
   double s = 0.0;
   int cnt = 0;
-  for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        if (dx == 0 && dy == 0 && dz == 0) continue;
-        if (!if3_cut(if3_at(a.vof, a.g, x + dx, y + dy, z + dz))) continue;
-        const double v = if3_at(a.kh, a.g, x + dx, y + dy, z + dz);
-        if (!isnan(v)) {
-          s += v;
-          ++cnt;
-        }
-      }
+#pragma unroll
+  for (int q = 0; q < 27; ++q) {  // dz, dy, dx from -1 to 1
+    if (q == 13 || !if3_cut((double)fv[q])) continue;
+    const double v = (double)kv[q];
+    if (!isnan(v)) {
+      s += v;
+      ++cnt;
+    }
+  }
   return cnt ? s / cnt : if3_levelset_kappa(a, x, y, z);
 }
 
 // the face gradient of a cell field across the face between cells L and R
 // (R = L + e_d, both mapped into the box)
 template <typename R>
-__device__ void if3_face_grad(const Iface3Args<R>& a, const R* f, int d, const int* L,
+__device__ __forceinline__ void if3_face_grad(const Iface3Args<R>& a, const R* f, int d, const int* L,
                               const int* Rc, double* gr) {
   const double h = a.h;
-  gr[d] = (if3_at(f, a.g, Rc[0], Rc[1], Rc[2]) - if3_at(f, a.g, L[0], L[1], L[2])) / h;
+  const double nrm = (if3_at(f, a.g, Rc[0], Rc[1], Rc[2]) - if3_at(f, a.g, L[0], L[1], L[2])) / h;
+#pragma unroll
   for (int t = 0; t < 3; ++t) {
-    if (t == d) continue;
     double s = 0.0;
+#pragma unroll
     for (int side = 0; side < 2; ++side) {
       const int* X = side == 0 ? L : Rc;
-      int p[3] = {X[0], X[1], X[2]}, q[3] = {X[0], X[1], X[2]};
-      p[t] += 1;
-      q[t] -= 1;
-      s += 0.5 * (if3_at(f, a.g, p[0], p[1], p[2]) - if3_at(f, a.g, q[0], q[1], q[2])) / (2.0 * h);
+      const int px = X[0] + (t == 0), py = X[1] + (t == 1), pz = X[2] + (t == 2);
+      const int qx = X[0] - (t == 0), qy = X[1] - (t == 1), qz = X[2] - (t == 2);
+      s += 0.5 * (if3_at(f, a.g, px, py, pz) - if3_at(f, a.g, qx, qy, qz)) / (2.0 * h);
     }
-    gr[t] = s;
+    gr[t] = t == d ? nrm : s;
   }
 }
 
 // the two forces on the face along d between cells L and R
 template <typename R>
-__device__ void if3_face(const Iface3Args<R>& a, int d, const int* L, const int* Rc, double& cap,
+__device__ __forceinline__ void if3_face(const Iface3Args<R>& a, int d, const int* L, const int* Rc, double& cap,
                          double& ma) {
   const long long iL = cell_index(a.g, L[0], L[1], L[2]), iR = cell_index(a.g, Rc[0], Rc[1], Rc[2]);
   const double cL = (double)a.vof[iL], cR = (double)a.vof[iR];
@@ -340,41 +412,128 @@ __device__ void if3_face(const Iface3Args<R>& a, int d, const int* L, const int*
   const double nd = d == 0 ? n0 : (d == 1 ? n1 : n2);
   const double ndot = n0 * gs[0] + n1 * gs[1] + n2 * gs[2];
   const double dmf = 0.5 * ((cutL ? (double)a.dm[iL] : 0.0) + (cutR ? (double)a.dm[iR] : 0.0));
-  ma = dmf * (gs[d] - nd * ndot);
+  const double gsd = d == 0 ? gs[0] : (d == 1 ? gs[1] : gs[2]);
+  ma = dmf * (gsd - nd * ndot);
 }
 
-// one thread per cell: rows of the box along x in chunks of 256, a workgroup
-// per (chunk, y, z)
+// The faces next to interfacial cells, over 16^3 tiles: the low face of a
+// cell along d is computed when the cell or its low neighbour along d is
+// interfacial (on a periodic axis the last cell also its high face, the
+// same two cells as face 0), the other faces keep the zero the cells pass
+// wrote.  Per axis the tile lists its faces in LDS and its threads take them
+// in turn, so the interfacial work of a tile packs into a wave or two.
 template <typename R>
-__global__ void __launch_bounds__(256) k_iface3_faces(Iface3Args<R> a, int chunks_x, R* cx,
-                                                      R* cy, R* cz, R* mx, R* my, R* mz) {
+__global__ void __launch_bounds__(IF3_NT) k_iface3_faces(Iface3Args<R> a, int tiles_x,
+                                                        int tiles_y) {
+  __shared__ unsigned short sList[3 * (IF3_T * IF3_T * IF3_T + IF3_NT)];
+  __shared__ int sWave[IF3_NT / 64];
   const Grid& g = a.g;
-  R* cap[3] = {cx, cy, cz};
-  R* ma[3] = {mx, my, mz};
-  const int row = blockIdx.x / chunks_x;
-  const int x = (blockIdx.x % chunks_x) * 256 + threadIdx.x;
-  const int y = row % g.n[1], z = row / g.n[1];
-  if (x >= g.n[0]) return;
-  const int X[3] = {x, y, z};
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int t = threadIdx.x;
+  const int r = blockIdx.x / tiles_x;
+  const int x0 = (blockIdx.x % tiles_x) * IF3_T, y0 = (r % tiles_y) * IF3_T,
+            z0 = (r / tiles_y) * IF3_T;
+  const int x = x0 + t % IF3_T, y = y0 + t / IF3_T;
+  const bool colin = x < nx && y < ny;
+  const long long pl = (long long)nx * ny;
+  // cut bits of the column (bit k: cell z0 + k) and of the column's low
+  // neighbours along x and y, the cell below the column and, for the last
+  // cells along an axis, the first cell along it
+  unsigned cc = 0, cxm = 0, cym = 0;
+  bool czm = false, cz0 = false;
+  if (colin) {
+    const long long cxy = (long long)x + (long long)nx * y;
+    const long long xm = (long long)(x == 0 ? nx - 1 : x - 1) + (long long)nx * y;
+    const long long ym = (long long)x + (long long)nx * (y == 0 ? ny - 1 : y - 1);
+    R v[IF3_T], vx[IF3_T], vy[IF3_T];
+#pragma unroll
+    for (int k = 0; k < IF3_T; ++k) {
+      const long long z = (long long)min(z0 + k, nz - 1);
+      v[k] = a.vof[cxy + pl * z];
+      vx[k] = a.vof[xm + pl * z];
+      vy[k] = a.vof[ym + pl * z];
+    }
+    const R vz = a.vof[cxy + pl * (z0 == 0 ? nz - 1 : z0 - 1)];  // the cell below
+    const R vz0 = a.vof[cxy];                                     // z = 0
+#pragma unroll
+    for (int k = 0; k < IF3_T; ++k) {
+      const unsigned b = z0 + k < nz ? (1u << k) : 0u;
+      cc |= if3_cut((double)v[k]) ? b : 0u;
+      cxm |= if3_cut((double)vx[k]) ? b : 0u;
+      cym |= if3_cut((double)vy[k]) ? b : 0u;
+    }
+    czm = if3_cut((double)vz);
+    cz0 = if3_cut((double)vz0);
+  }
+  // per axis the low faces (bit k when the face exists, interior or
+  // periodic, and a side is interfacial) and the high faces of the last
+  // cells on a periodic axis (the cell or the first one along the axis)
+  int n = 0;
   for (int d = 0; d < 3; ++d) {
     const bool per = g.bc[d][0] == BC_PERIODIC;
-    // the low face of the cell, and the high face for the last cell
-    for (int side = 0; side < (X[d] + 1 == g.n[d] ? 2 : 1); ++side) {
-      const int f = X[d] + side;  // face coordinate along d
-      double fc = 0.0, fm = 0.0;
-      if (per || (f > 0 && f < g.n[d])) {
-        int Rc[3] = {x, y, z}, L[3] = {x, y, z};
-        Rc[d] = f % g.n[d];
-        L[d] = (f - 1 + g.n[d]) % g.n[d];
-        if3_face(a, d, L, Rc, fc, fm);
+    unsigned lo = 0, hi = 0;
+    if (colin) {
+      if (d == 0) {
+        lo = (x > 0 || per) ? (cc | cxm) : 0u;
+      } else if (d == 1) {
+        lo = (y > 0 || per) ? (cc | cym) : 0u;
+      } else {
+        const unsigned below = (cc << 1) | (czm ? 1u : 0u);  // bit k: cell z0 + k - 1
+        lo = (cc | below) & ((1u << IF3_T) - 1u);
+        if (z0 == 0 && !per) lo &= ~1u;
       }
-      int F[3] = {x, y, z};
-      F[d] = f;
-      const long long fi = face_index(g, d, F[0], F[1], F[2]);
-      if (cap[d]) cap[d][fi] = (R)fc;
-      if (ma[d]) ma[d][fi] = (R)fm;
+      if (per) {
+        if (d == 0 && x == nx - 1) {
+          unsigned first = 0;  // the row's first cells
+          for (int k = 0; k < IF3_T; ++k)
+            if (z0 + k < nz && if3_cut((double)a.vof[(long long)nx * y + pl * (z0 + k)]))
+              first |= 1u << k;
+          hi = cc | first;
+        } else if (d == 1 && y == ny - 1) {
+          unsigned first = 0;  // the column's first cells
+          for (int k = 0; k < IF3_T; ++k)
+            if (z0 + k < nz && if3_cut((double)a.vof[(long long)x + pl * (z0 + k)])) first |= 1u << k;
+          hi = cc | first;
+        } else if (d == 2 && nz - 1 >= z0 && nz - 1 < z0 + IF3_T) {
+          const int k = nz - 1 - z0;
+          if (((cc >> k) & 1u) || cz0) hi = 1u << k;
+        }
+      }
+      const unsigned inbox = z0 + IF3_T <= nz ? 0xffffu : ((1u << (nz - z0)) - 1u);
+      lo &= inbox;
+      hi &= inbox;
     }
+    // tag: the axis in bits 12-13, a high face in bit 14
+    n += if3_list(lo, sList + n, sWave, (unsigned)d << 12);
+    n += if3_list(hi, sList + n, sWave, ((unsigned)d << 12) | (1u << 14));
   }
+  for (int i = t; i < n; i += IF3_NT) {
+    const int e = sList[i];
+    const int d = (e >> 12) & 3;
+    const bool high = (e >> 14) & 1;
+    const int cx = x0 + (e & 15), cy = y0 + ((e >> 4) & 15), cz = z0 + ((e >> 8) & 15);
+    const int X[3] = {cx, cy, cz};
+    const int nd = g.n[d], xd = d == 0 ? cx : (d == 1 ? cy : cz);
+    const int f = high ? nd : xd;  // face coordinate along d
+    const int rd = f == nd ? 0 : f, ld = f == 0 ? nd - 1 : f - 1;
+    const int Rc[3] = {d == 0 ? rd : X[0], d == 1 ? rd : X[1], d == 2 ? rd : X[2]};
+    const int L[3] = {d == 0 ? ld : X[0], d == 1 ? ld : X[1], d == 2 ? ld : X[2]};
+    double fc = 0.0, fm = 0.0;
+    if3_face(a, d, L, Rc, fc, fm);
+    const long long fi = if3_face_index(g, d, cx, cy, cz, f);
+    R* cap = d == 0 ? a.fc[0] : (d == 1 ? a.fc[1] : a.fc[2]);
+    R* ma = d == 0 ? a.fm[0] : (d == 1 ? a.fm[1] : a.fm[2]);
+    if (cap) cap[fi] = (R)fc;
+    if (ma) ma[fi] = (R)fm;
+  }
+}
+
+// zero over n values (the face arrays, before the interfacial faces are
+// written)
+template <typename R>
+__global__ void __launch_bounds__(256) k_zero(R* __restrict__ p, long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = R(0);
 }
 
 }  // namespace surf

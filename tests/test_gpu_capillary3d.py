@@ -74,6 +74,13 @@ def test_sphere_across_the_periodic_side(prec):
                        period_z=n[2] / n[0]), prec)
 
 
+@pytest.mark.parametrize("prec", [F64, F32])
+def test_sphere_cut_by_periodic_x_and_y_sides(prec):
+    # interfacial cells on the periodic x and y seams: their low faces wrap
+    # to the last cells, and the last cells' high faces repeat face 0
+    compare(*ball_case((18, 17, 19), (0.04, 0.03, 0.5), 0.25, ((1, 1), (1, 1), (0, 2)), 24), prec)
+
+
 def test_one_set_only_fp64():
     prob, vof, chi, sig = ball_case((16, 16, 16), (0.5, 0.48, 0.52), 0.3,
                                     ((1, 1), (1, 1), (1, 1)), 23)
