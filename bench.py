@@ -152,9 +152,9 @@ def kernel_source_digest(sources):
 # the same for the Marangoni face force (surf_force)
 FORCE_COUNTERS = {
     "expanding circle 1024^2 fp32 soluble": (
-        "k_force_expanding_circle_1024_counters.md", ("surf_common.hpp", "surf_kernels.hpp")),
+        "k_force2_expanding_circle_1024_counters.md", ("surf_common.hpp", "surf_kernels.hpp")),
     "translating sphere 256^3 fp32": (
-        "k_force_translating_sphere_256_counters.md", ("surf_common.hpp", "surf_kernels.hpp")),
+        "k_force3_translating_sphere_256_counters.md", ("surf_common.hpp", "surf_kernels.hpp")),
 }
 
 # the same for the interfacial-force kernel of the c1f workload

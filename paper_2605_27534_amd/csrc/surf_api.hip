@@ -1014,8 +1014,9 @@ CgArgs cg_args(surf_ctx* c, const ImpArgs<R>& a, int field) {
 
 void cg_iter_launch(surf_ctx* c, const CgArgs& k, int it) {
   const dim3 gr(k.nwg), bl(CG_WG);
-  if (c->grid.dim == 3) hipLaunchKernelGGL(k_cg_iter<3>, gr, bl, 0, c->stream, k, it);
-  else hipLaunchKernelGGL(k_cg_iter<2>, gr, bl, 0, c->stream, k, it);
+  if (c->grid.dim == 3) hipLaunchKernelGGL((k_cg_iter<3, false>), gr, bl, 0, c->stream, k, it);
+  else if (k.axi) hipLaunchKernelGGL((k_cg_iter<2, true>), gr, bl, 0, c->stream, k, it);
+  else hipLaunchKernelGGL((k_cg_iter<2, false>), gr, bl, 0, c->stream, k, it);
 }
 
 // Host-paced iteration launches: chunks of CG_CHUNK, enqueued once the device

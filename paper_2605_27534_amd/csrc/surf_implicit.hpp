@@ -434,7 +434,7 @@ __global__ void __launch_bounds__(CG_WG) k_cg_setup(ImpArgs<R> a, CgArgs c, int 
 }
 
 // one iteration (it >= 0) or the start launch (it = -1)
-template <int DIM>
+template <int DIM, bool AXI>
 __global__ void __launch_bounds__(CG_WG) k_cg_iter(CgArgs c, int it) {
   if (it >= 0 && c.sc[SC_DONE] != 0.0) return;  // uniform over the grid
   if (c.hp && blockIdx.x == 0 && threadIdx.x == 0)
@@ -503,7 +503,7 @@ __global__ void __launch_bounds__(CG_WG) k_cg_iter(CgArgs c, int it) {
     const int zoff = ny * zc;
     // face radii of the lane's column (axisymmetric; else 1)
     double rlo = 1.0, rhi = 1.0, rmid = 1.0;
-    if (c.axi) {
+    if (AXI) {
       const Rings r = rings_of(c.r0, c.h, xm);
       rlo = r.lo;
       rhi = r.hi;
@@ -560,10 +560,13 @@ __global__ void __launch_bounds__(CG_WG) k_cg_iter(CgArgs c, int it) {
       const int n = xm + nx * (ym + zoff);
       const double dgc = c.dg[n], xo = c.x[n], po = c.p[n];
       double Au = dgc * uc;
-      if (lane > 0 || lex) Au += kc * (fc + fL) * rlo * (uc - uL);
-      if (lane < rl || rex) Au += kc * (fc + fR) * rhi * (uc - uR);
-      if (y > 0 || pery) Au += kc * (fc + fr[k - 1]) * rmid * (uc - u[k - 1]);
-      if (y + 1 < ny || pery) Au += kc * (fc + fr[k + 1]) * rmid * (uc - u[k + 1]);
+      // (the radii are 1 on a Cartesian grid: the template drops the products)
+      if (lane > 0 || lex) Au += AXI ? kc * (fc + fL) * rlo * (uc - uL) : kc * (fc + fL) * (uc - uL);
+      if (lane < rl || rex) Au += AXI ? kc * (fc + fR) * rhi * (uc - uR) : kc * (fc + fR) * (uc - uR);
+      if (y > 0 || pery)
+        Au += AXI ? kc * (fc + fr[k - 1]) * rmid * (uc - u[k - 1]) : kc * (fc + fr[k - 1]) * (uc - u[k - 1]);
+      if (y + 1 < ny || pery)
+        Au += AXI ? kc * (fc + fr[k + 1]) * rmid * (uc - u[k + 1]) : kc * (fc + fr[k + 1]) * (uc - u[k + 1]);
       if (DIM == 3) {
 #pragma unroll
         for (int s = -1; s <= 1; s += 2) {
