@@ -355,8 +355,8 @@ int surf_time_acdi(surf_ctx* ctx, const void* const* u, int32_t reps, double* ms
 int surf_force(surf_ctx* ctx, const void* sigma, void* const* force);
 
 /* The interfacial forces of the coupling to a flow solver (section 2.4, the
- * capillary force and the Marangoni force with delta_m = A_f / V_c), 2D or
- * 3D Cartesian, on the faces of u.  Inputs (device, context precision, cell
+ * capillary force and the Marangoni force with delta_m = A_f / V_c), 2D
+ * (Cartesian or axisymmetric) or 3D Cartesian, on the faces of u.  Inputs (device, context precision, cell
  * layout): vof, the VoF fraction of fluid 1, and sigma, the surface tension
  * (e.g. surf_step's sigma_out); the context's cached level set supplies the
  * normal and the curvature fallback.  Outputs (device, caller-owned):
@@ -384,8 +384,12 @@ int surf_force(surf_ctx* ctx, const void* sigma, void* const* force);
  * what it keeps in them).
  * Either array set may be NULL (not both).  Faces on walls and open sides
  * get 0; on a periodic axis the last face repeats the first.  Enqueued on
- * the context's stream.  SURF_EINVAL for an axisymmetric grid, an axis
- * under 4 cells, in 2D (nx+1)(ny+1) >= 2^30, in 3D 2^31 or more 16^3
+ * the context's stream.  On axisymmetric rings (2D, x the radius) the
+ * interface is a surface of revolution: kappa adds the azimuthal curvature
+ * -n_r / r_i (the level-set fallback its own, moved with
+ * kappa / (1 - chi kappa / 2)), and delta_m is the area the chord sweeps
+ * about the axis over the ring's volume, (|chord| / h^2) r_m / r_i, r_m the
+ * radius of the chord's midpoint.  SURF_EINVAL for an axis under 4 cells, in 2D (nx+1)(ny+1) >= 2^30, in 3D 2^31 or more 16^3
  * tiles, NULL inputs or a NULL array in
  * a given set; SURF_ESTATE without a level set or with a prepared geometry
  * pending. */

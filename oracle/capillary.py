@@ -38,6 +38,19 @@ unit normal, pointing out of fluid 1.  Readings (the HIP library takes the same)
   its normal part, n from the same face gradient of chi bounded below by
   1e-6 (the rule of the regularized Marangoni force);
 * faces on walls and open sides carry no force.
+
+On axisymmetric rings (Appendix B; x the radius r, y the axis z, ring i at
+r_i = r0 + (i + 1/2) h) the interface is a surface of revolution, so:
+
+* kappa adds the azimuthal principal curvature to the meridional one: with
+  n = m / |m| (the Youngs normal, out of fluid 1), kappa = kappa_2D - n_r/r_i
+  (-2/R on a sphere of fluid 1, -1/R on a cylinder of radius R about the
+  axis); the level-set fallback adds (d chi / dr) / (|grad chi| r_i) to the
+  2D divergence and moves the sum to the interface with kappa / (1 - chi
+  kappa / 2) (exact on a sphere);
+* delta_m = A_f / V_c with A_f the area the PLIC chord sweeps about the axis,
+  2 pi r_m |chord| (r_m the radius of the chord's midpoint), and V_c = 2 pi
+  r_i h^2: delta_m = (|chord| / h^2) r_m / r_i.
 """
 from __future__ import annotations
 
@@ -68,6 +81,11 @@ def _at(a, j, i, q, per):
     return a[m(j, ny, per[1]), m(i, nx, per[0])]
 
 
+def ring_radius(q, i):
+    """r_i of ring column i (axisymmetric)."""
+    return float(q.get("origin", (0.0, 0.0, 0.0))[0]) + (i + 0.5) * q["h"]
+
+
 def levelset_curvature(prob, chi, j, i):
     q = O.full(prob)
     per = _axes(q)
@@ -81,6 +99,10 @@ def levelset_curvature(prob, chi, j, i):
     cxy = (c(1, 1) - c(1, -1) - c(-1, 1) + c(-1, -1)) / (4 * h * h)
     g = max(math.sqrt(cx * cx + cy * cy), 1e-6)
     kc = (cxx * cy * cy - 2 * cx * cy * cxy + cyy * cx * cx) / g ** 3
+    if q["axisym"]:
+        # div(grad chi / |grad chi|) in (r, z) adds (d chi / dr) / (|grad chi| r)
+        kc += cx / (g * ring_radius(q, i))
+        return kc / (1.0 - c(0, 0) * kc / 2.0)
     return kc / (1.0 - c(0, 0) * kc)
 
 
@@ -109,7 +131,11 @@ def cell_curvature(prob, vof, chi, j, i):
     if ok:
         d1 = 0.5 * (H[2] - H[0])
         d2 = (H[2] - 2.0 * H[1] + H[0]) / h
-        return d2 / (1.0 + d1 * d1) ** 1.5
+        kap = d2 / (1.0 + d1 * d1) ** 1.5
+        if q["axisym"] and (mx != 0.0 or my != 0.0):
+            # the azimuthal curvature -n_r / r_i, n the unit Youngs normal
+            kap -= mx / math.hypot(mx, my) / ring_radius(q, i)
+        return kap
     return levelset_curvature(prob, chi, j, i)
 
 
@@ -176,11 +202,11 @@ def plic_alpha(m, c):
     return 0.5 * (lo + hi)
 
 
-def plic_chord(m, c):
-    """Length of the PLIC line inside the unit square (0 when the cell is
-    full, empty or m = 0)."""
+def plic_segment(m, c):
+    """The end points of the PLIC line inside the unit square (None when the
+    cell is full, empty or m = 0)."""
     if not interfacial(c) or (m[0] == 0.0 and m[1] == 0.0):
-        return 0.0
+        return None
     alpha = plic_alpha(m, c)
     _, cuts = _clip(SQUARE, m, alpha)
     if len(cuts) < 2:
@@ -189,8 +215,17 @@ def plic_chord(m, c):
         pts = [p for p in SQUARE if abs(m[0] * p[0] + m[1] * p[1] - alpha) < 1e-14]
         cuts = cuts + pts
         if len(cuts) < 2:
-            return 0.0
-    (x0, y0), (x1, y1) = cuts[0], cuts[1]
+            return None
+    return cuts[0], cuts[1]
+
+
+def plic_chord(m, c):
+    """Length of the PLIC line inside the unit square (0 when the cell is
+    full, empty or m = 0)."""
+    seg = plic_segment(m, c)
+    if seg is None:
+        return 0.0
+    (x0, y0), (x1, y1) = seg
     return math.hypot(x1 - x0, y1 - y0)
 
 
@@ -209,7 +244,15 @@ def cell_delta(prob, vof, j, i):
     c = v[j, i]
     if not interfacial(c):
         return 0.0
-    return plic_chord(youngs_normal(v, j, i, q, per), c) / q["h"]
+    m = youngs_normal(v, j, i, q, per)
+    if q["axisym"]:
+        seg = plic_segment(m, c)
+        if seg is None:
+            return 0.0
+        (x0, y0), (x1, y1) = seg
+        rm = float(q.get("origin", (0.0, 0.0, 0.0))[0]) + (i + 0.5 * (x0 + x1)) * q["h"]
+        return math.hypot(x1 - x0, y1 - y0) / q["h"] * rm / ring_radius(q, i)
+    return plic_chord(m, c) / q["h"]
 
 
 def marangoni_delta(prob, vof):

@@ -1267,6 +1267,8 @@ int iface_force_impl(surf_ctx* c, const void* vof, const void* sigma, void* cons
   a.chi = (const R*)c->chi[c->chi_cur];
   a.sig = (const R*)sigma;
   a.h = c->grid.h;
+  a.axi = c->grid.axisym ? 1 : 0;
+  a.r0 = c->grid.origin[0];
   const unsigned tiles =
       (unsigned)iface_tiles_x(c->grid.n[0]) * (unsigned)iface_tiles_y(c->grid.n[1]);
   hipLaunchKernelGGL(k_iface_force<R>, dim3(tiles), dim3(IF_THREADS), 0, c->stream, a,
@@ -1927,7 +1929,6 @@ int surf_interface_force(surf_ctx* c, const void* vof, const void* sigma, void* 
   if (c && !c->materialized) touch_levelset(c);
   if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
   if (!c || !vof || !sigma || (!f_cap && !f_ma)) return SURF_EINVAL;
-  if (c->grid.axisym) return SURF_EINVAL;
   const int dim = c->grid.dim;
   for (int d = 0; d < dim; ++d)
     if (c->grid.n[d] < 4) return SURF_EINVAL;

@@ -24,7 +24,13 @@
 // normal difference, the two cells' centred transverse differences
 // averaged) minus its part along the face gradient of chi.  Faces on walls
 // and open sides carry no force; on a periodic axis the last face repeats
-// the first.
+// the first.  On axisymmetric rings (Appendix B; x the radius, ring i at
+// r_i = r0 + (i + 1/2) h) the interface is a surface of revolution: kappa
+// adds the azimuthal curvature -n_r / r_i (n the unit Youngs normal; the
+// level-set fallback adds (d chi / dr) / (|grad chi| r_i) and moves the sum
+// with kappa / (1 - chi kappa / 2)), and delta_m = A_f / V_c is the chord's
+// swept area over the ring's volume, (|chord| / h^2) r_m / r_i with r_m the
+// radius of the chord's midpoint.
 #pragma once
 #include "surf_kernels.hpp"
 
@@ -39,7 +45,9 @@ struct IfaceArgs {
   const R* vof;
   const R* chi;
   const R* sig;
-  double h;  // the cell size in FP64 for the geometry
+  double h;   // the cell size in FP64 for the geometry
+  int axi;    // axisymmetric rings: x is the radius, from r0
+  double r0;
 };
 
 template <typename R>
@@ -82,6 +90,57 @@ __device__ __forceinline__ double plic_chord(double mx, double my, double c) {
   if (c > c1 && c < 1.0 - c1) return sqrt(1.0 + (n1 / n2) * (n1 / n2));
   const double al = sqrt(2.0 * n1 * n2 * (c <= c1 ? c : 1.0 - c));
   return sqrt((al / n1) * (al / n1) + (al / n2) * (al / n2));
+}
+
+// The chord of the PLIC line and the x coordinate of its midpoint (0 .. 1
+// across the cell), for the rings' swept area.  In the frame (u, v) of the
+// normal's smaller and larger components, reflected so that both are >= 0,
+// the chord runs between the axes (fraction up to c1 = n_u / (2 n_v)) or
+// across the cell from u = 0 to 1 at mean height c; a fraction above 1/2 is
+// the point reflection through the centre of the complement's chord.
+__device__ __forceinline__ double plic_chord_mid(double mx, double my, double c, double& xmid) {
+  xmid = 0.5;
+  const double a1 = fabs(mx), a2 = fabs(my), s = a1 + a2;
+  if (!(s > 0.0)) return 0.0;
+  const bool swap = a1 > a2;  // u along y when the x component is the larger
+  const double nu = (swap ? a2 : a1) / s, nv = (swap ? a1 : a2) / s;
+  const bool flip = c > 0.5;
+  const double cc = flip ? 1.0 - c : c;
+  const double c1 = nu / (2.0 * nv);
+  double um, vm, chord;
+  if (cc > c1) {
+    um = 0.5;
+    vm = cc;
+    chord = sqrt(1.0 + (nu / nv) * (nu / nv));
+  } else {
+    const double al = sqrt(2.0 * nu * nv * cc);
+    um = al / (2.0 * nu);
+    vm = al / (2.0 * nv);
+    chord = sqrt((al / nu) * (al / nu) + (al / nv) * (al / nv));
+  }
+  if (flip) {
+    um = 1.0 - um;
+    vm = 1.0 - vm;
+  }
+  const double xr = swap ? vm : um;  // along x in the reflected frame
+  xmid = mx >= 0.0 ? xr : 1.0 - xr;
+  return chord;
+}
+
+// div(grad chi / |grad chi|) by central differences, moved to the interface
+// (on rings r > 0: with the azimuthal part (d chi / dr) / (|grad chi| r),
+// moved with kappa / (1 - chi kappa / 2), exact on a sphere)
+template <typename X>
+__device__ double levelset_curvature_axi(const X& x, double h, double r) {
+  const double c00 = x(0, 0);
+  const double cxp = x(0, 1), cxm = x(0, -1), cyp = x(1, 0), cym = x(-1, 0);
+  const double cx = (cxp - cxm) / (2.0 * h), cy = (cyp - cym) / (2.0 * h);
+  const double cxx = (cxp - 2.0 * c00 + cxm) / (h * h), cyy = (cyp - 2.0 * c00 + cym) / (h * h);
+  const double cxy = (x(1, 1) - x(1, -1) - x(-1, 1) + x(-1, -1)) / (4.0 * h * h);
+  const double gm = fmax(sqrt(cx * cx + cy * cy), 1e-6);
+  double kc = (cxx * cy * cy - 2.0 * cx * cy * cxy + cyy * cx * cx) / (gm * gm * gm);
+  kc += cx / (gm * r);
+  return kc / (1.0 - c00 * kc / 2.0);
 }
 
 // div(grad chi / |grad chi|) by central differences, moved to the interface
@@ -221,8 +280,21 @@ __global__ void __launch_bounds__(IF_THREADS) k_iface_force(IfaceArgs<R> a, R* _
         fallback = true;
         kap = __builtin_nan("");  // replaced below
       }
+      if (!a.axi) {
+        sd[gy][gx] = cell_delta_m(f, a.h);
+      } else {
+        // the ring's radius at the cell's geometric position (a mirrored
+        // ghost beyond the axis has r < 0 and its normal mirrored)
+        const int i = x0 - 1 + gx;
+        const double r = a.r0 + (i + 0.5) * a.h;
+        double mx, my, xm;
+        youngs(f, mx, my);
+        const double chord = plic_chord_mid(mx, my, f(0, 0), xm);
+        sd[gy][gx] = r != 0.0 ? chord / a.h * (a.r0 + (i + xm) * a.h) / r : 0.0;
+        const double nm = sqrt(mx * mx + my * my);
+        if (!isnan(kap) && nm > 0.0 && r != 0.0) kap -= mx / nm / r;  // -n_r / r
+      }
       sk[gy][gx] = kap;
-      sd[gy][gx] = cell_delta_m(f, a.h);
     }
 #pragma unroll
     for (int k = 0; k < IF_CPT; ++k) {
@@ -239,7 +311,9 @@ __global__ void __launch_bounds__(IF_THREADS) k_iface_force(IfaceArgs<R> a, R* _
         const int gy = l / IF_GX, gx = l - gy * IF_GX;
         if (isnan(sk[gy][gx])) {
           const auto x = [&](int dj, int di) { return (double)sx[gy + 1 + dj][gx + 1 + di]; };
-          sk[gy][gx] = levelset_curvature(x, a.h);
+          const double r = a.r0 + (x0 - 1 + gx + 0.5) * a.h;
+          sk[gy][gx] = (a.axi && r != 0.0) ? levelset_curvature_axi(x, a.h, r)
+                                           : levelset_curvature(x, a.h);
         }
       }
       __syncthreads();

@@ -403,3 +403,54 @@ def paper_implicit_residual(I=None, kinetics=1):
         worst = max(worst, float(np.max(np.abs(lhs - rhs)) / np.max(np.abs(lhs))))
     assert worst < 1e-9, worst
     return worst
+
+
+def _rings_case(n, centre_z, R, cylinder=False):
+    from paper_2605_27534_amd import synth
+    nr, nz = n
+    h = 1.0 / nz
+    prob = dict(dim=2, n=(nr, nz), h=h, bc=((0, 2), (1, 1)), axisym=1)
+    if cylinder:
+        r = (np.arange(nr) + 0.5) * h
+        c = np.clip((R - r) / h + 0.5, 0.0, 1.0)  # the interface r = R inside one ring
+        vof = np.broadcast_to(c[None, :], (nz, nr)).copy()[None]
+    else:
+        vof = synth.vof_ball((nr, nz), h, (0.0, centre_z, 0), R, 2, sub=64)
+    return prob, vof, O.geometry(prob, vof, 72)
+
+
+def rings_capillary(K=None):
+    """The interfacial forces on axisymmetric rings against the geometry of
+    surfaces of revolution: a cylinder of fluid 1 about the axis has, in
+    each ring layer, delta_m times the ring volumes equal to the lateral
+    area 2 pi R h (the chord is the layer's height at r = R), and kappa = the
+    azimuthal -1/r at the cell centre; a sphere on the axis has delta_m
+    times the volumes summing to 4 pi R^2 (1%) and kappa = -2/R (2% mean)."""
+    if K is None:
+        from oracle import capillary as K
+    nr, nz, R = 16, 12, 0.37
+    prob, vof, chi = _rings_case((nr, nz), 0.0, R, cylinder=True)
+    h = prob["h"]
+    dm = K.marangoni_delta(prob, vof)[0]
+    kap = K.curvature(prob, vof, chi)[0]
+    rmid = (np.arange(nr) + 0.5) * h
+    vol = 2 * math.pi * rmid * h * h
+    for j in range(nz):
+        assert abs(np.sum(dm[j] * vol) - 2 * math.pi * R * h) < 1e-13
+    i = int(R / h)
+    assert np.all(np.abs(kap[:, i] + 1.0 / rmid[i]) < 1e-12)
+    nr, nz, R = 48, 96, 0.3
+    prob, vof, chi = _rings_case((nr, nz), 0.5, R)
+    h = prob["h"]
+    dm = K.marangoni_delta(prob, vof)[0]
+    rmid = (np.arange(nr) + 0.5) * h
+    area = float(np.sum(dm * (2 * math.pi * rmid * h * h)[None, :]))
+    assert abs(area - 4 * math.pi * R * R) < 0.01 * 4 * math.pi * R * R, area
+    kap = K.curvature(prob, vof, chi)[0]
+    v = vof[0]
+    cut = (v > K.CUT) & (v < 1 - K.CUT)
+    err = np.abs(kap[cut] * R / 2 + 1.0)
+    assert err.mean() < 0.02 and np.median(err) < 0.01, (err.mean(), np.median(err))
+    # without the rings the same cells give the circle's -1/R
+    k2 = K.curvature(dict(prob, axisym=0), vof, chi)[0]
+    assert abs(np.median(k2[cut] * R) + 1.0) < 0.02

@@ -191,9 +191,9 @@ def test_axisym_validation():
 
 
 def test_interface_force_validation():
-    """surf_interface_force rejects axisymmetric grids, missing inputs and
-    half-given output sets before touching the device, and asks for a level
-    set first (2D and 3D)."""
+    """surf_interface_force rejects missing inputs and half-given output sets
+    before touching the device, and asks for a level set first (2D, rings
+    and 3D)."""
     import ctypes
     from paper_2605_27534_amd import surf as S
     L = S.lib()
@@ -224,7 +224,8 @@ def test_interface_force_validation():
     assert L.surf_interface_force(None, p, p, pair, pair) == -1
     assert L.surf_destroy(ctx) == 0
     ctx, buf, base = ctx_of(dict(axisym=1, **dict(two, bc=((0, 2), (0, 0)))))
-    assert L.surf_interface_force(ctx, p, p, pair, pair) == -1
+    assert L.surf_interface_force(ctx, p, p, pair, pair) == -4  # rings: no level set yet
+    assert L.surf_interface_force(ctx, p, p, half, pair) == -1
     assert L.surf_destroy(ctx) == 0
     cube = dict(dim=3, n=(16, 16, 16), h=1.0 / 16, bc=((0, 0), (0, 0), (1, 1)))
     ctx, buf, base = ctx_of(cube)

@@ -87,6 +87,32 @@ def test_disc_across_the_periodic_side_and_near_a_wall(prec):
     compare(prob, vof, chi, sig, prec)
 
 
+def rings_case(n, h, centre, R, bc, seed, r0=0.0):
+    prob = dict(dim=2, n=n, h=h, bc=bc, axisym=1, origin=(r0, 0.0, 0.0))
+    vof = synth.vof_disc(n, h, centre, R, origin=(r0, 0.0, 0.0))
+    chi = O.geometry(prob, vof, 80)
+    sig = 1.0 + 0.2 * synth.smooth_modes(n, h, seed, dim=2, origin=(r0, 0.0, 0.0))
+    return prob, vof, chi, sig
+
+
+@pytest.mark.parametrize("prec", [F64, F32])
+def test_rings_sphere_on_the_axis(prec):
+    # axisymmetric rings: a sphere of fluid 1 on the axis (wall at r = 0, open
+    # outside, periodic z); the azimuthal curvature and the swept-area delta
+    prob, vof, chi, sig = rings_case((40, 72), 1.0 / 72, (0.0, 0.5, 0), 0.27,
+                                     ((0, 2), (1, 1)), seed=14)
+    cap_o, ma_o, cap_g, ma_g = compare(prob, vof, chi, sig, prec)
+
+
+@pytest.mark.parametrize("prec", [F64, F32])
+def test_rings_torus_off_the_axis(prec):
+    # an annular box (r from 0.2, walls on both radial sides, open in z) with
+    # a ring of fluid 1 (a torus in 3D) away from the axis
+    prob, vof, chi, sig = rings_case((48, 40), 1.0 / 64, (0.55, 0.3, 0), 0.16,
+                                     ((0, 0), (2, 2)), seed=15, r0=0.2)
+    compare(prob, vof, chi, sig, prec)
+
+
 def test_diagonal_stripes_fp64():
     # 45-degree lines on a periodic box: exact Youngs normals, ties between
     # the column directions, the PLIC chord through cell corners

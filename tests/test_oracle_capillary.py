@@ -142,3 +142,9 @@ def test_marangoni_force_on_a_flat_interface():
     dsig = (sig[0, j, :] - np.roll(sig[0, j, :], 1)) / h
     assert np.max(np.abs(fx - dsig / h)) < 1e-12 * np.max(np.abs(dsig / h))
     assert np.max(np.abs(ma[1])) < 1e-12
+
+
+# ---- axisymmetric rings
+def test_axisym_cylinder_and_sphere():
+    from tests import oracle_pins as PINS
+    PINS.rings_capillary()

@@ -74,6 +74,15 @@ PY_MUTANTS = {
     "implicit-paper-downwind": ("oracle/implicit.py",
                                 [("up = np.where(Bf < 0.0, L, R)", "up = np.where(Bf < 0.0, R, L)")],
                                 PINS.paper_implicit_residual),
+    # the azimuthal curvature of the rings with the wrong sign
+    "rings-azimuthal-sign": ("oracle/capillary.py",
+                             [("kap -= mx / math.hypot(mx, my) / ring_radius(q, i)",
+                               "kap += mx / math.hypot(mx, my) / ring_radius(q, i)")],
+                             PINS.rings_capillary),
+    # the rings' delta_m without the swept radius (the 2D chord per ring)
+    "rings-swept-radius": ("oracle/capillary.py",
+                           [("* rm / ring_radius(q, i)", "* 1.0")],
+                           PINS.rings_capillary),
 }
 
 
