@@ -494,6 +494,32 @@ int surf_adjoint_step(surf_ctx* ctx, const void* const* u, const void* F_n, cons
                       const void* lamF_np1, const void* lamPsi_np1, const double* w_n,
                       void* lamF_n, void* lamPsi_n, double* dtheta_dev);
 
+/* The pair below lets a backward pass keep the advected state xi* of each
+ * recomputed step instead of advecting again inside the adjoint step.
+ *
+ * surf_step_advected: surf_step on a static level set (vof_next = NULL) that
+ * also writes xi* = (F*, psi*), the state after substep 1 (the advection of
+ * section 2.2) and before substep 2, into F_star/psi_star (cell fields, the
+ * layout of F and psi; F_star is ignored without bulk).  Outputs and totals
+ * are those of surf_step.  3D contexts on the plane-marching transport only
+ * (weighted flux form, no limiter or transverse terms, explicit substep 2,
+ * VoF interface); SURF_EINVAL otherwise, or when an output aliases an input
+ * or another output; SURF_ESTATE after surf_prepare_geometry or before a
+ * level set. */
+int surf_step_advected(surf_ctx* ctx, const void* const* u, const void* F_in, const void* psi_in,
+                       void* F_out, void* psi_out, void* sigma_out, double* totals_dev,
+                       void* F_star, void* psi_star);
+
+/* surf_adjoint_step with xi* of the step taken from (F_n, psi_n) given, as
+ * surf_step_advected wrote it for the same state, velocities and level set:
+ * the adjoint of the advection reads it in place of its own recomputation.
+ * Any context surf_adjoint_step accepts; F_star may be NULL without bulk.
+ * lamF_n/lamPsi_n must not alias the inputs (SURF_EINVAL). */
+int surf_adjoint_step_advected(surf_ctx* ctx, const void* const* u, const void* F_n,
+                               const void* psi_n, const void* F_star, const void* psi_star,
+                               const void* lamF_np1, const void* lamPsi_np1, const double* w_n,
+                               void* lamF_n, void* lamPsi_n, double* dtheta_dev);
+
 /* dL/dc0 = lamF^0 phi (cell field). */
 int surf_adjoint_c0(surf_ctx* ctx, const void* lamF0, void* grad_c0);
 

@@ -4,9 +4,11 @@ adjoint, behind a torch.autograd.Function with checkpointed recomputation.
 L(theta, c0) = (1/N) sum_{n=1..N} (<sigma>^n - target^n)^2, theta = (k_a, k_d,
 D_b, D_s), F^0 = c0 phi, psi^0 = gamma0 delta.  The forward run keeps the
 state every K steps; the backward pass replays each K-step segment from its
-checkpoint (storing the K states) and runs the adjoint steps over it in
-reverse.  Every step, adjoint step, loss weight and seed is a libsurf kernel;
-torch only holds the buffers.
+checkpoint (storing the K states and, on the 3D plane-marching transport, the
+advected state of each step, which the adjoint step then reads instead of
+advecting again) and runs the adjoint steps over it in reverse.  Every step,
+adjoint step, loss weight and seed is a libsurf kernel; torch only holds the
+buffers.
 """
 from __future__ import annotations
 
@@ -32,6 +34,9 @@ class Rollout:
         self.N = int(nsteps)
         self.K = max(1, int(checkpoint))
         self.bulk = bool(self.s.params.bulk_enabled)
+        # whether the recomputation keeps each step's advected state for the
+        # adjoint (3D plane-marching transport only; settled on first use)
+        self.keep_advected = None
 
     # one forward step from (F, P) into fresh buffers
     def _step(self, F, P, tot_row):
@@ -39,6 +44,32 @@ class Rollout:
         P2 = self.s.empty()
         self.s.step(F, P, F2, P2, u=self.u, totals=tot_row)
         return F2, P2
+
+    def _recompute_advected(self, F, P, k, states, scratch):
+        """Replays k steps from (F, P), appending the states after steps
+        1..k-1 to `states` and returning the advected state of each step;
+        None (and nothing appended) where the context has no such step."""
+        if self.keep_advected is False:
+            return None
+        s = self.s
+        stars = []
+        for i in range(k):
+            F2 = s.empty() if F is not None else None
+            P2 = s.empty()
+            st = (s.empty() if F is not None else None, s.empty())
+            try:
+                s.step(F, P, F2, P2, u=self.u, totals=scratch, star=st)
+            except S.SurfError as e:
+                if i or e.code != -1 or self.keep_advected:
+                    raise
+                self.keep_advected = False
+                return None
+            self.keep_advected = True
+            stars.append(st)
+            if i + 1 < k:
+                states.append((F2, P2))
+            F, P = F2, P2
+        return stars
 
     def forward(self, theta, c0, target, keep=None):
         """Returns (loss [device scalar], totals [N,16], checkpoints dict)."""
@@ -74,14 +105,17 @@ class Rollout:
             states = [ck[s0]]
             F, P = ck[s0]
             s.set_time(tot[s0 - 1, 11:12] if (tot is not None and s0 > 0) else None)
-            for n in range(s0, s1 - 1):
-                F, P = self._step(F, P, scratch)
-                states.append((F, P))
+            stars = self._recompute_advected(F, P, s1 - s0, states, scratch)
+            if stars is None:
+                for n in range(s0, s1 - 1):
+                    F, P = self._step(F, P, scratch)
+                    states.append((F, P))
             for n in range(s1 - 1, s0 - 1, -1):
                 Fn, Pn = states[n - s0]
                 nF, nP = s.empty(), s.empty()
                 wn = w[n - 1:n] if n >= 1 else None
-                s.adjoint_step(Fn if self.bulk else None, Pn, lF, lP, nF, nP, dth, u=self.u, w=wn)
+                s.adjoint_step(Fn if self.bulk else None, Pn, lF, lP, nF, nP, dth, u=self.u, w=wn,
+                               star=None if stars is None else stars[n - s0])
                 lF, lP = nF, nP
         gc0 = s.adjoint_c0(lF)
         return dth, gc0

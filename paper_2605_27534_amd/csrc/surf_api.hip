@@ -618,10 +618,17 @@ void launch_col2d(surf_ctx* c, const ColArgs<R>& a, bool has_u, bool bulk) {
 template <typename R, int TZ>
 void launch_col3d(surf_ctx* c, const Col3Args<R>& a, bool has_u, bool bulk) {
   const dim3 grid(8 * a.per_xcd), block(64 * C3_WAVES);
-  if (has_u && bulk) hipLaunchKernelGGL((k_col3d<R, TZ, true, true>), grid, block, 0, c->stream, a);
-  else if (has_u) hipLaunchKernelGGL((k_col3d<R, TZ, true, false>), grid, block, 0, c->stream, a);
-  else if (bulk) hipLaunchKernelGGL((k_col3d<R, TZ, false, true>), grid, block, 0, c->stream, a);
-  else hipLaunchKernelGGL((k_col3d<R, TZ, false, false>), grid, block, 0, c->stream, a);
+  if (a.Pst) {  // the instance that also stores the advected state
+    if (has_u && bulk) hipLaunchKernelGGL((k_col3d<R, TZ, true, true, true>), grid, block, 0, c->stream, a);
+    else if (has_u) hipLaunchKernelGGL((k_col3d<R, TZ, true, false, true>), grid, block, 0, c->stream, a);
+    else if (bulk) hipLaunchKernelGGL((k_col3d<R, TZ, false, true, true>), grid, block, 0, c->stream, a);
+    else hipLaunchKernelGGL((k_col3d<R, TZ, false, false, true>), grid, block, 0, c->stream, a);
+    return;
+  }
+  if (has_u && bulk) hipLaunchKernelGGL((k_col3d<R, TZ, true, true, false>), grid, block, 0, c->stream, a);
+  else if (has_u) hipLaunchKernelGGL((k_col3d<R, TZ, true, false, false>), grid, block, 0, c->stream, a);
+  else if (bulk) hipLaunchKernelGGL((k_col3d<R, TZ, false, true, false>), grid, block, 0, c->stream, a);
+  else hipLaunchKernelGGL((k_col3d<R, TZ, false, false, false>), grid, block, 0, c->stream, a);
 }
 
 template <typename R, int KH>
@@ -747,7 +754,8 @@ void col2d_transport(surf_ctx* c, const void* const* u, const void* F_in, const 
 // The 3D weighted-form transport kernel alone, on the context's stream.
 template <typename R>
 void col3d_transport(surf_ctx* c, const void* const* u, const void* F_in, const void* psi_in,
-                     void* F_out, void* psi_out, void* sigma_out, const void* chi = nullptr) {
+                     void* F_out, void* psi_out, void* sigma_out, const void* chi = nullptr,
+                     void* F_star = nullptr, void* psi_star = nullptr) {
   Col3Args<R> a;
   a.g = c->g;
   a.p = make_par<R>(c);
@@ -769,6 +777,8 @@ void col3d_transport(surf_ctx* c, const void* const* u, const void* F_in, const 
   a.zchunks = c->c3[2];
   a.nwg = c->c3_nwg;
   a.per_xcd = (c->c3_nwg + 7) / 8;
+  a.Fst = (R*)F_star;
+  a.Pst = (R*)psi_star;
   if constexpr (sizeof(R) == 4) launch_col3d<R, C3_TZ>(c, a, has_u, bulk);
   else launch_col3d<R, C3_TZ64>(c, a, has_u, bulk);
 }
@@ -1378,7 +1388,8 @@ void adj_launch(hipStream_t st, const AdjArgs<R>& a, int dim, bool bulk, dim3 gr
 template <typename R>
 int adjoint_step_impl(surf_ctx* c, const void* const* u, const void* F, const void* psi,
                       const void* mF, const void* mP, const double* w, void* lF, void* lP,
-                      double* dtheta) {
+                      double* dtheta, const void* F_star = nullptr,
+                      const void* psi_star = nullptr) {
   materialize<R>(c);
   AdjArgs<R> a;
   a.g = c->g;
@@ -1388,8 +1399,11 @@ int adjoint_step_impl(surf_ctx* c, const void* const* u, const void* F, const vo
   for (int d = 0; d < 3; ++d) a.u[d] = (a.has_u && d < c->grid.dim) ? (const R*)u[d] : nullptr;
   a.F = (const R*)F;
   a.psi = (const R*)psi;
-  a.Fs = (const R*)c->adj[0];
-  a.Ps = (const R*)c->adj[1];
+  // the advected state: given by the forward step that produced it, or
+  // recomputed here
+  const bool given = psi_star != nullptr;
+  a.Fs = given ? (const R*)F_star : (const R*)c->adj[0];
+  a.Ps = given ? (const R*)psi_star : (const R*)c->adj[1];
   a.mF = (const R*)mF;
   a.mP = (const R*)mP;
   a.nF = (R*)c->adj[2];
@@ -1404,7 +1418,9 @@ int adjoint_step_impl(surf_ctx* c, const void* const* u, const void* F, const vo
                    c->grid.n[2]);
   const dim3 ablock(ADJ_TX * ADJ_TY);
   const int nb = (int)(agrid.x * agrid.y * agrid.z);
-  if (a.has_u) {
+  if (given) {
+    // xi* from the caller
+  } else if (a.has_u) {
     adj_launch<R>(c->stream, a, c->grid.dim, c->prm.bulk_enabled != 0, agrid, ablock, 0);
   } else {
     size_t bytes = (size_t)c->ncell * sizeof(R);
@@ -2054,6 +2070,71 @@ int surf_adjoint_step(surf_ctx* c, const void* const* u, const void* F, const vo
   if (c->prm.precision == SURF_F64)
     return adjoint_step_impl<double>(c, u, F, psi, mF, mP, w, lF, lP, dtheta);
   return adjoint_step_impl<float>(c, u, F, psi, mF, mP, w, lF, lP, dtheta);
+}
+
+int surf_adjoint_step_advected(surf_ctx* c, const void* const* u, const void* F,
+                               const void* psi, const void* F_star, const void* psi_star,
+                               const void* mF, const void* mP, const double* w, void* lF,
+                               void* lP, double* dtheta) {
+  touch_levelset(c);
+  if (c && c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
+  if (!c || !psi || !psi_star || !mP || !lP || !dtheta) return SURF_EINVAL;
+  if (!c->prm.adjoint || c->prm.flux_form != SURF_FLUX_WEIGHTED) return SURF_ESTATE;
+  if (!c->has_chi) return SURF_ESTATE;
+  bool bulk = c->prm.bulk_enabled != 0;
+  if (bulk && (!F || !F_star || !mF || !lF)) return SURF_EINVAL;
+  if (lP == mP || lP == psi || lP == psi_star ||
+      (bulk && (lF == mF || lF == F || lF == F_star)))
+    return SURF_EINVAL;
+  if (u && u[0])
+    for (int d = 0; d < c->grid.dim; ++d)
+      if (!u[d]) return SURF_EINVAL;
+  if (c->prm.precision == SURF_F64)
+    return adjoint_step_impl<double>(c, u, F, psi, mF, mP, w, lF, lP, dtheta, F_star, psi_star);
+  return adjoint_step_impl<float>(c, u, F, psi, mF, mP, w, lF, lP, dtheta, F_star, psi_star);
+}
+
+int surf_step_advected(surf_ctx* c, const void* const* u, const void* F_in, const void* psi_in,
+                       void* F_out, void* psi_out, void* sigma_out, double* totals_dev,
+                       void* F_star, void* psi_star) {
+  if (!c || !psi_in || !psi_out || !psi_star) return SURF_EINVAL;
+  // the 3D weighted-form plane-marching transport on a static level set
+  if (c->grid.dim != 3 || c->c3_nwg == 0 || c->prm.interface != SURF_IFACE_VOF ||
+      c->prm.substep2 != SURF_SUBSTEP2_EXPLICIT)
+    return SURF_EINVAL;
+  if (c->prepared) return SURF_ESTATE;  // only surf_step may follow a prepare
+  if (!c->has_chi) return SURF_ESTATE;
+  const bool bulk = c->prm.bulk_enabled != 0;
+  if (bulk && (!F_in || !F_out || !F_star)) return SURF_EINVAL;
+  // every output distinct from the inputs and from each other
+  const void* ins[2] = {psi_in, bulk ? F_in : nullptr};
+  const void* outs[4] = {psi_out, psi_star, bulk ? F_out : nullptr, bulk ? F_star : nullptr};
+  for (int i = 0; i < 4; ++i) {
+    if (!outs[i]) continue;
+    for (const void* q : ins)
+      if (outs[i] == q) return SURF_EINVAL;
+    for (int j = i + 1; j < 4; ++j)
+      if (outs[i] == outs[j]) return SURF_EINVAL;
+  }
+  if (u && u[0])
+    for (int d = 0; d < c->grid.dim; ++d)
+      if (!u[d]) return SURF_EINVAL;
+  const size_t es = esize(&c->prm);
+  if (!aligned(psi_in, es) || !aligned(psi_out, es) || !aligned(psi_star, es)) return SURF_EINVAL;
+  touch_levelset(c);
+  const bool f32 = c->prm.precision == SURF_F32;
+  if (f32) materialize<float>(c);
+  else materialize<double>(c);
+  {
+    Timed tm(c, 0);
+    if (f32) col3d_transport<float>(c, u, F_in, psi_in, F_out, psi_out, sigma_out, nullptr,
+                                    bulk ? F_star : nullptr, psi_star);
+    else col3d_transport<double>(c, u, F_in, psi_in, F_out, psi_out, sigma_out, nullptr,
+                                 bulk ? F_star : nullptr, psi_star);
+  }
+  if (f32) finalize<float>(c, totals_dev, c->c3_nwg);
+  else finalize<double>(c, totals_dev, c->c3_nwg);
+  return status_of_launch();
 }
 
 int surf_adjoint_c0(surf_ctx* c, const void* lF0, void* gc0) {

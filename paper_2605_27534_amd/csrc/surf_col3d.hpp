@@ -61,12 +61,16 @@ struct Col3Args {
   int zchunks; // ceil(nz / TZ)
   int nwg;
   int per_xcd;
+  // optional: the advected state xi* (F*, psi*) of every cell, the input of
+  // the adjoint step's substep-2 and advection transposes
+  R* Fst = nullptr;
+  R* Pst = nullptr;
 };
 
 // One workgroup: strip x0, rows y0 - 1 .. y0 + 14, planes z0 .. z0 + TZ - 1.
 // IX: every column the strip reads lies inside the box away from the x
 // sides; IY: the same for the rows the workgroup reads and the y sides.
-template <typename R, int TZ, bool HU, bool BULK, bool IX, bool IY>
+template <typename R, int TZ, bool HU, bool BULK, bool IX, bool IY, bool ST>
 __device__ __forceinline__ void col3d_wg(const Col3Args<R>& a, Col3Lds<R>& L, const int x0,
                                          const int y0, const int z0, const int lane,
                                          const int wv, ColAcc<R>& acc, const unsigned tkey) {
@@ -357,6 +361,11 @@ __device__ __forceinline__ void col3d_wg(const Col3Args<R>& a, Col3Lds<R>& L, co
       // z face s (below plane s), from plane s-1 in registers
       R wzF = (pPh + ph) * (cs - pC), wzP = (pDe + de) * (Gs - pG);
       if (!pz && (s == 0 || s == nz)) { wzF = R(0); wzP = R(0); }
+      if (ST && out_lane && out_row && s >= z0 && s < z0 + TZ && s < nz) {
+        const int off = (nx * ny * s + nx * ys) * ES;
+        if (BULK) gst(Fs, a.Fst, vxs, off);
+        gst(Ps, a.Pst, vxs, off);
+      }
       const R uxL = from_left(ux);  // every lane takes part in the shift
       if (HU && out_lane && out_row && s >= z0 && s < z0 + TZ && s < nz) {
         // cell-mean velocities of the output cells of plane s (on a periodic
@@ -417,7 +426,7 @@ __device__ __forceinline__ void col3d_wg(const Col3Args<R>& a, Col3Lds<R>& L, co
   }
 }
 
-template <typename R, int TZ, bool HU, bool BULK>
+template <typename R, int TZ, bool HU, bool BULK, bool ST>
 __global__ void __launch_bounds__(64 * C3_WAVES) k_col3d(Col3Args<R> a) {
   __shared__ Col3Lds<R> L;
   const int b = blockIdx.x;
@@ -433,8 +442,8 @@ __global__ void __launch_bounds__(64 * C3_WAVES) k_col3d(Col3Args<R> a) {
   ColAcc<R> acc{0.0, 0.0, 0.0, 0.0, 0.0, R(0), R(-INFINITY), R(INFINITY), R(INFINITY), 0};
   const bool ix = x0 >= 3 && x0 + 62 <= nx, iy = y0 >= 3 && y0 + 17 <= ny;
   const unsigned tk = sizeof(R) == 4 ? step_key(a.state[S_TIME]) : 0u;
-  if (ix && iy) col3d_wg<R, TZ, HU, BULK, true, true>(a, L, x0, y0, z0, lane, wv, acc, tk);
-  else col3d_wg<R, TZ, HU, BULK, false, false>(a, L, x0, y0, z0, lane, wv, acc, tk);
+  if (ix && iy) col3d_wg<R, TZ, HU, BULK, true, true, ST>(a, L, x0, y0, z0, lane, wv, acc, tk);
+  else col3d_wg<R, TZ, HU, BULK, false, false, ST>(a, L, x0, y0, z0, lane, wv, acc, tk);
   double v[NPART];
   v[P_SUM_F] = acc.sF;
   v[P_SUM_PSI] = acc.sP;

@@ -42,7 +42,8 @@ EXPORTS = [
     "surf_adjoint_seed", "surf_adjoint_step", "surf_adjoint_c0",
     "surf_batch_workspace_bytes", "surf_batch_create", "surf_batch_set_geometry",
     "surf_batch_init_state", "surf_batch_step", "surf_batch_parity", "surf_batch_tune",
-    "surf_batch_destroy", "surf_step_static", "surf_set_time",
+    "surf_batch_destroy", "surf_step_static", "surf_set_time", "surf_step_advected",
+    "surf_adjoint_step_advected",
 ]
 
 
@@ -122,6 +123,8 @@ def lib():
         L.surf_adjoint_seed.argtypes = [vp, vp, vp, vp, vp]
         L.surf_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.surf_adjoint_c0.argtypes = [vp, vp, vp]
+        L.surf_step_advected.argtypes = [vp] * 10
+        L.surf_adjoint_step_advected.argtypes = [vp] * 12
         L.surf_profile_read.argtypes = [vp, vp, vp, vp, vp]
         L.surf_step_static.argtypes = [vp, vp, ctypes.c_double, vp, vp, vp, vp, vp, vp, vp, vp,
                                        vp]
@@ -265,11 +268,23 @@ class Surf:
         return F, psi
 
     def step(self, F_in, psi_in, F_out, psi_out, u=None, vof_next=None, sigma_out=None,
-             totals=None):
+             totals=None, star=None):
+        """One step; with star = (F_star, psi_star) (static level set only) the
+        advected state of the step is written there too."""
         ua = self._faces(u, "u")
         if totals is not None and (totals.dtype != torch.float64 or totals.numel() < 16
                                    or totals.device != self.device):
             raise ValueError("totals: 16 float64 on the device")
+        if star is not None:
+            if vof_next is not None:
+                raise ValueError("star: static level set only")
+            self._check(self.L.surf_step_advected(
+                self.ctx, ua, _ptr(self._cell(F_in, "F_in")), _ptr(self._cell(psi_in, "psi_in")),
+                _ptr(self._cell(F_out, "F_out")), _ptr(self._cell(psi_out, "psi_out")),
+                _ptr(self._cell(sigma_out, "sigma_out")), _ptr(totals),
+                _ptr(self._cell(star[0], "F_star")), _ptr(self._cell(star[1], "psi_star"))),
+                "surf_step_advected")
+            return
         self._check(self.L.surf_step(self.ctx, _ptr(self._cell(vof_next, "vof_next")), ua,
                                      _ptr(self._cell(F_in, "F_in")),
                                      _ptr(self._cell(psi_in, "psi_in")),
@@ -387,8 +402,19 @@ class Surf:
                                              _ptr(self._cell(lamF, "lamF")),
                                              _ptr(self._cell(lamP, "lamP"))), "surf_adjoint_seed")
 
-    def adjoint_step(self, F, psi, mF, mP, lF, lP, dtheta, u=None, w=None):
+    def adjoint_step(self, F, psi, mF, mP, lF, lP, dtheta, u=None, w=None, star=None):
+        """lambda^n from lambda^{n+1} = (mF, mP); star = (F_star, psi_star) from
+        step(..., star=...) on the same state skips the advection's
+        recomputation."""
         ua = self._faces(u, "u")
+        if star is not None:
+            self._check(self.L.surf_adjoint_step_advected(
+                self.ctx, ua, _ptr(self._cell(F, "F")), _ptr(self._cell(psi, "psi")),
+                _ptr(self._cell(star[0], "F_star")), _ptr(self._cell(star[1], "psi_star")),
+                _ptr(self._cell(mF, "mF")), _ptr(self._cell(mP, "mP")), _ptr(w),
+                _ptr(self._cell(lF, "lF")), _ptr(self._cell(lP, "lP")), _ptr(dtheta)),
+                "surf_adjoint_step_advected")
+            return
         self._check(self.L.surf_adjoint_step(self.ctx, ua, _ptr(self._cell(F, "F")),
                                              _ptr(self._cell(psi, "psi")),
                                              _ptr(self._cell(mF, "mF")), _ptr(self._cell(mP, "mP")),
