@@ -37,6 +37,7 @@ class Rollout:
         # whether the recomputation keeps each step's advected state for the
         # adjoint (3D plane-marching transport only; settled on first use)
         self.keep_advected = None
+        self._seg = None  # the recomputation's buffers, reused over segments
 
     # one forward step from (F, P) into fresh buffers
     def _step(self, F, P, tot_row):
@@ -52,11 +53,20 @@ class Rollout:
         if self.keep_advected is False:
             return None
         s = self.s
+        if self._seg is None or self._seg[0] < k:
+            # states after steps 1..k (the last one unused) and the k advected
+            # states, allocated once: each segment's adjoint steps are queued
+            # before the next segment's recomputation overwrites them
+            def block(on):
+                return torch.empty((k,) + tuple(s.shape), dtype=s.dtype,
+                                   device=s.device) if on else None
+            self._seg = (k, block(F is not None), block(True), block(F is not None), block(True))
+        _, bF, bP, sF, sP = self._seg
         stars = []
         for i in range(k):
-            F2 = s.empty() if F is not None else None
-            P2 = s.empty()
-            st = (s.empty() if F is not None else None, s.empty())
+            F2 = bF[i] if F is not None else None
+            P2 = bP[i]
+            st = (sF[i] if F is not None else None, sP[i])
             try:
                 s.step(F, P, F2, P2, u=self.u, totals=scratch, star=st)
             except S.SurfError as e:
@@ -95,8 +105,8 @@ class Rollout:
         s = self.s
         dth = torch.zeros(4, dtype=torch.float64, device=s.device)
         FN, PN = ck[self.N]
-        lF = s.empty()
-        lP = s.empty()
+        lF, lP = s.empty(), s.empty()
+        nF, nP = s.empty(), s.empty()  # lambda^n, then swapped with lambda^{n+1}
         s.adjoint_seed(PN, w[self.N - 1:self.N], lF, lP)
         scratch = torch.zeros(16, dtype=torch.float64, device=s.device)
         starts = sorted(k for k in ck if k < self.N)
@@ -112,11 +122,10 @@ class Rollout:
                     states.append((F, P))
             for n in range(s1 - 1, s0 - 1, -1):
                 Fn, Pn = states[n - s0]
-                nF, nP = s.empty(), s.empty()
                 wn = w[n - 1:n] if n >= 1 else None
                 s.adjoint_step(Fn if self.bulk else None, Pn, lF, lP, nF, nP, dth, u=self.u, w=wn,
                                star=None if stars is None else stars[n - s0])
-                lF, lP = nF, nP
+                lF, lP, nF, nP = nF, nP, lF, lP
         gc0 = s.adjoint_c0(lF)
         return dth, gc0
 

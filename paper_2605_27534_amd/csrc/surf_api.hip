@@ -1281,9 +1281,14 @@ int iface_force_impl(surf_ctx* c, const void* vof, const void* sigma, void* cons
   a.r0 = c->grid.origin[0];
   const unsigned tiles =
       (unsigned)iface_tiles_x(c->grid.n[0]) * (unsigned)iface_tiles_y(c->grid.n[1]);
-  hipLaunchKernelGGL(k_iface_force<R>, dim3(tiles), dim3(IF_THREADS), 0, c->stream, a,
-                     cap ? (R*)cap[0] : nullptr, cap ? (R*)cap[1] : nullptr,
-                     ma ? (R*)ma[0] : nullptr, ma ? (R*)ma[1] : nullptr);
+  R* const out[4] = {cap ? (R*)cap[0] : nullptr, cap ? (R*)cap[1] : nullptr,
+                     ma ? (R*)ma[0] : nullptr, ma ? (R*)ma[1] : nullptr};
+  if (a.axi)
+    hipLaunchKernelGGL((k_iface_force<R, true>), dim3(tiles), dim3(IF_THREADS), 0, c->stream, a,
+                       out[0], out[1], out[2], out[3]);
+  else
+    hipLaunchKernelGGL((k_iface_force<R, false>), dim3(tiles), dim3(IF_THREADS), 0, c->stream, a,
+                       out[0], out[1], out[2], out[3]);
   return status_of_launch();
 }
 

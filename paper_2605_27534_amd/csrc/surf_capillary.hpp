@@ -217,7 +217,8 @@ constexpr int IF_CPT = (IF_CX * IF_CY + IF_THREADS - 1) / IF_THREADS;  // per th
 __host__ __device__ __forceinline__ int iface_tiles_x(int nx) { return (nx + IF_TX - 1) / IF_TX; }
 __host__ __device__ __forceinline__ int iface_tiles_y(int ny) { return (ny + IF_TY - 1) / IF_TY; }
 
-template <typename R>
+// AXI: the ring terms, compiled only into the instance for rings
+template <typename R, bool AXI>
 __global__ void __launch_bounds__(IF_THREADS) k_iface_force(IfaceArgs<R> a, R* __restrict__ cap_x,
                                                             R* __restrict__ cap_y,
                                                             R* __restrict__ ma_x,
@@ -280,7 +281,7 @@ __global__ void __launch_bounds__(IF_THREADS) k_iface_force(IfaceArgs<R> a, R* _
         fallback = true;
         kap = __builtin_nan("");  // replaced below
       }
-      if (!a.axi) {
+      if constexpr (!AXI) {
         sd[gy][gx] = cell_delta_m(f, a.h);
       } else {
         // the ring's radius at the cell's geometric position (a mirrored
@@ -312,7 +313,7 @@ __global__ void __launch_bounds__(IF_THREADS) k_iface_force(IfaceArgs<R> a, R* _
         if (isnan(sk[gy][gx])) {
           const auto x = [&](int dj, int di) { return (double)sx[gy + 1 + dj][gx + 1 + di]; };
           const double r = a.r0 + (x0 - 1 + gx + 0.5) * a.h;
-          sk[gy][gx] = (a.axi && r != 0.0) ? levelset_curvature_axi(x, a.h, r)
+          sk[gy][gx] = (AXI && r != 0.0) ? levelset_curvature_axi(x, a.h, r)
                                            : levelset_curvature(x, a.h);
         }
       }
