@@ -186,7 +186,11 @@ int check_grid_params(const surf_grid* gr, const surf_params* p) {
   if (gr->axisym < 0 || gr->axisym > 1) return SURF_EINVAL;
   if (gr->axisym &&
       (gr->dim != 2 || gr->bc[0][0] == SURF_BC_PERIODIC || !(gr->origin[0] >= 0) ||
-       !std::isfinite(gr->origin[0]) || p->flux_form != SURF_FLUX_WEIGHTED || p->adjoint))
+       !std::isfinite(gr->origin[0]) || p->adjoint))
+    return SURF_EINVAL;
+  // the paper form on rings: the explicit tile step on a VoF interface
+  if (gr->axisym && p->flux_form != SURF_FLUX_WEIGHTED &&
+      (p->substep2 != SURF_SUBSTEP2_EXPLICIT || p->interface != SURF_IFACE_VOF))
     return SURF_EINVAL;
   if (p->interface == SURF_IFACE_ACDI &&
       (!(p->acdi_zeta > 0) || !std::isfinite(p->acdi_zeta) || !(p->acdi_vareps >= 0) ||
@@ -633,8 +637,14 @@ void launch_col3d(surf_ctx* c, const Col3Args<R>& a, bool has_u, bool bulk) {
 
 template <typename R, int KH>
 void launch_step2d(surf_ctx* c, const Step2dArgs<R>& a) {
-  hipLaunchKernelGGL((k_step2d<R, KH, STEP2D_THREADS, T2X, T2Y>), dim3(8 * c->per_xcd),
-                     dim3(STEP2D_THREADS), 0, c->stream, a);
+  // the paper form on axisymmetric rings takes the instance with the ring
+  // weights (the weighted form on rings runs in k_col2d)
+  if (c->grid.axisym)
+    hipLaunchKernelGGL((k_step2d<R, KH, STEP2D_THREADS, T2X, T2Y, true>), dim3(8 * c->per_xcd),
+                       dim3(STEP2D_THREADS), 0, c->stream, a);
+  else
+    hipLaunchKernelGGL((k_step2d<R, KH, STEP2D_THREADS, T2X, T2Y>), dim3(8 * c->per_xcd),
+                       dim3(STEP2D_THREADS), 0, c->stream, a);
 }
 
 FinalArgs final_of(const surf_grid& gr, const surf_params& q, int nblk, double dt) {
@@ -883,6 +893,7 @@ int step2d_impl(surf_ctx* c, const void* vof_next, const void* const* u, const v
   a.ntiles = c->ntiles2d;
   a.per_xcd = c->per_xcd;
   a.diag = (c->tiles2d[0] % 8) == 0 ? 1 : 0;
+  a.r0 = c->grid.origin[0];
   {
     Timed tm(c, 0);
     if (!moving) {
@@ -1469,7 +1480,8 @@ int surf_workspace_bytes(const surf_grid* grid, const surf_params* params, size_
   int n2 = ntiles_2d(grid, t2);
   int cs, cg;
   int ncol = col_shape(grid, params, &cs, &cg);
-  if (grid->axisym && ncol == 0) return SURF_EINVAL;  // the rings run on k_col2d only
+  // the weighted form on rings runs on k_col2d only (the paper form in k_step2d)
+  if (grid->axisym && ncol == 0 && params->flux_form == SURF_FLUX_WEIGHTED) return SURF_EINVAL;
   // so do the explicit substep-1 variants in 2D (3D: the tile transport)
   if ((params->limiter || params->transverse) && grid->dim == 2 && ncol == 0 &&
       params->substep2 != SURF_SUBSTEP2_IMPLICIT)

@@ -52,6 +52,7 @@ struct Step2dArgs {
   int ntiles;
   int per_xcd;       // tiles per XCD chunk
   int diag;          // 1: diagonal XCD mapping (tiles[0] % 8 == 0), 0: banded
+  double r0;         // axisymmetric rings: the radius of the low x side
 };
 
 // Workgroup -> tile.  Consecutive workgroups land on consecutive XCDs
@@ -366,7 +367,12 @@ __device__ __forceinline__ bool tile_geometry(const Step2dArgs<R>& a, const int 
 }
 
 // One tile of the step; its FP64 partial record goes to a.part[t].
-template <typename R, int KH, int NT, int TX, int TY>
+// AXI (paper form on axisymmetric rings, Appendix B; x is the radius): the
+// radial face fluxes of both substeps enter a cell's balance with weights
+// r_face / r_mid, the reductions count each cell with 2 pi r_mid (the
+// finalize multiplies by h^2) and the open-side budget each face with its
+// area 2 pi r h.
+template <typename R, int KH, int NT, int TX, int TY, bool AXI = false>
 __device__ __forceinline__ void step2d_tile(const Step2dArgs<R>& a, const int t) {
   // K sweeps reach K cells: within the 3 x 3 tile neighbourhood used to
   // decide which tiles stay quiescent
@@ -555,10 +561,13 @@ __device__ __forceinline__ void step2d_tile(const Step2dArgs<R>& a, const int t)
         const int fa = xf ? fi : fj, ta = xf ? TX : TY;
         const bool own_t = xf ? (fj >= 1 && fj <= TY && gy < ny) : (fi >= 1 && fi <= TX && gx < nx);
         if (own_t) {
+          double wa = 1.0;  // rings: the face's area over h
+          if constexpr (AXI)
+            wa = 2.0 * M_PI * (a.r0 + (xf ? (double)gd : (double)gx + 0.5) * (double)p.h);
           if (blo && g.bc[dd][0] == BC_OPEN && fa >= 1 && fa <= ta)
-            acc[P_OUTFLOW] -= (double)(a.area_dt * (fF + fP));
+            acc[P_OUTFLOW] -= wa * (double)(a.area_dt * (fF + fP));
           if (bhi && g.bc[dd][1] == BC_OPEN && fa >= 2 && fa <= ta + 1)
-            acc[P_OUTFLOW] += (double)(a.area_dt * (fF + fP));
+            acc[P_OUTFLOW] += wa * (double)(a.area_dt * (fF + fP));
         }
       }
       if (xf) { sFlx[mm] = fF; sFlx[NUX + mm] = fP; }
@@ -582,15 +591,23 @@ __device__ __forceinline__ void step2d_tile(const Step2dArgs<R>& a, const int t)
       Ps = sP3[l3];
       if (has_u) {
         const int xl = lx + (TX + 3) * ly, yl = lx + EX1 * ly;
-        const R dF = (sFlx[xl + 1] - sFlx[xl]) + (sFly[yl + EX1] - sFly[yl]);
-        const R dP = (sFlx[NUX + xl + 1] - sFlx[NUX + xl]) + (sFly[NUY + yl + EX1] - sFly[NUY + yl]);
+        R alo = R(1), ahi = R(1);
+        if constexpr (AXI) {
+          const double rl = a.r0 + (double)gx * (double)p.h, rm = rl + 0.5 * (double)p.h;
+          alo = (R)(rl / rm);
+          ahi = (R)((rl + (double)p.h) / rm);
+        }
+        const R dF = (ahi * sFlx[xl + 1] - alo * sFlx[xl]) + (sFly[yl + EX1] - sFly[yl]);
+        const R dP = (ahi * sFlx[NUX + xl + 1] - alo * sFlx[NUX + xl]) +
+                     (sFly[NUY + yl + EX1] - sFly[NUY + yl]);
         Fs = Fs - cfl * dF;
         Ps = Ps - cfl * dP;
         if (lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && gx < nx && gy < ny) {
           // cell-mean velocity magnitudes (on a periodic axis the upper
           // face of the last cell is face 0, as in the fluxes)
           R uxl = sUx[xl], uxh = sUx[xl + 1], uyl = sUy[yl], uyh = sUy[yl + EX1];
-          double us = fabs((double)(R(0.5) * (uxl + uxh))) + fabs((double)(R(0.5) * (uyl + uyh)));
+          double us = fabs((double)(R(0.5) * (alo * uxl + ahi * uxh))) +
+                      fabs((double)(R(0.5) * (uyl + uyh)));
           acc[P_MAX_USUM] = fmax(acc[P_MAX_USUM], us);
         }
       }
@@ -637,6 +654,12 @@ __device__ __forceinline__ void step2d_tile(const Step2dArgs<R>& a, const int t)
     } else {
       // paper form: B from the centred chi gradient (chi held with halo 2)
       const int cx = ix + 1, cy = iy + 1;
+      R alo = R(1), ahi = R(1);
+      if constexpr (AXI) {
+        const double rl = a.r0 + (double)gx * (double)p.h, rm = rl + 0.5 * (double)p.h;
+        alo = (R)(rl / rm);
+        ahi = (R)((rl + (double)p.h) / rm);
+      }
       for (int f = 0; f < 2; ++f) {
         if (f == 0 && !bulk) continue;
         const R* x = f == 0 ? sF1 : sP1;
@@ -646,15 +669,18 @@ __device__ __forceinline__ void step2d_tile(const Step2dArgs<R>& a, const int t)
           const int st = d == 0 ? 1 : EX1;
           const bool blo = d == 0 ? bxl : byl, bhi = d == 0 ? bxh : byh;
           const R Bc = paper_B_lds<R>(sChi, EXC, HC, cx, cy, d, f == 0, p);
+          const R wl = d == 0 ? alo : R(1), wh = d == 0 ? ahi : R(1);
           if (!blo) {
             R Bm = paper_B_lds<R>(sChi, EXC, HC, cx - (d == 0), cy - (d == 1), d, f == 0, p);
             R Bf = R(0.5) * (Bm + Bc);
-            acc2 -= D * (x[c] - x[c - st]) * p.inv_h + Bf * (Bf < R(0) ? x[c - st] : x[c]);
+            const R fl = D * (x[c] - x[c - st]) * p.inv_h + Bf * (Bf < R(0) ? x[c - st] : x[c]);
+            acc2 -= AXI ? wl * fl : fl;
           }
           if (!bhi) {
             R Bp = paper_B_lds<R>(sChi, EXC, HC, cx + (d == 0), cy + (d == 1), d, f == 0, p);
             R Bf = R(0.5) * (Bc + Bp);
-            acc2 += D * (x[c + st] - x[c]) * p.inv_h + Bf * (Bf < R(0) ? x[c] : x[c + st]);
+            const R fh = D * (x[c + st] - x[c]) * p.inv_h + Bf * (Bf < R(0) ? x[c] : x[c + st]);
+            acc2 += AXI ? wh * fh : fh;
           }
         }
         if (f == 0) divF = acc2 * p.inv_h; else divP = acc2 * p.inv_h;
@@ -674,10 +700,18 @@ __device__ __forceinline__ void step2d_tile(const Step2dArgs<R>& a, const int t)
     if (bulk) a.Fo[ci] = Fn;
     a.Po[ci] = Pn;
     if (a.sig) a.sig[ci] = sg;
-    sF += Fn;
-    sP += Pn;
-    sD += de;
-    sSD += sg * de;
+    if constexpr (AXI) {
+      const R wv = (R)(2.0 * M_PI * (a.r0 + ((double)gx + 0.5) * (double)p.h));
+      sF += wv * Fn;
+      sP += wv * Pn;
+      sD += wv * de;
+      sSD += wv * (sg * de);
+    } else {
+      sF += Fn;
+      sP += Pn;
+      sD += de;
+      sSD += sg * de;
+    }
     if (bulk) {
       mxC = fmax(mxC, rdiv<R>(Fn, ph + p.eta));
       mnF = fmin(mnF, Fn);
@@ -697,11 +731,11 @@ __device__ __forceinline__ void step2d_tile(const Step2dArgs<R>& a, const int t)
   block_partials<R, NT>(acc, a.part + (long long)t * NPART);
 }
 
-template <typename R, int KH, int NT = 512, int TX = 64, int TY = 16>
+template <typename R, int KH, int NT = 512, int TX = 64, int TY = 16, bool AXI = false>
 __global__ void __launch_bounds__(NT) k_step2d(Step2dArgs<R> a) {
   const int t = tile_of_block(blockIdx.x, a.tiles[0], a.per_xcd, a.diag);
   if (t >= a.ntiles) return;
-  step2d_tile<R, KH, NT, TX, TY>(a, t);
+  step2d_tile<R, KH, NT, TX, TY, AXI>(a, t);
 }
 
 // The moving-interface geometry alone (the step then runs the transport on

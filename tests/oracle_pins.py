@@ -38,7 +38,7 @@ def _flat_chi(prob, axis, x0):
 
 
 # ------------------------------------------------- paper form: zero flux
-def paper_form_zero_flux_residuals(dim=2, axis=0, eps=0.05, ratios=(2, 4, 8, 16)):
+def paper_form_zero_flux_residuals(dim=2, axis=0, eps=0.05, ratios=(2, 4, 8, 16), axisym=False):
     """The paper-form fluxes of substep 2 (section 2.6: D grad xi + B xi with
     B_F = -D (1 - phi) n / eps and B_psi = -D (1 - 2 phi) n / eps) vanish
     for F = c phi and psi = Gamma delta with c and Gamma uniform, whenever
@@ -48,7 +48,12 @@ def paper_form_zero_flux_residuals(dim=2, axis=0, eps=0.05, ratios=(2, 4, 8, 16)
 
     Returns, per resolution h = eps / r, the max-norm tendency of F and psi
     scaled by D c / eps^2 and D Gamma / eps^3 (the size of the separate
-    terms)."""
+    terms).
+
+    axisym (dim 2, axis 0): the same on the rings of Appendix B with the
+    plane r = 0.5, a cylinder of fluid 1 about the axis (the box's low x side
+    on the axis): the fluxes vanish pointwise whatever weights their
+    divergence takes, so the tendency goes to zero in the same way."""
     out = []
     D_b, D_s, c, G = 0.01, 0.002, 0.7, 0.4
     for r in ratios:
@@ -60,6 +65,9 @@ def paper_form_zero_flux_residuals(dim=2, axis=0, eps=0.05, ratios=(2, 4, 8, 16)
         bc[axis] = (0, 0)
         prob = dict(dim=dim, n=tuple(n), h=h, bc=tuple(bc), eps=eps, flux_form=1,
                     k_a=0.0, k_d=0.0, D_b=D_b, D_s=D_s)
+        if axisym:
+            assert dim == 2 and axis == 0
+            prob["axisym"] = 1
         chi = _flat_chi(prob, axis, 0.5)
         assert np.max(np.abs(chi)) < 12 * eps  # no cell at the clamp
         phi, de = _phi_of(prob, chi)

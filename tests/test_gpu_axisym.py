@@ -85,6 +85,51 @@ def test_axisym_translating_sphere_moving_geometry(prec):
 
 
 @pytest.mark.parametrize("prec", [F64, F32])
+@pytest.mark.parametrize("flow", [False, True], ids=["static", "strain"])
+def test_axisym_paper_form(flow, prec):
+    # the paper's flux form on the rings (k_step2d with ring weights): a
+    # sphere on the axis, walls or open sides, with and without the strain
+    # flow (ragged 64 x 16 tiles in both directions)
+    n = (100, 121)
+    h = 1.0 / 100
+    z0 = 0.55
+    prob = dict(dim=2, n=n, h=h, bc=((0, 2), (2, 2) if flow else (0, 0)), axisym=1,
+                flux_form=1, eos=1, eos_E=0.2, k_a=1.0, k_d=0.5)
+    vof = synth.vof_ball(n, h, (0.0, z0, 0), 0.27, 2)
+    u = synth.u_axisym_strain(n, h, 0.3, z0) if flow else None
+    dt = 0.1 * h * h / 1e-2
+    c0 = synth.uniform_field(n, 7, 0.8, 1.2)
+    o = run_oracle(prob, vof, 10, dt, u=u, c0=c0, gamma0=0.4)
+    g = run_gpu(prob, vof, 10, dt, prec, u=u, c0=c0, gamma0=0.4)
+    compare(o, g, prec)
+    if flow:
+        assert o[4][-1][O.T_OUTCUM] != 0.0
+
+
+@pytest.mark.parametrize("prec", [F64, F32])
+def test_axisym_paper_form_moving_geometry(prec):
+    # the paper form on the rings with the VoF recomputed every step (FP32:
+    # the fused tile step with its in-tile redistancing; FP64: the geometry
+    # kernels, then the static tile step), an annular box off the axis
+    n = (80, 130)
+    h = 1.0 / 96
+    U = 0.4
+    dt = 0.1 * h * h / 1e-2
+    z0 = 0.5
+    r0 = 0.1
+    prob = dict(dim=2, n=n, h=h, bc=((0, 2), (2, 2)), axisym=1, flux_form=1, eos=0,
+                eos_E=0.2, k_a=1.0, k_d=0.5, origin=(r0, 0.0, 0.0))
+    ball = lambda zc: synth.vof_ball(n, h, (0.45, zc, 0), 0.2, 2, origin=(r0, 0.0, 0.0))
+    vof = ball(z0)
+    seq = lambda k: ball(z0 + U * (k + 1) * dt)
+    u = synth.u_uniform(n, 2, (0.0, U))
+    c0 = synth.uniform_field(n, 10, 0.8, 1.2)
+    o = run_oracle(prob, vof, 8, dt, u=u, vof_seq=seq, c0=c0, gamma0=0.4)
+    g = run_gpu(prob, vof, 8, dt, prec, u=u, vof_seq=seq, c0=c0, gamma0=0.4)
+    compare(o, g, prec)
+
+
+@pytest.mark.parametrize("prec", [F64, F32])
 @pytest.mark.parametrize("variant", [(1, 0), (0, 1), (1, 1)], ids=["mc", "transverse", "mc-transverse"])
 def test_axisym_advection_variants(variant, prec):
     # the substep-1 variants on the rings (Cartesian face values, ring

@@ -1,7 +1,8 @@
 """Pins of the axisymmetric oracle (Appendix B: ring volumes, radial fluxes
 weighted by the face radius) against facts it must reproduce:
 
-- exact conservation of the total amount (ring volumes) with walls;
+- exact conservation of the total amount (ring volumes) with walls, in
+  either flux form;
 - a uniform field stays uniform under a flow that is divergence free in the
   axisymmetric sense (u_r = a r, u_z = -2 a z), which the Cartesian weights
   would not keep;
@@ -24,8 +25,10 @@ def axi_prob(nr, nz, R=1.0, bc=((0, 0), (0, 0)), **kw):
     return dict(dim=2, n=(nr, nz), h=h, bc=bc, axisym=1, **kw)
 
 
-def test_conserves_the_total_amount():
-    prob = axi_prob(40, 48, bc=((0, 0), (0, 0)), eos=1, eos_E=0.3, k_a=1.5, k_d=0.7)
+@pytest.mark.parametrize("form", [0, 1], ids=["weighted", "paper"])
+def test_conserves_the_total_amount(form):
+    prob = axi_prob(40, 48, bc=((0, 0), (0, 0)), eos=1, eos_E=0.3, k_a=1.5, k_d=0.7,
+                    flux_form=form)
     h = prob["h"]
     z0 = 0.6
     vof = synth.vof_ball(prob["n"], h, (0.0, z0, 0), 0.35, 2)  # a sphere on the axis

@@ -12,6 +12,10 @@ def test_paper_form_flux_vanishes_on_equilibrium_profiles(dim, axis):
     PINS.paper_form_zero_flux_residuals(dim, axis)
 
 
+def test_paper_form_flux_vanishes_about_a_cylinder_on_rings():
+    PINS.paper_form_zero_flux_residuals(2, 0, axisym=True)
+
+
 def test_paper_form_upwinding_keeps_positivity_at_high_cell_peclet():
     PINS.paper_form_upwind_positivity()
 
