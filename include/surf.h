@@ -139,8 +139,8 @@ typedef struct {
                         with r_face / r_i and every total is a volume
                         or area integral over the rings.  Weighted flux
                         form (either substep 2, VoF or ACDI interface)
-                        or the paper's (explicit substep 2, VoF
-                        interface); no adjoint, no batch.  Otherwise
+                        or the paper's (explicit substep 2, VoF or
+                        ACDI interface); no adjoint, no batch.  Otherwise
                         SURF_EINVAL at init.  0: Cartesian          */
   double h;          /* cell size (cubic cells)                    */
   double origin[3];  /* position of the lower box corner (axisym: the

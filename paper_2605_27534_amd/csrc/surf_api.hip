@@ -188,9 +188,8 @@ int check_grid_params(const surf_grid* gr, const surf_params* p) {
       (gr->dim != 2 || gr->bc[0][0] == SURF_BC_PERIODIC || !(gr->origin[0] >= 0) ||
        !std::isfinite(gr->origin[0]) || p->adjoint))
     return SURF_EINVAL;
-  // the paper form on rings: the explicit tile step on a VoF interface
-  if (gr->axisym && p->flux_form != SURF_FLUX_WEIGHTED &&
-      (p->substep2 != SURF_SUBSTEP2_EXPLICIT || p->interface != SURF_IFACE_VOF))
+  // the paper form on rings: the explicit tile step (VoF or ACDI interface)
+  if (gr->axisym && p->flux_form != SURF_FLUX_WEIGHTED && p->substep2 != SURF_SUBSTEP2_EXPLICIT)
     return SURF_EINVAL;
   if (p->interface == SURF_IFACE_ACDI &&
       (!(p->acdi_zeta > 0) || !std::isfinite(p->acdi_zeta) || !(p->acdi_vareps >= 0) ||

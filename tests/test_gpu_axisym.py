@@ -189,7 +189,7 @@ def test_axisym_implicit(flow, prec):
 # The ACDI interface (section 2.5) on the rings, with either substep 2: a
 # sphere carried along the axis, re-initialized from the VoF at step 3
 @pytest.mark.parametrize("prec", [F64, F32])
-@pytest.mark.parametrize("substep2", [0, 1], ids=["explicit", "implicit"])
+@pytest.mark.parametrize("substep2", [0, 1, "paper"], ids=["explicit", "implicit", "paper"])
 def test_axisym_acdi(substep2, prec):
     from tests.test_gpu_acdi import compare as acdi_compare
     from tests.test_gpu_acdi import run_both
@@ -199,11 +199,14 @@ def test_axisym_acdi(substep2, prec):
     U = 0.4
     z0 = 0.45
     u = synth.u_uniform(n, 2, (0.0, U))
-    # implicit: above the explicit surfactant bound, below the ACDI one
-    dt = 0.15 * h * h / 1e-2 * (1.5 if substep2 else 1)
+    # implicit: above the explicit surfactant bound, below the ACDI one;
+    # "paper": the paper's flux form, explicit, at a smaller step
+    paper = substep2 == "paper"
+    substep2 = 0 if paper else substep2
+    dt = 0.15 * h * h / 1e-2 * (1.5 if substep2 else (0.7 if paper else 1))
     prob = dict(dim=2, n=n, h=h, bc=((0, 2), (1, 1)), axisym=1, eos=1, eos_E=0.2,
                 k_a=1.0, k_d=0.5, acdi_zeta=1.1 * U, substep2=substep2,
-                **(CG[prec] if substep2 else {}))
+                flux_form=1 if paper else 0, **(CG[prec] if substep2 else {}))
     ball = lambda t: synth.vof_ball(n, h, (0.0, z0 + U * t, 0), 0.22, 2)
     reinit = lambda k: ball(k * dt) if k == 3 else None
     o, g = run_both(prob, ball(0.0), 7, dt, prec, u=u, reinit=reinit,
