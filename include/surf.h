@@ -137,11 +137,10 @@ typedef struct {
                         not periodic), y the axis; cell (i, j) is the
                         ring of volume 2 pi r_i h^2, radial fluxes enter
                         with r_face / r_i and every total is a volume
-                        or area integral over the rings.  Weighted flux
-                        form (either substep 2, VoF or ACDI interface)
-                        or the paper's (explicit substep 2, VoF or
-                        ACDI interface); no adjoint, no batch.  Otherwise
-                        SURF_EINVAL at init.  0: Cartesian          */
+                        or area integral over the rings.  Either flux
+                        form, either substep 2, VoF or ACDI interface;
+                        no adjoint, no batch (SURF_EINVAL at init).
+                        0: Cartesian                                 */
   double h;          /* cell size (cubic cells)                    */
   double origin[3];  /* position of the lower box corner (axisym: the
                         radius of the low x side; else informative)  */

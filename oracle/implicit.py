@@ -156,7 +156,8 @@ def paper_B(q, chi, phi, om, bulk_field):
 
 def paper_operator(q, chi, phi, om, bulk_field):
     """P (N x N, CSR): minus the paper-form flux divergence, -(1/h) sum_d
-    (flux_hi - flux_lo), as a matrix acting on xi."""
+    (flux_hi - flux_lo), as a matrix acting on xi (on rings the radial
+    fluxes weighted by r_face / r_i, as in the explicit step)."""
     nx, ny, nz = q["n"]
     N = nx * ny * nz
     h = q["h"]
@@ -164,6 +165,7 @@ def paper_operator(q, chi, phi, om, bulk_field):
     idx = np.arange(N).reshape(nz, ny, nx)
     B = paper_B(q, chi, phi, om, bulk_field)
     bc = list(q["bc"]) + [(0, 0)] * (3 - len(q["bc"]))
+    rmid, rhi = radii(q) if q["axisym"] else (None, None)
     rows, cols, vals = [], [], []
     for d in range(q["dim"]):
         ax = 2 - d
@@ -171,11 +173,19 @@ def paper_operator(q, chi, phi, om, bulk_field):
         L = idx
         R = np.roll(idx, -1, axis=ax)
         Bf = 0.5 * (B[d] + np.roll(B[d], -1, axis=ax))
+        if q["axisym"] and d == 0:
+            # rings: the face enters row L with r_face / r_L and row R with
+            # r_face / r_R (it is L's high face and R's low face)
+            wL = rhi / rmid
+            wR = rhi / np.roll(rmid, -1, axis=ax)
+        else:
+            wL = wR = np.ones(O.shape(q))
         if not per:
             sl = [slice(None)] * 3
             sl[ax] = slice(0, q["n"][d] - 1)
             L, R, Bf = L[tuple(sl)], R[tuple(sl)], Bf[tuple(sl)]
-        L, R, Bf = L.ravel(), R.ravel(), Bf.ravel()
+            wL, wR = wL[tuple(sl)], wR[tuple(sl)]
+        L, R, Bf, wL, wR = L.ravel(), R.ravel(), Bf.ravel(), wL.ravel(), wR.ravel()
         up = np.where(Bf < 0.0, L, R)
         # flux = D (xi_R - xi_L)/h + Bf xi_up through the high face of L and
         # the low face of R: minus the divergence takes -flux/h in row L and
@@ -183,8 +193,7 @@ def paper_operator(q, chi, phi, om, bulk_field):
         k = D / (h * h)
         rows += [L, L, R, R, L, R]
         cols += [L, R, R, L, up, up]
-        vals += [np.full(L.size, k), np.full(L.size, -k), np.full(L.size, k),
-                 np.full(L.size, -k), -Bf / h, Bf / h]
+        vals += [k * wL, -k * wL, k * wR, -k * wR, -Bf / h * wL, Bf / h * wR]
     rows = np.concatenate(rows)
     cols = np.concatenate(cols)
     vals = np.concatenate(vals)
@@ -197,7 +206,6 @@ def implicit_step(prob, chi, u, F, psi, dt, picard=3, totals=None):
     from the advective bound only (substep 2 has none)."""
     q = O.full(prob)
     paper = q["flux_form"] == 1
-    assert not (paper and q["axisym"]), "the paper form on Cartesian grids"
     shp = O.shape(prob)
     N = int(np.prod(shp))
     phi, om, de = O.cell_geometry(prob, chi)

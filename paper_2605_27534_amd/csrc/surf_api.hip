@@ -188,9 +188,6 @@ int check_grid_params(const surf_grid* gr, const surf_params* p) {
       (gr->dim != 2 || gr->bc[0][0] == SURF_BC_PERIODIC || !(gr->origin[0] >= 0) ||
        !std::isfinite(gr->origin[0]) || p->adjoint))
     return SURF_EINVAL;
-  // the paper form on rings: the explicit tile step (VoF or ACDI interface)
-  if (gr->axisym && p->flux_form != SURF_FLUX_WEIGHTED && p->substep2 != SURF_SUBSTEP2_EXPLICIT)
-    return SURF_EINVAL;
   if (p->interface == SURF_IFACE_ACDI &&
       (!(p->acdi_zeta > 0) || !std::isfinite(p->acdi_zeta) || !(p->acdi_vareps >= 0) ||
        p->acdi_vareps >= 0.5 || p->adjoint))
@@ -1146,6 +1143,9 @@ int bicg_solve(surf_ctx* c, const ImpArgs<R>& a, int field, int solve) {
   k.part = c->imp.part;
   k.sc = c->imp.sc;
   k.ncell = c->ncell;
+  k.axi = c->grid.axisym ? 1 : 0;
+  k.r0 = c->grid.origin[0];
+  k.h = c->grid.h;
   const long long nb = (c->ncell + BICG_WG - 1) / BICG_WG;
   k.nwg = (int)(nb < BICG_MAXWG ? nb : BICG_MAXWG);
   const dim3 gr(k.nwg), bl(BICG_WG);

@@ -73,7 +73,16 @@ struct BicgArgs {
   double* sc;
   int nwg;
   long long ncell;
+  int axi;           // axisymmetric rings: radial faces weighted r_face / r_i
+  double r0, h;      // rings: the radius of the low x side, the cell size
 };
+
+// rings (Appendix B): the weight of cell x's radial face on side s in its
+// balance, r_face / r_i
+__device__ __forceinline__ double bicg_ring_w(const BicgArgs& a, int i, int s) {
+  const double rl = a.r0 + (double)i * a.h, rm = rl + 0.5 * a.h;
+  return (s > 0 ? rl + a.h : rl) / rm;
+}
 
 // coordinates of cell c (32-bit: the implicit path keeps ncell < 2^31)
 __device__ __forceinline__ void bicg_coords(const Grid& g, int c, int* x) {
@@ -95,7 +104,8 @@ __device__ __forceinline__ int bicg_nb(const Grid& g, int c, const int* x, int d
 
 // (A y)_c for y given at the cell (yc) and by a callable at any other cell:
 // dg yc plus, per face, k (yc - y_nb) and the upwind term, minus Bbar/h
-// y_up on the high face and plus on the low face
+// y_up on the high face and plus on the low face; on rings a radial face's
+// terms take the cell's weight r_face / r_i
 template <int DIM, typename Y>
 __device__ __forceinline__ double bicg_apply(const BicgArgs& a, int c, const int* x, double yc,
                                              Y&& y) {
@@ -109,6 +119,12 @@ __device__ __forceinline__ double bicg_apply(const BicgArgs& a, int c, const int
       if (nb < 0) continue;
       const double yn = y(nb);
       const double bf = 0.5 * (Bc + a.B[d][nb]) * a.inv_h;
+      if (d == 0 && a.axi) {  // a radial face of a ring: the flux weighted
+        const double t = s > 0 ? a.k * (yc - yn) - bf * (bf < 0.0 ? yc : yn)
+                               : a.k * (yc - yn) + bf * (bf < 0.0 ? yn : yc);
+        Ay += bicg_ring_w(a, x[0], s) * t;
+        continue;
+      }
       Ay += a.k * (yc - yn);
       if (s > 0) Ay -= bf * (bf < 0.0 ? yc : yn);  // c is the low cell
       else Ay += bf * (bf < 0.0 ? yn : yc);        // c is the high cell
@@ -216,6 +232,13 @@ __global__ void __launch_bounds__(BICG_WG) k_bicg_setup(ImpArgs<R> ia, BicgArgs 
         const int nb = bicg_nb(a.g, c, x, d, s);
         if (nb < 0) continue;
         const double bf = 0.5 * (a.B[d][c] + a.B[d][nb]) * a.inv_h;
+        if (d == 0 && a.axi) {
+          double t = a.k;
+          if (s > 0 && bf < 0.0) t -= bf;
+          if (s < 0 && !(bf < 0.0)) t += bf;
+          m += bicg_ring_w(a, x[0], s) * t;
+          continue;
+        }
         m += a.k;
         if (s > 0 && bf < 0.0) m -= bf;
         if (s < 0 && !(bf < 0.0)) m += bf;

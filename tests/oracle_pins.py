@@ -384,7 +384,7 @@ def periodic_last_face_unread():
 
 
 # ------------------------------------- implicit substep 2, paper form
-def paper_implicit_residual(I=None, kinetics=1):
+def paper_implicit_residual(I=None, kinetics=1, axisym=False):
     """The implicit paper-form step (Appendix C with the paper's flux), with
     the Picard sweeps converged, satisfies its implicit equations when they
     are evaluated by the explicit C oracle: advancing the result by a tiny
@@ -392,7 +392,10 @@ def paper_implicit_residual(I=None, kinetics=1):
     must equal (xi - xi*)/dt.  A flipped anti-diffusive term or the wrong
     upwind cell in the implicit operator leaves a residual of the size of
     that term.  I: the implicit oracle module (a planted copy in the
-    mutation tests)."""
+    mutation tests).  axisym: on the rings of Appendix B (a sphere on the
+    axis), where the explicit step is pinned by conservation and by the
+    equilibrium profile about a cylinder, so that a missing or misplaced
+    ring weight in the implicit operator leaves a residual too."""
     if I is None:
         from oracle import implicit as I
     from paper_2605_27534_amd import synth
@@ -400,7 +403,11 @@ def paper_implicit_residual(I=None, kinetics=1):
     h = 1.0 / 40
     prob = dict(dim=2, n=n, h=h, bc=((0, 0), (1, 1)), kinetics=kinetics, eos=1, eos_E=0.3,
                 D_b=1e-2, D_s=2e-3, k_a=2.0, k_d=0.7, flux_form=1)
-    chi = O.geometry(prob, synth.vof_ball(n, h, (0.48, 0.41, 0), 0.21, 2), 60)
+    centre = (0.48, 0.41, 0)
+    if axisym:
+        prob["axisym"] = 1
+        centre = (0.0, 0.41, 0)
+    chi = O.geometry(prob, synth.vof_ball(n, h, centre, 0.21, 2), 60)
     F, P = O.init_state(prob, chi, c0=synth.uniform_field(n, 4, 0.8, 1.2), gamma0=0.4)
     dt = 20 * 0.2 * h * h / 1e-2
     Fn, Pn, _, _ = I.implicit_step(prob, chi, None, F, P, dt, picard=60)

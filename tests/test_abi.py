@@ -179,16 +179,15 @@ def test_axisym_validation():
     g, p, _ = S.make_structs(base, 1e-3, S.SURF_F32)
     assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == 0
     for bad in (dict(axisym=2), dict(bc=((1, 1), (0, 0))), dict(adjoint=1),
-                dict(flux_form=1, substep2=1),
                 dict(origin=(-0.1, 0.0, 0.0)),
                 dict(dim=3, n=(64, 64, 8), bc=((0, 2), (0, 0), (0, 0)))):
         g, p, _ = S.make_structs(dict(base, **bad), 1e-3, S.SURF_F32)
         assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == -1, bad
-    # the implicit substep, the ACDI interface and the paper form (explicit
-    # substep 2) run on the rings too
+    # the implicit substep, the ACDI interface and the paper form run on the
+    # rings too
     for good in (dict(substep2=1), dict(interface=1, acdi_zeta=0.5),
                  dict(substep2=1, interface=1, acdi_zeta=0.5), dict(flux_form=1),
-                 dict(flux_form=1, interface=1, acdi_zeta=0.5)):
+                 dict(flux_form=1, interface=1, acdi_zeta=0.5), dict(flux_form=1, substep2=1)):
         g, p, _ = S.make_structs(dict(base, **good), 1e-3, S.SURF_F32)
         assert L.surf_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(nb)) == 0, good
 

@@ -153,10 +153,12 @@ def test_axisym_advection_variants(variant, prec):
 # ring radius (a symmetric matrix), substep 1 with the ring weights
 @pytest.mark.parametrize("prec", [F64, F32])
 @pytest.mark.parametrize("flow", ["strain", "axial"])
-def test_axisym_implicit(flow, prec):
+@pytest.mark.parametrize("form", [0, 1], ids=["weighted", "paper"])
+def test_axisym_implicit(form, flow, prec):
+    # form 1: the paper's flux, BiCGSTAB with the radial faces weighted
     from oracle import implicit as I
     from tests.harness import default_hj_init
-    from tests.test_gpu_implicit import CG
+    from tests.test_gpu_implicit import CG, CG_P, compare_paper
     n = (130, 140)
     h = 1.0 / 130
     z0 = 0.55
@@ -172,7 +174,8 @@ def test_axisym_implicit(flow, prec):
         u = synth.u_uniform(n, 2, (0.0, 0.3))
         eos = 2
     prob = dict(dim=2, n=n, h=h, bc=bc, axisym=1, eos=eos, eos_E=0.3, kinetics=0,
-                D_b=1e-2, D_s=2e-3, k_a=1.5, k_d=0.7, substep2=1, **CG[prec])
+                D_b=1e-2, D_s=2e-3, k_a=1.5, k_d=0.7, substep2=1, flux_form=form,
+                **(CG_P if form else CG)[prec])
     vof = synth.vof_ball(n, h, (0.0, z0, 0), 0.25, 2)
     c0 = synth.uniform_field(n, 6, 0.8, 1.2)
     dt = 10 * 0.2 * h * h / 1e-2  # ten times the explicit diffusive step
@@ -181,7 +184,10 @@ def test_axisym_implicit(flow, prec):
     F, P = O.init_state(prob, chi, c0=c0, gamma0=0.4)
     o = I.run(prob, chi, u, F, P, dt, 4, picard=3)
     g = run_gpu(prob, vof, 4, dt, prec, u=u, c0=c0, gamma0=0.4)
-    compare(o, g, prec)
+    if form:
+        compare_paper(o, g, prec, 1.5 * h)
+    else:
+        compare(o, g, prec)
     if flow == "strain":
         assert o[4][-1][O.T_OUTCUM] != 0.0  # the open sides carried surfactant
 

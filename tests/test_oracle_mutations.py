@@ -67,9 +67,12 @@ GUARDS = {
 PY_MUTANTS = {
     # the anti-diffusive term with the wrong sign in the implicit operator
     "implicit-paper-sign": ("oracle/implicit.py",
-                            [("np.full(L.size, -k), -Bf / h, Bf / h]",
-                              "np.full(L.size, -k), Bf / h, -Bf / h]")],
+                            [("-Bf / h * wL, Bf / h * wR]", "Bf / h * wL, -Bf / h * wR]")],
                             PINS.paper_implicit_residual),
+    # the ring weight of a radial face taken from the wrong cell
+    "implicit-paper-ring-weight": ("oracle/implicit.py",
+                                   [("wR = rhi / np.roll(rmid, -1, axis=ax)", "wR = rhi / rmid")],
+                                   lambda I=None: PINS.paper_implicit_residual(I, axisym=True)),
     # the downwind cell of -B
     "implicit-paper-downwind": ("oracle/implicit.py",
                                 [("up = np.where(Bf < 0.0, L, R)", "up = np.where(Bf < 0.0, R, L)")],

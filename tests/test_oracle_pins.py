@@ -48,5 +48,6 @@ def test_periodic_last_face_is_never_read():
 
 
 @pytest.mark.parametrize("kinetics", [0, 1])
-def test_implicit_paper_form_satisfies_its_equations(kinetics):
-    PINS.paper_implicit_residual(kinetics=kinetics)
+@pytest.mark.parametrize("axisym", [False, True], ids=["cartesian", "rings"])
+def test_implicit_paper_form_satisfies_its_equations(kinetics, axisym):
+    PINS.paper_implicit_residual(kinetics=kinetics, axisym=axisym)
