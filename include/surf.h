@@ -139,8 +139,8 @@ typedef struct {
                         with r_face / r_i and every total is a volume
                         or area integral over the rings.  Either flux
                         form, either substep 2, VoF or ACDI interface;
-                        no adjoint, no batch (SURF_EINVAL at init).
-                        0: Cartesian                                 */
+                        no adjoint; in a batch the weighted form only
+                        (SURF_EINVAL otherwise).  0: Cartesian       */
   double h;          /* cell size (cubic cells)                    */
   double origin[3];  /* position of the lower box corner (axisym: the
                         radius of the low x side; else informative)  */
@@ -535,8 +535,8 @@ int surf_adjoint_c0(surf_ctx* ctx, const void* lamF0, void* grad_c0);
 int surf_batch_workspace_bytes(int32_t n_inst, const surf_grid* grids, const surf_params* params,
                                size_t* bytes);
 
-/* Validates every instance (dim 2, same precision, weighted or paper form)
- * and carves the workspace.  F and psi: 2 n_inst device buffers each, the
+/* Validates every instance (dim 2, same precision, weighted or paper form;
+ * on axisymmetric rings the weighted form) and carves the workspace.  F and psi: 2 n_inst device buffers each, the
  * state pair of instance i at [2i] and [2i+1]; sigma: n_inst buffers or NULL.
  * The state of instance i lives in buffer [2i + surf_batch_parity()]. */
 int surf_batch_create(surf_batch** batch, int32_t n_inst, const surf_grid* grids,

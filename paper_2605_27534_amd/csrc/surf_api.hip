@@ -2203,7 +2203,8 @@ int batch_layout(int32_t n, const surf_grid* grids, const surf_params* prm, Batc
   L->chi.resize(n);
   L->q.resize(n);
   for (int i = 0; i < n; ++i) {
-    if (grids[i].axisym) return SURF_EINVAL;  // the batch kernel is Cartesian
+    // rings run in the column kernel only (weighted form)
+    if (grids[i].axisym && !batch_col(prm[i])) return SURF_EINVAL;
     if (prm[i].limiter || prm[i].transverse) return SURF_EINVAL;  // and takes the default scheme
     int rc = check_grid_params(&grids[i], &prm[i]);
     if (rc) return rc;
@@ -2321,7 +2322,8 @@ void batch_tables(surf_batch* b) {
     c.state = b->states + (size_t)i * NSTATE;
     c.dt = a.dt;
     c.area_dt = a.area_dt;
-    c.r0 = 0.0;
+    c.r0 = gr.axisym ? gr.origin[0] : 0.0;
+    c.axi = gr.axisym ? 1 : 0;
     std::memcpy(b->host_col_inst.data() + sizeof(c) * i, &c, sizeof(c));
     if (batch_col(q)) continue;  // column entries: batch_col_tables
     // tile entries of the paper-form instances: records after the column ones
@@ -2336,14 +2338,26 @@ void batch_tables(surf_batch* b) {
 template <typename R>
 void batch_launch_col(surf_batch* b, int ty, int grid, int parity) {
   if (b->ncol_q == 0) return;
-  if (ty == 16)
-    hipLaunchKernelGGL((k_batch_col2d<R, 16>), dim3(grid), dim3(64 * COL_WAVES), 0, b->stream,
-                       (const ColArgs<R>*)b->col_inst, (const int2*)b->col_queue, b->ncol_q,
-                       (const int*)b->first, parity, b->part);
-  else
-    hipLaunchKernelGGL((k_batch_col2d<R, 8>), dim3(grid), dim3(64 * COL_WAVES), 0, b->stream,
-                       (const ColArgs<R>*)b->col_inst, (const int2*)b->col_queue, b->ncol_q,
-                       (const int*)b->first, parity, b->part);
+  bool rings = false;
+  for (int i = 0; i < b->n; ++i) rings = rings || b->grids[i].axisym != 0;
+  const ColArgs<R>* inst = (const ColArgs<R>*)b->col_inst;
+  const int2* queue = (const int2*)b->col_queue;
+  const int* first = (const int*)b->first;
+  const dim3 gr(grid), bl(64 * COL_WAVES);
+  if (rings) {
+    if (ty == 16)
+      hipLaunchKernelGGL((k_batch_col2d<R, 16, true>), gr, bl, 0, b->stream, inst, queue,
+                         b->ncol_q, first, parity, b->part);
+    else
+      hipLaunchKernelGGL((k_batch_col2d<R, 8, true>), gr, bl, 0, b->stream, inst, queue,
+                         b->ncol_q, first, parity, b->part);
+  } else if (ty == 16) {
+    hipLaunchKernelGGL((k_batch_col2d<R, 16>), gr, bl, 0, b->stream, inst, queue, b->ncol_q,
+                       first, parity, b->part);
+  } else {
+    hipLaunchKernelGGL((k_batch_col2d<R, 8>), gr, bl, 0, b->stream, inst, queue, b->ncol_q,
+                       first, parity, b->part);
+  }
 }
 
 template <typename R>

@@ -52,6 +52,7 @@ struct ColArgs {
   R dt;
   R area_dt;        // h dt: face length times the step
   double r0;        // axisymmetric: the radius of the low x side
+  int axi;          // batched form: 1 for an instance on axisymmetric rings
   int strips;       // ceil(nx / 58)
   int groups;       // ceil(chunks / 4): row-chunk groups per strip
   int nwg;          // strips * groups
@@ -557,8 +558,11 @@ __global__ void __launch_bounds__(64 * COL_WAVES) k_col2d(ColArgs<R> a) {
 // order of the single-problem launch.  The entries are dealt to the eight
 // XCDs in contiguous bands (workgroup b runs on XCD b mod 8), so that the
 // vertically adjacent chunks of a strip, which share halo rows, meet in one
-// L2.  The grid is a multiple of 8.
-template <typename R, int TY>
+// L2.  The grid is a multiple of 8.  RINGS: the instance for batches that
+// hold instances on axisymmetric rings (Appendix B), which run the ring
+// variant of the column waves; Cartesian-only batches keep the kernel
+// without it.
+template <typename R, int TY, bool RINGS = false>
 __global__ void __launch_bounds__(64 * COL_WAVES) k_batch_col2d(
     const ColArgs<R>* __restrict__ inst, const int2* __restrict__ queue, int nqueue,
     const int* __restrict__ first, int parity, double* __restrict__ part) {
@@ -587,7 +591,19 @@ __global__ void __launch_bounds__(64 * COL_WAVES) k_batch_col2d(
     const unsigned tk = sizeof(R) == 4 ? step_key(a.state[S_TIME]) : 0u;
     if (y0 < ny) {
       const bool ix = x0 >= 3 && x0 + 62 <= nx, iy = y0 >= 3 && y0 + TY + 3 <= ny;
-      if (a.p.bulk) {
+      if (RINGS && a.axi) {
+        if (a.p.bulk) {
+          if (ix && iy) col2d_wave<R, TY, false, true, true, true, true>(a, x0, y0, lane, acc, tk);
+          else if (iy) col2d_wave<R, TY, false, true, false, true, true>(a, x0, y0, lane, acc, tk);
+          else if (ix) col2d_wave<R, TY, false, true, true, false, true>(a, x0, y0, lane, acc, tk);
+          else col2d_wave<R, TY, false, true, false, false, true>(a, x0, y0, lane, acc, tk);
+        } else {
+          if (ix && iy) col2d_wave<R, TY, false, false, true, true, true>(a, x0, y0, lane, acc, tk);
+          else if (iy) col2d_wave<R, TY, false, false, false, true, true>(a, x0, y0, lane, acc, tk);
+          else if (ix) col2d_wave<R, TY, false, false, true, false, true>(a, x0, y0, lane, acc, tk);
+          else col2d_wave<R, TY, false, false, false, false, true>(a, x0, y0, lane, acc, tk);
+        }
+      } else if (a.p.bulk) {
         if (ix && iy) col2d_wave<R, TY, false, true, true, true, false>(a, x0, y0, lane, acc, tk);
         else if (iy) col2d_wave<R, TY, false, true, false, true, false>(a, x0, y0, lane, acc, tk);
         else if (ix) col2d_wave<R, TY, false, true, true, false, false>(a, x0, y0, lane, acc, tk);

@@ -112,6 +112,12 @@ def test_batch_workspace_validates_instances():
     g3, p3, _ = S.make_structs(dict(dim=3, n=(16, 16, 16), h=1 / 16.0), 1e-4, S.SURF_F32)
     grids[1], params[1] = g3, p3
     assert L.surf_batch_workspace_bytes(2, grids, params, ctypes.byref(nb)) == -1
+    # rings: the weighted form (the column kernel) only
+    ring = dict(dim=2, n=(64, 64), h=1 / 64.0, bc=((0, 2), (0, 0)), axisym=1)
+    grids[1], params[1], _ = S.make_structs(ring, 1e-4, S.SURF_F32)
+    assert L.surf_batch_workspace_bytes(2, grids, params, ctypes.byref(nb)) == 0
+    grids[1], params[1], _ = S.make_structs(dict(ring, flux_form=1), 1e-4, S.SURF_F32)
+    assert L.surf_batch_workspace_bytes(2, grids, params, ctypes.byref(nb)) == -1
     # creation needs device buffers: a null handle array is rejected first
     h = ctypes.c_void_p()
     assert L.surf_batch_create(ctypes.byref(h), 2, grids, params, None, None, None, None, 0,

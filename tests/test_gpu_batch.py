@@ -105,6 +105,47 @@ def test_batch_fp64_matches_oracle():
         assert got[i][3][O.T_T] == pytest.approx(hist[-1][O.T_T], rel=1e-14)
 
 
+def ring_instances():
+    # axisymmetric rings (Appendix B) beside a Cartesian instance: a sphere
+    # on the axis (open outer side), an annulus off the axis with a ring of
+    # fluid (walls), and a Cartesian disc
+    out = []
+    specs = [((90, 120), ((0, 2), (0, 0)), (0.0, 0.0, 0.0), (0.0, 0.55), 0.3),
+             ((70, 64), ((0, 0), (1, 1)), (0.2, 0.0, 0.0), (0.6, 0.5), 0.2)]
+    for (nx, ny), bc, org, (cx, cz), R in specs:
+        h = 1.0 / max(nx, ny)
+        prob = dict(dim=2, n=(nx, ny), h=h, bc=bc, axisym=1, origin=org, eos=1, eos_E=0.3,
+                    k_a=1.5, k_d=0.7)
+        vof = synth.vof_ball((nx, ny), h, (cx, cz, 0), R, 2, origin=org)
+        c0 = synth.uniform_field((nx, ny), 20 + len(out), 0.8, 1.2)
+        out.append((prob, 0.2 * h * h / 1e-2, vof, c0))
+    return out + [instances()[0]]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_with_rings(prec):
+    # the ring instances take the ring variant of the column waves in the
+    # same persistent launch as the Cartesian one: against the single-problem
+    # path (k_col2d's ring instance) and, in FP64, against the oracle
+    insts = ring_instances()
+    N = 9
+    got = run_batch(insts, prec, [4, 5])
+    ftol, ttol = (1e-13, 1e-12) if prec == 1 else (2e-6, 2e-6)
+    for i, (p, dt, vof, c0) in enumerate(insts):
+        ref = run_single(p, dt, vof, c0, prec, N)
+        for name, a, b in zip(("F", "psi", "sigma"), got[i][:3], ref[:3]):
+            assert rel_max(a, b) <= ftol, (i, name, rel_max(a, b))
+        for slot in range(16):
+            x, y = got[i][3][slot], ref[3][slot]
+            assert abs(x - y) <= ttol * max(abs(y), 1e-300), (i, slot, x, y)
+        if prec == 1:
+            chi, F, P, S, hist = run_oracle(p, vof, N, dt, c0=c0, gamma0=0.1)
+            for name, a, b in (("F", got[i][0], F), ("psi", got[i][1], P), ("sigma", got[i][2], S)):
+                assert rel_max(a.reshape(b.shape), b) <= 1e-12, (i, name)
+            for slot in (O.T_MB, O.T_MS, O.T_SDELTA, O.T_SSIGD, O.T_MTOT, O.T_GAVG, O.T_SAVG):
+                assert abs(got[i][3][slot] - hist[-1][slot]) <= 1e-12 * abs(hist[-1][slot]), (i, slot)
+
+
 def test_tuned_launch_shape_and_step_split_leave_results_unchanged():
     # the autotuner's choice changes only the launch shape; the fields are
     # per-cell and must not change, the totals only by reduction order
