@@ -37,6 +37,13 @@
  *  - Pointers must be device pointers aligned to their element size.
  *  - Numerical health is reported through a sticky status word
  *    (surf_get_status), not through return codes.
+ *  - Deliberate shapes of some calls: surf_init_state takes the bulk
+ *    concentration c0 and no VoF field (the level set comes first, from
+ *    surf_set_geometry); surf_force takes sigma, which surf_step returns,
+ *    rather than psi; surf_batch_create binds each instance's pair of state
+ *    buffers once and surf_batch_step takes none (the parity says which
+ *    buffer holds the state); surf_adjoint_step takes the loss weight w_n of
+ *    its own time level, so that one call adds that level's loss term.
  */
 #ifndef SURF_H
 #define SURF_H

@@ -57,18 +57,21 @@ def test_fp64_adjoint_matches_oracle(dim):
 
 @pytest.mark.parametrize("dim", [2, 3])
 def test_fp32_adjoint_against_fp64_oracle(dim):
-    # FP32 forward + adjoint against the FP64 oracle: the loss to 2e-5 and
-    # the gradients to 2e-4 relative (the gradient of a misfit is a difference
-    # of nearby sums, so it carries a larger relative error than the fields)
+    # FP32 forward + adjoint against the FP64 oracle: the loss and the
+    # gradients (each dtheta component relative to itself, dL/dc0 against its
+    # max-norm) within 2e-5, the bar of the FP32 field comparisons
     prob, chi, u, c0, dt, n, h = problem(dim)
     N = 12
     theta = np.array([1.3, 0.7, 0.012, 0.0008])
     target = np.linspace(0.97, 0.93, N)
     Lo, dto, gco = O.sigma_history_grad(prob, chi, u, c0, 0.2, dt, N, theta, target)
     Lg, dtg, gcg = gpu_grad(prob, chi, u, c0, dt, N, theta, target, 0, 4)
+    print("dim %d: loss %.3g, dtheta %s, dc0 %.3g" % (
+        dim, abs(Lg - Lo) / Lo, np.abs(dtg - dto) / np.abs(dto),
+        np.max(np.abs(gcg - gco)) / np.max(np.abs(gco))), flush=True)
     assert abs(Lg - Lo) <= 2e-5 * Lo
-    assert np.max(np.abs(dtg - dto) / np.abs(dto)) <= 2e-4, (dtg, dto)
-    assert np.max(np.abs(gcg - gco)) <= 2e-4 * np.max(np.abs(gco))
+    assert np.max(np.abs(dtg - dto) / np.abs(dto)) <= 2e-5, (dtg, dto)
+    assert np.max(np.abs(gcg - gco)) <= 2e-5 * np.max(np.abs(gco))
 
 
 def test_checkpoint_interval_does_not_change_gradients():
