@@ -249,14 +249,17 @@ __device__ __forceinline__ R geo3_update(const Par<R>& p, R dtau, R v, R gk, R x
 }
 
 // One Jacobi sweep (Godunov, pinned cut cells, clamp) over the listed tiles.
-// Thread (x, y) of a 256-thread workgroup owns the tile's z-column at
-// (x, y): it loads the column with one cell beyond each end, the four x and
-// y neighbour columns and the pin data, every load issued before any is
-// used, then updates its 16 cells.  Neighbours come from src everywhere:
-// quiescent tiles hold the clamp in every buffer a sweep reads.  Persistent grid (a
-// multiple of 8 workgroups).  The last sweep also writes each tile's new
-// flag.
-constexpr int G3_SWEEP_THREADS = G3 * G3, G3_SWEEP_GRID = 1024;
+// Thread (x, y, h) of a 512-thread workgroup owns G3_SZ = 8 cells of the
+// tile's z-column at (x, y), half h of it: it loads those cells with one
+// beyond each end, the four x and y neighbour columns over the same planes
+// and the pin data, every load issued before any is used, then updates its
+// cells.  Two threads per column (rather than one for all 16 cells) put
+// twice the waves on the band's few hundred tiles to wait out the load
+// latency.  Neighbours come from src everywhere: quiescent tiles hold the
+// clamp in every buffer a sweep reads.  Persistent grid (a multiple of 8
+// workgroups).  The last sweep also writes each tile's new flag.
+constexpr int G3_SZ = 8;
+constexpr int G3_SWEEP_THREADS = G3 * G3 * (G3 / G3_SZ), G3_SWEEP_GRID = 1024;
 template <typename R>
 __global__ void __launch_bounds__(G3_SWEEP_THREADS) k_geo3_sweep(Geo3Args ga, Par<R> p, R dtau,
                                                                  const R* __restrict__ src,
@@ -270,7 +273,7 @@ __global__ void __launch_bounds__(G3_SWEEP_THREADS) k_geo3_sweep(Geo3Args ga, Pa
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const long long pl = (long long)nx * ny;
   const int tid = threadIdx.x;
-  const int lx = tid % G3, ly = tid / G3;
+  const int lx = tid % G3, ly = (tid / G3) % G3, lz = (tid / (G3 * G3)) * G3_SZ;
   // XCD k (workgroups b with b % 8 == k) takes the k-th eighth of the list,
   // so that neighbouring tiles, which share cache lines, meet in one L2
   const int n = live[0];
@@ -279,7 +282,7 @@ __global__ void __launch_bounds__(G3_SWEEP_THREADS) k_geo3_sweep(Geo3Args ga, Pa
   for (int it = lo + (blockIdx.x >> 3); it < hi; it += slots) {
     const int t = live[1 + it];
     const int x0 = (t % ga.tiles[0]) * G3, y0 = ((t / ga.tiles[0]) % ga.tiles[1]) * G3,
-              z0 = (t / (ga.tiles[0] * ga.tiles[1])) * G3;
+              z0 = (t / (ga.tiles[0] * ga.tiles[1])) * G3 + lz;  // this thread's first plane
     const int gx = x0 + lx, gy = y0 + ly;
     const bool colin = gx < nx && gy < ny;
     // columns past the box edge read a valid column and store nothing
@@ -289,12 +292,12 @@ __global__ void __launch_bounds__(G3_SWEEP_THREADS) k_geo3_sweep(Geo3Args ga, Pa
     const long long cxp = (long long)map_axis_sel(cx + 1, nx, g.bc[0][0], g.bc[0][1]) + (long long)nx * cy;
     const long long cym = (long long)cx + (long long)nx * map_axis_sel(cy - 1, ny, g.bc[1][0], g.bc[1][1]);
     const long long cyp = (long long)cx + (long long)nx * map_axis_sel(cy + 1, ny, g.bc[1][0], g.bc[1][1]);
-    R col[G3 + 2], xm[G3], xp[G3], ym[G3], yp[G3], gv[G3];
+    R col[G3_SZ + 2], xm[G3_SZ], xp[G3_SZ], ym[G3_SZ], yp[G3_SZ], gv[G3_SZ];
 #pragma unroll
-    for (int z = -1; z <= G3; ++z) {
+    for (int z = -1; z <= G3_SZ; ++z) {
       const long long pz = pl * map_axis_sel(z0 + z, nz, g.bc[2][0], g.bc[2][1]);
       col[z + 1] = src[cxy + pz];
-      if (z >= 0 && z < G3) {
+      if (z >= 0 && z < G3_SZ) {
         xm[z] = src[cxm + pz];
         xp[z] = src[cxp + pz];
         ym[z] = src[cym + pz];
@@ -304,7 +307,7 @@ __global__ void __launch_bounds__(G3_SWEEP_THREADS) k_geo3_sweep(Geo3Args ga, Pa
     }
     bool allpos = true, allneg = true;
 #pragma unroll
-    for (int z = 0; z < G3; ++z) {
+    for (int z = 0; z < G3_SZ; ++z) {
       const R nv = geo3_update<R>(p, dtau, col[z + 1], gv[z], xm[z], xp[z], ym[z], yp[z], col[z],
                                   col[z + 2]);
       if (colin && z0 + z < nz) {
