@@ -50,6 +50,15 @@ def test_workspace_bytes_and_init_validate_arguments():
                              ctypes.c_void_p(base), ctypes.c_void_p(base)) == -4
     assert L.surf_set_geometry(ctx, ctypes.c_void_p(base), 0) == -4
     assert L.surf_step(ctx, None, None, None, None, None, None, None, None) == -1
+    # the step that keeps its advected state: 3D plane-marching contexts only;
+    # the adjoint step that reads it: adjoint contexts only
+    q = [ctypes.c_void_p(base + 256 * k) for k in range(8)]
+    assert L.surf_step_advected(ctx, None, q[0], q[1], q[2], q[3], None, None, q[4], q[5]) == -1
+    assert L.surf_step_advected(ctx, None, q[0], None, q[2], q[3], None, None, q[4], q[5]) == -1
+    assert L.surf_adjoint_step_advected(None, None, q[0], q[1], q[2], q[3], q[4], q[5], None,
+                                        q[6], q[7], q[0]) == -1
+    assert L.surf_adjoint_step_advected(ctx, None, q[0], q[1], q[2], q[3], q[4], q[5], None,
+                                        q[6], q[7], q[0]) == -4
     assert L.surf_set_dt(ctx, ctypes.c_double(-1.0)) == -1
     assert L.surf_destroy(ctx) == 0
     # too small a workspace, misaligned workspace
